@@ -1,0 +1,556 @@
+"""FP64 CPU oracle of the PRISM filter hot path -- test infrastructure only.
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg use
+this package.  It shares no code with the GPU library: the per-ray and
+per-voxel loops live in ``prism_oracle.c`` (plain C, double precision, built
+with gcc), the small linear-Gaussian algebra lives here in NumPy float64.
+
+Paper: Mirchev et al., PRISM (CoRL 2022, arXiv 2212.02988).
+
+=====================  ===================================================
+function               passage it follows
+=====================  ===================================================
+render                 App. B, ray-marching emission, first crossing of
+                       tau and the depth-interpolation equation; colour
+                       "analogously to depth"
+normals                App. E.3 (normal of the rendered depth image),
+                       App. G (discontinuous depth ignored)
+render_jacobian        Sec. 3.3.2 MAP objective with the render-through
+                       likelihood; App. G weights and gating
+track_p2               App. E.3 prediction-to-observation objective
+                       (point-to-plane and photometric terms)
+map_update             App. D Gaussian product in precision form, App. G
+                       update region, truncation and update scale
+render_vjp             adjoint of App. B's emission (App. B notes the
+                       emission is differentiable)
+predict / split        App. E.1 linearised transition, E.2 closed-form
+                       propagation and split into pose prior + velocity
+                       conditional
+gn_solve / laplace     Sec. 3.3.2 MAP pose + Laplace approximation;
+                       Sec. 4 / App. G Hessian as squared Jacobian, EMA 0.8
+combine                Sec. 3.3.2 product of pose posterior and velocity
+                       conditional
+filter_step            Sec. 3.3 map filter then state filter ordering
+=====================  ===================================================
+
+Readings where the paper is silent or ambiguous are listed in the design doc's
+table of readings; the ones that change arithmetic are repeated next to the
+code they affect.
+
+Parity status: every function above is pinned by a CPU test against a
+closed form, a brute force or finite differences, except ``filter_step`` as a
+whole, whose parity beyond its components is unpinned.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass, field
+from typing import Dict, Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "prism_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C part of the oracle with gcc (double precision, no FMA
+    contraction, OpenMP)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-fno-fast-math", "-Wall", "-o", _LIB_PATH + ".tmp", _SRC, "-lm"]
+    if force or not os.path.exists(_LIB_PATH):
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("pad_", ctypes.c_int32), ("voxel", ctypes.c_double),
+                ("origin", ctypes.c_double * 3), ("occ_out", ctypes.c_double),
+                ("rgb_out", ctypes.c_double)]
+
+
+class _Cam(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("fx", ctypes.c_double), ("fy", ctypes.c_double), ("cx", ctypes.c_double),
+                ("cy", ctypes.c_double), ("d_near", ctypes.c_double), ("d_far", ctypes.c_double),
+                ("n_samples", ctypes.c_int32), ("pad_", ctypes.c_int32), ("tau", ctypes.c_double)]
+
+
+class _Weights(ctypes.Structure):
+    _fields_ = [("w_depth", ctypes.c_double), ("w_rgb", ctypes.c_double),
+                ("gate_depth", ctypes.c_double), ("gate_rgb", ctypes.c_double)]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        lib.orc_render.argtypes = [P, P, P, P, ctypes.c_int, P, P, P, P]
+        lib.orc_normals.argtypes = [P, P, P, ctypes.c_double, P, P]
+        lib.orc_render_jacobian.argtypes = [P, P, P, P, ctypes.c_int, P, P, P, P, P, P, P, P, P, P]
+        lib.orc_track_p2.argtypes = [P, P, P, ctypes.c_int, P, P, P, P, P, P, P, P, P, P, P, P]
+        lib.orc_map_update.argtypes = [P, P, P, P, P, ctypes.c_int, P, P, ctypes.c_double,
+                                       ctypes.c_double, P]
+        lib.orc_map_update.restype = ctypes.c_int64
+        lib.orc_render_vjp.argtypes = [P, P, P, P, ctypes.c_int, P, P, P, P]
+        lib.orc_pose_to_rot.argtypes = [P, P]
+        _lib = lib
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+# ---------------------------------------------------------------------------
+# parameters
+# ---------------------------------------------------------------------------
+@dataclass
+class Grid:
+    n: int
+    voxel: float
+    origin: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    occ_out: float = -0.001      # App. G: first map belief has occupancy -0.001
+    rgb_out: float = 0.0         # ... and colour 0
+
+    def c(self) -> _Grid:
+        return _Grid(self.n, 0, self.voxel, (ctypes.c_double * 3)(*self.origin), self.occ_out,
+                     self.rgb_out)
+
+
+@dataclass
+class Cam:
+    width: int
+    height: int
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    d_near: float
+    d_far: float
+    n_samples: int
+    tau: float = 0.0             # App. G: hit threshold 0
+
+    def c(self) -> _Cam:
+        return _Cam(self.width, self.height, self.fx, self.fy, self.cx, self.cy, self.d_near,
+                    self.d_far, self.n_samples, 0, self.tau)
+
+
+@dataclass
+class Params:
+    """Filter hyper-parameters (App. G defaults where the paper gives them)."""
+    dt: float = 0.1
+    sigma_vel_t: float = 0.03    # App. G transition scales, per step
+    sigma_vel_r: float = 0.03
+    sigma_pose_t: float = 0.05
+    sigma_pose_r: float = 0.02
+    b_geo: float = 0.02          # App. G Laplace scales (EuRoC / TUM values)
+    b_rgb: float = 0.1
+    gate_geo: float = 0.45       # App. G gating
+    gate_rgb: float = 0.15
+    ema: float = 0.8             # App. G Laplace EMA coefficient
+    n_gn: int = 3
+    trunc_voxels: float = 4.0    # App. G truncation (Blackbird value)
+    sigma_update: float = 1.0    # App. G update scale
+    normal_disc: float = 0.1     # depth discontinuity for anchor normals (m)
+    objective: str = "p2"        # "p2" surrogate (paper) or "p1" render-through
+
+    def weights(self) -> _Weights:
+        return _Weights(1.0 / self.b_geo ** 2, 1.0 / self.b_rgb ** 2, self.gate_geo, self.gate_rgb)
+
+
+def grid_from_scene(scene) -> Grid:
+    return Grid(scene.n, scene.voxel, tuple(float(v) for v in scene.origin))
+
+
+def cam_from(c) -> Cam:
+    return Cam(c.width, c.height, c.fx, c.fy, c.cx, c.cy, c.d_near, c.d_far, c.n_samples, c.tau)
+
+
+# ---------------------------------------------------------------------------
+# per-ray / per-voxel loops (C)
+# ---------------------------------------------------------------------------
+def render(grid: Grid, mean: np.ndarray, cam: Cam, pose: np.ndarray, decide32: bool = True,
+           normals: bool = False, normal_disc: float = 0.1) -> Dict[str, np.ndarray]:
+    """App. B emission for one frame: depth, rgb, mask, hit sample index;
+    optionally the anchor normals."""
+    lib = _load()
+    H, W = cam.height, cam.width
+    mean = _f64(mean)
+    pose = _f64(pose)
+    out = dict(depth=np.zeros((H, W)), rgb=np.zeros((H, W, 3)), mask=np.zeros((H, W), np.uint8),
+               hit_k=np.zeros((H, W), np.int32))
+    g, c = grid.c(), cam.c()
+    lib.orc_render(ctypes.byref(g), _p(mean), ctypes.byref(c), _p(pose), int(decide32),
+                   _p(out["depth"]), _p(out["rgb"]), _p(out["mask"]), _p(out["hit_k"]))
+    if normals:
+        nrm, nmask = normals_of(cam, out["depth"], out["mask"], normal_disc)
+        out["normals"], out["nmask"] = nrm, nmask
+    return out
+
+
+def normals_of(cam: Cam, depth: np.ndarray, mask: np.ndarray, disc: float = 0.1):
+    lib = _load()
+    H, W = cam.height, cam.width
+    nrm = np.zeros((H, W, 3))
+    nmask = np.zeros((H, W), np.uint8)
+    c = cam.c()
+    lib.orc_normals(ctypes.byref(c), _p(_f64(depth)), _p(np.ascontiguousarray(mask, np.uint8)),
+                    disc, _p(nrm), _p(nmask))
+    return nrm, nmask
+
+
+def _neq_out():
+    return np.zeros(29)
+
+
+def render_jacobian(grid: Grid, mean, cam: Cam, pose, obs_depth, obs_rgb, params: Params,
+                    decide32: bool = True, want_J: bool = False) -> Dict[str, np.ndarray]:
+    """P1: render, per-ray 4x6 pose Jacobian, gated weighted normal equations."""
+    lib = _load()
+    H, W = cam.height, cam.width
+    out = dict(depth=np.zeros((H, W)), rgb=np.zeros((H, W, 3)), mask=np.zeros((H, W), np.uint8),
+               neq=_neq_out(), resid=np.zeros((H, W, 4)), rowmask=np.zeros((H, W), np.uint8))
+    if want_J:
+        out["J"] = np.zeros((H, W, 4, 6))
+    g, c, w = grid.c(), cam.c(), params.weights()
+    lib.orc_render_jacobian(ctypes.byref(g), _p(_f64(mean)), ctypes.byref(c), _p(_f64(pose)),
+                            int(decide32), _p(_f64(obs_depth)), _p(_f64(obs_rgb)), ctypes.byref(w),
+                            _p(out["depth"]), _p(out["rgb"]), _p(out["mask"]), _p(out.get("J")),
+                            _p(out["resid"]), _p(out["rowmask"]), _p(out["neq"]))
+    return out
+
+
+def track_p2(cam: Cam, pose, pose_prev, obs_depth, obs_rgb, anchor: Dict[str, np.ndarray],
+             params: Params, decide32: bool = True, want_J: bool = False) -> Dict[str, np.ndarray]:
+    """P2: prediction-to-observation residuals against the previous render."""
+    lib = _load()
+    H, W = cam.height, cam.width
+    out = dict(neq=_neq_out(), resid=np.zeros((H, W, 4)), rowmask=np.zeros((H, W), np.uint8))
+    if want_J:
+        out["J"] = np.zeros((H, W, 4, 6))
+    c, w = cam.c(), params.weights()
+    lib.orc_track_p2(ctypes.byref(c), _p(_f64(pose)), _p(_f64(pose_prev)), int(decide32),
+                     _p(_f64(obs_depth)), _p(_f64(obs_rgb)), _p(_f64(anchor["depth"])),
+                     _p(_f64(anchor["rgb"])), _p(np.ascontiguousarray(anchor["mask"], np.uint8)),
+                     _p(_f64(anchor["normals"])), _p(np.ascontiguousarray(anchor["nmask"], np.uint8)),
+                     ctypes.byref(w), _p(out.get("J")), _p(out["resid"]), _p(out["rowmask"]),
+                     _p(out["neq"]))
+    return out
+
+
+def map_update(grid: Grid, mean: np.ndarray, var: np.ndarray, cam: Cam, pose, obs_depth, obs_rgb,
+               params: Params, decide32: bool = True, want_mask: bool = False):
+    """App. D closed-form update, in place on (mean, var).  Returns the count
+    of updated voxels (and the per-voxel flag if asked)."""
+    lib = _load()
+    assert mean.dtype == np.float64 and mean.flags.c_contiguous
+    assert var.dtype == np.float64 and var.flags.c_contiguous
+    upd = np.zeros(mean.shape[1:], np.uint8) if want_mask else None
+    g, c = grid.c(), cam.c()
+    trunc = params.trunc_voxels * grid.voxel
+    n = lib.orc_map_update(ctypes.byref(g), _p(mean), _p(var), ctypes.byref(c), _p(_f64(pose)),
+                           int(decide32), _p(_f64(obs_depth)), _p(_f64(obs_rgb)), trunc,
+                           1.0 / params.sigma_update ** 2, _p(upd))
+    return (int(n), upd) if want_mask else int(n)
+
+
+def render_vjp(grid: Grid, mean, cam: Cam, pose, g_depth, g_rgb, decide32: bool = True):
+    """Adjoint of render: (dL/dmean [4][N][N][N], dL/ddelta [6])."""
+    lib = _load()
+    mean = _f64(mean)
+    gm = np.zeros_like(mean)
+    gp = np.zeros(6)
+    g, c = grid.c(), cam.c()
+    lib.orc_render_vjp(ctypes.byref(g), _p(mean), ctypes.byref(c), _p(_f64(pose)), int(decide32),
+                       _p(_f64(g_depth)), _p(_f64(g_rgb)), _p(gm), _p(gp))
+    return gm, gp
+
+
+# ---------------------------------------------------------------------------
+# rotations (NumPy float64)
+# ---------------------------------------------------------------------------
+def skew(v):
+    return np.array([[0.0, -v[2], v[1]], [v[2], 0.0, -v[0]], [-v[1], v[0], 0.0]])
+
+
+def so3_exp(phi) -> np.ndarray:
+    """Rodrigues' formula."""
+    phi = np.asarray(phi, float)
+    th = np.linalg.norm(phi)
+    K = skew(phi)
+    if th < 1e-8:
+        return np.eye(3) + K + 0.5 * K @ K
+    return np.eye(3) + math.sin(th) / th * K + (1 - math.cos(th)) / th ** 2 * K @ K
+
+
+def so3_log(R) -> np.ndarray:
+    c = (np.trace(R) - 1.0) / 2.0
+    c = min(1.0, max(-1.0, c))
+    th = math.acos(c)
+    w = np.array([R[2, 1] - R[1, 2], R[0, 2] - R[2, 0], R[1, 0] - R[0, 1]])
+    if th < 1e-8:
+        return 0.5 * w
+    if math.pi - th < 1e-6:
+        # near pi: axis from the symmetric part
+        A = (R + np.eye(3)) / 2.0
+        ax = A[:, int(np.argmax(np.diag(A)))]
+        ax = ax / np.linalg.norm(ax)
+        return th * ax
+    return th / (2.0 * math.sin(th)) * w
+
+
+def so3_left_jacobian(phi) -> np.ndarray:
+    """J_l(phi) with Exp(phi + d) ~= Exp(J_l(phi) d) Exp(phi)."""
+    phi = np.asarray(phi, float)
+    th = np.linalg.norm(phi)
+    K = skew(phi)
+    if th < 1e-6:
+        return np.eye(3) + 0.5 * K + K @ K / 6.0
+    return (np.eye(3) + (1 - math.cos(th)) / th ** 2 * K + (th - math.sin(th)) / th ** 3 * K @ K)
+
+
+def quat_to_rot(q) -> np.ndarray:
+    w, x, y, z = np.asarray(q, float) / np.linalg.norm(q)
+    return np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+        [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+        [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def rot_to_quat(R) -> np.ndarray:
+    """Rotation matrix to a unit quaternion with w >= 0 (branch on the largest
+    diagonal term for stability)."""
+    t = np.trace(R)
+    if t > 0:
+        s = 2.0 * math.sqrt(t + 1.0)
+        q = np.array([0.25 * s, (R[2, 1] - R[1, 2]) / s, (R[0, 2] - R[2, 0]) / s, (R[1, 0] - R[0, 1]) / s])
+    else:
+        i = int(np.argmax(np.diag(R)))
+        j, k = (i + 1) % 3, (i + 2) % 3
+        s = 2.0 * math.sqrt(1.0 + R[i, i] - R[j, j] - R[k, k])
+        q = np.zeros(4)
+        q[0] = (R[k, j] - R[j, k]) / s
+        q[1 + i] = 0.25 * s
+        q[1 + j] = (R[j, i] + R[i, j]) / s
+        q[1 + k] = (R[k, i] + R[i, k]) / s
+    if q[0] < 0:
+        q = -q
+    return q / np.linalg.norm(q)
+
+
+def retract(pose: np.ndarray, delta: np.ndarray) -> np.ndarray:
+    """Pose perturbation: t <- t + dt (world), R <- Exp(dtheta) R (left, world)."""
+    t = pose[:3] + delta[:3]
+    R = so3_exp(delta[3:]) @ quat_to_rot(pose[3:])
+    return np.concatenate([t, rot_to_quat(R)])
+
+
+def pose_error(pose: np.ndarray, ref: np.ndarray) -> np.ndarray:
+    """Tangent of `pose` relative to `ref`: (t - t_ref, Log(R R_ref^T))."""
+    return np.concatenate([pose[:3] - ref[:3],
+                           so3_log(quat_to_rot(pose[3:]) @ quat_to_rot(ref[3:]).T)])
+
+
+# ---------------------------------------------------------------------------
+# linear-Gaussian state filter (App. E)
+# ---------------------------------------------------------------------------
+def neq_unpack(neq: np.ndarray) -> Tuple[np.ndarray, np.ndarray, float, float]:
+    """29-vector -> (H 6x6 symmetric, g 6, cost, count)."""
+    H = np.zeros((6, 6))
+    q = 0
+    for a in range(6):
+        for b in range(a, 6):
+            H[a, b] = H[b, a] = neq[q]
+            q += 1
+    return H, np.array(neq[21:27]), float(neq[27]), float(neq[28])
+
+
+def transition_mean(x: Dict[str, np.ndarray], u: np.ndarray, dt: float) -> Dict[str, np.ndarray]:
+    """Euler integration (App. B / E.1): velocity first, then the pose with the
+    *new* velocity.  Reading: v' = v + u dt (the printed (dt)^2 is read as a
+    typo for an acceleration control)."""
+    v = x["v"] + u[:3] * dt
+    w = x["w"] + u[3:] * dt
+    t = x["t"] + v * dt
+    R = so3_exp(w * dt) @ quat_to_rot(x["q"])
+    return dict(t=t, q=rot_to_quat(R), v=v, w=w)
+
+
+def transition_jacobians(x_new: Dict[str, np.ndarray], dt: float):
+    """First-order error-state transition (App. E.1 linearisation) for the
+    tangent (dt, dtheta, dv, dw): returns M (12x12, old error -> new error)
+    and G (12x12, noise (n_t, n_theta, n_v, n_w) -> new error)."""
+    I = np.eye(3)
+    phi = x_new["w"] * dt
+    E = so3_exp(phi)
+    Jl = so3_left_jacobian(phi)
+    M = np.zeros((12, 12))
+    M[0:3, 0:3] = I
+    M[0:3, 6:9] = dt * I
+    M[3:6, 3:6] = E
+    M[3:6, 9:12] = dt * Jl
+    M[6:9, 6:9] = I
+    M[9:12, 9:12] = I
+    G = np.zeros((12, 12))
+    G[0:3, 0:3] = I
+    G[0:3, 6:9] = dt * I
+    G[3:6, 3:6] = I
+    G[3:6, 9:12] = dt * Jl
+    G[6:9, 6:9] = I
+    G[9:12, 9:12] = I
+    return M, G
+
+
+def predict(x: Dict[str, np.ndarray], P: np.ndarray, u: np.ndarray, p: Params):
+    """Closed-form propagation of the Gaussian state belief through the
+    linearised transition (App. E.2): returns the prior mean and covariance."""
+    xn = transition_mean(x, u, p.dt)
+    M, G = transition_jacobians(xn, p.dt)
+    Qd = np.diag([p.sigma_pose_t ** 2] * 3 + [p.sigma_pose_r ** 2] * 3 +
+                 [p.sigma_vel_t ** 2] * 3 + [p.sigma_vel_r ** 2] * 3)
+    Pn = M @ P @ M.T + G @ Qd @ G.T
+    return xn, 0.5 * (Pn + Pn.T)
+
+
+def split(P: np.ndarray):
+    """Split a joint Gaussian over (pose, velocity) into the pose marginal and
+    the linear-Gaussian velocity conditional N(v; mu_v + D (pose - mu_p), S)."""
+    Spp = P[:6, :6]
+    Svp = P[6:, :6]
+    Svv = P[6:, 6:]
+    D = np.linalg.solve(Spp, Svp.T).T          # Svp Spp^-1 (Spp symmetric)
+    S = Svv - D @ Svp.T
+    return Spp, D, 0.5 * (S + S.T)
+
+
+def gn_solve(neq: np.ndarray, Lp: np.ndarray, e_p: np.ndarray) -> np.ndarray:
+    """One Gauss-Newton step on  sum w r^2 + 1/2 e^T Lp e :
+    (2 H + Lp) delta = -(2 g + Lp e)."""
+    H, g, _, _ = neq_unpack(neq)
+    A = 2.0 * H + Lp
+    b = -(2.0 * g + Lp @ e_p)
+    L = np.linalg.cholesky(A)
+    return np.linalg.solve(L.T, np.linalg.solve(L, b))
+
+
+def laplace(neq: np.ndarray, Lp: np.ndarray) -> np.ndarray:
+    """Laplace covariance at the MAP pose, Hessian from the squared Jacobian of
+    the full objective including the dynamics prior: (2 H + Lp)^-1."""
+    H, _, _, _ = neq_unpack(neq)
+    A = 2.0 * H + Lp
+    Ai = np.linalg.inv(A)
+    return 0.5 * (Ai + Ai.T)
+
+
+def combine(pose_post: np.ndarray, S_pose: np.ndarray, prior_pose: np.ndarray, mu_v: np.ndarray,
+            D: np.ndarray, S_v: np.ndarray):
+    """Product of the pose posterior N(m, S_pose) with the velocity
+    conditional: velocity mean mu_v + D e (e = posterior offset from the prior
+    pose) and the joint covariance [[S, S D^T], [D S, S_v + D S D^T]]."""
+    e = pose_error(pose_post, prior_pose)
+    v_mean = mu_v + D @ e
+    P = np.zeros((12, 12))
+    P[:6, :6] = S_pose
+    P[:6, 6:] = S_pose @ D.T
+    P[6:, :6] = D @ S_pose
+    P[6:, 6:] = S_v + D @ S_pose @ D.T
+    return v_mean, 0.5 * (P + P.T)
+
+
+# ---------------------------------------------------------------------------
+# the filter (Sec. 3.3)
+# ---------------------------------------------------------------------------
+@dataclass
+class FilterState:
+    t: np.ndarray
+    q: np.ndarray
+    v: np.ndarray
+    w: np.ndarray
+    P: np.ndarray                      # 12x12 covariance, tangent (dt, dth, dv, dw)
+    Sbar: Optional[np.ndarray] = None  # EMA of Laplace pose covariances
+    step: int = 0
+    anchor: Optional[Dict[str, np.ndarray]] = None
+    anchor_pose: Optional[np.ndarray] = None
+    last: Dict = field(default_factory=dict)
+
+    @property
+    def pose(self) -> np.ndarray:
+        return np.concatenate([self.t, self.q])
+
+
+class Filter:
+    """FP64 reference of one agent's PRISM filter: map belief (dense mean and
+    variance) plus the Gaussian state belief."""
+
+    def __init__(self, grid: Grid, cam: Cam, params: Params, x0: Dict[str, np.ndarray],
+                 P0: np.ndarray, mean: np.ndarray, var: np.ndarray, decide32: bool = True):
+        self.grid, self.cam, self.p = grid, cam, params
+        self.mean = _f64(mean).copy()
+        self.var = _f64(var).copy()
+        self.decide32 = decide32
+        self.s = FilterState(t=_f64(x0["t"]).copy(), q=_f64(x0["q"]).copy(),
+                             v=_f64(x0["v"]).copy(), w=_f64(x0["w"]).copy(), P=_f64(P0).copy())
+
+    def _observe_and_anchor(self, pose, depth, rgb):
+        """Map update at the current mean (App. C nominal state), then render
+        the next anchor from the updated map at that mean."""
+        n = map_update(self.grid, self.mean, self.var, self.cam, pose, depth, rgb, self.p,
+                       self.decide32)
+        a = render(self.grid, self.mean[0:4], self.cam, pose, self.decide32, normals=True,
+                   normal_disc=self.p.normal_disc)
+        self.s.anchor = a
+        self.s.anchor_pose = pose.copy()
+        self.s.last["n_updated"] = n
+
+    def step(self, depth: np.ndarray, rgb: np.ndarray, u: Optional[np.ndarray]) -> FilterState:
+        s, p = self.s, self.p
+        if s.step == 0:
+            self._observe_and_anchor(s.pose, depth, rgb)
+            s.step += 1
+            return s
+        # predict and split (App. E.1-E.2)
+        xn, Pm = predict(dict(t=s.t, q=s.q, v=s.v, w=s.w), s.P, u, p)
+        prior = np.concatenate([xn["t"], xn["q"]])
+        Spp, D, Sv = split(Pm)
+        Lp = np.linalg.inv(Spp)
+        Lp = 0.5 * (Lp + Lp.T)
+        # MAP pose by Gauss-Newton from the prior mean (Sec. 3.3.2)
+        it = prior.copy()
+        for _ in range(p.n_gn):
+            neq = self._objective(it, depth, rgb)
+            delta = gn_solve(neq, Lp, pose_error(it, prior))
+            it = retract(it, delta)
+        neq = self._objective(it, depth, rgb)
+        S_lap = laplace(neq, Lp)
+        s.Sbar = S_lap if s.Sbar is None else p.ema * s.Sbar + (1.0 - p.ema) * S_lap
+        vel_prior = np.concatenate([xn["v"], xn["w"]])
+        v_mean, P = combine(it, s.Sbar, prior, vel_prior, D, Sv)
+        s.t, s.q = it[:3].copy(), it[3:].copy()
+        s.v, s.w = v_mean[:3].copy(), v_mean[3:].copy()
+        s.P = P
+        s.last.update(neq=neq, S_lap=S_lap, prior=prior)
+        # map filter with the current state mean, then the next anchor
+        self._observe_and_anchor(it, depth, rgb)
+        s.step += 1
+        return s
+
+    def _objective(self, pose, depth, rgb):
+        if self.p.objective == "p1":
+            return render_jacobian(self.grid, self.mean, self.cam, pose, depth, rgb, self.p,
+                                   self.decide32)["neq"]
+        return track_p2(self.cam, pose, self.s.anchor_pose, depth, rgb, self.s.anchor, self.p,
+                        self.decide32)["neq"]

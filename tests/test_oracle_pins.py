@@ -1,0 +1,678 @@
+"""Pins of the FP64 oracle against things other than itself: closed forms,
+library routines, brute force on tiny inputs and finite differences.
+
+Each test names the passage of the paper (Mirchev et al., PRISM, CoRL 2022)
+whose statement it pins.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.ndimage as ndi
+from scipy.spatial.transform import Rotation
+
+import synth
+
+
+def _pose(t, R):
+    q = Rotation.from_matrix(R).as_quat()        # (x, y, z, w)
+    return np.array([t[0], t[1], t[2], q[3], q[0], q[1], q[2]])
+
+
+def _look_rot(fwd, up=(0, 0, 1)):
+    """Camera->world rotation (x right, y down, z forward)."""
+    f = np.asarray(fwd, float) / np.linalg.norm(fwd)
+    r = np.cross(f, np.asarray(up, float))
+    r /= np.linalg.norm(r)
+    d = np.cross(f, r)
+    return np.stack([r, d, f], axis=1)
+
+
+def _affine_map(n, voxel, nrm, p0, A, b, occ_out=-0.001):
+    """Dense [4][n][n][n] map with occupancy n.(p - p0) and colour A p + b."""
+    ax = (np.arange(n) + 0.5) * voxel
+    z, y, x = np.meshgrid(ax, ax, ax, indexing="ij")
+    P = np.stack([x, y, z], -1)
+    m = np.empty((4, n, n, n))
+    m[0] = (P - p0) @ nrm
+    m[1:] = np.moveaxis(P @ A.T + b, -1, 0)
+    return m
+
+
+# ---------------------------------------------------------------------------
+# App. B emission
+# ---------------------------------------------------------------------------
+def test_render_affine_plane_is_exact(orc):
+    """Trilinear interpolation reproduces affine fields, and along a ray an
+    affine occupancy is affine in depth, so the interpolated crossing
+    (App. B depth-interpolation eq.) is the exact ray/plane intersection and
+    the blended colour is the colour field at that point."""
+    rng = np.random.default_rng(3)
+    n, s = 24, 0.1
+    nrm = np.array([0.9, 0.3, -0.2]); nrm /= np.linalg.norm(nrm)
+    cam_t = np.array([1.0, 1.2, 1.1])
+    p0 = cam_t + 0.55 * nrm
+    A = rng.normal(size=(3, 3)) * 0.3
+    b = rng.normal(size=3)
+    mean = _affine_map(n, s, nrm, p0, A, b)
+    R = _look_rot(nrm + np.array([0.1, -0.2, 0.05]))
+    pose = _pose(cam_t, R)
+    cam = orc.Cam(16, 12, 12.0, 12.0, 8.0, 6.0, 0.05, 0.95, 24)
+    grid = orc.Grid(n, s)
+    out = orc.render(grid, mean, cam, pose, decide32=False)
+    checked = 0
+    for v in range(cam.height):
+        for u in range(cam.width):
+            rc = np.array([(u + 0.5 - cam.cx) / cam.fx, (v + 0.5 - cam.cy) / cam.fy, 1.0])
+            d = R @ rc
+            dex = nrm @ (p0 - cam_t) / (nrm @ d)
+            ds = cam.d_near + np.arange(cam.n_samples) * (cam.d_far - cam.d_near) / (cam.n_samples - 1)
+            kx = int(np.argmax(ds > dex))
+            pts = cam_t + ds[:kx + 1, None] * d
+            g = pts / s - 0.5
+            if not (np.all(g >= 0) and np.all(g <= n - 1) and kx >= 1 and ds[-1] > dex):
+                continue
+            checked += 1
+            assert out["mask"][v, u] == 1
+            assert out["hit_k"][v, u] == kx
+            assert abs(out["depth"][v, u] - dex) < 1e-12
+            np.testing.assert_allclose(out["rgb"][v, u], A @ (cam_t + dex * d) + b, atol=1e-12)
+    assert checked > 100
+
+
+def _brute_render(mean, n, s, occ_out, rgb_out, cam, t, R, tau=0.0):
+    """Independent first-crossing search with scipy's linear interpolation
+    (map_coordinates order 1, constant padding)."""
+    H, W, K = cam.height, cam.width, cam.n_samples
+    ds = cam.d_near + np.arange(K) * (cam.d_far - cam.d_near) / (K - 1)
+    depth = np.zeros((H, W)); rgb = np.zeros((H, W, 3)); mask = np.zeros((H, W), np.uint8)
+    hit = np.full((H, W), -1)
+    for v in range(H):
+        for u in range(W):
+            rc = np.array([(u + 0.5 - cam.cx) / cam.fx, (v + 0.5 - cam.cy) / cam.fy, 1.0])
+            pts = t + ds[:, None] * (R @ rc)
+            coords = (pts / s - 0.5)[:, ::-1].T           # (k, j, i) order
+            f = ndi.map_coordinates(mean[0], coords, order=1, mode="grid-constant", cval=occ_out)
+            above = np.nonzero(f > tau)[0]
+            if len(above) == 0:
+                continue
+            k = above[0]
+            hit[v, u] = k
+            if k == 0:
+                continue
+            col = np.stack([ndi.map_coordinates(mean[c], coords[:, k - 1:k + 1], order=1,
+                                                mode="grid-constant", cval=rgb_out) for c in (1, 2, 3)], -1)
+            a = (tau - f[k - 1]) / (f[k] - f[k - 1])
+            depth[v, u] = a * ds[k] + (1 - a) * ds[k - 1]
+            rgb[v, u] = a * col[1] + (1 - a) * col[0]
+            mask[v, u] = 1
+    return depth, rgb, mask, hit
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_render_matches_bruteforce_tiny(orc, seed):
+    """First sample whose occupancy exceeds tau, strict (App. B); checked on
+    random 4^3 and 6^3 grids against an independent search."""
+    rng = np.random.default_rng(seed)
+    n = 4 + 2 * (seed % 2)
+    s = 0.25
+    mean = rng.uniform(-1, 1, size=(4, n, n, n))
+    mean[0] -= 0.3
+    t = np.array([0.5, 0.5, -0.3]) + rng.normal(0, 0.05, 3)
+    R = Rotation.from_rotvec(rng.normal(0, 0.2, 3)).as_matrix()
+    cam = orc.Cam(7, 5, 5.0, 5.0, 3.5, 2.5, 0.1, 1.6, 12)
+    out = orc.render(orc.Grid(n, s), mean, cam, _pose(t, R), decide32=False)
+    d, c, m, k = _brute_render(mean, n, s, -0.001, 0.0, cam, t, R)
+    np.testing.assert_array_equal(out["hit_k"], k)
+    np.testing.assert_array_equal(out["mask"], m)
+    np.testing.assert_allclose(out["depth"], d, atol=1e-12)
+    np.testing.assert_allclose(out["rgb"], c, atol=1e-12)
+    assert m.sum() > 5
+
+
+def test_render_tie_is_not_a_hit(orc):
+    """Occupancy equal to tau does not exceed it: an all-zero map has no hit,
+    in both decision precisions."""
+    n = 8
+    mean = np.zeros((4, n, n, n))
+    cam = orc.Cam(6, 4, 4.0, 4.0, 3.0, 2.0, 0.1, 1.5, 10)
+    g = orc.Grid(n, 0.25, occ_out=0.0)
+    pose = _pose(np.array([1.0, 1.0, 0.2]), np.eye(3))
+    for d32 in (False, True):
+        out = orc.render(g, mean, cam, pose, decide32=d32)
+        assert out["mask"].sum() == 0 and np.all(out["hit_k"] == -1)
+
+
+def test_render_room_matches_raycast(orc):
+    """On the synthetic room (axis-aligned walls, clamped SDF map) the render
+    equals the analytic ray cast wherever the crossing lies in a single
+    wall's affine band; elsewhere (edges) it is within two voxels."""
+    c = synth.single_frame_case(0)
+    scene = c["scene"]
+    mean, _ = synth.gt_map(scene)
+    g = orc.grid_from_scene(scene)
+    cam = orc.cam_from(c["cam"])
+    pose = synth.pose7(c["t_gt"], c["q_gt"])
+    out = orc.render(g, mean, cam, pose, decide32=False)
+    d_ex, _ = synth.raycast(scene, c["cam"], c["t_gt"], c["q_gt"])
+    err = np.abs(out["depth"] - d_ex)[out["mask"] == 1]
+    assert out["mask"].mean() > 0.99
+    assert np.mean(err < 1e-9) > 0.7
+    assert err.max() < 2 * scene.voxel
+
+
+def test_decide32_agrees_with_decide64(orc):
+    """Single-precision decisions change hit samples only where the FP64
+    occupancy is within rounding of tau; depth stays continuous."""
+    c = synth.single_frame_case(1)
+    mean, _ = synth.gt_map(c["scene"])
+    g = orc.grid_from_scene(c["scene"])
+    cam = orc.cam_from(c["cam"])
+    pose = synth.pose7(c["t_init"], c["q_init"])
+    a = orc.render(g, mean, cam, pose, decide32=True)
+    b = orc.render(g, mean, cam, pose, decide32=False)
+    assert np.mean(a["hit_k"] != b["hit_k"]) < 1e-3
+    both = (a["mask"] == 1) & (b["mask"] == 1)
+    np.testing.assert_allclose(a["depth"][both], b["depth"][both], rtol=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# pose Jacobian of the emission (P1) and normal equations
+# ---------------------------------------------------------------------------
+def _retract_np(pose, delta):
+    R = Rotation.from_quat([pose[4], pose[5], pose[6], pose[3]]).as_matrix()
+    R2 = Rotation.from_rotvec(delta[3:]).as_matrix() @ R
+    return _pose(pose[:3] + delta[:3], R2)
+
+
+def test_render_jacobian_finite_differences(orc):
+    """Per-ray d(depth, rgb)/d(delta) against central differences of the
+    render (eps 1e-6, FP64 decisions); rays whose hit sample changes are
+    excluded."""
+    c = synth.single_frame_case(0)
+    mean, _ = synth.gt_map(c["scene"])
+    g = orc.grid_from_scene(c["scene"])
+    cam = orc.cam_from(c["cam"])
+    pose = synth.pose7(c["t_init"], c["q_init"])
+    p = orc.Params()
+    obs = orc.render(g, mean, cam, pose)
+    out = orc.render_jacobian(g, mean, cam, pose, obs["depth"], obs["rgb"], p, decide32=False,
+                              want_J=True)
+    J = out["J"]
+    eps = 1e-6
+    good = 0
+    total = 0
+    for m in range(6):
+        e = np.zeros(6); e[m] = eps
+        a = orc.render(g, mean, cam, _retract_np(pose, e), decide32=False)
+        b = orc.render(g, mean, cam, _retract_np(pose, -e), decide32=False)
+        ok = (a["hit_k"] == b["hit_k"]) & (a["mask"] == 1) & (b["mask"] == 1) & (out["mask"] == 1)
+        fd = np.concatenate([(a["depth"] - b["depth"])[..., None], a["rgb"] - b["rgb"]], -1) / (2 * eps)
+        err = np.abs(fd - J[..., m])[ok]
+        scale = np.maximum(np.abs(J[..., m][ok]), 1e-2)
+        good += np.sum(np.all(err / scale < 1e-4, axis=-1))
+        total += ok.sum()
+    assert total > 0.9 * 6 * cam.width * cam.height
+    assert good / total > 0.99
+
+
+def test_neq_packing(orc):
+    """The 29-vector holds sum w J^T J (upper triangle), sum w J^T r, cost
+    and the contributing-pixel count of the rows that pass the gates."""
+    c = synth.single_frame_case(2)
+    mean, _ = synth.gt_map(c["scene"])
+    g = orc.grid_from_scene(c["scene"])
+    cam = orc.cam_from(c["cam"])
+    p = orc.Params()
+    obs_d, obs_c = synth.raycast(c["scene"], c["cam"], c["t_gt"], c["q_gt"],
+                                 np.random.default_rng(0), 0.01, 0.02)
+    out = orc.render_jacobian(g, mean, cam, synth.pose7(c["t_init"], c["q_init"]), obs_d, obs_c, p,
+                              want_J=True)
+    J, r, rm = out["J"], out["resid"], out["rowmask"]
+    w = np.zeros(r.shape)
+    w[..., 0] = np.where(rm & 1, 1 / p.b_geo ** 2, 0)
+    w[..., 1:] = np.where((rm & 2)[..., None], 1 / p.b_rgb ** 2, 0)
+    Hm = np.einsum("hwr,hwra,hwrb->ab", w, J, J)
+    gv = np.einsum("hwr,hwra,hwr->a", w, J, r)
+    H, gg, cost, cnt = orc.neq_unpack(out["neq"])
+    np.testing.assert_allclose(H, Hm, rtol=1e-10, atol=1e-6)
+    np.testing.assert_allclose(gg, gv, rtol=1e-10, atol=1e-8)
+    assert abs(cost - np.sum(w * r * r)) < 1e-8 * max(1, cost)
+    assert cnt == np.sum(rm > 0)
+    # gating: the rows kept are exactly those within the App. G thresholds
+    valid = (out["mask"] == 1) & (obs_d > 0)
+    np.testing.assert_array_equal((rm & 1) > 0, valid & (np.abs(r[..., 0]) <= p.gate_geo))
+    np.testing.assert_array_equal((rm & 2) > 0, valid & (np.abs(r[..., 1:]).sum(-1) <= p.gate_rgb))
+
+
+def test_known_pose_gives_zero_step(orc):
+    """Observation rendered at the true pose, prior centred there: every
+    residual vanishes, g = 0 and the Gauss-Newton step is 0."""
+    c = synth.single_frame_case(0)
+    mean, _ = synth.gt_map(c["scene"])
+    g = orc.grid_from_scene(c["scene"])
+    cam = orc.cam_from(c["cam"])
+    pose = synth.pose7(c["t_gt"], c["q_gt"])
+    p = orc.Params()
+    obs = orc.render(g, mean, cam, pose)
+    out = orc.render_jacobian(g, mean, cam, pose, obs["depth"], obs["rgb"], p)
+    H, gg, cost, cnt = orc.neq_unpack(out["neq"])
+    assert cnt > 0.9 * cam.width * cam.height
+    assert cost == 0.0 and np.all(gg == 0.0)
+    Lp = np.diag([1 / 0.05 ** 2] * 3 + [1 / 0.02 ** 2] * 3)
+    delta = orc.gn_solve(out["neq"], Lp, np.zeros(6))
+    assert np.all(np.abs(delta) < 1e-15)
+
+
+def test_gn_step_converges_from_perturbation(orc):
+    """From a 2 cm / 1 degree perturbation a few Gauss-Newton steps on the
+    render-through objective recover the pose (expected behaviour)."""
+    c = synth.single_frame_case(0)
+    mean, _ = synth.gt_map(c["scene"])
+    g = orc.grid_from_scene(c["scene"])
+    cam = orc.cam_from(c["cam"])
+    gt = synth.pose7(c["t_gt"], c["q_gt"])
+    p = orc.Params()
+    obs = orc.render(g, mean, cam, gt)
+    prior = synth.pose7(c["t_init"], c["q_init"])
+    Lp = np.diag([1 / 0.05 ** 2] * 3 + [1 / 0.02 ** 2] * 3) * 1e-3
+    it = prior.copy()
+    for _ in range(5):
+        out = orc.render_jacobian(g, mean, cam, it, obs["depth"], obs["rgb"], p)
+        it = orc.retract(it, orc.gn_solve(out["neq"], Lp, orc.pose_error(it, prior)))
+    e0 = np.linalg.norm(orc.pose_error(prior, gt))
+    e1 = np.linalg.norm(orc.pose_error(it, gt))
+    assert e1 < 0.1 * e0
+
+
+# ---------------------------------------------------------------------------
+# P2 surrogate (App. E.3)
+# ---------------------------------------------------------------------------
+def _plane_anchor(orc):
+    n, s = 24, 0.1
+    nrm = np.array([0.2, -0.1, 1.0]); nrm /= np.linalg.norm(nrm)
+    cam_t = np.array([1.2, 1.2, 0.6])
+    p0 = cam_t + 0.9 * nrm
+    mean = _affine_map(n, s, nrm, p0, np.zeros((3, 3)), np.zeros(3))
+    # smooth colour so the photometric term has a gradient
+    ax = (np.arange(n) + 0.5) * s
+    z, y, x = np.meshgrid(ax, ax, ax, indexing="ij")
+    mean[1] = 0.5 + 0.3 * np.sin(3 * x) * np.cos(2 * y)
+    mean[2] = 0.4 + 0.2 * np.cos(4 * y + z)
+    mean[3] = 0.3 + 0.1 * x
+    R = _look_rot(nrm + np.array([0.05, 0.1, 0.0]), up=(0, 1, 0))
+    pose = _pose(cam_t, R)
+    cam = orc.Cam(40, 30, 30.0, 30.0, 20.0, 15.0, 0.1, 1.8, 48)
+    g = orc.Grid(n, s)
+    a = orc.render(g, mean, cam, pose, decide32=False, normals=True)
+    return g, mean, cam, pose, a, nrm, p0
+
+
+def test_p2_identity_has_zero_residuals(orc):
+    """Observation equal to the anchor, current pose equal to the anchor
+    pose: every pixel associates with itself and all residuals vanish."""
+    g, mean, cam, pose, a, _, _ = _plane_anchor(orc)
+    p = orc.Params()
+    for d32 in (False, True):
+        out = orc.track_p2(cam, pose, pose, a["depth"], a["rgb"], a, p, decide32=d32)
+        used = out["rowmask"] > 0
+        assert used.sum() > 0.5 * cam.width * cam.height
+        assert np.max(np.abs(out["resid"][used])) < 1e-12
+
+
+def test_p2_point_to_plane_is_plane_distance(orc):
+    """Against a rendered plane, the point-to-plane residual n.(p_hat - Y)
+    equals the analytic signed distance of the moved point to that plane."""
+    g, mean, cam, pose, a, nrm, p0 = _plane_anchor(orc)
+    p = orc.Params(gate_geo=10.0, gate_rgb=10.0)
+    cur = _retract_np(pose, np.array([0.01, -0.02, 0.015, 0.01, -0.005, 0.008]))
+    rng = np.random.default_rng(0)
+    obs_d = rng.uniform(0.6, 1.2, size=(cam.height, cam.width))
+    obs_c = np.zeros((cam.height, cam.width, 3))
+    out = orc.track_p2(cam, cur, pose, obs_d, obs_c, a, p, decide32=False)
+    Rc = Rotation.from_quat([cur[4], cur[5], cur[6], cur[3]]).as_matrix()
+    Ra = Rotation.from_quat([pose[4], pose[5], pose[6], pose[3]]).as_matrix()
+    n_a = Ra.T @ nrm             # plane normal in the anchor camera frame (towards camera)
+    n_a = -n_a if n_a @ (Ra.T @ (p0 - pose[:3])) > 0 else n_a
+    p0_a = Ra.T @ (p0 - pose[:3])
+    checked = 0
+    for v in range(cam.height):
+        for u in range(cam.width):
+            if not out["rowmask"][v, u] & 1:
+                continue
+            rc = np.array([(u + 0.5 - cam.cx) / cam.fx, (v + 0.5 - cam.cy) / cam.fy, 1.0])
+            Y = Ra.T @ (Rc @ (obs_d[v, u] * rc) + cur[:3] - pose[:3])
+            assert abs(out["resid"][v, u, 0] - n_a @ (p0_a - Y)) < 1e-9
+            checked += 1
+    assert checked > 200
+
+
+def test_p2_jacobian_finite_differences(orc):
+    """P2 residual Jacobian against central differences (eps 1e-7); pixels
+    whose association or gating changes are excluded."""
+    g, mean, cam, pose, a, _, _ = _plane_anchor(orc)
+    p = orc.Params()
+    cur = _retract_np(pose, np.array([0.004, -0.003, 0.002, 0.003, -0.002, 0.002]))
+    obs_d = a["depth"] * 1.001
+    obs_c = a["rgb"] + 0.01
+    out = orc.track_p2(cam, cur, pose, obs_d, obs_c, a, p, decide32=False, want_J=True)
+    eps = 1e-7
+    tot = good = 0
+    for m in range(6):
+        e = np.zeros(6); e[m] = eps
+        A_ = orc.track_p2(cam, _retract_np(cur, e), pose, obs_d, obs_c, a, p, decide32=False)
+        B_ = orc.track_p2(cam, _retract_np(cur, -e), pose, obs_d, obs_c, a, p, decide32=False)
+        ok = (A_["rowmask"] == out["rowmask"]) & (B_["rowmask"] == out["rowmask"])
+        fd = (A_["resid"] - B_["resid"]) / (2 * eps)
+        for row, bit in ((slice(0, 1), 1), (slice(1, 4), 2)):
+            sel = ok & ((out["rowmask"] & bit) > 0)
+            err = np.abs(fd[..., row] - out["J"][..., row, m])[sel]
+            scale = np.maximum(np.abs(out["J"][..., row, m][sel]), 1e-2)
+            good += np.sum(np.all(err / scale < 1e-4, axis=-1))
+            tot += sel.sum()
+    assert tot > 1000 and good / tot > 0.98
+
+
+# ---------------------------------------------------------------------------
+# map update (App. D)
+# ---------------------------------------------------------------------------
+def _frontal_wall(orc, n=16, s=0.1):
+    """Camera looking along +x at a wall x = xw, exact constant z-depth."""
+    cam = orc.Cam(20, 16, 15.0, 15.0, 10.0, 8.0, 0.1, 2.0, 20)
+    t = np.array([0.33, 0.81, 0.79])
+    R = _look_rot([1.0, 0.0, 0.0])
+    xw = 1.17
+    depth = np.full((cam.height, cam.width), xw - t[0])
+    return orc.Grid(n, s), cam, _pose(t, R), depth, t, R
+
+
+def test_map_update_frontal_wall_closed_form(orc):
+    """With an uninformative prior (precision ~0) one update sets each voxel
+    in the update region to max(z - D, -trunc) and the observed colour;
+    voxels outside the region are bitwise unchanged."""
+    g, cam, pose, depth, t, R = _frontal_wall(orc)
+    p = orc.Params()
+    n = g.n
+    rng = np.random.default_rng(0)
+    mean = rng.normal(size=(4, n, n, n))
+    var = np.full((4, n, n, n), 1e300)
+    rgb = np.broadcast_to(np.array([0.2, 0.5, 0.7]), (cam.height, cam.width, 3)).copy()
+    m0, v0 = mean.copy(), var.copy()
+    cnt, upd = orc.map_update(g, mean, var, cam, pose, depth, rgb, p, decide32=False, want_mask=True)
+    trunc = p.trunc_voxels * g.voxel
+    ax = (np.arange(n) + 0.5) * g.voxel
+    Z, Y, X = np.meshgrid(ax, ax, ax, indexing="ij")
+    Pc = (np.stack([X, Y, Z], -1) - t) @ R      # camera-frame coordinates
+    z = Pc[..., 2]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        uu = cam.fx * Pc[..., 0] / z + cam.cx
+        vv = cam.fy * Pc[..., 1] / z + cam.cy
+    inside = (z > 0) & (uu >= 0) & (uu < cam.width) & (vv >= 0) & (vv < cam.height)
+    expect = inside & (z <= depth[0, 0] + trunc)
+    np.testing.assert_array_equal(upd.astype(bool), expect)
+    assert cnt == expect.sum() > 100
+    f = np.maximum(z - depth[0, 0], -trunc)
+    np.testing.assert_allclose(mean[0][expect], f[expect], rtol=0, atol=1e-12)
+    for c in range(3):
+        np.testing.assert_allclose(mean[1 + c][expect], rgb[0, 0, c], atol=1e-12)
+    np.testing.assert_array_equal(mean[:, ~expect], m0[:, ~expect])
+    np.testing.assert_array_equal(var[:, ~expect], v0[:, ~expect])
+
+
+def test_map_update_curless_levoy(orc):
+    """Precision-form product = Curless-Levoy running average (App. D): from
+    a flat prior, after n unit-precision updates the mean is the arithmetic
+    mean of the updates and the precision is n."""
+    g, cam, pose, depth0, t, R = _frontal_wall(orc)
+    p = orc.Params()
+    n = g.n
+    mean = np.zeros((4, n, n, n))
+    var = np.full((4, n, n, n), 1e300)
+    rng = np.random.default_rng(1)
+    fs = []
+    masks = []
+    for i in range(5):
+        dd = depth0 + rng.uniform(-0.02, 0.02)
+        col = rng.uniform(0, 1, 3)
+        rgb = np.broadcast_to(col, (cam.height, cam.width, 3)).copy()
+        _, upd = orc.map_update(g, mean, var, cam, pose, dd, rgb, p, decide32=False, want_mask=True)
+        masks.append(upd.astype(bool))
+        fs.append((dd[0, 0], col))
+    allm = np.logical_and.reduce(masks)
+    assert allm.sum() > 100
+    trunc = p.trunc_voxels * g.voxel
+    ax = (np.arange(n) + 0.5) * g.voxel
+    Z, Y, X = np.meshgrid(ax, ax, ax, indexing="ij")
+    z = ((np.stack([X, Y, Z], -1) - t) @ R)[..., 2]
+    f_mean = np.mean([np.maximum(z - D, -trunc) for D, _ in fs], axis=0)
+    np.testing.assert_allclose(mean[0][allm], f_mean[allm], atol=1e-12)
+    np.testing.assert_allclose(mean[1][allm], np.mean([c[0] for _, c in fs]), atol=1e-12)
+    np.testing.assert_allclose(1.0 / var[:, allm], 5.0, rtol=1e-12)
+
+
+def test_map_update_precision_sum(orc):
+    """Two Gaussians multiply to precision Lambda + Lambda_u and a precision-
+    weighted mean (App. D); checked against the covariance form of the
+    product, sigma'^2 = s1 s2 / (s1 + s2), mu' = (s2 mu1 + s1 mu2)/(s1+s2)."""
+    g, cam, pose, depth, t, R = _frontal_wall(orc)
+    p = orc.Params(sigma_update=0.7)
+    n = g.n
+    rng = np.random.default_rng(5)
+    mean = rng.normal(size=(4, n, n, n))
+    var = rng.uniform(0.1, 3.0, size=(4, n, n, n))
+    m0, v0 = mean.copy(), var.copy()
+    rgb = rng.uniform(0, 1, size=(cam.height, cam.width, 3))
+    _, upd = orc.map_update(g, mean, var, cam, pose, depth, rgb, p, decide32=False, want_mask=True)
+    u = upd.astype(bool)
+    s2 = p.sigma_update ** 2
+    trunc = p.trunc_voxels * g.voxel
+    ax = (np.arange(n) + 0.5) * g.voxel
+    Z, Y, X = np.meshgrid(ax, ax, ax, indexing="ij")
+    z = ((np.stack([X, Y, Z], -1) - t) @ R)[..., 2]
+    f0 = np.maximum(z - depth[0, 0], -trunc)
+    np.testing.assert_allclose(var[:, u], v0[:, u] * s2 / (v0[:, u] + s2), rtol=1e-12)
+    np.testing.assert_allclose(mean[0][u], (s2 * m0[0][u] + v0[0][u] * f0[u]) / (v0[0][u] + s2),
+                               rtol=1e-10, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# adjoint of the emission
+# ---------------------------------------------------------------------------
+def test_render_vjp_finite_differences(orc):
+    """dL/dmean and dL/ddelta of L = sum(gd * depth + gc . rgb), against
+    central differences on a small case (hit samples held; rays whose hit
+    changes under the perturbation are rare and excluded via tolerance)."""
+    rng = np.random.default_rng(0)
+    n, s = 12, 0.2
+    mean = np.empty((4, n, n, n))
+    ax = (np.arange(n) + 0.5) * s
+    Z, Y, X = np.meshgrid(ax, ax, ax, indexing="ij")
+    mean[0] = 0.3 * np.sin(2.1 * X) + 0.25 * np.cos(1.7 * Y + 0.5 * Z) + 0.2 * Z - 0.2
+    mean[1:] = rng.uniform(0, 1, size=(3, n, n, n))
+    t = np.array([1.2, 1.1, 0.3])
+    R = _look_rot([0.1, 0.05, 1.0], up=(0, 1, 0))
+    pose = _pose(t, R)
+    cam = orc.Cam(10, 8, 8.0, 8.0, 5.0, 4.0, 0.1, 1.9, 24)
+    g = orc.Grid(n, s)
+    gd = rng.normal(size=(cam.height, cam.width))
+    gc = rng.normal(size=(cam.height, cam.width, 3))
+    gm, gp = orc.render_vjp(g, mean, cam, pose, gd, gc, decide32=False)
+    base = orc.render(g, mean, cam, pose, decide32=False)
+    assert base["mask"].sum() > 40
+
+    def L(mm, pp):
+        o = orc.render(g, mm, cam, pp, decide32=False)
+        return np.sum(gd * o["depth"]) + np.sum(gc * o["rgb"]), o["hit_k"]
+
+    eps = 1e-6
+    for m in range(6):
+        e = np.zeros(6); e[m] = eps
+        la, ka = L(mean, _retract_np(pose, e))
+        lb, kb = L(mean, _retract_np(pose, -e))
+        assert np.array_equal(ka, kb)
+        assert abs((la - lb) / (2 * eps) - gp[m]) < 1e-5 * max(1.0, abs(gp[m]))
+    idx = np.argwhere(np.abs(gm).sum(0) > 0)
+    assert len(idx) > 50
+    pick = idx[rng.choice(len(idx), size=40, replace=False)]
+    for (k, j, i) in pick:
+        for ch in range(4):
+            mp = mean.copy(); mp[ch, k, j, i] += eps
+            mq = mean.copy(); mq[ch, k, j, i] -= eps
+            la, ka = L(mp, pose)
+            lb, kb = L(mq, pose)
+            if not np.array_equal(ka, kb):
+                continue
+            assert abs((la - lb) / (2 * eps) - gm[ch, k, j, i]) < 1e-6 * max(1.0, abs(gm[ch, k, j, i]))
+
+
+def test_render_vjp_pose_is_jacobian_transpose(orc):
+    """The pose part of the adjoint is J^T g for the per-ray P1 Jacobian."""
+    c = synth.single_frame_case(0)
+    mean, _ = synth.gt_map(c["scene"])
+    g = orc.grid_from_scene(c["scene"])
+    cam = orc.cam_from(c["cam"])
+    pose = synth.pose7(c["t_init"], c["q_init"])
+    p = orc.Params()
+    rng = np.random.default_rng(1)
+    gd = rng.normal(size=(cam.height, cam.width))
+    gc = rng.normal(size=(cam.height, cam.width, 3))
+    out = orc.render_jacobian(g, mean, cam, pose, np.ones((cam.height, cam.width)),
+                              np.zeros((cam.height, cam.width, 3)), p, want_J=True)
+    _, gp = orc.render_vjp(g, mean, cam, pose, gd, gc)
+    ug = np.concatenate([gd[..., None], gc], -1) * (out["mask"][..., None] == 1)
+    np.testing.assert_allclose(gp, np.einsum("hwr,hwrm->m", ug, out["J"]), rtol=1e-10, atol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# linear-Gaussian state filter (App. E)
+# ---------------------------------------------------------------------------
+def _transition_with_noise(orc, x, u, dt, n):
+    """The generative transition of App. B with explicit noise: velocity
+    integration (+ n_v), then pose integration with the new velocity
+    (+ n_t on position, rotation perturbed by Exp(n_theta))."""
+    v = x["v"] + u[:3] * dt + n[6:9]
+    w = x["w"] + u[3:] * dt + n[9:12]
+    t = x["t"] + v * dt + n[0:3]
+    R = (Rotation.from_rotvec(n[3:6]) * Rotation.from_rotvec(w * dt) *
+         Rotation.from_quat([x["q"][1], x["q"][2], x["q"][3], x["q"][0]])).as_matrix()
+    return dict(t=t, R=R, v=v, w=w)
+
+
+def _err(a, b):
+    return np.concatenate([a["t"] - b["t"], Rotation.from_matrix(a["R"] @ b["R"].T).as_rotvec(),
+                           a["v"] - b["v"], a["w"] - b["w"]])
+
+
+def test_transition_linearisation_matches_fd(orc):
+    """M and G of the linearised transition (App. E.1) against central
+    differences of the generative transition in the error state."""
+    rng = np.random.default_rng(2)
+    q = Rotation.from_rotvec(rng.normal(size=3)).as_quat()
+    x = dict(t=rng.normal(size=3), q=np.array([q[3], q[0], q[1], q[2]]),
+             v=rng.normal(size=3), w=rng.normal(size=3))
+    u = rng.normal(size=6)
+    dt = 0.1
+    xn = orc.transition_mean(x, u, dt)
+    M, G = orc.transition_jacobians(xn, dt)
+    base = _transition_with_noise(orc, x, u, dt, np.zeros(12))
+    np.testing.assert_allclose(base["t"], xn["t"], atol=1e-14)
+    np.testing.assert_allclose(base["R"], orc.quat_to_rot(xn["q"]), atol=1e-14)
+    eps = 1e-6
+    Mfd = np.zeros((12, 12)); Gfd = np.zeros((12, 12))
+    Rx = Rotation.from_quat([q[0], q[1], q[2], q[3]])
+    for i in range(12):
+        for sgn in (1, -1):
+            d = np.zeros(12); d[i] = sgn * eps
+            R2 = (Rotation.from_rotvec(d[3:6]) * Rx).as_quat()
+            xp = dict(t=x["t"] + d[0:3], q=np.array([R2[3], R2[0], R2[1], R2[2]]),
+                      v=x["v"] + d[6:9], w=x["w"] + d[9:12])
+            Mfd[:, i] += sgn * _err(_transition_with_noise(orc, xp, u, dt, np.zeros(12)), base) / (2 * eps)
+            Gfd[:, i] += sgn * _err(_transition_with_noise(orc, x, u, dt, d), base) / (2 * eps)
+    np.testing.assert_allclose(M, Mfd, atol=1e-7)
+    np.testing.assert_allclose(G, Gfd, atol=1e-7)
+
+
+def _rand_spd(rng, n):
+    A = rng.normal(size=(n, n))
+    return A @ A.T + n * np.eye(n)
+
+
+def test_split_and_combine_are_gaussian_identities(orc):
+    """Marginal x conditional of a joint Gaussian reproduce the joint; the
+    product of a pose posterior with the conditional has that posterior as
+    its pose marginal and the conditional's (D, S) (Sec. 3.3.2, App. E.2)."""
+    rng = np.random.default_rng(4)
+    P = _rand_spd(rng, 12)
+    Spp, D, Sv = orc.split(P)
+    J = np.zeros((12, 12))
+    J[:6, :6] = Spp
+    J[:6, 6:] = Spp @ D.T
+    J[6:, :6] = D @ Spp
+    J[6:, 6:] = Sv + D @ Spp @ D.T
+    np.testing.assert_allclose(J, P, rtol=1e-12, atol=1e-12)
+    # conditional by the Schur complement of the precision matrix
+    Lam = np.linalg.inv(P)
+    np.testing.assert_allclose(Sv, np.linalg.inv(Lam[6:, 6:]), rtol=1e-10)
+    np.testing.assert_allclose(D, -np.linalg.solve(Lam[6:, 6:], Lam[6:, :6]), rtol=1e-10, atol=1e-12)
+    prior = np.array([0.1, 0.2, 0.3, 1.0, 0.0, 0.0, 0.0])
+    post = orc.retract(prior, rng.normal(0, 0.01, 6))
+    S_post = _rand_spd(rng, 6) * 1e-3
+    mu_v = rng.normal(size=6)
+    vm, Pj = orc.combine(post, S_post, prior, mu_v, D, Sv)
+    np.testing.assert_allclose(Pj[:6, :6], S_post, rtol=1e-12)
+    Sv2, D2 = orc.split(Pj)[2], orc.split(Pj)[1]
+    np.testing.assert_allclose(D2, D, rtol=1e-8, atol=1e-10)
+    np.testing.assert_allclose(Sv2, Sv, rtol=1e-8, atol=1e-10)
+    np.testing.assert_allclose(vm, mu_v + D @ orc.pose_error(post, prior), rtol=1e-12)
+
+
+def test_gn_and_laplace_equal_kalman_for_linear_measurements(orc):
+    """For a linear-Gaussian measurement one Gauss-Newton step is the Kalman
+    posterior mean and the Laplace covariance its covariance (Sec. 3.3.2;
+    objective sum w r^2 = Gaussian with variance 1/(2w))."""
+    rng = np.random.default_rng(6)
+    m = 40
+    Jm = rng.normal(size=(m, 6))
+    r0 = rng.normal(size=m)
+    w = rng.uniform(0.5, 3.0, m)
+    neq = np.zeros(29)
+    q = 0
+    for a in range(6):
+        for b in range(a, 6):
+            neq[q] = np.sum(w * Jm[:, a] * Jm[:, b]); q += 1
+    neq[21:27] = (w * r0) @ Jm
+    P0 = _rand_spd(rng, 6) * 0.01
+    Lp = np.linalg.inv(P0)
+    e0 = rng.normal(0, 0.01, 6)
+    delta = orc.gn_solve(neq, Lp, e0)
+    S = orc.laplace(neq, Lp)
+    # Kalman gain form: state x = prior offset, measurement 0 = r0 + J x, R = diag(1/(2w))
+    Rm = np.diag(1.0 / (2 * w))
+    x0 = -e0
+    K = P0 @ Jm.T @ np.linalg.inv(Jm @ P0 @ Jm.T + Rm)
+    x_post = x0 + K @ (-(r0 + Jm @ np.zeros(6)) - Jm @ x0)
+    P_post = P0 - K @ Jm @ P0
+    np.testing.assert_allclose(delta, x_post, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(S, P_post, rtol=1e-9, atol=1e-14)
+
+
+@pytest.mark.slow
+def test_filter_tracks_small_trajectory(orc):
+    """Sanity (not parity): on a short synthetic trajectory (128^3 room,
+    160x120 textured frames) the filter keeps the position error at the
+    centimetre level."""
+    case = synth.trajectory_case(seed=1, n=128, width=160, height=120, n_samples=64, n_frames=12)
+    tr = case["traj"]
+    g = orc.grid_from_scene(case["scene"])
+    cam = orc.cam_from(case["cam"])
+    n = g.n
+    mean = np.zeros((4, n, n, n)); mean[0] = -0.001
+    var = np.full((4, n, n, n), 1e4)
+    x0 = dict(t=tr.t[0], q=tr.q[0], v=tr.v[0], w=tr.w[0])
+    P0 = np.diag([1e-6] * 6 + [1e-4] * 6)
+    f = orc.Filter(g, cam, orc.Params(), x0, P0, mean, var)
+    errs = []
+    for i in range(len(tr.t)):
+        f.step(case["depth"][i], case["rgb"][i], tr.u[i - 1] if i else None)
+        errs.append(np.linalg.norm(f.s.t - tr.t[i]))
+    assert max(errs) < 0.05
