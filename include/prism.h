@@ -1,0 +1,366 @@
+/*
+ * prism.h -- C ABI of the MI355X (gfx950) PRISM filter hot path.
+ *
+ * Paper: A. Mirchev, B. Kayalibay, A. Agha, P. van der Smagt, D. Cremers,
+ * J. Bayer, "PRISM: Probabilistic Real-Time Inference in Spatial World
+ * Models", CoRL 2022 (arXiv 2212.02988).
+ *
+ * The library computes, on one GPU, the data-parallel steps of the paper's
+ * approximate marginal filters:
+ *   - the ray-marching RGB-D emission from the voxel map        (App. B)
+ *   - its 6-DoF pose Jacobian reduced to normal equations       (Sec. 3.3.2)
+ *   - the prediction-to-observation tracking objective          (App. E.3)
+ *   - Gauss-Newton MAP pose, Laplace covariance, linear-Gaussian
+ *     propagation / split / combination of the state belief     (App. E.1-E.3)
+ *   - the closed-form per-voxel Gaussian map update             (App. D)
+ *   - the adjoint of the emission w.r.t. voxel means and pose
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * World frame right-handed.  A pose is 7 doubles (t[3], q[4] = w,x,y,z),
+ * camera -> world: X_w = R(q) X_c + t (q need not be normalised; it is
+ * normalised on use).  Camera frame: x right, y down, z forward.  Pixel
+ * (u, v) has centre (u + 1/2, v + 1/2) and looks along
+ * ((u + 1/2 - cx)/fx, (v + 1/2 - cy)/fy, 1): rendered and observed depths are
+ * z-depths.  Sample k of a ray (k = 0..K-1) is at depth
+ * d_near + k (d_far - d_near)/(K - 1).  A pose perturbation delta =
+ * (dt, dtheta) acts as t <- t + dt, R <- Exp(dtheta) R (world frame); all
+ * Jacobians and covariances are in that tangent.
+ *
+ * The voxel map holds per voxel and channel (occupancy = -SDF, R, G, B) a
+ * Gaussian mean and variance.  Voxel (i, j, k) has its centre at
+ * origin + voxel * (i + 1/2, j + 1/2, k + 1/2).  Trilinear interpolation
+ * uses the 8 surrounding centres; corners outside the grid take the values
+ * occ_out / rgb_out (the paper's first map belief, App. G).
+ *
+ * Memory: the library never allocates device memory.  Every pointer named
+ * "device" must point to device memory the caller owns and keeps alive until
+ * the call's work on `stream` has completed.  Calls are asynchronous on
+ * `stream` (NULL = the default stream); outputs are valid once the stream is
+ * synchronised.  Numeric conditions (no valid pixel, a non positive-definite
+ * system) never fail a call: they are reported in device-side flags.
+ *
+ * Errors: every call returns a prism_status.  Non-zero values leave outputs
+ * untouched and set a thread-local message readable with prism_last_error().
+ */
+#ifndef PRISM_H
+#define PRISM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t prism_status;
+#define PRISM_OK 0
+#define PRISM_INVALID_ARGUMENT 1 /* null pointer, bad size, misaligned buffer */
+#define PRISM_UNSUPPORTED 2      /* dtype / shape outside the supported set */
+#define PRISM_HIP_ERROR 3        /* a HIP runtime call failed (message has the code) */
+
+/* Map storage types. */
+#define PRISM_F32 0
+#define PRISM_BF16 1
+
+/* Device-side flags (prism_filter_state.flags). */
+#define PRISM_FLAG_NO_VALID_PIXELS 1 /* an objective evaluation had no contributing pixel */
+#define PRISM_FLAG_CHOL_FALLBACK 2   /* a normal matrix was not positive definite: the
+                                        pose kept the prior mean and covariance */
+
+/* Objectives for the pose update. */
+#define PRISM_OBJ_P2 0 /* prediction-to-observation surrogate against the previous
+                          render (App. E.3), the paper's objective */
+#define PRISM_OBJ_P1 1 /* render-through likelihood of the current map (Sec. 3.3.2) */
+
+typedef struct {
+    int32_t n;        /* voxels per axis; multiple of 8, 8 <= n <= 1024 */
+    int32_t dtype;    /* PRISM_F32 or PRISM_BF16 (storage of means and variances) */
+    double voxel;     /* voxel edge length (m), > 0 */
+    double origin[3]; /* grid min corner (m) */
+    double occ_out;   /* occupancy of corners outside the grid (paper: -0.001) */
+    double rgb_out;   /* colour of corners outside the grid (paper: 0) */
+} prism_grid;
+
+typedef struct {
+    int32_t width, height; /* pixels, 1..8192 each */
+    double fx, fy, cx, cy; /* pinhole intrinsics (pixels) */
+    double d_near, d_far;  /* first and last sample depth (m), 0 <= d_near < d_far */
+    int32_t n_samples;     /* K samples per ray, 2..4096 */
+    int32_t pad_;
+    double tau; /* hit threshold on occupancy (paper: 0) */
+} prism_camera;
+
+typedef struct {
+    double t[3];
+    double q[4]; /* w, x, y, z */
+} prism_pose;
+
+typedef struct {
+    double w_depth;    /* weight of a depth / point-to-plane row, 1/b_geo^2 */
+    double w_rgb;      /* weight of each colour row, 1/b_rgb^2 */
+    double gate_depth; /* a depth row is dropped if |r| > gate_depth (m) */
+    double gate_rgb;   /* the colour rows are dropped if |r_r|+|r_g|+|r_b| > gate_rgb */
+} prism_weights;
+
+typedef struct {
+    double trunc;      /* truncation distance (m), > 0 */
+    double lam_update; /* update precision 1/sigma_u^2, > 0 */
+} prism_map_params;
+
+/* Normal equations of one frame: 29 doubles
+ *   [0..20]  upper triangle of H = sum_rows w J^T J, row-major (a <= b)
+ *   [21..26] g = sum_rows w J^T r
+ *   [27]     cost sum_rows w r^2
+ *   [28]     number of pixels that contributed at least one row
+ * Rows are the depth (or point-to-plane) row and the three colour rows of a
+ * pixel, each kept or dropped by the gates of prism_weights. */
+#define PRISM_NEQ 29
+
+/* Last error message of the calling thread ("" if none). */
+const char *prism_last_error(void);
+
+/* Library version string. */
+const char *prism_version(void);
+
+/* sizeof() of a public struct given its name ("prism_grid", "prism_camera",
+ * "prism_pose", "prism_weights", "prism_map_params", "prism_filter_cfg",
+ * "prism_filter_state", "prism_frame"); 0 for an unknown name.  Lets
+ * bindings verify their struct mirrors. */
+size_t prism_sizeof(const char *type_name);
+
+/* ------------------------------------------------------------------------ */
+/* Voxel map                                                                */
+/* ------------------------------------------------------------------------ */
+/* The map is one opaque device buffer of prism_map_bytes() bytes: eight
+ * planes (mean occupancy, mean R, G, B, then the four variances) of n^3
+ * values of the grid's dtype, each plane in 8x8x8-brick order.  Use
+ * prism_map_from_dense / prism_map_to_dense to exchange it with the dense
+ * layout [4][n][n][n] (channel, z, y, x; x fastest). */
+
+/* Bytes of a map of this grid (App. D map belief: mean and variance per
+ * voxel and channel).  Fails on an unsupported grid. */
+prism_status prism_map_bytes(const prism_grid *grid, size_t *bytes);
+
+/* Sets every voxel to (occ0, rgb0, rgb0, rgb0) with variance var0 in all
+ * four channels (App. B/G first map belief: occupancy -0.001, colour 0,
+ * broad variance).  map: device, prism_map_bytes() bytes, 256-byte aligned. */
+prism_status prism_map_init(const prism_grid *grid, void *map, float occ0, float rgb0, float var0,
+                            hipStream_t stream);
+
+/* Dense FP32 [4][n][n][n] means and variances (device) -> map.  BF16 maps
+ * round to nearest-even.  Either of mean4 / var4 may be NULL to leave that
+ * half untouched. */
+prism_status prism_map_from_dense(const prism_grid *grid, void *map, const float *mean4,
+                                  const float *var4, hipStream_t stream);
+
+/* map -> dense FP32 [4][n][n][n] (device); either output may be NULL. */
+prism_status prism_map_to_dense(const prism_grid *grid, const void *map, float *mean4, float *var4,
+                                hipStream_t stream);
+
+/* FP32 [c][n^3] brick-ordered planes <-> dense [c][n][n][n] (device), for
+ * gradients of the map means (see prism_render_vjp). */
+prism_status prism_bricks_to_dense(int32_t n, int32_t channels, const float *bricks, float *dense,
+                                   hipStream_t stream);
+prism_status prism_dense_to_bricks(int32_t n, int32_t channels, const float *dense, float *bricks,
+                                   hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Emission (App. B)                                                        */
+/* ------------------------------------------------------------------------ */
+/* Renders n_frames RGB-D frames from the map means.  Per pixel ray: the
+ * occupancy at the K samples by trilinear interpolation; the first sample k*
+ * whose occupancy exceeds tau; alpha = (tau - f(k*-1)) / (f(k*) - f(k*-1));
+ * depth = alpha d(k*) + (1 - alpha) d(k*-1) and colour the same blend of the
+ * two samples' interpolated colours (App. B, depth-interpolation equation;
+ * colour "analogously").  A ray without a crossing, or whose first sample is
+ * already occupied (k* = 0), is invalid: depth 0, rgb 0, mask 0.
+ *
+ * poses:   device, n_frames prism_pose.
+ * depth:   device [n_frames][H][W] float.      rgb: [n_frames][H][W][3] float.
+ * mask:    device [n_frames][H][W] uint8 (1 = valid).
+ * hit_k:   nullable, device [n_frames][H][W] int32: k*, or -1 without crossing.
+ * normals: nullable, device [n_frames][H][W][3] float, camera frame, with
+ * nmask:   (required iff normals) [n_frames][H][W] uint8: normal of the
+ *          rendered depth image by central differences of the back-projected
+ *          points, oriented towards the camera; 0 on the border, next to an
+ *          invalid pixel or where a neighbour's depth differs by more than
+ *          normal_disc metres (App. E.3 anchor normals; App. G discontinuous
+ *          depth ignored). */
+prism_status prism_render(const prism_grid *grid, const void *map, const prism_camera *cam,
+                          const prism_pose *poses, int32_t n_frames, float *depth, float *rgb,
+                          uint8_t *mask, int32_t *hit_k, float *normals, uint8_t *nmask,
+                          double normal_disc, hipStream_t stream);
+
+/* Workspace bytes needed by prism_render_jacobian / prism_track_p2 /
+ * prism_render_vjp for n_frames frames of this camera. */
+prism_status prism_reduce_workspace_bytes(const prism_camera *cam, int32_t n_frames, size_t *bytes);
+
+/* Render-through (P1) pose Jacobian and normal equations (Sec. 3.3.2 MAP
+ * objective with the emission likelihood): for every valid ray, the 4x6
+ * derivative of (depth, r, g, b) w.r.t. delta with k* held fixed; residuals
+ * r = rendered - observed; rows gated and weighted by `w`; per frame the
+ * 29-double normal equations (see PRISM_NEQ).  A pixel contributes only if
+ * its ray is valid and its observed depth is finite and > 0.
+ *
+ * obs_depth: device [n][H][W] float;  obs_rgb: device [n][H][W][3] float.
+ * depth/rgb/mask: nullable outputs as in prism_render.
+ * J:      nullable, device [n][H][W][4][6] float (0 for pixels that do not
+ *         contribute).  resid: nullable [n][H][W][4] float.
+ * rowmask: nullable [n][H][W] uint8, bit0 depth row kept, bit1 colour rows kept.
+ * neq:    device [n][29] double.
+ * workspace: device, >= prism_reduce_workspace_bytes(cam, n) bytes. */
+prism_status prism_render_jacobian(const prism_grid *grid, const void *map,
+                                   const prism_camera *cam, const prism_pose *poses,
+                                   int32_t n_frames, const float *obs_depth, const float *obs_rgb,
+                                   const prism_weights *w, float *depth, float *rgb, uint8_t *mask,
+                                   float *J, float *resid, uint8_t *rowmask, double *neq,
+                                   void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Prediction-to-observation objective (App. E.3, P2) for one frame: each
+ * observed pixel with valid depth D is back-projected (D r_c), moved by the
+ * pose iterate `pose` and brought into the camera of `pose_prev` (the pose the
+ * anchor frame was rendered at).  Geometric row: point-to-plane residual
+ * n.(p - Y) with the nearest anchor pixel's back-projected point p and normal
+ * n (requires a valid anchor pixel and normal).  Colour rows: anchor colour
+ * bilinearly interpolated at the projection minus the observed colour
+ * (requires the 4 taps valid).  Derivatives w.r.t. delta of `pose`; gating,
+ * weights and outputs as in prism_render_jacobian (n_frames = 1).
+ * anchor_*: device buffers as produced by prism_render (+ normals). */
+prism_status prism_track_p2(const prism_camera *cam, const prism_pose *pose,
+                            const prism_pose *pose_prev, const float *obs_depth,
+                            const float *obs_rgb, const float *anchor_depth,
+                            const float *anchor_rgb, const uint8_t *anchor_mask,
+                            const float *anchor_normals, const uint8_t *anchor_nmask,
+                            const prism_weights *w, float *J, float *resid, uint8_t *rowmask,
+                            double *neq, void *workspace, size_t workspace_bytes,
+                            hipStream_t stream);
+
+/* Adjoint of prism_render w.r.t. the map means and the pose (k* of each ray
+ * held fixed, as given in hit_k from the forward render of the same map and
+ * poses).  Given upstream gradients of depth and rgb:
+ *   grad_mean += dL/dmean, FP32 [4][n^3] in brick order (the first four planes
+ *                of an FP32 map; prism_bricks_to_dense converts);
+ *   grad_pose  = dL/ddelta per frame, device [n_frames][6] double.
+ * The map must be FP32.  Scatter into grad_mean uses atomic adds (order of
+ * additions, hence the last bits, may vary between runs). */
+prism_status prism_render_vjp(const prism_grid *grid, const void *map, const prism_camera *cam,
+                              const prism_pose *poses, int32_t n_frames, const int32_t *hit_k,
+                              const float *g_depth, const float *g_rgb, float *grad_mean,
+                              double *grad_pose, void *workspace, size_t workspace_bytes,
+                              hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Map update (App. D)                                                      */
+/* ------------------------------------------------------------------------ */
+/* Closed-form update of the map belief with one RGB-D frame at `pose`: every
+ * voxel whose centre has camera depth z > 0, projects into the image at pixel
+ * (floor(u), floor(v)) with observed depth D finite and > 0, and z <= D +
+ * trunc, is multiplied per channel by the update Gaussian
+ * N(f, 1/lam_update), f = (max(z - D, -trunc), observed rgb):
+ *   lambda' = 1/var + lam_update,  mean' = (mean/var + lam_update f)/lambda',
+ *   var' = 1/lambda'.  Other voxels are left bitwise unchanged.
+ * pose: device.  obs_depth [H][W], obs_rgb [H][W][3]: device float.
+ * n_updated: nullable, device int64: receives the number of updated voxels. */
+prism_status prism_map_update(const prism_grid *grid, void *map, const prism_camera *cam,
+                              const prism_pose *pose, const float *obs_depth,
+                              const float *obs_rgb, const prism_map_params *p,
+                              int64_t *n_updated, hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Filter (Sec. 3.3; App. C, E)                                             */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    prism_grid grid;
+    prism_camera cam;
+    double dt;                          /* frame interval (s) */
+    double sigma_vel_t, sigma_vel_r;    /* transition scales per step (App. G table) */
+    double sigma_pose_t, sigma_pose_r;
+    prism_weights w;                    /* residual weights and gates (App. G) */
+    double ema;                         /* EMA coefficient of Laplace covariances (0.8) */
+    int32_t n_gn;                       /* Gauss-Newton iterations per step, 0..64 */
+    int32_t objective;                  /* PRISM_OBJ_P2 or PRISM_OBJ_P1 */
+    prism_map_params map;               /* update truncation and precision */
+    double normal_disc;                 /* anchor-normal discontinuity threshold (m) */
+} prism_filter_cfg;
+
+/* Device-resident filter state (first bytes of the state buffer), FP64.
+ * Covariances are row-major over the tangent (dt, dtheta, dv, dw). */
+typedef struct {
+    prism_pose pose;        /* posterior mean pose */
+    double v[3], w[3];      /* posterior mean velocity (world, linear / angular) */
+    double P[144];          /* 12x12 state covariance */
+    double Sbar[36];        /* EMA of the Laplace pose covariances */
+    prism_pose anchor;      /* pose the anchor frame was rendered at */
+    prism_pose prior;       /* predicted pose mean of the current step */
+    prism_pose iter;        /* Gauss-Newton iterate */
+    double vel_prior[6];    /* predicted velocity mean */
+    double Lp[36];          /* prior pose precision */
+    double D[36];           /* velocity-conditional gain: E[dv | dpose] = D dpose */
+    double Sv[36];          /* velocity-conditional covariance */
+    double S_lap[36];       /* last Laplace covariance */
+    double neq[29];         /* normal equations at the final iterate */
+    double u[6];            /* control of the last step */
+    int64_t step;           /* frames consumed */
+    int64_t n_updated;      /* voxels updated by the last map update */
+    int32_t flags;          /* PRISM_FLAG_* of the last step */
+    int32_t has_sbar;
+} prism_filter_state;
+
+typedef struct prism_filter prism_filter;
+
+/* One frame for a filter step.  All pointers device. */
+typedef struct {
+    const float *depth; /* [H][W] observed z-depth (<= 0 or non-finite: invalid) */
+    const float *rgb;   /* [H][W][3] observed colour */
+    const double *u;    /* [6] control between the previous and this frame:
+                           linear then angular acceleration, world frame;
+                           ignored for a filter's first frame */
+} prism_frame;
+
+/* Bytes of the state buffer of a filter (state struct, anchor frame, reduction
+ * workspace), excluding the map. */
+prism_status prism_filter_bytes(const prism_filter_cfg *cfg, size_t *bytes);
+
+/* Creates a handle that borrows state_mem (prism_filter_bytes, 256-byte
+ * aligned) and map_mem (prism_map_bytes of cfg->grid).  The handle owns only
+ * host memory; prism_filter_destroy never frees the borrowed buffers. */
+prism_status prism_filter_create(const prism_filter_cfg *cfg, void *state_mem, void *map_mem,
+                                 prism_filter **out);
+prism_status prism_filter_destroy(prism_filter *f);
+
+/* Sets the state belief: x0 = (t[3], q[4], v[3], w[3]) and P0 [12x12], both
+ * host; resets the step counter (the next frame is the first, App. C: x_1
+ * given).  Does not touch the map. */
+prism_status prism_filter_reset(prism_filter *f, const double *x0, const double *P0,
+                                hipStream_t stream);
+
+/* State filter only (Sec. 3.3.2): predict and split the state belief with
+ * the frame's control, n_gn Gauss-Newton steps of the configured objective
+ * from the predicted pose, Laplace covariance at the final iterate (EMA'd),
+ * and combination with the velocity conditional.  Not valid for the first
+ * frame. */
+prism_status prism_pose_update(prism_filter *f, const prism_frame *frame, hipStream_t stream);
+
+/* One full filter step for each of n handles (Sec. 3.3): the state filter
+ * as in prism_pose_update (skipped for a filter's first frame), then the map
+ * update at the posterior mean pose (App. C nominal state), then the anchor
+ * frame rendered from the updated map at that pose for the next step.
+ * frames: host array of n descriptors. */
+prism_status prism_filter_step(prism_filter *const *fs, int32_t n, const prism_frame *frames,
+                               hipStream_t stream);
+
+/* Device pointer to the filter's prism_filter_state (inside state_mem). */
+prism_status prism_filter_state_ptr(const prism_filter *f, prism_filter_state **state);
+
+/* Device pointers to the anchor frame buffers (inside state_mem). */
+prism_status prism_filter_anchor(const prism_filter *f, float **depth, float **rgb, uint8_t **mask,
+                                 float **normals, uint8_t **nmask);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PRISM_H */

@@ -513,9 +513,18 @@ void orc_track_p2(const orc_camera *c, const double *pose, const double *pose_pr
     double R[3][3], Rp[3][3];
     quat_to_rot(pose, R);
     quat_to_rot(pose_prev, Rp);
-    dec32 dc, dp;
+    dec32 dc;
     dec32_init(&dc, NULL, c, pose);
-    dec32_init(&dp, NULL, c, pose_prev);
+    /* relative transform current camera -> anchor camera, formed in double
+     * (Rrel = Rp^T R, trel = Rp^T (t - t_prev), sums in index order) and
+     * rounded to float for the single-precision association recipe */
+    struct { float R[3][3], t[3]; } rel;
+    for (int a = 0; a < 3; ++a) {
+        for (int b = 0; b < 3; ++b)
+            rel.R[a][b] = (float)((Rp[0][a] * R[0][b] + Rp[1][a] * R[1][b]) + Rp[2][a] * R[2][b]);
+        double d0 = pose[0] - pose_prev[0], d1 = pose[1] - pose_prev[1], d2 = pose[2] - pose_prev[2];
+        rel.t[a] = (float)((Rp[0][a] * d0 + Rp[1][a] * d1) + Rp[2][a] * d2);
+    }
     int W = c->width, H = c->height;
     double *rows = (double *)calloc((size_t)H * 29, sizeof(double));
 #pragma omp parallel for schedule(dynamic, 1)
@@ -537,11 +546,9 @@ void orc_track_p2(const orc_camera *c, const double *pose, const double *pose_pr
                     float rx = ((float)u + 0.5f - dc.cx) * dc.ifx;
                     float ry = ((float)v + 0.5f - dc.cy) * dc.ify;
                     float X[3] = {D32 * rx, D32 * ry, D32};
-                    float dW[3], Y[3];
+                    float Y[3];
                     for (int a = 0; a < 3; ++a)
-                        dW[a] = (((dc.R[a][0] * X[0] + dc.R[a][1] * X[1]) + dc.R[a][2] * X[2]) + dc.t[a]) - dp.t[a];
-                    for (int a = 0; a < 3; ++a)
-                        Y[a] = (dp.R[0][a] * dW[0] + dp.R[1][a] * dW[1]) + dp.R[2][a] * dW[2];
+                        Y[a] = ((rel.R[a][0] * X[0] + rel.R[a][1] * X[1]) + rel.R[a][2] * X[2]) + rel.t[a];
                     if (Y[2] > 0.0f) {
                         front = 1;
                         float uu = dc.fx * (Y[0] / Y[2]) + dc.cx;

@@ -1,0 +1,544 @@
+// C ABI of the library: argument validation, per-call constants, launch
+// sequencing and filter handles.  Semantics of every entry point are stated
+// in include/prism.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "common.hpp"
+#include "launch.hpp"
+
+using namespace prism;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+prism_status fail(prism_status code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(PRISM_HIP_ERROR, "%s: %s (%d)", #expr, hipGetErrorString(e_), (int)e_); \
+    } while (0)
+
+#define REQUIRE(cond, ...)                                        \
+    do {                                                          \
+        if (!(cond)) return fail(PRISM_INVALID_ARGUMENT, __VA_ARGS__); \
+    } while (0)
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+prism_status check_grid(const prism_grid* g) {
+    REQUIRE(g, "grid is NULL");
+    if (g->dtype != PRISM_F32 && g->dtype != PRISM_BF16)
+        return fail(PRISM_UNSUPPORTED, "grid dtype %d unsupported (PRISM_F32 or PRISM_BF16)", g->dtype);
+    if (g->n < 8 || g->n > 1024 || g->n % 8)
+        return fail(PRISM_UNSUPPORTED, "grid n=%d unsupported (multiple of 8 in [8, 1024])", g->n);
+    REQUIRE(isfinite(g->voxel) && g->voxel > 0, "grid voxel must be finite and > 0");
+    REQUIRE(isfinite(g->origin[0]) && isfinite(g->origin[1]) && isfinite(g->origin[2]), "grid origin not finite");
+    REQUIRE(isfinite(g->occ_out) && isfinite(g->rgb_out), "grid outside values not finite");
+    return PRISM_OK;
+}
+
+prism_status check_cam(const prism_camera* c) {
+    REQUIRE(c, "camera is NULL");
+    if (c->width < 1 || c->height < 1 || c->width > 8192 || c->height > 8192)
+        return fail(PRISM_UNSUPPORTED, "camera %dx%d unsupported (1..8192 each)", c->width, c->height);
+    if (c->n_samples < 2 || c->n_samples > 4096)
+        return fail(PRISM_UNSUPPORTED, "n_samples=%d unsupported (2..4096)", c->n_samples);
+    REQUIRE(isfinite(c->fx) && isfinite(c->fy) && c->fx > 0 && c->fy > 0, "fx, fy must be finite and > 0");
+    REQUIRE(isfinite(c->cx) && isfinite(c->cy), "cx, cy must be finite");
+    REQUIRE(isfinite(c->d_near) && isfinite(c->d_far) && c->d_near >= 0 && c->d_far > c->d_near,
+            "need 0 <= d_near < d_far (finite)");
+    REQUIRE(isfinite(c->tau), "tau must be finite");
+    return PRISM_OK;
+}
+
+prism_status check_weights(const prism_weights* w) {
+    REQUIRE(w, "weights is NULL");
+    REQUIRE(isfinite(w->w_depth) && isfinite(w->w_rgb) && w->w_depth >= 0 && w->w_rgb >= 0,
+            "weights must be finite and >= 0");
+    REQUIRE(!isnan(w->gate_depth) && !isnan(w->gate_rgb), "gates must not be NaN");
+    return PRISM_OK;
+}
+
+// Constants of the single-precision recipe, formed from the double
+// parameters exactly as the recipe states (see common.hpp).
+GridC grid_c(const prism_grid* g) {
+    GridC o;
+    for (int i = 0; i < 3; ++i) o.o[i] = (float)g->origin[i];
+    o.s = (float)g->voxel;
+    o.inv_s = (float)(1.0 / g->voxel);
+    o.occ_out = (float)g->occ_out;
+    o.rgb_out = (float)g->rgb_out;
+    o.n = g->n;
+    o.nb = g->n / 8;
+    o.nvox = (long long)g->n * g->n * g->n;
+    return o;
+}
+
+CamC cam_c(const prism_camera* c) {
+    CamC o;
+    o.ifx = (float)(1.0 / c->fx);
+    o.ify = (float)(1.0 / c->fy);
+    o.fx = (float)c->fx;
+    o.fy = (float)c->fy;
+    o.cx = (float)c->cx;
+    o.cy = (float)c->cy;
+    o.dn = (float)c->d_near;
+    o.dstep = (float)((c->d_far - c->d_near) / (c->n_samples - 1));
+    o.tau = (float)c->tau;
+    o.W = c->width;
+    o.H = c->height;
+    o.K = c->n_samples;
+    return o;
+}
+
+WeightsC weights_c(const prism_weights* w) {
+    return WeightsC{(float)w->w_depth, (float)w->w_rgb, (float)w->gate_depth, (float)w->gate_rgb};
+}
+
+size_t elem_size(int dtype) { return dtype == PRISM_BF16 ? 2 : 4; }
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+size_t reduce_bytes(const CamC& c, int n_frames) {
+    int nb = render_blocks(c) > track_blocks(c) ? render_blocks(c) : track_blocks(c);
+    return (size_t)nb * n_frames * PRISM_NEQ * sizeof(double);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// filter handle
+// ---------------------------------------------------------------------------
+struct prism_filter {
+    prism_filter_cfg cfg;
+    GridC g;
+    CamC c;
+    WeightsC w;
+    TransC tc;
+    prism_filter_state* S;
+    float *a_depth, *a_rgb, *a_normals;
+    uint8_t *a_mask, *a_nmask;
+    double* partials;
+    void* map;
+    int64_t steps;
+    prism_filter_state host_state;   // source of prism_filter_reset uploads
+};
+
+namespace {
+
+struct StateLayout {
+    size_t state, a_depth, a_rgb, a_normals, a_mask, a_nmask, partials, total;
+};
+
+StateLayout state_layout(const prism_camera* c) {
+    StateLayout L;
+    size_t npix = (size_t)c->width * c->height;
+    CamC cc = cam_c(c);
+    size_t off = 0;
+    L.state = off;
+    off = round_up(off + sizeof(prism_filter_state), 256);
+    L.a_depth = off;
+    off = round_up(off + 4 * npix, 256);
+    L.a_rgb = off;
+    off = round_up(off + 12 * npix, 256);
+    L.a_normals = off;
+    off = round_up(off + 12 * npix, 256);
+    L.a_mask = off;
+    off = round_up(off + npix, 256);
+    L.a_nmask = off;
+    off = round_up(off + npix, 256);
+    L.partials = off;
+    off = round_up(off + reduce_bytes(cc, 1), 256);
+    L.total = off;
+    return L;
+}
+
+prism_status check_cfg(const prism_filter_cfg* cfg) {
+    REQUIRE(cfg, "cfg is NULL");
+    prism_status s;
+    if ((s = check_grid(&cfg->grid))) return s;
+    if ((s = check_cam(&cfg->cam))) return s;
+    if ((s = check_weights(&cfg->w))) return s;
+    REQUIRE(isfinite(cfg->dt) && cfg->dt > 0, "dt must be > 0");
+    REQUIRE(cfg->sigma_vel_t >= 0 && cfg->sigma_vel_r >= 0 && cfg->sigma_pose_t >= 0 && cfg->sigma_pose_r >= 0,
+            "transition scales must be >= 0");
+    REQUIRE(cfg->ema >= 0 && cfg->ema <= 1, "ema must be in [0, 1]");
+    REQUIRE(cfg->n_gn >= 0 && cfg->n_gn <= 64, "n_gn must be in [0, 64]");
+    REQUIRE(cfg->objective == PRISM_OBJ_P2 || cfg->objective == PRISM_OBJ_P1, "objective must be P2 or P1");
+    REQUIRE(cfg->map.trunc > 0 && cfg->map.lam_update > 0, "map trunc and lam_update must be > 0");
+    REQUIRE(!isnan(cfg->normal_disc), "normal_disc is NaN");
+    return PRISM_OK;
+}
+
+prism_status check_frame(const prism_frame* fr, bool need_u) {
+    REQUIRE(fr, "frame is NULL");
+    REQUIRE(fr->depth && fr->rgb, "frame depth/rgb must be non-NULL");
+    REQUIRE(aligned(fr->depth, 4) && aligned(fr->rgb, 4), "frame buffers must be 4-byte aligned");
+    REQUIRE(!need_u || (fr->u && aligned(fr->u, 8)), "frame control u must be non-NULL and 8-byte aligned");
+    return PRISM_OK;
+}
+
+// objective at S->iter into the handle's partials; returns the block count
+prism_status eval_objective(prism_filter* f, const prism_frame* fr, int* nb, hipStream_t st) {
+    if (f->cfg.objective == PRISM_OBJ_P1) {
+        HIP_TRY(launch_render_jac(f->g, f->c, f->cfg.grid.dtype, f->map, &f->S->iter, 1, fr->depth, fr->rgb, f->w,
+                                  nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, f->partials, st));
+        *nb = render_blocks(f->c);
+    } else {
+        HIP_TRY(launch_track_p2(f->c, &f->S->iter, &f->S->anchor, fr->depth, fr->rgb, f->a_depth, f->a_rgb,
+                                f->a_mask, f->a_normals, f->a_nmask, f->w, nullptr, nullptr, nullptr, f->partials,
+                                st));
+        *nb = track_blocks(f->c);
+    }
+    return PRISM_OK;
+}
+
+prism_status pose_update_impl(prism_filter* f, const prism_frame* fr, hipStream_t st) {
+    HIP_TRY(launch_predict(f->S, fr->u, f->tc, st));
+    int nb = 0;
+    prism_status s;
+    for (int i = 0; i < f->cfg.n_gn; ++i) {
+        if ((s = eval_objective(f, fr, &nb, st))) return s;
+        HIP_TRY(launch_gn_step(f->S, f->partials, nb, st));
+    }
+    if ((s = eval_objective(f, fr, &nb, st))) return s;
+    HIP_TRY(launch_laplace_combine(f->S, f->partials, nb, f->cfg.ema, st));
+    return PRISM_OK;
+}
+
+prism_status map_and_anchor(prism_filter* f, const prism_frame* fr, hipStream_t st) {
+    HIP_TRY(launch_map_update(f->g, f->c, f->cfg.grid.dtype, f->map, &f->S->pose, fr->depth, fr->rgb,
+                              (float)f->cfg.map.trunc, (float)f->cfg.map.lam_update, &f->S->n_updated, st));
+    HIP_TRY(launch_render(f->g, f->c, f->cfg.grid.dtype, f->map, &f->S->pose, 1, f->a_depth, f->a_rgb, f->a_mask,
+                          nullptr, st));
+    HIP_TRY(launch_normals(f->c, 1, f->a_depth, f->a_mask, (float)f->cfg.normal_disc, f->a_normals, f->a_nmask,
+                           st));
+    return PRISM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* prism_last_error(void) { return g_err; }
+
+const char* prism_version(void) { return "prism-mi355x 0.1 (gfx950)"; }
+
+size_t prism_sizeof(const char* name) {
+    if (!name) return 0;
+    struct { const char* n; size_t s; } t[] = {
+        {"prism_grid", sizeof(prism_grid)},         {"prism_camera", sizeof(prism_camera)},
+        {"prism_pose", sizeof(prism_pose)},         {"prism_weights", sizeof(prism_weights)},
+        {"prism_map_params", sizeof(prism_map_params)}, {"prism_filter_cfg", sizeof(prism_filter_cfg)},
+        {"prism_filter_state", sizeof(prism_filter_state)}, {"prism_frame", sizeof(prism_frame)}};
+    for (auto& e : t)
+        if (!strcmp(e.n, name)) return e.s;
+    return 0;
+}
+
+prism_status prism_map_bytes(const prism_grid* grid, size_t* bytes) {
+    prism_status s = check_grid(grid);
+    if (s) return s;
+    REQUIRE(bytes, "bytes is NULL");
+    *bytes = 8 * (size_t)grid->n * grid->n * grid->n * elem_size(grid->dtype);
+    return PRISM_OK;
+}
+
+prism_status prism_map_init(const prism_grid* grid, void* map, float occ0, float rgb0, float var0,
+                            hipStream_t stream) {
+    prism_status s = check_grid(grid);
+    if (s) return s;
+    REQUIRE(map && aligned(map, 256), "map must be non-NULL and 256-byte aligned");
+    HIP_TRY(launch_map_init(grid_c(grid), grid->dtype, map, occ0, rgb0, var0, stream));
+    return PRISM_OK;
+}
+
+prism_status prism_map_from_dense(const prism_grid* grid, void* map, const float* mean4, const float* var4,
+                                  hipStream_t stream) {
+    prism_status s = check_grid(grid);
+    if (s) return s;
+    REQUIRE(map && aligned(map, 256), "map must be non-NULL and 256-byte aligned");
+    REQUIRE(!mean4 || aligned(mean4, 4), "mean4 misaligned");
+    REQUIRE(!var4 || aligned(var4, 4), "var4 misaligned");
+    if (!mean4 && !var4) return PRISM_OK;
+    HIP_TRY(launch_from_dense(grid_c(grid), grid->dtype, map, mean4, var4, stream));
+    return PRISM_OK;
+}
+
+prism_status prism_map_to_dense(const prism_grid* grid, const void* map, float* mean4, float* var4,
+                                hipStream_t stream) {
+    prism_status s = check_grid(grid);
+    if (s) return s;
+    REQUIRE(map && aligned(map, 256), "map must be non-NULL and 256-byte aligned");
+    REQUIRE(!mean4 || aligned(mean4, 4), "mean4 misaligned");
+    REQUIRE(!var4 || aligned(var4, 4), "var4 misaligned");
+    if (!mean4 && !var4) return PRISM_OK;
+    HIP_TRY(launch_to_dense(grid_c(grid), grid->dtype, map, mean4, var4, stream));
+    return PRISM_OK;
+}
+
+static prism_status planes(int32_t n, int32_t channels, const float* src, float* dst, int to_dense,
+                           hipStream_t stream) {
+    if (n < 8 || n > 1024 || n % 8) return fail(PRISM_UNSUPPORTED, "n=%d unsupported (multiple of 8 in [8, 1024])", n);
+    REQUIRE(channels >= 1 && channels <= 8, "channels must be in [1, 8]");
+    REQUIRE(src && dst && aligned(src, 4) && aligned(dst, 4), "src/dst must be non-NULL and 4-byte aligned");
+    REQUIRE(src != dst, "src and dst must not alias");
+    HIP_TRY(launch_planes(n, channels, src, dst, to_dense, stream));
+    return PRISM_OK;
+}
+
+prism_status prism_bricks_to_dense(int32_t n, int32_t channels, const float* bricks, float* dense,
+                                   hipStream_t stream) {
+    return planes(n, channels, bricks, dense, 1, stream);
+}
+
+prism_status prism_dense_to_bricks(int32_t n, int32_t channels, const float* dense, float* bricks,
+                                   hipStream_t stream) {
+    return planes(n, channels, dense, bricks, 0, stream);
+}
+
+prism_status prism_render(const prism_grid* grid, const void* map, const prism_camera* cam, const prism_pose* poses,
+                          int32_t n_frames, float* depth, float* rgb, uint8_t* mask, int32_t* hit_k, float* normals,
+                          uint8_t* nmask, double normal_disc, hipStream_t stream) {
+    prism_status s;
+    if ((s = check_grid(grid)) || (s = check_cam(cam))) return s;
+    REQUIRE(map && aligned(map, 256), "map must be non-NULL and 256-byte aligned");
+    REQUIRE(poses && aligned(poses, 8), "poses must be non-NULL and 8-byte aligned");
+    REQUIRE(n_frames >= 1 && n_frames <= 65535, "n_frames must be in [1, 65535]");
+    REQUIRE(depth && rgb && mask, "depth, rgb, mask must be non-NULL");
+    REQUIRE(aligned(depth, 4) && aligned(rgb, 4) && (!hit_k || aligned(hit_k, 4)), "outputs misaligned");
+    REQUIRE(!normals || (nmask && aligned(normals, 4)), "normals needs nmask (and 4-byte alignment)");
+    REQUIRE(!normals || !isnan(normal_disc), "normal_disc is NaN");
+    CamC c = cam_c(cam);
+    HIP_TRY(launch_render(grid_c(grid), c, grid->dtype, map, poses, n_frames, depth, rgb, mask, hit_k, stream));
+    if (normals) HIP_TRY(launch_normals(c, n_frames, depth, mask, (float)normal_disc, normals, nmask, stream));
+    return PRISM_OK;
+}
+
+prism_status prism_reduce_workspace_bytes(const prism_camera* cam, int32_t n_frames, size_t* bytes) {
+    prism_status s = check_cam(cam);
+    if (s) return s;
+    REQUIRE(n_frames >= 1 && n_frames <= 65535, "n_frames must be in [1, 65535]");
+    REQUIRE(bytes, "bytes is NULL");
+    *bytes = reduce_bytes(cam_c(cam), n_frames);
+    return PRISM_OK;
+}
+
+prism_status prism_render_jacobian(const prism_grid* grid, const void* map, const prism_camera* cam,
+                                   const prism_pose* poses, int32_t n_frames, const float* obs_depth,
+                                   const float* obs_rgb, const prism_weights* w, float* depth, float* rgb,
+                                   uint8_t* mask, float* J, float* resid, uint8_t* rowmask, double* neq,
+                                   void* workspace, size_t workspace_bytes, hipStream_t stream) {
+    prism_status s;
+    if ((s = check_grid(grid)) || (s = check_cam(cam)) || (s = check_weights(w))) return s;
+    REQUIRE(map && aligned(map, 256), "map must be non-NULL and 256-byte aligned");
+    REQUIRE(poses && aligned(poses, 8), "poses must be non-NULL and 8-byte aligned");
+    REQUIRE(n_frames >= 1 && n_frames <= 65535, "n_frames must be in [1, 65535]");
+    REQUIRE(obs_depth && obs_rgb && aligned(obs_depth, 4) && aligned(obs_rgb, 4), "observations must be non-NULL, aligned");
+    REQUIRE(neq && aligned(neq, 8), "neq must be non-NULL and 8-byte aligned");
+    REQUIRE((!J || aligned(J, 16)) && (!resid || aligned(resid, 16)), "J and resid must be 16-byte aligned");
+    REQUIRE((!depth || aligned(depth, 4)) && (!rgb || aligned(rgb, 4)), "outputs misaligned");
+    CamC c = cam_c(cam);
+    REQUIRE(workspace && aligned(workspace, 8) && workspace_bytes >= reduce_bytes(c, n_frames),
+            "workspace too small: need %zu bytes", reduce_bytes(c, n_frames));
+    double* part = (double*)workspace;
+    HIP_TRY(launch_render_jac(grid_c(grid), c, grid->dtype, map, poses, n_frames, obs_depth, obs_rgb, weights_c(w),
+                              depth, rgb, mask, J, resid, rowmask, part, stream));
+    HIP_TRY(launch_finalize(part, render_blocks(c), n_frames, PRISM_NEQ, neq, PRISM_NEQ, stream));
+    return PRISM_OK;
+}
+
+prism_status prism_track_p2(const prism_camera* cam, const prism_pose* pose, const prism_pose* pose_prev,
+                            const float* obs_depth, const float* obs_rgb, const float* anchor_depth,
+                            const float* anchor_rgb, const uint8_t* anchor_mask, const float* anchor_normals,
+                            const uint8_t* anchor_nmask, const prism_weights* w, float* J, float* resid,
+                            uint8_t* rowmask, double* neq, void* workspace, size_t workspace_bytes,
+                            hipStream_t stream) {
+    prism_status s;
+    if ((s = check_cam(cam)) || (s = check_weights(w))) return s;
+    REQUIRE(pose && pose_prev && aligned(pose, 8) && aligned(pose_prev, 8), "poses must be non-NULL and aligned");
+    REQUIRE(obs_depth && obs_rgb && aligned(obs_depth, 4) && aligned(obs_rgb, 4), "observations must be non-NULL, aligned");
+    REQUIRE(anchor_depth && anchor_rgb && anchor_mask && anchor_normals && anchor_nmask, "anchor buffers must be non-NULL");
+    REQUIRE(aligned(anchor_depth, 4) && aligned(anchor_rgb, 4) && aligned(anchor_normals, 4), "anchor buffers misaligned");
+    REQUIRE(neq && aligned(neq, 8), "neq must be non-NULL and 8-byte aligned");
+    REQUIRE((!J || aligned(J, 16)) && (!resid || aligned(resid, 16)), "J and resid must be 16-byte aligned");
+    CamC c = cam_c(cam);
+    REQUIRE(workspace && aligned(workspace, 8) && workspace_bytes >= reduce_bytes(c, 1),
+            "workspace too small: need %zu bytes", reduce_bytes(c, 1));
+    double* part = (double*)workspace;
+    HIP_TRY(launch_track_p2(c, pose, pose_prev, obs_depth, obs_rgb, anchor_depth, anchor_rgb, anchor_mask,
+                            anchor_normals, anchor_nmask, weights_c(w), J, resid, rowmask, part, stream));
+    HIP_TRY(launch_finalize(part, track_blocks(c), 1, PRISM_NEQ, neq, PRISM_NEQ, stream));
+    return PRISM_OK;
+}
+
+prism_status prism_render_vjp(const prism_grid* grid, const void* map, const prism_camera* cam,
+                              const prism_pose* poses, int32_t n_frames, const int32_t* hit_k, const float* g_depth,
+                              const float* g_rgb, float* grad_mean, double* grad_pose, void* workspace,
+                              size_t workspace_bytes, hipStream_t stream) {
+    prism_status s;
+    if ((s = check_grid(grid)) || (s = check_cam(cam))) return s;
+    if (grid->dtype != PRISM_F32) return fail(PRISM_UNSUPPORTED, "render_vjp needs an FP32 map");
+    REQUIRE(map && aligned(map, 256), "map must be non-NULL and 256-byte aligned");
+    REQUIRE(poses && aligned(poses, 8), "poses must be non-NULL and 8-byte aligned");
+    REQUIRE(n_frames >= 1 && n_frames <= 65535, "n_frames must be in [1, 65535]");
+    REQUIRE(hit_k && g_depth && g_rgb && grad_mean && grad_pose, "inputs and outputs must be non-NULL");
+    REQUIRE(aligned(hit_k, 4) && aligned(g_depth, 4) && aligned(g_rgb, 4) && aligned(grad_mean, 4) &&
+                aligned(grad_pose, 8),
+            "buffers misaligned");
+    CamC c = cam_c(cam);
+    REQUIRE(workspace && aligned(workspace, 8) && workspace_bytes >= reduce_bytes(c, n_frames),
+            "workspace too small: need %zu bytes", reduce_bytes(c, n_frames));
+    double* part = (double*)workspace;
+    HIP_TRY(launch_render_vjp(grid_c(grid), c, (const float*)map, poses, n_frames, hit_k, g_depth, g_rgb, grad_mean,
+                              part, stream));
+    HIP_TRY(launch_finalize(part, render_blocks(c), n_frames, 6, grad_pose, 6, stream));
+    return PRISM_OK;
+}
+
+prism_status prism_map_update(const prism_grid* grid, void* map, const prism_camera* cam, const prism_pose* pose,
+                              const float* obs_depth, const float* obs_rgb, const prism_map_params* p,
+                              int64_t* n_updated, hipStream_t stream) {
+    prism_status s;
+    if ((s = check_grid(grid)) || (s = check_cam(cam))) return s;
+    REQUIRE(map && aligned(map, 256), "map must be non-NULL and 256-byte aligned");
+    REQUIRE(pose && aligned(pose, 8), "pose must be non-NULL and 8-byte aligned");
+    REQUIRE(obs_depth && obs_rgb && aligned(obs_depth, 4) && aligned(obs_rgb, 4), "observations must be non-NULL, aligned");
+    REQUIRE(p && isfinite(p->trunc) && p->trunc > 0 && isfinite(p->lam_update) && p->lam_update > 0,
+            "map params: trunc and lam_update must be finite and > 0");
+    REQUIRE(!n_updated || aligned(n_updated, 8), "n_updated misaligned");
+    HIP_TRY(launch_map_update(grid_c(grid), cam_c(cam), grid->dtype, map, pose, obs_depth, obs_rgb, (float)p->trunc,
+                              (float)p->lam_update, n_updated, stream));
+    return PRISM_OK;
+}
+
+prism_status prism_filter_bytes(const prism_filter_cfg* cfg, size_t* bytes) {
+    prism_status s = check_cfg(cfg);
+    if (s) return s;
+    REQUIRE(bytes, "bytes is NULL");
+    *bytes = state_layout(&cfg->cam).total;
+    return PRISM_OK;
+}
+
+prism_status prism_filter_create(const prism_filter_cfg* cfg, void* state_mem, void* map_mem, prism_filter** out) {
+    prism_status s = check_cfg(cfg);
+    if (s) return s;
+    REQUIRE(state_mem && aligned(state_mem, 256), "state_mem must be non-NULL and 256-byte aligned");
+    REQUIRE(map_mem && aligned(map_mem, 256), "map_mem must be non-NULL and 256-byte aligned");
+    REQUIRE(out, "out is NULL");
+    prism_filter* f = new (std::nothrow) prism_filter();
+    if (!f) return fail(PRISM_INVALID_ARGUMENT, "out of host memory");
+    f->cfg = *cfg;
+    f->g = grid_c(&cfg->grid);
+    f->c = cam_c(&cfg->cam);
+    f->w = weights_c(&cfg->w);
+    f->tc.dt = cfg->dt;
+    for (int i = 0; i < 3; ++i) {
+        f->tc.q[i] = cfg->sigma_pose_t * cfg->sigma_pose_t;
+        f->tc.q[3 + i] = cfg->sigma_pose_r * cfg->sigma_pose_r;
+        f->tc.q[6 + i] = cfg->sigma_vel_t * cfg->sigma_vel_t;
+        f->tc.q[9 + i] = cfg->sigma_vel_r * cfg->sigma_vel_r;
+    }
+    StateLayout L = state_layout(&cfg->cam);
+    char* base = (char*)state_mem;
+    f->S = (prism_filter_state*)(base + L.state);
+    f->a_depth = (float*)(base + L.a_depth);
+    f->a_rgb = (float*)(base + L.a_rgb);
+    f->a_normals = (float*)(base + L.a_normals);
+    f->a_mask = (uint8_t*)(base + L.a_mask);
+    f->a_nmask = (uint8_t*)(base + L.a_nmask);
+    f->partials = (double*)(base + L.partials);
+    f->map = map_mem;
+    f->steps = 0;
+    *out = f;
+    return PRISM_OK;
+}
+
+prism_status prism_filter_destroy(prism_filter* f) {
+    delete f;
+    return PRISM_OK;
+}
+
+prism_status prism_filter_reset(prism_filter* f, const double* x0, const double* P0, hipStream_t stream) {
+    REQUIRE(f && x0 && P0, "filter, x0 and P0 must be non-NULL");
+    for (int i = 0; i < 13; ++i) REQUIRE(isfinite(x0[i]), "x0 not finite");
+    for (int i = 0; i < 144; ++i) REQUIRE(isfinite(P0[i]), "P0 not finite");
+    prism_filter_state& h = f->host_state;
+    memset(&h, 0, sizeof h);
+    for (int i = 0; i < 3; ++i) h.pose.t[i] = x0[i];
+    for (int i = 0; i < 4; ++i) h.pose.q[i] = x0[3 + i];
+    for (int i = 0; i < 3; ++i) {
+        h.v[i] = x0[7 + i];
+        h.w[i] = x0[10 + i];
+    }
+    memcpy(h.P, P0, sizeof h.P);
+    h.anchor = h.pose;
+    h.prior = h.pose;
+    h.iter = h.pose;
+    HIP_TRY(hipMemcpyAsync(f->S, &h, sizeof h, hipMemcpyHostToDevice, stream));
+    f->steps = 0;
+    return PRISM_OK;
+}
+
+prism_status prism_pose_update(prism_filter* f, const prism_frame* frame, hipStream_t stream) {
+    REQUIRE(f, "filter is NULL");
+    prism_status s = check_frame(frame, true);
+    if (s) return s;
+    REQUIRE(f->steps > 0, "pose_update needs a filter past its first frame");
+    return pose_update_impl(f, frame, stream);
+}
+
+prism_status prism_filter_step(prism_filter* const* fs, int32_t n, const prism_frame* frames, hipStream_t stream) {
+    REQUIRE(fs && frames && n >= 1, "need n >= 1 filters and frames");
+    for (int i = 0; i < n; ++i) {
+        REQUIRE(fs[i], "filter %d is NULL", i);
+        prism_status s = check_frame(&frames[i], fs[i]->steps > 0);
+        if (s) return s;
+    }
+    for (int i = 0; i < n; ++i) {
+        prism_filter* f = fs[i];
+        prism_status s;
+        if (f->steps == 0) {
+            if ((s = map_and_anchor(f, &frames[i], stream))) return s;
+            HIP_TRY(launch_first_frame(f->S, stream));
+        } else {
+            if ((s = pose_update_impl(f, &frames[i], stream))) return s;
+            if ((s = map_and_anchor(f, &frames[i], stream))) return s;
+        }
+        f->steps += 1;
+    }
+    return PRISM_OK;
+}
+
+prism_status prism_filter_state_ptr(const prism_filter* f, prism_filter_state** state) {
+    REQUIRE(f && state, "filter and state must be non-NULL");
+    *state = f->S;
+    return PRISM_OK;
+}
+
+prism_status prism_filter_anchor(const prism_filter* f, float** depth, float** rgb, uint8_t** mask, float** normals,
+                                 uint8_t** nmask) {
+    REQUIRE(f, "filter is NULL");
+    if (depth) *depth = f->a_depth;
+    if (rgb) *rgb = f->a_rgb;
+    if (mask) *mask = f->a_mask;
+    if (normals) *normals = f->a_normals;
+    if (nmask) *nmask = f->a_nmask;
+    return PRISM_OK;
+}
+
+}  // extern "C"

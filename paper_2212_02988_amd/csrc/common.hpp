@@ -1,0 +1,231 @@
+// Device-side building blocks shared by the gfx950 kernels.
+//
+// Single-precision decision recipe.  Every integer the kernels derive from
+// floating point (interpolation cell, hit sample, pixel of a voxel, anchor
+// pixel of a point) is computed in IEEE single precision with a fixed
+// operation order and no contraction (this library is built with
+// -ffp-contract=off; division is IEEE correctly rounded).  The order is:
+//   ray:    rx = ((float)u + 0.5f - cx) * ifx;  ry likewise;
+//           dir_i = (R_i0 rx + R_i1 ry) + R_i2
+//   sample: d_k = d_near + (float)k * dstep;  p_i = t_i + d_k dir_i;
+//           g_i = clamp((p_i - o_i) * inv_s - 0.5f, -2, n+1); cell = floor(g);
+//           w = g - cell;  occupancy = lerp_z(lerp_y(lerp_x(corners)))
+//           with lerp(a, b, w) = a + w (b - a)
+//   voxel:  x_i = o_i + s ((float)i + 0.5f);  d = x - t;
+//           X_a = (R_0a d_0 + R_1a d_1) + R_2a d_2;
+//           u = fx (X_0 / X_2) + cx,  v = fy (X_1 / X_2) + cy
+// where R, t are the pose rounded to float after the quaternion -> matrix
+// conversion in double precision, and ifx = (float)(1/fx), inv_s =
+// (float)(1/voxel), dstep = (float)((d_far - d_near)/(K - 1)).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/prism.h"
+
+namespace prism {
+
+constexpr int kBrick = 8;          // brick edge (voxels)
+constexpr int kBrickVox = 512;     // voxels per brick
+
+// ---------------------------------------------------------------------------
+// per-call constants (computed on the host, passed by value)
+// ---------------------------------------------------------------------------
+struct GridC {
+    float o[3];
+    float s, inv_s;
+    float occ_out, rgb_out;
+    int n;       // voxels per axis
+    int nb;      // bricks per axis
+    long long nvox;   // n^3 (plane stride in elements)
+};
+
+struct CamC {
+    float ifx, ify, fx, fy, cx, cy;
+    float dn, dstep, tau;
+    int W, H, K;
+};
+
+// ---------------------------------------------------------------------------
+// pose -> single-precision rotation/translation
+// ---------------------------------------------------------------------------
+struct Pose32 {
+    float R[3][3];
+    float t[3];
+};
+
+struct Pose64 {
+    double R[3][3];
+    double t[3];
+};
+
+__device__ inline void quat_to_rot64(const prism_pose& p, double R[3][3]) {
+    double w = p.q[0], x = p.q[1], y = p.q[2], z = p.q[3];
+    double nrm = sqrt(w * w + x * x + y * y + z * z);
+    w /= nrm; x /= nrm; y /= nrm; z /= nrm;
+    R[0][0] = 1.0 - 2.0 * (y * y + z * z);
+    R[0][1] = 2.0 * (x * y - w * z);
+    R[0][2] = 2.0 * (x * z + w * y);
+    R[1][0] = 2.0 * (x * y + w * z);
+    R[1][1] = 1.0 - 2.0 * (x * x + z * z);
+    R[1][2] = 2.0 * (y * z - w * x);
+    R[2][0] = 2.0 * (x * z - w * y);
+    R[2][1] = 2.0 * (y * z + w * x);
+    R[2][2] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+__device__ inline Pose64 load_pose64(const prism_pose* pp) {
+    Pose64 o;
+    prism_pose p = *pp;
+    quat_to_rot64(p, o.R);
+    for (int i = 0; i < 3; ++i) o.t[i] = p.t[i];
+    return o;
+}
+
+__device__ inline Pose32 to32(const Pose64& p) {
+    Pose32 o;
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) o.R[i][j] = (float)p.R[i][j];
+        o.t[i] = (float)p.t[i];
+    }
+    return o;
+}
+
+// ---------------------------------------------------------------------------
+// map storage
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float ld(const float* p, long long i) { return p[i]; }
+__device__ __forceinline__ float ld(const uint16_t* p, long long i) {
+    return __uint_as_float(((uint32_t)p[i]) << 16);
+}
+__device__ __forceinline__ void st(float* p, long long i, float v) { p[i] = v; }
+__device__ __forceinline__ uint16_t f2bf(float v) {
+    uint32_t b = __float_as_uint(v);
+    if ((b & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((b >> 16) | 0x40);   // quiet NaN
+    b += 0x7fffu + ((b >> 16) & 1u);                                            // nearest even
+    return (uint16_t)(b >> 16);
+}
+__device__ __forceinline__ void st(uint16_t* p, long long i, float v) { p[i] = f2bf(v); }
+
+// brick-order index of voxel (i, j, k); all in [0, n)
+__device__ __forceinline__ long long vidx(const GridC& g, int i, int j, int k) {
+    long long b = ((long long)(k >> 3) * g.nb + (j >> 3)) * g.nb + (i >> 3);
+    return (b << 9) | ((k & 7) << 6) | ((j & 7) << 3) | (i & 7);
+}
+
+// ---------------------------------------------------------------------------
+// the single-precision ray/sample recipe
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void ray_dir32(const CamC& c, const Pose32& P, int u, int v, float dir[3]) {
+    float rx = ((float)u + 0.5f - c.cx) * c.ifx;
+    float ry = ((float)v + 0.5f - c.cy) * c.ify;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dir[a] = (P.R[a][0] * rx + P.R[a][1] * ry) + P.R[a][2];
+}
+
+// continuous grid coordinate of sample k, clamped; cell and weights
+struct Cell {
+    int i[3];
+    float w[3];
+};
+
+__device__ __forceinline__ Cell sample_cell(const GridC& g, const CamC& c, const Pose32& P,
+                                            const float dir[3], int k) {
+    Cell o;
+    float dk = c.dn + (float)k * c.dstep;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float p = P.t[a] + dk * dir[a];
+        float gc = (p - g.o[a]) * g.inv_s - 0.5f;
+        gc = fminf(fmaxf(gc, -2.0f), (float)(g.n + 1));
+        float fl = floorf(gc);
+        o.i[a] = (int)fl;
+        o.w[a] = gc - fl;
+    }
+    return o;
+}
+
+__device__ __forceinline__ float lerp32(float a, float b, float w) { return a + w * (b - a); }
+
+// 8 corner values of one plane (out-of-grid corners take `outv`)
+template <typename T>
+__device__ __forceinline__ void corners(const GridC& g, const T* plane, const Cell& c, float outv,
+                                        float v[8]) {
+    bool okx0 = (unsigned)c.i[0] < (unsigned)g.n, okx1 = (unsigned)(c.i[0] + 1) < (unsigned)g.n;
+    bool oky0 = (unsigned)c.i[1] < (unsigned)g.n, oky1 = (unsigned)(c.i[1] + 1) < (unsigned)g.n;
+    bool okz0 = (unsigned)c.i[2] < (unsigned)g.n, okz1 = (unsigned)(c.i[2] + 1) < (unsigned)g.n;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        int dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
+        bool ok = (dx ? okx1 : okx0) && (dy ? oky1 : oky0) && (dz ? okz1 : okz0);
+        v[q] = ok ? ld(plane, vidx(g, c.i[0] + dx, c.i[1] + dy, c.i[2] + dz)) : outv;
+    }
+}
+
+// trilinear value from corners v[q], q = dx + 2 dy + 4 dz
+__device__ __forceinline__ float trilerp(const float v[8], const float w[3]) {
+    float l00 = lerp32(v[0], v[1], w[0]);
+    float l10 = lerp32(v[2], v[3], w[0]);
+    float l01 = lerp32(v[4], v[5], w[0]);
+    float l11 = lerp32(v[6], v[7], w[0]);
+    float m0 = lerp32(l00, l10, w[1]);
+    float m1 = lerp32(l01, l11, w[1]);
+    return lerp32(m0, m1, w[2]);
+}
+
+// gradient of the trilinear interpolant w.r.t. the grid coordinate
+__device__ __forceinline__ void trigrad(const float v[8], const float w[3], float gr[3]) {
+    float wx0 = 1.0f - w[0], wy0 = 1.0f - w[1], wz0 = 1.0f - w[2];
+    gr[0] = wy0 * wz0 * (v[1] - v[0]) + w[1] * wz0 * (v[3] - v[2]) + wy0 * w[2] * (v[5] - v[4]) +
+            w[1] * w[2] * (v[7] - v[6]);
+    gr[1] = wx0 * wz0 * (v[2] - v[0]) + w[0] * wz0 * (v[3] - v[1]) + wx0 * w[2] * (v[6] - v[4]) +
+            w[0] * w[2] * (v[7] - v[5]);
+    gr[2] = wx0 * wy0 * (v[4] - v[0]) + w[0] * wy0 * (v[5] - v[1]) + wx0 * w[1] * (v[6] - v[2]) +
+            w[0] * w[1] * (v[7] - v[3]);
+}
+
+// ---------------------------------------------------------------------------
+// reductions of the 29-double normal equations
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// Reduce a per-thread 29-vector over the block (blockDim.x multiple of 64,
+// <= 1024) and write it to out[0..28] (thread 0).  lds: 29 * 16 doubles.
+__device__ inline void block_reduce29(double acc[PRISM_NEQ], double* lds, double* out) {
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int q = 0; q < PRISM_NEQ; ++q) {
+        double s = wave_sum(acc[q]);
+        if (lane == 0) lds[q * 16 + wv] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < PRISM_NEQ) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += lds[threadIdx.x * 16 + w];
+        out[threadIdx.x] = s;
+    }
+}
+
+__device__ __forceinline__ void neq_add(double acc[PRISM_NEQ], const float j[6], float r, float w) {
+    int q = 0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+#pragma unroll
+        for (int b = a; b < 6; ++b) acc[q++] += (double)(w * j[a] * j[b]);
+#pragma unroll
+    for (int a = 0; a < 6; ++a) acc[21 + a] += (double)(w * j[a] * r);
+    acc[27] += (double)(w * r * r);
+}
+
+struct WeightsC {
+    float w_depth, w_rgb, gate_depth, gate_rgb;
+};
+
+__device__ __forceinline__ bool depth_ok(float d) { return d > 0.0f && isfinite(d); }
+
+}  // namespace prism

@@ -1,0 +1,180 @@
+// Prediction-to-observation tracking objective (App. E.3): point-to-plane
+// against the nearest anchor pixel and photometric error against the
+// bilinearly interpolated anchor colour, with the fused reduction of the
+// gated, weighted normal equations.  One observed pixel per lane, pixels in
+// row-major order so observation reads are coalesced; anchor reads are
+// gathers around the reprojected location.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace prism {
+
+struct Rel32 {
+    float R[3][3], t[3];   // current camera -> anchor camera
+    float Rp[3][3];        // anchor rotation (camera -> world)
+    float Rc[3][3];        // current rotation (camera -> world)
+};
+
+__global__ __launch_bounds__(256) void k_track_p2(CamC c, const prism_pose* __restrict__ pose,
+                                                  const prism_pose* __restrict__ pose_prev,
+                                                  const float* __restrict__ obs_depth,
+                                                  const float* __restrict__ obs_rgb,
+                                                  const float* __restrict__ a_depth,
+                                                  const float* __restrict__ a_rgb,
+                                                  const uint8_t* __restrict__ a_mask,
+                                                  const float* __restrict__ a_normals,
+                                                  const uint8_t* __restrict__ a_nmask, WeightsC wt,
+                                                  float* __restrict__ Jout, float* __restrict__ resid,
+                                                  uint8_t* __restrict__ rowmask,
+                                                  double* __restrict__ partials) {
+    __shared__ Rel32 srel;
+    __shared__ double lds[PRISM_NEQ * 16];
+    if (threadIdx.x == 0) {
+        Pose64 P = load_pose64(pose), Q = load_pose64(pose_prev);
+        double d[3] = {P.t[0] - Q.t[0], P.t[1] - Q.t[1], P.t[2] - Q.t[2]};
+        for (int a = 0; a < 3; ++a) {
+            for (int b = 0; b < 3; ++b) {
+                srel.R[a][b] = (float)((Q.R[0][a] * P.R[0][b] + Q.R[1][a] * P.R[1][b]) + Q.R[2][a] * P.R[2][b]);
+                srel.Rp[a][b] = (float)Q.R[a][b];
+                srel.Rc[a][b] = (float)P.R[a][b];
+            }
+            srel.t[a] = (float)((Q.R[0][a] * d[0] + Q.R[1][a] * d[1]) + Q.R[2][a] * d[2]);
+        }
+    }
+    __syncthreads();
+    const Rel32& rel = srel;
+    double acc[PRISM_NEQ];
+#pragma unroll
+    for (int q = 0; q < PRISM_NEQ; ++q) acc[q] = 0.0;
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < c.W * c.H) {
+        int u = p % c.W, v = p / c.W;
+        float J[4][6];
+        float r[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int m = 0; m < 6; ++m) J[a][m] = 0.0f;
+        uint8_t rm = 0;
+        float D = obs_depth[p];
+        if (depth_ok(D)) {
+            float rx = ((float)u + 0.5f - c.cx) * c.ifx;
+            float ry = ((float)v + 0.5f - c.cy) * c.ify;
+            float X[3] = {D * rx, D * ry, D};
+            float Y[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                Y[a] = ((rel.R[a][0] * X[0] + rel.R[a][1] * X[1]) + rel.R[a][2] * X[2]) + rel.t[a];
+            bool geo = false, pho = false;
+            int giu = 0, giv = 0, bix = 0, biy = 0;
+            float uu = 0.0f, vv = 0.0f;
+            if (Y[2] > 0.0f) {
+                uu = c.fx * (Y[0] / Y[2]) + c.cx;
+                vv = c.fy * (Y[1] / Y[2]) + c.cy;
+                if (uu >= 0.0f && uu < (float)c.W && vv >= 0.0f && vv < (float)c.H) {
+                    giu = (int)uu;
+                    giv = (int)vv;
+                    geo = true;
+                }
+                float bx = uu - 0.5f, by = vv - 0.5f;
+                if (bx >= 0.0f && bx < (float)(c.W - 1) && by >= 0.0f && by < (float)(c.H - 1)) {
+                    bix = (int)bx;
+                    biy = (int)by;
+                    pho = true;
+                }
+            }
+            if (geo) {
+                int q = giv * c.W + giu;
+                geo = a_mask[q] && a_nmask[q];
+            }
+            int q00 = biy * c.W + bix;
+            if (pho) pho = a_mask[q00] && a_mask[q00 + 1] && a_mask[q00 + c.W] && a_mask[q00 + c.W + 1];
+            if (geo || pho) {
+                // dY/ddelta = Rp^T [I | -[R X]x]
+                float RX[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) RX[a] = rel.Rc[a][0] * X[0] + rel.Rc[a][1] * X[1] + rel.Rc[a][2] * X[2];
+                float dY[3][6];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    float e0 = rel.Rp[0][a], e1 = rel.Rp[1][a], e2 = rel.Rp[2][a];
+                    dY[a][0] = e0;
+                    dY[a][1] = e1;
+                    dY[a][2] = e2;
+                    dY[a][3] = RX[1] * e2 - RX[2] * e1;
+                    dY[a][4] = RX[2] * e0 - RX[0] * e2;
+                    dY[a][5] = RX[0] * e1 - RX[1] * e0;
+                }
+                if (geo) {
+                    int q = giv * c.W + giu;
+                    float da = a_depth[q];
+                    float ph[3] = {da * (((float)giu + 0.5f - c.cx) * c.ifx),
+                                   da * (((float)giv + 0.5f - c.cy) * c.ify), da};
+                    float n0 = a_normals[3 * q], n1 = a_normals[3 * q + 1], n2 = a_normals[3 * q + 2];
+                    r[0] = n0 * (ph[0] - Y[0]) + n1 * (ph[1] - Y[1]) + n2 * (ph[2] - Y[2]);
+#pragma unroll
+                    for (int m = 0; m < 6; ++m) J[0][m] = -(n0 * dY[0][m] + n1 * dY[1][m] + n2 * dY[2][m]);
+                    if (fabsf(r[0]) <= wt.gate_depth) {
+                        neq_add(acc, J[0], r[0], wt.w_depth);
+                        rm |= 1;
+                    }
+                }
+                if (pho) {
+                    float ax = (uu - 0.5f) - (float)bix, ay = (vv - 0.5f) - (float)biy;
+                    float iz = 1.0f / Y[2];
+                    float du_[3] = {c.fx * iz, 0.0f, -c.fx * Y[0] * iz * iz};
+                    float dv_[3] = {0.0f, c.fy * iz, -c.fy * Y[1] * iz * iz};
+                    float dum[6], dvm[6];
+#pragma unroll
+                    for (int m = 0; m < 6; ++m) {
+                        dum[m] = du_[0] * dY[0][m] + du_[2] * dY[2][m];
+                        dvm[m] = dv_[1] * dY[1][m] + dv_[2] * dY[2][m];
+                    }
+                    float l1 = 0.0f;
+#pragma unroll
+                    for (int ch = 0; ch < 3; ++ch) {
+                        float I00 = a_rgb[3 * q00 + ch], I10 = a_rgb[3 * (q00 + 1) + ch];
+                        float I01 = a_rgb[3 * (q00 + c.W) + ch], I11 = a_rgb[3 * (q00 + c.W + 1) + ch];
+                        float Ii = (1.0f - ay) * ((1.0f - ax) * I00 + ax * I10) + ay * ((1.0f - ax) * I01 + ax * I11);
+                        float gu = (1.0f - ay) * (I10 - I00) + ay * (I11 - I01);
+                        float gv = (1.0f - ax) * (I01 - I00) + ax * (I11 - I10);
+                        r[1 + ch] = Ii - obs_rgb[3 * p + ch];
+                        l1 += fabsf(r[1 + ch]);
+#pragma unroll
+                        for (int m = 0; m < 6; ++m) J[1 + ch][m] = gu * dum[m] + gv * dvm[m];
+                    }
+                    if (l1 <= wt.gate_rgb) {
+#pragma unroll
+                        for (int ch = 0; ch < 3; ++ch) neq_add(acc, J[1 + ch], r[1 + ch], wt.w_rgb);
+                        rm |= 2;
+                    }
+                }
+                if (rm) acc[28] = 1.0;
+            }
+        }
+        if (Jout) {
+            float4* jo = reinterpret_cast<float4*>(Jout + 24 * (long long)p);
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+                jo[q] = make_float4(J[(4 * q) / 6][(4 * q) % 6], J[(4 * q + 1) / 6][(4 * q + 1) % 6],
+                                    J[(4 * q + 2) / 6][(4 * q + 2) % 6], J[(4 * q + 3) / 6][(4 * q + 3) % 6]);
+        }
+        if (resid) reinterpret_cast<float4*>(resid)[p] = make_float4(r[0], r[1], r[2], r[3]);
+        if (rowmask) rowmask[p] = rm;
+    }
+    block_reduce29(acc, lds, partials + (long long)blockIdx.x * PRISM_NEQ);
+}
+
+int track_blocks(const CamC& c) { return (c.W * c.H + 255) / 256; }
+
+hipError_t launch_track_p2(const CamC& c, const prism_pose* pose, const prism_pose* pose_prev,
+                           const float* obs_depth, const float* obs_rgb, const float* a_depth,
+                           const float* a_rgb, const uint8_t* a_mask, const float* a_normals,
+                           const uint8_t* a_nmask, const WeightsC& w, float* J, float* resid,
+                           uint8_t* rowmask, double* partials, hipStream_t st) {
+    k_track_p2<<<track_blocks(c), 256, 0, st>>>(c, pose, pose_prev, obs_depth, obs_rgb, a_depth, a_rgb,
+                                                a_mask, a_normals, a_nmask, w, J, resid, rowmask, partials);
+    return hipGetLastError();
+}
+
+}  // namespace prism

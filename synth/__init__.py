@@ -198,19 +198,23 @@ def voxel_centres(scene: Scene) -> np.ndarray:
     return np.stack([x, y, z], axis=-1)   # [k][j][i][3]
 
 
-def gt_map(scene: Scene, var: float = 1e-2) -> Tuple[np.ndarray, np.ndarray]:
-    """Ground-truth dense map (mean [4][N][N][N], var [4][N][N][N]), float64."""
+def gt_map(scene: Scene, var: float = 1e-2, dtype=np.float64) -> Tuple[np.ndarray, np.ndarray]:
+    """Ground-truth dense map (mean [4][N][N][N], var [4][N][N][N]): occupancy
+    = -SDF clamped to +-clamp_voxels voxels, colour of the nearest solid at
+    the voxel centre."""
     n = scene.n
-    mean = np.empty((4, n, n, n))
+    mean = np.empty((4, n, n, n), dtype)
     clamp = scene.clamp_voxels * scene.voxel
-    for k in range(n):  # slab by slab to bound memory
-        ax = (np.arange(n) + 0.5) * scene.voxel
-        y, x = np.meshgrid(ax + scene.origin[1], ax + scene.origin[0], indexing="ij")
-        zc = np.full_like(x, scene.origin[2] + (k + 0.5) * scene.voxel)
-        p = np.stack([x, y, zc], axis=-1)
+    ax = (np.arange(n) + 0.5) * scene.voxel
+    y, x = np.meshgrid(ax + scene.origin[1], ax + scene.origin[0], indexing="ij")
+    step = max(1, (1 << 21) // (n * n))
+    for k0 in range(0, n, step):  # slabs, to bound memory
+        ks = np.arange(k0, min(n, k0 + step))
+        zc = scene.origin[2] + (ks + 0.5) * scene.voxel
+        p = np.stack(np.broadcast_arrays(x[None], y[None], zc[:, None, None]), axis=-1)
         sdf, sid = scene_sdf(scene, p)
-        mean[0, k] = np.clip(-sdf, -clamp, clamp)
-        mean[1:, k] = np.moveaxis(scene.colour_at(sid, p), -1, 0)
+        mean[0, ks] = np.clip(-sdf, -clamp, clamp)
+        mean[1:, ks] = np.moveaxis(scene.colour_at(sid, p), -1, 0)
     return mean, np.full_like(mean, var)
 
 

@@ -1,0 +1,95 @@
+"""The C-ABI library loads on the CPU host, exports every entry point that
+include/prism.h declares, its struct mirrors match, and host-side argument
+validation rejects bad input (no GPU needed: validation runs before any HIP
+call)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "prism.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(prism_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_2212_02988_amd import prism
+    return prism
+
+
+def test_every_declared_symbol_is_exported(P):
+    L = P.lib()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_struct_mirrors(P):
+    L = P.lib()
+    for name, cls in [("prism_grid", P.Grid), ("prism_camera", P.Camera), ("prism_pose", P.Pose),
+                      ("prism_weights", P.Weights), ("prism_map_params", P.MapParams),
+                      ("prism_filter_cfg", P.FilterCfg), ("prism_filter_state", P.FilterState),
+                      ("prism_frame", P.Frame)]:
+        assert L.prism_sizeof(name.encode()) == ctypes.sizeof(cls), name
+    assert L.prism_sizeof(b"nope") == 0
+
+
+def test_map_bytes_and_validation(P):
+    L = P.lib()
+    b = ctypes.c_size_t()
+    g = P.Grid.make(64, 0.04)
+    assert L.prism_map_bytes(ctypes.byref(g), ctypes.byref(b)) == 0
+    assert b.value == 8 * 64 ** 3 * 4
+    g = P.Grid.make(64, 0.04, dtype=P.PRISM_BF16)
+    assert L.prism_map_bytes(ctypes.byref(g), ctypes.byref(b)) == 0
+    assert b.value == 8 * 64 ** 3 * 2
+    for bad in (P.Grid.make(60, 0.04), P.Grid.make(64, 0.04, dtype=7), P.Grid.make(2048, 0.01)):
+        assert L.prism_map_bytes(ctypes.byref(bad), ctypes.byref(b)) == 2
+        assert b"unsupported" in L.prism_last_error()
+    assert L.prism_map_bytes(ctypes.byref(P.Grid.make(64, -1.0)), ctypes.byref(b)) == 1
+    assert L.prism_map_bytes(None, ctypes.byref(b)) == 1
+
+
+def test_render_rejects_bad_arguments(P):
+    L = P.lib()
+    g = P.Grid.make(64, 0.04)
+    cam = P.Camera.make(80, 60, 60, 60, 40, 30, 0.1, 3.0, 32)
+    # NULL map
+    st = L.prism_render(ctypes.byref(g), None, ctypes.byref(cam), ctypes.c_void_p(256), 1, ctypes.c_void_p(256),
+                        ctypes.c_void_p(256), ctypes.c_void_p(256), None, None, None, 0.1, None)
+    assert st == 1 and b"map" in L.prism_last_error()
+    bad = P.Camera.make(80, 60, 60, 60, 40, 30, 3.0, 0.1, 32)     # d_far < d_near
+    st = L.prism_render(ctypes.byref(g), ctypes.c_void_p(256), ctypes.byref(bad), ctypes.c_void_p(256), 1,
+                        ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_void_p(256), None, None, None, 0.1,
+                        None)
+    assert st == 1
+    one = P.Camera.make(80, 60, 60, 60, 40, 30, 0.1, 3.0, 1)       # K < 2
+    st = L.prism_render(ctypes.byref(g), ctypes.c_void_p(256), ctypes.byref(one), ctypes.c_void_p(256), 1,
+                        ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_void_p(256), None, None, None, 0.1,
+                        None)
+    assert st == 2
+    # misaligned map
+    st = L.prism_render(ctypes.byref(g), ctypes.c_void_p(260), ctypes.byref(cam), ctypes.c_void_p(256), 1,
+                        ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_void_p(256), None, None, None, 0.1,
+                        None)
+    assert st == 1 and b"aligned" in L.prism_last_error()
+
+
+def test_workspace_and_filter_sizes(P):
+    L = P.lib()
+    cam = P.Camera.make(320, 240, 240, 240, 160, 120, 0.1, 7.5, 128)
+    b = ctypes.c_size_t()
+    assert L.prism_reduce_workspace_bytes(ctypes.byref(cam), 2, ctypes.byref(b)) == 0
+    assert b.value == 2 * 300 * 29 * 8
+    cfg = P.filter_cfg(P.Grid.make(256, 0.025), cam, P.FilterParams())
+    assert L.prism_filter_bytes(ctypes.byref(cfg), ctypes.byref(b)) == 0
+    assert b.value >= 30 * 320 * 240
+    bad = P.filter_cfg(P.Grid.make(256, 0.025), cam, P.FilterParams(n_gn=100))
+    assert L.prism_filter_bytes(ctypes.byref(bad), ctypes.byref(b)) == 1

@@ -1,0 +1,367 @@
+"""HIP library (through the C ABI) against the FP64 oracle, element by element
+on the same seeded inputs.
+
+Integer decisions (hit sample, interpolation cell, updated-voxel set, pixel
+association) are compared bit for bit; the oracle takes them with the same
+single-precision recipe as the kernels.  Values are compared with the
+tolerances in gpu_util.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+import synth
+from gpu_util import (DEV, banner, cam_of, depth_close, gpu_map, grid_of, oracle_map_values, rgb_close,
+                      rot_angle, t, P)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    P().lib()
+    yield
+
+
+@pytest.fixture(scope="module")
+def case1():
+    c = synth.single_frame_case(0)
+    mean, var = synth.gt_map(c["scene"])
+    return c, mean, var
+
+
+@pytest.fixture(scope="module")
+def case2():
+    """One frame of the 256^3 / 320x240 / 128-sample trajectory workload."""
+    c = synth.trajectory_case(seed=1, n=256, width=320, height=240, n_samples=128, n_frames=6)
+    mean, var = synth.gt_map(c["scene"], dtype=np.float32)
+    return c, mean, var
+
+
+# ---------------------------------------------------------------------------
+def test_map_roundtrip(case1):
+    banner("map roundtrip")
+    c, mean, var = case1
+    for dtype in (0, 1):
+        g = grid_of(c["scene"], dtype)
+        vm = gpu_map(g, mean, var)
+        m2, v2 = vm.to_dense()
+        exp_m = oracle_map_values(mean, dtype).astype(np.float32)
+        exp_v = oracle_map_values(var, dtype).astype(np.float32)
+        np.testing.assert_array_equal(m2.cpu().numpy(), exp_m)
+        np.testing.assert_array_equal(v2.cpu().numpy(), exp_v)
+    # planes helpers
+    n = 16
+    x = torch.randn(3, n, n, n, device=DEV)
+    b = P().dense_to_bricks(n, x)
+    np.testing.assert_array_equal(P().bricks_to_dense(n, b).cpu().numpy(), x.cpu().numpy())
+
+
+def _render_compare(c, mean, var, pose, dtype, normals=True, label=""):
+    g = grid_of(c["scene"], dtype)
+    cam = cam_of(c["cam"])
+    vm = gpu_map(g, mean, var)
+    out = P().render(g, vm, cam, P().poses_tensor(pose), normals=normals, hit_k=True)
+    torch.cuda.synchronize()
+    og = orc.grid_from_scene(c["scene"])
+    oc = orc.cam_from(c["cam"])
+    ref = orc.render(og, oracle_map_values(mean, dtype), oc, pose, decide32=True, normals=normals)
+    hk = out["hit_k"][0].cpu().numpy()
+    np.testing.assert_array_equal(hk, ref["hit_k"], err_msg=f"hit sample {label}")
+    mk = out["mask"][0].cpu().numpy()
+    np.testing.assert_array_equal(mk, ref["mask"])
+    v = mk == 1
+    d = out["depth"][0].cpu().numpy()
+    assert np.all(depth_close(d[v], ref["depth"][v])), np.max(np.abs(d[v] - ref["depth"][v]))
+    assert np.all(d[~v] == 0)
+    rgb = out["rgb"][0].cpu().numpy()
+    assert np.all(rgb_close(rgb[v], ref["rgb"][v])), np.max(np.abs(rgb[v] - ref["rgb"][v]))
+    if normals:
+        nm = out["nmask"][0].cpu().numpy()
+        agree = nm == ref["nmask"]
+        assert agree.mean() > 0.999, (agree.mean(), label)
+        both = (nm == 1) & (ref["nmask"] == 1)
+        nrm = out["normals"][0].cpu().numpy()
+        assert np.max(np.abs(nrm[both] - ref["normals"][both])) < 1e-3
+    return out, ref
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_render_small(case1, dtype):
+    banner(f"render 64^3 80x60 dtype={dtype}")
+    c, mean, var = case1
+    for pose in (synth.pose7(c["t_gt"], c["q_gt"]), synth.pose7(c["t_init"], c["q_init"])):
+        _render_compare(c, mean, var, pose, dtype)
+
+
+def test_render_edge_cases(case1):
+    """Camera outside the grid looking away (no hits), camera inside a solid
+    (k* = 0 everywhere: invalid), ragged image (not a multiple of the 16x16
+    tile), minimal sample count."""
+    banner("render edge cases")
+    c, mean, var = case1
+    g = grid_of(c["scene"])
+    vm = gpu_map(g, mean, var)
+    og = orc.grid_from_scene(c["scene"])
+    cases = [
+        (synth.Camera(37, 23, 30.0, 30.0, 18.5, 11.5, 0.1, 3.0, 32), np.array([-5.0, -5.0, -5.0, 1.0, 0, 0, 0])),
+        (synth.Camera(17, 9, 12.0, 12.0, 8.0, 4.0, 0.1, 3.0, 2), synth.pose7(c["t_gt"], c["q_gt"])),
+        (synth.Camera(33, 17, 25.0, 25.0, 16.0, 8.5, 0.0, 1.0, 7), np.array([0.05, 0.05, 0.05, 1.0, 0, 0, 0])),
+    ]
+    for cm, pose in cases:
+        cam = cam_of(cm)
+        out = P().render(g, vm, cam, P().poses_tensor(pose), hit_k=True)
+        ref = orc.render(og, oracle_map_values(mean, 0), orc.cam_from(cm), pose)
+        np.testing.assert_array_equal(out["hit_k"][0].cpu().numpy(), ref["hit_k"])
+        np.testing.assert_array_equal(out["mask"][0].cpu().numpy(), ref["mask"])
+        v = ref["mask"] == 1
+        assert np.all(depth_close(out["depth"][0].cpu().numpy()[v], ref["depth"][v]))
+
+
+def test_render_batched_frames(case1):
+    """n_frames > 1 in one launch equals the frames rendered one by one."""
+    banner("render batched")
+    c, mean, var = case1
+    g = grid_of(c["scene"])
+    cam = cam_of(c["cam"])
+    vm = gpu_map(g, mean, var)
+    rng = np.random.default_rng(0)
+    poses = np.stack([synth.pose7(*synth.perturb_pose(rng, c["t_gt"], c["q_gt"], 0.1, 0.2)) for _ in range(5)])
+    allb = P().render(g, vm, cam, P().poses_tensor(poses), normals=True, hit_k=True)
+    for i in range(5):
+        one = P().render(g, vm, cam, P().poses_tensor(poses[i]), normals=True, hit_k=True)
+        for k in one:
+            assert torch.equal(one[k][0], allb[k][i]), k
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_render_full_size_frame(case2, dtype):
+    banner(f"render 256^3 320x240x128 dtype={dtype}")
+    c, mean, var = case2
+    tr = c["traj"]
+    for i in (0, 3):
+        _render_compare(c, mean, var, synth.pose7(tr.t[i], tr.q[i]), dtype, label=f"frame {i}")
+
+
+# ---------------------------------------------------------------------------
+def _neq_close(a, b, rtol=1e-4):
+    Ha, ga, ca, na = orc.neq_unpack(a)
+    Hb, gb, cb, nb = orc.neq_unpack(b)
+    assert abs(na - nb) <= max(2, 1e-3 * nb), (na, nb)
+    assert np.linalg.norm(Ha - Hb) <= rtol * np.linalg.norm(Hb), np.linalg.norm(Ha - Hb) / np.linalg.norm(Hb)
+    # g can be small at the optimum: compare against the scale sqrt(|H| cost)
+    gs = max(np.linalg.norm(gb), 1e-3 * math.sqrt(np.linalg.norm(Hb) * max(cb, 1e-12)))
+    assert np.linalg.norm(ga - gb) <= 1e-3 * gs, (np.linalg.norm(ga - gb), gs)
+    assert abs(ca - cb) <= 1e-3 * max(cb, 1e-9)
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_render_jacobian(case1, dtype):
+    banner(f"render_jacobian 64^3 dtype={dtype}")
+    c, mean, var = case1
+    g = grid_of(c["scene"], dtype)
+    cam = cam_of(c["cam"])
+    vm = gpu_map(g, mean, var)
+    rng = np.random.default_rng(3)
+    od, oc = synth.raycast(c["scene"], c["cam"], c["t_gt"], c["q_gt"], rng, 0.01, 0.02)
+    od = od.astype(np.float32); oc = oc.astype(np.float32)
+    pose = synth.pose7(c["t_init"], c["q_init"])
+    out = P().render_jacobian(g, vm, cam, P().poses_tensor(pose), t(od)[None], t(oc)[None], P().Weights.make(),
+                              want_J=True, want_resid=True)
+    torch.cuda.synchronize()
+    ref = orc.render_jacobian(orc.grid_from_scene(c["scene"]), oracle_map_values(mean, dtype),
+                              orc.cam_from(c["cam"]), pose, od, oc, orc.Params(), want_J=True)
+    np.testing.assert_array_equal(out["mask"][0].cpu().numpy(), ref["mask"])
+    rm = out["rowmask"][0].cpu().numpy()
+    assert np.mean(rm != ref["rowmask"]) < 1e-3
+    same = (rm == ref["rowmask"]) & (rm > 0)
+    J = out["J"][0].cpu().numpy()
+    scale = np.median(np.abs(ref["J"][same]), axis=0) + 1e-6
+    err = np.abs(J[same] - ref["J"][same]) / np.maximum(np.abs(ref["J"][same]), scale)
+    assert np.quantile(err, 0.999) < 1e-3 and err.max() < 5e-2, (np.quantile(err, 0.999), err.max())
+    _neq_close(out["neq"][0].cpu().numpy(), ref["neq"])
+
+
+def _anchor(c, mean, pose):
+    og = orc.grid_from_scene(c["scene"])
+    a = orc.render(og, mean, orc.cam_from(c["cam"]), pose, normals=True)
+    # the GPU gets the float32 anchor; the oracle the same values in float64
+    a32 = {k: (v.astype(np.float32) if v.dtype == np.float64 else v) for k, v in a.items()}
+    a64 = {k: (v.astype(np.float64) if v.dtype == np.float32 else v) for k, v in a32.items()}
+    return a32, a64
+
+
+def test_track_p2(case1):
+    banner("track_p2 80x60")
+    c, mean, var = case1
+    prev = synth.pose7(c["t_gt"], c["q_gt"])
+    a32, a64 = _anchor(c, mean, prev)
+    rng = np.random.default_rng(4)
+    tt, qq = synth.perturb_pose(rng, c["t_gt"], c["q_gt"], 0.03, 0.03)
+    od, oc = synth.raycast(c["scene"], c["cam"], tt, qq, rng, 0.01, 0.02)
+    od = od.astype(np.float32); oc = oc.astype(np.float32)
+    cur = synth.pose7(*synth.perturb_pose(rng, tt, qq, 0.01, 0.01))
+    cam = cam_of(c["cam"])
+    anchor = {k: t(v, torch.uint8 if v.dtype == np.uint8 else torch.float32) for k, v in a32.items()
+              if k in ("depth", "rgb", "mask", "normals", "nmask")}
+    out = P().track_p2(cam, P().poses_tensor(cur), P().poses_tensor(prev), t(od), t(oc), anchor,
+                       P().Weights.make(), want_J=True, want_resid=True)
+    torch.cuda.synchronize()
+    ref = orc.track_p2(orc.cam_from(c["cam"]), cur, prev, od, oc, a64, orc.Params(), want_J=True)
+    rm = out["rowmask"].cpu().numpy()
+    assert np.mean(rm != ref["rowmask"]) < 2e-3
+    same = (rm == ref["rowmask"]) & (rm > 0)
+    assert same.sum() > 1000
+    r = out["resid"].cpu().numpy()
+    assert np.max(np.abs(r[same] - ref["resid"][same])) < 1e-5
+    J = out["J"].cpu().numpy()
+    scale = np.median(np.abs(ref["J"][same]), axis=0) + 1e-6
+    err = np.abs(J[same] - ref["J"][same]) / np.maximum(np.abs(ref["J"][same]), scale)
+    assert np.quantile(err, 0.999) < 1e-3, np.quantile(err, 0.999)
+    _neq_close(out["neq"][0].cpu().numpy(), ref["neq"])
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("warm", [False, True])
+def test_map_update(case1, dtype, warm):
+    banner(f"map_update 64^3 dtype={dtype} warm={warm}")
+    c, mean_gt, _ = case1
+    n = c["scene"].n
+    if warm:
+        mean = mean_gt.copy()
+        var = np.full_like(mean, 0.25)
+    else:
+        mean = np.zeros((4, n, n, n)); mean[0] = -0.001
+        var = np.full_like(mean, 1e4)
+    g = grid_of(c["scene"], dtype)
+    cam = cam_of(c["cam"])
+    vm = gpu_map(g, mean, var)
+    rng = np.random.default_rng(5)
+    od, oc = synth.raycast(c["scene"], c["cam"], c["t_gt"], c["q_gt"], rng, 0.01, 0.02)
+    od = od.astype(np.float32); oc = oc.astype(np.float32)
+    od[3, 5] = np.nan; od[10, 10] = -1.0; od[20, 7] = np.inf   # invalid observations
+    pose = synth.pose7(c["t_init"], c["q_init"])
+    p = orc.Params()
+    nupd = P().map_update(g, vm, cam, P().poses_tensor(pose), t(od), t(oc), p.trunc_voxels * g.voxel, 1.0)
+    m2, v2 = vm.to_dense()
+    torch.cuda.synchronize()
+    om = oracle_map_values(mean, dtype)
+    ov = oracle_map_values(var, dtype)
+    m0, v0 = om.copy(), ov.copy()
+    cnt, upd = orc.map_update(orc.grid_from_scene(c["scene"]), om, ov, orc.cam_from(c["cam"]), pose, od, oc, p,
+                              decide32=True, want_mask=True)
+    assert int(nupd.item()) == cnt > 1000
+    m2 = m2.cpu().numpy().astype(np.float64)
+    v2 = v2.cpu().numpy().astype(np.float64)
+    u = upd.astype(bool)
+    # unchanged voxels are bitwise unchanged
+    np.testing.assert_array_equal(m2[:, ~u], m0[:, ~u])
+    np.testing.assert_array_equal(v2[:, ~u], v0[:, ~u])
+    if dtype == 0:
+        assert np.max(np.abs(m2[:, u] - om[:, u]) / np.maximum(np.abs(om[:, u]), 1e-3)) < 1e-5
+        assert np.max(np.abs(v2[:, u] - ov[:, u]) / ov[:, u]) < 1e-6
+    else:
+        # one BF16 rounding of a value that differs from the FP64 one by ~1e-7
+        ref_m = synth.bf16_round(om[:, u]).astype(np.float64)
+        ulp = np.abs(synth.bf16_round(np.abs(om[:, u]) * (1 + 2 ** -7)).astype(np.float64) - np.abs(ref_m))
+        assert np.all(np.abs(m2[:, u] - ref_m) <= ulp + 1e-30)
+        ref_v = synth.bf16_round(ov[:, u]).astype(np.float64)
+        assert np.all(np.abs(v2[:, u] - ref_v) <= 2 ** -7 * ref_v)
+
+
+def test_map_update_full_size(case2):
+    """256^3 map, 320x240 frame: the updated set is identical voxel for voxel."""
+    banner("map_update 256^3 320x240")
+    c, _, _ = case2
+    n = c["scene"].n
+    g = grid_of(c["scene"])
+    cam = cam_of(c["cam"])
+    vm = P().VoxelMap(g).init()
+    tr = c["traj"]
+    pose = synth.pose7(tr.t[2], tr.q[2])
+    od = c["depth"][2]; oc = c["rgb"][2]
+    p = orc.Params()
+    nupd = P().map_update(g, vm, cam, P().poses_tensor(pose), t(od), t(oc), p.trunc_voxels * g.voxel, 1.0)
+    m2, v2 = vm.to_dense()
+    om = np.zeros((4, n, n, n)); om[0] = np.float32(-0.001)
+    ov = np.full_like(om, 1e4)
+    cnt, upd = orc.map_update(orc.grid_from_scene(c["scene"]), om, ov, orc.cam_from(c["cam"]), pose, od, oc, p,
+                              want_mask=True)
+    assert int(nupd.item()) == cnt > 100000
+    changed = (v2[0].cpu().numpy() != np.float32(1e4))
+    np.testing.assert_array_equal(changed, upd.astype(bool))
+    u = upd.astype(bool)
+    m2 = m2.cpu().numpy()
+    assert np.max(np.abs(m2[0][u] - om[0][u])) < 1e-6
+
+
+# ---------------------------------------------------------------------------
+def test_render_vjp(case1):
+    banner("render_vjp 64^3")
+    c, mean, var = case1
+    g = grid_of(c["scene"])
+    cam = cam_of(c["cam"])
+    vm = gpu_map(g, mean, var)
+    pose = synth.pose7(c["t_init"], c["q_init"])
+    pt = P().poses_tensor(pose)
+    fwd = P().render(g, vm, cam, pt, hit_k=True)
+    rng = np.random.default_rng(6)
+    H, W = cam.height, cam.width
+    gd = rng.normal(size=(1, H, W)).astype(np.float32)
+    gc = rng.normal(size=(1, H, W, 3)).astype(np.float32)
+    gm, gp = P().render_vjp(g, vm, cam, pt, fwd["hit_k"], t(gd), t(gc))
+    gm_dense = P().bricks_to_dense(g.n, gm).cpu().numpy()
+    torch.cuda.synchronize()
+    rgm, rgp = orc.render_vjp(orc.grid_from_scene(c["scene"]), mean.astype(np.float32).astype(np.float64),
+                              orc.cam_from(c["cam"]), pose, gd[0], gc[0])
+    assert np.linalg.norm(gp[0].cpu().numpy() - rgp) <= 1e-4 * np.linalg.norm(rgp)
+    nz = (np.abs(rgm) > 0) | (np.abs(gm_dense) > 0)
+    assert np.linalg.norm(gm_dense[nz] - rgm[nz]) <= 1e-5 * np.linalg.norm(rgm[nz])
+
+
+# ---------------------------------------------------------------------------
+def _filter_run(n, width, n_frames, objective, dtype=0):
+    c = synth.trajectory_case(seed=2, n=n, width=width, height=width * 3 // 4, n_samples=n // 2,
+                              n_frames=n_frames)
+    tr = c["traj"]
+    g = grid_of(c["scene"], dtype)
+    cam = cam_of(c["cam"])
+    fp = P().FilterParams(objective=objective)
+    f = P().Filter(g, cam, fp)
+    f.map.init()
+    x0 = np.concatenate([tr.t[0], tr.q[0], tr.v[0], tr.w[0]])
+    P0 = np.diag([1e-6] * 6 + [1e-4] * 6)
+    f.reset(x0, P0)
+    og = orc.grid_from_scene(c["scene"])
+    mean = np.zeros((4, n, n, n)); mean[0] = np.float32(-0.001)
+    var = np.full_like(mean, 1e4)
+    of = orc.Filter(og, orc.cam_from(c["cam"]), orc.Params(objective="p1" if objective else "p2"),
+                    dict(t=tr.t[0], q=tr.q[0], v=tr.v[0], w=tr.w[0]), P0, mean, var)
+    D = t(c["depth"]); C = t(c["rgb"]); U = t(tr.u, torch.float64)
+    res = []
+    for i in range(n_frames):
+        f.step(D[i], C[i], U[i - 1] if i else None)
+        of.step(c["depth"][i].astype(np.float64), c["rgb"][i].astype(np.float64), tr.u[i - 1] if i else None)
+        s = f.state()
+        res.append((np.array(s.pose.t), np.array(s.pose.q), np.array(s.v), np.array(s.w),
+                    np.array(s.P).reshape(12, 12), s.flags, of.s.t.copy(), of.s.q.copy(), of.s.v.copy(),
+                    of.s.w.copy(), of.s.P.copy(), int(s.n_updated), of.s.last["n_updated"]))
+    return res
+
+
+@pytest.mark.parametrize("objective", [0, 1])
+def test_filter_steps_match_oracle(objective):
+    banner(f"filter 128^3 160x120 objective={objective}")
+    res = _filter_run(128, 160, 6, objective)
+    for i, (tg, qg, vg, wg, Pg, flags, to, qo, vo, wo, Po, nu_g, nu_o) in enumerate(res):
+        assert flags == 0
+        assert np.linalg.norm(tg - to) <= 1e-5, (i, np.linalg.norm(tg - to))
+        assert rot_angle(qg, qo) <= 1e-5, (i, rot_angle(qg, qo))
+        assert np.linalg.norm(vg - vo) <= 1e-4, i
+        assert np.linalg.norm(Pg - Po) <= 1e-4 * np.linalg.norm(Po), (i, np.linalg.norm(Pg - Po) / np.linalg.norm(Po))
+        assert abs(nu_g - nu_o) <= max(10, 1e-4 * nu_o), (i, nu_g, nu_o)
