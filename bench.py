@@ -53,7 +53,7 @@ def main():
 
     dev = "cuda"
     torch.cuda.set_device(0)
-    n_frames = 1 + args.warmup + args.steps
+    n_frames = 2 + args.warmup + args.steps
     N, Wd, Ht, K = 256, 320, 240, 128
     t0 = time.time()
     case = synth.trajectory_case(seed=1, n=N, width=Wd, height=Ht, n_samples=K, n_frames=min(n_frames, 300))
@@ -128,8 +128,8 @@ def main():
     total_ms = evs[0].elapsed_time(evs[-1])
     ms_per_step = total_ms / args.steps
     st = f.state()
-    gt = np.concatenate([tr.t[min(int(idx.item()) - 1, nf - 1)]])
-    pos_err = float(np.linalg.norm(np.array(st.pose.t) - gt))
+    last = int(st.step) - 1                      # frame index of the last step
+    pos_err = float(np.linalg.norm(np.array(st.pose.t) - tr.t[min(last, nf - 1)]))
     log(f"{args.steps} steps: {ms_per_step:.3f} ms/step (events), wall {wall * 1e3 / args.steps:.3f} ms/step, "
         f"pos err {pos_err:.4f} m, flags {st.flags}")
 

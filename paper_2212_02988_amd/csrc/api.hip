@@ -105,9 +105,28 @@ CamC cam_c(const prism_camera* c) {
     return o;
 }
 
-WeightsC weights_c(const prism_weights* w) {
-    return WeightsC{(float)w->w_depth, (float)w->w_rgb, (float)w->gate_depth, (float)w->gate_rgb};
+GridD grid_d(const prism_grid* g) {
+    GridD o;
+    for (int i = 0; i < 3; ++i) o.o[i] = g->origin[i];
+    o.s = g->voxel;
+    o.occ_out = g->occ_out;
+    o.rgb_out = g->rgb_out;
+    return o;
 }
+
+CamD cam_d(const prism_camera* c) {
+    CamD o;
+    o.fx = c->fx;
+    o.fy = c->fy;
+    o.cx = c->cx;
+    o.cy = c->cy;
+    o.dn = c->d_near;
+    o.step = (c->d_far - c->d_near) / (c->n_samples - 1);
+    o.tau = c->tau;
+    return o;
+}
+
+WeightsC weights_c(const prism_weights* w) { return WeightsC{w->w_depth, w->w_rgb, w->gate_depth, w->gate_rgb}; }
 
 size_t elem_size(int dtype) { return dtype == PRISM_BF16 ? 2 : 4; }
 
@@ -127,6 +146,8 @@ struct prism_filter {
     prism_filter_cfg cfg;
     GridC g;
     CamC c;
+    GridD gd;
+    CamD cd;
     WeightsC w;
     TransC tc;
     prism_filter_state* S;
@@ -195,11 +216,12 @@ prism_status check_frame(const prism_frame* fr, bool need_u) {
 // objective at S->iter into the handle's partials; returns the block count
 prism_status eval_objective(prism_filter* f, const prism_frame* fr, int* nb, hipStream_t st) {
     if (f->cfg.objective == PRISM_OBJ_P1) {
-        HIP_TRY(launch_render_jac(f->g, f->c, f->cfg.grid.dtype, f->map, &f->S->iter, 1, fr->depth, fr->rgb, f->w,
+        HIP_TRY(launch_render_jac(f->g, f->c, f->gd, f->cd, f->cfg.grid.dtype, f->map, &f->S->iter, 1, fr->depth,
+                                  fr->rgb, f->w,
                                   nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, f->partials, st));
         *nb = render_blocks(f->c);
     } else {
-        HIP_TRY(launch_track_p2(f->c, &f->S->iter, &f->S->anchor, fr->depth, fr->rgb, f->a_depth, f->a_rgb,
+        HIP_TRY(launch_track_p2(f->c, f->cd, &f->S->iter, &f->S->anchor, fr->depth, fr->rgb, f->a_depth, f->a_rgb,
                                 f->a_mask, f->a_normals, f->a_nmask, f->w, nullptr, nullptr, nullptr, f->partials,
                                 st));
         *nb = track_blocks(f->c);
@@ -221,10 +243,10 @@ prism_status pose_update_impl(prism_filter* f, const prism_frame* fr, hipStream_
 }
 
 prism_status map_and_anchor(prism_filter* f, const prism_frame* fr, hipStream_t st) {
-    HIP_TRY(launch_map_update(f->g, f->c, f->cfg.grid.dtype, f->map, &f->S->pose, fr->depth, fr->rgb,
-                              (float)f->cfg.map.trunc, (float)f->cfg.map.lam_update, &f->S->n_updated, st));
-    HIP_TRY(launch_render(f->g, f->c, f->cfg.grid.dtype, f->map, &f->S->pose, 1, f->a_depth, f->a_rgb, f->a_mask,
-                          nullptr, st));
+    HIP_TRY(launch_map_update(f->g, f->c, f->gd, f->cfg.grid.dtype, f->map, &f->S->pose, fr->depth, fr->rgb,
+                              f->cfg.map.trunc, f->cfg.map.lam_update, &f->S->n_updated, st));
+    HIP_TRY(launch_render(f->g, f->c, f->gd, f->cd, f->cfg.grid.dtype, f->map, &f->S->pose, 1, f->a_depth, f->a_rgb,
+                          f->a_mask, nullptr, st));
     HIP_TRY(launch_normals(f->c, 1, f->a_depth, f->a_mask, (float)f->cfg.normal_disc, f->a_normals, f->a_nmask,
                            st));
     return PRISM_OK;
@@ -324,7 +346,8 @@ prism_status prism_render(const prism_grid* grid, const void* map, const prism_c
     REQUIRE(!normals || (nmask && aligned(normals, 4)), "normals needs nmask (and 4-byte alignment)");
     REQUIRE(!normals || !isnan(normal_disc), "normal_disc is NaN");
     CamC c = cam_c(cam);
-    HIP_TRY(launch_render(grid_c(grid), c, grid->dtype, map, poses, n_frames, depth, rgb, mask, hit_k, stream));
+    HIP_TRY(launch_render(grid_c(grid), c, grid_d(grid), cam_d(cam), grid->dtype, map, poses, n_frames, depth, rgb,
+                          mask, hit_k, stream));
     if (normals) HIP_TRY(launch_normals(c, n_frames, depth, mask, (float)normal_disc, normals, nmask, stream));
     return PRISM_OK;
 }
@@ -356,7 +379,8 @@ prism_status prism_render_jacobian(const prism_grid* grid, const void* map, cons
     REQUIRE(workspace && aligned(workspace, 8) && workspace_bytes >= reduce_bytes(c, n_frames),
             "workspace too small: need %zu bytes", reduce_bytes(c, n_frames));
     double* part = (double*)workspace;
-    HIP_TRY(launch_render_jac(grid_c(grid), c, grid->dtype, map, poses, n_frames, obs_depth, obs_rgb, weights_c(w),
+    HIP_TRY(launch_render_jac(grid_c(grid), c, grid_d(grid), cam_d(cam), grid->dtype, map, poses, n_frames, obs_depth,
+                              obs_rgb, weights_c(w),
                               depth, rgb, mask, J, resid, rowmask, part, stream));
     HIP_TRY(launch_finalize(part, render_blocks(c), n_frames, PRISM_NEQ, neq, PRISM_NEQ, stream));
     return PRISM_OK;
@@ -380,7 +404,7 @@ prism_status prism_track_p2(const prism_camera* cam, const prism_pose* pose, con
     REQUIRE(workspace && aligned(workspace, 8) && workspace_bytes >= reduce_bytes(c, 1),
             "workspace too small: need %zu bytes", reduce_bytes(c, 1));
     double* part = (double*)workspace;
-    HIP_TRY(launch_track_p2(c, pose, pose_prev, obs_depth, obs_rgb, anchor_depth, anchor_rgb, anchor_mask,
+    HIP_TRY(launch_track_p2(c, cam_d(cam), pose, pose_prev, obs_depth, obs_rgb, anchor_depth, anchor_rgb, anchor_mask,
                             anchor_normals, anchor_nmask, weights_c(w), J, resid, rowmask, part, stream));
     HIP_TRY(launch_finalize(part, track_blocks(c), 1, PRISM_NEQ, neq, PRISM_NEQ, stream));
     return PRISM_OK;
@@ -404,7 +428,7 @@ prism_status prism_render_vjp(const prism_grid* grid, const void* map, const pri
     REQUIRE(workspace && aligned(workspace, 8) && workspace_bytes >= reduce_bytes(c, n_frames),
             "workspace too small: need %zu bytes", reduce_bytes(c, n_frames));
     double* part = (double*)workspace;
-    HIP_TRY(launch_render_vjp(grid_c(grid), c, (const float*)map, poses, n_frames, hit_k, g_depth, g_rgb, grad_mean,
+    HIP_TRY(launch_render_vjp(grid_c(grid), c, grid_d(grid), cam_d(cam), (const float*)map, poses, n_frames, hit_k, g_depth, g_rgb, grad_mean,
                               part, stream));
     HIP_TRY(launch_finalize(part, render_blocks(c), n_frames, 6, grad_pose, 6, stream));
     return PRISM_OK;
@@ -421,8 +445,8 @@ prism_status prism_map_update(const prism_grid* grid, void* map, const prism_cam
     REQUIRE(p && isfinite(p->trunc) && p->trunc > 0 && isfinite(p->lam_update) && p->lam_update > 0,
             "map params: trunc and lam_update must be finite and > 0");
     REQUIRE(!n_updated || aligned(n_updated, 8), "n_updated misaligned");
-    HIP_TRY(launch_map_update(grid_c(grid), cam_c(cam), grid->dtype, map, pose, obs_depth, obs_rgb, (float)p->trunc,
-                              (float)p->lam_update, n_updated, stream));
+    HIP_TRY(launch_map_update(grid_c(grid), cam_c(cam), grid_d(grid), grid->dtype, map, pose, obs_depth, obs_rgb,
+                              p->trunc, p->lam_update, n_updated, stream));
     return PRISM_OK;
 }
 
@@ -445,6 +469,8 @@ prism_status prism_filter_create(const prism_filter_cfg* cfg, void* state_mem, v
     f->cfg = *cfg;
     f->g = grid_c(&cfg->grid);
     f->c = cam_c(&cfg->cam);
+    f->gd = grid_d(&cfg->grid);
+    f->cd = cam_d(&cfg->cam);
     f->w = weights_c(&cfg->w);
     f->tc.dt = cfg->dt;
     for (int i = 0; i < 3; ++i) {

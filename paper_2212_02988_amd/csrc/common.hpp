@@ -47,6 +47,21 @@ struct CamC {
     int W, H, K;
 };
 
+// Double-precision copies of the parameters for the value path: once the
+// integer decisions are taken, values (sample points, interpolation weights,
+// occupancies, depths, colours, camera depths of voxels) are computed in
+// double precision from the definitions and rounded once on output.
+struct GridD {
+    double o[3];
+    double s;
+    double occ_out, rgb_out;
+};
+
+struct CamD {
+    double fx, fy, cx, cy;
+    double dn, step, tau;
+};
+
 // ---------------------------------------------------------------------------
 // pose -> single-precision rotation/translation
 // ---------------------------------------------------------------------------
@@ -81,6 +96,12 @@ __device__ inline Pose64 load_pose64(const prism_pose* pp) {
     quat_to_rot64(p, o.R);
     for (int i = 0; i < 3; ++i) o.t[i] = p.t[i];
     return o;
+}
+
+__device__ __forceinline__ void pixel_dir64(const CamD& c, int u, int v, double r[3]) {
+    r[0] = (((double)u + 0.5) - c.cx) / c.fx;
+    r[1] = (((double)v + 0.5) - c.cy) / c.fy;
+    r[2] = 1.0;
 }
 
 __device__ inline Pose32 to32(const Pose64& p) {
@@ -211,19 +232,24 @@ __device__ inline void block_reduce29(double acc[PRISM_NEQ], double* lds, double
     }
 }
 
-__device__ __forceinline__ void neq_add(double acc[PRISM_NEQ], const float j[6], float r, float w) {
+// one residual row (Jacobian row j, residual r, weight w) into the
+// 29-double normal equations, products formed in double precision
+__device__ __forceinline__ void neq_add(double acc[PRISM_NEQ], const float j[6], double r, double w) {
+    double jd[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) jd[a] = (double)j[a];
     int q = 0;
 #pragma unroll
     for (int a = 0; a < 6; ++a)
 #pragma unroll
-        for (int b = a; b < 6; ++b) acc[q++] += (double)(w * j[a] * j[b]);
+        for (int b = a; b < 6; ++b) acc[q++] += w * jd[a] * jd[b];
 #pragma unroll
-    for (int a = 0; a < 6; ++a) acc[21 + a] += (double)(w * j[a] * r);
-    acc[27] += (double)(w * r * r);
+    for (int a = 0; a < 6; ++a) acc[21 + a] += w * jd[a] * r;
+    acc[27] += w * r * r;
 }
 
 struct WeightsC {
-    float w_depth, w_rgb, gate_depth, gate_rgb;
+    double w_depth, w_rgb, gate_depth, gate_rgb;
 };
 
 __device__ __forceinline__ bool depth_ok(float d) { return d > 0.0f && isfinite(d); }

@@ -15,19 +15,19 @@ struct TransC {
 int render_blocks(const CamC& c);
 int track_blocks(const CamC& c);
 
-hipError_t launch_render(const GridC& g, const CamC& c, int dtype, const void* map, const prism_pose* poses,
-                         int n_frames, float* depth, float* rgb, uint8_t* mask, int32_t* hit_k,
-                         hipStream_t st);
+hipError_t launch_render(const GridC& g, const CamC& c, const GridD& gd, const CamD& cd, int dtype, const void* map,
+                         const prism_pose* poses, int n_frames, float* depth, float* rgb, uint8_t* mask,
+                         int32_t* hit_k, hipStream_t st);
 hipError_t launch_normals(const CamC& c, int n_frames, const float* depth, const uint8_t* mask, float disc,
                           float* normals, uint8_t* nmask, hipStream_t st);
-hipError_t launch_render_jac(const GridC& g, const CamC& c, int dtype, const void* map, const prism_pose* poses,
-                             int n_frames, const float* obs_depth, const float* obs_rgb, const WeightsC& w,
-                             float* depth, float* rgb, uint8_t* mask, float* J, float* resid,
-                             uint8_t* rowmask, double* partials, hipStream_t st);
-hipError_t launch_render_vjp(const GridC& g, const CamC& c, const float* map, const prism_pose* poses,
-                             int n_frames, const int32_t* hit_k, const float* g_depth, const float* g_rgb,
-                             float* grad_mean, double* partials, hipStream_t st);
-hipError_t launch_track_p2(const CamC& c, const prism_pose* pose, const prism_pose* pose_prev,
+hipError_t launch_render_jac(const GridC& g, const CamC& c, const GridD& gd, const CamD& cd, int dtype,
+                             const void* map, const prism_pose* poses, int n_frames, const float* obs_depth,
+                             const float* obs_rgb, const WeightsC& w, float* depth, float* rgb, uint8_t* mask,
+                             float* J, float* resid, uint8_t* rowmask, double* partials, hipStream_t st);
+hipError_t launch_render_vjp(const GridC& g, const CamC& c, const GridD& gd, const CamD& cd, const float* map,
+                             const prism_pose* poses, int n_frames, const int32_t* hit_k, const float* g_depth,
+                             const float* g_rgb, float* grad_mean, double* partials, hipStream_t st);
+hipError_t launch_track_p2(const CamC& c, const CamD& cd, const prism_pose* pose, const prism_pose* pose_prev,
                            const float* obs_depth, const float* obs_rgb, const float* a_depth,
                            const float* a_rgb, const uint8_t* a_mask, const float* a_normals,
                            const uint8_t* a_nmask, const WeightsC& w, float* J, float* resid,
@@ -42,8 +42,8 @@ hipError_t launch_from_dense(const GridC& g, int dtype, void* map, const float* 
 hipError_t launch_to_dense(const GridC& g, int dtype, const void* map, float* mean4, float* var4,
                            hipStream_t st);
 hipError_t launch_planes(int n, int channels, const float* src, float* dst, int to_dense, hipStream_t st);
-hipError_t launch_map_update(const GridC& g, const CamC& c, int dtype, void* map, const prism_pose* pose,
-                             const float* depth, const float* rgb, float trunc, float lam_u,
+hipError_t launch_map_update(const GridC& g, const CamC& c, const GridD& gd, int dtype, void* map,
+                             const prism_pose* pose, const float* depth, const float* rgb, double trunc, double lam_u,
                              int64_t* n_updated, hipStream_t st);
 
 hipError_t launch_predict(prism_filter_state* S, const double* u, const TransC& tc, hipStream_t st);

@@ -80,7 +80,8 @@ __global__ __launch_bounds__(256) void k_planes(int n, int nb, int channels, con
 __global__ void k_zero_i64(int64_t* p) { *p = 0; }
 
 struct MapUpdC {
-    float trunc, lam_u;
+    float trunc32;          // decision: z <= D + trunc in single precision
+    double trunc, lam_u;    // values
 };
 
 // Conservative brick cull: true if no voxel centre of the brick can pass the
@@ -109,15 +110,17 @@ __device__ inline bool brick_culled(const GridC& g, const CamC& c, const Pose32&
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_map_update(GridC g, CamC c, T* __restrict__ map,
+__global__ __launch_bounds__(256) void k_map_update(GridC g, CamC c, GridD gd, T* __restrict__ map,
                                                     const prism_pose* __restrict__ pose,
                                                     const float* __restrict__ depth,
                                                     const float* __restrict__ rgb, MapUpdC mp,
                                                     int64_t* __restrict__ n_updated) {
     __shared__ Pose32 sp;
+    __shared__ Pose64 sp64;
     __shared__ int s_cnt;
     if (threadIdx.x == 0) {
-        sp = to32(load_pose64(pose));
+        sp64 = load_pose64(pose);
+        sp = to32(sp64);
         s_cnt = 0;
     }
     __syncthreads();
@@ -142,17 +145,29 @@ __global__ __launch_bounds__(256) void k_map_update(GridC g, CamC c, T* __restri
         if (!(uu >= 0.0f && uu < (float)c.W && vv >= 0.0f && vv < (float)c.H)) continue;
         int pix = (int)vv * c.W + (int)uu;
         float D = depth[pix];
-        if (!(depth_ok(D) && X[2] <= D + mp.trunc)) continue;
-        float f[4] = {fmaxf(X[2] - D, -mp.trunc), rgb[3 * pix], rgb[3 * pix + 1], rgb[3 * pix + 2]};
+        if (!(depth_ok(D) && X[2] <= D + mp.trunc32)) continue;
+        // values in double precision: camera depth of the voxel centre,
+        // truncated negative SDF, Gaussian product in precision form
+        const Pose64& Q = sp64;
+        double dd0 = (gd.o[0] + gd.s * ((double)i + 0.5)) - Q.t[0];
+        double dd1 = (gd.o[1] + gd.s * ((double)j + 0.5)) - Q.t[1];
+        double dd2 = (gd.o[2] + gd.s * ((double)k + 0.5)) - Q.t[2];
+        double z = Q.R[0][2] * dd0 + Q.R[1][2] * dd1 + Q.R[2][2] * dd2;
+        double f[4];
+        f[0] = z - (double)D;
+        if (f[0] < -mp.trunc) f[0] = -mp.trunc;
+        f[1] = (double)rgb[3 * pix];
+        f[2] = (double)rgb[3 * pix + 1];
+        f[3] = (double)rgb[3 * pix + 2];
         long long id = (b << 9) | l;
 #pragma unroll
         for (int ch = 0; ch < 4; ++ch) {
-            float mu = ld(map, ch * g.nvox + id);
-            float var = ld(map, (4 + ch) * g.nvox + id);
-            float lam = 1.0f / var;
-            float lam2 = lam + mp.lam_u;
-            st(map, ch * g.nvox + id, (lam * mu + mp.lam_u * f[ch]) / lam2);
-            st(map, (4 + ch) * g.nvox + id, 1.0f / lam2);
+            double mu = (double)ld(map, ch * g.nvox + id);
+            double var = (double)ld(map, (4 + ch) * g.nvox + id);
+            double lam = 1.0 / var;
+            double lam2 = lam + mp.lam_u;
+            st(map, ch * g.nvox + id, (float)((lam * mu + mp.lam_u * f[ch]) / lam2));
+            st(map, (4 + ch) * g.nvox + id, (float)(1.0 / lam2));
         }
         ++cnt;
     }
@@ -200,20 +215,20 @@ hipError_t launch_planes(int n, int channels, const float* src, float* dst, int 
     return hipGetLastError();
 }
 
-hipError_t launch_map_update(const GridC& g, const CamC& c, int dtype, void* map, const prism_pose* pose,
-                             const float* depth, const float* rgb, float trunc, float lam_u,
+hipError_t launch_map_update(const GridC& g, const CamC& c, const GridD& gd, int dtype, void* map,
+                             const prism_pose* pose, const float* depth, const float* rgb, double trunc, double lam_u,
                              int64_t* n_updated, hipStream_t st) {
     if (n_updated) {
         k_zero_i64<<<1, 1, 0, st>>>(n_updated);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    MapUpdC mp{trunc, lam_u};
+    MapUpdC mp{(float)trunc, trunc, lam_u};
     unsigned nbricks = (unsigned)((long long)g.nb * g.nb * g.nb);
     if (dtype == PRISM_BF16)
-        k_map_update<uint16_t><<<nbricks, 256, 0, st>>>(g, c, (uint16_t*)map, pose, depth, rgb, mp, n_updated);
+        k_map_update<uint16_t><<<nbricks, 256, 0, st>>>(g, c, gd, (uint16_t*)map, pose, depth, rgb, mp, n_updated);
     else
-        k_map_update<float><<<nbricks, 256, 0, st>>>(g, c, (float*)map, pose, depth, rgb, mp, n_updated);
+        k_map_update<float><<<nbricks, 256, 0, st>>>(g, c, gd, (float*)map, pose, depth, rgb, mp, n_updated);
     return hipGetLastError();
 }
 

@@ -67,27 +67,82 @@ __device__ __forceinline__ RayHit march(const GridC& g, const CamC& c, const Pos
 }
 
 struct Shade {
-    float depth, rgb[3], alpha, d0, d1;
+    float alpha, d0, d1;       // single-precision copies for the Jacobian
     float c0[3], c1[3];
+    float w0[3], w1[3];        // interpolation weights from the double-precision points
+    double depth, rgb[3];      // double-precision values at the hit
+    double f0, f1;
 };
 
+// trilinear value of one plane in double precision: cell from the decision
+// recipe, weights from the double-precision grid coordinate, sum over the 8
+// corners of the product of 1-D hat weights (z, y, x order)
 template <typename T>
-__device__ __forceinline__ Shade shade(const GridC& g, const CamC& c, const T* map, const RayHit& h) {
+__device__ __forceinline__ double tri64(const GridC& g, const T* plane, const double gc[3], const int cell[3],
+                                        double outv) {
+    double w0 = gc[0] - (double)cell[0], w1 = gc[1] - (double)cell[1], w2 = gc[2] - (double)cell[2];
+    double s = 0.0;
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+            for (int cx = 0; cx < 2; ++cx) {
+                double hx = cx ? w0 : 1.0 - w0;
+                double hy = cy ? w1 : 1.0 - w1;
+                double hz = cz ? w2 : 1.0 - w2;
+                int i = cell[0] + cx, j = cell[1] + cy, k = cell[2] + cz;
+                bool in = (unsigned)i < (unsigned)g.n && (unsigned)j < (unsigned)g.n && (unsigned)k < (unsigned)g.n;
+                double V = in ? (double)ld(plane, vidx(g, i, j, k)) : outv;
+                s += hx * hy * hz * V;
+            }
+    return s;
+}
+
+// double-precision sample point k of the ray with direction dir (world)
+__device__ __forceinline__ void grid_coord64(const GridD& gd, const CamD& cd, const Pose64& P, const double dir[3],
+                                             int k, double gc[3]) {
+    double dk = cd.dn + (double)k * cd.step;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double p = P.t[a] + dk * dir[a];
+        gc[a] = (p - gd.o[a]) / gd.s - 0.5;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ Shade shade(const GridC& g, const GridD& gd, const CamD& cd, const Pose64& P, int u,
+                                       int v, const T* map, const RayHit& h) {
     Shade s;
-    s.d0 = c.dn + (float)(h.k - 1) * c.dstep;
-    s.d1 = c.dn + (float)h.k * c.dstep;
-    s.alpha = (c.tau - h.f0) / (h.f1 - h.f0);
-    s.depth = s.alpha * s.d1 + (1.0f - s.alpha) * s.d0;
+    double rc[3], dir[3], gc0[3], gc1[3];
+    pixel_dir64(cd, u, v, rc);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dir[a] = P.R[a][0] * rc[0] + P.R[a][1] * rc[1] + P.R[a][2] * rc[2];
+    grid_coord64(gd, cd, P, dir, h.k - 1, gc0);
+    grid_coord64(gd, cd, P, dir, h.k, gc1);
+    double d0 = cd.dn + (double)(h.k - 1) * cd.step;
+    double d1 = cd.dn + (double)h.k * cd.step;
+    s.f0 = tri64(g, map, gc0, h.c0.i, gd.occ_out);
+    s.f1 = tri64(g, map, gc1, h.c1.i, gd.occ_out);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        s.w0[a] = (float)(gc0[a] - (double)h.c0.i[a]);
+        s.w1[a] = (float)(gc1[a] - (double)h.c1.i[a]);
+    }
+    double al = (cd.tau - s.f0) / (s.f1 - s.f0);
+    s.depth = al * d1 + (1.0 - al) * d0;
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
         const T* pl = map + (long long)(1 + ch) * g.nvox;
-        float v[8];
-        corners(g, pl, h.c0, g.rgb_out, v);
-        s.c0[ch] = trilerp(v, h.c0.w);
-        corners(g, pl, h.c1, g.rgb_out, v);
-        s.c1[ch] = trilerp(v, h.c1.w);
-        s.rgb[ch] = s.alpha * s.c1[ch] + (1.0f - s.alpha) * s.c0[ch];
+        double c0 = tri64(g, pl, gc0, h.c0.i, gd.rgb_out);
+        double c1 = tri64(g, pl, gc1, h.c1.i, gd.rgb_out);
+        s.rgb[ch] = al * c1 + (1.0 - al) * c0;
+        s.c0[ch] = (float)c0;
+        s.c1[ch] = (float)c1;
     }
+    s.alpha = (float)al;
+    s.d0 = (float)d0;
+    s.d1 = (float)d1;
     return s;
 }
 
@@ -106,9 +161,9 @@ __device__ __forceinline__ void ray_jacobian(const GridC& g, const T* map, const
     for (int i = 0; i < 3; ++i) { a0[i] = s.d0 * dir[i]; a1[i] = s.d1 * dir[i]; }
     float v[8], gr0[3], gr1[3], cr[3];
     corners(g, map, h.c0, g.occ_out, v);
-    trigrad(v, h.c0.w, gr0);
+    trigrad(v, s.w0, gr0);
     corners(g, map, h.c1, g.occ_out, v);
-    trigrad(v, h.c1.w, gr1);
+    trigrad(v, s.w1, gr1);
     float rf0[6], rf1[6];
 #pragma unroll
     for (int i = 0; i < 3; ++i) { gr0[i] *= g.inv_s; gr1[i] *= g.inv_s; rf0[i] = gr0[i]; rf1[i] = gr1[i]; }
@@ -118,7 +173,7 @@ __device__ __forceinline__ void ray_jacobian(const GridC& g, const T* map, const
     cross3(a1, gr1, cr);
 #pragma unroll
     for (int i = 0; i < 3; ++i) rf1[3 + i] = cr[i];
-    float inv_den = 1.0f / (h.f1 - h.f0);
+    float inv_den = (float)(1.0 / (s.f1 - s.f0));
     float al = s.alpha;
     float dal[6];
 #pragma unroll
@@ -130,9 +185,9 @@ __device__ __forceinline__ void ray_jacobian(const GridC& g, const T* map, const
         const T* pl = map + (long long)(1 + ch) * g.nvox;
         float G0[3], G1[3], g0[6], g1[6];
         corners(g, pl, h.c0, g.rgb_out, v);
-        trigrad(v, h.c0.w, G0);
+        trigrad(v, s.w0, G0);
         corners(g, pl, h.c1, g.rgb_out, v);
-        trigrad(v, h.c1.w, G1);
+        trigrad(v, s.w1, G1);
 #pragma unroll
         for (int i = 0; i < 3; ++i) { G0[i] *= g.inv_s; G1[i] *= g.inv_s; g0[i] = G0[i]; g1[i] = G1[i]; }
         cross3(a0, G0, cr);
@@ -155,37 +210,44 @@ __device__ __forceinline__ void tile_pixel(const CamC& c, int& u, int& v) {
     v = (by << 4) + ((wv >> 1) << 3) + (l >> 3);
 }
 
-__device__ __forceinline__ void block_pose(const prism_pose* poses, Pose32* sp, Pose32& P) {
-    if (threadIdx.x == 0) *sp = to32(load_pose64(poses + blockIdx.y));
+struct BlockPose {
+    Pose64 d;
+    Pose32 f;
+};
+
+__device__ __forceinline__ const BlockPose& block_pose(const prism_pose* poses, BlockPose* sp) {
+    if (threadIdx.x == 0) {
+        sp->d = load_pose64(poses + blockIdx.y);
+        sp->f = to32(sp->d);
+    }
     __syncthreads();
-    P = *sp;
+    return *sp;
 }
 
 // ---------------------------------------------------------------------------
 // render
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_render(GridC g, CamC c, const T* __restrict__ map,
+__global__ __launch_bounds__(256) void k_render(GridC g, CamC c, GridD gd, CamD cd, const T* __restrict__ map,
                                                 const prism_pose* __restrict__ poses,
                                                 float* __restrict__ depth, float* __restrict__ rgb,
                                                 uint8_t* __restrict__ mask, int32_t* __restrict__ hit_k) {
-    __shared__ Pose32 sp;
-    Pose32 P;
-    block_pose(poses, &sp, P);
+    __shared__ BlockPose sp;
+    const BlockPose& P = block_pose(poses, &sp);
     int u, v;
     tile_pixel(c, u, v);
     if (u >= c.W || v >= c.H) return;
     float dir[3];
-    ray_dir32(c, P, u, v, dir);
-    RayHit h = march(g, c, P, dir, map);
+    ray_dir32(c, P.f, u, v, dir);
+    RayHit h = march(g, c, P.f, dir, map);
     long long pix = (long long)blockIdx.y * c.W * c.H + (long long)v * c.W + u;
     if (hit_k) hit_k[pix] = h.k;
     if (h.k >= 1) {
-        Shade s = shade(g, c, map, h);
-        depth[pix] = s.depth;
-        rgb[3 * pix] = s.rgb[0];
-        rgb[3 * pix + 1] = s.rgb[1];
-        rgb[3 * pix + 2] = s.rgb[2];
+        Shade s = shade(g, gd, cd, P.d, u, v, map, h);
+        depth[pix] = (float)s.depth;
+        rgb[3 * pix] = (float)s.rgb[0];
+        rgb[3 * pix + 1] = (float)s.rgb[1];
+        rgb[3 * pix + 2] = (float)s.rgb[2];
         mask[pix] = 1;
     } else {
         depth[pix] = 0.0f;
@@ -238,7 +300,7 @@ __global__ __launch_bounds__(256) void k_normals(CamC c, int n_frames, const flo
 // render + P1 Jacobian + gated weighted normal equations
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, const T* __restrict__ map,
+__global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, GridD gd, CamD cd, const T* __restrict__ map,
                                                     const prism_pose* __restrict__ poses,
                                                     const float* __restrict__ obs_depth,
                                                     const float* __restrict__ obs_rgb, WeightsC wt,
@@ -246,10 +308,9 @@ __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, const T* __
                                                     uint8_t* __restrict__ mask, float* __restrict__ Jout,
                                                     float* __restrict__ resid, uint8_t* __restrict__ rowmask,
                                                     double* __restrict__ partials) {
-    __shared__ Pose32 sp;
+    __shared__ BlockPose sp;
     __shared__ double lds[PRISM_NEQ * 16];
-    Pose32 P;
-    block_pose(poses, &sp, P);
+    const BlockPose& P = block_pose(poses, &sp);
     int u, v;
     tile_pixel(c, u, v);
     double acc[PRISM_NEQ];
@@ -257,11 +318,11 @@ __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, const T* __
     for (int q = 0; q < PRISM_NEQ; ++q) acc[q] = 0.0;
     if (u < c.W && v < c.H) {
         float dir[3];
-        ray_dir32(c, P, u, v, dir);
-        RayHit h = march(g, c, P, dir, map);
+        ray_dir32(c, P.f, u, v, dir);
+        RayHit h = march(g, c, P.f, dir, map);
         long long pix = (long long)blockIdx.y * c.W * c.H + (long long)v * c.W + u;
         float J[4][6];
-        float r[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        double r[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -270,18 +331,18 @@ __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, const T* __
         bool valid = h.k >= 1;
         Shade s;
         if (valid) {
-            s = shade(g, c, map, h);
+            s = shade(g, gd, cd, P.d, u, v, map, h);
             float D = obs_depth[pix];
             if (depth_ok(D)) {
                 ray_jacobian(g, map, h, s, dir, J);
-                r[0] = s.depth - D;
-                float l1 = 0.0f;
+                r[0] = s.depth - (double)D;
+                double l1 = 0.0;
 #pragma unroll
                 for (int ch = 0; ch < 3; ++ch) {
-                    r[1 + ch] = s.rgb[ch] - obs_rgb[3 * pix + ch];
-                    l1 += fabsf(r[1 + ch]);
+                    r[1 + ch] = s.rgb[ch] - (double)obs_rgb[3 * pix + ch];
+                    l1 += fabs(r[1 + ch]);
                 }
-                if (fabsf(r[0]) <= wt.gate_depth) {
+                if (fabs(r[0]) <= wt.gate_depth) {
                     neq_add(acc, J[0], r[0], wt.w_depth);
                     rm |= 1;
                 }
@@ -299,10 +360,10 @@ __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, const T* __
                     for (int m = 0; m < 6; ++m) J[a][m] = 0.0f;
             }
         }
-        if (depth) depth[pix] = valid ? s.depth : 0.0f;
+        if (depth) depth[pix] = valid ? (float)s.depth : 0.0f;
         if (rgb) {
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) rgb[3 * pix + ch] = valid ? s.rgb[ch] : 0.0f;
+            for (int ch = 0; ch < 3; ++ch) rgb[3 * pix + ch] = valid ? (float)s.rgb[ch] : 0.0f;
         }
         if (mask) mask[pix] = valid ? 1 : 0;
         if (Jout) {
@@ -312,7 +373,8 @@ __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, const T* __
                 jo[q] = make_float4(J[(4 * q) / 6][(4 * q) % 6], J[(4 * q + 1) / 6][(4 * q + 1) % 6],
                                     J[(4 * q + 2) / 6][(4 * q + 2) % 6], J[(4 * q + 3) / 6][(4 * q + 3) % 6]);
         }
-        if (resid) reinterpret_cast<float4*>(resid)[pix] = make_float4(r[0], r[1], r[2], r[3]);
+        if (resid)
+            reinterpret_cast<float4*>(resid)[pix] = make_float4((float)r[0], (float)r[1], (float)r[2], (float)r[3]);
         if (rowmask) rowmask[pix] = rm;
     }
     block_reduce29(acc, lds, partials + ((long long)blockIdx.y * gridDim.x + blockIdx.x) * PRISM_NEQ);
@@ -321,17 +383,16 @@ __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, const T* __
 // ---------------------------------------------------------------------------
 // adjoint of render w.r.t. map means (atomic scatter) and pose
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_render_vjp(GridC g, CamC c, const float* __restrict__ map,
+__global__ __launch_bounds__(256) void k_render_vjp(GridC g, CamC c, GridD gd, CamD cd, const float* __restrict__ map,
                                                     const prism_pose* __restrict__ poses,
                                                     const int32_t* __restrict__ hit_k,
                                                     const float* __restrict__ g_depth,
                                                     const float* __restrict__ g_rgb,
                                                     float* __restrict__ grad_mean,
                                                     double* __restrict__ partials) {
-    __shared__ Pose32 sp;
+    __shared__ BlockPose sp;
     __shared__ double lds[PRISM_NEQ * 16];
-    Pose32 P;
-    block_pose(poses, &sp, P);
+    const BlockPose& P = block_pose(poses, &sp);
     int u, v;
     tile_pixel(c, u, v);
     double acc[PRISM_NEQ];
@@ -342,15 +403,15 @@ __global__ __launch_bounds__(256) void k_render_vjp(GridC g, CamC c, const float
         int k = hit_k[pix];
         if (k >= 1 && k < c.K) {
             float dir[3];
-            ray_dir32(c, P, u, v, dir);
+            ray_dir32(c, P.f, u, v, dir);
             RayHit h;
             h.k = k;
-            h.c0 = sample_cell(g, c, P, dir, k - 1);
-            h.c1 = sample_cell(g, c, P, dir, k);
+            h.c0 = sample_cell(g, c, P.f, dir, k - 1);
+            h.c1 = sample_cell(g, c, P.f, dir, k);
             h.f0 = occ_at(g, map, h.c0);
             h.f1 = occ_at(g, map, h.c1);
             if (h.f1 > c.tau && !(h.f0 > c.tau)) {
-                Shade s = shade(g, c, map, h);
+                Shade s = shade(g, gd, cd, P.d, u, v, map, h);
                 float gd = g_depth[pix];
                 float gc[3] = {g_rgb[3 * pix], g_rgb[3 * pix + 1], g_rgb[3 * pix + 2]};
                 float J[4][6];
@@ -361,7 +422,7 @@ __global__ __launch_bounds__(256) void k_render_vjp(GridC g, CamC c, const float
                 float al = s.alpha;
                 float ga = gd * (s.d1 - s.d0) + gc[0] * (s.c1[0] - s.c0[0]) + gc[1] * (s.c1[1] - s.c0[1]) +
                            gc[2] * (s.c1[2] - s.c0[2]);
-                float inv_den = 1.0f / (h.f1 - h.f0);
+                float inv_den = (float)(1.0 / (s.f1 - s.f0));
                 float gf[2] = {-ga * (1.0f - al) * inv_den, -ga * al * inv_den};
                 float cw[2] = {1.0f - al, al};
 #pragma unroll
@@ -374,8 +435,9 @@ __global__ __launch_bounds__(256) void k_render_vjp(GridC g, CamC c, const float
                         if ((unsigned)i >= (unsigned)g.n || (unsigned)j >= (unsigned)g.n ||
                             (unsigned)kk >= (unsigned)g.n)
                             continue;
-                        float hw = (dx ? cl.w[0] : 1.0f - cl.w[0]) * (dy ? cl.w[1] : 1.0f - cl.w[1]) *
-                                   (dz ? cl.w[2] : 1.0f - cl.w[2]);
+                        const float* cw3 = sm ? s.w1 : s.w0;
+                        float hw = (dx ? cw3[0] : 1.0f - cw3[0]) * (dy ? cw3[1] : 1.0f - cw3[1]) *
+                                   (dz ? cw3[2] : 1.0f - cw3[2]);
                         long long id = vidx(g, i, j, kk);
                         atomicAdd(grad_mean + id, gf[sm] * hw);
 #pragma unroll
@@ -394,14 +456,14 @@ __global__ __launch_bounds__(256) void k_render_vjp(GridC g, CamC c, const float
 // ---------------------------------------------------------------------------
 int render_blocks(const CamC& c) { return ((c.W + 15) >> 4) * ((c.H + 15) >> 4); }
 
-hipError_t launch_render(const GridC& g, const CamC& c, int dtype, const void* map, const prism_pose* poses,
-                         int n_frames, float* depth, float* rgb, uint8_t* mask, int32_t* hit_k,
-                         hipStream_t st) {
+hipError_t launch_render(const GridC& g, const CamC& c, const GridD& gd, const CamD& cd, int dtype, const void* map,
+                         const prism_pose* poses, int n_frames, float* depth, float* rgb, uint8_t* mask,
+                         int32_t* hit_k, hipStream_t st) {
     dim3 grid(render_blocks(c), n_frames);
     if (dtype == PRISM_BF16)
-        k_render<uint16_t><<<grid, 256, 0, st>>>(g, c, (const uint16_t*)map, poses, depth, rgb, mask, hit_k);
+        k_render<uint16_t><<<grid, 256, 0, st>>>(g, c, gd, cd, (const uint16_t*)map, poses, depth, rgb, mask, hit_k);
     else
-        k_render<float><<<grid, 256, 0, st>>>(g, c, (const float*)map, poses, depth, rgb, mask, hit_k);
+        k_render<float><<<grid, 256, 0, st>>>(g, c, gd, cd, (const float*)map, poses, depth, rgb, mask, hit_k);
     return hipGetLastError();
 }
 
@@ -412,25 +474,25 @@ hipError_t launch_normals(const CamC& c, int n_frames, const float* depth, const
     return hipGetLastError();
 }
 
-hipError_t launch_render_jac(const GridC& g, const CamC& c, int dtype, const void* map, const prism_pose* poses,
-                             int n_frames, const float* obs_depth, const float* obs_rgb, const WeightsC& w,
-                             float* depth, float* rgb, uint8_t* mask, float* J, float* resid,
-                             uint8_t* rowmask, double* partials, hipStream_t st) {
+hipError_t launch_render_jac(const GridC& g, const CamC& c, const GridD& gd, const CamD& cd, int dtype,
+                             const void* map, const prism_pose* poses, int n_frames, const float* obs_depth,
+                             const float* obs_rgb, const WeightsC& w, float* depth, float* rgb, uint8_t* mask,
+                             float* J, float* resid, uint8_t* rowmask, double* partials, hipStream_t st) {
     dim3 grid(render_blocks(c), n_frames);
     if (dtype == PRISM_BF16)
-        k_render_jac<uint16_t><<<grid, 256, 0, st>>>(g, c, (const uint16_t*)map, poses, obs_depth, obs_rgb, w,
-                                                     depth, rgb, mask, J, resid, rowmask, partials);
+        k_render_jac<uint16_t><<<grid, 256, 0, st>>>(g, c, gd, cd, (const uint16_t*)map, poses, obs_depth, obs_rgb,
+                                                     w, depth, rgb, mask, J, resid, rowmask, partials);
     else
-        k_render_jac<float><<<grid, 256, 0, st>>>(g, c, (const float*)map, poses, obs_depth, obs_rgb, w, depth,
-                                                  rgb, mask, J, resid, rowmask, partials);
+        k_render_jac<float><<<grid, 256, 0, st>>>(g, c, gd, cd, (const float*)map, poses, obs_depth, obs_rgb, w,
+                                                  depth, rgb, mask, J, resid, rowmask, partials);
     return hipGetLastError();
 }
 
-hipError_t launch_render_vjp(const GridC& g, const CamC& c, const float* map, const prism_pose* poses,
-                             int n_frames, const int32_t* hit_k, const float* g_depth, const float* g_rgb,
-                             float* grad_mean, double* partials, hipStream_t st) {
+hipError_t launch_render_vjp(const GridC& g, const CamC& c, const GridD& gd, const CamD& cd, const float* map,
+                             const prism_pose* poses, int n_frames, const int32_t* hit_k, const float* g_depth,
+                             const float* g_rgb, float* grad_mean, double* partials, hipStream_t st) {
     dim3 grid(render_blocks(c), n_frames);
-    k_render_vjp<<<grid, 256, 0, st>>>(g, c, map, poses, hit_k, g_depth, g_rgb, grad_mean, partials);
+    k_render_vjp<<<grid, 256, 0, st>>>(g, c, gd, cd, map, poses, hit_k, g_depth, g_rgb, grad_mean, partials);
     return hipGetLastError();
 }
 

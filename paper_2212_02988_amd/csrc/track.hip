@@ -10,12 +10,11 @@
 namespace prism {
 
 struct Rel32 {
-    float R[3][3], t[3];   // current camera -> anchor camera
-    float Rp[3][3];        // anchor rotation (camera -> world)
-    float Rc[3][3];        // current rotation (camera -> world)
+    float R[3][3], t[3];   // current camera -> anchor camera (association recipe)
+    Pose64 cur, prev;      // both poses in double precision (values)
 };
 
-__global__ __launch_bounds__(256) void k_track_p2(CamC c, const prism_pose* __restrict__ pose,
+__global__ __launch_bounds__(256) void k_track_p2(CamC c, CamD cd, const prism_pose* __restrict__ pose,
                                                   const prism_pose* __restrict__ pose_prev,
                                                   const float* __restrict__ obs_depth,
                                                   const float* __restrict__ obs_rgb,
@@ -33,13 +32,12 @@ __global__ __launch_bounds__(256) void k_track_p2(CamC c, const prism_pose* __re
         Pose64 P = load_pose64(pose), Q = load_pose64(pose_prev);
         double d[3] = {P.t[0] - Q.t[0], P.t[1] - Q.t[1], P.t[2] - Q.t[2]};
         for (int a = 0; a < 3; ++a) {
-            for (int b = 0; b < 3; ++b) {
+            for (int b = 0; b < 3; ++b)
                 srel.R[a][b] = (float)((Q.R[0][a] * P.R[0][b] + Q.R[1][a] * P.R[1][b]) + Q.R[2][a] * P.R[2][b]);
-                srel.Rp[a][b] = (float)Q.R[a][b];
-                srel.Rc[a][b] = (float)P.R[a][b];
-            }
             srel.t[a] = (float)((Q.R[0][a] * d[0] + Q.R[1][a] * d[1]) + Q.R[2][a] * d[2]);
         }
+        srel.cur = P;
+        srel.prev = Q;
     }
     __syncthreads();
     const Rel32& rel = srel;
@@ -50,7 +48,7 @@ __global__ __launch_bounds__(256) void k_track_p2(CamC c, const prism_pose* __re
     if (p < c.W * c.H) {
         int u = p % c.W, v = p / c.W;
         float J[4][6];
-        float r[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        double r[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -90,14 +88,26 @@ __global__ __launch_bounds__(256) void k_track_p2(CamC c, const prism_pose* __re
             int q00 = biy * c.W + bix;
             if (pho) pho = a_mask[q00] && a_mask[q00 + 1] && a_mask[q00 + c.W] && a_mask[q00 + c.W + 1];
             if (geo || pho) {
-                // dY/ddelta = Rp^T [I | -[R X]x]
-                float RX[3];
+                // values in double precision: back-projected point, moved into
+                // the anchor camera; Jacobians in single precision
+                const Pose64& Pc = rel.cur;
+                const Pose64& Pp = rel.prev;
+                double rc[3], Xd[3], RXd[3], dW[3], Yd[3];
+                pixel_dir64(cd, u, v, rc);
 #pragma unroll
-                for (int a = 0; a < 3; ++a) RX[a] = rel.Rc[a][0] * X[0] + rel.Rc[a][1] * X[1] + rel.Rc[a][2] * X[2];
+                for (int a = 0; a < 3; ++a) Xd[a] = (double)D * rc[a];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) RXd[a] = Pc.R[a][0] * Xd[0] + Pc.R[a][1] * Xd[1] + Pc.R[a][2] * Xd[2];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) dW[a] = RXd[a] + Pc.t[a] - Pp.t[a];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) Yd[a] = Pp.R[0][a] * dW[0] + Pp.R[1][a] * dW[1] + Pp.R[2][a] * dW[2];
+                // dY/ddelta = Rp^T [I | -[R X]x]
+                float RX[3] = {(float)RXd[0], (float)RXd[1], (float)RXd[2]};
                 float dY[3][6];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    float e0 = rel.Rp[0][a], e1 = rel.Rp[1][a], e2 = rel.Rp[2][a];
+                    float e0 = (float)Pp.R[0][a], e1 = (float)Pp.R[1][a], e2 = (float)Pp.R[2][a];
                     dY[a][0] = e0;
                     dY[a][1] = e1;
                     dY[a][2] = e2;
@@ -107,45 +117,52 @@ __global__ __launch_bounds__(256) void k_track_p2(CamC c, const prism_pose* __re
                 }
                 if (geo) {
                     int q = giv * c.W + giu;
-                    float da = a_depth[q];
-                    float ph[3] = {da * (((float)giu + 0.5f - c.cx) * c.ifx),
-                                   da * (((float)giv + 0.5f - c.cy) * c.ify), da};
-                    float n0 = a_normals[3 * q], n1 = a_normals[3 * q + 1], n2 = a_normals[3 * q + 2];
-                    r[0] = n0 * (ph[0] - Y[0]) + n1 * (ph[1] - Y[1]) + n2 * (ph[2] - Y[2]);
+                    double ra[3];
+                    pixel_dir64(cd, giu, giv, ra);
+                    double da = (double)a_depth[q];
+                    double n0 = a_normals[3 * q], n1 = a_normals[3 * q + 1], n2 = a_normals[3 * q + 2];
+                    double rg = n0 * (da * ra[0] - Yd[0]) + n1 * (da * ra[1] - Yd[1]) + n2 * (da * ra[2] - Yd[2]);
+                    r[0] = rg;
+                    float fn0 = (float)n0, fn1 = (float)n1, fn2 = (float)n2;
 #pragma unroll
-                    for (int m = 0; m < 6; ++m) J[0][m] = -(n0 * dY[0][m] + n1 * dY[1][m] + n2 * dY[2][m]);
-                    if (fabsf(r[0]) <= wt.gate_depth) {
-                        neq_add(acc, J[0], r[0], wt.w_depth);
+                    for (int m = 0; m < 6; ++m) J[0][m] = -(fn0 * dY[0][m] + fn1 * dY[1][m] + fn2 * dY[2][m]);
+                    if (fabs(rg) <= wt.gate_depth) {
+                        neq_add(acc, J[0], rg, wt.w_depth);
                         rm |= 1;
                     }
                 }
                 if (pho) {
-                    float ax = (uu - 0.5f) - (float)bix, ay = (vv - 0.5f) - (float)biy;
-                    float iz = 1.0f / Y[2];
-                    float du_[3] = {c.fx * iz, 0.0f, -c.fx * Y[0] * iz * iz};
-                    float dv_[3] = {0.0f, c.fy * iz, -c.fy * Y[1] * iz * iz};
+                    double ud = cd.fx * Yd[0] / Yd[2] + cd.cx;
+                    double vd = cd.fy * Yd[1] / Yd[2] + cd.cy;
+                    double ax = (ud - 0.5) - (double)bix, ay = (vd - 0.5) - (double)biy;
+                    float Y2 = (float)Yd[2];
+                    float iz = 1.0f / Y2;
+                    float du_[3] = {c.fx * iz, 0.0f, -c.fx * (float)Yd[0] * iz * iz};
+                    float dv_[3] = {0.0f, c.fy * iz, -c.fy * (float)Yd[1] * iz * iz};
                     float dum[6], dvm[6];
 #pragma unroll
                     for (int m = 0; m < 6; ++m) {
                         dum[m] = du_[0] * dY[0][m] + du_[2] * dY[2][m];
                         dvm[m] = dv_[1] * dY[1][m] + dv_[2] * dY[2][m];
                     }
-                    float l1 = 0.0f;
+                    double l1 = 0.0;
+                    double rp[3];
 #pragma unroll
                     for (int ch = 0; ch < 3; ++ch) {
-                        float I00 = a_rgb[3 * q00 + ch], I10 = a_rgb[3 * (q00 + 1) + ch];
-                        float I01 = a_rgb[3 * (q00 + c.W) + ch], I11 = a_rgb[3 * (q00 + c.W + 1) + ch];
-                        float Ii = (1.0f - ay) * ((1.0f - ax) * I00 + ax * I10) + ay * ((1.0f - ax) * I01 + ax * I11);
-                        float gu = (1.0f - ay) * (I10 - I00) + ay * (I11 - I01);
-                        float gv = (1.0f - ax) * (I01 - I00) + ax * (I11 - I10);
-                        r[1 + ch] = Ii - obs_rgb[3 * p + ch];
-                        l1 += fabsf(r[1 + ch]);
+                        double I00 = a_rgb[3 * q00 + ch], I10 = a_rgb[3 * (q00 + 1) + ch];
+                        double I01 = a_rgb[3 * (q00 + c.W) + ch], I11 = a_rgb[3 * (q00 + c.W + 1) + ch];
+                        double Ii = (1 - ax) * (1 - ay) * I00 + ax * (1 - ay) * I10 + (1 - ax) * ay * I01 + ax * ay * I11;
+                        float gu = (float)((1 - ay) * (I10 - I00) + ay * (I11 - I01));
+                        float gv = (float)((1 - ax) * (I01 - I00) + ax * (I11 - I10));
+                        rp[ch] = Ii - (double)obs_rgb[3 * p + ch];
+                        r[1 + ch] = rp[ch];
+                        l1 += fabs(rp[ch]);
 #pragma unroll
                         for (int m = 0; m < 6; ++m) J[1 + ch][m] = gu * dum[m] + gv * dvm[m];
                     }
                     if (l1 <= wt.gate_rgb) {
 #pragma unroll
-                        for (int ch = 0; ch < 3; ++ch) neq_add(acc, J[1 + ch], r[1 + ch], wt.w_rgb);
+                        for (int ch = 0; ch < 3; ++ch) neq_add(acc, J[1 + ch], rp[ch], wt.w_rgb);
                         rm |= 2;
                     }
                 }
@@ -159,7 +176,8 @@ __global__ __launch_bounds__(256) void k_track_p2(CamC c, const prism_pose* __re
                 jo[q] = make_float4(J[(4 * q) / 6][(4 * q) % 6], J[(4 * q + 1) / 6][(4 * q + 1) % 6],
                                     J[(4 * q + 2) / 6][(4 * q + 2) % 6], J[(4 * q + 3) / 6][(4 * q + 3) % 6]);
         }
-        if (resid) reinterpret_cast<float4*>(resid)[p] = make_float4(r[0], r[1], r[2], r[3]);
+        if (resid)
+            reinterpret_cast<float4*>(resid)[p] = make_float4((float)r[0], (float)r[1], (float)r[2], (float)r[3]);
         if (rowmask) rowmask[p] = rm;
     }
     block_reduce29(acc, lds, partials + (long long)blockIdx.x * PRISM_NEQ);
@@ -167,12 +185,12 @@ __global__ __launch_bounds__(256) void k_track_p2(CamC c, const prism_pose* __re
 
 int track_blocks(const CamC& c) { return (c.W * c.H + 255) / 256; }
 
-hipError_t launch_track_p2(const CamC& c, const prism_pose* pose, const prism_pose* pose_prev,
+hipError_t launch_track_p2(const CamC& c, const CamD& cd, const prism_pose* pose, const prism_pose* pose_prev,
                            const float* obs_depth, const float* obs_rgb, const float* a_depth,
                            const float* a_rgb, const uint8_t* a_mask, const float* a_normals,
                            const uint8_t* a_nmask, const WeightsC& w, float* J, float* resid,
                            uint8_t* rowmask, double* partials, hipStream_t st) {
-    k_track_p2<<<track_blocks(c), 256, 0, st>>>(c, pose, pose_prev, obs_depth, obs_rgb, a_depth, a_rgb,
+    k_track_p2<<<track_blocks(c), 256, 0, st>>>(c, cd, pose, pose_prev, obs_depth, obs_rgb, a_depth, a_rgb,
                                                 a_mask, a_normals, a_nmask, w, J, resid, rowmask, partials);
     return hipGetLastError();
 }
