@@ -41,6 +41,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--eager", action="store_true", help="launch each step eagerly instead of a graph")
+    ap.add_argument("--calib", action="store_true", help="also run a 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported (each agent stream is "
@@ -76,52 +77,45 @@ def main():
     f.step(D[0], C[0], None)
     torch.cuda.synchronize()
 
-    # staging slot: the graph copies frame idx (device counter) in, steps, advances idx
-    sd = torch.empty_like(D[0]); sc = torch.empty_like(C[0]); su = torch.empty_like(U[0])
-    idx = torch.ones(1, dtype=torch.int64, device=dev)
-    nfm1 = torch.tensor([nf - 1], dtype=torch.int64, device=dev)
-
-    def one_step():
-        sd.copy_(torch.index_select(D, 0, idx)[0])
-        sc.copy_(torch.index_select(C, 0, idx)[0])
-        su.copy_(torch.index_select(U, 0, idx - 1)[0])
-        f.step(sd, sc, su)
-        idx.add_(1)
-        torch.minimum(idx, nfm1, out=idx)      # hold the last frame past the end
-
+    # Each filter step is one HIP graph (13 kernels) reading its frame
+    # straight from the resident frame array; the timed region replays one
+    # graph per step, with events on the stream between steps for the
+    # per-step latencies (the launch of each graph is inside the timing).
     stream = torch.cuda.Stream()
-    graph = None
-    if not args.eager:
-        with torch.cuda.stream(stream):
-            one_step()           # the first non-initial step runs eagerly (switches the handle's path)
-        torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph, stream=stream):
-            one_step()
-        torch.cuda.synchronize()
-        # restart the trajectory: re-initialise filter + map, replay from frame 1
-        f.map.init(); f.reset(x0, P0); f.step(D[0], C[0], None); idx.fill_(1)
-        torch.cuda.synchronize()
-        with torch.cuda.stream(stream):
-            one_step()
-        torch.cuda.synchronize()
-
-    def run(k):
-        evs = [torch.cuda.Event(enable_timing=True) for _ in range(k + 1)]
-        with torch.cuda.stream(stream):
-            evs[0].record()
-            for i in range(k):
-                if graph is not None:
-                    graph.replay()
-                else:
-                    one_step()
-                evs[i + 1].record()
-        return evs
-
-    run(args.warmup)
+    f.step(D[1], C[1], U[0], stream=stream)        # first step past the initial frame, eager
     torch.cuda.synchronize()
+    t0 = time.time()
+    graphs = []
+    for i in range(2, 2 + args.warmup + args.steps):
+        if args.eager:
+            graphs.append(i)
+            continue
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr, stream=stream):
+            f.step(D[i], C[i], U[i - 1])
+        graphs.append(gr)
+    torch.cuda.synchronize()
+    log(f"{len(graphs)} step graphs captured in {time.time() - t0:.2f}s")
+    graph = None if args.eager else graphs[0]
+
+    def run_step(j):
+        if args.eager:
+            i = graphs[j]
+            f.step(D[i], C[i], U[i - 1], stream=stream)
+        else:
+            graphs[j].replay()
+
+    with torch.cuda.stream(stream):
+        for j in range(args.warmup):
+            run_step(j)
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     wall0 = time.perf_counter()
-    evs = run(args.steps)
+    with torch.cuda.stream(stream):
+        evs[0].record()
+        for j in range(args.steps):
+            run_step(args.warmup + j)
+            evs[j + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
@@ -131,7 +125,13 @@ def main():
     last = int(st.step) - 1                      # frame index of the last step
     pos_err = float(np.linalg.norm(np.array(st.pose.t) - tr.t[min(last, nf - 1)]))
     log(f"{args.steps} steps: {ms_per_step:.3f} ms/step (events), wall {wall * 1e3 / args.steps:.3f} ms/step, "
-        f"pos err {pos_err:.4f} m, flags {st.flags}")
+        f"pos err {pos_err:.4f} m (frame {last}), flags {st.flags}")
+    if args.calib:
+        # plain copy of known size for scaling the FETCH_SIZE / WRITE_SIZE counters
+        src = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
 
     # ---- render + Jacobian throughput (render-through P1 objective) ------------------
     poses = P.poses_tensor(np.stack([np.concatenate([tr.t[i], tr.q[i]]) for i in range(8)]))
@@ -162,7 +162,7 @@ def main():
     # ---- map update: the HBM-streaming kernel -----------------------------------------
     nup = torch.empty(1, dtype=torch.int64, device=dev)
     pose_last = P.poses_tensor(np.concatenate([np.array(st.pose.t), np.array(st.pose.q)]))
-    fi = max(1, min(int(idx.item()) - 1, nf - 1))
+    fi = max(1, min(last, nf - 1))
     ms_mu = timed(lambda: P.map_update(grid, f.map, cam, pose_last, D[fi], C[fi], 4 * grid.voxel, 1.0,
                                        n_updated=nup), 50)
     n_upd = int(nup.item())

@@ -136,9 +136,15 @@ size_t prism_sizeof(const char *type_name);
 /* ------------------------------------------------------------------------ */
 /* The map is one opaque device buffer of prism_map_bytes() bytes: eight
  * planes (mean occupancy, mean R, G, B, then the four variances) of n^3
- * values of the grid's dtype, each plane in 8x8x8-brick order.  Use
- * prism_map_from_dense / prism_map_to_dense to exchange it with the dense
- * layout [4][n][n][n] (channel, z, y, x; x fastest). */
+ * values of the grid's dtype, each plane in 8x8x8-brick order, followed by a
+ * brick summary (largest occupancy mean per 8^3 brick, which the renderer
+ * uses to skip free space when tau == 0) and a small scratch area used by
+ * prism_map_update.  Every call of this library that writes the map keeps the
+ * summary current; after writing the planes directly (e.g. a gradient step on
+ * the means), call prism_map_refresh before rendering.  Calls that write the
+ * same map must not overlap.  Use prism_map_from_dense / prism_map_to_dense
+ * to exchange the planes with the dense layout [4][n][n][n] (channel, z, y,
+ * x; x fastest). */
 
 /* Bytes of a map of this grid (App. D map belief: mean and variance per
  * voxel and channel).  Fails on an unsupported grid. */
@@ -155,6 +161,9 @@ prism_status prism_map_init(const prism_grid *grid, void *map, float occ0, float
  * half untouched. */
 prism_status prism_map_from_dense(const prism_grid *grid, void *map, const float *mean4,
                                   const float *var4, hipStream_t stream);
+
+/* Recomputes the brick summary from the mean planes (after direct writes). */
+prism_status prism_map_refresh(const prism_grid *grid, void *map, hipStream_t stream);
 
 /* map -> dense FP32 [4][n][n][n] (device); either output may be NULL. */
 prism_status prism_map_to_dense(const prism_grid *grid, const void *map, float *mean4, float *var4,

@@ -132,8 +132,42 @@ size_t elem_size(int dtype) { return dtype == PRISM_BF16 ? 2 : 4; }
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// map buffer: 8 planes, then brick summary, free-space bits, update counts,
+// frustum brick list, its segment lengths, pose scratch
+struct MapLayout {
+    size_t bmax, bits, counts, list, segcnt, pose, total;
+};
+
+MapLayout map_layout(const prism_grid* g) {
+    MapLayout L;
+    size_t nvox = (size_t)g->n * g->n * g->n;
+    size_t nb3 = nvox / 512;
+    size_t nseg = (nb3 + 255) / 256;
+    L.bmax = round_up(8 * nvox * elem_size(g->dtype), 256);
+    L.bits = L.bmax + round_up(4 * nb3, 256);
+    L.counts = L.bits + round_up(4 * ((nb3 + 31) / 32), 256);
+    L.list = L.counts + round_up(4 * (size_t)kUpdateGrid, 256);
+    L.segcnt = L.list + round_up(4 * nseg * 256, 256);
+    L.pose = L.segcnt + round_up(4 * nseg, 256);
+    L.total = L.pose + 256;
+    return L;
+}
+
+MapAux map_aux(const prism_grid* g, const void* map) {
+    MapLayout L = map_layout(g);
+    char* b = (char*)map;
+    return MapAux{(float*)(b + L.bmax), (unsigned*)(b + L.bits), (int*)(b + L.counts),
+                  (int*)(b + L.list),   (int*)(b + L.segcnt),    (void*)(b + L.pose)};
+}
+
+// free-space bits for the renderer, NULL when skipping is not exact (tau != 0)
+const unsigned* skip_table(const prism_grid* g, const prism_camera* c, const void* map) {
+    return (float)c->tau == 0.0f ? map_aux(g, map).bits : nullptr;
+}
+
 size_t reduce_bytes(const CamC& c, int n_frames) {
     int nb = render_blocks(c) > track_blocks(c) ? render_blocks(c) : track_blocks(c);
+    nb = nb > vjp_blocks(c) ? nb : vjp_blocks(c);
     return (size_t)nb * n_frames * PRISM_NEQ * sizeof(double);
 }
 
@@ -216,7 +250,8 @@ prism_status check_frame(const prism_frame* fr, bool need_u) {
 // objective at S->iter into the handle's partials; returns the block count
 prism_status eval_objective(prism_filter* f, const prism_frame* fr, int* nb, hipStream_t st) {
     if (f->cfg.objective == PRISM_OBJ_P1) {
-        HIP_TRY(launch_render_jac(f->g, f->c, f->gd, f->cd, f->cfg.grid.dtype, f->map, &f->S->iter, 1, fr->depth,
+        HIP_TRY(launch_render_jac(f->g, f->c, f->gd, f->cd, f->cfg.grid.dtype, f->map,
+                                  skip_table(&f->cfg.grid, &f->cfg.cam, f->map), &f->S->iter, 1, fr->depth,
                                   fr->rgb, f->w,
                                   nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, f->partials, st));
         *nb = render_blocks(f->c);
@@ -244,8 +279,10 @@ prism_status pose_update_impl(prism_filter* f, const prism_frame* fr, hipStream_
 
 prism_status map_and_anchor(prism_filter* f, const prism_frame* fr, hipStream_t st) {
     HIP_TRY(launch_map_update(f->g, f->c, f->gd, f->cfg.grid.dtype, f->map, &f->S->pose, fr->depth, fr->rgb,
-                              f->cfg.map.trunc, f->cfg.map.lam_update, &f->S->n_updated, st));
-    HIP_TRY(launch_render(f->g, f->c, f->gd, f->cd, f->cfg.grid.dtype, f->map, &f->S->pose, 1, f->a_depth, f->a_rgb,
+                              f->cfg.map.trunc, f->cfg.map.lam_update, map_aux(&f->cfg.grid, f->map),
+                              &f->S->n_updated, st));
+    HIP_TRY(launch_render(f->g, f->c, f->gd, f->cd, f->cfg.grid.dtype, f->map,
+                          skip_table(&f->cfg.grid, &f->cfg.cam, f->map), &f->S->pose, 1, f->a_depth, f->a_rgb,
                           f->a_mask, nullptr, st));
     HIP_TRY(launch_normals(f->c, 1, f->a_depth, f->a_mask, (float)f->cfg.normal_disc, f->a_normals, f->a_nmask,
                            st));
@@ -276,7 +313,7 @@ prism_status prism_map_bytes(const prism_grid* grid, size_t* bytes) {
     prism_status s = check_grid(grid);
     if (s) return s;
     REQUIRE(bytes, "bytes is NULL");
-    *bytes = 8 * (size_t)grid->n * grid->n * grid->n * elem_size(grid->dtype);
+    *bytes = map_layout(grid).total;
     return PRISM_OK;
 }
 
@@ -285,7 +322,7 @@ prism_status prism_map_init(const prism_grid* grid, void* map, float occ0, float
     prism_status s = check_grid(grid);
     if (s) return s;
     REQUIRE(map && aligned(map, 256), "map must be non-NULL and 256-byte aligned");
-    HIP_TRY(launch_map_init(grid_c(grid), grid->dtype, map, occ0, rgb0, var0, stream));
+    HIP_TRY(launch_map_init(grid_c(grid), grid->dtype, map, occ0, rgb0, var0, map_aux(grid, map), stream));
     return PRISM_OK;
 }
 
@@ -297,7 +334,15 @@ prism_status prism_map_from_dense(const prism_grid* grid, void* map, const float
     REQUIRE(!mean4 || aligned(mean4, 4), "mean4 misaligned");
     REQUIRE(!var4 || aligned(var4, 4), "var4 misaligned");
     if (!mean4 && !var4) return PRISM_OK;
-    HIP_TRY(launch_from_dense(grid_c(grid), grid->dtype, map, mean4, var4, stream));
+    HIP_TRY(launch_from_dense(grid_c(grid), grid->dtype, map, mean4, var4, map_aux(grid, map), stream));
+    return PRISM_OK;
+}
+
+prism_status prism_map_refresh(const prism_grid* grid, void* map, hipStream_t stream) {
+    prism_status s = check_grid(grid);
+    if (s) return s;
+    REQUIRE(map && aligned(map, 256), "map must be non-NULL and 256-byte aligned");
+    HIP_TRY(launch_brick_max(grid_c(grid), grid->dtype, map, map_aux(grid, map), stream));
     return PRISM_OK;
 }
 
@@ -346,8 +391,8 @@ prism_status prism_render(const prism_grid* grid, const void* map, const prism_c
     REQUIRE(!normals || (nmask && aligned(normals, 4)), "normals needs nmask (and 4-byte alignment)");
     REQUIRE(!normals || !isnan(normal_disc), "normal_disc is NaN");
     CamC c = cam_c(cam);
-    HIP_TRY(launch_render(grid_c(grid), c, grid_d(grid), cam_d(cam), grid->dtype, map, poses, n_frames, depth, rgb,
-                          mask, hit_k, stream));
+    HIP_TRY(launch_render(grid_c(grid), c, grid_d(grid), cam_d(cam), grid->dtype, map, skip_table(grid, cam, map),
+                          poses, n_frames, depth, rgb, mask, hit_k, stream));
     if (normals) HIP_TRY(launch_normals(c, n_frames, depth, mask, (float)normal_disc, normals, nmask, stream));
     return PRISM_OK;
 }
@@ -379,8 +424,8 @@ prism_status prism_render_jacobian(const prism_grid* grid, const void* map, cons
     REQUIRE(workspace && aligned(workspace, 8) && workspace_bytes >= reduce_bytes(c, n_frames),
             "workspace too small: need %zu bytes", reduce_bytes(c, n_frames));
     double* part = (double*)workspace;
-    HIP_TRY(launch_render_jac(grid_c(grid), c, grid_d(grid), cam_d(cam), grid->dtype, map, poses, n_frames, obs_depth,
-                              obs_rgb, weights_c(w),
+    HIP_TRY(launch_render_jac(grid_c(grid), c, grid_d(grid), cam_d(cam), grid->dtype, map,
+                              skip_table(grid, cam, map), poses, n_frames, obs_depth, obs_rgb, weights_c(w),
                               depth, rgb, mask, J, resid, rowmask, part, stream));
     HIP_TRY(launch_finalize(part, render_blocks(c), n_frames, PRISM_NEQ, neq, PRISM_NEQ, stream));
     return PRISM_OK;
@@ -430,7 +475,7 @@ prism_status prism_render_vjp(const prism_grid* grid, const void* map, const pri
     double* part = (double*)workspace;
     HIP_TRY(launch_render_vjp(grid_c(grid), c, grid_d(grid), cam_d(cam), (const float*)map, poses, n_frames, hit_k, g_depth, g_rgb, grad_mean,
                               part, stream));
-    HIP_TRY(launch_finalize(part, render_blocks(c), n_frames, 6, grad_pose, 6, stream));
+    HIP_TRY(launch_finalize(part, vjp_blocks(c), n_frames, 6, grad_pose, 6, stream));
     return PRISM_OK;
 }
 
@@ -446,7 +491,7 @@ prism_status prism_map_update(const prism_grid* grid, void* map, const prism_cam
             "map params: trunc and lam_update must be finite and > 0");
     REQUIRE(!n_updated || aligned(n_updated, 8), "n_updated misaligned");
     HIP_TRY(launch_map_update(grid_c(grid), cam_c(cam), grid_d(grid), grid->dtype, map, pose, obs_depth, obs_rgb,
-                              p->trunc, p->lam_update, n_updated, stream));
+                              p->trunc, p->lam_update, map_aux(grid, map), n_updated, stream));
     return PRISM_OK;
 }
 

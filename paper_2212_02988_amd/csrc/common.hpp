@@ -62,6 +62,18 @@ struct CamD {
     double dn, step, tau;
 };
 
+// Derived data and scratch that live in the map buffer after the planes.
+struct MapAux {
+    float* bmax;      // [nb^3] largest occupancy mean of each brick
+    unsigned* bits;   // [ceil(nb^3/32)] bit b set iff bmax[b] <= 0 (free-space bricks)
+    int* counts;      // [kUpdateGrid] updated voxels per workgroup of the last update
+    int* list;        // [nb^3] bricks in the view frustum, in 256-brick segments
+    int* segcnt;      // [ceil(nb^3/256)] entries used in each segment
+    void* pose;       // Pose32 then Pose64 of the current update (256 bytes)
+};
+
+constexpr int kUpdateGrid = 2048;   // workgroups of the map-update kernel
+
 // ---------------------------------------------------------------------------
 // pose -> single-precision rotation/translation
 // ---------------------------------------------------------------------------
@@ -215,19 +227,40 @@ __device__ __forceinline__ double wave_sum(double x) {
     return x;
 }
 
-// Reduce a per-thread 29-vector over the block (blockDim.x multiple of 64,
-// <= 1024) and write it to out[0..28] (thread 0).  lds: 29 * 16 doubles.
+constexpr int kRedLds = 32 * 16;   // doubles of LDS scratch for block_reduce29
+
+// Reduce a per-thread 29-vector over the block (blockDim.x a multiple of 64,
+// <= 1024) into out[0..28] (written by threads 0..28).  lds: kRedLds doubles.
+//
+// Within a wave the 29 sums use a halving exchange instead of 29 separate
+// butterfly reductions: at the step with offset o (16, 8, 4, 2, 1) each lane
+// keeps the half of its remaining values selected by its lane bit o, sends
+// the other half to lane ^ o and adds what it receives.  After five steps
+// lane l holds value l & 31 summed over its 32-lane half, one more exchange
+// (offset 32) completes the wave sum: 32 double shuffles per wave instead of
+// 29 * 6.  Summation order is fixed, so results are deterministic.
 __device__ inline void block_reduce29(double acc[PRISM_NEQ], double* lds, double* out) {
-    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    double v[32];
 #pragma unroll
-    for (int q = 0; q < PRISM_NEQ; ++q) {
-        double s = wave_sum(acc[q]);
-        if (lane == 0) lds[q * 16 + wv] = s;
+    for (int q = 0; q < 32; ++q) v[q] = q < PRISM_NEQ ? acc[q] : 0.0;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int half = 16; half >= 1; half >>= 1) {
+        bool hi = (lane & half) != 0;
+#pragma unroll
+        for (int j = 0; j < half; ++j) {
+            double send = hi ? v[j] : v[j + half];
+            double keep = hi ? v[j + half] : v[j];
+            v[j] = keep + __shfl_xor(send, half, 64);
+        }
     }
+    double w = v[0] + __shfl_xor(v[0], 32, 64);   // value (lane & 31), whole wave
+    const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (lane < 32) lds[lane * 16 + wv] = w;
     __syncthreads();
     if (threadIdx.x < PRISM_NEQ) {
         double s = 0.0;
-        for (int w = 0; w < nw; ++w) s += lds[threadIdx.x * 16 + w];
+        for (int k = 0; k < nw; ++k) s += lds[threadIdx.x * 16 + k];
         out[threadIdx.x] = s;
     }
 }

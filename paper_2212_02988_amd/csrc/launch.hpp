@@ -12,16 +12,21 @@ struct TransC {
     double q[12];
 };
 
-int render_blocks(const CamC& c);
+int render_blocks(const CamC& c);   // render, render_jacobian
+int vjp_blocks(const CamC& c);      // render_vjp
 int track_blocks(const CamC& c);
 
+// bits: the map's free-space bits, or NULL to evaluate every sample (they are
+// only passed when tau == 0, where skipping a brick whose occupancies are all
+// <= 0 cannot change a decision)
 hipError_t launch_render(const GridC& g, const CamC& c, const GridD& gd, const CamD& cd, int dtype, const void* map,
-                         const prism_pose* poses, int n_frames, float* depth, float* rgb, uint8_t* mask,
-                         int32_t* hit_k, hipStream_t st);
+                         const unsigned* bits, const prism_pose* poses, int n_frames, float* depth, float* rgb,
+                         uint8_t* mask, int32_t* hit_k, hipStream_t st);
 hipError_t launch_normals(const CamC& c, int n_frames, const float* depth, const uint8_t* mask, float disc,
                           float* normals, uint8_t* nmask, hipStream_t st);
 hipError_t launch_render_jac(const GridC& g, const CamC& c, const GridD& gd, const CamD& cd, int dtype,
-                             const void* map, const prism_pose* poses, int n_frames, const float* obs_depth,
+                             const void* map, const unsigned* bits, const prism_pose* poses, int n_frames,
+                             const float* obs_depth,
                              const float* obs_rgb, const WeightsC& w, float* depth, float* rgb, uint8_t* mask,
                              float* J, float* resid, uint8_t* rowmask, double* partials, hipStream_t st);
 hipError_t launch_render_vjp(const GridC& g, const CamC& c, const GridD& gd, const CamD& cd, const float* map,
@@ -36,15 +41,16 @@ hipError_t launch_finalize(const double* partials, int nblocks, int n_frames, in
                            int stride, hipStream_t st);
 
 hipError_t launch_map_init(const GridC& g, int dtype, void* map, float occ0, float rgb0, float var0,
-                           hipStream_t st);
+                           const MapAux& aux, hipStream_t st);
+hipError_t launch_brick_max(const GridC& g, int dtype, const void* map, const MapAux& aux, hipStream_t st);
 hipError_t launch_from_dense(const GridC& g, int dtype, void* map, const float* mean4, const float* var4,
-                             hipStream_t st);
+                             const MapAux& aux, hipStream_t st);
 hipError_t launch_to_dense(const GridC& g, int dtype, const void* map, float* mean4, float* var4,
                            hipStream_t st);
 hipError_t launch_planes(int n, int channels, const float* src, float* dst, int to_dense, hipStream_t st);
 hipError_t launch_map_update(const GridC& g, const CamC& c, const GridD& gd, int dtype, void* map,
                              const prism_pose* pose, const float* depth, const float* rgb, double trunc, double lam_u,
-                             int64_t* n_updated, hipStream_t st);
+                             const MapAux& aux, int64_t* n_updated, hipStream_t st);
 
 hipError_t launch_predict(prism_filter_state* S, const double* u, const TransC& tc, hipStream_t st);
 hipError_t launch_gn_step(prism_filter_state* S, const double* partials, int nblocks, hipStream_t st);

@@ -1,21 +1,44 @@
 // Voxel-map storage kernels and the closed-form map update (App. D).
 //
 // Storage: 8 planes (mean occ, R, G, B, var occ, R, G, B) of n^3 values in
-// 8x8x8-brick order, brick-major, x fastest inside a brick.  The map update
-// runs one workgroup per brick: the brick's voxel-centre box is first tested
-// against the view frustum (conservatively, with margins far above single-
-// precision rounding), then each lane decides its voxels with the single-
-// precision recipe and updates only those, so HBM traffic is the updated
-// voxels' 8 planes read and written once.
+// 8x8x8-brick order, brick-major, x fastest inside a brick, followed by the
+// brick summary (largest occupancy mean of each brick), a bit per brick
+// telling whether that maximum is <= 0 (the renderer keeps these bits in LDS
+// to skip free space) and per-workgroup update counts.
+//
+// The map update runs in three kernels and uses no global atomics.
+//   cull:   one thread per brick tests the brick's voxel-centre box against
+//           the view frustum (conservatively, with margins far above
+//           single-precision rounding); each workgroup compacts its survivors
+//           into its own 256-entry segment of a brick list (ballot + prefix
+//           sums) and stores the segment length.  Block 0 also stores the
+//           pose in both precisions for the next kernel.
+//   update: a fixed grid of workgroups scans the segment lengths in LDS and
+//           walks the compacted list, one brick per workgroup at a time: each
+//           lane decides its two voxels with the single-precision recipe and
+//           updates only those, so HBM traffic is the updated voxels' 8 planes
+//           read and written once; the brick's occupancy maximum is refreshed
+//           in the same pass, and each workgroup stores its update count.
+//   pack:   packs the free-space bits from the brick maxima and sums the
+//           per-workgroup counts.
 #include "common.hpp"
 #include "launch.hpp"
 
 namespace prism {
 
+// value as it reads back after a store of type T
+template <typename T>
+__device__ __forceinline__ float stored(float v);
+template <>
+__device__ __forceinline__ float stored<float>(float v) { return v; }
+template <>
+__device__ __forceinline__ float stored<uint16_t>(float v) { return __uint_as_float(((uint32_t)f2bf(v)) << 16); }
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_map_init(long long nvox, T* __restrict__ map, float occ0, float rgb0,
-                                                  float var0) {
+                                                  float var0, MapAux aux, int nbricks) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nbricks) aux.bmax[i] = stored<T>(occ0);
     if (i >= nvox) return;
     st(map, i, occ0);
     st(map, nvox + i, rgb0);
@@ -77,7 +100,64 @@ __global__ __launch_bounds__(256) void k_planes(int n, int nb, int channels, con
     }
 }
 
-__global__ void k_zero_i64(int64_t* p) { *p = 0; }
+// maximum over a 256-thread block (lds: 4 floats); every thread gets it
+__device__ __forceinline__ float block_max(float m, float* lds) {
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) lds[wv] = m;
+    __syncthreads();
+    float r = lds[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = fmaxf(r, lds[w]);
+    return r;
+}
+
+// brick summary of every brick (after writes that bypass the map update)
+template <typename T>
+__global__ __launch_bounds__(256) void k_brick_max(GridC g, const T* __restrict__ map, MapAux aux) {
+    __shared__ float lds[4];
+    long long base = (long long)blockIdx.x << 9;
+    float m = fmaxf(ld(map, base + threadIdx.x), ld(map, base + threadIdx.x + 256));
+    m = block_max(m, lds);
+    if (threadIdx.x == 0) aux.bmax[blockIdx.x] = m;
+}
+
+// packs the free-space bits from the brick summary; block 0 also sums the
+// per-workgroup counts of the last update into n_updated (if requested)
+__global__ __launch_bounds__(256) void k_pack_bits(int nbricks, MapAux aux, int ngroups,
+                                                   int64_t* __restrict__ n_updated) {
+    __shared__ long long lsum[4];
+    int w = blockIdx.x * blockDim.x + threadIdx.x;
+    int nwords = (nbricks + 31) >> 5;
+    if (w < nwords) {
+        unsigned word = 0;
+        if ((w << 5) + 32 <= nbricks) {
+            // 32 contiguous floats: eight 16-byte loads issued together
+            const float4* p4 = reinterpret_cast<const float4*>(aux.bmax + (w << 5));
+            float4 v[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = p4[i];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                word |= (v[i].x <= 0.0f ? 1u : 0u) << (4 * i);
+                word |= (v[i].y <= 0.0f ? 1u : 0u) << (4 * i + 1);
+                word |= (v[i].z <= 0.0f ? 1u : 0u) << (4 * i + 2);
+                word |= (v[i].w <= 0.0f ? 1u : 0u) << (4 * i + 3);
+            }
+        } else {
+            for (int i = 0; (w << 5) + i < nbricks; ++i)
+                if (aux.bmax[(w << 5) + i] <= 0.0f) word |= 1u << i;
+        }
+        aux.bits[w] = word;
+    }
+    if (blockIdx.x == 0 && n_updated) {
+        long long s = 0;
+        for (int i = threadIdx.x; i < ngroups; i += blockDim.x) s += aux.counts[i];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        if ((threadIdx.x & 63) == 0) lsum[threadIdx.x >> 6] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) *n_updated = lsum[0] + lsum[1] + lsum[2] + lsum[3];
+    }
+}
 
 struct MapUpdC {
     float trunc32;          // decision: z <= D + trunc in single precision
@@ -85,8 +165,9 @@ struct MapUpdC {
 };
 
 // Conservative brick cull: true if no voxel centre of the brick can pass the
-// per-voxel test.  Each test is a convex region (intersection of half-spaces)
-// checked on the 8 corners of the brick's voxel-centre box.
+// per-voxel test.  Each test is a convex region (behind the camera, or beyond
+// one side plane of the frustum) checked on the 8 corners of the brick's
+// voxel-centre box.
 __device__ inline bool brick_culled(const GridC& g, const CamC& c, const Pose32& P, int bx, int by, int bz) {
     const float mz = 1e-3f, mp = 0.5f;
     bool all_behind = true, all_l = true, all_r = true, all_t = true, all_b = true;
@@ -109,95 +190,195 @@ __device__ inline bool brick_culled(const GridC& g, const CamC& c, const Pose32&
     return all_behind || all_l || all_r || all_t || all_b;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_map_update(GridC g, CamC c, GridD gd, T* __restrict__ map,
-                                                    const prism_pose* __restrict__ pose,
-                                                    const float* __restrict__ depth,
-                                                    const float* __restrict__ rgb, MapUpdC mp,
-                                                    int64_t* __restrict__ n_updated) {
-    __shared__ Pose32 sp;
-    __shared__ Pose64 sp64;
-    __shared__ int s_cnt;
+struct PosePair {
+    Pose32 f;
+    Pose64 d;
+};
+
+__global__ __launch_bounds__(256) void k_cull(GridC g, CamC c, const prism_pose* __restrict__ pose, MapAux aux) {
+    __shared__ PosePair sp;
+    __shared__ int wcount[4];
     if (threadIdx.x == 0) {
-        sp64 = load_pose64(pose);
-        sp = to32(sp64);
-        s_cnt = 0;
+        sp.d = load_pose64(pose);
+        sp.f = to32(sp.d);
+        if (blockIdx.x == 0) *reinterpret_cast<PosePair*>(aux.pose) = sp;
     }
     __syncthreads();
-    const Pose32 P = sp;
-    long long b = blockIdx.x;
-    int bx = (int)(b % g.nb), by = (int)((b / g.nb) % g.nb), bz = (int)(b / ((long long)g.nb * g.nb));
-    if (brick_culled(g, c, P, bx, by, bz)) return;   // uniform over the block
-    int cnt = 0;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        int l = threadIdx.x + h * 256;
-        int i = (bx << 3) | (l & 7), j = (by << 3) | ((l >> 3) & 7), k = (bz << 3) | (l >> 6);
-        float x[3] = {g.o[0] + g.s * ((float)i + 0.5f), g.o[1] + g.s * ((float)j + 0.5f),
-                      g.o[2] + g.s * ((float)k + 0.5f)};
-        float d[3] = {x[0] - P.t[0], x[1] - P.t[1], x[2] - P.t[2]};
-        float X[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) X[a] = (P.R[0][a] * d[0] + P.R[1][a] * d[1]) + P.R[2][a] * d[2];
-        if (!(X[2] > 0.0f)) continue;
-        float uu = c.fx * (X[0] / X[2]) + c.cx;
-        float vv = c.fy * (X[1] / X[2]) + c.cy;
-        if (!(uu >= 0.0f && uu < (float)c.W && vv >= 0.0f && vv < (float)c.H)) continue;
-        int pix = (int)vv * c.W + (int)uu;
-        float D = depth[pix];
-        if (!(depth_ok(D) && X[2] <= D + mp.trunc32)) continue;
-        // values in double precision: camera depth of the voxel centre,
-        // truncated negative SDF, Gaussian product in precision form
-        const Pose64& Q = sp64;
-        double dd0 = (gd.o[0] + gd.s * ((double)i + 0.5)) - Q.t[0];
-        double dd1 = (gd.o[1] + gd.s * ((double)j + 0.5)) - Q.t[1];
-        double dd2 = (gd.o[2] + gd.s * ((double)k + 0.5)) - Q.t[2];
-        double z = Q.R[0][2] * dd0 + Q.R[1][2] * dd1 + Q.R[2][2] * dd2;
-        double f[4];
-        f[0] = z - (double)D;
-        if (f[0] < -mp.trunc) f[0] = -mp.trunc;
-        f[1] = (double)rgb[3 * pix];
-        f[2] = (double)rgb[3 * pix + 1];
-        f[3] = (double)rgb[3 * pix + 2];
-        long long id = (b << 9) | l;
-#pragma unroll
-        for (int ch = 0; ch < 4; ++ch) {
-            double mu = (double)ld(map, ch * g.nvox + id);
-            double var = (double)ld(map, (4 + ch) * g.nvox + id);
-            double lam = 1.0 / var;
-            double lam2 = lam + mp.lam_u;
-            st(map, ch * g.nvox + id, (float)((lam * mu + mp.lam_u * f[ch]) / lam2));
-            st(map, (4 + ch) * g.nvox + id, (float)(1.0 / lam2));
+    int nbricks = g.nb * g.nb * g.nb;
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    bool keep = false;
+    if (b < nbricks) {
+        int bx = b % g.nb, by = (b / g.nb) % g.nb, bz = b / (g.nb * g.nb);
+        keep = !brick_culled(g, c, sp.f, bx, by, bz);
+    }
+    // compaction inside the workgroup: rank = survivors before this thread
+    unsigned long long m = __ballot(keep);
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int rank = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wcount[wv] = __popcll(m);
+    __syncthreads();
+    int base = 0;
+    for (int w = 0; w < wv; ++w) base += wcount[w];
+    if (keep) aux.list[blockIdx.x * 256 + base + rank] = b;
+    if (threadIdx.x == 0) aux.segcnt[blockIdx.x] = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_map_update(GridC g, CamC c, GridD gd, T* __restrict__ map,
+                                                    const float* __restrict__ depth,
+                                                    const float* __restrict__ rgb, MapUpdC mp, MapAux aux,
+                                                    int nseg) {
+    extern __shared__ int sstart[];    // [nseg + 1] exclusive prefix of the segment lengths
+    __shared__ PosePair sp;
+    __shared__ float lmax[4];
+    __shared__ int lcnt[4];
+    __shared__ int chunk_sum[256];
+    // segment lengths -> exclusive prefix sums (each thread one contiguous chunk)
+    int per = (nseg + 255) / 256;
+    int lo = threadIdx.x * per, hi = min(lo + per, nseg);
+    int s = 0;
+    for (int i = lo; i < hi; ++i) {
+        sstart[i] = s;
+        s += aux.segcnt[i];
+    }
+    chunk_sum[threadIdx.x] = s;
+    if (threadIdx.x == 0) sp = *reinterpret_cast<const PosePair*>(aux.pose);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int t = 0; t < 256; ++t) {
+            int v = chunk_sum[t];
+            chunk_sum[t] = run;
+            run += v;
         }
-        ++cnt;
+        sstart[nseg] = run;
     }
-    if (n_updated) {
-        // wave sum then one LDS atomic per wave, one global atomic per block
-        for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
-        if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(&s_cnt, cnt);
-        __syncthreads();
-        if (threadIdx.x == 0 && s_cnt) atomicAdd((unsigned long long*)n_updated, (unsigned long long)s_cnt);
+    __syncthreads();
+    for (int i = lo; i < hi; ++i) sstart[i] += chunk_sum[threadIdx.x];
+    __syncthreads();
+    const Pose32& P = sp.f;
+    const Pose64& Q = sp.d;
+    const int total = sstart[nseg];
+    int cnt = 0;
+    for (int e = blockIdx.x; e < total; e += gridDim.x) {
+        // segment holding entry e (binary search over the prefix sums)
+        int a = 0, z = nseg;
+        while (z - a > 1) {
+            int mid = (a + z) >> 1;
+            if (sstart[mid] <= e) a = mid; else z = mid;
+        }
+        const int b = aux.list[a * 256 + (e - sstart[a])];
+        int bx = b % g.nb, by = (b / g.nb) % g.nb, bz = b / (g.nb * g.nb);
+        float m = -INFINITY;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            int l = threadIdx.x + h * 256;
+            long long id = ((long long)b << 9) | l;
+            int i = (bx << 3) | (l & 7), j = (by << 3) | ((l >> 3) & 7), k = (bz << 3) | (l >> 6);
+            float x[3] = {g.o[0] + g.s * ((float)i + 0.5f), g.o[1] + g.s * ((float)j + 0.5f),
+                          g.o[2] + g.s * ((float)k + 0.5f)};
+            float d[3] = {x[0] - P.t[0], x[1] - P.t[1], x[2] - P.t[2]};
+            float X[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) X[q] = (P.R[0][q] * d[0] + P.R[1][q] * d[1]) + P.R[2][q] * d[2];
+            bool upd = false;
+            int pix = 0;
+            float D = 0.0f;
+            if (X[2] > 0.0f) {
+                float uu = c.fx * (X[0] / X[2]) + c.cx;
+                float vv = c.fy * (X[1] / X[2]) + c.cy;
+                if (uu >= 0.0f && uu < (float)c.W && vv >= 0.0f && vv < (float)c.H) {
+                    pix = (int)vv * c.W + (int)uu;
+                    D = depth[pix];
+                    upd = depth_ok(D) && X[2] <= D + mp.trunc32;
+                }
+            }
+            if (!upd) {
+                m = fmaxf(m, ld(map, id));
+                continue;
+            }
+            // values in double precision: camera depth of the voxel centre,
+            // truncated negative SDF, Gaussian product in precision form
+            double dd0 = (gd.o[0] + gd.s * ((double)i + 0.5)) - Q.t[0];
+            double dd1 = (gd.o[1] + gd.s * ((double)j + 0.5)) - Q.t[1];
+            double dd2 = (gd.o[2] + gd.s * ((double)k + 0.5)) - Q.t[2];
+            double z = Q.R[0][2] * dd0 + Q.R[1][2] * dd1 + Q.R[2][2] * dd2;
+            double f[4];
+            f[0] = z - (double)D;
+            if (f[0] < -mp.trunc) f[0] = -mp.trunc;
+            f[1] = (double)rgb[3 * pix];
+            f[2] = (double)rgb[3 * pix + 1];
+            f[3] = (double)rgb[3 * pix + 2];
+            double mu[4], var[4];
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch) {
+                mu[ch] = (double)ld(map, ch * g.nvox + id);
+                var[ch] = (double)ld(map, (4 + ch) * g.nvox + id);
+            }
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch) {
+                double lam = 1.0 / var[ch];
+                double lam2 = lam + mp.lam_u;
+                float nm = (float)((lam * mu[ch] + mp.lam_u * f[ch]) / lam2);
+                st(map, ch * g.nvox + id, nm);
+                st(map, (4 + ch) * g.nvox + id, (float)(1.0 / lam2));
+                if (ch == 0) m = fmaxf(m, stored<T>(nm));
+            }
+            ++cnt;
+        }
+        m = block_max(m, lmax);
+        if (threadIdx.x == 0) aux.bmax[b] = m;
+        __syncthreads();   // lmax is reused by the next brick
     }
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+    if ((threadIdx.x & 63) == 0) lcnt[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) aux.counts[blockIdx.x] = lcnt[0] + lcnt[1] + lcnt[2] + lcnt[3];
 }
 
 static unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
 
-hipError_t launch_map_init(const GridC& g, int dtype, void* map, float occ0, float rgb0, float var0,
-                           hipStream_t st) {
-    if (dtype == PRISM_BF16)
-        k_map_init<uint16_t><<<blocks_for(g.nvox), 256, 0, st>>>(g.nvox, (uint16_t*)map, occ0, rgb0, var0);
-    else
-        k_map_init<float><<<blocks_for(g.nvox), 256, 0, st>>>(g.nvox, (float*)map, occ0, rgb0, var0);
+static hipError_t launch_pack(const GridC& g, const MapAux& aux, int ngroups, int64_t* n_updated, hipStream_t st) {
+    int nbricks = g.nb * g.nb * g.nb;
+    int nwords = (nbricks + 31) >> 5;
+    k_pack_bits<<<(unsigned)((nwords + 255) / 256), 256, 0, st>>>(nbricks, aux, ngroups, n_updated);
     return hipGetLastError();
 }
 
+
+hipError_t launch_map_init(const GridC& g, int dtype, void* map, float occ0, float rgb0, float var0,
+                           const MapAux& aux, hipStream_t st) {
+    int nbricks = g.nb * g.nb * g.nb;
+    if (dtype == PRISM_BF16)
+        k_map_init<uint16_t><<<blocks_for(g.nvox), 256, 0, st>>>(g.nvox, (uint16_t*)map, occ0, rgb0, var0, aux,
+                                                                 nbricks);
+    else
+        k_map_init<float><<<blocks_for(g.nvox), 256, 0, st>>>(g.nvox, (float*)map, occ0, rgb0, var0, aux, nbricks);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_pack(g, aux, 0, nullptr, st);
+}
+
+hipError_t launch_brick_max(const GridC& g, int dtype, const void* map, const MapAux& aux, hipStream_t st) {
+    unsigned nbricks = (unsigned)(g.nb * g.nb * g.nb);
+    if (dtype == PRISM_BF16)
+        k_brick_max<uint16_t><<<nbricks, 256, 0, st>>>(g, (const uint16_t*)map, aux);
+    else
+        k_brick_max<float><<<nbricks, 256, 0, st>>>(g, (const float*)map, aux);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_pack(g, aux, 0, nullptr, st);
+}
+
 hipError_t launch_from_dense(const GridC& g, int dtype, void* map, const float* mean4, const float* var4,
-                             hipStream_t st) {
+                             const MapAux& aux, hipStream_t st) {
     if (dtype == PRISM_BF16)
         k_from_dense<uint16_t><<<blocks_for(g.nvox), 256, 0, st>>>(g.n, g.nb, (uint16_t*)map, mean4, var4);
     else
         k_from_dense<float><<<blocks_for(g.nvox), 256, 0, st>>>(g.n, g.nb, (float*)map, mean4, var4);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_brick_max(g, dtype, map, aux, st);
 }
 
 hipError_t launch_to_dense(const GridC& g, int dtype, const void* map, float* mean4, float* var4,
@@ -215,21 +396,31 @@ hipError_t launch_planes(int n, int channels, const float* src, float* dst, int 
     return hipGetLastError();
 }
 
+// workgroups of the update kernel: enough to keep every CU busy, never more
+// than there are bricks
+static int update_grid(const GridC& g) {
+    int nbricks = g.nb * g.nb * g.nb;
+    return nbricks < kUpdateGrid ? nbricks : kUpdateGrid;
+}
+
 hipError_t launch_map_update(const GridC& g, const CamC& c, const GridD& gd, int dtype, void* map,
                              const prism_pose* pose, const float* depth, const float* rgb, double trunc, double lam_u,
-                             int64_t* n_updated, hipStream_t st) {
-    if (n_updated) {
-        k_zero_i64<<<1, 1, 0, st>>>(n_updated);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
+                             const MapAux& aux, int64_t* n_updated, hipStream_t st) {
+    int nbricks = g.nb * g.nb * g.nb;
+    int nseg = (nbricks + 255) / 256;
+    k_cull<<<nseg, 256, 0, st>>>(g, c, pose, aux);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     MapUpdC mp{(float)trunc, trunc, lam_u};
-    unsigned nbricks = (unsigned)((long long)g.nb * g.nb * g.nb);
+    int ng = update_grid(g);
+    size_t lds = (size_t)(nseg + 1) * sizeof(int);
     if (dtype == PRISM_BF16)
-        k_map_update<uint16_t><<<nbricks, 256, 0, st>>>(g, c, gd, (uint16_t*)map, pose, depth, rgb, mp, n_updated);
+        k_map_update<uint16_t><<<ng, 256, lds, st>>>(g, c, gd, (uint16_t*)map, depth, rgb, mp, aux, nseg);
     else
-        k_map_update<float><<<nbricks, 256, 0, st>>>(g, c, gd, (float*)map, pose, depth, rgb, mp, n_updated);
-    return hipGetLastError();
+        k_map_update<float><<<ng, 256, lds, st>>>(g, c, gd, (float*)map, depth, rgb, mp, aux, nseg);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_pack(g, aux, ng, n_updated, st);
 }
 
 }  // namespace prism

@@ -1,17 +1,28 @@
 // Ray-marching emission (App. B), its pose Jacobian with the fused normal-
 // equation reduction, anchor normals, and the adjoint w.r.t. map means.
 //
-// Work split: one ray per lane, an 8x8 pixel tile per wave, 4 waves (16x16
-// pixels) per workgroup, blockIdx.y = frame.  The sample loop evaluates
-// kUnroll samples per trip so that 8*kUnroll independent gathers are in
-// flight per lane before the first-crossing test; samples past the hit are
-// evaluated but never used.
+// Work split of render and render_jacobian: four lanes per ray (a quad), an
+// 8x2 pixel strip per wave, an 8x8 tile per workgroup, blockIdx.y = frame.
+// A single frame is only ~10^5 rays, so the march is latency-bound: the four
+// lanes of a ray evaluate interleaved samples (lane s takes k0 + s + 4 j,
+// j < kPerLane) and a two-step shuffle finds the first crossing of the trip,
+// which shortens each ray's chain of dependent gathers four-fold and gives the
+// GPU four times more waves to overlap.  Samples in bricks whose occupancy
+// is <= 0 everywhere are decided without touching the map (free-space bits
+// in LDS).  At the hit the quad splits the double-precision shading and the
+// Jacobian by channel: lane 0 occupancy / depth, lanes 1-3 one colour each.
+//
+// The adjoint keeps one ray per lane (16x16 pixels per workgroup): it
+// recomputes two samples per ray from the given hit index, nothing to march.
 #include "common.hpp"
 #include "launch.hpp"
 
 namespace prism {
 
-constexpr int kUnroll = 4;
+constexpr int kUnroll = 8;      // samples per trip, one-lane-per-ray march
+constexpr int kLanes = 4;       // lanes per ray in render / render_jacobian
+constexpr int kPerLane = 2;     // samples per lane per trip
+constexpr int kMaxLdsWords = 12288;   // free-space bits kept in LDS up to 48 KB (grids up to n = 576)
 
 struct RayHit {
     int k;          // k* or -1
@@ -26,42 +37,70 @@ __device__ __forceinline__ float occ_at(const GridC& g, const T* occ, const Cell
     return trilerp(v, c.w);
 }
 
-// first sample whose occupancy exceeds tau (strictly), with the bracketing cells
+// True if the free-space bits prove that the sample's occupancy is <= 0:
+// every corner of its cell lies inside the grid and in bricks whose largest
+// occupancy mean is <= 0.  Each lerp of values <= 0 with a weight in [0, 1]
+// is <= 0 under round-to-nearest (rounding is monotonic and 0 is
+// representable), so the single-precision recipe would have produced a value
+// <= 0 as well and the sample cannot be the hit when tau == 0.
+__device__ __forceinline__ bool skip_cell(const GridC& g, const unsigned* bits, const Cell& c) {
+    if (!bits) return false;
+    int lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (c.i[a] < 0 || c.i[a] + 1 >= g.n) return false;
+        lo[a] = c.i[a] >> 3;
+        hi[a] = (c.i[a] + 1) >> 3;
+    }
+    bool all = true;
+    for (int bz = lo[2]; bz <= hi[2]; ++bz)
+        for (int by = lo[1]; by <= hi[1]; ++by)
+            for (int bx = lo[0]; bx <= hi[0]; ++bx) {
+                int b = (bz * g.nb + by) * g.nb + bx;
+                all &= (bits[b >> 5] >> (b & 31)) & 1u;
+            }
+    return all;
+}
+
+// Free-space bits for this block: copied into LDS when they fit, else read
+// from global memory; NULL disables skipping.
+__device__ __forceinline__ const unsigned* block_bits(const GridC& g, const unsigned* __restrict__ gbits,
+                                                      unsigned* lbits) {
+    if (!gbits) return nullptr;
+    int nwords = (g.nb * g.nb * g.nb + 31) >> 5;
+    if (nwords > kMaxLdsWords) return gbits;
+    for (int i = threadIdx.x; i < nwords; i += blockDim.x) lbits[i] = gbits[i];
+    __syncthreads();
+    return lbits;
+}
+
+// first sample whose occupancy exceeds tau (strictly), with the bracketing
+// cells (recomputed from k*: cheaper than keeping them in registers)
 template <typename T>
 __device__ __forceinline__ RayHit march(const GridC& g, const CamC& c, const Pose32& P,
-                                        const float dir[3], const T* occ) {
+                                        const float dir[3], const T* occ, const unsigned* bits) {
     RayHit h;
     h.k = -1;
     h.f0 = h.f1 = 0.0f;
-    Cell prev = {};
-    float fprev = 0.0f;
     for (int k0 = 0; k0 < c.K; k0 += kUnroll) {
         float f[kUnroll];
-        Cell cl[kUnroll];
 #pragma unroll
         for (int j = 0; j < kUnroll; ++j) {
-            int k = min(k0 + j, c.K - 1);
-            cl[j] = sample_cell(g, c, P, dir, k);
-            f[j] = occ_at(g, occ, cl[j]);
+            Cell cl = sample_cell(g, c, P, dir, min(k0 + j, c.K - 1));
+            f[j] = skip_cell(g, bits, cl) ? -1.0f : occ_at(g, occ, cl);
         }
-        bool done = false;
+        int hit = -1;
 #pragma unroll
-        for (int j = 0; j < kUnroll; ++j) {
-            if (!done && k0 + j < c.K) {
-                if (f[j] > c.tau) {
-                    h.k = k0 + j;
-                    h.f1 = f[j];
-                    h.c1 = cl[j];
-                    h.f0 = fprev;
-                    h.c0 = prev;
-                    done = true;
-                } else {
-                    fprev = f[j];
-                    prev = cl[j];
-                }
-            }
+        for (int j = kUnroll - 1; j >= 0; --j)
+            if (k0 + j < c.K && f[j] > c.tau) hit = j;
+        if (hit >= 0) {
+            h.k = k0 + hit;
+            break;
         }
-        if (done) break;
+    }
+    if (h.k >= 1) {
+        h.c0 = sample_cell(g, c, P, dir, h.k - 1);
+        h.c1 = sample_cell(g, c, P, dir, h.k);
     }
     return h;
 }
@@ -131,7 +170,7 @@ __device__ __forceinline__ Shade shade(const GridC& g, const GridD& gd, const Ca
     }
     double al = (cd.tau - s.f0) / (s.f1 - s.f0);
     s.depth = al * d1 + (1.0 - al) * d0;
-#pragma unroll
+#pragma unroll 1
     for (int ch = 0; ch < 3; ++ch) {
         const T* pl = map + (long long)(1 + ch) * g.nvox;
         double c0 = tri64(g, pl, gc0, h.c0.i, gd.rgb_out);
@@ -225,34 +264,184 @@ __device__ __forceinline__ const BlockPose& block_pose(const prism_pose* poses, 
 }
 
 // ---------------------------------------------------------------------------
+// quad (four lanes per ray) march and shading
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int quad_min(int x) {
+    x = min(x, __shfl_xor(x, 1, 64));
+    x = min(x, __shfl_xor(x, 2, 64));
+    return x;
+}
+
+__device__ __forceinline__ float quad_sum(float x) {
+    x += __shfl_xor(x, 1, 64);
+    x += __shfl_xor(x, 2, 64);
+    return x;
+}
+
+__device__ __forceinline__ double quad_bcast(double x, int src_lane_in_quad) {
+    int base = (threadIdx.x & 63) & ~3;
+    return __shfl(x, base + src_lane_in_quad, 64);
+}
+
+__device__ __forceinline__ float quad_bcastf(float x, int src_lane_in_quad) {
+    int base = (threadIdx.x & 63) & ~3;
+    return __shfl(x, base + src_lane_in_quad, 64);
+}
+
+// first sample index whose occupancy exceeds tau (strictly), or -1; every
+// lane of the quad returns the same value
+template <typename T>
+__device__ __forceinline__ int march_quad(const GridC& g, const CamC& c, const Pose32& P, const float dir[3],
+                                          const T* occ, const unsigned* bits, int s) {
+    constexpr int G = kLanes * kPerLane;
+    for (int k0 = 0; k0 < c.K; k0 += G) {
+        float f[kPerLane];
+#pragma unroll
+        for (int j = 0; j < kPerLane; ++j) {
+            int k = k0 + j * kLanes + s;
+            Cell cl = sample_cell(g, c, P, dir, min(k, c.K - 1));
+            f[j] = skip_cell(g, bits, cl) ? -1.0f : occ_at(g, occ, cl);
+        }
+        int first = 0x7fffffff;
+#pragma unroll
+        for (int j = kPerLane - 1; j >= 0; --j) {
+            int k = k0 + j * kLanes + s;
+            if (k < c.K && f[j] > c.tau) first = k;
+        }
+        first = quad_min(first);
+        if (first != 0x7fffffff) return first;
+    }
+    return -1;
+}
+
+// This lane's share of the shading at a valid hit: plane s (0 occupancy,
+// 1..3 colour) at samples k*-1 and k*, in double precision, plus the
+// double-precision interpolation weights.
+struct QuadShade {
+    double v0, v1;          // plane s at samples k*-1, k*
+    double f0, f1;          // occupancy at k*-1, k* (from lane 0)
+    double alpha, value;    // alpha and this lane's output (depth or colour)
+    float w0[3], w1[3];
+    float d0, d1;
+};
+
+template <typename T>
+__device__ __forceinline__ QuadShade shade_quad(const GridC& g, const GridD& gd, const CamD& cd, const Pose64& P,
+                                                int u, int v, const T* map, const Cell& c0, const Cell& c1, int k,
+                                                int s) {
+    QuadShade q;
+    double rc[3], dir[3], gc0[3], gc1[3];
+    pixel_dir64(cd, u, v, rc);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dir[a] = P.R[a][0] * rc[0] + P.R[a][1] * rc[1] + P.R[a][2] * rc[2];
+    grid_coord64(gd, cd, P, dir, k - 1, gc0);
+    grid_coord64(gd, cd, P, dir, k, gc1);
+    double d0 = cd.dn + (double)(k - 1) * cd.step;
+    double d1 = cd.dn + (double)k * cd.step;
+    const T* pl = map + (long long)s * g.nvox;
+    double outv = s == 0 ? gd.occ_out : gd.rgb_out;
+    q.v0 = tri64(g, pl, gc0, c0.i, outv);
+    q.v1 = tri64(g, pl, gc1, c1.i, outv);
+    q.f0 = quad_bcast(q.v0, 0);
+    q.f1 = quad_bcast(q.v1, 0);
+    q.alpha = (cd.tau - q.f0) / (q.f1 - q.f0);
+    q.value = s == 0 ? q.alpha * d1 + (1.0 - q.alpha) * d0 : q.alpha * q.v1 + (1.0 - q.alpha) * q.v0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        q.w0[a] = (float)(gc0[a] - (double)c0.i[a]);
+        q.w1[a] = (float)(gc1[a] - (double)c1.i[a]);
+    }
+    q.d0 = (float)d0;
+    q.d1 = (float)d1;
+    return q;
+}
+
+// This lane's row of the 4x6 Jacobian d(depth, r, g, b)/d(delta), k* fixed.
+// Lane 0 forms d(alpha)/d(delta) from the occupancy gradients and shares it.
+template <typename T>
+__device__ __forceinline__ void jac_row_quad(const GridC& g, const T* map, const Cell& c0, const Cell& c1,
+                                             const QuadShade& q, const float dir[3], int s, float row[6]) {
+    float a0[3], a1[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { a0[i] = q.d0 * dir[i]; a1[i] = q.d1 * dir[i]; }
+    const T* pl = map + (long long)s * g.nvox;
+    float outv = s == 0 ? g.occ_out : g.rgb_out;
+    float v[8], G0[3], G1[3], cr[3], r0[6], r1[6];
+    corners(g, pl, c0, outv, v);
+    trigrad(v, q.w0, G0);
+    corners(g, pl, c1, outv, v);
+    trigrad(v, q.w1, G1);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { G0[i] *= g.inv_s; G1[i] *= g.inv_s; r0[i] = G0[i]; r1[i] = G1[i]; }
+    cross3(a0, G0, cr);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) r0[3 + i] = cr[i];
+    cross3(a1, G1, cr);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) r1[3 + i] = cr[i];
+    // lane 0: d(alpha) = -[(1-alpha) df0 + alpha df1] / (f1 - f0)
+    float al = (float)q.alpha;
+    float inv_den = (float)(1.0 / (q.f1 - q.f0));
+    float dal[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) dal[m] = quad_bcastf(-((1.0f - al) * r0[m] + al * r1[m]) * inv_den, 0);
+    if (s == 0) {
+#pragma unroll
+        for (int m = 0; m < 6; ++m) row[m] = (q.d1 - q.d0) * dal[m];
+    } else {
+        float dc = (float)(q.v1 - q.v0);
+#pragma unroll
+        for (int m = 0; m < 6; ++m) row[m] = dc * dal[m] + al * r1[m] + (1.0f - al) * r0[m];
+    }
+}
+
+// quad tile mapping: 8x8 pixels per 256-thread workgroup, 8x2 per wave
+__device__ __forceinline__ void quad_pixel(const CamC& c, int& u, int& v, int& s) {
+    int tiles_x = (c.W + 7) >> 3;
+    int bx = blockIdx.x % tiles_x, by = blockIdx.x / tiles_x;
+    int t = threadIdx.x;
+    s = t & 3;
+    int r = t >> 2;    // 0..63 ray of the tile
+    u = (bx << 3) + (r & 7);
+    v = (by << 3) + (r >> 3);
+}
+
+// ---------------------------------------------------------------------------
 // render
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_render(GridC g, CamC c, GridD gd, CamD cd, const T* __restrict__ map,
+                                                const unsigned* __restrict__ gbits,
                                                 const prism_pose* __restrict__ poses,
                                                 float* __restrict__ depth, float* __restrict__ rgb,
                                                 uint8_t* __restrict__ mask, int32_t* __restrict__ hit_k) {
     __shared__ BlockPose sp;
+    extern __shared__ unsigned lbits[];
+    const unsigned* bits = block_bits(g, gbits, lbits);
     const BlockPose& P = block_pose(poses, &sp);
-    int u, v;
-    tile_pixel(c, u, v);
-    if (u >= c.W || v >= c.H) return;
+    int u, v, s;
+    quad_pixel(c, u, v, s);
+    if (u >= c.W || v >= c.H) return;   // whole quads leave together
     float dir[3];
     ray_dir32(c, P.f, u, v, dir);
-    RayHit h = march(g, c, P.f, dir, map);
+    int k = march_quad(g, c, P.f, dir, map, bits, s);
     long long pix = (long long)blockIdx.y * c.W * c.H + (long long)v * c.W + u;
-    if (hit_k) hit_k[pix] = h.k;
-    if (h.k >= 1) {
-        Shade s = shade(g, gd, cd, P.d, u, v, map, h);
-        depth[pix] = (float)s.depth;
-        rgb[3 * pix] = (float)s.rgb[0];
-        rgb[3 * pix + 1] = (float)s.rgb[1];
-        rgb[3 * pix + 2] = (float)s.rgb[2];
-        mask[pix] = 1;
+    if (s == 0) {
+        if (hit_k) hit_k[pix] = k;
+        mask[pix] = k >= 1 ? 1 : 0;
+    }
+    if (k >= 1) {
+        Cell c0 = sample_cell(g, c, P.f, dir, k - 1), c1 = sample_cell(g, c, P.f, dir, k);
+        QuadShade q = shade_quad(g, gd, cd, P.d, u, v, map, c0, c1, k, s);
+        if (s == 0)
+            depth[pix] = (float)q.value;
+        else
+            rgb[3 * pix + s - 1] = (float)q.value;
     } else {
-        depth[pix] = 0.0f;
-        rgb[3 * pix] = rgb[3 * pix + 1] = rgb[3 * pix + 2] = 0.0f;
-        mask[pix] = 0;
+        if (s == 0)
+            depth[pix] = 0.0f;
+        else
+            rgb[3 * pix + s - 1] = 0.0f;
     }
 }
 
@@ -301,6 +490,7 @@ __global__ __launch_bounds__(256) void k_normals(CamC c, int n_frames, const flo
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, GridD gd, CamD cd, const T* __restrict__ map,
+                                                    const unsigned* __restrict__ gbits,
                                                     const prism_pose* __restrict__ poses,
                                                     const float* __restrict__ obs_depth,
                                                     const float* __restrict__ obs_rgb, WeightsC wt,
@@ -309,73 +499,62 @@ __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, GridD gd, C
                                                     float* __restrict__ resid, uint8_t* __restrict__ rowmask,
                                                     double* __restrict__ partials) {
     __shared__ BlockPose sp;
-    __shared__ double lds[PRISM_NEQ * 16];
+    __shared__ double lds[kRedLds];
+    extern __shared__ unsigned lbits[];
+    const unsigned* bits = block_bits(g, gbits, lbits);
     const BlockPose& P = block_pose(poses, &sp);
-    int u, v;
-    tile_pixel(c, u, v);
+    int u, v, s;
+    quad_pixel(c, u, v, s);
     double acc[PRISM_NEQ];
 #pragma unroll
     for (int q = 0; q < PRISM_NEQ; ++q) acc[q] = 0.0;
     if (u < c.W && v < c.H) {
         float dir[3];
         ray_dir32(c, P.f, u, v, dir);
-        RayHit h = march(g, c, P.f, dir, map);
+        int k = march_quad(g, c, P.f, dir, map, bits, s);
         long long pix = (long long)blockIdx.y * c.W * c.H + (long long)v * c.W + u;
-        float J[4][6];
-        double r[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int m = 0; m < 6; ++m) J[a][m] = 0.0f;
-        uint8_t rm = 0;
-        bool valid = h.k >= 1;
-        Shade s;
+        float row[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        double r = 0.0;
+        int rm = 0;
+        bool valid = k >= 1;
+        double value = 0.0;
         if (valid) {
-            s = shade(g, gd, cd, P.d, u, v, map, h);
+            Cell c0 = sample_cell(g, c, P.f, dir, k - 1), c1 = sample_cell(g, c, P.f, dir, k);
+            QuadShade q = shade_quad(g, gd, cd, P.d, u, v, map, c0, c1, k, s);
+            value = q.value;
             float D = obs_depth[pix];
             if (depth_ok(D)) {
-                ray_jacobian(g, map, h, s, dir, J);
-                r[0] = s.depth - (double)D;
-                double l1 = 0.0;
-#pragma unroll
-                for (int ch = 0; ch < 3; ++ch) {
-                    r[1 + ch] = s.rgb[ch] - (double)obs_rgb[3 * pix + ch];
-                    l1 += fabs(r[1 + ch]);
-                }
-                if (fabs(r[0]) <= wt.gate_depth) {
-                    neq_add(acc, J[0], r[0], wt.w_depth);
-                    rm |= 1;
-                }
-                if (l1 <= wt.gate_rgb) {
-#pragma unroll
-                    for (int ch = 0; ch < 3; ++ch) neq_add(acc, J[1 + ch], r[1 + ch], wt.w_rgb);
-                    rm |= 2;
-                }
-                if (rm) acc[28] = 1.0;
+                jac_row_quad(g, map, c0, c1, q, dir, s, row);
+                r = s == 0 ? value - (double)D : value - (double)obs_rgb[3 * pix + s - 1];
+                // colour gate on |r_r| + |r_g| + |r_b| (lanes 1-3), depth gate on lane 0
+                double l1 = s == 0 ? 0.0 : fabs(r);
+                l1 += __shfl_xor(l1, 1, 64);
+                l1 += __shfl_xor(l1, 2, 64);
+                bool use_depth = fabs(quad_bcast(r, 0)) <= wt.gate_depth;
+                bool use_rgb = l1 <= wt.gate_rgb;
+                rm = (use_depth ? 1 : 0) | (use_rgb ? 2 : 0);
+                if (s == 0 ? use_depth : use_rgb) neq_add(acc, row, r, s == 0 ? wt.w_depth : wt.w_rgb);
+                if (rm && s == 0) acc[28] = 1.0;
             }
             if (!rm) {
 #pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int m = 0; m < 6; ++m) J[a][m] = 0.0f;
+                for (int m = 0; m < 6; ++m) row[m] = 0.0f;
+                r = 0.0;
             }
         }
-        if (depth) depth[pix] = valid ? (float)s.depth : 0.0f;
-        if (rgb) {
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) rgb[3 * pix + ch] = valid ? (float)s.rgb[ch] : 0.0f;
+        if (s == 0) {
+            if (depth) depth[pix] = valid ? (float)value : 0.0f;
+            if (mask) mask[pix] = valid ? 1 : 0;
+            if (rowmask) rowmask[pix] = (uint8_t)rm;
+        } else if (rgb) {
+            rgb[3 * pix + s - 1] = valid ? (float)value : 0.0f;
         }
-        if (mask) mask[pix] = valid ? 1 : 0;
         if (Jout) {
-            float4* jo = reinterpret_cast<float4*>(Jout + 24 * pix);
+            float* jo = Jout + 24 * pix + 6 * s;
 #pragma unroll
-            for (int q = 0; q < 6; ++q)
-                jo[q] = make_float4(J[(4 * q) / 6][(4 * q) % 6], J[(4 * q + 1) / 6][(4 * q + 1) % 6],
-                                    J[(4 * q + 2) / 6][(4 * q + 2) % 6], J[(4 * q + 3) / 6][(4 * q + 3) % 6]);
+            for (int m = 0; m < 6; ++m) jo[m] = row[m];
         }
-        if (resid)
-            reinterpret_cast<float4*>(resid)[pix] = make_float4((float)r[0], (float)r[1], (float)r[2], (float)r[3]);
-        if (rowmask) rowmask[pix] = rm;
+        if (resid) resid[4 * pix + s] = (float)r;
     }
     block_reduce29(acc, lds, partials + ((long long)blockIdx.y * gridDim.x + blockIdx.x) * PRISM_NEQ);
 }
@@ -391,7 +570,7 @@ __global__ __launch_bounds__(256) void k_render_vjp(GridC g, CamC c, GridD gd, C
                                                     float* __restrict__ grad_mean,
                                                     double* __restrict__ partials) {
     __shared__ BlockPose sp;
-    __shared__ double lds[PRISM_NEQ * 16];
+    __shared__ double lds[kRedLds];
     const BlockPose& P = block_pose(poses, &sp);
     int u, v;
     tile_pixel(c, u, v);
@@ -454,16 +633,25 @@ __global__ __launch_bounds__(256) void k_render_vjp(GridC g, CamC c, GridD gd, C
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-int render_blocks(const CamC& c) { return ((c.W + 15) >> 4) * ((c.H + 15) >> 4); }
+int render_blocks(const CamC& c) { return ((c.W + 7) >> 3) * ((c.H + 7) >> 3); }
+int vjp_blocks(const CamC& c) { return ((c.W + 15) >> 4) * ((c.H + 15) >> 4); }
+
+static size_t bits_lds(const GridC& g, const unsigned* bits) {
+    int nwords = (g.nb * g.nb * g.nb + 31) >> 5;
+    return (bits && nwords <= kMaxLdsWords) ? (size_t)nwords * 4 : 0;
+}
 
 hipError_t launch_render(const GridC& g, const CamC& c, const GridD& gd, const CamD& cd, int dtype, const void* map,
-                         const prism_pose* poses, int n_frames, float* depth, float* rgb, uint8_t* mask,
-                         int32_t* hit_k, hipStream_t st) {
+                         const unsigned* bits, const prism_pose* poses, int n_frames, float* depth, float* rgb,
+                         uint8_t* mask, int32_t* hit_k, hipStream_t st) {
     dim3 grid(render_blocks(c), n_frames);
+    size_t lds = bits_lds(g, bits);
     if (dtype == PRISM_BF16)
-        k_render<uint16_t><<<grid, 256, 0, st>>>(g, c, gd, cd, (const uint16_t*)map, poses, depth, rgb, mask, hit_k);
+        k_render<uint16_t><<<grid, 256, lds, st>>>(g, c, gd, cd, (const uint16_t*)map, bits, poses, depth, rgb, mask,
+                                                   hit_k);
     else
-        k_render<float><<<grid, 256, 0, st>>>(g, c, gd, cd, (const float*)map, poses, depth, rgb, mask, hit_k);
+        k_render<float><<<grid, 256, lds, st>>>(g, c, gd, cd, (const float*)map, bits, poses, depth, rgb, mask,
+                                                hit_k);
     return hipGetLastError();
 }
 
@@ -475,23 +663,25 @@ hipError_t launch_normals(const CamC& c, int n_frames, const float* depth, const
 }
 
 hipError_t launch_render_jac(const GridC& g, const CamC& c, const GridD& gd, const CamD& cd, int dtype,
-                             const void* map, const prism_pose* poses, int n_frames, const float* obs_depth,
-                             const float* obs_rgb, const WeightsC& w, float* depth, float* rgb, uint8_t* mask,
-                             float* J, float* resid, uint8_t* rowmask, double* partials, hipStream_t st) {
+                             const void* map, const unsigned* bits, const prism_pose* poses, int n_frames,
+                             const float* obs_depth, const float* obs_rgb, const WeightsC& w, float* depth,
+                             float* rgb, uint8_t* mask, float* J, float* resid, uint8_t* rowmask, double* partials,
+                             hipStream_t st) {
     dim3 grid(render_blocks(c), n_frames);
+    size_t lds = bits_lds(g, bits);
     if (dtype == PRISM_BF16)
-        k_render_jac<uint16_t><<<grid, 256, 0, st>>>(g, c, gd, cd, (const uint16_t*)map, poses, obs_depth, obs_rgb,
-                                                     w, depth, rgb, mask, J, resid, rowmask, partials);
+        k_render_jac<uint16_t><<<grid, 256, lds, st>>>(g, c, gd, cd, (const uint16_t*)map, bits, poses, obs_depth,
+                                                       obs_rgb, w, depth, rgb, mask, J, resid, rowmask, partials);
     else
-        k_render_jac<float><<<grid, 256, 0, st>>>(g, c, gd, cd, (const float*)map, poses, obs_depth, obs_rgb, w,
-                                                  depth, rgb, mask, J, resid, rowmask, partials);
+        k_render_jac<float><<<grid, 256, lds, st>>>(g, c, gd, cd, (const float*)map, bits, poses, obs_depth, obs_rgb,
+                                                    w, depth, rgb, mask, J, resid, rowmask, partials);
     return hipGetLastError();
 }
 
 hipError_t launch_render_vjp(const GridC& g, const CamC& c, const GridD& gd, const CamD& cd, const float* map,
                              const prism_pose* poses, int n_frames, const int32_t* hit_k, const float* g_depth,
                              const float* g_rgb, float* grad_mean, double* partials, hipStream_t st) {
-    dim3 grid(render_blocks(c), n_frames);
+    dim3 grid(vjp_blocks(c), n_frames);
     k_render_vjp<<<grid, 256, 0, st>>>(g, c, gd, cd, map, poses, hit_k, g_depth, g_rgb, grad_mean, partials);
     return hipGetLastError();
 }

@@ -40,45 +40,66 @@ __device__ inline void symmetrize(double* A, int n) {
     __syncthreads();
 }
 
-// in-place lower Cholesky of n x n (single thread); false if not PD
-__device__ inline bool chol(double* A, int n) {
-    for (int j = 0; j < n; ++j) {
-        double s = A[j * n + j];
-        for (int k = 0; k < j; ++k) s -= A[j * n + k] * A[j * n + k];
-        if (!(s > 0.0)) return false;
-        double d = sqrt(s);
-        A[j * n + j] = d;
-        for (int i = j + 1; i < n; ++i) {
-            double t = A[i * n + j];
-            for (int k = 0; k < j; ++k) t -= A[i * n + k] * A[j * n + k];
-            A[i * n + j] = t / d;
+// In-place lower Cholesky of an N x N matrix (single thread); false if not
+// positive definite.  Sizes are compile-time constants and every loop is
+// unrolled so the matrix stays in registers.
+template <int N>
+__device__ inline bool chol(double* A) {
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double s = A[j * N + j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) s -= A[j * N + k] * A[j * N + k];
+        ok = ok && (s > 0.0);
+        double d = sqrt(fmax(s, 1e-300));
+        double id = 1.0 / d;
+        A[j * N + j] = d;
+#pragma unroll
+        for (int i = j + 1; i < N; ++i) {
+            double t = A[i * N + j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) t -= A[i * N + k] * A[j * N + k];
+            A[i * N + j] = t * id;
         }
-        for (int i = 0; i < j; ++i) A[i * n + j] = 0.0;
+#pragma unroll
+        for (int i = 0; i < j; ++i) A[i * N + j] = 0.0;
     }
-    return true;
+    return ok;
 }
 
 // solve L L^T x = b in place (single thread)
-__device__ inline void chol_solve(const double* L, double* b, int n) {
-    for (int i = 0; i < n; ++i) {
+template <int N>
+__device__ inline void chol_solve(const double* L, double* b) {
+    double id[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) id[i] = 1.0 / L[i * N + i];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
         double s = b[i];
-        for (int k = 0; k < i; ++k) s -= L[i * n + k] * b[k];
-        b[i] = s / L[i * n + i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) s -= L[i * N + k] * b[k];
+        b[i] = s * id[i];
     }
-    for (int i = n - 1; i >= 0; --i) {
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {
         double s = b[i];
-        for (int k = i + 1; k < n; ++k) s -= L[k * n + i] * b[k];
-        b[i] = s / L[i * n + i];
+#pragma unroll
+        for (int k = i + 1; k < N; ++k) s -= L[k * N + i] * b[k];
+        b[i] = s * id[i];
     }
 }
 
-// inverse from the Cholesky factor, columns in parallel (threads < n)
-__device__ inline void chol_inverse(const double* L, double* Ainv, int n) {
-    if ((int)threadIdx.x < n) {
-        double x[12];
-        for (int i = 0; i < n; ++i) x[i] = (i == (int)threadIdx.x) ? 1.0 : 0.0;
-        chol_solve(L, x, n);
-        for (int i = 0; i < n; ++i) Ainv[i * n + threadIdx.x] = x[i];
+// inverse from the Cholesky factor (in LDS), one column per thread (< N)
+template <int N>
+__device__ inline void chol_inverse(const double* L, double* Ainv) {
+    if ((int)threadIdx.x < N) {
+        double x[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) x[i] = (i == (int)threadIdx.x) ? 1.0 : 0.0;
+        chol_solve<N>(L, x);
+#pragma unroll
+        for (int i = 0; i < N; ++i) Ainv[i * N + threadIdx.x] = x[i];
     }
     __syncthreads();
 }
@@ -130,48 +151,74 @@ __device__ inline void so3_log(const double R[9], double w[3]) {
         return;
     }
     if (M_PI - th < 1e-6) {
-        int k = (R[0] >= R[4] && R[0] >= R[8]) ? 0 : (R[4] >= R[8] ? 1 : 2);
-        double ax[3];
-        for (int i = 0; i < 3; ++i) ax[i] = (R[i * 3 + k] + (i == k ? 1.0 : 0.0)) * 0.5;
-        double n = sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
-        for (int i = 0; i < 3; ++i) w[i] = th * ax[i] / n;
+        // near pi: axis from the column of (R + I)/2 with the largest diagonal
+        double ax0, ax1, ax2;
+        if (R[0] >= R[4] && R[0] >= R[8]) {
+            ax0 = (R[0] + 1.0) * 0.5; ax1 = R[3] * 0.5; ax2 = R[6] * 0.5;
+        } else if (R[4] >= R[8]) {
+            ax0 = R[1] * 0.5; ax1 = (R[4] + 1.0) * 0.5; ax2 = R[7] * 0.5;
+        } else {
+            ax0 = R[2] * 0.5; ax1 = R[5] * 0.5; ax2 = (R[8] + 1.0) * 0.5;
+        }
+        double n = sqrt(ax0 * ax0 + ax1 * ax1 + ax2 * ax2);
+        w[0] = th * ax0 / n;
+        w[1] = th * ax1 / n;
+        w[2] = th * ax2 / n;
         return;
     }
     double f = th / (2.0 * sin(th));
     for (int i = 0; i < 3; ++i) w[i] = f * v[i];
 }
 
+// unit-quaternion rotation for the pose algebra (one reciprocal)
 __device__ inline void quat_to_R9(const double q[4], double R[9]) {
-    prism_pose p;
-    for (int i = 0; i < 4; ++i) p.q[i] = q[i];
-    double M[3][3];
-    quat_to_rot64(p, M);
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) R[i * 3 + j] = M[i][j];
+    double in = 1.0 / sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    double w = q[0] * in, x = q[1] * in, y = q[2] * in, z = q[3] * in;
+    R[0] = 1.0 - 2.0 * (y * y + z * z);
+    R[1] = 2.0 * (x * y - w * z);
+    R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);
+    R[4] = 1.0 - 2.0 * (x * x + z * z);
+    R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);
+    R[7] = 2.0 * (y * z + w * x);
+    R[8] = 1.0 - 2.0 * (x * x + y * y);
 }
 
-// rotation matrix -> unit quaternion (w >= 0), largest-diagonal branch
+// rotation matrix -> unit quaternion (w >= 0), branch on the largest of
+// trace and diagonal (constant indices only, so nothing leaves registers)
 __device__ inline void R9_to_quat(const double R[9], double q[4]) {
     double tr = R[0] + R[4] + R[8];
     if (tr > 0.0) {
-        double s = 2.0 * sqrt(tr + 1.0);
+        double s = 2.0 * sqrt(tr + 1.0), is = 1.0 / s;
         q[0] = 0.25 * s;
-        q[1] = (R[7] - R[5]) / s;
-        q[2] = (R[2] - R[6]) / s;
-        q[3] = (R[3] - R[1]) / s;
+        q[1] = (R[7] - R[5]) * is;
+        q[2] = (R[2] - R[6]) * is;
+        q[3] = (R[3] - R[1]) * is;
+    } else if (R[0] >= R[4] && R[0] >= R[8]) {
+        double s = 2.0 * sqrt(1.0 + R[0] - R[4] - R[8]), is = 1.0 / s;
+        q[0] = (R[7] - R[5]) * is;
+        q[1] = 0.25 * s;
+        q[2] = (R[1] + R[3]) * is;
+        q[3] = (R[2] + R[6]) * is;
+    } else if (R[4] >= R[8]) {
+        double s = 2.0 * sqrt(1.0 + R[4] - R[8] - R[0]), is = 1.0 / s;
+        q[0] = (R[2] - R[6]) * is;
+        q[1] = (R[1] + R[3]) * is;
+        q[2] = 0.25 * s;
+        q[3] = (R[5] + R[7]) * is;
     } else {
-        int i = (R[0] >= R[4] && R[0] >= R[8]) ? 0 : (R[4] >= R[8] ? 1 : 2);
-        int j = (i + 1) % 3, k = (i + 2) % 3;
-        double s = 2.0 * sqrt(1.0 + R[i * 4] - R[j * 4] - R[k * 4]);
-        q[0] = (R[k * 3 + j] - R[j * 3 + k]) / s;
-        q[1 + i] = 0.25 * s;
-        q[1 + j] = (R[j * 3 + i] + R[i * 3 + j]) / s;
-        q[1 + k] = (R[k * 3 + i] + R[i * 3 + k]) / s;
+        double s = 2.0 * sqrt(1.0 + R[8] - R[0] - R[4]), is = 1.0 / s;
+        q[0] = (R[3] - R[1]) * is;
+        q[1] = (R[2] + R[6]) * is;
+        q[2] = (R[5] + R[7]) * is;
+        q[3] = 0.25 * s;
     }
-    if (q[0] < 0.0)
-        for (int a = 0; a < 4; ++a) q[a] = -q[a];
-    double n = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    for (int a = 0; a < 4; ++a) q[a] /= n;
+    if (q[0] < 0.0) {
+        q[0] = -q[0]; q[1] = -q[1]; q[2] = -q[2]; q[3] = -q[3];
+    }
+    double in = 1.0 / sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    q[0] *= in; q[1] *= in; q[2] *= in; q[3] *= in;
 }
 
 // tangent of pose a relative to pose b: (t_a - t_b, Log(R_a R_b^T))
@@ -220,14 +267,34 @@ __device__ inline void unpack_H(const double* neq, double* H, double* g) {
     for (int a = 0; a < 6; ++a) g[a] = neq[21 + a];
 }
 
+// The state lives in global memory; each kernel copies it into LDS once
+// (one parallel round trip), works on the copy and writes it back, so the
+// single-thread parts never wait on dependent global loads.
+__device__ inline void state_in(const prism_filter_state* g, prism_filter_state* l) {
+    const unsigned long long* s = reinterpret_cast<const unsigned long long*>(g);
+    unsigned long long* d = reinterpret_cast<unsigned long long*>(l);
+    for (int i = threadIdx.x; i < (int)(sizeof(prism_filter_state) / 8); i += blockDim.x) d[i] = s[i];
+    __syncthreads();
+}
+
+__device__ inline void state_out(const prism_filter_state* l, prism_filter_state* g) {
+    __syncthreads();
+    const unsigned long long* s = reinterpret_cast<const unsigned long long*>(l);
+    unsigned long long* d = reinterpret_cast<unsigned long long*>(g);
+    for (int i = threadIdx.x; i < (int)(sizeof(prism_filter_state) / 8); i += blockDim.x) d[i] = s[i];
+}
+
 // ---------------------------------------------------------------------------
 // predict + split
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_predict(prism_filter_state* __restrict__ S,
+__global__ __launch_bounds__(256) void k_predict(prism_filter_state* __restrict__ Sg,
                                                  const double* __restrict__ u, TransC tc) {
     __shared__ double M[144], G[144], T1[144], T2[144], P[144], Spp[36], L[36], Sinv[36];
     __shared__ double vnew[6], E[9], Jl[9];
     __shared__ int ok;
+    __shared__ prism_filter_state Ls;
+    state_in(Sg, &Ls);
+    prism_filter_state* S = &Ls;
     if (threadIdx.x == 0) {
         S->flags = 0;
         for (int i = 0; i < 6; ++i) S->u[i] = u[i];
@@ -295,13 +362,14 @@ __global__ __launch_bounds__(256) void k_predict(prism_filter_state* __restrict_
         L[e] = T2[i * 12 + j];
     }
     __syncthreads();
-    if (threadIdx.x == 0) ok = chol(L, 6);
+    if (threadIdx.x == 0) ok = chol<6>(L);
     __syncthreads();
     if (!ok) {
         if (threadIdx.x == 0) S->flags |= PRISM_FLAG_CHOL_FALLBACK;
+        state_out(S, Sg);
         return;
     }
-    chol_inverse(L, Sinv, 6);
+    chol_inverse<6>(L, Sinv);
     symmetrize(Sinv, 6);
     // D = Svp Sinv
     for (int e = threadIdx.x; e < 36; e += blockDim.x) {
@@ -324,16 +392,14 @@ __global__ __launch_bounds__(256) void k_predict(prism_filter_state* __restrict_
         S->D[e] = T1[e];
         S->Sv[e] = P[e];
     }
+    state_out(S, Sg);
 }
 
 // ---------------------------------------------------------------------------
 // one Gauss-Newton step of the MAP pose objective
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_gn_step(prism_filter_state* __restrict__ S,
-                                                 const double* __restrict__ partials, int nblocks) {
-    __shared__ double red[PRISM_NEQ * 16], neq[PRISM_NEQ];
-    sum_partials(partials, nblocks, red, neq);
-    if (threadIdx.x != 0) return;
+// thread 0: one Gauss-Newton step on the state copy
+__device__ inline void gn_step_body(prism_filter_state* S, const double* neq) {
     if (S->flags & PRISM_FLAG_CHOL_FALLBACK) return;
     if (!(neq[28] > 0.0)) S->flags |= PRISM_FLAG_NO_VALID_PIXELS;
     double H[36], g[6], A[36], b[6], e[6];
@@ -348,25 +414,42 @@ __global__ __launch_bounds__(256) void k_gn_step(prism_filter_state* __restrict_
         }
         b[i] = -(2.0 * g[i] + le);
     }
-    if (!chol(A, 6)) {
+    if (!chol<6>(A)) {
         S->flags |= PRISM_FLAG_CHOL_FALLBACK;
         S->iter = pr;
         return;
     }
-    chol_solve(A, b, 6);
+    chol_solve<6>(A, b);
     retract(it, b);
     S->iter = it;
+}
+
+__global__ __launch_bounds__(256) void k_gn_step(prism_filter_state* __restrict__ Sg,
+                                                 const double* __restrict__ partials, int nblocks) {
+    __shared__ double red[kRedLds], neq[PRISM_NEQ];
+    __shared__ prism_filter_state Ls;
+    state_in(Sg, &Ls);
+    sum_partials(partials, nblocks, red, neq);
+    if (threadIdx.x == 0) gn_step_body(&Ls, neq);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Sg->iter = Ls.iter;
+        Sg->flags = Ls.flags;
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Laplace covariance, EMA, product with the velocity conditional
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_laplace_combine(prism_filter_state* __restrict__ S,
+__global__ __launch_bounds__(256) void k_laplace_combine(prism_filter_state* __restrict__ Sg,
                                                          const double* __restrict__ partials, int nblocks,
                                                          double ema) {
-    __shared__ double red[PRISM_NEQ * 16], neq[PRISM_NEQ];
+    __shared__ double red[kRedLds], neq[PRISM_NEQ];
     __shared__ double A[36], Sl[36], Sb[36], D[36], T[36], P[144], e[6];
     __shared__ int ok;
+    __shared__ prism_filter_state Ls;
+    state_in(Sg, &Ls);
+    prism_filter_state* S = &Ls;
     sum_partials(partials, nblocks, red, neq);
     if (threadIdx.x < PRISM_NEQ) S->neq[threadIdx.x] = neq[threadIdx.x];
     if (threadIdx.x == 0) {
@@ -374,7 +457,7 @@ __global__ __launch_bounds__(256) void k_laplace_combine(prism_filter_state* __r
         double H[36], g[6];
         unpack_H(neq, H, g);
         for (int i = 0; i < 36; ++i) A[i] = 2.0 * H[i] + S->Lp[i];
-        ok = !(S->flags & PRISM_FLAG_CHOL_FALLBACK) && chol(A, 6);
+        ok = !(S->flags & PRISM_FLAG_CHOL_FALLBACK) && chol<6>(A);
         if (!ok) {
             S->flags |= PRISM_FLAG_CHOL_FALLBACK;
             S->iter = S->prior;
@@ -382,15 +465,15 @@ __global__ __launch_bounds__(256) void k_laplace_combine(prism_filter_state* __r
     }
     __syncthreads();
     if (ok) {
-        chol_inverse(A, Sl, 6);
+        chol_inverse<6>(A, Sl);
     } else {
         // prior pose covariance = Lp^-1
         if (threadIdx.x == 0) {
             for (int i = 0; i < 36; ++i) T[i] = S->Lp[i];
-            chol(T, 6);
+            chol<6>(T);
         }
         __syncthreads();
-        chol_inverse(T, Sl, 6);
+        chol_inverse<6>(T, Sl);
     }
     symmetrize(Sl, 6);
     if (threadIdx.x < 36) {
@@ -431,6 +514,7 @@ __global__ __launch_bounds__(256) void k_laplace_combine(prism_filter_state* __r
         S->anchor = S->iter;
         S->step += 1;
     }
+    state_out(S, Sg);
 }
 
 __global__ void k_first_frame(prism_filter_state* __restrict__ S) {
@@ -443,7 +527,7 @@ __global__ void k_first_frame(prism_filter_state* __restrict__ S) {
 // each frame go to out[frame * stride + q]
 __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partials, int nblocks, int nvals,
                                                   double* __restrict__ out, int stride) {
-    __shared__ double red[PRISM_NEQ * 16], neq[PRISM_NEQ];
+    __shared__ double red[kRedLds], neq[PRISM_NEQ];
     sum_partials(partials + (long long)blockIdx.x * nblocks * PRISM_NEQ, nblocks, red, neq);
     if ((int)threadIdx.x < nvals) out[(long long)blockIdx.x * stride + threadIdx.x] = neq[threadIdx.x];
 }

@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) void k_track_p2(CamC c, CamD cd, const prism_p
                                                   uint8_t* __restrict__ rowmask,
                                                   double* __restrict__ partials) {
     __shared__ Rel32 srel;
-    __shared__ double lds[PRISM_NEQ * 16];
+    __shared__ double lds[kRedLds];
     if (threadIdx.x == 0) {
         Pose64 P = load_pose64(pose), Q = load_pose64(pose_prev);
         double d[3] = {P.t[0] - Q.t[0], P.t[1] - Q.t[1], P.t[2] - Q.t[2]};

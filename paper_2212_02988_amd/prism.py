@@ -104,6 +104,7 @@ _SIGS = {
     "prism_map_init": (["p", "p", ctypes.c_float, ctypes.c_float, ctypes.c_float, "p"], None),
     "prism_map_from_dense": (["p", "p", "p", "p", "p"], None),
     "prism_map_to_dense": (["p", "p", "p", "p", "p"], None),
+    "prism_map_refresh": (["p", "p", "p"], None),
     "prism_bricks_to_dense": ([ctypes.c_int32, ctypes.c_int32, "p", "p", "p"], None),
     "prism_dense_to_bricks": ([ctypes.c_int32, ctypes.c_int32, "p", "p", "p"], None),
     "prism_render": (["p", "p", "p", "p", ctypes.c_int32, "p", "p", "p", "p", "p", "p", ctypes.c_double, "p"], None),
@@ -213,6 +214,11 @@ class VoxelMap:
         if var4 is not None:
             _dev(var4, torch.float32, "var4", (4, n, n, n))
         _check(lib().prism_map_from_dense(_by(self.grid), _ptr(self.buf), _ptr(mean4), _ptr(var4), _stream(stream)))
+        return self
+
+    def refresh(self, stream=None):
+        """Recompute the brick summary after writing the mean planes directly."""
+        _check(lib().prism_map_refresh(_by(self.grid), _ptr(self.buf), _stream(stream)))
         return self
 
     def to_dense(self, stream=None):

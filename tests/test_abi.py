@@ -46,10 +46,15 @@ def test_map_bytes_and_validation(P):
     b = ctypes.c_size_t()
     g = P.Grid.make(64, 0.04)
     assert L.prism_map_bytes(ctypes.byref(g), ctypes.byref(b)) == 0
-    assert b.value == 8 * 64 ** 3 * 4
+    nb3 = (64 // 8) ** 3
+    r256 = lambda x: (x + 255) // 256 * 256
+    nseg = (nb3 + 255) // 256
+    # summary, free-space bits, counts, brick list, segment lengths, pose scratch
+    aux = r256(4 * nb3) + r256(4 * ((nb3 + 31) // 32)) + r256(4 * 2048) + r256(4 * nseg * 256) + r256(4 * nseg) + 256
+    assert b.value == 8 * 64 ** 3 * 4 + aux
     g = P.Grid.make(64, 0.04, dtype=P.PRISM_BF16)
     assert L.prism_map_bytes(ctypes.byref(g), ctypes.byref(b)) == 0
-    assert b.value == 8 * 64 ** 3 * 2
+    assert b.value == 8 * 64 ** 3 * 2 + aux
     for bad in (P.Grid.make(60, 0.04), P.Grid.make(64, 0.04, dtype=7), P.Grid.make(2048, 0.01)):
         assert L.prism_map_bytes(ctypes.byref(bad), ctypes.byref(b)) == 2
         assert b"unsupported" in L.prism_last_error()
@@ -87,7 +92,7 @@ def test_workspace_and_filter_sizes(P):
     cam = P.Camera.make(320, 240, 240, 240, 160, 120, 0.1, 7.5, 128)
     b = ctypes.c_size_t()
     assert L.prism_reduce_workspace_bytes(ctypes.byref(cam), 2, ctypes.byref(b)) == 0
-    assert b.value == 2 * 300 * 29 * 8
+    assert b.value == 2 * (40 * 30) * 29 * 8      # 8x8-pixel workgroups of the render Jacobian
     cfg = P.filter_cfg(P.Grid.make(256, 0.025), cam, P.FilterParams())
     assert L.prism_filter_bytes(ctypes.byref(cfg), ctypes.byref(b)) == 0
     assert b.value >= 30 * 320 * 240
