@@ -361,6 +361,21 @@ prism_status prism_pose_update(prism_filter *f, const prism_frame *frame, hipStr
 prism_status prism_filter_step(prism_filter *const *fs, int32_t n, const prism_frame *frames,
                                hipStream_t stream);
 
+/* Same result as prism_filter_step, bit for bit, for serving loops that
+ * replay steps: after a filter's first frame each step is launched as one
+ * HIP graph that the handle records the first time it sees a frame with
+ * these buffer addresses (depth, rgb, u) and replays afterwards, so callers
+ * keep a few fixed input slots per stream and copy each frame into one.  A
+ * handle keeps up to 4 graphs; recording a fifth evicts the least recently
+ * used one once its last launch has finished.  stream must be a non-default
+ * stream that is not being captured; a graph launched on a stream other than
+ * its previous launch's first waits (on the host) for that launch.  The
+ * graphs hold the addresses of the handle's state and map buffers, which
+ * must stay where they are; prism_filter_destroy waits for each graph's last
+ * launch, then frees them. */
+prism_status prism_filter_step_graph(prism_filter *const *fs, int32_t n, const prism_frame *frames,
+                                     hipStream_t stream);
+
 /* Device pointer to the filter's prism_filter_state (inside state_mem). */
 prism_status prism_filter_state_ptr(const prism_filter *f, prism_filter_state **state);
 

@@ -191,9 +191,30 @@ struct prism_filter {
     void* map;
     int64_t steps;
     prism_filter_state host_state;   // source of prism_filter_reset uploads
+    // executable graphs of a full step, keyed by the frame's buffer addresses
+    struct StepGraph {
+        const void *depth, *rgb, *u;
+        hipGraphExec_t exec;
+        hipEvent_t done;            // recorded after each launch of exec
+        hipStream_t last_stream;    // stream of the latest launch (NULL: never launched)
+        uint64_t last_use;
+    };
+    static constexpr int kMaxGraphs = 4;
+    StepGraph graphs[kMaxGraphs];
+    int n_graphs;
+    uint64_t graph_clock;
 };
 
 namespace {
+
+// Waits for the graph's last launch, then frees it.  Every earlier launch is
+// complete by then: a launch on a new stream first waits for the previous one.
+hipError_t release_graph(prism_filter::StepGraph& G) {
+    hipError_t e = hipEventSynchronize(G.done);
+    hipGraphExecDestroy(G.exec);
+    hipEventDestroy(G.done);
+    return e;
+}
 
 struct StateLayout {
     size_t state, a_depth, a_rgb, a_normals, a_mask, a_nmask, partials, total;
@@ -540,7 +561,14 @@ prism_status prism_filter_create(const prism_filter_cfg* cfg, void* state_mem, v
 }
 
 prism_status prism_filter_destroy(prism_filter* f) {
+    if (!f) return PRISM_OK;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < f->n_graphs; ++i) {
+        hipError_t ei = release_graph(f->graphs[i]);
+        if (e == hipSuccess) e = ei;
+    }
     delete f;
+    if (e != hipSuccess) return fail(PRISM_HIP_ERROR, "releasing step graphs: %s", hipGetErrorString(e));
     return PRISM_OK;
 }
 
@@ -573,23 +601,123 @@ prism_status prism_pose_update(prism_filter* f, const prism_frame* frame, hipStr
     return pose_update_impl(f, frame, stream);
 }
 
-prism_status prism_filter_step(prism_filter* const* fs, int32_t n, const prism_frame* frames, hipStream_t stream) {
+namespace {
+
+prism_status step_one(prism_filter* f, const prism_frame* fr, hipStream_t stream) {
+    prism_status s;
+    if (f->steps == 0) {
+        if ((s = map_and_anchor(f, fr, stream))) return s;
+        HIP_TRY(launch_first_frame(f->S, stream));
+    } else {
+        if ((s = pose_update_impl(f, fr, stream))) return s;
+        if ((s = map_and_anchor(f, fr, stream))) return s;
+    }
+    f->steps += 1;
+    return PRISM_OK;
+}
+
+prism_status check_batch(prism_filter* const* fs, int32_t n, const prism_frame* frames) {
     REQUIRE(fs && frames && n >= 1, "need n >= 1 filters and frames");
     for (int i = 0; i < n; ++i) {
         REQUIRE(fs[i], "filter %d is NULL", i);
         prism_status s = check_frame(&frames[i], fs[i]->steps > 0);
         if (s) return s;
     }
+    return PRISM_OK;
+}
+
+// Records the steady-state step (state filter, map update, anchor) of f for
+// the buffers of fr into an executable graph.
+prism_status capture_step(prism_filter* f, const prism_frame* fr, hipStream_t stream, hipGraphExec_t* out) {
+    HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    prism_status s = pose_update_impl(f, fr, stream);
+    if (!s) s = map_and_anchor(f, fr, stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(stream, &g);
+    if (s) {
+        if (g) hipGraphDestroy(g);
+        return s;
+    }
+    if (e != hipSuccess || !g) {
+        if (g) hipGraphDestroy(g);
+        return fail(PRISM_HIP_ERROR, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    }
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(PRISM_HIP_ERROR, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    return PRISM_OK;
+}
+
+prism_status graph_for(prism_filter* f, const prism_frame* fr, hipStream_t stream, int* out) {
+    f->graph_clock += 1;
+    for (int i = 0; i < f->n_graphs; ++i) {
+        prism_filter::StepGraph& G = f->graphs[i];
+        if (G.depth == fr->depth && G.rgb == fr->rgb && G.u == fr->u) {
+            G.last_use = f->graph_clock;
+            *out = i;
+            return PRISM_OK;
+        }
+    }
+    hipEvent_t done = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    hipGraphExec_t ex = nullptr;
+    prism_status s = capture_step(f, fr, stream, &ex);
+    if (s) {
+        hipEventDestroy(done);
+        return s;
+    }
+    int slot = f->n_graphs;
+    if (slot == prism_filter::kMaxGraphs) {
+        slot = 0;
+        for (int i = 1; i < f->n_graphs; ++i)
+            if (f->graphs[i].last_use < f->graphs[slot].last_use) slot = i;
+        hipError_t e = release_graph(f->graphs[slot]);   // the evicted graph may still be running
+        if (e != hipSuccess) {
+            hipGraphExecDestroy(ex);
+            hipEventDestroy(done);
+            f->n_graphs -= 1;
+            f->graphs[slot] = f->graphs[f->n_graphs];
+            return fail(PRISM_HIP_ERROR, "releasing an evicted step graph: %s", hipGetErrorString(e));
+        }
+    } else {
+        f->n_graphs += 1;
+    }
+    f->graphs[slot] = {fr->depth, fr->rgb, fr->u, ex, done, nullptr, f->graph_clock};
+    *out = slot;
+    return PRISM_OK;
+}
+
+}  // namespace
+
+prism_status prism_filter_step(prism_filter* const* fs, int32_t n, const prism_frame* frames, hipStream_t stream) {
+    prism_status s = check_batch(fs, n, frames);
+    if (s) return s;
+    for (int i = 0; i < n; ++i)
+        if ((s = step_one(fs[i], &frames[i], stream))) return s;
+    return PRISM_OK;
+}
+
+prism_status prism_filter_step_graph(prism_filter* const* fs, int32_t n, const prism_frame* frames,
+                                     hipStream_t stream) {
+    prism_status s = check_batch(fs, n, frames);
+    if (s) return s;
+    REQUIRE(stream != nullptr, "graph-replayed steps need a non-default stream");
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(stream, &cs));
+    REQUIRE(cs == hipStreamCaptureStatusNone, "stream is being captured: use prism_filter_step inside a capture");
     for (int i = 0; i < n; ++i) {
         prism_filter* f = fs[i];
-        prism_status s;
         if (f->steps == 0) {
-            if ((s = map_and_anchor(f, &frames[i], stream))) return s;
-            HIP_TRY(launch_first_frame(f->S, stream));
-        } else {
-            if ((s = pose_update_impl(f, &frames[i], stream))) return s;
-            if ((s = map_and_anchor(f, &frames[i], stream))) return s;
+            if ((s = step_one(f, &frames[i], stream))) return s;
+            continue;
         }
+        int slot = -1;
+        if ((s = graph_for(f, &frames[i], stream, &slot))) return s;
+        prism_filter::StepGraph& G = f->graphs[slot];
+        if (G.last_stream && G.last_stream != stream) HIP_TRY(hipEventSynchronize(G.done));
+        HIP_TRY(hipGraphLaunch(G.exec, stream));
+        HIP_TRY(hipEventRecord(G.done, stream));
+        G.last_stream = stream;
         f->steps += 1;
     }
     return PRISM_OK;

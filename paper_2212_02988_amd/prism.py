@@ -122,6 +122,7 @@ _SIGS = {
     "prism_filter_reset": (["p", "p", "p", "p"], None),
     "prism_pose_update": (["p", "p", "p"], None),
     "prism_filter_step": (["p", ctypes.c_int32, "p", "p"], None),
+    "prism_filter_step_graph": (["p", ctypes.c_int32, "p", "p"], None),
     "prism_filter_state_ptr": (["p", "p"], None),
     "prism_filter_anchor": (["p", "p", "p", "p", "p", "p"], None),
 }
@@ -465,6 +466,13 @@ class Filter:
         arr = (ctypes.c_void_p * 1)(self.h)
         _check(lib().prism_filter_step(arr, 1, _by(fr), _stream(stream)))
 
+    def step_graph(self, depth: torch.Tensor, rgb: torch.Tensor, u: Optional[torch.Tensor], stream):
+        """Same as step, replayed from a graph the handle records per input
+        buffer set (stream: a non-default torch stream)."""
+        fr = self.frame(depth, rgb, u)
+        arr = (ctypes.c_void_p * 1)(self.h)
+        _check(lib().prism_filter_step_graph(arr, 1, _by(fr), _stream(stream)))
+
     def pose_update(self, depth, rgb, u, stream=None):
         fr = self.frame(depth, rgb, u)
         _check(lib().prism_pose_update(self.h, _by(fr), _stream(stream)))
@@ -489,6 +497,14 @@ class Filter:
                     mask=view(ptrs[2], H * W, torch.uint8, (H, W)),
                     normals=view(ptrs[3], 12 * H * W, torch.float32, (H, W, 3)),
                     nmask=view(ptrs[4], H * W, torch.uint8, (H, W)))
+
+
+def filter_step_graph(filters: Sequence[Filter], depths, rgbs, us, stream):
+    """filter_step with each steady-state step replayed from a per-handle graph."""
+    n = len(filters)
+    frames = (Frame * n)(*[Filter.frame(d, r, u) for d, r, u in zip(depths, rgbs, us)])
+    hs = (ctypes.c_void_p * n)(*[f.h for f in filters])
+    _check(lib().prism_filter_step_graph(hs, n, frames, _stream(stream)))
 
 
 def filter_step(filters: Sequence[Filter], depths, rgbs, us, stream=None):

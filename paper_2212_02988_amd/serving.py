@@ -1,0 +1,291 @@
+"""Continuous-batching serving loop for many concurrent agent streams.
+
+Each agent stream is one PRISM filter whose voxel map and filter state stay
+resident in HBM for the stream's lifetime.  Frames arrive at their own pace
+(a stream's frames in order).  The loop
+
+* admits a stream only when its device footprint (map + filter state + input
+  slots, all sized by the library's size queries) fits the HBM budget, keeps
+  the others queued in arrival order, and admits queued streams as soon as
+  finished ones release their memory;
+* keeps every admitted stream's steps flowing without waiting for the
+  others: whenever a stream has a pending frame and a free input slot, the
+  frame is copied into the slot and the step is launched on the stream's HIP
+  stream (one of a small pool shared round-robin), as one HIP graph replay
+  recorded by the library per slot, so steps of different agents overlap on
+  the device and frames arriving while others run join immediately;
+* allows up to ``depth`` steps of one agent in flight (they are ordered on its
+  HIP stream; each slot is reused only after the step that read it finished),
+  and records per-frame latency from arrival to host-visible completion.
+
+Results are independent of the mix: every kernel of a step reads and writes
+only its own agent's buffers and every reduction has a fixed order, so an
+agent's state and map are bitwise the same alone and among others.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Callable, Deque, Dict, List, Optional, Tuple
+
+import numpy as np
+import torch
+
+from . import prism as P
+
+
+@dataclasses.dataclass
+class StreamSpec:
+    stream_id: int
+    grid: P.Grid
+    cam: P.Camera
+    params: P.FilterParams
+    x0: np.ndarray                   # (t, q, v, w), 13 values
+    P0: np.ndarray                   # 12 x 12
+    n_frames: int                    # the stream closes after this many frames
+
+
+@dataclasses.dataclass
+class _Frame:
+    arrival: float                   # host clock (perf_counter) of arrival
+    depth: object                    # [H, W] float32: device tensor or host array
+    rgb: object                      # [H, W, 3]
+    u: object                        # [6] float64 or None (first frame)
+    index: int
+
+
+def footprint_bytes(spec: StreamSpec, depth: int = 2, staged: bool = False) -> int:
+    """Device bytes an admitted stream holds: map, filter state and `depth`
+    input slots (depth f32, rgb f32, control f64), each rounded to the
+    allocator's 512-byte granule."""
+    r = lambda b: (b + 511) // 512 * 512
+    cfg = P.filter_cfg(spec.grid, spec.cam, spec.params)
+    npix = spec.cam.width * spec.cam.height
+    slot = r(4 * npix) + r(12 * npix) + r(48)
+    return r(P.map_bytes(spec.grid)) + r(P.filter_bytes(cfg)) + depth * slot
+
+
+class _Agent:
+    def __init__(self, spec: StreamSpec, hip_stream: torch.cuda.Stream, depth: int, staged: bool,
+                 use_graph: bool):
+        self.spec = spec
+        self.stream = hip_stream
+        self.depth = depth
+        self.staged = staged
+        self.use_graph = use_graph
+        H, W = spec.cam.height, spec.cam.width
+        with torch.cuda.stream(hip_stream):
+            self.filter = P.Filter(spec.grid, spec.cam, spec.params)
+            self.filter.map.init(stream=hip_stream)
+            self.filter.reset(spec.x0, spec.P0, stream=hip_stream)
+            self.slots = []
+            for _ in range(depth):
+                s = dict(d=torch.empty((H, W), dtype=torch.float32, device="cuda"),
+                         c=torch.empty((H, W, 3), dtype=torch.float32, device="cuda"),
+                         u=torch.zeros(6, dtype=torch.float64, device="cuda"))
+                if staged:
+                    s.update(hd=torch.empty((H, W), dtype=torch.float32).pin_memory(),
+                             hc=torch.empty((H, W, 3), dtype=torch.float32).pin_memory(),
+                             hu=torch.zeros(6, dtype=torch.float64).pin_memory())
+                self.slots.append(s)
+        self.pending: Deque[_Frame] = collections.deque()
+        self.in_flight: Deque[Tuple[torch.cuda.Event, _Frame]] = collections.deque()
+        self.launched = 0
+        self.done = 0
+
+    def ready(self) -> bool:
+        return bool(self.pending) and len(self.in_flight) < self.depth
+
+    def launch(self):
+        fr = self.pending.popleft()
+        s = self.slots[self.launched % self.depth]
+        st = self.stream
+        with torch.cuda.stream(st):
+            if self.staged:
+                s["hd"].numpy()[...] = fr.depth
+                s["hc"].numpy()[...] = fr.rgb
+                if fr.u is not None:
+                    s["hu"].numpy()[...] = fr.u
+                s["d"].copy_(s["hd"], non_blocking=True)
+                s["c"].copy_(s["hc"], non_blocking=True)
+                s["u"].copy_(s["hu"], non_blocking=True)
+            else:
+                s["d"].copy_(fr.depth, non_blocking=True)
+                s["c"].copy_(fr.rgb, non_blocking=True)
+                if fr.u is not None:
+                    s["u"].copy_(fr.u, non_blocking=True)
+            u = None if self.launched == 0 else s["u"]
+            if self.use_graph:
+                self.filter.step_graph(s["d"], s["c"], u, stream=st)
+            else:
+                self.filter.step(s["d"], s["c"], u, stream=st)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        self.in_flight.append((ev, fr))
+        self.launched += 1
+
+    def finished(self) -> bool:
+        return self.done >= self.spec.n_frames
+
+
+class ServingLoop:
+    """Admission, continuous launching and completion tracking of agent
+    streams on one GPU.
+
+    hbm_budget: bytes the streams may hold together (None: the free device
+    memory less `reserve`).  staged=False: frames are device tensors already in
+    HBM (copied device-to-device into a slot); staged=True: host arrays copied
+    through pinned buffers.  keep_final=True reads back each stream's final
+    state and dense map when it retires (for tests)."""
+
+    def __init__(self, hbm_budget: Optional[int] = None, n_hip_streams: int = 4, depth: int = 2,
+                 staged: bool = False, use_graphs: bool = True, reserve: int = 2 << 30, keep_final: bool = False):
+        free, _ = torch.cuda.mem_get_info()
+        cap = max(0, free - reserve)
+        self.budget = cap if hbm_budget is None else min(int(hbm_budget), cap)
+        self.pool = [torch.cuda.Stream() for _ in range(n_hip_streams)]
+        self.depth = depth
+        self.staged = staged
+        self.use_graphs = use_graphs
+        self.keep_final = keep_final
+        self.queue: Deque[StreamSpec] = collections.deque()
+        self.agents: Dict[int, _Agent] = {}
+        self.held = 0
+        self.waiting: Dict[int, Deque[_Frame]] = collections.defaultdict(collections.deque)
+        self.latencies: List[float] = []
+        self.per_stream_latency: Dict[int, List[float]] = collections.defaultdict(list)
+        self.admit_time: Dict[int, float] = {}
+        self.completed = 0
+        self.max_concurrent = 0
+        self.max_held_bytes = 0
+        self.final: Dict[int, dict] = {}
+        self._rr = 0
+
+    # ---- admission -------------------------------------------------------
+    def open_stream(self, spec: StreamSpec):
+        need = footprint_bytes(spec, self.depth, self.staged)
+        if need > self.budget:
+            raise P.PrismError(f"stream {spec.stream_id} needs {need} bytes, more than the budget {self.budget}")
+        self.queue.append(spec)
+        self._admit()
+
+    def _admit(self):
+        while self.queue:
+            spec = self.queue[0]
+            need = footprint_bytes(spec, self.depth, self.staged)
+            if self.held + need > self.budget:
+                return
+            self.queue.popleft()
+            hs = self.pool[self._rr % len(self.pool)]
+            self._rr += 1
+            ag = _Agent(spec, hs, self.depth, self.staged, self.use_graphs)
+            self.agents[spec.stream_id] = ag
+            self.held += need
+            self.max_held_bytes = max(self.max_held_bytes, self.held)
+            self.admit_time[spec.stream_id] = time.perf_counter()
+            self.max_concurrent = max(self.max_concurrent, len(self.agents))
+            ag.pending.extend(self.waiting.pop(spec.stream_id, ()))
+
+    def _retire(self, ag: _Agent):
+        sid = ag.spec.stream_id
+        if self.keep_final:
+            st = ag.filter.state()
+            mean, var = ag.filter.map.to_dense(stream=ag.stream)
+            torch.cuda.synchronize()
+            self.final[sid] = dict(state=st, mean=mean.cpu(), var=var.cpu())
+        ag.stream.synchronize()
+        del self.agents[sid]
+        self.held -= footprint_bytes(ag.spec, self.depth, self.staged)
+        ag.filter = None
+        ag.slots = None
+        self._admit()
+
+    # ---- frames ----------------------------------------------------------
+    def push_frame(self, stream_id: int, arrival: float, depth, rgb, u, index: int):
+        fr = _Frame(arrival, depth, rgb, u, index)
+        ag = self.agents.get(stream_id)
+        if ag is None:
+            self.waiting[stream_id].append(fr)       # queued on the host until the stream is admitted
+        else:
+            ag.pending.append(fr)
+
+    # ---- progress --------------------------------------------------------
+    def poll(self) -> int:
+        """Retire finished steps (in order per agent); returns how many."""
+        n = 0
+        for ag in list(self.agents.values()):
+            while ag.in_flight and ag.in_flight[0][0].query():
+                _, fr = ag.in_flight.popleft()
+                lat = time.perf_counter() - fr.arrival
+                self.latencies.append(lat)
+                self.per_stream_latency[ag.spec.stream_id].append(lat)
+                ag.done += 1
+                self.completed += 1
+                n += 1
+            if ag.finished():
+                self._retire(ag)
+        return n
+
+    def tick(self) -> int:
+        """Launch every step that can start now; returns how many."""
+        n = 0
+        progress = True
+        while progress:
+            progress = False
+            for ag in self.agents.values():
+                if ag.ready():
+                    ag.launch()
+                    n += 1
+                    progress = True
+        return n
+
+    def busy(self) -> bool:
+        return bool(self.queue) or bool(self.agents) or bool(self.waiting)
+
+    def run_until_idle(self, timeout: float = 600.0):
+        t0 = time.perf_counter()
+        while self.busy():
+            self.poll()
+            self.tick()
+            if time.perf_counter() - t0 > timeout:
+                raise TimeoutError("serving loop did not drain")
+        torch.cuda.synchronize()
+
+    def stats(self) -> Dict[str, float]:
+        lat = np.array(self.latencies) * 1e3
+        pct = (lambda q: float(np.percentile(lat, q))) if len(lat) else (lambda q: float("nan"))
+        return {"completed": self.completed, "p50_ms": pct(50), "p99_ms": pct(99),
+                "max_ms": float(lat.max()) if len(lat) else float("nan"),
+                "max_concurrent": self.max_concurrent, "max_held_bytes": self.max_held_bytes,
+                "budget_bytes": self.budget}
+
+
+def run_schedule(loop: ServingLoop, specs: List[StreamSpec], schedule: List[tuple],
+                 frame_source: Callable[[int, int], tuple], realtime: bool = True,
+                 timeout: float = 900.0) -> float:
+    """Open every stream, then feed frames at their arrival times (schedule:
+    (t_seconds, stream_id, index) sorted by t) while keeping the loop going.
+    realtime=False delivers every frame at time 0 (backlog: throughput).
+    Returns the wall time from start to the last completion."""
+    t0 = time.perf_counter()
+    for sp in specs:
+        loop.open_stream(sp)
+    i = 0
+    while i < len(schedule) or loop.busy():
+        now = time.perf_counter() - t0
+        while i < len(schedule) and (not realtime or schedule[i][0] <= now):
+            ta, sid, idx = schedule[i]
+            d, c, u = frame_source(sid, idx)
+            loop.push_frame(sid, t0 + (ta if realtime else 0.0), d, c, u, idx)
+            i += 1
+        loop.poll()
+        loop.tick()
+        if time.perf_counter() - t0 > timeout:
+            raise TimeoutError("serving run did not finish")
+        if realtime and i < len(schedule) and not any(a.in_flight for a in loop.agents.values()):
+            wait = schedule[i][0] - (time.perf_counter() - t0)
+            if wait > 2e-4:
+                time.sleep(min(wait, 1e-3))
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0

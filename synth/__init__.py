@@ -461,3 +461,98 @@ def bf16_round(x: np.ndarray) -> np.ndarray:
     r = ((b + 0x7FFF + lsb) >> 16) << 16
     out = r.astype(np.uint32).view(np.float32)
     return np.where(np.isnan(a), a, out)
+
+
+# --------------------------------------------------------------------------
+# device-side frame generation (large serving workloads)
+# --------------------------------------------------------------------------
+def raycast_torch(scene: Scene, cam: Camera, ts: np.ndarray, qs: np.ndarray, seed: int,
+                  depth_noise: float = 0.0, rgb_noise: float = 0.0, device="cuda", chunk: int = 16):
+    """Same analytic ray cast as `raycast`, for a batch of poses ts [F,3],
+    qs [F,4], evaluated with torch on `device` in float64 and returned as
+    float32 depth [F,H,W] and colour [F,H,W,3].  Noise comes from a torch
+    generator seeded with `seed` (so values differ from `raycast`'s numpy
+    noise; the noise-free part agrees to rounding)."""
+    import torch
+    F = len(ts)
+    H, W = cam.height, cam.width
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    dc = torch.as_tensor(pixel_dirs(cam), dtype=torch.float64, device=device)          # [H,W,3]
+    Rs = torch.as_tensor(np.stack([_quat_to_mat(np.asarray(q, float)) for q in qs]), dtype=torch.float64,
+                         device=device)
+    T = torch.as_tensor(np.asarray(ts, float), dtype=torch.float64, device=device)
+    lo = torch.as_tensor(scene.inner_lo, dtype=torch.float64, device=device)
+    hi = torch.as_tensor(scene.inner_hi, dtype=torch.float64, device=device)
+    cols = torch.as_tensor(scene.colours, dtype=torch.float64, device=device)
+    boxes = torch.as_tensor(scene.boxes, dtype=torch.float64, device=device)
+    depth_out = torch.empty((F, H, W), dtype=torch.float32, device=device)
+    rgb_out = torch.empty((F, H, W, 3), dtype=torch.float32, device=device)
+    for f0 in range(0, F, chunk):
+        f1 = min(F, f0 + chunk)
+        d = torch.einsum("hwj,fij->fhwi", dc, Rs[f0:f1])                             # world directions
+        o = T[f0:f1, None, None, :].expand_as(d)
+        inv = 1.0 / d
+        t1 = (lo - o) * inv
+        t2 = (hi - o) * inv
+        texit = torch.maximum(t1, t2)
+        tw, wall_axis = torch.min(texit, dim=-1)
+        wall_side = torch.gather(d, -1, wall_axis[..., None])[..., 0] > 0
+        sid = 2 * wall_axis + wall_side.long()
+        tbest = tw
+        for b in range(boxes.shape[0]):
+            c, h = boxes[b, 0], boxes[b, 1]
+            b1 = (c - h - o) * inv
+            b2 = (c + h - o) * inv
+            tmin = torch.minimum(b1, b2).amax(-1)
+            tmax = torch.maximum(b1, b2).amin(-1)
+            hit = (tmax >= tmin) & (tmin > 0)
+            tb = torch.where(hit, tmin, torch.full_like(tmin, math.inf))
+            closer = tb < tbest
+            tbest = torch.where(closer, tb, tbest)
+            sid = torch.where(closer, torch.full_like(sid, 6 + b), sid)
+        fin = torch.isfinite(tbest)
+        hitp = o + torch.where(fin, tbest, torch.zeros_like(tbest))[..., None] * d
+        c = cols[sid]
+        if scene.texture > 0:
+            wv = torch.as_tensor(scene.tex_waves, dtype=torch.float64, device=device)
+            ph = torch.as_tensor(scene.tex_phase, dtype=torch.float64, device=device)
+            tex = torch.zeros_like(c)
+            for w in range(2):
+                tex = tex + torch.sin(2 * math.pi * (hitp @ wv[w].T) + ph[w])
+            c = torch.clamp(c + 0.5 * scene.texture * tex, 0.0, 1.0)
+        depth = tbest
+        if depth_noise > 0:
+            depth = depth + depth_noise * torch.randn(depth.shape, generator=gen, dtype=torch.float64, device=device)
+        if rgb_noise > 0:
+            c = c + rgb_noise * torch.randn(c.shape, generator=gen, dtype=torch.float64, device=device)
+        depth = torch.where(torch.isfinite(depth) & (depth > 0), depth, torch.zeros_like(depth))
+        depth_out[f0:f1] = depth.float()
+        rgb_out[f0:f1] = c.float()
+    return depth_out, rgb_out
+
+
+def serving_streams(n_streams: int = 16, n_frames: int = 300, seed_base: int = 1000,
+                    sizes=((160, 120), (320, 240), (640, 480)), grids=(128, 256, 384),
+                    room: float = 6.4, d_near: float = 0.1, d_far: float = 7.5, period: float = 0.1,
+                    jitter_mean: float = 0.01) -> List[Dict]:
+    """Agent streams for the serving workload.  Stream i (seed seed_base + i)
+    draws its image size from `sizes` and its grid from `grids` (K = N/2
+    samples over [d_near, d_far] in a `room`-metre cube), has its own scene
+    and UAV trajectory, and its frame k arrives at T_i + period*k + J_k with
+    T_i ~ U[0, period) and J_k ~ Exp(mean jitter_mean) (kept in order)."""
+    out = []
+    for i in range(n_streams):
+        seed = seed_base + i
+        rng = np.random.default_rng(seed)
+        w, h = sizes[int(rng.integers(len(sizes)))]
+        n = int(grids[int(rng.integers(len(grids)))])
+        T0 = rng.uniform(0.0, period)
+        arr = T0 + period * np.arange(n_frames) + rng.exponential(jitter_mean, n_frames)
+        arr = np.maximum.accumulate(arr)
+        voxel = room / n
+        traj = uav_trajectory(seed, n_frames, np.full(3, room / 2))
+        scene = make_scene(n, voxel, seed, keep_clear=traj.t, clear_radius=0.5, texture=0.25)
+        cam = Camera.scaled(w, h, n // 2, d_near, d_far)
+        out.append(dict(seed=seed, width=w, height=h, n=n, scene=scene, cam=cam, traj=traj, arrivals=arr))
+    return out

@@ -1,0 +1,152 @@
+"""Serving loop: admission by memory, continuous launching, per-slot graph
+replay, and results that do not depend on the mix."""
+import numpy as np
+import pytest
+
+import synth
+
+
+def _specs(n_streams=4, n_frames=8, dtype=None):
+    from gpu_util import P
+    from paper_2212_02988_amd.serving import StreamSpec
+    Pm = P()
+    dtype = Pm.PRISM_BF16 if dtype is None else dtype
+    streams = synth.serving_streams(n_streams, n_frames, sizes=((80, 60), (160, 120)), grids=(64, 128))
+    specs, frames = [], {}
+    import torch
+    for i, s in enumerate(streams):
+        sc, cm, tr = s["scene"], s["cam"], s["traj"]
+        grid = Pm.Grid.make(sc.n, sc.voxel, tuple(float(v) for v in sc.origin), dtype=dtype)
+        cam = Pm.Camera.make(cm.width, cm.height, cm.fx, cm.fy, cm.cx, cm.cy, cm.d_near, cm.d_far, cm.n_samples)
+        x0 = np.concatenate([tr.t[0], tr.q[0], tr.v[0], tr.w[0]])
+        P0 = np.diag([1e-6] * 6 + [1e-4] * 6)
+        specs.append(StreamSpec(i, grid, cam, Pm.FilterParams(), x0, P0, n_frames))
+        D, C = synth.raycast_torch(sc, cm, tr.t, tr.q, s["seed"], 0.01, 0.02)
+        U = torch.tensor(tr.u, dtype=torch.float64, device="cuda")
+        frames[i] = (D, C, U, s["arrivals"])
+    torch.cuda.synchronize()
+    return specs, frames
+
+
+def _source(frames, host=False):
+    def get(sid, k):
+        D, C, U, _ = frames[sid]
+        u = None if k == 0 else U[k - 1]
+        if host:
+            return D[k].cpu().numpy(), C[k].cpu().numpy(), None if u is None else u.cpu().numpy()
+        return D[k], C[k], u
+    return get
+
+
+def _schedule(specs, frames, ids=None):
+    ids = [s.stream_id for s in specs] if ids is None else ids
+    sched = [(float(frames[i][3][k]), i, k) for i in ids for k in range(specs[i].n_frames)]
+    return sorted(sched)
+
+
+def _run(specs, frames, ids, realtime=False, **kw):
+    from paper_2212_02988_amd.serving import ServingLoop, run_schedule
+    host = kw.pop("host", False)
+    loop = ServingLoop(keep_final=True, staged=host, **kw)
+    wall = run_schedule(loop, [specs[i] for i in ids], _schedule(specs, frames, ids), _source(frames, host),
+                        realtime=realtime, timeout=120)
+    return loop, wall
+
+
+def _same(a, b):
+    sa, sb = a["state"], b["state"]
+    assert bytes(sa) == bytes(sb), "filter state differs"
+    assert np.array_equal(a["mean"].numpy(), b["mean"].numpy())
+    assert np.array_equal(a["var"].numpy(), b["var"].numpy())
+
+
+@pytest.mark.gpu
+def test_serving_alone_equals_mix_and_admission():
+    from gpu_util import banner
+    from paper_2212_02988_amd.serving import footprint_bytes
+    banner("serving 4 streams: alone vs mix, admission by memory")
+    specs, frames = _specs()
+    ids = [s.stream_id for s in specs]
+    alone = {}
+    for i in ids:
+        loop, _ = _run(specs, frames, [i])
+        assert loop.completed == specs[i].n_frames
+        alone[i] = loop.final[i]
+        st = alone[i]["state"]
+        assert st.step == specs[i].n_frames and st.flags == 0
+    mix, _ = _run(specs, frames, ids, n_hip_streams=2)
+    assert mix.completed == sum(s.n_frames for s in specs) and mix.max_concurrent == len(ids)
+    for i in ids:
+        _same(alone[i], mix.final[i])
+    # a budget below the sum of all footprints: some streams wait for memory
+    fp = sorted(footprint_bytes(s) for s in specs)
+    tight, _ = _run(specs, frames, ids, hbm_budget=fp[-1] + fp[-2])
+    assert tight.max_concurrent < len(ids) and tight.max_held_bytes <= tight.budget
+    assert tight.completed == mix.completed
+    for i in ids:
+        _same(alone[i], tight.final[i])
+
+
+@pytest.mark.gpu
+def test_serving_graph_eager_and_staged_agree():
+    from gpu_util import banner
+    banner("serving: graph replay vs eager launches, host-staged vs resident frames")
+    specs, frames = _specs(n_streams=3, n_frames=6)
+    ids = [s.stream_id for s in specs]
+    ref, _ = _run(specs, frames, ids, use_graphs=False, depth=1)
+    for kw in (dict(use_graphs=True, depth=2), dict(use_graphs=True, depth=3, host=True)):
+        got, _ = _run(specs, frames, ids, **kw)
+        for i in ids:
+            _same(ref.final[i], got.final[i])
+
+
+@pytest.mark.gpu
+def test_serving_realtime_latency_and_budget_errors():
+    from gpu_util import banner, P
+    from paper_2212_02988_amd.serving import ServingLoop
+    banner("serving: real-time arrivals, latency accounting, oversize stream")
+    specs, frames = _specs(n_streams=3, n_frames=10)
+    ids = [s.stream_id for s in specs]
+    loop, wall = _run(specs, frames, ids, realtime=True)
+    st = loop.stats()
+    assert st["completed"] == 30 and len(loop.latencies) == 30
+    last_arrival = max(frames[i][3][-1] for i in ids)
+    assert wall >= last_arrival
+    assert 0 < st["p50_ms"] <= st["p99_ms"] < 1000
+    small = ServingLoop(hbm_budget=1 << 20)
+    with pytest.raises(P().PrismError):
+        small.open_stream(specs[0])
+
+
+@pytest.mark.gpu
+def test_step_graph_matches_step_via_c_abi():
+    """prism_filter_step_graph (recorded per input slot) against
+    prism_filter_step, bit for bit, over 6 frames alternating two slots."""
+    import torch
+    from gpu_util import banner, P
+    banner("prism_filter_step_graph vs prism_filter_step")
+    Pm = P()
+    specs, frames = _specs(n_streams=1, n_frames=6, dtype=Pm.PRISM_F32)
+    sp = specs[0]
+    D, C, U, _ = frames[0]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        fa = Pm.Filter(sp.grid, sp.cam, sp.params)
+        fb = Pm.Filter(sp.grid, sp.cam, sp.params)
+        slots = [(torch.empty_like(D[0]), torch.empty_like(C[0]), torch.empty_like(U[0])) for _ in range(2)]
+        for f in (fa, fb):
+            f.map.init(stream=s)
+            f.reset(sp.x0, sp.P0, stream=s)
+        for k in range(sp.n_frames):
+            u = None if k == 0 else U[k - 1]
+            fa.step(D[k], C[k], u, stream=s)
+            d, c, uu = slots[k % 2]
+            d.copy_(D[k]); c.copy_(C[k])
+            if u is not None:
+                uu.copy_(u)
+            fb.step_graph(d, c, None if u is None else uu, stream=s)
+    torch.cuda.synchronize()
+    assert bytes(fa.state()) == bytes(fb.state())
+    ma, va = fa.map.to_dense()
+    mb, vb = fb.map.to_dense()
+    assert torch.equal(ma, mb) and torch.equal(va, vb)
