@@ -8,7 +8,7 @@
  * The library computes, on one GPU, the data-parallel steps of the paper's
  * approximate marginal filters:
  *   - the ray-marching RGB-D emission from the voxel map        (App. B)
- *   - its 6-DoF pose Jacobian reduced to normal equations       (Sec. 3.3.2)
+ *   - its 6-DoF pose Jacobian reduced to normal equations       (Sec. 4.3.2)
  *   - the prediction-to-observation tracking objective          (App. E.3)
  *   - Gauss-Newton MAP pose, Laplace covariance, linear-Gaussian
  *     propagation / split / combination of the state belief     (App. E.1-E.3)
@@ -73,7 +73,7 @@ typedef int32_t prism_status;
 /* Objectives for the pose update. */
 #define PRISM_OBJ_P2 0 /* prediction-to-observation surrogate against the previous
                           render (App. E.3), the paper's objective */
-#define PRISM_OBJ_P1 1 /* render-through likelihood of the current map (Sec. 3.3.2) */
+#define PRISM_OBJ_P1 1 /* render-through likelihood of the current map (Sec. 4.3.2) */
 
 typedef struct {
     int32_t n;        /* voxels per axis; multiple of 8, 8 <= n <= 1024 */
@@ -207,7 +207,7 @@ prism_status prism_render(const prism_grid *grid, const void *map, const prism_c
  * prism_render_vjp for n_frames frames of this camera. */
 prism_status prism_reduce_workspace_bytes(const prism_camera *cam, int32_t n_frames, size_t *bytes);
 
-/* Render-through (P1) pose Jacobian and normal equations (Sec. 3.3.2 MAP
+/* Render-through (P1) pose Jacobian and normal equations (Sec. 4.3.2 MAP
  * objective with the emission likelihood): for every valid ray, the 4x6
  * derivative of (depth, r, g, b) w.r.t. delta with k* held fixed; residuals
  * r = rendered - observed; rows gated and weighted by `w`; per frame the
@@ -279,7 +279,7 @@ prism_status prism_map_update(const prism_grid *grid, void *map, const prism_cam
                               int64_t *n_updated, hipStream_t stream);
 
 /* ------------------------------------------------------------------------ */
-/* Filter (Sec. 3.3; App. C, E)                                             */
+/* Filter (Sec. 4.3; App. C, E)                                             */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     prism_grid grid;
@@ -341,19 +341,19 @@ prism_status prism_filter_create(const prism_filter_cfg *cfg, void *state_mem, v
 prism_status prism_filter_destroy(prism_filter *f);
 
 /* Sets the state belief: x0 = (t[3], q[4], v[3], w[3]) and P0 [12x12], both
- * host; resets the step counter (the next frame is the first, App. C: x_1
+ * host; resets the step counter (the next frame is the first, Sec. 4.1: x_1
  * given).  Does not touch the map. */
 prism_status prism_filter_reset(prism_filter *f, const double *x0, const double *P0,
                                 hipStream_t stream);
 
-/* State filter only (Sec. 3.3.2): predict and split the state belief with
+/* State filter only (Sec. 4.3.2): predict and split the state belief with
  * the frame's control, n_gn Gauss-Newton steps of the configured objective
  * from the predicted pose, Laplace covariance at the final iterate (EMA'd),
  * and combination with the velocity conditional.  Not valid for the first
  * frame. */
 prism_status prism_pose_update(prism_filter *f, const prism_frame *frame, hipStream_t stream);
 
-/* One full filter step for each of n handles (Sec. 3.3): the state filter
+/* One full filter step for each of n handles (Sec. 4.3): the state filter
  * as in prism_pose_update (skipped for a filter's first frame), then the map
  * update at the posterior mean pose (App. C nominal state), then the anchor
  * frame rendered from the updated map at that pose for the next step.

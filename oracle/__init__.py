@@ -15,7 +15,7 @@ render                 App. B, ray-marching emission, first crossing of
                        "analogously to depth"
 normals                App. E.3 (normal of the rendered depth image),
                        App. G (discontinuous depth ignored)
-render_jacobian        Sec. 3.3.2 MAP objective with the render-through
+render_jacobian        Sec. 4.3.2 MAP objective with the render-through
                        likelihood; App. G weights and gating
 track_p2               App. E.3 prediction-to-observation objective
                        (point-to-plane and photometric terms)
@@ -26,11 +26,11 @@ render_vjp             adjoint of App. B's emission (App. B notes the
 predict / split        App. E.1 linearised transition, E.2 closed-form
                        propagation and split into pose prior + velocity
                        conditional
-gn_solve / laplace     Sec. 3.3.2 MAP pose + Laplace approximation;
-                       Sec. 4 / App. G Hessian as squared Jacobian, EMA 0.8
-combine                Sec. 3.3.2 product of pose posterior and velocity
+gn_solve / laplace     Sec. 4.3.2 MAP pose + Laplace approximation;
+                       Sec. 5.1 / App. G.2 Hessian as squared Jacobian, EMA 0.8
+combine                Sec. 4.3.2 product of pose posterior and velocity
                        conditional
-filter_step            Sec. 3.3 map filter then state filter ordering
+filter_step            Sec. 4.3 map filter then state filter ordering
 =====================  ===================================================
 
 Readings where the paper is silent or ambiguous are listed in the design doc's
@@ -472,7 +472,7 @@ def combine(pose_post: np.ndarray, S_pose: np.ndarray, prior_pose: np.ndarray, m
 
 
 # ---------------------------------------------------------------------------
-# the filter (Sec. 3.3)
+# the filter (Sec. 4.3)
 # ---------------------------------------------------------------------------
 @dataclass
 class FilterState:
@@ -528,7 +528,7 @@ class Filter:
         Spp, D, Sv = split(Pm)
         Lp = np.linalg.inv(Spp)
         Lp = 0.5 * (Lp + Lp.T)
-        # MAP pose by Gauss-Newton from the prior mean (Sec. 3.3.2)
+        # MAP pose by Gauss-Newton from the prior mean (Sec. 4.3.2)
         it = prior.copy()
         for _ in range(p.n_gn):
             neq = self._objective(it, depth, rgb)

@@ -11,7 +11,7 @@
  *
  *   render            App. B, ray-marching emission and depth-interpolation eq.
  *   render_jacobian   derivative of that emission w.r.t. a 6-DoF pose
- *                     perturbation, reduced to normal equations (Sec. 3.3.2
+ *                     perturbation, reduced to normal equations (Sec. 4.3.2
  *                     MAP objective; App. G Laplace / gating parameters)
  *   track_p2          App. E.3, point-to-plane + photometric surrogate
  *                     against the previous rendered frame

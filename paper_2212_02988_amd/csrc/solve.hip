@@ -1,4 +1,4 @@
-// FP64 state-filter algebra on the device (App. E.1-E.3, Sec. 3.3.2):
+// FP64 state-filter algebra on the device (App. E.1-E.3, Sec. 4.3.2):
 // linearised transition + propagation + split into pose prior and velocity
 // conditional; Gauss-Newton step of the MAP pose objective; Laplace
 // covariance (squared-Jacobian Hessian, with the dynamics prior), its EMA,

@@ -600,7 +600,7 @@ def _rand_spd(rng, n):
 def test_split_and_combine_are_gaussian_identities(orc):
     """Marginal x conditional of a joint Gaussian reproduce the joint; the
     product of a pose posterior with the conditional has that posterior as
-    its pose marginal and the conditional's (D, S) (Sec. 3.3.2, App. E.2)."""
+    its pose marginal and the conditional's (D, S) (Sec. 4.3.2, App. E.2)."""
     rng = np.random.default_rng(4)
     P = _rand_spd(rng, 12)
     Spp, D, Sv = orc.split(P)
@@ -628,7 +628,7 @@ def test_split_and_combine_are_gaussian_identities(orc):
 
 def test_gn_and_laplace_equal_kalman_for_linear_measurements(orc):
     """For a linear-Gaussian measurement one Gauss-Newton step is the Kalman
-    posterior mean and the Laplace covariance its covariance (Sec. 3.3.2;
+    posterior mean and the Laplace covariance its covariance (Sec. 4.3.2;
     objective sum w r^2 = Gaussian with variance 1/(2w))."""
     rng = np.random.default_rng(6)
     m = 40
