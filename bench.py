@@ -262,7 +262,9 @@ def main():
     loop, wall = run_mix(specs, frames, fps, realtime=False)
     assert loop.completed == steps
     value = steps / wall
-    log(f"backlog run: {steps} steps in {wall:.3f} s = {value:.0f} steps/s, max concurrent {loop.max_concurrent}")
+    log(f"backlog run: {steps} steps in {wall:.3f} s = {value:.0f} steps/s, max concurrent {loop.max_concurrent}; "
+        f"host {1e6 * loop.host_submit_s / steps:.1f} us/step in submit, {1e6 * loop.host_poll_s / steps:.1f} us/step "
+        f"in poll")
     # the same mix under an artificial admission budget
     bloop, bwall = run_mix(specs, frames, fps, realtime=False, budget=int(args.budget_gb * 2**30))
     log(f"{args.budget_gb:g} GB budget: {bloop.completed} steps in {bwall:.3f} s, max concurrent "

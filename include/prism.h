@@ -60,6 +60,7 @@ typedef int32_t prism_status;
 #define PRISM_INVALID_ARGUMENT 1 /* null pointer, bad size, misaligned buffer */
 #define PRISM_UNSUPPORTED 2      /* dtype / shape outside the supported set */
 #define PRISM_HIP_ERROR 3        /* a HIP runtime call failed (message has the code) */
+#define PRISM_BUSY 4             /* every input slot of the handle holds a step still running */
 
 /* Map storage types. */
 #define PRISM_F32 0
@@ -375,6 +376,33 @@ prism_status prism_filter_step(prism_filter *const *fs, int32_t n, const prism_f
  * launch, then frees them. */
 prism_status prism_filter_step_graph(prism_filter *const *fs, int32_t n, const prism_frame *frames,
                                      hipStream_t stream);
+
+/* ---- serving: per-handle input slots, submission and completion ---------- */
+
+/* Registers n_slots (1..4) input slots: caller-owned device buffers, each a
+ * depth [H][W] f32, rgb [H][W][3] f32 and control [6] f64 (16-byte aligned),
+ * that prism_filter_submit copies frames into.  Resets the submission and
+ * completion counters; must not be called while submitted steps run. */
+prism_status prism_filter_set_slots(prism_filter *f, int32_t n_slots, const prism_frame *slots);
+
+#define PRISM_SUBMIT_FROM_HOST 1 /* src buffers are host memory (pinned for an asynchronous copy) */
+#define PRISM_SUBMIT_EAGER 2     /* launch the step's kernels one by one instead of a graph */
+
+/* Queues one filter step for the frame src (u may be NULL only for the
+ * handle's first frame) without waiting: the frame is copied into the next
+ * slot (round robin; one staging kernel for device sources, asynchronous
+ * copies for host sources), then the step runs as in prism_filter_step_graph
+ * on that slot, and an event marks its end.  *seq (nullable) receives the
+ * step's 0-based submission number.  Returns PRISM_BUSY, and queues nothing,
+ * when the slot's previous step has not finished.  All submissions of a
+ * handle must use one non-default stream; the copy out of src is
+ * asynchronous, so src must stay unchanged until the step has completed. */
+prism_status prism_filter_submit(prism_filter *f, const prism_frame *src, int32_t flags, hipStream_t stream,
+                                 int64_t *seq);
+
+/* Non-blocking: *completed = number of submitted steps that have finished
+ * (steps finish in submission order). */
+prism_status prism_filter_poll(prism_filter *f, int64_t *completed);
 
 /* Device pointer to the filter's prism_filter_state (inside state_mem). */
 prism_status prism_filter_state_ptr(const prism_filter *f, prism_filter_state **state);

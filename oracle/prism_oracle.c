@@ -668,8 +668,10 @@ void orc_track_p2(const orc_camera *c, const double *pose, const double *pose_pr
 /* For every voxel whose centre projects into the image in front of the
  * camera, onto a valid observed depth D, with camera z <= D + trunc:
  *   f = (max(z - D, -trunc), rgb_obs)      (negative SDF, then colour)
- *   Lambda' = Lambda + lam_u,  mu' = (Lambda mu + lam_u f) / Lambda'
- * applied per channel in place on mean/var ([4][N^3] each).
+ *   Lambda' = Lambda + lam_u,  mu' = (Lambda')^-1 (Lambda mu + lam_u f)
+ * (the product written with the inverse of the new precision, as App. D
+ * prints it; the stored variance is that inverse), applied per channel in
+ * place on mean/var ([4][N^3] each).
  * upd (nullable) receives a 0/1 flag per voxel.  Returns the update count. */
 int64_t orc_map_update(const orc_grid *g, double *mean, double *var, const orc_camera *c,
                        const double *pose, int decide32, const double *obs_depth,
@@ -736,8 +738,9 @@ int64_t orc_map_update(const orc_grid *g, double *mean, double *var, const orc_c
                     size_t q = (size_t)ch * NV + idx;
                     double lam = 1.0 / var[q];
                     double lam2 = lam + lam_u;
-                    mean[q] = (lam * mean[q] + lam_u * f[ch]) / lam2;
-                    var[q] = 1.0 / lam2;
+                    double var2 = 1.0 / lam2;
+                    mean[q] = var2 * (lam * mean[q] + lam_u * f[ch]);
+                    var[q] = var2;
                 }
                 if (upd) upd[idx] = 1;
                 count += 1;

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libprism.so")
-SOURCES = ["render.hip", "track.hip", "map.hip", "solve.hip", "api.hip"]
+SOURCES = ["render.hip", "track.hip", "map.hip", "solve.hip", "stage.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -203,6 +203,13 @@ struct prism_filter {
     StepGraph graphs[kMaxGraphs];
     int n_graphs;
     uint64_t graph_clock;
+    // serving input slots (caller memory) and their completion events
+    static constexpr int kMaxSlots = 4;
+    prism_frame slots[kMaxSlots];
+    hipEvent_t slot_done[kMaxSlots];
+    int n_slots;
+    int64_t submitted, completed;
+    hipStream_t submit_stream;
 };
 
 namespace {
@@ -211,8 +218,8 @@ namespace {
 // complete by then: a launch on a new stream first waits for the previous one.
 hipError_t release_graph(prism_filter::StepGraph& G) {
     hipError_t e = hipEventSynchronize(G.done);
-    hipGraphExecDestroy(G.exec);
-    hipEventDestroy(G.done);
+    (void)hipGraphExecDestroy(G.exec);
+    (void)hipEventDestroy(G.done);
     return e;
 }
 
@@ -299,14 +306,15 @@ prism_status pose_update_impl(prism_filter* f, const prism_frame* fr, hipStream_
 }
 
 prism_status map_and_anchor(prism_filter* f, const prism_frame* fr, hipStream_t st) {
+    // the update's count of voxels is totalled by the normals kernel at the end
+    MapAux aux = map_aux(&f->cfg.grid, f->map);
     HIP_TRY(launch_map_update(f->g, f->c, f->gd, f->cfg.grid.dtype, f->map, &f->S->pose, fr->depth, fr->rgb,
-                              f->cfg.map.trunc, f->cfg.map.lam_update, map_aux(&f->cfg.grid, f->map),
-                              &f->S->n_updated, st));
+                              f->cfg.map.trunc, f->cfg.map.lam_update, aux, nullptr, st));
     HIP_TRY(launch_render(f->g, f->c, f->gd, f->cd, f->cfg.grid.dtype, f->map,
                           skip_table(&f->cfg.grid, &f->cfg.cam, f->map), &f->S->pose, 1, f->a_depth, f->a_rgb,
                           f->a_mask, nullptr, st));
     HIP_TRY(launch_normals(f->c, 1, f->a_depth, f->a_mask, (float)f->cfg.normal_disc, f->a_normals, f->a_nmask,
-                           st));
+                           aux.counts, map_update_groups(f->g), &f->S->n_updated, st));
     return PRISM_OK;
 }
 
@@ -414,7 +422,9 @@ prism_status prism_render(const prism_grid* grid, const void* map, const prism_c
     CamC c = cam_c(cam);
     HIP_TRY(launch_render(grid_c(grid), c, grid_d(grid), cam_d(cam), grid->dtype, map, skip_table(grid, cam, map),
                           poses, n_frames, depth, rgb, mask, hit_k, stream));
-    if (normals) HIP_TRY(launch_normals(c, n_frames, depth, mask, (float)normal_disc, normals, nmask, stream));
+    if (normals)
+        HIP_TRY(launch_normals(c, n_frames, depth, mask, (float)normal_disc, normals, nmask, nullptr, 0, nullptr,
+                               stream));
     return PRISM_OK;
 }
 
@@ -563,6 +573,11 @@ prism_status prism_filter_create(const prism_filter_cfg* cfg, void* state_mem, v
 prism_status prism_filter_destroy(prism_filter* f) {
     if (!f) return PRISM_OK;
     hipError_t e = hipSuccess;
+    for (int i = 0; i < f->n_slots; ++i) {
+        hipError_t ei = hipEventSynchronize(f->slot_done[i]);
+        if (e == hipSuccess) e = ei;
+        (void)hipEventDestroy(f->slot_done[i]);
+    }
     for (int i = 0; i < f->n_graphs; ++i) {
         hipError_t ei = release_graph(f->graphs[i]);
         if (e == hipSuccess) e = ei;
@@ -635,15 +650,15 @@ prism_status capture_step(prism_filter* f, const prism_frame* fr, hipStream_t st
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(stream, &g);
     if (s) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return s;
     }
     if (e != hipSuccess || !g) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return fail(PRISM_HIP_ERROR, "hipStreamEndCapture: %s", hipGetErrorString(e));
     }
     e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(PRISM_HIP_ERROR, "hipGraphInstantiate: %s", hipGetErrorString(e));
     return PRISM_OK;
 }
@@ -663,7 +678,7 @@ prism_status graph_for(prism_filter* f, const prism_frame* fr, hipStream_t strea
     hipGraphExec_t ex = nullptr;
     prism_status s = capture_step(f, fr, stream, &ex);
     if (s) {
-        hipEventDestroy(done);
+        (void)hipEventDestroy(done);
         return s;
     }
     int slot = f->n_graphs;
@@ -673,8 +688,8 @@ prism_status graph_for(prism_filter* f, const prism_frame* fr, hipStream_t strea
             if (f->graphs[i].last_use < f->graphs[slot].last_use) slot = i;
         hipError_t e = release_graph(f->graphs[slot]);   // the evicted graph may still be running
         if (e != hipSuccess) {
-            hipGraphExecDestroy(ex);
-            hipEventDestroy(done);
+            (void)hipGraphExecDestroy(ex);
+            (void)hipEventDestroy(done);
             f->n_graphs -= 1;
             f->graphs[slot] = f->graphs[f->n_graphs];
             return fail(PRISM_HIP_ERROR, "releasing an evicted step graph: %s", hipGetErrorString(e));
@@ -720,6 +735,94 @@ prism_status prism_filter_step_graph(prism_filter* const* fs, int32_t n, const p
         G.last_stream = stream;
         f->steps += 1;
     }
+    return PRISM_OK;
+}
+
+prism_status prism_filter_set_slots(prism_filter* f, int32_t n_slots, const prism_frame* slots) {
+    REQUIRE(f, "filter is NULL");
+    REQUIRE(n_slots >= 1 && n_slots <= prism_filter::kMaxSlots, "n_slots must be in [1, %d]", prism_filter::kMaxSlots);
+    REQUIRE(slots, "slots is NULL");
+    for (int i = 0; i < n_slots; ++i)
+        REQUIRE(slots[i].depth && slots[i].rgb && slots[i].u && aligned(slots[i].depth, 16) &&
+                    aligned(slots[i].rgb, 16) && aligned(slots[i].u, 16),
+                "slot %d: depth, rgb and u must be non-NULL and 16-byte aligned", i);
+    for (int i = 0; i < f->n_slots; ++i) {
+        HIP_TRY(hipEventSynchronize(f->slot_done[i]));
+        HIP_TRY(hipEventDestroy(f->slot_done[i]));
+    }
+    f->n_slots = 0;
+    for (int i = 0; i < n_slots; ++i) {
+        f->slots[i] = slots[i];
+        HIP_TRY(hipEventCreateWithFlags(&f->slot_done[i], hipEventDisableTiming));
+        f->n_slots = i + 1;
+    }
+    f->submitted = f->completed = 0;
+    f->submit_stream = nullptr;
+    return PRISM_OK;
+}
+
+namespace {
+
+prism_status poll_impl(prism_filter* f) {
+    while (f->completed < f->submitted) {
+        hipError_t q = hipEventQuery(f->slot_done[f->completed % f->n_slots]);
+        if (q == hipErrorNotReady) break;
+        if (q != hipSuccess) return fail(PRISM_HIP_ERROR, "hipEventQuery: %s", hipGetErrorString(q));
+        f->completed += 1;
+    }
+    return PRISM_OK;
+}
+
+}  // namespace
+
+prism_status prism_filter_submit(prism_filter* f, const prism_frame* src, int32_t flags, hipStream_t stream,
+                                 int64_t* seq) {
+    REQUIRE(f, "filter is NULL");
+    REQUIRE(f->n_slots > 0, "no input slots: call prism_filter_set_slots first");
+    REQUIRE(stream != nullptr, "submission needs a non-default stream");
+    REQUIRE(!f->submit_stream || f->completed == f->submitted || f->submit_stream == stream,
+            "all in-flight submissions of a handle must use one stream");
+    prism_status s = check_frame(src, f->steps > 0);
+    if (s) return s;
+    if ((s = poll_impl(f))) return s;
+    if (f->submitted - f->completed >= f->n_slots) return fail(PRISM_BUSY, "every input slot is in flight");
+    const int k = (int)(f->submitted % f->n_slots);
+    const prism_frame& slot = f->slots[k];
+    const size_t npix = (size_t)f->cfg.cam.width * f->cfg.cam.height;
+    if (flags & PRISM_SUBMIT_FROM_HOST) {
+        // slot buffers are caller-owned writable memory (prism_frame holds const pointers)
+        HIP_TRY(hipMemcpyAsync((void*)slot.depth, src->depth, 4 * npix, hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipMemcpyAsync((void*)slot.rgb, src->rgb, 12 * npix, hipMemcpyHostToDevice, stream));
+        if (src->u) HIP_TRY(hipMemcpyAsync((void*)slot.u, src->u, 48, hipMemcpyHostToDevice, stream));
+    } else {
+        HIP_TRY(launch_stage(src->depth, src->rgb, src->u, (float*)slot.depth, (float*)slot.rgb, (double*)slot.u,
+                             (long long)npix, stream));
+    }
+    prism_frame fr{slot.depth, slot.rgb, src->u ? slot.u : nullptr};
+    if (f->steps == 0 || (flags & PRISM_SUBMIT_EAGER)) {
+        if ((s = step_one(f, &fr, stream))) return s;
+    } else {
+        int g = -1;
+        if ((s = graph_for(f, &fr, stream, &g))) return s;
+        prism_filter::StepGraph& G = f->graphs[g];
+        if (G.last_stream && G.last_stream != stream) HIP_TRY(hipEventSynchronize(G.done));
+        HIP_TRY(hipGraphLaunch(G.exec, stream));
+        HIP_TRY(hipEventRecord(G.done, stream));
+        G.last_stream = stream;
+        f->steps += 1;
+    }
+    HIP_TRY(hipEventRecord(f->slot_done[k], stream));
+    f->submit_stream = stream;
+    if (seq) *seq = f->submitted;
+    f->submitted += 1;
+    return PRISM_OK;
+}
+
+prism_status prism_filter_poll(prism_filter* f, int64_t* completed) {
+    REQUIRE(f && completed, "filter and completed must be non-NULL");
+    prism_status s = poll_impl(f);
+    if (s) return s;
+    *completed = f->completed;
     return PRISM_OK;
 }
 

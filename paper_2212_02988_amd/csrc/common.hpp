@@ -287,4 +287,24 @@ struct WeightsC {
 
 __device__ __forceinline__ bool depth_ok(float d) { return d > 0.0f && isfinite(d); }
 
+// *n_updated = sum of counts[0..ngroups) (ngroups <= 2048) by a whole
+// 256-thread workgroup: every lane issues its (up to 8) loads before adding,
+// so the sum costs one memory round trip, not ngroups / 64 of them
+__device__ inline void sum_counts_block(const int* __restrict__ counts, int ngroups, int64_t* __restrict__ n_updated,
+                                        long long* part) {
+    int v[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        int i = threadIdx.x + 256 * r;
+        v[r] = i < ngroups ? counts[i] : 0;
+    }
+    long long t = 0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) t += v[r];
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) *n_updated = part[0] + part[1] + part[2] + part[3];
+}
+
 }  // namespace prism

@@ -22,8 +22,11 @@ int track_blocks(const CamC& c);
 hipError_t launch_render(const GridC& g, const CamC& c, const GridD& gd, const CamD& cd, int dtype, const void* map,
                          const unsigned* bits, const prism_pose* poses, int n_frames, float* depth, float* rgb,
                          uint8_t* mask, int32_t* hit_k, hipStream_t st);
+// counts/ngroups/n_updated (nullable): also total the preceding map update's
+// per-workgroup counts into *n_updated
 hipError_t launch_normals(const CamC& c, int n_frames, const float* depth, const uint8_t* mask, float disc,
-                          float* normals, uint8_t* nmask, hipStream_t st);
+                          float* normals, uint8_t* nmask, const int* counts, int ngroups, int64_t* n_updated,
+                          hipStream_t st);
 hipError_t launch_render_jac(const GridC& g, const CamC& c, const GridD& gd, const CamD& cd, int dtype,
                              const void* map, const unsigned* bits, const prism_pose* poses, int n_frames,
                              const float* obs_depth,
@@ -48,9 +51,17 @@ hipError_t launch_from_dense(const GridC& g, int dtype, void* map, const float* 
 hipError_t launch_to_dense(const GridC& g, int dtype, const void* map, float* mean4, float* var4,
                            hipStream_t st);
 hipError_t launch_planes(int n, int channels, const float* src, float* dst, int to_dense, hipStream_t st);
+// n_updated (nullable): total of updated voxels, by an extra one-wavefront kernel
 hipError_t launch_map_update(const GridC& g, const CamC& c, const GridD& gd, int dtype, void* map,
                              const prism_pose* pose, const float* depth, const float* rgb, double trunc, double lam_u,
                              const MapAux& aux, int64_t* n_updated, hipStream_t st);
+// workgroups (and per-workgroup counts) of one update launch
+int map_update_groups(const GridC& g);
+
+// frame staging: depth [npix] f32, rgb [3 npix] f32 and (if u) 6 f64 copied
+// into a serving slot in one kernel
+hipError_t launch_stage(const void* depth, const void* rgb, const void* u, float* d_out, float* c_out, double* u_out,
+                        long long npix, hipStream_t st);
 
 hipError_t launch_predict(prism_filter_state* S, const double* u, const TransC& tc, hipStream_t st);
 hipError_t launch_gn_step(prism_filter_state* S, const double* partials, int nblocks, hipStream_t st);

@@ -18,9 +18,10 @@
 //           lane decides its two voxels with the single-precision recipe and
 //           updates only those, so HBM traffic is the updated voxels' 8 planes
 //           read and written once; the brick's occupancy maximum is refreshed
-//           in the same pass, and each workgroup stores its update count.
-//   pack:   packs the free-space bits from the brick maxima and sums the
-//           per-workgroup counts.
+//           in the same pass (its free-space bit toggled when it crosses 0),
+//           and each workgroup stores its update count.
+//   The count of updated voxels is the sum of the per-workgroup counts, taken
+//   by a one-wavefront kernel or by the next kernel of a filter step.
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -121,42 +122,30 @@ __global__ __launch_bounds__(256) void k_brick_max(GridC g, const T* __restrict_
     if (threadIdx.x == 0) aux.bmax[blockIdx.x] = m;
 }
 
-// packs the free-space bits from the brick summary; block 0 also sums the
-// per-workgroup counts of the last update into n_updated (if requested)
-__global__ __launch_bounds__(256) void k_pack_bits(int nbricks, MapAux aux, int ngroups,
-                                                   int64_t* __restrict__ n_updated) {
-    __shared__ long long lsum[4];
+// packs the free-space bits (brick maximum <= 0) from the brick summary
+__global__ __launch_bounds__(256) void k_pack_bits(int nbricks, MapAux aux) {
     int w = blockIdx.x * blockDim.x + threadIdx.x;
     int nwords = (nbricks + 31) >> 5;
-    if (w < nwords) {
-        unsigned word = 0;
-        if ((w << 5) + 32 <= nbricks) {
-            // 32 contiguous floats: eight 16-byte loads issued together
-            const float4* p4 = reinterpret_cast<const float4*>(aux.bmax + (w << 5));
-            float4 v[8];
+    if (w >= nwords) return;
+    unsigned word = 0;
+    if ((w << 5) + 32 <= nbricks) {
+        // 32 contiguous floats: eight 16-byte loads issued together
+        const float4* p4 = reinterpret_cast<const float4*>(aux.bmax + (w << 5));
+        float4 v[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) v[i] = p4[i];
+        for (int i = 0; i < 8; ++i) v[i] = p4[i];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                word |= (v[i].x <= 0.0f ? 1u : 0u) << (4 * i);
-                word |= (v[i].y <= 0.0f ? 1u : 0u) << (4 * i + 1);
-                word |= (v[i].z <= 0.0f ? 1u : 0u) << (4 * i + 2);
-                word |= (v[i].w <= 0.0f ? 1u : 0u) << (4 * i + 3);
-            }
-        } else {
-            for (int i = 0; (w << 5) + i < nbricks; ++i)
-                if (aux.bmax[(w << 5) + i] <= 0.0f) word |= 1u << i;
+        for (int i = 0; i < 8; ++i) {
+            word |= (v[i].x <= 0.0f ? 1u : 0u) << (4 * i);
+            word |= (v[i].y <= 0.0f ? 1u : 0u) << (4 * i + 1);
+            word |= (v[i].z <= 0.0f ? 1u : 0u) << (4 * i + 2);
+            word |= (v[i].w <= 0.0f ? 1u : 0u) << (4 * i + 3);
         }
-        aux.bits[w] = word;
+    } else {
+        for (int i = 0; (w << 5) + i < nbricks; ++i)
+            if (aux.bmax[(w << 5) + i] <= 0.0f) word |= 1u << i;
     }
-    if (blockIdx.x == 0 && n_updated) {
-        long long s = 0;
-        for (int i = threadIdx.x; i < ngroups; i += blockDim.x) s += aux.counts[i];
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-        if ((threadIdx.x & 63) == 0) lsum[threadIdx.x >> 6] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) *n_updated = lsum[0] + lsum[1] + lsum[2] + lsum[3];
-    }
+    aux.bits[w] = word;
 }
 
 struct MapUpdC {
@@ -232,8 +221,10 @@ __global__ __launch_bounds__(256) void k_map_update(GridC g, CamC c, GridD gd, T
     __shared__ PosePair sp;
     __shared__ float lmax[4];
     __shared__ int lcnt[4];
-    __shared__ int chunk_sum[256];
-    // segment lengths -> exclusive prefix sums (each thread one contiguous chunk)
+    __shared__ int wsum[4];
+    // segment lengths -> exclusive prefix sums: each thread sums one
+    // contiguous chunk, the chunk sums are scanned across the workgroup
+    // (shuffle scan per wavefront, then the four wavefront totals)
     int per = (nseg + 255) / 256;
     int lo = threadIdx.x * per, hi = min(lo + per, nseg);
     int s = 0;
@@ -241,20 +232,20 @@ __global__ __launch_bounds__(256) void k_map_update(GridC g, CamC c, GridD gd, T
         sstart[i] = s;
         s += aux.segcnt[i];
     }
-    chunk_sum[threadIdx.x] = s;
     if (threadIdx.x == 0) sp = *reinterpret_cast<const PosePair*>(aux.pose);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int run = 0;
-        for (int t = 0; t < 256; ++t) {
-            int v = chunk_sum[t];
-            chunk_sum[t] = run;
-            run += v;
-        }
-        sstart[nseg] = run;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int incl = s;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int t = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += t;
     }
+    if (lane == 63) wsum[wv] = incl;
     __syncthreads();
-    for (int i = lo; i < hi; ++i) sstart[i] += chunk_sum[threadIdx.x];
+    int excl = incl - s;
+    for (int w = 0; w < wv; ++w) excl += wsum[w];
+    for (int i = lo; i < hi; ++i) sstart[i] += excl;
+    if (threadIdx.x == 0) sstart[nseg] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
     __syncthreads();
     const Pose32& P = sp.f;
     const Pose64& Q = sp.d;
@@ -317,31 +308,48 @@ __global__ __launch_bounds__(256) void k_map_update(GridC g, CamC c, GridD gd, T
             }
 #pragma unroll
             for (int ch = 0; ch < 4; ++ch) {
+                // App. D: new precision = old + update precision; new mean =
+                // inverse of the new precision times the precision-weighted sum
                 double lam = 1.0 / var[ch];
                 double lam2 = lam + mp.lam_u;
-                float nm = (float)((lam * mu[ch] + mp.lam_u * f[ch]) / lam2);
+                double var2 = 1.0 / lam2;
+                float nm = (float)(var2 * (lam * mu[ch] + mp.lam_u * f[ch]));
                 st(map, ch * g.nvox + id, nm);
-                st(map, (4 + ch) * g.nvox + id, (float)(1.0 / lam2));
+                st(map, (4 + ch) * g.nvox + id, (float)var2);
                 if (ch == 0) m = fmaxf(m, stored<T>(nm));
             }
             ++cnt;
         }
         m = block_max(m, lmax);
-        if (threadIdx.x == 0) aux.bmax[b] = m;
+        if (threadIdx.x == 0) {
+            // keep the free-space bit equal to (maximum <= 0): toggle it when
+            // the brick crosses over (each brick has one owner per launch, so
+            // toggles of one word touch different bits)
+            bool was_free = aux.bmax[b] <= 0.0f, now_free = m <= 0.0f;
+            aux.bmax[b] = m;
+            if (was_free != now_free) atomicXor(&aux.bits[b >> 5], 1u << (b & 31));
+        }
         __syncthreads();   // lmax is reused by the next brick
     }
     for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
-    if ((threadIdx.x & 63) == 0) lcnt[threadIdx.x >> 6] = cnt;
+    if (lane == 0) lcnt[wv] = cnt;
     __syncthreads();
     if (threadIdx.x == 0) aux.counts[blockIdx.x] = lcnt[0] + lcnt[1] + lcnt[2] + lcnt[3];
 }
 
+// n_updated = sum of the per-workgroup counts of the last update
+__global__ __launch_bounds__(256) void k_sum_counts(const int* __restrict__ counts, int ngroups,
+                                                    int64_t* __restrict__ n_updated) {
+    __shared__ long long part[4];
+    sum_counts_block(counts, ngroups, n_updated, part);
+}
+
 static unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
 
-static hipError_t launch_pack(const GridC& g, const MapAux& aux, int ngroups, int64_t* n_updated, hipStream_t st) {
+static hipError_t launch_pack(const GridC& g, const MapAux& aux, hipStream_t st) {
     int nbricks = g.nb * g.nb * g.nb;
     int nwords = (nbricks + 31) >> 5;
-    k_pack_bits<<<(unsigned)((nwords + 255) / 256), 256, 0, st>>>(nbricks, aux, ngroups, n_updated);
+    k_pack_bits<<<(unsigned)((nwords + 255) / 256), 256, 0, st>>>(nbricks, aux);
     return hipGetLastError();
 }
 
@@ -356,7 +364,7 @@ hipError_t launch_map_init(const GridC& g, int dtype, void* map, float occ0, flo
         k_map_init<float><<<blocks_for(g.nvox), 256, 0, st>>>(g.nvox, (float*)map, occ0, rgb0, var0, aux, nbricks);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_pack(g, aux, 0, nullptr, st);
+    return launch_pack(g, aux, st);
 }
 
 hipError_t launch_brick_max(const GridC& g, int dtype, const void* map, const MapAux& aux, hipStream_t st) {
@@ -367,7 +375,7 @@ hipError_t launch_brick_max(const GridC& g, int dtype, const void* map, const Ma
         k_brick_max<float><<<nbricks, 256, 0, st>>>(g, (const float*)map, aux);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_pack(g, aux, 0, nullptr, st);
+    return launch_pack(g, aux, st);
 }
 
 hipError_t launch_from_dense(const GridC& g, int dtype, void* map, const float* mean4, const float* var4,
@@ -419,8 +427,11 @@ hipError_t launch_map_update(const GridC& g, const CamC& c, const GridD& gd, int
     else
         k_map_update<float><<<ng, 256, lds, st>>>(g, c, gd, (float*)map, depth, rgb, mp, aux, nseg);
     e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return launch_pack(g, aux, ng, n_updated, st);
+    if (e != hipSuccess || !n_updated) return e;
+    k_sum_counts<<<1, 256, 0, st>>>(aux.counts, ng, n_updated);
+    return hipGetLastError();
 }
+
+int map_update_groups(const GridC& g) { return update_grid(g); }
 
 }  // namespace prism

@@ -450,7 +450,13 @@ __global__ __launch_bounds__(256) void k_render(GridC g, CamC c, GridD gd, CamD 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_normals(CamC c, int n_frames, const float* __restrict__ depth,
                                                  const uint8_t* __restrict__ mask, float disc,
-                                                 float* __restrict__ normals, uint8_t* __restrict__ nmask) {
+                                                 float* __restrict__ normals, uint8_t* __restrict__ nmask,
+                                                 const int* __restrict__ counts, int ngroups,
+                                                 int64_t* __restrict__ n_updated) {
+    // in a filter step, the first workgroup also totals the preceding map
+    // update (before any thread returns: the sum synchronises the workgroup)
+    __shared__ long long part[4];
+    if (n_updated && blockIdx.x == 0) sum_counts_block(counts, ngroups, n_updated, part);
     long long npix = (long long)c.W * c.H;
     long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= npix * n_frames) return;
@@ -656,9 +662,11 @@ hipError_t launch_render(const GridC& g, const CamC& c, const GridD& gd, const C
 }
 
 hipError_t launch_normals(const CamC& c, int n_frames, const float* depth, const uint8_t* mask, float disc,
-                          float* normals, uint8_t* nmask, hipStream_t st) {
+                          float* normals, uint8_t* nmask, const int* counts, int ngroups, int64_t* n_updated,
+                          hipStream_t st) {
     long long n = (long long)c.W * c.H * n_frames;
-    k_normals<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(c, n_frames, depth, mask, disc, normals, nmask);
+    k_normals<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(c, n_frames, depth, mask, disc, normals, nmask, counts,
+                                                           ngroups, n_updated);
     return hipGetLastError();
 }
 

@@ -24,6 +24,11 @@ FLAG_NO_VALID_PIXELS, FLAG_CHOL_FALLBACK = 1, 2
 NEQ = 29
 
 
+PRISM_BUSY = 4
+SUBMIT_FROM_HOST = 1
+SUBMIT_EAGER = 2
+
+
 class PrismError(RuntimeError):
     pass
 
@@ -123,6 +128,9 @@ _SIGS = {
     "prism_pose_update": (["p", "p", "p"], None),
     "prism_filter_step": (["p", ctypes.c_int32, "p", "p"], None),
     "prism_filter_step_graph": (["p", ctypes.c_int32, "p", "p"], None),
+    "prism_filter_set_slots": (["p", ctypes.c_int32, "p"], None),
+    "prism_filter_submit": (["p", "p", ctypes.c_int32, "p", "p"], None),
+    "prism_filter_poll": (["p", "p"], None),
     "prism_filter_state_ptr": (["p", "p"], None),
     "prism_filter_anchor": (["p", "p", "p", "p", "p", "p"], None),
 }
@@ -472,6 +480,36 @@ class Filter:
         fr = self.frame(depth, rgb, u)
         arr = (ctypes.c_void_p * 1)(self.h)
         _check(lib().prism_filter_step_graph(arr, 1, _by(fr), _stream(stream)))
+
+    def set_slots(self, slots):
+        """Register serving input slots: a list of (depth [H,W] f32, rgb
+        [H,W,3] f32, u [6] f64) device tensors, 16-byte aligned."""
+        H, W = self.cam.height, self.cam.width
+        for d, c, u in slots:
+            _dev(d, torch.float32, "slot depth", (H, W))
+            _dev(c, torch.float32, "slot rgb", (H, W, 3))
+            _dev(u, torch.float64, "slot u", (6,))
+        arr = (Frame * len(slots))(*[Filter.frame(d, c, u) for d, c, u in slots])
+        _check(lib().prism_filter_set_slots(self.h, len(slots), arr))
+        self._slots = list(slots)          # keep the buffers alive
+
+    def submit(self, depth, rgb, u, stream, flags: int = 0) -> Optional[int]:
+        """Queue one step (see prism_filter_submit); returns its submission
+        number, or None when every slot is in flight.  depth/rgb/u are device
+        tensors, or pinned host tensors with flags |= SUBMIT_FROM_HOST."""
+        fr = self.frame(depth, rgb, u)
+        seq = ctypes.c_int64()
+        st = lib().prism_filter_submit(self.h, _by(fr), flags, _stream(stream), _by(seq))
+        if st == PRISM_BUSY:
+            return None
+        _check(st)
+        return seq.value
+
+    def poll(self) -> int:
+        """Number of submitted steps that have completed."""
+        c = ctypes.c_int64()
+        _check(lib().prism_filter_poll(self.h, _by(c)))
+        return c.value
 
     def pose_update(self, depth, rgb, u, stream=None):
         fr = self.frame(depth, rgb, u)

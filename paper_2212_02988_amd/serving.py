@@ -9,11 +9,13 @@ resident in HBM for the stream's lifetime.  Frames arrive at their own pace
   the others queued in arrival order, and admits queued streams as soon as
   finished ones release their memory;
 * keeps every admitted stream's steps flowing without waiting for the
-  others: whenever a stream has a pending frame and a free input slot, the
-  frame is copied into the slot and the step is launched on the stream's HIP
-  stream (one of a small pool shared round-robin), as one HIP graph replay
-  recorded by the library per slot, so steps of different agents overlap on
-  the device and frames arriving while others run join immediately;
+  others: whenever a stream has a pending frame and a free input slot, one
+  library call (prism_filter_submit) copies the frame into the slot and
+  launches the step on the stream's HIP stream (one of a small pool shared
+  round-robin) as the HIP graph the library recorded for that slot, so steps
+  of different agents overlap on the device and frames arriving while others
+  run join immediately; completions come from the library's per-slot events
+  (prism_filter_poll);
 * allows up to ``depth`` steps of one agent in flight (they are ordered on its
   HIP stream; each slot is reused only after the step that read it finished),
   and records per-frame latency from arrival to host-visible completion.
@@ -67,63 +69,64 @@ def footprint_bytes(spec: StreamSpec, depth: int = 2, staged: bool = False) -> i
 
 
 class _Agent:
+    """One admitted stream: its filter, `depth` device input slots registered
+    with the library (plus pinned host slots when frames come from the host),
+    and the frames waiting or in flight."""
+
     def __init__(self, spec: StreamSpec, hip_stream: torch.cuda.Stream, depth: int, staged: bool,
                  use_graph: bool):
         self.spec = spec
         self.stream = hip_stream
         self.depth = depth
         self.staged = staged
-        self.use_graph = use_graph
+        self.flags = (P.SUBMIT_FROM_HOST if staged else 0) | (0 if use_graph else P.SUBMIT_EAGER)
         H, W = spec.cam.height, spec.cam.width
         with torch.cuda.stream(hip_stream):
             self.filter = P.Filter(spec.grid, spec.cam, spec.params)
             self.filter.map.init(stream=hip_stream)
             self.filter.reset(spec.x0, spec.P0, stream=hip_stream)
-            self.slots = []
-            for _ in range(depth):
-                s = dict(d=torch.empty((H, W), dtype=torch.float32, device="cuda"),
-                         c=torch.empty((H, W, 3), dtype=torch.float32, device="cuda"),
-                         u=torch.zeros(6, dtype=torch.float64, device="cuda"))
-                if staged:
-                    s.update(hd=torch.empty((H, W), dtype=torch.float32).pin_memory(),
-                             hc=torch.empty((H, W, 3), dtype=torch.float32).pin_memory(),
-                             hu=torch.zeros(6, dtype=torch.float64).pin_memory())
-                self.slots.append(s)
+            slots = [(torch.empty((H, W), dtype=torch.float32, device="cuda"),
+                      torch.empty((H, W, 3), dtype=torch.float32, device="cuda"),
+                      torch.zeros(6, dtype=torch.float64, device="cuda")) for _ in range(depth)]
+            self.filter.set_slots(slots)
+            self.host = None
+            if staged:
+                self.host = [(torch.empty((H, W), dtype=torch.float32).pin_memory(),
+                              torch.empty((H, W, 3), dtype=torch.float32).pin_memory(),
+                              torch.zeros(6, dtype=torch.float64).pin_memory()) for _ in range(depth)]
         self.pending: Deque[_Frame] = collections.deque()
-        self.in_flight: Deque[Tuple[torch.cuda.Event, _Frame]] = collections.deque()
+        self.in_flight: Deque[_Frame] = collections.deque()
         self.launched = 0
         self.done = 0
 
     def ready(self) -> bool:
-        return bool(self.pending) and len(self.in_flight) < self.depth
+        return bool(self.pending) and self.launched - self.done < self.depth
 
     def launch(self):
-        fr = self.pending.popleft()
-        s = self.slots[self.launched % self.depth]
-        st = self.stream
-        with torch.cuda.stream(st):
-            if self.staged:
-                s["hd"].numpy()[...] = fr.depth
-                s["hc"].numpy()[...] = fr.rgb
-                if fr.u is not None:
-                    s["hu"].numpy()[...] = fr.u
-                s["d"].copy_(s["hd"], non_blocking=True)
-                s["c"].copy_(s["hc"], non_blocking=True)
-                s["u"].copy_(s["hu"], non_blocking=True)
-            else:
-                s["d"].copy_(fr.depth, non_blocking=True)
-                s["c"].copy_(fr.rgb, non_blocking=True)
-                if fr.u is not None:
-                    s["u"].copy_(fr.u, non_blocking=True)
-            u = None if self.launched == 0 else s["u"]
-            if self.use_graph:
-                self.filter.step_graph(s["d"], s["c"], u, stream=st)
-            else:
-                self.filter.step(s["d"], s["c"], u, stream=st)
-            ev = torch.cuda.Event()
-            ev.record(st)
-        self.in_flight.append((ev, fr))
+        fr = self.pending[0]
+        if self.staged:
+            hd, hc, hu = self.host[self.launched % self.depth]
+            hd.numpy()[...] = fr.depth
+            hc.numpy()[...] = fr.rgb
+            if fr.u is not None:
+                hu.numpy()[...] = fr.u
+            src = (hd, hc, None if fr.u is None else hu)
+        else:
+            src = (fr.depth, fr.rgb, fr.u)
+        if self.filter.submit(*src, stream=self.stream, flags=self.flags) is None:
+            return False
+        self.pending.popleft()
+        self.in_flight.append(fr)
         self.launched += 1
+        return True
+
+    def poll(self) -> List[_Frame]:
+        c = self.filter.poll()
+        out = []
+        while self.done < c:
+            out.append(self.in_flight.popleft())
+            self.done += 1
+        return out
 
     def finished(self) -> bool:
         return self.done >= self.spec.n_frames
@@ -161,6 +164,8 @@ class ServingLoop:
         self.max_held_bytes = 0
         self.final: Dict[int, dict] = {}
         self._rr = 0
+        self.host_submit_s = 0.0          # host time inside step submissions
+        self.host_poll_s = 0.0            # host time inside completion polls
 
     # ---- admission -------------------------------------------------------
     def open_stream(self, spec: StreamSpec):
@@ -198,7 +203,7 @@ class ServingLoop:
         del self.agents[sid]
         self.held -= footprint_bytes(ag.spec, self.depth, self.staged)
         ag.filter = None
-        ag.slots = None
+        ag.host = None
         self._admit()
 
     # ---- frames ----------------------------------------------------------
@@ -215,14 +220,19 @@ class ServingLoop:
         """Retire finished steps (in order per agent); returns how many."""
         n = 0
         for ag in list(self.agents.values()):
-            while ag.in_flight and ag.in_flight[0][0].query():
-                _, fr = ag.in_flight.popleft()
-                lat = time.perf_counter() - fr.arrival
-                self.latencies.append(lat)
-                self.per_stream_latency[ag.spec.stream_id].append(lat)
-                ag.done += 1
-                self.completed += 1
-                n += 1
+            if not ag.in_flight:
+                continue
+            t0 = time.perf_counter()
+            done = ag.poll()
+            self.host_poll_s += time.perf_counter() - t0
+            if done:
+                now = time.perf_counter()
+                for fr in done:
+                    lat = now - fr.arrival
+                    self.latencies.append(lat)
+                    self.per_stream_latency[ag.spec.stream_id].append(lat)
+                self.completed += len(done)
+                n += len(done)
             if ag.finished():
                 self._retire(ag)
         return n
@@ -235,9 +245,12 @@ class ServingLoop:
             progress = False
             for ag in self.agents.values():
                 if ag.ready():
-                    ag.launch()
-                    n += 1
-                    progress = True
+                    t0 = time.perf_counter()
+                    ok = ag.launch()
+                    self.host_submit_s += time.perf_counter() - t0
+                    if ok:
+                        n += 1
+                        progress = True
         return n
 
     def busy(self) -> bool:

@@ -306,6 +306,35 @@ def test_map_update_full_size(case2):
     np.testing.assert_array_equal(m2[:, u], om[:, u].astype(np.float32))
 
 
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_free_space_bits_follow_updates(case2, dtype):
+    """The map update keeps each brick's free-space bit equal to (maximum
+    occupancy <= 0) incrementally: after several updates, renders with the
+    maintained bits equal renders after the bits are rebuilt from scratch,
+    and the hit samples equal the oracle's (which marches every sample)."""
+    banner(f"free-space bits after map updates, dtype {dtype}")
+    c, _, _ = case2
+    g = grid_of(c["scene"], dtype)
+    cam = cam_of(c["cam"])
+    vm = P().VoxelMap(g).init()
+    tr = c["traj"]
+    p = orc.Params()
+    for i in range(0, 6, 2):
+        P().map_update(g, vm, cam, P().poses_tensor(synth.pose7(tr.t[i], tr.q[i])), t(c["depth"][i]),
+                       t(c["rgb"][i]), p.trunc_voxels * g.voxel, 1.0)
+    poses = P().poses_tensor(np.stack([synth.pose7(tr.t[i], tr.q[i]) for i in (1, 3, 5)]))
+    a = P().render(g, vm, cam, poses, hit_k=True)
+    a = {k: v.clone() for k, v in a.items()}
+    vm.refresh()
+    b = P().render(g, vm, cam, poses, hit_k=True)
+    for k in ("hit_k", "depth", "rgb", "mask"):
+        assert torch.equal(a[k], b[k]), k
+    m, _ = vm.to_dense()
+    mv = m.cpu().numpy().astype(np.float64)
+    ref = orc.render(orc.grid_from_scene(c["scene"]), mv, orc.cam_from(c["cam"]), synth.pose7(tr.t[3], tr.q[3]))
+    np.testing.assert_array_equal(a["hit_k"][1].cpu().numpy(), ref["hit_k"])
+
+
 # ---------------------------------------------------------------------------
 def test_render_vjp(case1):
     banner("render_vjp 64^3")

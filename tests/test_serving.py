@@ -150,3 +150,48 @@ def test_step_graph_matches_step_via_c_abi():
     ma, va = fa.map.to_dense()
     mb, vb = fb.map.to_dense()
     assert torch.equal(ma, mb) and torch.equal(va, vb)
+
+
+@pytest.mark.gpu
+def test_submit_poll_via_c_abi():
+    """prism_filter_submit / prism_filter_poll: two slots, steps replayed from
+    per-slot graphs, bit for bit equal to prism_filter_step; a third
+    submission while both slots are in flight is refused (PRISM_BUSY) and
+    queues nothing; completions arrive in order."""
+    import torch
+    from gpu_util import banner, P
+    banner("prism_filter_submit / prism_filter_poll")
+    Pm = P()
+    specs, frames = _specs(n_streams=1, n_frames=6)
+    sp = specs[0]
+    D, C, U, _ = frames[0]
+    H, W = sp.cam.height, sp.cam.width
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        fa = Pm.Filter(sp.grid, sp.cam, sp.params)
+        fb = Pm.Filter(sp.grid, sp.cam, sp.params)
+        for f in (fa, fb):
+            f.map.init(stream=s)
+            f.reset(sp.x0, sp.P0, stream=s)
+        fb.set_slots([(torch.empty((H, W), device="cuda"), torch.empty((H, W, 3), device="cuda"),
+                       torch.zeros(6, dtype=torch.float64, device="cuda")) for _ in range(2)])
+        for k in range(sp.n_frames):
+            fa.step(D[k], C[k], None if k == 0 else U[k - 1], stream=s)
+    torch.cuda.synchronize()
+    assert fb.poll() == 0
+    with torch.cuda.stream(s):
+        torch.cuda._sleep(20_000_000)            # keep the stream busy so both slots stay in flight
+    seqs = [fb.submit(D[0], C[0], None, stream=s), fb.submit(D[1], C[1], U[0], stream=s)]
+    assert seqs == [0, 1]
+    assert fb.submit(D[2], C[2], U[1], stream=s) is None
+    torch.cuda.synchronize()
+    assert fb.poll() == 2
+    for k in range(2, sp.n_frames):
+        while fb.submit(D[k], C[k], U[k - 1], stream=s) is None:
+            pass
+    torch.cuda.synchronize()
+    assert fb.poll() == sp.n_frames
+    assert bytes(fa.state()) == bytes(fb.state())
+    ma, va = fa.map.to_dense()
+    mb, vb = fb.map.to_dense()
+    assert torch.equal(ma, mb) and torch.equal(va, vb)
