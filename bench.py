@@ -62,7 +62,7 @@ def build_mix(n_streams, n_frames, P, torch):
     return specs, frames
 
 
-def run_mix(specs, frames, n_frames, realtime, budget=None, n_hip_streams=4):
+def run_mix(specs, frames, n_frames, realtime, budget=None, n_hip_streams=4, batched=True):
     import dataclasses
     from paper_2212_02988_amd.serving import ServingLoop, run_schedule
     sp = [dataclasses.replace(s, n_frames=n_frames) for s in specs]
@@ -72,7 +72,7 @@ def run_mix(specs, frames, n_frames, realtime, budget=None, n_hip_streams=4):
     def source(sid, k):
         fr = frames[sid]
         return fr["D"][k], fr["C"][k], None if k == 0 else fr["U"][k - 1]
-    loop = ServingLoop(hbm_budget=budget, n_hip_streams=n_hip_streams)
+    loop = ServingLoop(hbm_budget=budget, n_hip_streams=n_hip_streams, batched=batched)
     wall = run_schedule(loop, sp, sched, source, realtime=realtime)
     return loop, wall
 
@@ -228,6 +228,9 @@ def main():
     ap.add_argument("--rt-frames", type=int, default=100, help="frames per stream of the 10 Hz real-time run")
     ap.add_argument("--budget-gb", type=float, default=1.5, help="artificial admission budget of the third run")
     ap.add_argument("--single-steps", type=int, default=100)
+    ap.add_argument("--hip-streams", type=int, default=4, help="HIP streams the serving loop spreads agents over")
+    ap.add_argument("--per-stream", action="store_true",
+                    help="serve without batching (each agent's step its own graph launch)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=16.0)
     ap.add_argument("--calib", action="store_true", help="also run a 256 MiB device copy (counter calibration)")
@@ -258,19 +261,20 @@ def main():
         f"resident footprint {foot / 2**30:.2f} GiB")
 
     # warm-up pass (fresh filters), then the timed backlog run
-    run_mix(specs, frames, wfps, realtime=False)
-    loop, wall = run_mix(specs, frames, fps, realtime=False)
+    mk = dict(n_hip_streams=args.hip_streams, batched=not args.per_stream)
+    run_mix(specs, frames, wfps, realtime=False, **mk)
+    loop, wall = run_mix(specs, frames, fps, realtime=False, **mk)
     assert loop.completed == steps
     value = steps / wall
     log(f"backlog run: {steps} steps in {wall:.3f} s = {value:.0f} steps/s, max concurrent {loop.max_concurrent}; "
         f"host {1e6 * loop.host_submit_s / steps:.1f} us/step in submit, {1e6 * loop.host_poll_s / steps:.1f} us/step "
-        f"in poll")
+        f"in poll, {loop.batches} batches (mean {steps / max(loop.batches, 1):.1f} steps)")
     # the same mix under an artificial admission budget
-    bloop, bwall = run_mix(specs, frames, fps, realtime=False, budget=int(args.budget_gb * 2**30))
+    bloop, bwall = run_mix(specs, frames, fps, realtime=False, budget=int(args.budget_gb * 2**30), **mk)
     log(f"{args.budget_gb:g} GB budget: {bloop.completed} steps in {bwall:.3f} s, max concurrent "
         f"{bloop.max_concurrent}")
     # real-time arrivals at 10 Hz
-    rloop, rwall = run_mix(specs, frames, args.rt_frames, realtime=True)
+    rloop, rwall = run_mix(specs, frames, args.rt_frames, realtime=True, **mk)
     rst = rloop.stats()
     log(f"10 Hz run: {rloop.completed} steps in {rwall:.2f} s, p50 {rst['p50_ms']:.2f} ms, p99 {rst['p99_ms']:.2f} ms")
     if args.calib:
@@ -305,8 +309,10 @@ def main():
         "config": {"workload": f"serving mix: {ns} agent streams, image sizes from {{160x120, 320x240, 640x480}}, "
                                "grids from {128^3, 256^3, 384^3} over a 6.4 m room, K = N/2, BF16 maps resident in "
                                "HBM, P2 objective with 3 Gauss-Newton iterations, full filter step per frame",
-                   "streams": mix_desc, "frames_per_stream": fps, "hip_streams": 4, "slots_per_stream": 2,
-                   "launch": "hip-graph per step (recorded per input slot)",
+                   "streams": mix_desc, "frames_per_stream": fps, "hip_streams": args.hip_streams,
+                   "slots_per_stream": 2,
+                   "launch": ("hip-graph per step (recorded per input slot)" if args.per_stream else
+                              "continuous batching: one launch per stage for all ready streams of a HIP stream"),
                    "latency_run": f"{args.rt_frames} frames per stream at 10 Hz + Exp(10 ms) jitter"},
         "serving": {"backlog_steps_per_s": r(value, 1), "backlog_wall_s": r(wall),
                     "realtime": {"steps": rloop.completed, "wall_s": r(rwall, 2), "p50_ms": r(rst["p50_ms"]),

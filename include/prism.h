@@ -400,9 +400,25 @@ prism_status prism_filter_set_slots(prism_filter *f, int32_t n_slots, const pris
 prism_status prism_filter_submit(prism_filter *f, const prism_frame *src, int32_t flags, hipStream_t stream,
                                  int64_t *seq);
 
+/* Continuous batching: one filter step for each of n distinct handles (frame
+ * src[i] for fs[i]) in a single batch, with the same effect on each handle,
+ * bit for bit, as prism_filter_submit.  Each stage of the step (frame
+ * staging, predict, tracking, Gauss-Newton, Laplace/combine, cull, map
+ * update, anchor render, normals) is one kernel launch for the whole batch,
+ * workgroups assigned to handles by ragged block ranges, so handles of
+ * different image and map sizes share launches.  Handles must use the P2
+ * objective and have input slots registered; each takes its next slot.
+ * Returns PRISM_BUSY, and queues nothing, when any handle has every slot in
+ * flight.  flags: PRISM_SUBMIT_FROM_HOST as for prism_filter_submit. */
+prism_status prism_filter_step_batch(prism_filter *const *fs, int32_t n, const prism_frame *src, int32_t flags,
+                                     hipStream_t stream);
+
 /* Non-blocking: *completed = number of submitted steps that have finished
  * (steps finish in submission order). */
 prism_status prism_filter_poll(prism_filter *f, int64_t *completed);
+
+/* prism_filter_poll for n handles: completed[i] for fs[i] (host array). */
+prism_status prism_filter_poll_batch(prism_filter *const *fs, int32_t n, int64_t *completed);
 
 /* Device pointer to the filter's prism_filter_state (inside state_mem). */
 prism_status prism_filter_state_ptr(const prism_filter *f, prism_filter_state **state);

@@ -210,6 +210,11 @@ struct prism_filter {
     int n_slots;
     int64_t submitted, completed;
     hipStream_t submit_stream;
+    // descriptor for batched steps: host copy, its place in state_mem, and
+    // whether the device copy is stale
+    AgentDesc desc;
+    AgentDesc* desc_dev;
+    bool desc_dirty;
 };
 
 namespace {
@@ -224,7 +229,7 @@ hipError_t release_graph(prism_filter::StepGraph& G) {
 }
 
 struct StateLayout {
-    size_t state, a_depth, a_rgb, a_normals, a_mask, a_nmask, partials, total;
+    size_t state, a_depth, a_rgb, a_normals, a_mask, a_nmask, partials, desc, total;
 };
 
 StateLayout state_layout(const prism_camera* c) {
@@ -246,6 +251,8 @@ StateLayout state_layout(const prism_camera* c) {
     off = round_up(off + npix, 256);
     L.partials = off;
     off = round_up(off + reduce_bytes(cc, 1), 256);
+    L.desc = off;
+    off = round_up(off + sizeof(AgentDesc), 256);
     L.total = off;
     return L;
 }
@@ -566,6 +573,34 @@ prism_status prism_filter_create(const prism_filter_cfg* cfg, void* state_mem, v
     f->partials = (double*)(base + L.partials);
     f->map = map_mem;
     f->steps = 0;
+    // batched-step descriptor (slots are filled in by prism_filter_set_slots)
+    AgentDesc& D = f->desc;
+    D.g = f->g;
+    D.c = f->c;
+    D.gd = f->gd;
+    D.cd = f->cd;
+    D.w = f->w;
+    D.tc = f->tc;
+    D.mp = MapUpdC{(float)cfg->map.trunc, cfg->map.trunc, cfg->map.lam_update};
+    D.aux = map_aux(&cfg->grid, map_mem);
+    D.ema = cfg->ema;
+    D.normal_disc = (float)cfg->normal_disc;
+    D.dtype = cfg->grid.dtype;
+    D.n_gn = cfg->n_gn;
+    D.nseg = (f->g.nb * f->g.nb * f->g.nb + 255) / 256;
+    D.upd_groups = map_update_groups(f->g);
+    D.track_blocks = track_blocks(f->c);
+    D.map = map_mem;
+    D.bits = skip_table(&cfg->grid, &cfg->cam, map_mem);
+    D.S = f->S;
+    D.a_depth = f->a_depth;
+    D.a_rgb = f->a_rgb;
+    D.a_normals = f->a_normals;
+    D.a_mask = f->a_mask;
+    D.a_nmask = f->a_nmask;
+    D.partials = f->partials;
+    f->desc_dev = (AgentDesc*)(base + L.desc);
+    f->desc_dirty = true;
     *out = f;
     return PRISM_OK;
 }
@@ -753,9 +788,11 @@ prism_status prism_filter_set_slots(prism_filter* f, int32_t n_slots, const pris
     f->n_slots = 0;
     for (int i = 0; i < n_slots; ++i) {
         f->slots[i] = slots[i];
+        f->desc.slots[i] = slots[i];
         HIP_TRY(hipEventCreateWithFlags(&f->slot_done[i], hipEventDisableTiming));
         f->n_slots = i + 1;
     }
+    f->desc_dirty = true;
     f->submitted = f->completed = 0;
     f->submit_stream = nullptr;
     return PRISM_OK;
@@ -815,6 +852,161 @@ prism_status prism_filter_submit(prism_filter* f, const prism_frame* src, int32_
     f->submit_stream = stream;
     if (seq) *seq = f->submitted;
     f->submitted += 1;
+    return PRISM_OK;
+}
+
+namespace {
+
+// block counts of one filter for each batched stage
+int blocks_of(const prism_filter* f, int stage) {
+    const CamC& c = f->c;
+    switch (stage) {
+        case 0: return stage_blocks(c);
+        case 1: return 1;                                    // predict, GN, Laplace, first frame
+        case 2: return track_blocks(c);
+        case 3: return f->desc.nseg;                         // cull
+        case 4: return f->desc.upd_groups;                   // update
+        case 5: return render_blocks(c);
+        default: return (c.W * c.H + 255) / 256;             // normals
+    }
+}
+
+// kernel argument for `stage` over the filters fs[i] (i in idx[0..m)) with
+// the given slots
+BatchArgs make_batch(prism_filter* const* fs, const int* idx, int m, const int* slot, int stage) {
+    BatchArgs b;
+    b.n = m;
+    b.start[0] = 0;
+    for (int j = 0; j < m; ++j) {
+        const prism_filter* f = fs[idx[j]];
+        b.d[j] = f->desc_dev;
+        b.slot[j] = (unsigned char)slot[idx[j]];
+        b.start[j + 1] = b.start[j] + blocks_of(f, stage);
+    }
+    for (int j = m; j < kMaxBatch; ++j) {
+        b.d[j] = nullptr;
+        b.slot[j] = 0;
+        b.start[j + 1] = b.start[m];
+    }
+    return b;
+}
+
+// one batched step for up to kMaxBatch filters already staged into slot[i]
+prism_status step_batch_chunk(prism_filter* const* fs, int n, const int* slot, hipStream_t st) {
+    int all[kMaxBatch], pu[kMaxBatch], ff[kMaxBatch], sub[kMaxBatch];
+    int n_all = 0, n_pu = 0, n_ff = 0, max_gn = 0;
+    for (int i = 0; i < n; ++i) {
+        all[n_all++] = i;
+        if (fs[i]->steps == 0) {
+            ff[n_ff++] = i;
+        } else {
+            pu[n_pu++] = i;
+            if (fs[i]->cfg.n_gn > max_gn) max_gn = fs[i]->cfg.n_gn;
+        }
+    }
+    if (n_pu) {
+        HIP_TRY(launch_predict_batch(make_batch(fs, pu, n_pu, slot, 1), st));
+        for (int it = 0; it < max_gn; ++it) {
+            int m = 0;
+            for (int j = 0; j < n_pu; ++j)
+                if (fs[pu[j]]->cfg.n_gn > it) sub[m++] = pu[j];
+            HIP_TRY(launch_track_p2_batch(make_batch(fs, sub, m, slot, 2), st));
+            HIP_TRY(launch_gn_step_batch(make_batch(fs, sub, m, slot, 1), st));
+        }
+        HIP_TRY(launch_track_p2_batch(make_batch(fs, pu, n_pu, slot, 2), st));
+        HIP_TRY(launch_laplace_combine_batch(make_batch(fs, pu, n_pu, slot, 1), st));
+    }
+    HIP_TRY(launch_cull_batch(make_batch(fs, all, n_all, slot, 3), st));
+    for (int dt = PRISM_F32; dt <= PRISM_BF16; ++dt) {
+        int m = 0, max_nseg = 0, max_words = 0;
+        for (int j = 0; j < n_all; ++j) {
+            const prism_filter* f = fs[all[j]];
+            if (f->cfg.grid.dtype != dt) continue;
+            sub[m++] = all[j];
+            if (f->desc.nseg > max_nseg) max_nseg = f->desc.nseg;
+            int words = f->desc.bits ? (f->g.nb * f->g.nb * f->g.nb + 31) >> 5 : 0;
+            if (words > max_words) max_words = words;
+        }
+        if (!m) continue;
+        HIP_TRY(launch_map_update_batch(make_batch(fs, sub, m, slot, 4), dt, max_nseg, st));
+        HIP_TRY(launch_render_batch(make_batch(fs, sub, m, slot, 5), dt, max_words, st));
+    }
+    HIP_TRY(launch_normals_batch(make_batch(fs, all, n_all, slot, 6), st));
+    if (n_ff) HIP_TRY(launch_first_frame_batch(make_batch(fs, ff, n_ff, slot, 1), st));
+    return PRISM_OK;
+}
+
+}  // namespace
+
+prism_status prism_filter_step_batch(prism_filter* const* fs, int32_t n, const prism_frame* src, int32_t flags,
+                                     hipStream_t stream) {
+    REQUIRE(fs && src && n >= 1, "need n >= 1 filters and frames");
+    REQUIRE(stream != nullptr, "batched steps need a non-default stream");
+    prism_status s;
+    for (int i = 0; i < n; ++i) {
+        prism_filter* f = fs[i];
+        REQUIRE(f, "filter %d is NULL", i);
+        REQUIRE(f->n_slots > 0, "filter %d has no input slots (prism_filter_set_slots)", i);
+        REQUIRE(f->cfg.objective == PRISM_OBJ_P2, "filter %d: batched steps take the P2 objective", i);
+        REQUIRE(!f->submit_stream || f->completed == f->submitted || f->submit_stream == stream,
+                "filter %d: all in-flight submissions of a handle must use one stream", i);
+        for (int j = 0; j < i; ++j) REQUIRE(fs[j] != f, "filter %d appears twice in the batch", i);
+        if ((s = check_frame(&src[i], f->steps > 0))) return s;
+        if ((s = poll_impl(f))) return s;
+        if (f->submitted - f->completed >= f->n_slots)
+            return fail(PRISM_BUSY, "filter %d: every input slot is in flight", i);
+    }
+    int slot[kMaxBatch];
+    for (int c0 = 0; c0 < n; c0 += kMaxBatch) {
+        const int m = n - c0 < kMaxBatch ? n - c0 : kMaxBatch;
+        prism_filter* const* fc = fs + c0;
+        const prism_frame* sc = src + c0;
+        StageSrc ss;
+        int dev_idx[kMaxBatch], n_dev = 0;
+        for (int i = 0; i < m; ++i) {
+            prism_filter* f = fc[i];
+            slot[i] = (int)(f->submitted % f->n_slots);
+            if (f->desc_dirty) {
+                HIP_TRY(hipMemcpyAsync(f->desc_dev, &f->desc, sizeof(AgentDesc), hipMemcpyHostToDevice, stream));
+                f->desc_dirty = false;
+            }
+            const prism_frame& sl = f->slots[slot[i]];
+            if (flags & PRISM_SUBMIT_FROM_HOST) {
+                const size_t npix = (size_t)f->cfg.cam.width * f->cfg.cam.height;
+                HIP_TRY(hipMemcpyAsync((void*)sl.depth, sc[i].depth, 4 * npix, hipMemcpyHostToDevice, stream));
+                HIP_TRY(hipMemcpyAsync((void*)sl.rgb, sc[i].rgb, 12 * npix, hipMemcpyHostToDevice, stream));
+                if (sc[i].u) HIP_TRY(hipMemcpyAsync((void*)sl.u, sc[i].u, 48, hipMemcpyHostToDevice, stream));
+            } else {
+                ss.depth[n_dev] = sc[i].depth;
+                ss.rgb[n_dev] = sc[i].rgb;
+                ss.u[n_dev] = sc[i].u;
+                dev_idx[n_dev++] = i;
+            }
+        }
+        if (n_dev) {
+            for (int j = n_dev; j < kMaxBatch; ++j) ss.depth[j] = ss.rgb[j] = ss.u[j] = nullptr;
+            HIP_TRY(launch_stage_batch(make_batch(fc, dev_idx, n_dev, slot, 0), ss, stream));
+        }
+        if ((s = step_batch_chunk(fc, m, slot, stream))) return s;
+        for (int i = 0; i < m; ++i) {
+            prism_filter* f = fc[i];
+            HIP_TRY(hipEventRecord(f->slot_done[slot[i]], stream));
+            f->steps += 1;
+            f->submitted += 1;
+            f->submit_stream = stream;
+        }
+    }
+    return PRISM_OK;
+}
+
+prism_status prism_filter_poll_batch(prism_filter* const* fs, int32_t n, int64_t* completed) {
+    REQUIRE(fs && completed && n >= 0, "filters and completed must be non-NULL");
+    for (int i = 0; i < n; ++i) {
+        REQUIRE(fs[i], "filter %d is NULL", i);
+        prism_status s = poll_impl(fs[i]);
+        if (s) return s;
+        completed[i] = fs[i]->completed;
+    }
     return PRISM_OK;
 }
 

@@ -12,6 +12,77 @@ struct TransC {
     double q[12];
 };
 
+struct MapUpdC {
+    float trunc32;          // decision: z <= D + trunc in single precision
+    double trunc, lam_u;    // values
+};
+
+// ---------------------------------------------------------------------------
+// batched steps over many filters (serving)
+// ---------------------------------------------------------------------------
+// Everything a kernel needs to run one filter's part of a batched step.  One
+// copy lives in each filter's state buffer (device), written from the
+// handle's host copy whenever it changes.
+struct AgentDesc {
+    GridC g;
+    CamC c;
+    GridD gd;
+    CamD cd;
+    WeightsC w;
+    TransC tc;
+    MapUpdC mp;
+    MapAux aux;
+    double ema;
+    float normal_disc;
+    int dtype, n_gn, nseg, upd_groups, track_blocks;
+    void* map;
+    const unsigned* bits;   // free-space bits for the renderer (NULL when tau != 0)
+    prism_filter_state* S;
+    float *a_depth, *a_rgb, *a_normals;
+    uint8_t *a_mask, *a_nmask;
+    double* partials;
+    prism_frame slots[4];
+};
+
+constexpr int kMaxBatch = 32;
+
+// kernel argument of a batched launch: workgroups [start[a], start[a+1]) of
+// the grid run filter a's part, reading its descriptor d[a] and input slot
+// slot[a]
+struct BatchArgs {
+    const AgentDesc* d[kMaxBatch];
+    int start[kMaxBatch + 1];
+    unsigned char slot[kMaxBatch];
+    int n;
+};
+
+// filter of workgroup blk (the start table is uniform: a scalar search)
+__device__ __forceinline__ int batch_agent(const BatchArgs& b, int blk) {
+    int a = 0;
+    while (a + 1 < b.n && b.start[a + 1] <= blk) ++a;
+    return a;
+}
+
+// sources of the frames a batched step stages into the slots
+struct StageSrc {
+    const void* depth[kMaxBatch];
+    const void* rgb[kMaxBatch];
+    const void* u[kMaxBatch];
+};
+
+// Batched launchers: one launch per stage for all filters of the batch.
+hipError_t launch_stage_batch(const BatchArgs& b, const StageSrc& src, hipStream_t st);
+hipError_t launch_predict_batch(const BatchArgs& b, hipStream_t st);
+hipError_t launch_track_p2_batch(const BatchArgs& b, hipStream_t st);
+hipError_t launch_gn_step_batch(const BatchArgs& b, hipStream_t st);
+hipError_t launch_laplace_combine_batch(const BatchArgs& b, hipStream_t st);
+hipError_t launch_first_frame_batch(const BatchArgs& b, hipStream_t st);
+hipError_t launch_cull_batch(const BatchArgs& b, hipStream_t st);
+hipError_t launch_map_update_batch(const BatchArgs& b, int dtype, int max_nseg, hipStream_t st);
+hipError_t launch_render_batch(const BatchArgs& b, int dtype, int max_bits_words, hipStream_t st);
+hipError_t launch_normals_batch(const BatchArgs& b, hipStream_t st);
+int stage_blocks(const CamC& c);
+
 int render_blocks(const CamC& c);   // render, render_jacobian
 int vjp_blocks(const CamC& c);      // render_vjp
 int track_blocks(const CamC& c);

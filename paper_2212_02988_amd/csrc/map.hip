@@ -148,11 +148,6 @@ __global__ __launch_bounds__(256) void k_pack_bits(int nbricks, MapAux aux) {
     aux.bits[w] = word;
 }
 
-struct MapUpdC {
-    float trunc32;          // decision: z <= D + trunc in single precision
-    double trunc, lam_u;    // values
-};
-
 // Conservative brick cull: true if no voxel centre of the brick can pass the
 // per-voxel test.  Each test is a convex region (behind the camera, or beyond
 // one side plane of the frustum) checked on the 8 corners of the brick's
@@ -184,17 +179,19 @@ struct PosePair {
     Pose64 d;
 };
 
-__global__ __launch_bounds__(256) void k_cull(GridC g, CamC c, const prism_pose* __restrict__ pose, MapAux aux) {
+// workgroup blk of the cull (bricks blk*256 .. blk*256+255)
+__device__ __forceinline__ void cull_block(int blk, const GridC& g, const CamC& c, const prism_pose* __restrict__ pose,
+                                           const MapAux& aux) {
     __shared__ PosePair sp;
     __shared__ int wcount[4];
     if (threadIdx.x == 0) {
         sp.d = load_pose64(pose);
         sp.f = to32(sp.d);
-        if (blockIdx.x == 0) *reinterpret_cast<PosePair*>(aux.pose) = sp;
+        if (blk == 0) *reinterpret_cast<PosePair*>(aux.pose) = sp;
     }
     __syncthreads();
     int nbricks = g.nb * g.nb * g.nb;
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    int b = blk * blockDim.x + threadIdx.x;
     bool keep = false;
     if (b < nbricks) {
         int bx = b % g.nb, by = (b / g.nb) % g.nb, bz = b / (g.nb * g.nb);
@@ -208,15 +205,22 @@ __global__ __launch_bounds__(256) void k_cull(GridC g, CamC c, const prism_pose*
     __syncthreads();
     int base = 0;
     for (int w = 0; w < wv; ++w) base += wcount[w];
-    if (keep) aux.list[blockIdx.x * 256 + base + rank] = b;
-    if (threadIdx.x == 0) aux.segcnt[blockIdx.x] = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+    if (keep) aux.list[blk * 256 + base + rank] = b;
+    if (threadIdx.x == 0) aux.segcnt[blk] = wcount[0] + wcount[1] + wcount[2] + wcount[3];
 }
 
+__global__ __launch_bounds__(256) void k_cull(GridC g, CamC c, const prism_pose* __restrict__ pose, MapAux aux) {
+    cull_block(blockIdx.x, g, c, pose, aux);
+}
+
+
+
+// workgroup blk of ngroups of the update
 template <typename T>
-__global__ __launch_bounds__(256) void k_map_update(GridC g, CamC c, GridD gd, T* __restrict__ map,
-                                                    const float* __restrict__ depth,
-                                                    const float* __restrict__ rgb, MapUpdC mp, MapAux aux,
-                                                    int nseg) {
+__device__ __forceinline__ void map_update_block(int blk, int ngroups, const GridC& g, const CamC& c, const GridD& gd,
+                                                 T* __restrict__ map, const float* __restrict__ depth,
+                                                 const float* __restrict__ rgb, const MapUpdC& mp, const MapAux& aux,
+                                                 int nseg) {
     extern __shared__ int sstart[];    // [nseg + 1] exclusive prefix of the segment lengths
     __shared__ PosePair sp;
     __shared__ float lmax[4];
@@ -251,7 +255,7 @@ __global__ __launch_bounds__(256) void k_map_update(GridC g, CamC c, GridD gd, T
     const Pose64& Q = sp.d;
     const int total = sstart[nseg];
     int cnt = 0;
-    for (int e = blockIdx.x; e < total; e += gridDim.x) {
+    for (int e = blk; e < total; e += ngroups) {
         // segment holding entry e (binary search over the prefix sums)
         int a = 0, z = nseg;
         while (z - a > 1) {
@@ -334,7 +338,32 @@ __global__ __launch_bounds__(256) void k_map_update(GridC g, CamC c, GridD gd, T
     for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
     if (lane == 0) lcnt[wv] = cnt;
     __syncthreads();
-    if (threadIdx.x == 0) aux.counts[blockIdx.x] = lcnt[0] + lcnt[1] + lcnt[2] + lcnt[3];
+    if (threadIdx.x == 0) aux.counts[blk] = lcnt[0] + lcnt[1] + lcnt[2] + lcnt[3];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_map_update(GridC g, CamC c, GridD gd, T* __restrict__ map,
+                                                    const float* __restrict__ depth,
+                                                    const float* __restrict__ rgb, MapUpdC mp, MapAux aux,
+                                                    int nseg) {
+    map_update_block<T>(blockIdx.x, gridDim.x, g, c, gd, map, depth, rgb, mp, aux, nseg);
+}
+
+// batched: every filter culls / updates its map at its posterior mean with
+// its slot's frame
+__global__ __launch_bounds__(256) void k_cull_batch(BatchArgs b) {
+    const int a = batch_agent(b, blockIdx.x);
+    const AgentDesc& D = *b.d[a];
+    cull_block(blockIdx.x - b.start[a], D.g, D.c, &D.S->pose, D.aux);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_map_update_batch(BatchArgs b) {
+    const int a = batch_agent(b, blockIdx.x);
+    const AgentDesc& D = *b.d[a];
+    const prism_frame& fr = D.slots[b.slot[a]];
+    map_update_block<T>(blockIdx.x - b.start[a], D.upd_groups, D.g, D.c, D.gd, (T*)D.map, (const float*)fr.depth,
+                        (const float*)fr.rgb, D.mp, D.aux, D.nseg);
 }
 
 // n_updated = sum of the per-workgroup counts of the last update
@@ -433,5 +462,19 @@ hipError_t launch_map_update(const GridC& g, const CamC& c, const GridD& gd, int
 }
 
 int map_update_groups(const GridC& g) { return update_grid(g); }
+
+hipError_t launch_cull_batch(const BatchArgs& b, hipStream_t st) {
+    k_cull_batch<<<b.start[b.n], 256, 0, st>>>(b);
+    return hipGetLastError();
+}
+
+hipError_t launch_map_update_batch(const BatchArgs& b, int dtype, int max_nseg, hipStream_t st) {
+    size_t lds = (size_t)(max_nseg + 1) * sizeof(int);
+    if (dtype == PRISM_BF16)
+        k_map_update_batch<uint16_t><<<b.start[b.n], 256, lds, st>>>(b);
+    else
+        k_map_update_batch<float><<<b.start[b.n], 256, lds, st>>>(b);
+    return hipGetLastError();
+}
 
 }  // namespace prism

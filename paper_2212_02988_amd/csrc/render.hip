@@ -254,9 +254,9 @@ struct BlockPose {
     Pose32 f;
 };
 
-__device__ __forceinline__ const BlockPose& block_pose(const prism_pose* poses, BlockPose* sp) {
+__device__ __forceinline__ const BlockPose& block_pose(const prism_pose* pose, BlockPose* sp) {
     if (threadIdx.x == 0) {
-        sp->d = load_pose64(poses + blockIdx.y);
+        sp->d = load_pose64(pose);
         sp->f = to32(sp->d);
     }
     __syncthreads();
@@ -396,9 +396,9 @@ __device__ __forceinline__ void jac_row_quad(const GridC& g, const T* map, const
 }
 
 // quad tile mapping: 8x8 pixels per 256-thread workgroup, 8x2 per wave
-__device__ __forceinline__ void quad_pixel(const CamC& c, int& u, int& v, int& s) {
+__device__ __forceinline__ void quad_pixel(const CamC& c, int blk, int& u, int& v, int& s) {
     int tiles_x = (c.W + 7) >> 3;
-    int bx = blockIdx.x % tiles_x, by = blockIdx.x / tiles_x;
+    int bx = blk % tiles_x, by = blk / tiles_x;
     int t = threadIdx.x;
     s = t & 3;
     int r = t >> 2;    // 0..63 ray of the tile
@@ -409,23 +409,24 @@ __device__ __forceinline__ void quad_pixel(const CamC& c, int& u, int& v, int& s
 // ---------------------------------------------------------------------------
 // render
 // ---------------------------------------------------------------------------
+// workgroup blk (8x8 pixel tile) of frame `frame`, rendered at *pose
 template <typename T>
-__global__ __launch_bounds__(256) void k_render(GridC g, CamC c, GridD gd, CamD cd, const T* __restrict__ map,
-                                                const unsigned* __restrict__ gbits,
-                                                const prism_pose* __restrict__ poses,
-                                                float* __restrict__ depth, float* __restrict__ rgb,
-                                                uint8_t* __restrict__ mask, int32_t* __restrict__ hit_k) {
+__device__ __forceinline__ void render_block(int blk, int frame, const GridC& g, const CamC& c, const GridD& gd,
+                                             const CamD& cd, const T* __restrict__ map,
+                                             const unsigned* __restrict__ gbits, const prism_pose* __restrict__ pose,
+                                             float* __restrict__ depth, float* __restrict__ rgb,
+                                             uint8_t* __restrict__ mask, int32_t* __restrict__ hit_k) {
     __shared__ BlockPose sp;
     extern __shared__ unsigned lbits[];
     const unsigned* bits = block_bits(g, gbits, lbits);
-    const BlockPose& P = block_pose(poses, &sp);
+    const BlockPose& P = block_pose(pose, &sp);
     int u, v, s;
-    quad_pixel(c, u, v, s);
+    quad_pixel(c, blk, u, v, s);
     if (u >= c.W || v >= c.H) return;   // whole quads leave together
     float dir[3];
     ray_dir32(c, P.f, u, v, dir);
     int k = march_quad(g, c, P.f, dir, map, bits, s);
-    long long pix = (long long)blockIdx.y * c.W * c.H + (long long)v * c.W + u;
+    long long pix = (long long)frame * c.W * c.H + (long long)v * c.W + u;
     if (s == 0) {
         if (hit_k) hit_k[pix] = k;
         mask[pix] = k >= 1 ? 1 : 0;
@@ -445,20 +446,39 @@ __global__ __launch_bounds__(256) void k_render(GridC g, CamC c, GridD gd, CamD 
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_render(GridC g, CamC c, GridD gd, CamD cd, const T* __restrict__ map,
+                                                const unsigned* __restrict__ gbits,
+                                                const prism_pose* __restrict__ poses,
+                                                float* __restrict__ depth, float* __restrict__ rgb,
+                                                uint8_t* __restrict__ mask, int32_t* __restrict__ hit_k) {
+    render_block<T>(blockIdx.x, blockIdx.y, g, c, gd, cd, map, gbits, poses + blockIdx.y, depth, rgb, mask, hit_k);
+}
+
+// batched: every filter renders its next anchor from its updated map at its
+// posterior mean
+template <typename T>
+__global__ __launch_bounds__(256) void k_render_batch(BatchArgs b) {
+    const int a = batch_agent(b, blockIdx.x);
+    const AgentDesc& D = *b.d[a];
+    render_block<T>(blockIdx.x - b.start[a], 0, D.g, D.c, D.gd, D.cd, (const T*)D.map, D.bits, &D.S->pose, D.a_depth,
+                    D.a_rgb, D.a_mask, nullptr);
+}
+
 // ---------------------------------------------------------------------------
 // normals of a rendered depth image
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_normals(CamC c, int n_frames, const float* __restrict__ depth,
-                                                 const uint8_t* __restrict__ mask, float disc,
-                                                 float* __restrict__ normals, uint8_t* __restrict__ nmask,
-                                                 const int* __restrict__ counts, int ngroups,
-                                                 int64_t* __restrict__ n_updated) {
+__device__ __forceinline__ void normals_block(int blk, const CamC& c, int n_frames, const float* __restrict__ depth,
+                                              const uint8_t* __restrict__ mask, float disc,
+                                              float* __restrict__ normals, uint8_t* __restrict__ nmask,
+                                              const int* __restrict__ counts, int ngroups,
+                                              int64_t* __restrict__ n_updated) {
     // in a filter step, the first workgroup also totals the preceding map
     // update (before any thread returns: the sum synchronises the workgroup)
     __shared__ long long part[4];
-    if (n_updated && blockIdx.x == 0) sum_counts_block(counts, ngroups, n_updated, part);
+    if (n_updated && blk == 0) sum_counts_block(counts, ngroups, n_updated, part);
     long long npix = (long long)c.W * c.H;
-    long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long gid = (long long)blk * blockDim.x + threadIdx.x;
     if (gid >= npix * n_frames) return;
     long long f = gid / npix;
     int p = (int)(gid - f * npix);
@@ -491,6 +511,21 @@ __global__ __launch_bounds__(256) void k_normals(CamC c, int n_frames, const flo
     nmask[gid] = 1;
 }
 
+__global__ __launch_bounds__(256) void k_normals(CamC c, int n_frames, const float* __restrict__ depth,
+                                                 const uint8_t* __restrict__ mask, float disc,
+                                                 float* __restrict__ normals, uint8_t* __restrict__ nmask,
+                                                 const int* __restrict__ counts, int ngroups,
+                                                 int64_t* __restrict__ n_updated) {
+    normals_block(blockIdx.x, c, n_frames, depth, mask, disc, normals, nmask, counts, ngroups, n_updated);
+}
+
+__global__ __launch_bounds__(256) void k_normals_batch(BatchArgs b) {
+    const int a = batch_agent(b, blockIdx.x);
+    const AgentDesc& D = *b.d[a];
+    normals_block(blockIdx.x - b.start[a], D.c, 1, D.a_depth, D.a_mask, D.normal_disc, D.a_normals, D.a_nmask,
+                  D.aux.counts, D.upd_groups, &D.S->n_updated);
+}
+
 // ---------------------------------------------------------------------------
 // render + P1 Jacobian + gated weighted normal equations
 // ---------------------------------------------------------------------------
@@ -508,9 +543,9 @@ __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, GridD gd, C
     __shared__ double lds[kRedLds];
     extern __shared__ unsigned lbits[];
     const unsigned* bits = block_bits(g, gbits, lbits);
-    const BlockPose& P = block_pose(poses, &sp);
+    const BlockPose& P = block_pose(poses + blockIdx.y, &sp);
     int u, v, s;
-    quad_pixel(c, u, v, s);
+    quad_pixel(c, blockIdx.x, u, v, s);
     double acc[PRISM_NEQ];
 #pragma unroll
     for (int q = 0; q < PRISM_NEQ; ++q) acc[q] = 0.0;
@@ -577,7 +612,7 @@ __global__ __launch_bounds__(256) void k_render_vjp(GridC g, CamC c, GridD gd, C
                                                     double* __restrict__ partials) {
     __shared__ BlockPose sp;
     __shared__ double lds[kRedLds];
-    const BlockPose& P = block_pose(poses, &sp);
+    const BlockPose& P = block_pose(poses + blockIdx.y, &sp);
     int u, v;
     tile_pixel(c, u, v);
     double acc[PRISM_NEQ];
@@ -658,6 +693,22 @@ hipError_t launch_render(const GridC& g, const CamC& c, const GridD& gd, const C
     else
         k_render<float><<<grid, 256, lds, st>>>(g, c, gd, cd, (const float*)map, bits, poses, depth, rgb, mask,
                                                 hit_k);
+    return hipGetLastError();
+}
+
+hipError_t launch_render_batch(const BatchArgs& b, int dtype, int max_bits_words, hipStream_t st) {
+    // filters whose bits fit copy them to LDS, the others read them from
+    // global memory (block_bits), so the allocation is the largest that fits
+    size_t lds = (size_t)(max_bits_words < kMaxLdsWords ? max_bits_words : kMaxLdsWords) * 4;
+    if (dtype == PRISM_BF16)
+        k_render_batch<uint16_t><<<b.start[b.n], 256, lds, st>>>(b);
+    else
+        k_render_batch<float><<<b.start[b.n], 256, lds, st>>>(b);
+    return hipGetLastError();
+}
+
+hipError_t launch_normals_batch(const BatchArgs& b, hipStream_t st) {
+    k_normals_batch<<<b.start[b.n], 256, 0, st>>>(b);
     return hipGetLastError();
 }
 

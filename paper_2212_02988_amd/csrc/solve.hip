@@ -287,8 +287,8 @@ __device__ inline void state_out(const prism_filter_state* l, prism_filter_state
 // ---------------------------------------------------------------------------
 // predict + split
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_predict(prism_filter_state* __restrict__ Sg,
-                                                 const double* __restrict__ u, TransC tc) {
+__device__ __forceinline__ void predict_block(prism_filter_state* __restrict__ Sg, const double* __restrict__ u,
+                                              const TransC& tc) {
     __shared__ double M[144], G[144], T1[144], T2[144], P[144], Spp[36], L[36], Sinv[36];
     __shared__ double vnew[6], E[9], Jl[9];
     __shared__ int ok;
@@ -395,6 +395,11 @@ __global__ __launch_bounds__(256) void k_predict(prism_filter_state* __restrict_
     state_out(S, Sg);
 }
 
+__global__ __launch_bounds__(256) void k_predict(prism_filter_state* __restrict__ Sg,
+                                                 const double* __restrict__ u, TransC tc) {
+    predict_block(Sg, u, tc);
+}
+
 // ---------------------------------------------------------------------------
 // one Gauss-Newton step of the MAP pose objective
 // ---------------------------------------------------------------------------
@@ -424,8 +429,8 @@ __device__ inline void gn_step_body(prism_filter_state* S, const double* neq) {
     S->iter = it;
 }
 
-__global__ __launch_bounds__(256) void k_gn_step(prism_filter_state* __restrict__ Sg,
-                                                 const double* __restrict__ partials, int nblocks) {
+__device__ __forceinline__ void gn_step_block(prism_filter_state* __restrict__ Sg,
+                                              const double* __restrict__ partials, int nblocks) {
     __shared__ double red[kRedLds], neq[PRISM_NEQ];
     __shared__ prism_filter_state Ls;
     state_in(Sg, &Ls);
@@ -438,12 +443,16 @@ __global__ __launch_bounds__(256) void k_gn_step(prism_filter_state* __restrict_
     }
 }
 
+__global__ __launch_bounds__(256) void k_gn_step(prism_filter_state* __restrict__ Sg,
+                                                 const double* __restrict__ partials, int nblocks) {
+    gn_step_block(Sg, partials, nblocks);
+}
+
 // ---------------------------------------------------------------------------
 // Laplace covariance, EMA, product with the velocity conditional
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_laplace_combine(prism_filter_state* __restrict__ Sg,
-                                                         const double* __restrict__ partials, int nblocks,
-                                                         double ema) {
+__device__ __forceinline__ void laplace_combine_block(prism_filter_state* __restrict__ Sg,
+                                                      const double* __restrict__ partials, int nblocks, double ema) {
     __shared__ double red[kRedLds], neq[PRISM_NEQ];
     __shared__ double A[36], Sl[36], Sb[36], D[36], T[36], P[144], e[6];
     __shared__ int ok;
@@ -517,11 +526,39 @@ __global__ __launch_bounds__(256) void k_laplace_combine(prism_filter_state* __r
     state_out(S, Sg);
 }
 
-__global__ void k_first_frame(prism_filter_state* __restrict__ S) {
-    S->anchor = S->pose;
-    S->step = 1;
-    S->flags = 0;
+__global__ __launch_bounds__(256) void k_laplace_combine(prism_filter_state* __restrict__ Sg,
+                                                         const double* __restrict__ partials, int nblocks,
+                                                         double ema) {
+    laplace_combine_block(Sg, partials, nblocks, ema);
 }
+
+__device__ __forceinline__ void first_frame_block(prism_filter_state* __restrict__ S) {
+    if (threadIdx.x == 0) {
+        S->anchor = S->pose;
+        S->step = 1;
+        S->flags = 0;
+    }
+}
+
+__global__ void k_first_frame(prism_filter_state* __restrict__ S) { first_frame_block(S); }
+
+// batched: one workgroup per filter
+__global__ __launch_bounds__(256) void k_predict_batch(BatchArgs b) {
+    const AgentDesc& D = *b.d[blockIdx.x];
+    predict_block(D.S, (const double*)D.slots[b.slot[blockIdx.x]].u, D.tc);
+}
+
+__global__ __launch_bounds__(256) void k_gn_step_batch(BatchArgs b) {
+    const AgentDesc& D = *b.d[blockIdx.x];
+    gn_step_block(D.S, D.partials, D.track_blocks);
+}
+
+__global__ __launch_bounds__(256) void k_laplace_combine_batch(BatchArgs b) {
+    const AgentDesc& D = *b.d[blockIdx.x];
+    laplace_combine_block(D.S, D.partials, D.track_blocks, D.ema);
+}
+
+__global__ __launch_bounds__(64) void k_first_frame_batch(BatchArgs b) { first_frame_block(b.d[blockIdx.x]->S); }
 
 // per-frame fixed-order sum of block partials; the first nvals values of
 // each frame go to out[frame * stride + q]
@@ -550,6 +587,26 @@ hipError_t launch_laplace_combine(prism_filter_state* S, const double* partials,
 
 hipError_t launch_first_frame(prism_filter_state* S, hipStream_t st) {
     k_first_frame<<<1, 1, 0, st>>>(S);
+    return hipGetLastError();
+}
+
+hipError_t launch_predict_batch(const BatchArgs& b, hipStream_t st) {
+    k_predict_batch<<<b.n, 256, 0, st>>>(b);
+    return hipGetLastError();
+}
+
+hipError_t launch_gn_step_batch(const BatchArgs& b, hipStream_t st) {
+    k_gn_step_batch<<<b.n, 256, 0, st>>>(b);
+    return hipGetLastError();
+}
+
+hipError_t launch_laplace_combine_batch(const BatchArgs& b, hipStream_t st) {
+    k_laplace_combine_batch<<<b.n, 256, 0, st>>>(b);
+    return hipGetLastError();
+}
+
+hipError_t launch_first_frame_batch(const BatchArgs& b, hipStream_t st) {
+    k_first_frame_batch<<<b.n, 64, 0, st>>>(b);
     return hipGetLastError();
 }
 

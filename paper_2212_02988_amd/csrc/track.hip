@@ -14,18 +14,20 @@ struct Rel32 {
     Pose64 cur, prev;      // both poses in double precision (values)
 };
 
-__global__ __launch_bounds__(256) void k_track_p2(CamC c, CamD cd, const prism_pose* __restrict__ pose,
-                                                  const prism_pose* __restrict__ pose_prev,
-                                                  const float* __restrict__ obs_depth,
-                                                  const float* __restrict__ obs_rgb,
-                                                  const float* __restrict__ a_depth,
-                                                  const float* __restrict__ a_rgb,
-                                                  const uint8_t* __restrict__ a_mask,
-                                                  const float* __restrict__ a_normals,
-                                                  const uint8_t* __restrict__ a_nmask, WeightsC wt,
-                                                  float* __restrict__ Jout, float* __restrict__ resid,
-                                                  uint8_t* __restrict__ rowmask,
-                                                  double* __restrict__ partials) {
+// one workgroup (blk: its index within this frame's grid) of the tracking
+// objective; partials receives the workgroup's 29 sums at row blk
+__device__ __forceinline__ void track_p2_block(int blk, const CamC& c, const CamD& cd,
+                                               const prism_pose* __restrict__ pose,
+                                               const prism_pose* __restrict__ pose_prev,
+                                               const float* __restrict__ obs_depth,
+                                               const float* __restrict__ obs_rgb,
+                                               const float* __restrict__ a_depth,
+                                               const float* __restrict__ a_rgb,
+                                               const uint8_t* __restrict__ a_mask,
+                                               const float* __restrict__ a_normals,
+                                               const uint8_t* __restrict__ a_nmask, const WeightsC& wt,
+                                               float* __restrict__ Jout, float* __restrict__ resid,
+                                               uint8_t* __restrict__ rowmask, double* __restrict__ partials) {
     __shared__ Rel32 srel;
     __shared__ double lds[kRedLds];
     if (threadIdx.x == 0) {
@@ -44,7 +46,7 @@ __global__ __launch_bounds__(256) void k_track_p2(CamC c, CamD cd, const prism_p
     double acc[PRISM_NEQ];
 #pragma unroll
     for (int q = 0; q < PRISM_NEQ; ++q) acc[q] = 0.0;
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    int p = blk * blockDim.x + threadIdx.x;
     if (p < c.W * c.H) {
         int u = p % c.W, v = p / c.W;
         float J[4][6];
@@ -180,10 +182,42 @@ __global__ __launch_bounds__(256) void k_track_p2(CamC c, CamD cd, const prism_p
             reinterpret_cast<float4*>(resid)[p] = make_float4((float)r[0], (float)r[1], (float)r[2], (float)r[3]);
         if (rowmask) rowmask[p] = rm;
     }
-    block_reduce29(acc, lds, partials + (long long)blockIdx.x * PRISM_NEQ);
+    block_reduce29(acc, lds, partials + (long long)blk * PRISM_NEQ);
+}
+
+__global__ __launch_bounds__(256) void k_track_p2(CamC c, CamD cd, const prism_pose* __restrict__ pose,
+                                                  const prism_pose* __restrict__ pose_prev,
+                                                  const float* __restrict__ obs_depth,
+                                                  const float* __restrict__ obs_rgb,
+                                                  const float* __restrict__ a_depth,
+                                                  const float* __restrict__ a_rgb,
+                                                  const uint8_t* __restrict__ a_mask,
+                                                  const float* __restrict__ a_normals,
+                                                  const uint8_t* __restrict__ a_nmask, WeightsC wt,
+                                                  float* __restrict__ Jout, float* __restrict__ resid,
+                                                  uint8_t* __restrict__ rowmask,
+                                                  double* __restrict__ partials) {
+    track_p2_block(blockIdx.x, c, cd, pose, pose_prev, obs_depth, obs_rgb, a_depth, a_rgb, a_mask, a_normals, a_nmask,
+                   wt, Jout, resid, rowmask, partials);
+}
+
+// batched: every filter tracks its slot's frame from its current iterate
+// against its anchor
+__global__ __launch_bounds__(256) void k_track_p2_batch(BatchArgs b) {
+    const int a = batch_agent(b, blockIdx.x);
+    const AgentDesc& D = *b.d[a];
+    const prism_frame& fr = D.slots[b.slot[a]];
+    track_p2_block(blockIdx.x - b.start[a], D.c, D.cd, &D.S->iter, &D.S->anchor, (const float*)fr.depth,
+                   (const float*)fr.rgb, D.a_depth, D.a_rgb, D.a_mask, D.a_normals, D.a_nmask, D.w, nullptr, nullptr,
+                   nullptr, D.partials);
 }
 
 int track_blocks(const CamC& c) { return (c.W * c.H + 255) / 256; }
+
+hipError_t launch_track_p2_batch(const BatchArgs& b, hipStream_t st) {
+    k_track_p2_batch<<<b.start[b.n], 256, 0, st>>>(b);
+    return hipGetLastError();
+}
 
 hipError_t launch_track_p2(const CamC& c, const CamD& cd, const prism_pose* pose, const prism_pose* pose_prev,
                            const float* obs_depth, const float* obs_rgb, const float* a_depth,

@@ -131,6 +131,8 @@ _SIGS = {
     "prism_filter_set_slots": (["p", ctypes.c_int32, "p"], None),
     "prism_filter_submit": (["p", "p", ctypes.c_int32, "p", "p"], None),
     "prism_filter_poll": (["p", "p"], None),
+    "prism_filter_step_batch": (["p", ctypes.c_int32, "p", ctypes.c_int32, "p"], None),
+    "prism_filter_poll_batch": (["p", ctypes.c_int32, "p"], None),
     "prism_filter_state_ptr": (["p", "p"], None),
     "prism_filter_anchor": (["p", "p", "p", "p", "p", "p"], None),
 }
@@ -543,6 +545,30 @@ def filter_step_graph(filters: Sequence[Filter], depths, rgbs, us, stream):
     frames = (Frame * n)(*[Filter.frame(d, r, u) for d, r, u in zip(depths, rgbs, us)])
     hs = (ctypes.c_void_p * n)(*[f.h for f in filters])
     _check(lib().prism_filter_step_graph(hs, n, frames, _stream(stream)))
+
+
+def filter_step_batch(filters: Sequence[Filter], frames, stream, flags: int = 0) -> bool:
+    """Continuous batching: one step for each filter (frames[i] = (depth, rgb,
+    u) for filters[i]) with one launch per stage for the whole batch (see
+    prism_filter_step_batch).  False, with nothing queued, when some filter
+    has every input slot in flight."""
+    n = len(filters)
+    fr = (Frame * n)(*[Filter.frame(d, c, u) for d, c, u in frames])
+    hs = (ctypes.c_void_p * n)(*[f.h for f in filters])
+    st = lib().prism_filter_step_batch(hs, n, fr, flags, _stream(stream))
+    if st == PRISM_BUSY:
+        return False
+    _check(st)
+    return True
+
+
+def filters_poll(filters: Sequence[Filter]) -> list:
+    """Completed-step counts of several filters with one call."""
+    n = len(filters)
+    hs = (ctypes.c_void_p * n)(*[f.h for f in filters])
+    out = (ctypes.c_int64 * n)()
+    _check(lib().prism_filter_poll_batch(hs, n, out))
+    return list(out)
 
 
 def filter_step(filters: Sequence[Filter], depths, rgbs, us, stream=None):

@@ -8,14 +8,15 @@ resident in HBM for the stream's lifetime.  Frames arrive at their own pace
   slots, all sized by the library's size queries) fits the HBM budget, keeps
   the others queued in arrival order, and admits queued streams as soon as
   finished ones release their memory;
-* keeps every admitted stream's steps flowing without waiting for the
-  others: whenever a stream has a pending frame and a free input slot, one
-  library call (prism_filter_submit) copies the frame into the slot and
-  launches the step on the stream's HIP stream (one of a small pool shared
-  round-robin) as the HIP graph the library recorded for that slot, so steps
-  of different agents overlap on the device and frames arriving while others
-  run join immediately; completions come from the library's per-slot events
-  (prism_filter_poll);
+* batches continuously: on every tick, the admitted streams that have a
+  pending frame and a free input slot form one batch per HIP stream (agents
+  are spread over a small pool of HIP streams at admission), and one library
+  call (prism_filter_step_batch) stages their frames into their slots and runs
+  the whole step for all of them with one kernel launch per stage, ragged over
+  their different image and map sizes; frames arriving while a batch runs
+  join the next one.  (batched=False submits each stream's step on its own,
+  as a HIP graph recorded per slot.)  Completions come from the library's
+  per-slot events (prism_filter_poll on one member per batch);
 * allows up to ``depth`` steps of one agent in flight (they are ordered on its
   HIP stream; each slot is reused only after the step that read it finished),
   and records per-frame latency from arrival to host-visible completion.
@@ -102,31 +103,33 @@ class _Agent:
     def ready(self) -> bool:
         return bool(self.pending) and self.launched - self.done < self.depth
 
-    def launch(self):
+    def source(self):
+        """The next frame's buffers as the library reads them (staged: copied
+        into this step's pinned host slot first)."""
         fr = self.pending[0]
-        if self.staged:
-            hd, hc, hu = self.host[self.launched % self.depth]
-            hd.numpy()[...] = fr.depth
-            hc.numpy()[...] = fr.rgb
-            if fr.u is not None:
-                hu.numpy()[...] = fr.u
-            src = (hd, hc, None if fr.u is None else hu)
-        else:
-            src = (fr.depth, fr.rgb, fr.u)
-        if self.filter.submit(*src, stream=self.stream, flags=self.flags) is None:
-            return False
-        self.pending.popleft()
-        self.in_flight.append(fr)
+        if not self.staged:
+            return fr.depth, fr.rgb, fr.u
+        hd, hc, hu = self.host[self.launched % self.depth]
+        hd.numpy()[...] = fr.depth
+        hc.numpy()[...] = fr.rgb
+        if fr.u is not None:
+            hu.numpy()[...] = fr.u
+        return hd, hc, None if fr.u is None else hu
+
+    def launched_one(self):
+        self.in_flight.append(self.pending.popleft())
         self.launched += 1
+
+    def launch(self):
+        """Submit the next frame on its own (one step graph per slot)."""
+        if self.filter.submit(*self.source(), stream=self.stream, flags=self.flags) is None:
+            return False
+        self.launched_one()
         return True
 
-    def poll(self) -> List[_Frame]:
-        c = self.filter.poll()
-        out = []
-        while self.done < c:
-            out.append(self.in_flight.popleft())
-            self.done += 1
-        return out
+    def complete_one(self) -> _Frame:
+        self.done += 1
+        return self.in_flight.popleft()
 
     def finished(self) -> bool:
         return self.done >= self.spec.n_frames
@@ -143,7 +146,8 @@ class ServingLoop:
     state and dense map when it retires (for tests)."""
 
     def __init__(self, hbm_budget: Optional[int] = None, n_hip_streams: int = 4, depth: int = 2,
-                 staged: bool = False, use_graphs: bool = True, reserve: int = 2 << 30, keep_final: bool = False):
+                 staged: bool = False, use_graphs: bool = True, reserve: int = 2 << 30, keep_final: bool = False,
+                 batched: bool = True):
         free, _ = torch.cuda.mem_get_info()
         cap = max(0, free - reserve)
         self.budget = cap if hbm_budget is None else min(int(hbm_budget), cap)
@@ -151,7 +155,13 @@ class ServingLoop:
         self.depth = depth
         self.staged = staged
         self.use_graphs = use_graphs
+        self.batched = batched
         self.keep_final = keep_final
+        self.batches = 0
+        # launched batches per HIP stream, oldest first: (agents, probe agent,
+        # the probe's submission count that marks the batch complete).  A
+        # batch's steps end together on its stream, so one event tells.
+        self.inflight: Dict[int, Deque[tuple]] = collections.defaultdict(collections.deque)
         self.queue: Deque[StreamSpec] = collections.deque()
         self.agents: Dict[int, _Agent] = {}
         self.held = 0
@@ -217,44 +227,76 @@ class ServingLoop:
 
     # ---- progress --------------------------------------------------------
     def poll(self) -> int:
-        """Retire finished steps (in order per agent); returns how many."""
+        """Retire finished batches (oldest first on each HIP stream); returns
+        how many steps completed."""
         n = 0
-        for ag in list(self.agents.values()):
-            if not ag.in_flight:
-                continue
-            t0 = time.perf_counter()
-            done = ag.poll()
-            self.host_poll_s += time.perf_counter() - t0
-            if done:
+        retire = []
+        for q in self.inflight.values():
+            while q:
+                ags, probe, need = q[0]
+                t0 = time.perf_counter()
+                c = probe.filter.poll()
+                self.host_poll_s += time.perf_counter() - t0
+                if c < need:
+                    break
+                q.popleft()
                 now = time.perf_counter()
-                for fr in done:
+                for ag in ags:
+                    fr = ag.complete_one()
                     lat = now - fr.arrival
                     self.latencies.append(lat)
                     self.per_stream_latency[ag.spec.stream_id].append(lat)
-                self.completed += len(done)
-                n += len(done)
-            if ag.finished():
-                self._retire(ag)
+                    if ag.finished():
+                        retire.append(ag)
+                self.completed += len(ags)
+                n += len(ags)
+        for ag in retire:
+            self._retire(ag)
         return n
 
     def tick(self) -> int:
-        """Launch every step that can start now; returns how many."""
+        """Launch every step that can start now; returns how many.  Batched:
+        the ready agents of each HIP stream form one batch (one launch per
+        stage for all of them); otherwise each agent submits on its own."""
         n = 0
         progress = True
         while progress:
             progress = False
-            for ag in self.agents.values():
-                if ag.ready():
+            if self.batched:
+                groups: Dict[int, List[_Agent]] = collections.defaultdict(list)
+                for ag in self.agents.values():
+                    if ag.ready():
+                        groups[id(ag.stream)].append(ag)
+                for ags in groups.values():
                     t0 = time.perf_counter()
-                    ok = ag.launch()
+                    ok = P.filter_step_batch([ag.filter for ag in ags], [ag.source() for ag in ags],
+                                             stream=ags[0].stream, flags=ags[0].flags & P.SUBMIT_FROM_HOST)
                     self.host_submit_s += time.perf_counter() - t0
                     if ok:
-                        n += 1
+                        for ag in ags:
+                            ag.launched_one()
+                        self.inflight[id(ags[0].stream)].append((ags, ags[-1], ags[-1].launched))
+                        n += len(ags)
+                        self.batches += 1
                         progress = True
+            else:
+                for ag in self.agents.values():
+                    if ag.ready():
+                        t0 = time.perf_counter()
+                        ok = ag.launch()
+                        self.host_submit_s += time.perf_counter() - t0
+                        if ok:
+                            self.inflight[id(ag.stream)].append(([ag], ag, ag.launched))
+                            self.batches += 1
+                            n += 1
+                            progress = True
         return n
 
     def busy(self) -> bool:
         return bool(self.queue) or bool(self.agents) or bool(self.waiting)
+
+    def idle_device(self) -> bool:
+        return not any(self.inflight.values())
 
     def run_until_idle(self, timeout: float = 600.0):
         t0 = time.perf_counter()

@@ -90,11 +90,12 @@ def test_serving_alone_equals_mix_and_admission():
 @pytest.mark.gpu
 def test_serving_graph_eager_and_staged_agree():
     from gpu_util import banner
-    banner("serving: graph replay vs eager launches, host-staged vs resident frames")
+    banner("serving: batched vs per-stream graph replay vs eager, host-staged vs resident frames")
     specs, frames = _specs(n_streams=3, n_frames=6)
     ids = [s.stream_id for s in specs]
-    ref, _ = _run(specs, frames, ids, use_graphs=False, depth=1)
-    for kw in (dict(use_graphs=True, depth=2), dict(use_graphs=True, depth=3, host=True)):
+    ref, _ = _run(specs, frames, ids, batched=False, use_graphs=False, depth=1)
+    for kw in (dict(batched=False, use_graphs=True, depth=2), dict(batched=True, depth=2),
+               dict(batched=True, depth=3, host=True, n_hip_streams=1)):
         got, _ = _run(specs, frames, ids, **kw)
         for i in ids:
             _same(ref.final[i], got.final[i])
@@ -195,3 +196,59 @@ def test_submit_poll_via_c_abi():
     ma, va = fa.map.to_dense()
     mb, vb = fb.map.to_dense()
     assert torch.equal(ma, mb) and torch.equal(va, vb)
+
+
+@pytest.mark.gpu
+def test_step_batch_matches_single_steps():
+    """prism_filter_step_batch over filters of different image sizes, grid
+    sizes, storage types and Gauss-Newton counts, one of them joining (first
+    frame) while the others are mid-trajectory: every filter's state and map
+    equal its own sequence of prism_filter_step calls, bit for bit."""
+    import dataclasses
+    import torch
+    from gpu_util import banner, P
+    banner("prism_filter_step_batch vs single steps (mixed batch)")
+    Pm = P()
+    specs, frames = _specs(n_streams=4, n_frames=6)
+    kinds = [(Pm.PRISM_F32, 3), (Pm.PRISM_BF16, 2), (Pm.PRISM_BF16, 3), (Pm.PRISM_F32, 1)]
+    for sp, (dt, ngn) in zip(specs, kinds):
+        sp.grid = Pm.Grid.make(sp.grid.n, sp.grid.voxel, tuple(sp.grid.origin), dtype=dt)
+        sp.params = dataclasses.replace(sp.params, n_gn=ngn)
+    join = {0: 0, 1: 0, 2: 0, 3: 2}        # frame index at which each filter starts
+    s = torch.cuda.Stream()
+    ref, bat = [], []
+    with torch.cuda.stream(s):
+        for sp in specs:
+            H, W = sp.cam.height, sp.cam.width
+            fa = Pm.Filter(sp.grid, sp.cam, sp.params)
+            fb = Pm.Filter(sp.grid, sp.cam, sp.params)
+            for f in (fa, fb):
+                f.map.init(stream=s)
+                f.reset(sp.x0, sp.P0, stream=s)
+            fb.set_slots([(torch.empty((H, W), device="cuda"), torch.empty((H, W, 3), device="cuda"),
+                           torch.zeros(6, dtype=torch.float64, device="cuda")) for _ in range(2)])
+            ref.append(fa)
+            bat.append(fb)
+        for t in range(6):
+            members, srcs = [], []
+            for i, sp in enumerate(specs):
+                k = t - join[i]
+                if k < 0:
+                    continue
+                D, C, U, _ = frames[i]
+                u = None if k == 0 else U[k - 1]
+                ref[i].step(D[k], C[k], u, stream=s)
+                members.append(bat[i])
+                srcs.append((D[k], C[k], u))
+            assert Pm.filter_step_batch(members, srcs, stream=s)
+            torch.cuda.synchronize()          # both slots are reused across iterations
+    torch.cuda.synchronize()
+    assert Pm.filters_poll(bat) == [6, 6, 6, 4]
+    for fa, fb in zip(ref, bat):
+        assert bytes(fa.state()) == bytes(fb.state())
+        ma, va = fa.map.to_dense()
+        mb, vb = fb.map.to_dense()
+        assert torch.equal(ma, mb) and torch.equal(va, vb)
+        aa, ab = fa.anchor(), fb.anchor()
+        for key in aa:
+            assert torch.equal(aa[key], ab[key]), key
