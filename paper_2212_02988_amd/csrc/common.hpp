@@ -181,10 +181,57 @@ __device__ __forceinline__ Cell sample_cell(const GridC& g, const CamC& c, const
 
 __device__ __forceinline__ float lerp32(float a, float b, float w) { return a + w * (b - a); }
 
+// Addressing of a trilinear cell whose 8 corners are all inside the grid:
+// the base corner's element index within a plane (32 bits: n <= 1024) and the
+// steps to its +x, +y and +z neighbours, which jump to the next brick when the
+// base sits on a brick's last voxel along that axis.
+struct CellAddr {
+    int base, dx, dy, dz;
+    int b0;       // brick of the base corner
+    bool cross;   // the cell spans more than one brick
+};
+
+__device__ __forceinline__ bool cell_inside(const GridC& g, const Cell& c) {
+    const unsigned lim = (unsigned)(g.n - 1);
+    return (unsigned)c.i[0] < lim && (unsigned)c.i[1] < lim && (unsigned)c.i[2] < lim;
+}
+
+__device__ __forceinline__ CellAddr cell_addr(const GridC& g, const Cell& c) {
+    CellAddr a;
+    const int lx = c.i[0] & 7, ly = c.i[1] & 7, lz = c.i[2] & 7;
+    a.b0 = ((c.i[2] >> 3) * g.nb + (c.i[1] >> 3)) * g.nb + (c.i[0] >> 3);
+    a.base = (a.b0 << 9) | (lz << 6) | (ly << 3) | lx;
+    a.dx = lx == 7 ? 512 - 7 : 1;
+    a.dy = ly == 7 ? 512 * g.nb - 56 : 8;
+    a.dz = lz == 7 ? 512 * g.nb * g.nb - 448 : 64;
+    a.cross = (lx == 7) | (ly == 7) | (lz == 7);
+    return a;
+}
+
+__device__ __forceinline__ float ldu(const float* p, unsigned i) { return p[i]; }
+__device__ __forceinline__ float ldu(const uint16_t* p, unsigned i) { return __uint_as_float(((uint32_t)p[i]) << 16); }
+
+template <typename T>
+__device__ __forceinline__ void corners_in(const T* plane, const CellAddr& a, float v[8]) {
+    const unsigned o = (unsigned)a.base;
+    v[0] = ldu(plane, o);
+    v[1] = ldu(plane, o + a.dx);
+    v[2] = ldu(plane, o + a.dy);
+    v[3] = ldu(plane, o + a.dy + a.dx);
+    v[4] = ldu(plane, o + a.dz);
+    v[5] = ldu(plane, o + a.dz + a.dx);
+    v[6] = ldu(plane, o + a.dz + a.dy);
+    v[7] = ldu(plane, o + a.dz + a.dy + a.dx);
+}
+
 // 8 corner values of one plane (out-of-grid corners take `outv`)
 template <typename T>
 __device__ __forceinline__ void corners(const GridC& g, const T* plane, const Cell& c, float outv,
                                         float v[8]) {
+    if (cell_inside(g, c)) {
+        corners_in(plane, cell_addr(g, c), v);
+        return;
+    }
     bool okx0 = (unsigned)c.i[0] < (unsigned)g.n, okx1 = (unsigned)(c.i[0] + 1) < (unsigned)g.n;
     bool oky0 = (unsigned)c.i[1] < (unsigned)g.n, oky1 = (unsigned)(c.i[1] + 1) < (unsigned)g.n;
     bool okz0 = (unsigned)c.i[2] < (unsigned)g.n, okz1 = (unsigned)(c.i[2] + 1) < (unsigned)g.n;

@@ -43,23 +43,30 @@ __device__ __forceinline__ float occ_at(const GridC& g, const T* occ, const Cell
 // is <= 0 under round-to-nearest (rounding is monotonic and 0 is
 // representable), so the single-precision recipe would have produced a value
 // <= 0 as well and the sample cannot be the hit when tau == 0.
-__device__ __forceinline__ bool skip_cell(const GridC& g, const unsigned* bits, const Cell& c) {
-    if (!bits) return false;
-    int lo[3], hi[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        if (c.i[a] < 0 || c.i[a] + 1 >= g.n) return false;
-        lo[a] = c.i[a] >> 3;
-        hi[a] = (c.i[a] + 1) >> 3;
-    }
+__device__ __forceinline__ bool bit_of(const unsigned* bits, int b) { return (bits[b >> 5] >> (b & 31)) & 1u; }
+
+__device__ __forceinline__ bool cell_free(const GridC& g, const unsigned* bits, const CellAddr& a) {
+    if (!a.cross) return bit_of(bits, a.b0);
+    const int sx = a.dx != 1 ? 1 : 0, sy = a.dy != 8 ? g.nb : 0, sz = a.dz != 64 ? g.nb * g.nb : 0;
     bool all = true;
-    for (int bz = lo[2]; bz <= hi[2]; ++bz)
-        for (int by = lo[1]; by <= hi[1]; ++by)
-            for (int bx = lo[0]; bx <= hi[0]; ++bx) {
-                int b = (bz * g.nb + by) * g.nb + bx;
-                all &= (bits[b >> 5] >> (b & 31)) & 1u;
-            }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        all &= bit_of(bits, a.b0 + ((q & 1) ? sx : 0) + ((q & 2) ? sy : 0) + ((q & 4) ? sz : 0));
     return all;
+}
+
+// occupancy of a marched sample, or -1 when the free-space bits prove it is
+// <= 0 (bits non-NULL only when tau == 0)
+template <typename T>
+__device__ __forceinline__ float march_occ(const GridC& g, const T* occ, const unsigned* bits, const Cell& cl) {
+    if (cell_inside(g, cl)) {
+        CellAddr a = cell_addr(g, cl);
+        if (bits && cell_free(g, bits, a)) return -1.0f;
+        float v[8];
+        corners_in(occ, a, v);
+        return trilerp(v, cl.w);
+    }
+    return occ_at(g, occ, cl);
 }
 
 // Free-space bits for this block: copied into LDS when they fit, else read
@@ -87,7 +94,7 @@ __device__ __forceinline__ RayHit march(const GridC& g, const CamC& c, const Pos
 #pragma unroll
         for (int j = 0; j < kUnroll; ++j) {
             Cell cl = sample_cell(g, c, P, dir, min(k0 + j, c.K - 1));
-            f[j] = skip_cell(g, bits, cl) ? -1.0f : occ_at(g, occ, cl);
+            f[j] = march_occ(g, occ, bits, cl);
         }
         int hit = -1;
 #pragma unroll
@@ -300,7 +307,7 @@ __device__ __forceinline__ int march_quad(const GridC& g, const CamC& c, const P
         for (int j = 0; j < kPerLane; ++j) {
             int k = k0 + j * kLanes + s;
             Cell cl = sample_cell(g, c, P, dir, min(k, c.K - 1));
-            f[j] = skip_cell(g, bits, cl) ? -1.0f : occ_at(g, occ, cl);
+            f[j] = march_occ(g, occ, bits, cl);
         }
         int first = 0x7fffffff;
 #pragma unroll
