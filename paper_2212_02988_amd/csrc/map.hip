@@ -223,7 +223,6 @@ __device__ __forceinline__ void map_update_block(int blk, int ngroups, const Gri
                                                  int nseg) {
     extern __shared__ int sstart[];    // [nseg + 1] exclusive prefix of the segment lengths
     __shared__ PosePair sp;
-    __shared__ float lmax[4];
     __shared__ int lcnt[4];
     __shared__ int wsum[4];
     // segment lengths -> exclusive prefix sums: each thread sums one
@@ -254,8 +253,12 @@ __device__ __forceinline__ void map_update_block(int blk, int ngroups, const Gri
     const Pose32& P = sp.f;
     const Pose64& Q = sp.d;
     const int total = sstart[nseg];
+    // one brick per wavefront at a time: lane `lane` owns voxel (lane & 7,
+    // lane >> 3) of each of the brick's 8 z-slices, so every load and store
+    // of a slice is 64 consecutive elements; no workgroup barrier per brick
+    const int nwaves = ngroups * 4;
     int cnt = 0;
-    for (int e = blk; e < total; e += ngroups) {
+    for (int e = blk * 4 + wv; e < total; e += nwaves) {
         // segment holding entry e (binary search over the prefix sums)
         int a = 0, z = nseg;
         while (z - a > 1) {
@@ -263,32 +266,52 @@ __device__ __forceinline__ void map_update_block(int blk, int ngroups, const Gri
             if (sstart[mid] <= e) a = mid; else z = mid;
         }
         const int b = aux.list[a * 256 + (e - sstart[a])];
-        int bx = b % g.nb, by = (b / g.nb) % g.nb, bz = b / (g.nb * g.nb);
-        float m = -INFINITY;
+        const int bx = b % g.nb, by = (b / g.nb) % g.nb, bz = b / (g.nb * g.nb);
+        const int i = (bx << 3) | (lane & 7), j = (by << 3) | (lane >> 3);
+        // decisions for the lane's 8 voxels in single precision
+        int pix[8];
+        float Dv[8];
+        bool upd[8];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            int l = threadIdx.x + h * 256;
-            long long id = ((long long)b << 9) | l;
-            int i = (bx << 3) | (l & 7), j = (by << 3) | ((l >> 3) & 7), k = (bz << 3) | (l >> 6);
+        for (int h = 0; h < 8; ++h) {
+            const int k = (bz << 3) | h;
             float x[3] = {g.o[0] + g.s * ((float)i + 0.5f), g.o[1] + g.s * ((float)j + 0.5f),
                           g.o[2] + g.s * ((float)k + 0.5f)};
             float d[3] = {x[0] - P.t[0], x[1] - P.t[1], x[2] - P.t[2]};
             float X[3];
 #pragma unroll
             for (int q = 0; q < 3; ++q) X[q] = (P.R[0][q] * d[0] + P.R[1][q] * d[1]) + P.R[2][q] * d[2];
-            bool upd = false;
-            int pix = 0;
-            float D = 0.0f;
+            upd[h] = false;
+            pix[h] = 0;
+            Dv[h] = 0.0f;
             if (X[2] > 0.0f) {
                 float uu = c.fx * (X[0] / X[2]) + c.cx;
                 float vv = c.fy * (X[1] / X[2]) + c.cy;
                 if (uu >= 0.0f && uu < (float)c.W && vv >= 0.0f && vv < (float)c.H) {
-                    pix = (int)vv * c.W + (int)uu;
-                    D = depth[pix];
-                    upd = depth_ok(D) && X[2] <= D + mp.trunc32;
+                    pix[h] = (int)vv * c.W + (int)uu;
+                    upd[h] = true;
                 }
             }
-            if (!upd) {
+        }
+#pragma unroll
+        for (int h = 0; h < 8; ++h)
+            if (upd[h]) Dv[h] = depth[pix[h]];
+        float m = -INFINITY;
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+            const int k = (bz << 3) | h;
+            const long long id = ((long long)b << 9) | (h << 6) | lane;
+            if (upd[h]) {
+                float X2;
+                {
+                    float x[3] = {g.o[0] + g.s * ((float)i + 0.5f), g.o[1] + g.s * ((float)j + 0.5f),
+                                  g.o[2] + g.s * ((float)k + 0.5f)};
+                    float d[3] = {x[0] - P.t[0], x[1] - P.t[1], x[2] - P.t[2]};
+                    X2 = (P.R[0][2] * d[0] + P.R[1][2] * d[1]) + P.R[2][2] * d[2];
+                }
+                upd[h] = depth_ok(Dv[h]) && X2 <= Dv[h] + mp.trunc32;
+            }
+            if (!upd[h]) {
                 m = fmaxf(m, ld(map, id));
                 continue;
             }
@@ -297,35 +320,53 @@ __device__ __forceinline__ void map_update_block(int blk, int ngroups, const Gri
             double dd0 = (gd.o[0] + gd.s * ((double)i + 0.5)) - Q.t[0];
             double dd1 = (gd.o[1] + gd.s * ((double)j + 0.5)) - Q.t[1];
             double dd2 = (gd.o[2] + gd.s * ((double)k + 0.5)) - Q.t[2];
-            double z = Q.R[0][2] * dd0 + Q.R[1][2] * dd1 + Q.R[2][2] * dd2;
+            double zc = Q.R[0][2] * dd0 + Q.R[1][2] * dd1 + Q.R[2][2] * dd2;
+            const int px = pix[h];
             double f[4];
-            f[0] = z - (double)D;
+            f[0] = zc - (double)Dv[h];
             if (f[0] < -mp.trunc) f[0] = -mp.trunc;
-            f[1] = (double)rgb[3 * pix];
-            f[2] = (double)rgb[3 * pix + 1];
-            f[3] = (double)rgb[3 * pix + 2];
+            f[1] = (double)rgb[3 * px];
+            f[2] = (double)rgb[3 * px + 1];
+            f[3] = (double)rgb[3 * px + 2];
             double mu[4], var[4];
 #pragma unroll
             for (int ch = 0; ch < 4; ++ch) {
                 mu[ch] = (double)ld(map, ch * g.nvox + id);
                 var[ch] = (double)ld(map, (4 + ch) * g.nvox + id);
             }
+            // App. D: new precision = old + update precision; new mean =
+            // inverse of the new precision times the precision-weighted sum.
+            // The four channels of a voxel are always updated together with
+            // one update precision, so their variances are normally equal bit
+            // for bit: the precision algebra is then done once (same inputs,
+            // same operations, same results as per channel).
+            double lam[4], var2[4];
+            if (var[0] == var[1] && var[1] == var[2] && var[2] == var[3]) {
+                double l = 1.0 / var[0];
+                double v2 = 1.0 / (l + mp.lam_u);
+#pragma unroll
+                for (int ch = 0; ch < 4; ++ch) {
+                    lam[ch] = l;
+                    var2[ch] = v2;
+                }
+            } else {
+#pragma unroll
+                for (int ch = 0; ch < 4; ++ch) {
+                    lam[ch] = 1.0 / var[ch];
+                    var2[ch] = 1.0 / (lam[ch] + mp.lam_u);
+                }
+            }
 #pragma unroll
             for (int ch = 0; ch < 4; ++ch) {
-                // App. D: new precision = old + update precision; new mean =
-                // inverse of the new precision times the precision-weighted sum
-                double lam = 1.0 / var[ch];
-                double lam2 = lam + mp.lam_u;
-                double var2 = 1.0 / lam2;
-                float nm = (float)(var2 * (lam * mu[ch] + mp.lam_u * f[ch]));
+                float nm = (float)(var2[ch] * (lam[ch] * mu[ch] + mp.lam_u * f[ch]));
                 st(map, ch * g.nvox + id, nm);
-                st(map, (4 + ch) * g.nvox + id, (float)var2);
+                st(map, (4 + ch) * g.nvox + id, (float)var2[ch]);
                 if (ch == 0) m = fmaxf(m, stored<T>(nm));
             }
             ++cnt;
         }
-        m = block_max(m, lmax);
-        if (threadIdx.x == 0) {
+        for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+        if (lane == 0) {
             // keep the free-space bit equal to (maximum <= 0): toggle it when
             // the brick crosses over (each brick has one owner per launch, so
             // toggles of one word touch different bits)
@@ -333,7 +374,6 @@ __device__ __forceinline__ void map_update_block(int blk, int ngroups, const Gri
             aux.bmax[b] = m;
             if (was_free != now_free) atomicXor(&aux.bits[b >> 5], 1u << (b & 31));
         }
-        __syncthreads();   // lmax is reused by the next brick
     }
     for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
     if (lane == 0) lcnt[wv] = cnt;

@@ -235,12 +235,19 @@ def test_track_p2(case1):
 
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("dtype", [0, 1])
-@pytest.mark.parametrize("warm", [False, True])
+@pytest.mark.parametrize("warm", [False, True, "mixed"])
 def test_map_update(case1, dtype, warm):
+    """cold: prior map; warm: ground-truth means, variance 0.25; mixed:
+    random means and a different random variance per channel and voxel (the
+    per-channel precision path of the kernel)."""
     banner(f"map_update 64^3 dtype={dtype} warm={warm}")
     c, mean_gt, _ = case1
     n = c["scene"].n
-    if warm:
+    if warm == "mixed":
+        r = np.random.default_rng(11)
+        mean = r.normal(0.0, 0.05, size=(4, n, n, n))
+        var = r.uniform(0.05, 3.0, size=(4, n, n, n))
+    elif warm:
         mean = mean_gt.copy()
         var = np.full_like(mean, 0.25)
     else:
