@@ -34,6 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
 
 
 def log(msg):
@@ -62,7 +63,7 @@ def build_mix(n_streams, n_frames, P, torch):
     return specs, frames
 
 
-def run_mix(specs, frames, n_frames, realtime, budget=None, n_hip_streams=4, batched=True):
+def run_mix(specs, frames, n_frames, realtime, budget=None, n_hip_streams=4, batched=True, timer=False):
     import dataclasses
     from paper_2212_02988_amd.serving import ServingLoop, run_schedule
     sp = [dataclasses.replace(s, n_frames=n_frames) for s in specs]
@@ -73,8 +74,59 @@ def run_mix(specs, frames, n_frames, realtime, budget=None, n_hip_streams=4, bat
         fr = frames[sid]
         return fr["D"][k], fr["C"][k], None if k == 0 else fr["U"][k - 1]
     loop = ServingLoop(hbm_budget=budget, n_hip_streams=n_hip_streams, batched=batched)
+    if timer:
+        from paper_2212_02988_amd import prism as P
+        P.stage_timer_arm(1 << 14)
     wall = run_schedule(loop, sp, sched, source, realtime=realtime)
+    if timer:
+        loop.stage_times = P.stage_timer_read()
     return loop, wall
+
+
+def stage_rooflines(loop, specs, fps):
+    """Per-stage share of the timed run and, for the three data-parallel
+    stages, achieved throughput against the roofline that bounds them:
+    map update HBM (algorithmic bytes: updated voxels x 32 B for BF16 / 64 B
+    for FP32 plus 16 B per frame pixel), render and tracking as stated in the
+    design notes (render: K samples x 40 FLOP per ray plus 200 FLOP of
+    shading, the emission's definition; tracking: 80 B per pixel)."""
+    from paper_2212_02988_amd import prism as P
+    times = loop.stage_times
+    total_ms = sum(v[0] for v in times.values())
+    out = {}
+    for name, (ms, n) in times.items():
+        if n:
+            out[name] = {"ms": round(ms, 3), "launches": int(n), "avg_us": round(1e3 * ms / n, 2),
+                         "share": round(ms / total_ms, 4)}
+    pix = sum(s.cam.width * s.cam.height * fps for s in specs)
+    ray_flop = sum(s.cam.width * s.cam.height * (s.cam.n_samples * 40 + 200) * fps for s in specs)
+    trk_pix = sum(s.cam.width * s.cam.height * (s.params.n_gn + 1) * (fps - 1) for s in specs)
+    upd_bytes = 0
+    for s in specs:
+        tot = loop.totals.get(s.stream_id)
+        per = 32 if s.grid.dtype == P.PRISM_BF16 else 64
+        upd_bytes += (tot["n_updated_total"] if tot else 0) * per
+    upd_bytes += 16 * pix
+    roof = {}
+    if "map_update" in out:
+        ms, n = times["map_update"]
+        a = upd_bytes / (ms * 1e-3) / 1e9
+        roof["map_update"] = {"bound": "hbm", "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(a / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": int(upd_bytes / n)}
+    if "render" in out:
+        ms, n = times["render"]
+        a = ray_flop / (ms * 1e-3) / 1e12
+        roof["render"] = {"bound": "alu", "achieved": round(a, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                          "frac": round(a / FP32_PEAK_TFLOPS, 4), "algorithmic_flop_per_launch": int(ray_flop / n)}
+    if "track" in out:
+        ms, n = times["track"]
+        a = 80 * trk_pix / (ms * 1e-3) / 1e9
+        roof["track"] = {"bound": "hbm", "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(a / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": int(80 * trk_pix / n)}
+    for k, v in roof.items():
+        out[k].update(roofline=v)
+    dom = max(out, key=lambda k: out[k]["ms"])
+    return out, dom, roof.get(dom)
 
 
 # ---------------------------------------------------------------------------
@@ -219,6 +271,52 @@ def cpu_baseline(frames, specs, budget_s):
                       f"each stream, about {per_stream:.1f} s per stream), {spent:.1f} s"}
 
 
+STAGE_KERNELS = {"render": "k_render_batch", "track": "k_track_p2_batch", "map_update": "k_map_update_batch",
+                 "gn": "k_gn_step_batch", "laplace": "k_laplace_combine_batch", "predict": "k_predict_batch",
+                 "cull": "k_cull_batch", "normals": "k_normals_batch", "staging": "k_stage_batch"}
+
+
+def source_digest():
+    """Digest of the kernel sources: measured HBM traffic is only reported for
+    the kernels it was measured on."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2212_02988_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        with open(os.path.join(d, name), "rb") as fh:
+            h.update(name.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` in this workload from the committed
+    counter summary (FETCH_SIZE, WRITE_SIZE scaled by a plain copy), or None
+    when the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "serving_mix_traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_digest") != source_digest():
+        return None
+    e = t.get("kernels", {}).get(kernel)
+    return None if e is None else e.get("hbm_bytes_per_launch")
+
+
+def roofline_obj(dominant, roof, breakdown):
+    if not dominant or not roof:
+        return None
+    kern = STAGE_KERNELS.get(dominant, dominant)
+    o = {"kernel": f"{kern} (serving mix on one HIP stream, batches of 16; {breakdown[dominant]['share']:.0%} "
+                   f"of stage time)"}
+    o.update({k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac")})
+    o["traffic"] = measured_traffic(kern)
+    o.update({k: v for k, v in roof.items() if k not in o})
+    o["avg_launch_us"] = breakdown[dominant]["avg_us"]
+    return o
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -269,6 +367,19 @@ def main():
     log(f"backlog run: {steps} steps in {wall:.3f} s = {value:.0f} steps/s, max concurrent {loop.max_concurrent}; "
         f"host {1e6 * loop.host_submit_s / steps:.1f} us/step in submit, {1e6 * loop.host_poll_s / steps:.1f} us/step "
         f"in poll, {loop.batches} batches (mean {steps / max(loop.batches, 1):.1f} steps)")
+    # kernel view: the same backlog on one HIP stream (batches of all 16
+    # streams, no overlap between streams), every stage launch timed with HIP
+    # events on the stream it runs on
+    breakdown, dominant, dom_roof, kv_rate = {}, None, None, None
+    if not args.per_stream:
+        kloop, kwall = run_mix(specs, frames, fps, realtime=False, n_hip_streams=1, timer=True)
+        kv_rate = kloop.completed / kwall
+        breakdown, dominant, dom_roof = stage_rooflines(kloop, specs, fps)
+        log(f"kernel view (one HIP stream): {kloop.completed} steps in {kwall:.3f} s = {kv_rate:.0f} steps/s, "
+            f"{kloop.batches} batches")
+    if breakdown:
+        log("stage shares: " + ", ".join(f"{k} {v['share']:.1%} ({v['avg_us']:.0f} us)" for k, v in
+                                         sorted(breakdown.items(), key=lambda kv: -kv[1]["ms"])))
     # the same mix under an artificial admission budget
     bloop, bwall = run_mix(specs, frames, fps, realtime=False, budget=int(args.budget_gb * 2**30), **mk)
     log(f"{args.budget_gb:g} GB budget: {bloop.completed} steps in {bwall:.3f} s, max concurrent "
@@ -315,6 +426,7 @@ def main():
                               "continuous batching: one launch per stage for all ready streams of a HIP stream"),
                    "latency_run": f"{args.rt_frames} frames per stream at 10 Hz + Exp(10 ms) jitter"},
         "serving": {"backlog_steps_per_s": r(value, 1), "backlog_wall_s": r(wall),
+                    "backlog_one_hip_stream_steps_per_s": None if kv_rate is None else r(kv_rate, 1),
                     "realtime": {"steps": rloop.completed, "wall_s": r(rwall, 2), "p50_ms": r(rst["p50_ms"]),
                                  "p99_ms": r(rst["p99_ms"]), "max_ms": r(rst["max_ms"]),
                                  "per_stream_hz": r(args.rt_frames / rwall, 2)},
@@ -331,10 +443,13 @@ def main():
                                         "workload": "256^3 FP32, 320x240, K = 128"},
         "kernels_us": {"render_jacobian_1f": r(single["us_rj1"], 2), "render_jacobian_8f": r(single["us_rj8"], 2),
                        "render": r(single["us_render"], 2), "map_update": r(single["us_mu"], 2)},
-        "roofline": {"kernel": "map_update (cull + update + pack), 256^3 FP32, 320x240, 4 rotating frames",
-                     "bound": "hbm", "achieved": r(single["mu_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": r(single["mu_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
-                     "algorithmic_bytes": int(single["mu_bytes"]), "updated_voxels": int(single["n_upd"])},
+        "roofline": roofline_obj(dominant, dom_roof, breakdown),
+        "kernel_breakdown": breakdown,
+        "roofline_map_update_single": {
+            "kernel": "map_update (cull + update + count), 256^3 FP32, 320x240, 4 rotating frames",
+            "bound": "hbm", "achieved": r(single["mu_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": r(single["mu_gbs"] / HBM_PEAK_GBS, 4), "algorithmic_bytes": int(single["mu_bytes"]),
+            "updated_voxels": int(single["n_upd"])},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

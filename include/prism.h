@@ -317,6 +317,7 @@ typedef struct {
     int64_t n_updated;      /* voxels updated by the last map update */
     int32_t flags;          /* PRISM_FLAG_* of the last step */
     int32_t has_sbar;
+    int64_t n_updated_total; /* voxels updated by all map updates of the filter's steps */
 } prism_filter_state;
 
 typedef struct prism_filter prism_filter;
@@ -412,6 +413,26 @@ prism_status prism_filter_submit(prism_filter *f, const prism_frame *src, int32_
  * flight.  flags: PRISM_SUBMIT_FROM_HOST as for prism_filter_submit. */
 prism_status prism_filter_step_batch(prism_filter *const *fs, int32_t n, const prism_frame *src, int32_t flags,
                                      hipStream_t stream);
+
+/* Stage timer (profiling aid): prism_stage_timer_arm(cap) makes every later
+ * prism_filter_step_batch record an event pair around each stage's launch,
+ * up to cap launches per stage (cap 0 disarms); prism_stage_timer_read
+ * waits for them, disarms, and returns per stage (index PRISM_STAGE_*) the
+ * summed launch time in ms and the number of launches timed.  Process-wide;
+ * events are created on arm and kept for reuse. */
+#define PRISM_STAGE_STAGING 0
+#define PRISM_STAGE_PREDICT 1
+#define PRISM_STAGE_TRACK 2
+#define PRISM_STAGE_GN 3
+#define PRISM_STAGE_LAPLACE 4
+#define PRISM_STAGE_CULL 5
+#define PRISM_STAGE_MAP_UPDATE 6
+#define PRISM_STAGE_RENDER 7
+#define PRISM_STAGE_NORMALS 8
+#define PRISM_STAGE_FIRST_FRAME 9
+#define PRISM_N_STAGES 10
+prism_status prism_stage_timer_arm(int32_t cap);
+prism_status prism_stage_timer_read(double *ms /* [PRISM_N_STAGES] */, int64_t *launches /* [PRISM_N_STAGES] */);
 
 /* Non-blocking: *completed = number of submitted steps that have finished
  * (steps finish in submission order). */

@@ -6,7 +6,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
+#include <vector>
 
 #include "common.hpp"
 #include "launch.hpp"
@@ -321,7 +323,7 @@ prism_status map_and_anchor(prism_filter* f, const prism_frame* fr, hipStream_t 
                           skip_table(&f->cfg.grid, &f->cfg.cam, f->map), &f->S->pose, 1, f->a_depth, f->a_rgb,
                           f->a_mask, nullptr, st));
     HIP_TRY(launch_normals(f->c, 1, f->a_depth, f->a_mask, (float)f->cfg.normal_disc, f->a_normals, f->a_nmask,
-                           aux.counts, map_update_groups(f->g), &f->S->n_updated, st));
+                           aux.counts, map_update_groups(f->g), &f->S->n_updated, &f->S->n_updated_total, st));
     return PRISM_OK;
 }
 
@@ -431,7 +433,7 @@ prism_status prism_render(const prism_grid* grid, const void* map, const prism_c
                           poses, n_frames, depth, rgb, mask, hit_k, stream));
     if (normals)
         HIP_TRY(launch_normals(c, n_frames, depth, mask, (float)normal_disc, normals, nmask, nullptr, 0, nullptr,
-                               stream));
+                               nullptr, stream));
     return PRISM_OK;
 }
 
@@ -857,6 +859,73 @@ prism_status prism_filter_submit(prism_filter* f, const prism_frame* src, int32_
 
 namespace {
 
+// ---- stage timer (profiling aid for batched steps) -------------------------
+// While armed, every batched step records an event pair around each stage's
+// launch (up to `cap` pairs per stage); prism_stage_timer_read sums them.
+struct StageTimer {
+    std::mutex mu;
+    bool armed = false;
+    int cap = 0;
+    std::vector<hipEvent_t> ev[PRISM_N_STAGES];   // pairs: begin, end
+    int used[PRISM_N_STAGES] = {};
+};
+StageTimer g_timer;
+
+struct StageScope {
+    int stage;
+    hipStream_t st;
+    hipEvent_t end_ev = nullptr;
+    StageScope(int s, hipStream_t stream) : stage(s), st(stream) {
+        std::lock_guard<std::mutex> lk(g_timer.mu);
+        if (!g_timer.armed || g_timer.used[s] >= g_timer.cap) return;
+        int i = g_timer.used[s]++;
+        if (hipEventRecord(g_timer.ev[s][2 * i], st) != hipSuccess) return;
+        end_ev = g_timer.ev[s][2 * i + 1];
+    }
+    ~StageScope() {
+        if (end_ev) (void)hipEventRecord(end_ev, st);
+    }
+};
+
+}  // namespace
+
+prism_status prism_stage_timer_arm(int32_t cap) {
+    REQUIRE(cap >= 0 && cap <= 1 << 16, "cap must be in [0, 65536]");
+    std::lock_guard<std::mutex> lk(g_timer.mu);
+    for (int s = 0; s < PRISM_N_STAGES; ++s) {
+        while ((int)g_timer.ev[s].size() < 2 * cap) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            g_timer.ev[s].push_back(e);
+        }
+        g_timer.used[s] = 0;
+    }
+    g_timer.cap = cap;
+    g_timer.armed = cap > 0;
+    return PRISM_OK;
+}
+
+prism_status prism_stage_timer_read(double* ms, int64_t* launches) {
+    REQUIRE(ms && launches, "ms and launches must be non-NULL");
+    std::lock_guard<std::mutex> lk(g_timer.mu);
+    g_timer.armed = false;
+    for (int s = 0; s < PRISM_N_STAGES; ++s) {
+        double t = 0.0;
+        for (int i = 0; i < g_timer.used[s]; ++i) {
+            HIP_TRY(hipEventSynchronize(g_timer.ev[s][2 * i + 1]));
+            float e = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&e, g_timer.ev[s][2 * i], g_timer.ev[s][2 * i + 1]));
+            t += e;
+        }
+        ms[s] = t;
+        launches[s] = g_timer.used[s];
+        g_timer.used[s] = 0;
+    }
+    return PRISM_OK;
+}
+
+namespace {
+
 // block counts of one filter for each batched stage
 int blocks_of(const prism_filter* f, int stage) {
     const CamC& c = f->c;
@@ -905,18 +974,36 @@ prism_status step_batch_chunk(prism_filter* const* fs, int n, const int* slot, h
         }
     }
     if (n_pu) {
-        HIP_TRY(launch_predict_batch(make_batch(fs, pu, n_pu, slot, 1), st));
+        {
+            StageScope t(PRISM_STAGE_PREDICT, st);
+            HIP_TRY(launch_predict_batch(make_batch(fs, pu, n_pu, slot, 1), st));
+        }
         for (int it = 0; it < max_gn; ++it) {
             int m = 0;
             for (int j = 0; j < n_pu; ++j)
                 if (fs[pu[j]]->cfg.n_gn > it) sub[m++] = pu[j];
-            HIP_TRY(launch_track_p2_batch(make_batch(fs, sub, m, slot, 2), st));
-            HIP_TRY(launch_gn_step_batch(make_batch(fs, sub, m, slot, 1), st));
+            {
+                StageScope t(PRISM_STAGE_TRACK, st);
+                HIP_TRY(launch_track_p2_batch(make_batch(fs, sub, m, slot, 2), st));
+            }
+            {
+                StageScope t(PRISM_STAGE_GN, st);
+                HIP_TRY(launch_gn_step_batch(make_batch(fs, sub, m, slot, 1), st));
+            }
         }
-        HIP_TRY(launch_track_p2_batch(make_batch(fs, pu, n_pu, slot, 2), st));
-        HIP_TRY(launch_laplace_combine_batch(make_batch(fs, pu, n_pu, slot, 1), st));
+        {
+            StageScope t(PRISM_STAGE_TRACK, st);
+            HIP_TRY(launch_track_p2_batch(make_batch(fs, pu, n_pu, slot, 2), st));
+        }
+        {
+            StageScope t(PRISM_STAGE_LAPLACE, st);
+            HIP_TRY(launch_laplace_combine_batch(make_batch(fs, pu, n_pu, slot, 1), st));
+        }
     }
-    HIP_TRY(launch_cull_batch(make_batch(fs, all, n_all, slot, 3), st));
+    {
+        StageScope t(PRISM_STAGE_CULL, st);
+        HIP_TRY(launch_cull_batch(make_batch(fs, all, n_all, slot, 3), st));
+    }
     for (int dt = PRISM_F32; dt <= PRISM_BF16; ++dt) {
         int m = 0, max_nseg = 0, max_words = 0;
         for (int j = 0; j < n_all; ++j) {
@@ -928,11 +1015,23 @@ prism_status step_batch_chunk(prism_filter* const* fs, int n, const int* slot, h
             if (words > max_words) max_words = words;
         }
         if (!m) continue;
-        HIP_TRY(launch_map_update_batch(make_batch(fs, sub, m, slot, 4), dt, max_nseg, st));
-        HIP_TRY(launch_render_batch(make_batch(fs, sub, m, slot, 5), dt, max_words, st));
+        {
+            StageScope t(PRISM_STAGE_MAP_UPDATE, st);
+            HIP_TRY(launch_map_update_batch(make_batch(fs, sub, m, slot, 4), dt, max_nseg, st));
+        }
+        {
+            StageScope t(PRISM_STAGE_RENDER, st);
+            HIP_TRY(launch_render_batch(make_batch(fs, sub, m, slot, 5), dt, max_words, st));
+        }
     }
-    HIP_TRY(launch_normals_batch(make_batch(fs, all, n_all, slot, 6), st));
-    if (n_ff) HIP_TRY(launch_first_frame_batch(make_batch(fs, ff, n_ff, slot, 1), st));
+    {
+        StageScope t(PRISM_STAGE_NORMALS, st);
+        HIP_TRY(launch_normals_batch(make_batch(fs, all, n_all, slot, 6), st));
+    }
+    if (n_ff) {
+        StageScope t(PRISM_STAGE_FIRST_FRAME, st);
+        HIP_TRY(launch_first_frame_batch(make_batch(fs, ff, n_ff, slot, 1), st));
+    }
     return PRISM_OK;
 }
 
@@ -985,6 +1084,7 @@ prism_status prism_filter_step_batch(prism_filter* const* fs, int32_t n, const p
         }
         if (n_dev) {
             for (int j = n_dev; j < kMaxBatch; ++j) ss.depth[j] = ss.rgb[j] = ss.u[j] = nullptr;
+            StageScope t(PRISM_STAGE_STAGING, stream);
             HIP_TRY(launch_stage_batch(make_batch(fc, dev_idx, n_dev, slot, 0), ss, stream));
         }
         if ((s = step_batch_chunk(fc, m, slot, stream))) return s;

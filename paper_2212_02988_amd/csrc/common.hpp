@@ -328,6 +328,21 @@ __device__ __forceinline__ void neq_add(double acc[PRISM_NEQ], const float j[6],
     acc[27] += w * r * r;
 }
 
+// the same in single precision, for one pixel's few rows
+__device__ __forceinline__ void neq_add32(float acc[PRISM_NEQ], const float j[6], float r, float w) {
+    float wj[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) wj[a] = w * j[a];
+    int q = 0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+#pragma unroll
+        for (int b = a; b < 6; ++b) acc[q++] += wj[a] * j[b];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) acc[21 + a] += wj[a] * r;
+    acc[27] += w * r * r;
+}
+
 struct WeightsC {
     double w_depth, w_rgb, gate_depth, gate_rgb;
 };
@@ -338,7 +353,7 @@ __device__ __forceinline__ bool depth_ok(float d) { return d > 0.0f && isfinite(
 // 256-thread workgroup: every lane issues its (up to 8) loads before adding,
 // so the sum costs one memory round trip, not ngroups / 64 of them
 __device__ inline void sum_counts_block(const int* __restrict__ counts, int ngroups, int64_t* __restrict__ n_updated,
-                                        long long* part) {
+                                        long long* part, int64_t* __restrict__ total = nullptr) {
     int v[8];
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
@@ -351,7 +366,11 @@ __device__ inline void sum_counts_block(const int* __restrict__ counts, int ngro
     for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = t;
     __syncthreads();
-    if (threadIdx.x == 0) *n_updated = part[0] + part[1] + part[2] + part[3];
+    if (threadIdx.x == 0) {
+        const long long sum = part[0] + part[1] + part[2] + part[3];
+        *n_updated = sum;
+        if (total) *total += sum;
+    }
 }
 
 }  // namespace prism

@@ -97,7 +97,7 @@ hipError_t launch_render(const GridC& g, const CamC& c, const GridD& gd, const C
 // per-workgroup counts into *n_updated
 hipError_t launch_normals(const CamC& c, int n_frames, const float* depth, const uint8_t* mask, float disc,
                           float* normals, uint8_t* nmask, const int* counts, int ngroups, int64_t* n_updated,
-                          hipStream_t st);
+                          int64_t* n_updated_total, hipStream_t st);
 hipError_t launch_render_jac(const GridC& g, const CamC& c, const GridD& gd, const CamD& cd, int dtype,
                              const void* map, const unsigned* bits, const prism_pose* poses, int n_frames,
                              const float* obs_depth,

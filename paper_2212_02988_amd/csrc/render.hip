@@ -479,11 +479,12 @@ __device__ __forceinline__ void normals_block(int blk, const CamC& c, int n_fram
                                               const uint8_t* __restrict__ mask, float disc,
                                               float* __restrict__ normals, uint8_t* __restrict__ nmask,
                                               const int* __restrict__ counts, int ngroups,
-                                              int64_t* __restrict__ n_updated) {
+                                              int64_t* __restrict__ n_updated,
+                                              int64_t* __restrict__ n_updated_total) {
     // in a filter step, the first workgroup also totals the preceding map
     // update (before any thread returns: the sum synchronises the workgroup)
     __shared__ long long part[4];
-    if (n_updated && blk == 0) sum_counts_block(counts, ngroups, n_updated, part);
+    if (n_updated && blk == 0) sum_counts_block(counts, ngroups, n_updated, part, n_updated_total);
     long long npix = (long long)c.W * c.H;
     long long gid = (long long)blk * blockDim.x + threadIdx.x;
     if (gid >= npix * n_frames) return;
@@ -522,15 +523,17 @@ __global__ __launch_bounds__(256) void k_normals(CamC c, int n_frames, const flo
                                                  const uint8_t* __restrict__ mask, float disc,
                                                  float* __restrict__ normals, uint8_t* __restrict__ nmask,
                                                  const int* __restrict__ counts, int ngroups,
-                                                 int64_t* __restrict__ n_updated) {
-    normals_block(blockIdx.x, c, n_frames, depth, mask, disc, normals, nmask, counts, ngroups, n_updated);
+                                                 int64_t* __restrict__ n_updated,
+                                                 int64_t* __restrict__ n_updated_total) {
+    normals_block(blockIdx.x, c, n_frames, depth, mask, disc, normals, nmask, counts, ngroups, n_updated,
+                  n_updated_total);
 }
 
 __global__ __launch_bounds__(256) void k_normals_batch(BatchArgs b) {
     const int a = batch_agent(b, blockIdx.x);
     const AgentDesc& D = *b.d[a];
     normals_block(blockIdx.x - b.start[a], D.c, 1, D.a_depth, D.a_mask, D.normal_disc, D.a_normals, D.a_nmask,
-                  D.aux.counts, D.upd_groups, &D.S->n_updated);
+                  D.aux.counts, D.upd_groups, &D.S->n_updated, &D.S->n_updated_total);
 }
 
 // ---------------------------------------------------------------------------
@@ -721,10 +724,10 @@ hipError_t launch_normals_batch(const BatchArgs& b, hipStream_t st) {
 
 hipError_t launch_normals(const CamC& c, int n_frames, const float* depth, const uint8_t* mask, float disc,
                           float* normals, uint8_t* nmask, const int* counts, int ngroups, int64_t* n_updated,
-                          hipStream_t st) {
+                          int64_t* n_updated_total, hipStream_t st) {
     long long n = (long long)c.W * c.H * n_frames;
     k_normals<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(c, n_frames, depth, mask, disc, normals, nmask, counts,
-                                                           ngroups, n_updated);
+                                                           ngroups, n_updated, n_updated_total);
     return hipGetLastError();
 }
 

@@ -43,9 +43,12 @@ __device__ __forceinline__ void track_p2_block(int blk, const CamC& c, const Cam
     }
     __syncthreads();
     const Rel32& rel = srel;
-    double acc[PRISM_NEQ];
+    // this pixel's rows summed in single precision (at most 4 rows of
+    // single-precision Jacobians), widened once for the double-precision
+    // reduction over pixels
+    float pacc[PRISM_NEQ];
 #pragma unroll
-    for (int q = 0; q < PRISM_NEQ; ++q) acc[q] = 0.0;
+    for (int q = 0; q < PRISM_NEQ; ++q) pacc[q] = 0.0f;
     int p = blk * blockDim.x + threadIdx.x;
     if (p < c.W * c.H) {
         int u = p % c.W, v = p / c.W;
@@ -129,7 +132,7 @@ __device__ __forceinline__ void track_p2_block(int blk, const CamC& c, const Cam
 #pragma unroll
                     for (int m = 0; m < 6; ++m) J[0][m] = -(fn0 * dY[0][m] + fn1 * dY[1][m] + fn2 * dY[2][m]);
                     if (fabs(rg) <= wt.gate_depth) {
-                        neq_add(acc, J[0], rg, wt.w_depth);
+                        neq_add32(pacc, J[0], (float)rg, (float)wt.w_depth);
                         rm |= 1;
                     }
                 }
@@ -164,11 +167,11 @@ __device__ __forceinline__ void track_p2_block(int blk, const CamC& c, const Cam
                     }
                     if (l1 <= wt.gate_rgb) {
 #pragma unroll
-                        for (int ch = 0; ch < 3; ++ch) neq_add(acc, J[1 + ch], rp[ch], wt.w_rgb);
+                        for (int ch = 0; ch < 3; ++ch) neq_add32(pacc, J[1 + ch], (float)rp[ch], (float)wt.w_rgb);
                         rm |= 2;
                     }
                 }
-                if (rm) acc[28] = 1.0;
+                if (rm) pacc[28] = 1.0f;
             }
         }
         if (Jout) {
@@ -182,6 +185,9 @@ __device__ __forceinline__ void track_p2_block(int blk, const CamC& c, const Cam
             reinterpret_cast<float4*>(resid)[p] = make_float4((float)r[0], (float)r[1], (float)r[2], (float)r[3]);
         if (rowmask) rowmask[p] = rm;
     }
+    double acc[PRISM_NEQ];
+#pragma unroll
+    for (int q = 0; q < PRISM_NEQ; ++q) acc[q] = (double)pacc[q];
     block_reduce29(acc, lds, partials + (long long)blk * PRISM_NEQ);
 }
 

@@ -89,7 +89,7 @@ class FilterState(ctypes.Structure):
                 ("Lp", ctypes.c_double * 36), ("D", ctypes.c_double * 36), ("Sv", ctypes.c_double * 36),
                 ("S_lap", ctypes.c_double * 36), ("neq", ctypes.c_double * 29), ("u", ctypes.c_double * 6),
                 ("step", ctypes.c_int64), ("n_updated", ctypes.c_int64), ("flags", ctypes.c_int32),
-                ("has_sbar", ctypes.c_int32)]
+                ("has_sbar", ctypes.c_int32), ("n_updated_total", ctypes.c_int64)]
 
 
 class Frame(ctypes.Structure):
@@ -133,6 +133,8 @@ _SIGS = {
     "prism_filter_poll": (["p", "p"], None),
     "prism_filter_step_batch": (["p", ctypes.c_int32, "p", ctypes.c_int32, "p"], None),
     "prism_filter_poll_batch": (["p", ctypes.c_int32, "p"], None),
+    "prism_stage_timer_arm": ([ctypes.c_int32], None),
+    "prism_stage_timer_read": (["p", "p"], None),
     "prism_filter_state_ptr": (["p", "p"], None),
     "prism_filter_anchor": (["p", "p", "p", "p", "p", "p"], None),
 }
@@ -569,6 +571,22 @@ def filters_poll(filters: Sequence[Filter]) -> list:
     out = (ctypes.c_int64 * n)()
     _check(lib().prism_filter_poll_batch(hs, n, out))
     return list(out)
+
+
+STAGES = ("staging", "predict", "track", "gn", "laplace", "cull", "map_update", "render", "normals", "first_frame")
+
+
+def stage_timer_arm(cap: int):
+    """Time every batched stage launch (up to cap per stage) from now on."""
+    _check(lib().prism_stage_timer_arm(cap))
+
+
+def stage_timer_read() -> Dict[str, tuple]:
+    """{stage: (summed launch ms, launches)}; disarms the timer."""
+    ms = (ctypes.c_double * len(STAGES))()
+    n = (ctypes.c_int64 * len(STAGES))()
+    _check(lib().prism_stage_timer_read(ms, n))
+    return {name: (ms[i], n[i]) for i, name in enumerate(STAGES)}
 
 
 def filter_step(filters: Sequence[Filter], depths, rgbs, us, stream=None):

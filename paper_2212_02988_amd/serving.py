@@ -173,6 +173,7 @@ class ServingLoop:
         self.max_concurrent = 0
         self.max_held_bytes = 0
         self.final: Dict[int, dict] = {}
+        self.totals: Dict[int, dict] = {}
         self._rr = 0
         self.host_submit_s = 0.0          # host time inside step submissions
         self.host_poll_s = 0.0            # host time inside completion polls
@@ -204,6 +205,9 @@ class ServingLoop:
 
     def _retire(self, ag: _Agent):
         sid = ag.spec.stream_id
+        # totals for throughput accounting (one small read of the state)
+        st0 = ag.filter.state()
+        self.totals[sid] = dict(steps=int(st0.step), n_updated_total=int(st0.n_updated_total))
         if self.keep_final:
             st = ag.filter.state()
             mean, var = ag.filter.map.to_dense(stream=ag.stream)
