@@ -556,9 +556,11 @@ __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, GridD gd, C
     const BlockPose& P = block_pose(poses + blockIdx.y, &sp);
     int u, v, s;
     quad_pixel(c, blockIdx.x, u, v, s);
-    double acc[PRISM_NEQ];
+    // this lane's row in single precision, widened once for the
+    // double-precision reduction over rays
+    float pacc[PRISM_NEQ];
 #pragma unroll
-    for (int q = 0; q < PRISM_NEQ; ++q) acc[q] = 0.0;
+    for (int q = 0; q < PRISM_NEQ; ++q) pacc[q] = 0.0f;
     if (u < c.W && v < c.H) {
         float dir[3];
         ray_dir32(c, P.f, u, v, dir);
@@ -584,8 +586,9 @@ __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, GridD gd, C
                 bool use_depth = fabs(quad_bcast(r, 0)) <= wt.gate_depth;
                 bool use_rgb = l1 <= wt.gate_rgb;
                 rm = (use_depth ? 1 : 0) | (use_rgb ? 2 : 0);
-                if (s == 0 ? use_depth : use_rgb) neq_add(acc, row, r, s == 0 ? wt.w_depth : wt.w_rgb);
-                if (rm && s == 0) acc[28] = 1.0;
+                if (s == 0 ? use_depth : use_rgb)
+                    neq_add32(pacc, row, (float)r, (float)(s == 0 ? wt.w_depth : wt.w_rgb));
+                if (rm && s == 0) pacc[28] = 1.0f;
             }
             if (!rm) {
 #pragma unroll
@@ -607,6 +610,9 @@ __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, GridD gd, C
         }
         if (resid) resid[4 * pix + s] = (float)r;
     }
+    double acc[PRISM_NEQ];
+#pragma unroll
+    for (int q = 0; q < PRISM_NEQ; ++q) acc[q] = (double)pacc[q];
     block_reduce29(acc, lds, partials + ((long long)blockIdx.y * gridDim.x + blockIdx.x) * PRISM_NEQ);
 }
 

@@ -243,15 +243,30 @@ __device__ inline void retract(prism_pose& p, const double d[6]) {
     R9_to_quat(R2, p.q);
 }
 
-// fixed-order block sum of partial normal equations into lds_out[29]
+// fixed-order block sum of partial normal equations into lds_out[29]; each
+// thread loads two rows per round so a few hundred to a few thousand rows
+// take only a couple of dependent memory round trips
 __device__ inline void sum_partials(const double* __restrict__ partials, int nblocks, double* lds_red,
                                     double* lds_out) {
     double acc[PRISM_NEQ];
 #pragma unroll
     for (int q = 0; q < PRISM_NEQ; ++q) acc[q] = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+    const int bd = blockDim.x;
+    int b = threadIdx.x;
+    for (; b + bd < nblocks; b += 2 * bd) {
+        double x[PRISM_NEQ], y[PRISM_NEQ];
+#pragma unroll
+        for (int q = 0; q < PRISM_NEQ; ++q) {
+            x[q] = partials[(long long)b * PRISM_NEQ + q];
+            y[q] = partials[(long long)(b + bd) * PRISM_NEQ + q];
+        }
+#pragma unroll
+        for (int q = 0; q < PRISM_NEQ; ++q) acc[q] += x[q] + y[q];
+    }
+    if (b < nblocks) {
 #pragma unroll
         for (int q = 0; q < PRISM_NEQ; ++q) acc[q] += partials[(long long)b * PRISM_NEQ + q];
+    }
     block_reduce29(acc, lds_red, lds_out);
     __syncthreads();
 }
@@ -443,7 +458,7 @@ __device__ __forceinline__ void gn_step_block(prism_filter_state* __restrict__ S
     }
 }
 
-__global__ __launch_bounds__(256) void k_gn_step(prism_filter_state* __restrict__ Sg,
+__global__ __launch_bounds__(512) void k_gn_step(prism_filter_state* __restrict__ Sg,
                                                  const double* __restrict__ partials, int nblocks) {
     gn_step_block(Sg, partials, nblocks);
 }
@@ -526,7 +541,7 @@ __device__ __forceinline__ void laplace_combine_block(prism_filter_state* __rest
     state_out(S, Sg);
 }
 
-__global__ __launch_bounds__(256) void k_laplace_combine(prism_filter_state* __restrict__ Sg,
+__global__ __launch_bounds__(512) void k_laplace_combine(prism_filter_state* __restrict__ Sg,
                                                          const double* __restrict__ partials, int nblocks,
                                                          double ema) {
     laplace_combine_block(Sg, partials, nblocks, ema);
@@ -548,12 +563,12 @@ __global__ __launch_bounds__(256) void k_predict_batch(BatchArgs b) {
     predict_block(D.S, (const double*)D.slots[b.slot[blockIdx.x]].u, D.tc);
 }
 
-__global__ __launch_bounds__(256) void k_gn_step_batch(BatchArgs b) {
+__global__ __launch_bounds__(512) void k_gn_step_batch(BatchArgs b) {
     const AgentDesc& D = *b.d[blockIdx.x];
     gn_step_block(D.S, D.partials, D.track_blocks);
 }
 
-__global__ __launch_bounds__(256) void k_laplace_combine_batch(BatchArgs b) {
+__global__ __launch_bounds__(512) void k_laplace_combine_batch(BatchArgs b) {
     const AgentDesc& D = *b.d[blockIdx.x];
     laplace_combine_block(D.S, D.partials, D.track_blocks, D.ema);
 }
@@ -562,7 +577,7 @@ __global__ __launch_bounds__(64) void k_first_frame_batch(BatchArgs b) { first_f
 
 // per-frame fixed-order sum of block partials; the first nvals values of
 // each frame go to out[frame * stride + q]
-__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partials, int nblocks, int nvals,
+__global__ __launch_bounds__(512) void k_finalize(const double* __restrict__ partials, int nblocks, int nvals,
                                                   double* __restrict__ out, int stride) {
     __shared__ double red[kRedLds], neq[PRISM_NEQ];
     sum_partials(partials + (long long)blockIdx.x * nblocks * PRISM_NEQ, nblocks, red, neq);
@@ -575,13 +590,13 @@ hipError_t launch_predict(prism_filter_state* S, const double* u, const TransC& 
 }
 
 hipError_t launch_gn_step(prism_filter_state* S, const double* partials, int nblocks, hipStream_t st) {
-    k_gn_step<<<1, 256, 0, st>>>(S, partials, nblocks);
+    k_gn_step<<<1, 512, 0, st>>>(S, partials, nblocks);
     return hipGetLastError();
 }
 
 hipError_t launch_laplace_combine(prism_filter_state* S, const double* partials, int nblocks, double ema,
                                   hipStream_t st) {
-    k_laplace_combine<<<1, 256, 0, st>>>(S, partials, nblocks, ema);
+    k_laplace_combine<<<1, 512, 0, st>>>(S, partials, nblocks, ema);
     return hipGetLastError();
 }
 
@@ -596,12 +611,12 @@ hipError_t launch_predict_batch(const BatchArgs& b, hipStream_t st) {
 }
 
 hipError_t launch_gn_step_batch(const BatchArgs& b, hipStream_t st) {
-    k_gn_step_batch<<<b.n, 256, 0, st>>>(b);
+    k_gn_step_batch<<<b.n, 512, 0, st>>>(b);
     return hipGetLastError();
 }
 
 hipError_t launch_laplace_combine_batch(const BatchArgs& b, hipStream_t st) {
-    k_laplace_combine_batch<<<b.n, 256, 0, st>>>(b);
+    k_laplace_combine_batch<<<b.n, 512, 0, st>>>(b);
     return hipGetLastError();
 }
 
@@ -612,7 +627,7 @@ hipError_t launch_first_frame_batch(const BatchArgs& b, hipStream_t st) {
 
 hipError_t launch_finalize(const double* partials, int nblocks, int n_frames, int nvals, double* out,
                            int stride, hipStream_t st) {
-    k_finalize<<<n_frames, 256, 0, st>>>(partials, nblocks, nvals, out, stride);
+    k_finalize<<<n_frames, 512, 0, st>>>(partials, nblocks, nvals, out, stride);
     return hipGetLastError();
 }
 
