@@ -225,8 +225,9 @@ def single_stream(P, torch, steps, warmup):
     n_upd = np.mean([int(c.item()) for c in counts])
     mu_bytes = n_upd * 64 + rays * 16
     mu_gbs = mu_bytes / (ms_mu * 1e-3) / 1e9
+
     log(f"render_jacobian 1 frame {ms_rj1 * 1e3:.1f} us, 8 frames {ms_rj8 * 1e3:.1f} us; render {ms_r * 1e3:.1f} us; "
-        f"map_update {ms_mu * 1e3:.1f} us, {n_upd:.0f} voxels, {mu_gbs:.0f} GB/s")
+        f"map_update call {ms_mu * 1e3:.1f} us ({mu_gbs:.0f} GB/s), {n_upd:.0f} voxels")
     return dict(
         ms_per_step=ms, p50_ms=float(np.percentile(per, 50)), p99_ms=float(np.percentile(per, 99)),
         pos_err=pos_err, mrays_1=rays / (ms_rj1 * 1e-3) / 1e6, mrays_8=8 * rays / (ms_rj8 * 1e-3) / 1e6,
@@ -446,10 +447,10 @@ def main():
         "roofline": roofline_obj(dominant, dom_roof, breakdown),
         "kernel_breakdown": breakdown,
         "roofline_map_update_single": {
-            "kernel": "map_update (cull + update + count), 256^3 FP32, 320x240, 4 rotating frames",
+            "kernel": "prism_map_update call (cull + update + count), 256^3 FP32, 320x240, 4 rotating frames",
             "bound": "hbm", "achieved": r(single["mu_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": r(single["mu_gbs"] / HBM_PEAK_GBS, 4), "algorithmic_bytes": int(single["mu_bytes"]),
-            "updated_voxels": int(single["n_upd"])},
+            "updated_voxels": int(single["n_upd"]), "avg_call_us": r(single["us_mu"], 2)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -173,6 +173,44 @@ size_t reduce_bytes(const CamC& c, int n_frames) {
     return (size_t)nb * n_frames * PRISM_NEQ * sizeof(double);
 }
 
+// ---- stage timer (profiling aid for batched steps) -------------------------
+// While armed, every batched step records an event pair around each stage's
+// launch (up to `cap` pairs per stage); prism_stage_timer_read sums them.
+struct StageTimer {
+    std::mutex mu;
+    bool armed = false;
+    int cap = 0;
+    std::vector<hipEvent_t> ev[PRISM_N_STAGES];   // pairs: begin, end
+    int used[PRISM_N_STAGES] = {};
+};
+StageTimer g_timer;
+
+// reserves the next event pair of `stage` when the timer is armed and the
+// stream is not being captured into a graph
+bool timer_pair(int s, hipStream_t st, hipEvent_t* b, hipEvent_t* e) {
+    std::lock_guard<std::mutex> lk(g_timer.mu);
+    if (!g_timer.armed || g_timer.used[s] >= g_timer.cap) return false;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return false;
+    int i = g_timer.used[s]++;
+    *b = g_timer.ev[s][2 * i];
+    *e = g_timer.ev[s][2 * i + 1];
+    return true;
+}
+
+struct StageScope {
+    hipStream_t st;
+    hipEvent_t end_ev = nullptr;
+    StageScope(int s, hipStream_t stream) : st(stream) {
+        hipEvent_t b;
+        if (timer_pair(s, stream, &b, &end_ev) && hipEventRecord(b, st) != hipSuccess) end_ev = nullptr;
+    }
+    ~StageScope() {
+        if (end_ev) (void)hipEventRecord(end_ev, st);
+    }
+};
+
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -317,8 +355,10 @@ prism_status pose_update_impl(prism_filter* f, const prism_frame* fr, hipStream_
 prism_status map_and_anchor(prism_filter* f, const prism_frame* fr, hipStream_t st) {
     // the update's count of voxels is totalled by the normals kernel at the end
     MapAux aux = map_aux(&f->cfg.grid, f->map);
+    hipEvent_t tb = nullptr, te = nullptr;
+    if (!timer_pair(PRISM_STAGE_MAP_UPDATE, st, &tb, &te)) tb = te = nullptr;
     HIP_TRY(launch_map_update(f->g, f->c, f->gd, f->cfg.grid.dtype, f->map, &f->S->pose, fr->depth, fr->rgb,
-                              f->cfg.map.trunc, f->cfg.map.lam_update, aux, nullptr, st));
+                              f->cfg.map.trunc, f->cfg.map.lam_update, aux, nullptr, st, tb, te));
     HIP_TRY(launch_render(f->g, f->c, f->gd, f->cd, f->cfg.grid.dtype, f->map,
                           skip_table(&f->cfg.grid, &f->cfg.cam, f->map), &f->S->pose, 1, f->a_depth, f->a_rgb,
                           f->a_mask, nullptr, st));
@@ -530,8 +570,10 @@ prism_status prism_map_update(const prism_grid* grid, void* map, const prism_cam
     REQUIRE(p && isfinite(p->trunc) && p->trunc > 0 && isfinite(p->lam_update) && p->lam_update > 0,
             "map params: trunc and lam_update must be finite and > 0");
     REQUIRE(!n_updated || aligned(n_updated, 8), "n_updated misaligned");
+    hipEvent_t tb = nullptr, te = nullptr;
+    if (!timer_pair(PRISM_STAGE_MAP_UPDATE, stream, &tb, &te)) tb = te = nullptr;
     HIP_TRY(launch_map_update(grid_c(grid), cam_c(cam), grid_d(grid), grid->dtype, map, pose, obs_depth, obs_rgb,
-                              p->trunc, p->lam_update, map_aux(grid, map), n_updated, stream));
+                              p->trunc, p->lam_update, map_aux(grid, map), n_updated, stream, tb, te));
     return PRISM_OK;
 }
 
@@ -856,38 +898,6 @@ prism_status prism_filter_submit(prism_filter* f, const prism_frame* src, int32_
     f->submitted += 1;
     return PRISM_OK;
 }
-
-namespace {
-
-// ---- stage timer (profiling aid for batched steps) -------------------------
-// While armed, every batched step records an event pair around each stage's
-// launch (up to `cap` pairs per stage); prism_stage_timer_read sums them.
-struct StageTimer {
-    std::mutex mu;
-    bool armed = false;
-    int cap = 0;
-    std::vector<hipEvent_t> ev[PRISM_N_STAGES];   // pairs: begin, end
-    int used[PRISM_N_STAGES] = {};
-};
-StageTimer g_timer;
-
-struct StageScope {
-    int stage;
-    hipStream_t st;
-    hipEvent_t end_ev = nullptr;
-    StageScope(int s, hipStream_t stream) : stage(s), st(stream) {
-        std::lock_guard<std::mutex> lk(g_timer.mu);
-        if (!g_timer.armed || g_timer.used[s] >= g_timer.cap) return;
-        int i = g_timer.used[s]++;
-        if (hipEventRecord(g_timer.ev[s][2 * i], st) != hipSuccess) return;
-        end_ev = g_timer.ev[s][2 * i + 1];
-    }
-    ~StageScope() {
-        if (end_ev) (void)hipEventRecord(end_ev, st);
-    }
-};
-
-}  // namespace
 
 prism_status prism_stage_timer_arm(int32_t cap) {
     REQUIRE(cap >= 0 && cap <= 1 << 16, "cap must be in [0, 65536]");

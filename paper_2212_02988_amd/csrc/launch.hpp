@@ -122,10 +122,12 @@ hipError_t launch_from_dense(const GridC& g, int dtype, void* map, const float* 
 hipError_t launch_to_dense(const GridC& g, int dtype, const void* map, float* mean4, float* var4,
                            hipStream_t st);
 hipError_t launch_planes(int n, int channels, const float* src, float* dst, int to_dense, hipStream_t st);
-// n_updated (nullable): total of updated voxels, by an extra one-wavefront kernel
+// n_updated (nullable): total of updated voxels, by an extra one-workgroup
+// kernel; t_begin / t_end (nullable): events recorded around the update kernel
 hipError_t launch_map_update(const GridC& g, const CamC& c, const GridD& gd, int dtype, void* map,
                              const prism_pose* pose, const float* depth, const float* rgb, double trunc, double lam_u,
-                             const MapAux& aux, int64_t* n_updated, hipStream_t st);
+                             const MapAux& aux, int64_t* n_updated, hipStream_t st, hipEvent_t t_begin = nullptr,
+                             hipEvent_t t_end = nullptr);
 // workgroups (and per-workgroup counts) of one update launch
 int map_update_groups(const GridC& g);
 

@@ -482,7 +482,8 @@ static int update_grid(const GridC& g) {
 
 hipError_t launch_map_update(const GridC& g, const CamC& c, const GridD& gd, int dtype, void* map,
                              const prism_pose* pose, const float* depth, const float* rgb, double trunc, double lam_u,
-                             const MapAux& aux, int64_t* n_updated, hipStream_t st) {
+                             const MapAux& aux, int64_t* n_updated, hipStream_t st, hipEvent_t t_begin,
+                             hipEvent_t t_end) {
     int nbricks = g.nb * g.nb * g.nb;
     int nseg = (nbricks + 255) / 256;
     k_cull<<<nseg, 256, 0, st>>>(g, c, pose, aux);
@@ -491,12 +492,15 @@ hipError_t launch_map_update(const GridC& g, const CamC& c, const GridD& gd, int
     MapUpdC mp{(float)trunc, trunc, lam_u};
     int ng = update_grid(g);
     size_t lds = (size_t)(nseg + 1) * sizeof(int);
+    if (t_begin && (e = hipEventRecord(t_begin, st)) != hipSuccess) return e;
     if (dtype == PRISM_BF16)
         k_map_update<uint16_t><<<ng, 256, lds, st>>>(g, c, gd, (uint16_t*)map, depth, rgb, mp, aux, nseg);
     else
         k_map_update<float><<<ng, 256, lds, st>>>(g, c, gd, (float*)map, depth, rgb, mp, aux, nseg);
     e = hipGetLastError();
-    if (e != hipSuccess || !n_updated) return e;
+    if (e != hipSuccess) return e;
+    if (t_end && (e = hipEventRecord(t_end, st)) != hipSuccess) return e;
+    if (!n_updated) return hipSuccess;
     k_sum_counts<<<1, 256, 0, st>>>(aux.counts, ng, n_updated);
     return hipGetLastError();
 }
