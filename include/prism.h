@@ -70,6 +70,10 @@ typedef int32_t prism_status;
 #define PRISM_FLAG_NO_VALID_PIXELS 1 /* an objective evaluation had no contributing pixel */
 #define PRISM_FLAG_CHOL_FALLBACK 2   /* a normal matrix was not positive definite: the
                                         pose kept the prior mean and covariance */
+#define PRISM_FLAG_PRIOR_NOT_PD 4    /* set with CHOL_FALLBACK when the predicted pose
+                                        covariance itself was not positive definite: the
+                                        whole state kept the predicted mean and joint
+                                        covariance, the Laplace average is unchanged */
 
 /* Objectives for the pose update. */
 #define PRISM_OBJ_P2 0 /* prediction-to-observation surrogate against the previous

@@ -474,6 +474,14 @@ def combine(pose_post: np.ndarray, S_pose: np.ndarray, prior_pose: np.ndarray, m
 # ---------------------------------------------------------------------------
 # the filter (Sec. 4.3)
 # ---------------------------------------------------------------------------
+def _is_pd(A: np.ndarray) -> bool:
+    try:
+        np.linalg.cholesky(A)
+        return True
+    except np.linalg.LinAlgError:
+        return False
+
+
 @dataclass
 class FilterState:
     t: np.ndarray
@@ -525,6 +533,16 @@ class Filter:
         # predict and split (App. E.1-E.2)
         xn, Pm = predict(dict(t=s.t, q=s.q, v=s.v, w=s.w), s.P, u, p)
         prior = np.concatenate([xn["t"], xn["q"]])
+        if not _is_pd(Pm[:6, :6]):
+            # the paper assumes a proper Gaussian belief; a predicted pose
+            # covariance that is not positive definite has no MAP problem,
+            # so the step keeps the prediction and still updates the map
+            s.t, s.q, s.v, s.w, s.P = xn["t"], xn["q"], xn["v"], xn["w"], Pm
+            s.last.update(neq=None, S_lap=None, prior=prior, prior_not_pd=True)
+            self._observe_and_anchor(prior, depth, rgb)
+            s.step += 1
+            return s
+        s.last["prior_not_pd"] = False
         Spp, D, Sv = split(Pm)
         Lp = np.linalg.inv(Spp)
         Lp = 0.5 * (Lp + Lp.T)

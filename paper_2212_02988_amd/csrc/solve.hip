@@ -380,7 +380,11 @@ __device__ __forceinline__ void predict_block(prism_filter_state* __restrict__ S
     if (threadIdx.x == 0) ok = chol<6>(L);
     __syncthreads();
     if (!ok) {
-        if (threadIdx.x == 0) S->flags |= PRISM_FLAG_CHOL_FALLBACK;
+        // the predicted pose block is not positive definite: the step keeps
+        // the predicted mean and joint covariance, and no pose objective is
+        // solved (the Gauss-Newton and Laplace kernels see the flag)
+        for (int e = threadIdx.x; e < 144; e += blockDim.x) S->P[e] = T2[e];
+        if (threadIdx.x == 0) S->flags |= PRISM_FLAG_CHOL_FALLBACK | PRISM_FLAG_PRIOR_NOT_PD;
         state_out(S, Sg);
         return;
     }
@@ -476,6 +480,20 @@ __device__ __forceinline__ void laplace_combine_block(prism_filter_state* __rest
     prism_filter_state* S = &Ls;
     sum_partials(partials, nblocks, red, neq);
     if (threadIdx.x < PRISM_NEQ) S->neq[threadIdx.x] = neq[threadIdx.x];
+    if (S->flags & PRISM_FLAG_PRIOR_NOT_PD) {
+        // predicted mean and covariance as they are (the covariance was
+        // written by the predict kernel); the Laplace EMA is left unchanged
+        if (threadIdx.x == 0) {
+            if (!(neq[28] > 0.0)) S->flags |= PRISM_FLAG_NO_VALID_PIXELS;
+            for (int i = 0; i < 3; ++i) { S->v[i] = S->vel_prior[i]; S->w[i] = S->vel_prior[3 + i]; }
+            S->iter = S->prior;
+            S->pose = S->prior;
+            S->anchor = S->prior;
+            S->step += 1;
+        }
+        state_out(S, Sg);
+        return;
+    }
     if (threadIdx.x == 0) {
         if (!(neq[28] > 0.0)) S->flags |= PRISM_FLAG_NO_VALID_PIXELS;
         double H[36], g[6];

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libprism.so")
 
 PRISM_F32, PRISM_BF16 = 0, 1
 OBJ_P2, OBJ_P1 = 0, 1
-FLAG_NO_VALID_PIXELS, FLAG_CHOL_FALLBACK = 1, 2
+FLAG_NO_VALID_PIXELS, FLAG_CHOL_FALLBACK, FLAG_PRIOR_NOT_PD = 1, 2, 4
 NEQ = 29
 
 

@@ -415,3 +415,69 @@ def test_filter_steps_match_oracle(objective):
         assert np.linalg.norm(vg - vo) <= 1e-4, i
         assert np.linalg.norm(Pg - Po) <= 1e-4 * np.linalg.norm(Po), (i, np.linalg.norm(Pg - Po) / np.linalg.norm(Po))
         assert abs(nu_g - nu_o) <= max(10, 1e-4 * nu_o), (i, nu_g, nu_o)
+
+
+def _degenerate_run(P0, frames):
+    """GPU filter and oracle filter stepped on the same frames; `frames` maps
+    a step index to a replacement (depth, rgb) pair."""
+    c = synth.trajectory_case(seed=4, n=64, width=80, height=60, n_samples=32, n_frames=3)
+    tr = c["traj"]
+    g = grid_of(c["scene"], 0)
+    f = P().Filter(g, cam_of(c["cam"]), P().FilterParams(objective=0))
+    f.map.init()
+    x0 = np.concatenate([tr.t[0], tr.q[0], tr.v[0], tr.w[0]])
+    f.reset(x0, P0)
+    og = orc.grid_from_scene(c["scene"])
+    mean = np.zeros((4, 64, 64, 64)); mean[0] = np.float32(-0.001)
+    of = orc.Filter(og, orc.cam_from(c["cam"]), orc.Params(objective="p2"),
+                    dict(t=tr.t[0], q=tr.q[0], v=tr.v[0], w=tr.w[0]), P0, mean, np.full_like(mean, 1e4))
+    out = []
+    for i in range(3):
+        d, rgb = frames.get(i, (c["depth"][i], c["rgb"][i]))
+        u = tr.u[i - 1] if i else None
+        f.step(t(d), t(rgb), t(u, torch.float64) if i else None)
+        of.step(d.astype(np.float64), rgb.astype(np.float64), u)
+        out.append((f.state(), of.s.t.copy(), of.s.q.copy(), np.concatenate([of.s.v, of.s.w]),
+                    of.s.P.copy(), of.s.last["n_updated"]))
+    return out
+
+
+def _state_close(s, to, qo, vo, Po, rel_P=1e-9):
+    assert np.linalg.norm(np.array(s.pose.t) - to) <= 1e-9
+    assert rot_angle(np.array(s.pose.q), qo) <= 1e-9
+    assert np.linalg.norm(np.concatenate([s.v, s.w]) - vo) <= 1e-9
+    Pg = np.array(s.P).reshape(12, 12)
+    assert np.linalg.norm(Pg - Po) <= rel_P * np.linalg.norm(Po)
+
+
+def test_filter_step_without_valid_pixels():
+    """A frame with no valid depth: the flag is raised, nothing is fused and
+    the state is the pure prediction, as in the oracle."""
+    banner("filter degenerate: zero depth frame")
+    c0 = synth.trajectory_case(seed=4, n=64, width=80, height=60, n_samples=32, n_frames=3)
+    zero = (np.zeros_like(c0["depth"][1]), c0["rgb"][1])
+    P0 = np.diag([1e-6] * 6 + [1e-4] * 6)
+    out = _degenerate_run(P0, {1: zero})
+    s, to, qo, vo, Po, nu_o = out[1]
+    print(f"flags {s.flags} n_updated {s.n_updated}", flush=True)
+    assert s.flags & P().FLAG_NO_VALID_PIXELS
+    assert not s.flags & P().FLAG_CHOL_FALLBACK
+    assert s.n_updated == 0 and nu_o == 0
+    _state_close(s, to, qo, vo, Po)
+    s, to, qo, vo, Po, nu_o = out[2]   # the next frame tracks again
+    assert s.flags == 0
+    assert abs(int(s.n_updated) - nu_o) <= 10
+
+
+def test_filter_step_with_improper_covariance():
+    """A state covariance whose predicted pose block is not positive definite:
+    the fallback flags are raised and the step keeps the predicted mean and
+    covariance while the map is still updated at that pose."""
+    banner("filter degenerate: P0 = -I")
+    out = _degenerate_run(-np.eye(12), {})
+    for i in (1, 2):
+        s, to, qo, vo, Po, nu_o = out[i]
+        print(f"step {i}: flags {s.flags} n_updated {s.n_updated} / {nu_o}", flush=True)
+        assert s.flags & P().FLAG_CHOL_FALLBACK and s.flags & P().FLAG_PRIOR_NOT_PD
+        _state_close(s, to, qo, vo, Po, rel_P=1e-12)
+        assert abs(int(s.n_updated) - nu_o) <= 10

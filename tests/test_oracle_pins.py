@@ -676,3 +676,54 @@ def test_filter_tracks_small_trajectory(orc):
         f.step(case["depth"][i], case["rgb"][i], tr.u[i - 1] if i else None)
         errs.append(np.linalg.norm(f.s.t - tr.t[i]))
     assert max(errs) < 0.05
+
+
+def _small_filter(orc, P0, n_frames=3):
+    case = synth.trajectory_case(seed=3, n=32, width=40, height=30, n_samples=16, n_frames=n_frames)
+    tr = case["traj"]
+    g = orc.grid_from_scene(case["scene"])
+    n = g.n
+    mean = np.zeros((4, n, n, n)); mean[0] = -0.001
+    var = np.full((4, n, n, n), 1e4)
+    x0 = dict(t=tr.t[0], q=tr.q[0], v=tr.v[0], w=tr.w[0])
+    f = orc.Filter(g, orc.cam_from(case["cam"]), orc.Params(), x0, P0, mean, var)
+    return case, tr, f
+
+
+def test_filter_without_data_is_pure_prediction(orc):
+    """A frame with no valid depth carries no likelihood: the MAP pose is the
+    prior mean, the Laplace covariance is the prior pose covariance, and the
+    product with the velocity conditional rebuilds the predicted joint
+    covariance exactly (Gaussian marginal/conditional identity)."""
+    P0 = np.diag([1e-6] * 6 + [1e-4] * 6)
+    case, tr, f = _small_filter(orc, P0)
+    f.step(case["depth"][0], case["rgb"][0], None)
+    s = f.s
+    xn, Pm = orc.predict(dict(t=s.t, q=s.q, v=s.v, w=s.w), s.P, tr.u[0], f.p)
+    mean_before = f.mean.copy()
+    f.step(np.zeros_like(case["depth"][1]), case["rgb"][1], tr.u[0])
+    assert f.s.last["n_updated"] == 0
+    assert np.array_equal(f.mean, mean_before)
+    assert np.all(f.s.last["neq"] == 0.0)
+    np.testing.assert_allclose(f.s.t, xn["t"], rtol=0, atol=1e-15)
+    assert orc.pose_error(f.s.pose, np.concatenate([xn["t"], xn["q"]])) == pytest.approx(np.zeros(6), abs=1e-15)
+    np.testing.assert_allclose(np.concatenate([f.s.v, f.s.w]), np.concatenate([xn["v"], xn["w"]]), atol=1e-15)
+    np.testing.assert_allclose(f.s.P, Pm, rtol=1e-9, atol=1e-18)
+
+
+def test_filter_keeps_prediction_for_improper_covariance(orc):
+    """A covariance whose predicted pose block is not positive definite
+    defines no MAP problem: the step keeps the transition mean and the
+    predicted covariance, and the map is still updated at that pose."""
+    case, tr, f = _small_filter(orc, -np.eye(12))
+    f.step(case["depth"][0], case["rgb"][0], None)
+    s = f.s
+    xn, Pm = orc.predict(dict(t=s.t, q=s.q, v=s.v, w=s.w), s.P, tr.u[0], f.p)
+    assert np.all(np.linalg.eigvalsh(Pm[:6, :6]) < 0)
+    f.step(case["depth"][1], case["rgb"][1], tr.u[0])
+    assert f.s.last["prior_not_pd"]
+    assert f.s.last["n_updated"] > 0
+    for k in "tqvw":
+        assert np.array_equal(getattr(f.s, k), xn[k])
+    assert np.array_equal(f.s.P, Pm)
+    assert np.array_equal(f.s.anchor_pose, np.concatenate([xn["t"], xn["q"]]))
