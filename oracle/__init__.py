@@ -23,6 +23,10 @@ map_update             App. D Gaussian product in precision form, App. G
                        update region, truncation and update scale
 render_vjp             adjoint of App. B's emission (App. B notes the
                        emission is differentiable)
+map_gd                 Sec. 4.3.1 alternative: the map-filter objective
+                       (emission likelihood times previous map belief)
+                       minimised by gradient descent through the renderer,
+                       as compared against the closed form in Sec. 5
 predict / split        App. E.1 linearised transition, E.2 closed-form
                        propagation and split into pose prior + velocity
                        conditional
@@ -33,9 +37,8 @@ combine                Sec. 4.3.2 product of pose posterior and velocity
 filter_step            Sec. 4.3 map filter then state filter ordering
 =====================  ===================================================
 
-Readings where the paper is silent or ambiguous are listed in the design doc's
-table of readings; the ones that change arithmetic are repeated next to the
-code they affect.
+Readings where the paper is silent or ambiguous are stated next to the code
+they affect.
 
 Parity status: every function above is pinned by a CPU test against a
 closed form, a brute force or finite differences, except ``filter_step`` as a
@@ -278,6 +281,52 @@ def render_vjp(grid: Grid, mean, cam: Cam, pose, g_depth, g_rgb, decide32: bool 
     lib.orc_render_vjp(ctypes.byref(g), _p(mean), ctypes.byref(c), _p(_f64(pose)), int(decide32),
                        _p(_f64(g_depth)), _p(_f64(g_rgb)), _p(gm), _p(gp))
     return gm, gp
+
+
+def map_gd_objective(grid: Grid, mean, mean0, var0, cam: Cam, pose, obs_depth, obs_rgb,
+                     params: Params, decide32: bool = True):
+    """Negative log of the map-filter target at the nominal pose (Sec. 4.3.1:
+    emission likelihood of the frame times the previous map belief), up to
+    constants:
+
+        E(mu) = sum over kept rows  w r(mu)^2  +  1/2 sum (mu - mu0)^2 / var0
+
+    The rows, weights and gates are those of the render-through objective
+    (Sec. 4.3.2, App. G): r = rendered - observed per valid ray with valid
+    observed depth.  Returns (E, dE/dmu) with the gradient through the
+    renderer's adjoint (first crossing held fixed)."""
+    rj = render_jacobian(grid, mean, cam, pose, obs_depth, obs_rgb, params, decide32)
+    r, rm = rj["resid"], rj["rowmask"]
+    g_depth = np.where(rm & 1, 2.0 / params.b_geo ** 2 * r[..., 0], 0.0)
+    g_rgb = np.where((rm & 2)[..., None] != 0, 2.0 / params.b_rgb ** 2 * r[..., 1:], 0.0)
+    g_data, _ = render_vjp(grid, mean, cam, pose, g_depth, g_rgb, decide32)
+    lam0 = 1.0 / var0
+    diff = mean - mean0
+    E = rj["neq"][27] + 0.5 * float(np.sum(lam0 * diff * diff))
+    return E, g_data + lam0 * diff
+
+
+def map_gd(grid: Grid, mean0: np.ndarray, var0: np.ndarray, cam: Cam, pose, obs_depth, obs_rgb,
+           params: Params, lr_occ: float, lr_rgb: float, n_iters: int, decide32: bool = True,
+           store32: bool = True):
+    """Map inference by plain gradient descent on map_gd_objective, starting
+    from the previous belief's means: mu <- mu - lr * dE/dmu, one step size
+    for occupancy and one for colour.  MAP descent estimates no variance: the
+    variances stay those of the previous belief.  With store32 the means are
+    rounded to single precision after every step, the storage precision of
+    an FP32 map.  Returns (means, [E before each step])."""
+    mean = _f64(mean0).copy()
+    mean0 = _f64(mean0)
+    var0 = _f64(var0)
+    lr = np.array([lr_occ, lr_rgb, lr_rgb, lr_rgb]).reshape(4, 1, 1, 1)
+    costs = []
+    for _ in range(n_iters):
+        E, g = map_gd_objective(grid, mean, mean0, var0, cam, pose, obs_depth, obs_rgb, params, decide32)
+        costs.append(E)
+        mean = mean - lr * g
+        if store32:
+            mean = mean.astype(np.float32).astype(np.float64)
+    return mean, costs
 
 
 # ---------------------------------------------------------------------------

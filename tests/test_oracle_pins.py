@@ -544,6 +544,98 @@ def test_render_vjp_pose_is_jacobian_transpose(orc):
 
 
 # ---------------------------------------------------------------------------
+# map inference by gradient descent through the renderer (Sec. 4.3.1, Sec. 5)
+# ---------------------------------------------------------------------------
+def _gd_case(orc, seed=0):
+    rng = np.random.default_rng(seed)
+    n, s = 12, 0.2
+    ax = (np.arange(n) + 0.5) * s
+    Z, Y, X = np.meshgrid(ax, ax, ax, indexing="ij")
+    mean0 = np.empty((4, n, n, n))
+    mean0[0] = 0.3 * np.sin(2.1 * X) + 0.25 * np.cos(1.7 * Y + 0.5 * Z) + 0.2 * Z - 0.2
+    mean0[1:] = rng.uniform(0, 1, size=(3, n, n, n))
+    var0 = rng.uniform(0.5, 2.0, size=(4, n, n, n))
+    pose = _pose(np.array([1.2, 1.1, 0.3]), _look_rot([0.1, 0.05, 1.0], up=(0, 1, 0)))
+    cam = orc.Cam(10, 8, 8.0, 8.0, 5.0, 4.0, 0.1, 1.9, 24)
+    g = orc.Grid(n, s)
+    ref = orc.render(g, mean0, cam, pose, decide32=False)
+    obs_d = np.where(ref["mask"] == 1, ref["depth"] + rng.normal(0, 0.05, ref["depth"].shape), 0.0)
+    obs_c = np.clip(ref["rgb"] + rng.normal(0, 0.05, ref["rgb"].shape), 0, 1)
+    return rng, g, cam, pose, mean0, var0, obs_d, obs_c
+
+
+def test_map_gd_gradient_finite_differences(orc):
+    """dE/dmu of the map-filter objective (data rows through the adjoint plus
+    the quadratic previous-belief term) against central differences of E,
+    at a point away from the previous mean so the prior term is live; rays
+    whose hit or kept rows change under the perturbation are skipped."""
+    rng, g, cam, pose, mean0, var0, obs_d, obs_c = _gd_case(orc)
+    p = orc.Params(gate_rgb=0.3)
+    mean = mean0 + rng.normal(0, 0.01, mean0.shape)
+    E, grad = orc.map_gd_objective(g, mean, mean0, var0, cam, pose, obs_d, obs_c, p, decide32=False)
+    rj = orc.render_jacobian(g, mean, cam, pose, obs_d, obs_c, p, decide32=False)
+    assert rj["neq"][28] > 30 and 0 < np.count_nonzero(rj["rowmask"] == 1) < rj["neq"][28]
+
+    def ev(mm):
+        e, _ = orc.map_gd_objective(g, mm, mean0, var0, cam, pose, obs_d, obs_c, p, decide32=False)
+        o = orc.render_jacobian(g, mm, cam, pose, obs_d, obs_c, p, decide32=False)
+        return e, (o["rowmask"].tobytes(), orc.render(g, mm, cam, pose, decide32=False)["hit_k"].tobytes())
+
+    eps = 1e-6
+    touched = np.argwhere(np.abs(grad - (mean - mean0) / var0).sum(0) > 1e-9)
+    assert len(touched) > 50
+    pick = touched[rng.choice(len(touched), size=30, replace=False)]
+    checked = 0
+    for (k, j, i) in pick:
+        for ch in range(4):
+            mp = mean.copy(); mp[ch, k, j, i] += eps
+            mq = mean.copy(); mq[ch, k, j, i] -= eps
+            ea, ka = ev(mp)
+            eb, kb = ev(mq)
+            if ka != kb:
+                continue
+            fd = (ea - eb) / (2 * eps)
+            assert abs(fd - grad[ch, k, j, i]) < 1e-5 * max(1.0, abs(grad[ch, k, j, i])), (ch, k, j, i)
+            checked += 1
+    assert checked > 80
+    # a voxel no ray touches: central differences of E see only the
+    # previous-belief term (mu - mu0) / var0
+    far = np.argwhere(np.abs(grad - (mean - mean0) / var0).sum(0) == 0)
+    assert len(far) > 100
+    for (k, j, i) in far[rng.choice(len(far), size=5, replace=False)]:
+        for ch in range(4):
+            mp = mean.copy(); mp[ch, k, j, i] += 1e-4
+            mq = mean.copy(); mq[ch, k, j, i] -= 1e-4
+            fd = (ev(mp)[0] - ev(mq)[0]) / 2e-4
+            exp = (mean[ch, k, j, i] - mean0[ch, k, j, i]) / var0[ch, k, j, i]
+            assert abs(fd - exp) < 1e-8 and abs(grad[ch, k, j, i] - exp) < 1e-15
+
+
+def test_map_gd_without_data_keeps_the_previous_belief(orc):
+    """No valid observed depth: the data term is empty and the previous mean
+    is the minimiser, so descent stays there with zero objective."""
+    _, g, cam, pose, mean0, var0, obs_d, obs_c = _gd_case(orc)
+    mean, costs = orc.map_gd(g, mean0.astype(np.float32), var0, cam, pose, np.zeros_like(obs_d), obs_c,
+                             orc.Params(), 0.01, 0.01, 3)
+    assert costs == [0.0, 0.0, 0.0]
+    assert np.array_equal(mean, mean0.astype(np.float32).astype(np.float64))
+
+
+def test_map_gd_descends(orc):
+    """With a small step the objective decreases at every step, and the
+    first decrease matches the first-order prediction lr * |grad|^2."""
+    _, g, cam, pose, mean0, var0, obs_d, obs_c = _gd_case(orc, seed=1)
+    p = orc.Params(gate_geo=10.0, gate_rgb=10.0)
+    lr_occ, lr_rgb = 2e-7, 1e-4
+    mean, costs = orc.map_gd(g, mean0, var0, cam, pose, obs_d, obs_c, p, lr_occ, lr_rgb, 5, decide32=False,
+                             store32=False)
+    assert all(b < a for a, b in zip(costs, costs[1:])), costs
+    _, g0 = orc.map_gd_objective(g, mean0, mean0, var0, cam, pose, obs_d, obs_c, p, decide32=False)
+    pred = lr_occ * float(np.sum(g0[0] ** 2)) + lr_rgb * float(np.sum(g0[1:] ** 2))
+    assert abs((costs[0] - costs[1]) - pred) < 0.05 * pred
+
+
+# ---------------------------------------------------------------------------
 # linear-Gaussian state filter (App. E)
 # ---------------------------------------------------------------------------
 def _transition_with_noise(orc, x, u, dt, n):
