@@ -284,6 +284,37 @@ prism_status prism_map_update(const prism_grid *grid, void *map, const prism_cam
                               int64_t *n_updated, hipStream_t stream);
 
 /* ------------------------------------------------------------------------ */
+/* Map inference by gradient descent (Sec. 4.3.1 alternative, Sec. 5)       */
+/* ------------------------------------------------------------------------ */
+/* The map-filter target of Sec. 4.3.1 (emission likelihood of one frame at
+ * the nominal pose times the previous map belief) minimised directly by
+ * gradient descent through the renderer, the alternative the paper compares
+ * the closed-form update against.  Objective, up to constants:
+ *   E(mean) = sum over kept rows w r^2 + 1/2 sum (mean - mean0)^2 / var
+ * with the rows, weights and gates of prism_render_jacobian (r = rendered -
+ * observed) and (mean0, var) the map on entry.  Each of n_iters steps renders
+ * at the current means, forms dE/dmean through the adjoint of the emission
+ * (first crossing held) and takes mean <- mean - lr dE/dmean, lr = lr_occ for
+ * occupancy and lr_rgb for colour.  Only bricks some ray touched move; the
+ * variances stay as they were (descent estimates none); the brick summary is
+ * kept current.  FP32 maps only.
+ *
+ * map:       device, updated in place (the previous belief on entry).
+ * pose:      device.  obs_depth [H][W], obs_rgb [H][W][3]: device float.
+ * cost:      nullable, device double [n_iters]: E at the means before each step.
+ * workspace: device, 256-byte aligned, >= prism_map_gd_workspace_bytes().
+ *            Its gradient accumulators must be zero on entry: zero-fill the
+ *            workspace once; every call that returns PRISM_OK leaves them
+ *            zero again.  Calls sharing a workspace must not overlap. */
+prism_status prism_map_gd_workspace_bytes(const prism_grid *grid, const prism_camera *cam,
+                                          size_t *bytes);
+prism_status prism_map_gd(const prism_grid *grid, void *map, const prism_camera *cam,
+                          const prism_pose *pose, const float *obs_depth, const float *obs_rgb,
+                          const prism_weights *w, double lr_occ, double lr_rgb, int32_t n_iters,
+                          double *cost, void *workspace, size_t workspace_bytes,
+                          hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
 /* Filter (Sec. 4.3; App. C, E)                                             */
 /* ------------------------------------------------------------------------ */
 typedef struct {

@@ -577,6 +577,79 @@ prism_status prism_map_update(const prism_grid* grid, void* map, const prism_cam
     return PRISM_OK;
 }
 
+// descent-mapping workspace: gradient accumulators (double), the means of
+// every stepped brick before the run, brick marks, cost partials
+struct GdLayout {
+    size_t grad, save, marks, saved, pd, pp, total;
+    int words;
+};
+
+GdLayout gd_layout(const prism_grid* g, const prism_camera* cam) {
+    GdLayout L;
+    size_t nvox = (size_t)g->n * g->n * g->n;
+    size_t nb3 = nvox / 512;
+    L.words = (int)((nb3 + 31) / 32);
+    L.grad = 0;
+    L.save = round_up(4 * nvox * sizeof(double), 256);
+    L.marks = L.save + round_up(4 * nvox * sizeof(float), 256);
+    L.saved = L.marks + round_up(4 * (size_t)L.words, 256);
+    L.pd = L.saved + round_up(4 * (size_t)L.words, 256);
+    L.pp = L.pd + round_up(sizeof(double) * (size_t)render_blocks(cam_c(cam)), 256);
+    L.total = L.pp + round_up(sizeof(double) * (size_t)gd_update_groups(grid_c(g)), 256);
+    return L;
+}
+
+prism_status prism_map_gd_workspace_bytes(const prism_grid* grid, const prism_camera* cam, size_t* bytes) {
+    prism_status s;
+    if ((s = check_grid(grid)) || (s = check_cam(cam))) return s;
+    REQUIRE(bytes, "bytes is NULL");
+    *bytes = gd_layout(grid, cam).total;
+    return PRISM_OK;
+}
+
+prism_status prism_map_gd(const prism_grid* grid, void* map, const prism_camera* cam, const prism_pose* pose,
+                          const float* obs_depth, const float* obs_rgb, const prism_weights* w, double lr_occ,
+                          double lr_rgb, int32_t n_iters, double* cost, void* workspace, size_t workspace_bytes,
+                          hipStream_t stream) {
+    prism_status s;
+    if ((s = check_grid(grid)) || (s = check_cam(cam)) || (s = check_weights(w))) return s;
+    if (grid->dtype != PRISM_F32) return fail(PRISM_UNSUPPORTED, "map_gd needs an FP32 map");
+    REQUIRE(map && aligned(map, 256), "map must be non-NULL and 256-byte aligned");
+    REQUIRE(pose && aligned(pose, 8), "pose must be non-NULL and 8-byte aligned");
+    REQUIRE(obs_depth && obs_rgb && aligned(obs_depth, 4) && aligned(obs_rgb, 4), "observations must be non-NULL, aligned");
+    REQUIRE(isfinite(lr_occ) && lr_occ >= 0 && isfinite(lr_rgb) && lr_rgb >= 0, "step sizes must be finite and >= 0");
+    REQUIRE(n_iters >= 0, "n_iters must be >= 0");
+    REQUIRE(!cost || aligned(cost, 8), "cost misaligned");
+    GdLayout L = gd_layout(grid, cam);
+    REQUIRE(workspace && aligned(workspace, 256) && workspace_bytes >= L.total,
+            "workspace must be 256-byte aligned and hold %zu bytes", L.total);
+    if (n_iters == 0) return PRISM_OK;
+    char* ws = (char*)workspace;
+    double* grad = (double*)(ws + L.grad);
+    float* save = (float*)(ws + L.save);
+    unsigned* marks = (unsigned*)(ws + L.marks);
+    unsigned* saved = (unsigned*)(ws + L.saved);
+    double* pd = (double*)(ws + L.pd);
+    double* pp = (double*)(ws + L.pp);
+    GridC g = grid_c(grid);
+    CamC c = cam_c(cam);
+    GridD gd = grid_d(grid);
+    CamD cd = cam_d(cam);
+    WeightsC wc = weights_c(w);
+    MapAux aux = map_aux(grid, map);
+    const unsigned* bits = skip_table(grid, cam, map);
+    HIP_TRY(launch_gd_clear(marks, L.words, stream));
+    HIP_TRY(launch_gd_clear(saved, L.words, stream));
+    for (int it = 0; it < n_iters; ++it) {
+        HIP_TRY(launch_gd_grad(g, c, gd, cd, (const float*)map, bits, pose, obs_depth, obs_rgb, wc, grad, marks, pd,
+                               stream));
+        HIP_TRY(launch_gd_update(g, (float*)map, aux, save, grad, marks, saved, lr_occ, lr_rgb, pp, stream));
+        if (cost)
+            HIP_TRY(launch_gd_cost(pd, render_blocks(c), pp, gd_update_groups(g), cost + it, stream));
+    }
+    return PRISM_OK;
+}
+
 prism_status prism_filter_bytes(const prism_filter_cfg* cfg, size_t* bytes) {
     prism_status s = check_cfg(cfg);
     if (s) return s;

@@ -131,6 +131,17 @@ hipError_t launch_map_update(const GridC& g, const CamC& c, const GridD& gd, int
 // workgroups (and per-workgroup counts) of one update launch
 int map_update_groups(const GridC& g);
 
+// descent mapping (gradient pass, step on marked bricks, cost total)
+hipError_t launch_gd_grad(const GridC& g, const CamC& c, const GridD& gd, const CamD& cd, const float* map,
+                          const unsigned* bits, const prism_pose* pose, const float* obs_depth, const float* obs_rgb,
+                          const WeightsC& w, double* grad, unsigned* marks, double* partials, hipStream_t st);
+hipError_t launch_gd_update(const GridC& g, float* map, const MapAux& aux, float* save, double* grad,
+                            const unsigned* marks, unsigned* saved, double lr_occ, double lr_rgb, double* partials,
+                            hipStream_t st);
+hipError_t launch_gd_cost(const double* pd, int nd, const double* pp, int np, double* cost, hipStream_t st);
+hipError_t launch_gd_clear(unsigned* words, int n, hipStream_t st);
+int gd_update_groups(const GridC& g);
+
 // frame staging: depth [npix] f32, rgb [3 npix] f32 and (if u) 6 f64 copied
 // into a serving slot in one kernel
 hipError_t launch_stage(const void* depth, const void* rgb, const void* u, float* d_out, float* c_out, double* u_out,

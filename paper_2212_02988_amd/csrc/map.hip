@@ -406,6 +406,116 @@ __global__ __launch_bounds__(256) void k_map_update_batch(BatchArgs b) {
                         (const float*)fr.rgb, D.mp, D.aux, D.nseg);
 }
 
+// ---------------------------------------------------------------------------
+// descent mapping: one gradient step on the marked bricks
+// ---------------------------------------------------------------------------
+// Every brick marked by the gradient pass of this run (marks) takes the step
+// mean <- mean - lr (grad + (mean - mean0) / var) per voxel and channel, with
+// mean0 the brick's means before the run's first step (copied into `save`
+// the first time the brick is seen, recorded in `saved`) and var the map's
+// variance, which descent leaves unchanged.  grad is cleared behind the step,
+// the brick summary and free-space bit follow the new occupancy means, and
+// each workgroup writes its share of the previous-belief term
+// 1/2 sum (mean - mean0)^2 / var at the means before the step.  Unmarked
+// bricks have zero gradient and means equal to mean0: the step leaves them as
+// they are.
+__global__ __launch_bounds__(256) void k_gd_update(GridC g, float* __restrict__ map, MapAux aux,
+                                                   float* __restrict__ save, double* __restrict__ grad,
+                                                   const unsigned* __restrict__ marks, unsigned* __restrict__ saved,
+                                                   double lr_occ, double lr_rgb, double* __restrict__ partials) {
+    __shared__ double wsum[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nbricks = g.nb * g.nb * g.nb;
+    double cost = 0.0;
+    for (int b = blockIdx.x * 4 + wv; b < nbricks; b += gridDim.x * 4) {
+        if (!((marks[b >> 5] >> (b & 31)) & 1u)) continue;
+        const bool first = !((saved[b >> 5] >> (b & 31)) & 1u);
+        float m = -INFINITY;
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+            const double lr = ch ? lr_rgb : lr_occ;
+#pragma unroll
+            for (int h = 0; h < 8; ++h) {
+                const long long id = ((long long)b << 9) | (h << 6) | lane;
+                const long long e = (long long)ch * g.nvox + id;
+                const float mu = map[e];
+                float mu0;
+                if (first) {
+                    save[e] = mu;
+                    mu0 = mu;
+                } else {
+                    mu0 = save[e];
+                }
+                const double lam = 1.0 / (double)map[(long long)(4 + ch) * g.nvox + id];
+                const double diff = (double)mu - (double)mu0;
+                cost += 0.5 * lam * diff * diff;
+                const float nm = (float)((double)mu - lr * (grad[e] + lam * diff));
+                map[e] = nm;
+                grad[e] = 0.0;
+                if (ch == 0) m = fmaxf(m, nm);
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+        if (lane == 0) {
+            bool was_free = aux.bmax[b] <= 0.0f, now_free = m <= 0.0f;
+            aux.bmax[b] = m;
+            if (was_free != now_free) atomicXor(&aux.bits[b >> 5], 1u << (b & 31));
+            if (first) atomicOr(&saved[b >> 5], 1u << (b & 31));
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) cost += __shfl_xor(cost, off, 64);
+    if (lane == 0) wsum[wv] = cost;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+}
+
+// cost[0] = sum of the data partials + sum of the previous-belief partials
+__global__ __launch_bounds__(256) void k_gd_cost(const double* __restrict__ pd, int nd,
+                                                 const double* __restrict__ pp, int np, double* __restrict__ cost) {
+    __shared__ double red[256];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < nd; i += 256) a += pd[i];
+    for (int i = threadIdx.x; i < np; i += 256) a += pp[i];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) cost[0] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_clear_words(unsigned* __restrict__ w, int n) {
+    int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) w[i] = 0u;
+}
+
+int gd_update_groups(const GridC& g) {
+    int nbricks = g.nb * g.nb * g.nb;
+    int groups = (nbricks + 3) / 4;
+    return groups < kUpdateGrid ? groups : kUpdateGrid;
+}
+
+hipError_t launch_gd_clear(unsigned* words, int n, hipStream_t st) {
+    k_clear_words<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(words, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_gd_update(const GridC& g, float* map, const MapAux& aux, float* save, double* grad,
+                            const unsigned* marks, unsigned* saved, double lr_occ, double lr_rgb, double* partials,
+                            hipStream_t st) {
+    k_gd_update<<<gd_update_groups(g), 256, 0, st>>>(g, map, aux, save, grad, marks, saved, lr_occ, lr_rgb,
+                                                     partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_gd_cost(const double* pd, int nd, const double* pp, int np, double* cost, hipStream_t st) {
+    k_gd_cost<<<1, 256, 0, st>>>(pd, nd, pp, np, cost);
+    return hipGetLastError();
+}
+
 // n_updated = sum of the per-workgroup counts of the last update
 __global__ __launch_bounds__(256) void k_sum_counts(const int* __restrict__ counts, int ngroups,
                                                     int64_t* __restrict__ n_updated) {

@@ -688,6 +688,106 @@ __global__ __launch_bounds__(256) void k_render_vjp(GridC g, CamC c, GridD gd, C
 }
 
 // ---------------------------------------------------------------------------
+// gradient of the map-filter objective w.r.t. the map means (descent mapping)
+// ---------------------------------------------------------------------------
+// Adds coef * (trilinear weight) to plane[corner] for the 8 corners of the
+// cell that lie inside the grid.
+__device__ __forceinline__ void scatter_cell(const GridC& g, double* __restrict__ plane, const Cell& cl,
+                                             const float w[3], double coef) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
+        const int i = cl.i[0] + dx, j = cl.i[1] + dy, k = cl.i[2] + dz;
+        if ((unsigned)i >= (unsigned)g.n || (unsigned)j >= (unsigned)g.n || (unsigned)k >= (unsigned)g.n) continue;
+        const double hw = (double)(dx ? w[0] : 1.0f - w[0]) * (double)(dy ? w[1] : 1.0f - w[1]) *
+                          (double)(dz ? w[2] : 1.0f - w[2]);
+        unsafeAtomicAdd(plane + vidx(g, i, j, k), coef * hw);
+    }
+}
+
+// Sets the bit of every brick holding an in-grid corner of the cell.
+__device__ __forceinline__ void mark_cell(const GridC& g, unsigned* __restrict__ marks, const Cell& cl) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int i = cl.i[0] + (q & 1), j = cl.i[1] + ((q >> 1) & 1), k = cl.i[2] + (q >> 2);
+        if ((unsigned)i >= (unsigned)g.n || (unsigned)j >= (unsigned)g.n || (unsigned)k >= (unsigned)g.n) continue;
+        const int b = ((k >> 3) * g.nb + (j >> 3)) * g.nb + (i >> 3);
+        const unsigned bit = 1u << (b & 31);
+        if (!(marks[b >> 5] & bit)) atomicOr(marks + (b >> 5), bit);
+    }
+}
+
+// One frame's rows of the map-filter objective at the current means: the
+// render-through rows (same validity, gates and weights as the P1 objective)
+// give the cost sum w r^2 (per-workgroup partial) and, through the adjoint of
+// the emission with the first crossing held, dE/dmean = sum 2 w r d(out)/dmean
+// accumulated in double precision into grad [4][n^3] (brick order).  The
+// bricks whose voxels receive a contribution are marked.
+__global__ __launch_bounds__(256) void k_gd_grad(GridC g, CamC c, GridD gd, CamD cd, const float* __restrict__ map,
+                                                 const unsigned* __restrict__ gbits,
+                                                 const prism_pose* __restrict__ pose,
+                                                 const float* __restrict__ obs_depth,
+                                                 const float* __restrict__ obs_rgb, WeightsC wt,
+                                                 double* __restrict__ grad, unsigned* __restrict__ marks,
+                                                 double* __restrict__ partials) {
+    __shared__ BlockPose sp;
+    __shared__ double wsum[4];
+    extern __shared__ unsigned lbits[];
+    const unsigned* bits = block_bits(g, gbits, lbits);
+    const BlockPose& P = block_pose(pose, &sp);
+    int u, v, s;
+    quad_pixel(c, blockIdx.x, u, v, s);
+    double cost = 0.0;
+    if (u < c.W && v < c.H) {
+        float dir[3];
+        ray_dir32(c, P.f, u, v, dir);
+        const int k = march_quad(g, c, P.f, dir, map, bits, s);
+        const long long pix = (long long)v * c.W + u;
+        const float D = obs_depth[pix];
+        if (k >= 1 && depth_ok(D)) {   // the same for the four lanes of a ray
+            const Cell c0 = sample_cell(g, c, P.f, dir, k - 1), c1 = sample_cell(g, c, P.f, dir, k);
+            const QuadShade q = shade_quad(g, gd, cd, P.d, u, v, map, c0, c1, k, s);
+            const double r = s == 0 ? q.value - (double)D : q.value - (double)obs_rgb[3 * pix + s - 1];
+            double l1 = s == 0 ? 0.0 : fabs(r);
+            l1 += __shfl_xor(l1, 1, 64);
+            l1 += __shfl_xor(l1, 2, 64);
+            const bool use_depth = fabs(quad_bcast(r, 0)) <= wt.gate_depth;
+            const bool use_rgb = l1 <= wt.gate_rgb;
+            const bool keep = s == 0 ? use_depth : use_rgb;
+            const double w = s == 0 ? wt.w_depth : wt.w_rgb;
+            const double gout = keep ? 2.0 * w * r : 0.0;   // dE / d(this lane's output)
+            if (keep) cost = w * r * r;
+            // every output depends on the two occupancies through alpha
+            const double d0 = cd.dn + (double)(k - 1) * cd.step, d1 = cd.dn + (double)k * cd.step;
+            double ga = gout * (s == 0 ? d1 - d0 : q.v1 - q.v0);
+            ga += __shfl_xor(ga, 1, 64);
+            ga += __shfl_xor(ga, 2, 64);
+            const double inv_den = 1.0 / (q.f1 - q.f0);
+            double k0, k1;   // coefficients of this lane's plane at the cells of samples k*-1, k*
+            if (s == 0) {
+                k0 = -ga * (1.0 - q.alpha) * inv_den;
+                k1 = -ga * q.alpha * inv_den;
+            } else {
+                k0 = gout * (1.0 - q.alpha);
+                k1 = gout * q.alpha;
+            }
+            double* plane = grad + (long long)s * g.nvox;
+            if (k0 != 0.0) scatter_cell(g, plane, c0, q.w0, k0);
+            if (k1 != 0.0) scatter_cell(g, plane, c1, q.w1, k1);
+            if (use_depth || use_rgb) {
+                if (s == 1) mark_cell(g, marks, c0);
+                if (s == 2) mark_cell(g, marks, c1);
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) cost += __shfl_xor(cost, off, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = cost;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 int render_blocks(const CamC& c) { return ((c.W + 7) >> 3) * ((c.H + 7) >> 3); }
@@ -750,6 +850,14 @@ hipError_t launch_render_jac(const GridC& g, const CamC& c, const GridD& gd, con
     else
         k_render_jac<float><<<grid, 256, lds, st>>>(g, c, gd, cd, (const float*)map, bits, poses, obs_depth, obs_rgb,
                                                     w, depth, rgb, mask, J, resid, rowmask, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_gd_grad(const GridC& g, const CamC& c, const GridD& gd, const CamD& cd, const float* map,
+                          const unsigned* bits, const prism_pose* pose, const float* obs_depth, const float* obs_rgb,
+                          const WeightsC& w, double* grad, unsigned* marks, double* partials, hipStream_t st) {
+    k_gd_grad<<<render_blocks(c), 256, bits_lds(g, bits), st>>>(g, c, gd, cd, map, bits, pose, obs_depth, obs_rgb, w,
+                                                                grad, marks, partials);
     return hipGetLastError();
 }
 

@@ -121,6 +121,9 @@ _SIGS = {
     "prism_render_vjp": (["p", "p", "p", "p", ctypes.c_int32, "p", "p", "p", "p", "p", "p", ctypes.c_size_t,
                           "p"], None),
     "prism_map_update": (["p", "p", "p", "p", "p", "p", "p", "p", "p"], None),
+    "prism_map_gd_workspace_bytes": (["p", "p", "p"], None),
+    "prism_map_gd": (["p", "p", "p", "p", "p", "p", "p", ctypes.c_double, ctypes.c_double, ctypes.c_int32, "p",
+                      "p", ctypes.c_size_t, "p"], None),
     "prism_filter_bytes": (["p", "p"], None),
     "prism_filter_create": (["p", "p", "p", "p"], None),
     "prism_filter_destroy": (["p"], None),
@@ -385,6 +388,34 @@ def render_vjp(grid: Grid, vmap: VoxelMap, cam: Camera, poses: torch.Tensor, hit
                                   _ptr(g_rgb), _ptr(grad_mean), _ptr(grad_pose), _ptr(ws), ws.numel(),
                                   _stream(stream)))
     return grad_mean, grad_pose
+
+
+def map_gd_workspace(grid: Grid, cam: Camera, device="cuda") -> torch.Tensor:
+    """A zero-filled workspace for map_gd (reusable across calls that do not
+    overlap)."""
+    b = ctypes.c_size_t()
+    _check(lib().prism_map_gd_workspace_bytes(_by(grid), _by(cam), _by(b)))
+    return torch.zeros(b.value, dtype=torch.uint8, device=device)
+
+
+def map_gd(grid: Grid, vmap: VoxelMap, cam: Camera, pose: torch.Tensor, obs_depth: torch.Tensor,
+           obs_rgb: torch.Tensor, weights: Weights, lr_occ: float, lr_rgb: float, n_iters: int,
+           ws: torch.Tensor, cost: Optional[torch.Tensor] = None, stream=None) -> Optional[torch.Tensor]:
+    """Map inference by gradient descent through the renderer, in place on
+    vmap (FP32): n_iters steps on the map-filter objective of one frame.
+    Returns the objective before each step when `cost` (float64 [n_iters])
+    is given."""
+    H, W = cam.height, cam.width
+    _dev(pose, torch.float64, "pose", (1, 7))
+    _dev(obs_depth, torch.float32, "obs_depth", (H, W))
+    _dev(obs_rgb, torch.float32, "obs_rgb", (H, W, 3))
+    _dev(ws, torch.uint8, "ws")
+    if cost is not None:
+        _dev(cost, torch.float64, "cost", (n_iters,))
+    _check(lib().prism_map_gd(_by(grid), _ptr(vmap.buf), _by(cam), _ptr(pose), _ptr(obs_depth), _ptr(obs_rgb),
+                              _by(weights), float(lr_occ), float(lr_rgb), int(n_iters), _ptr(cost), _ptr(ws),
+                              ws.numel(), _stream(stream)))
+    return cost
 
 
 def map_update(grid: Grid, vmap: VoxelMap, cam: Camera, pose: torch.Tensor, obs_depth: torch.Tensor,

@@ -481,3 +481,112 @@ def test_filter_step_with_improper_covariance():
         assert s.flags & P().FLAG_CHOL_FALLBACK and s.flags & P().FLAG_PRIOR_NOT_PD
         _state_close(s, to, qo, vo, Po, rel_P=1e-12)
         assert abs(int(s.n_updated) - nu_o) <= 10
+
+
+# ---------------------------------------------------------------------------
+# map inference by gradient descent through the renderer
+# ---------------------------------------------------------------------------
+def _gd_inputs(seed=5):
+    c = synth.trajectory_case(seed=2, n=64, width=80, height=60, n_samples=32, n_frames=1)
+    mean, _ = synth.gt_map(c["scene"])
+    rng = np.random.default_rng(seed)
+    m0 = np.asarray(mean, np.float32)
+    m0 = (m0 + np.concatenate([rng.normal(0, 0.01, (1,) + m0.shape[1:]),
+                               rng.normal(0, 0.05, (3,) + m0.shape[1:])]).astype(np.float32)).astype(np.float32)
+    v0 = rng.uniform(0.5, 2.0, m0.shape).astype(np.float32)
+    tr = c["traj"]
+    pose = np.concatenate([tr.t[0], tr.q[0]])
+    return c, m0, v0, pose
+
+
+def test_map_gd_matches_oracle():
+    """Descent mapping against the oracle: objective before every step, the
+    means after the first step (same decisions on both sides) and after three
+    (the first crossings of the second and third renders may differ on rays
+    whose occupancy lands within rounding of tau)."""
+    banner("map_gd 64^3 80x60, 3 steps")
+    c, m0, v0, pose = _gd_inputs()
+    g = grid_of(c["scene"], 0)
+    cam = cam_of(c["cam"])
+    og, oc = orc.grid_from_scene(c["scene"]), orc.cam_from(c["cam"])
+    p = orc.Params()
+    w = P().Weights.make(p.b_geo, p.b_rgb, p.gate_geo, p.gate_rgb)
+    lro, lrc = 3e-6, 3e-3
+    D, C, pt = t(c["depth"][0]), t(c["rgb"][0]), P().poses_tensor(pose)
+    ws = P().map_gd_workspace(g, cam)
+    prior = gpu_map(g, m0, v0)
+    ref1, cost1 = orc.map_gd(og, m0.astype(np.float64), v0.astype(np.float64), oc, pose, c["depth"][0],
+                             c["rgb"][0], p, lro, lrc, 1)
+    ref3, cost3 = orc.map_gd(og, m0.astype(np.float64), v0.astype(np.float64), oc, pose, c["depth"][0],
+                             c["rgb"][0], p, lro, lrc, 3)
+    tol = lambda b: 1e-6 * np.maximum(np.abs(b), 1e-2)
+    for n_iters, ref, rcost in ((1, ref1, cost1), (3, ref3, cost3)):
+        vm = P().VoxelMap(g)
+        vm.buf.copy_(prior.buf)
+        cost = torch.zeros(n_iters, dtype=torch.float64, device=DEV)
+        P().map_gd(g, vm, cam, pt, D, C, w, lro, lrc, n_iters, ws, cost)
+        torch.cuda.synchronize()
+        mg, vg = vm.to_dense()
+        mg, vg = mg.cpu().numpy().astype(np.float64), vg.cpu().numpy()
+        cg = cost.cpu().numpy()
+        print(f"{n_iters} steps: cost gpu {cg} oracle {np.array(rcost)}", flush=True)
+        np.testing.assert_allclose(cg, rcost, rtol=1e-5)
+        assert np.array_equal(vg, v0), "descent must leave the variances"
+        bad = np.abs(mg - ref) > tol(ref)
+        moved = np.count_nonzero(ref != m0)
+        print(f"  voxels moved {moved}, outside tolerance {bad.sum()}, max err {np.abs(mg - ref).max():.3e}",
+              flush=True)
+        assert moved > 10000
+        if n_iters == 1:
+            assert not bad.any()
+        else:
+            assert bad.sum() <= 1e-3 * moved
+        # untouched voxels keep their exact values
+        same = ref == m0
+        assert np.array_equal(mg[same & ~bad], m0.astype(np.float64)[same & ~bad])
+        # the gradient accumulators are left zero, the brick summary current
+        nv = g.n ** 3
+        assert not ws[:4 * nv * 8].view(torch.float64).any()
+        vr = P().VoxelMap(g)
+        vr.buf.copy_(vm.buf)
+        vr.refresh()
+        torch.cuda.synchronize()
+        assert torch.equal(vr.buf, vm.buf), "brick summary not maintained"
+
+
+def test_map_gd_edge_cases():
+    """Zero steps and a frame without valid depth leave the map bitwise as it
+    was (objective 0 at the previous means); repeated calls through one
+    workspace agree bit for bit; BF16 maps are refused."""
+    banner("map_gd edge cases")
+    c, m0, v0, pose = _gd_inputs(seed=6)
+    g = grid_of(c["scene"], 0)
+    cam = cam_of(c["cam"])
+    w = P().Weights.make()
+    pt = P().poses_tensor(pose)
+    ws = P().map_gd_workspace(g, cam)
+    prior = gpu_map(g, m0, v0)
+    vm = P().VoxelMap(g)
+    vm.buf.copy_(prior.buf)
+    P().map_gd(g, vm, cam, pt, t(c["depth"][0]), t(c["rgb"][0]), w, 1e-6, 1e-3, 0, ws)
+    cost = torch.full((2,), -1.0, dtype=torch.float64, device=DEV)
+    P().map_gd(g, vm, cam, pt, t(np.zeros_like(c["depth"][0])), t(c["rgb"][0]), w, 1e-6, 1e-3, 2, ws, cost)
+    torch.cuda.synchronize()
+    assert torch.equal(vm.buf[:8 * g.n ** 3 * 4], prior.buf[:8 * g.n ** 3 * 4])
+    assert cost.cpu().tolist() == [0.0, 0.0]
+    outs = []
+    for _ in range(2):
+        vm.buf.copy_(prior.buf)
+        P().map_gd(g, vm, cam, pt, t(c["depth"][0]), t(c["rgb"][0]), w, 3e-6, 3e-3, 2, ws)
+        outs.append(vm.to_dense()[0].clone())
+    torch.cuda.synchronize()
+    # double-precision accumulation makes the order of the atomic adds
+    # invisible in all but (in principle) a handful of roundings
+    ndiff = int((outs[0] != outs[1]).sum())
+    print(f"repeat: {ndiff} voxel values differ", flush=True)
+    assert ndiff <= 4
+    gb = grid_of(c["scene"], 1)
+    vb = gpu_map(gb, m0, v0)
+    with pytest.raises(P().PrismError, match="FP32"):
+        P().map_gd(gb, vb, cam, pt, t(c["depth"][0]), t(c["rgb"][0]), w, 1e-6, 1e-3, 1,
+                   P().map_gd_workspace(gb, cam))
