@@ -580,7 +580,7 @@ prism_status prism_map_update(const prism_grid* grid, void* map, const prism_cam
 // descent-mapping workspace: gradient accumulators (double), the means of
 // every stepped brick before the run, brick marks, cost partials
 struct GdLayout {
-    size_t grad, save, marks, saved, pd, pp, total;
+    size_t grad, save, marks, saved, list, pd, pp, total;
     int words;
 };
 
@@ -593,7 +593,8 @@ GdLayout gd_layout(const prism_grid* g, const prism_camera* cam) {
     L.save = round_up(4 * nvox * sizeof(double), 256);
     L.marks = L.save + round_up(4 * nvox * sizeof(float), 256);
     L.saved = L.marks + round_up(4 * (size_t)L.words, 256);
-    L.pd = L.saved + round_up(4 * (size_t)L.words, 256);
+    L.list = L.saved + round_up(4 * (size_t)L.words, 256);
+    L.pd = L.list + round_up(4 * (nb3 + 1), 256);
     L.pp = L.pd + round_up(sizeof(double) * (size_t)render_blocks(cam_c(cam)), 256);
     L.total = L.pp + round_up(sizeof(double) * (size_t)gd_update_groups(grid_c(g)), 256);
     return L;
@@ -629,6 +630,7 @@ prism_status prism_map_gd(const prism_grid* grid, void* map, const prism_camera*
     float* save = (float*)(ws + L.save);
     unsigned* marks = (unsigned*)(ws + L.marks);
     unsigned* saved = (unsigned*)(ws + L.saved);
+    int* list = (int*)(ws + L.list);
     double* pd = (double*)(ws + L.pd);
     double* pp = (double*)(ws + L.pp);
     GridC g = grid_c(grid);
@@ -640,10 +642,11 @@ prism_status prism_map_gd(const prism_grid* grid, void* map, const prism_camera*
     const unsigned* bits = skip_table(grid, cam, map);
     HIP_TRY(launch_gd_clear(marks, L.words, stream));
     HIP_TRY(launch_gd_clear(saved, L.words, stream));
+    HIP_TRY(launch_gd_clear((unsigned*)list, 1, stream));
     for (int it = 0; it < n_iters; ++it) {
-        HIP_TRY(launch_gd_grad(g, c, gd, cd, (const float*)map, bits, pose, obs_depth, obs_rgb, wc, grad, marks, pd,
-                               stream));
-        HIP_TRY(launch_gd_update(g, (float*)map, aux, save, grad, marks, saved, lr_occ, lr_rgb, pp, stream));
+        HIP_TRY(launch_gd_grad(g, c, gd, cd, (const float*)map, bits, pose, obs_depth, obs_rgb, wc, grad, marks, list,
+                               pd, stream));
+        HIP_TRY(launch_gd_update(g, (float*)map, aux, save, grad, list, saved, lr_occ, lr_rgb, pp, stream));
         if (cost)
             HIP_TRY(launch_gd_cost(pd, render_blocks(c), pp, gd_update_groups(g), cost + it, stream));
     }

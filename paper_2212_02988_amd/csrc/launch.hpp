@@ -132,11 +132,13 @@ hipError_t launch_map_update(const GridC& g, const CamC& c, const GridD& gd, int
 int map_update_groups(const GridC& g);
 
 // descent mapping (gradient pass, step on marked bricks, cost total)
+// list: [0] number of bricks, then the bricks, in the order first touched
 hipError_t launch_gd_grad(const GridC& g, const CamC& c, const GridD& gd, const CamD& cd, const float* map,
                           const unsigned* bits, const prism_pose* pose, const float* obs_depth, const float* obs_rgb,
-                          const WeightsC& w, double* grad, unsigned* marks, double* partials, hipStream_t st);
+                          const WeightsC& w, double* grad, unsigned* marks, int* list, double* partials,
+                          hipStream_t st);
 hipError_t launch_gd_update(const GridC& g, float* map, const MapAux& aux, float* save, double* grad,
-                            const unsigned* marks, unsigned* saved, double lr_occ, double lr_rgb, double* partials,
+                            const int* list, unsigned* saved, double lr_occ, double lr_rgb, double* partials,
                             hipStream_t st);
 hipError_t launch_gd_cost(const double* pd, int nd, const double* pp, int np, double* cost, hipStream_t st);
 hipError_t launch_gd_clear(unsigned* words, int n, hipStream_t st);

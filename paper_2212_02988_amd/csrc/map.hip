@@ -409,60 +409,74 @@ __global__ __launch_bounds__(256) void k_map_update_batch(BatchArgs b) {
 // ---------------------------------------------------------------------------
 // descent mapping: one gradient step on the marked bricks
 // ---------------------------------------------------------------------------
-// Every brick marked by the gradient pass of this run (marks) takes the step
-// mean <- mean - lr (grad + (mean - mean0) / var) per voxel and channel, with
-// mean0 the brick's means before the run's first step (copied into `save`
-// the first time the brick is seen, recorded in `saved`) and var the map's
-// variance, which descent leaves unchanged.  grad is cleared behind the step,
-// the brick summary and free-space bit follow the new occupancy means, and
-// each workgroup writes its share of the previous-belief term
-// 1/2 sum (mean - mean0)^2 / var at the means before the step.  Unmarked
-// bricks have zero gradient and means equal to mean0: the step leaves them as
-// they are.
+// Every brick on the run's list (bricks some ray of some gradient pass
+// touched; count first) takes the step mean <- mean - lr (grad + (mean -
+// mean0) / var) per voxel and channel, with mean0 the brick's means before the
+// run's first step (copied into `save` the first time the brick is visited,
+// recorded in `saved`) and var the map's variance, which descent leaves
+// unchanged.  One workgroup per brick, two voxels per thread, all four
+// channels.  grad is cleared behind the step, the brick summary and
+// free-space bit follow the new occupancy means, and each workgroup writes its
+// share of the previous-belief term 1/2 sum (mean - mean0)^2 / var at the
+// means before the step.  Bricks off the list have zero gradient and means
+// equal to mean0: the step leaves them as they are.
 __global__ __launch_bounds__(256) void k_gd_update(GridC g, float* __restrict__ map, MapAux aux,
                                                    float* __restrict__ save, double* __restrict__ grad,
-                                                   const unsigned* __restrict__ marks, unsigned* __restrict__ saved,
+                                                   const int* __restrict__ list, unsigned* __restrict__ saved,
                                                    double lr_occ, double lr_rgb, double* __restrict__ partials) {
     __shared__ double wsum[4];
+    __shared__ float wmax[4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int nbricks = g.nb * g.nb * g.nb;
+    const int count = list[0];
     double cost = 0.0;
-    for (int b = blockIdx.x * 4 + wv; b < nbricks; b += gridDim.x * 4) {
-        if (!((marks[b >> 5] >> (b & 31)) & 1u)) continue;
+    for (int e = blockIdx.x; e < count; e += gridDim.x) {
+        const int b = list[1 + e];
         const bool first = !((saved[b >> 5] >> (b & 31)) & 1u);
+        float mu[4][2], mu0[4][2], var[4][2];
+        double gr[4][2];
+        const long long id0 = ((long long)b << 9) | threadIdx.x;
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const long long e2 = (long long)ch * g.nvox + id0 + 256 * h;
+                mu[ch][h] = map[e2];
+                var[ch][h] = map[(long long)(4 + ch) * g.nvox + id0 + 256 * h];
+                gr[ch][h] = grad[e2];
+                if (!first) mu0[ch][h] = save[e2];
+            }
         float m = -INFINITY;
 #pragma unroll
         for (int ch = 0; ch < 4; ++ch) {
             const double lr = ch ? lr_rgb : lr_occ;
 #pragma unroll
-            for (int h = 0; h < 8; ++h) {
-                const long long id = ((long long)b << 9) | (h << 6) | lane;
-                const long long e = (long long)ch * g.nvox + id;
-                const float mu = map[e];
-                float mu0;
+            for (int h = 0; h < 2; ++h) {
+                const long long e2 = (long long)ch * g.nvox + id0 + 256 * h;
                 if (first) {
-                    save[e] = mu;
-                    mu0 = mu;
-                } else {
-                    mu0 = save[e];
+                    save[e2] = mu[ch][h];
+                    mu0[ch][h] = mu[ch][h];
                 }
-                const double lam = 1.0 / (double)map[(long long)(4 + ch) * g.nvox + id];
-                const double diff = (double)mu - (double)mu0;
+                const double lam = 1.0 / (double)var[ch][h];
+                const double diff = (double)mu[ch][h] - (double)mu0[ch][h];
                 cost += 0.5 * lam * diff * diff;
-                const float nm = (float)((double)mu - lr * (grad[e] + lam * diff));
-                map[e] = nm;
-                grad[e] = 0.0;
+                const float nm = (float)((double)mu[ch][h] - lr * (gr[ch][h] + lam * diff));
+                map[e2] = nm;
+                grad[e2] = 0.0;
                 if (ch == 0) m = fmaxf(m, nm);
             }
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
-        if (lane == 0) {
-            bool was_free = aux.bmax[b] <= 0.0f, now_free = m <= 0.0f;
-            aux.bmax[b] = m;
+        if (lane == 0) wmax[wv] = m;
+        __syncthreads();   // every thread has read `saved` and its values
+        if (threadIdx.x == 0) {
+            const float mb = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+            bool was_free = aux.bmax[b] <= 0.0f, now_free = mb <= 0.0f;
+            aux.bmax[b] = mb;
             if (was_free != now_free) atomicXor(&aux.bits[b >> 5], 1u << (b & 31));
             if (first) atomicOr(&saved[b >> 5], 1u << (b & 31));
         }
+        __syncthreads();   // wmax is reused by the next brick
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) cost += __shfl_xor(cost, off, 64);
@@ -494,8 +508,7 @@ __global__ __launch_bounds__(256) void k_clear_words(unsigned* __restrict__ w, i
 
 int gd_update_groups(const GridC& g) {
     int nbricks = g.nb * g.nb * g.nb;
-    int groups = (nbricks + 3) / 4;
-    return groups < kUpdateGrid ? groups : kUpdateGrid;
+    return nbricks < kUpdateGrid ? nbricks : kUpdateGrid;
 }
 
 hipError_t launch_gd_clear(unsigned* words, int n, hipStream_t st) {
@@ -504,9 +517,9 @@ hipError_t launch_gd_clear(unsigned* words, int n, hipStream_t st) {
 }
 
 hipError_t launch_gd_update(const GridC& g, float* map, const MapAux& aux, float* save, double* grad,
-                            const unsigned* marks, unsigned* saved, double lr_occ, double lr_rgb, double* partials,
+                            const int* list, unsigned* saved, double lr_occ, double lr_rgb, double* partials,
                             hipStream_t st) {
-    k_gd_update<<<gd_update_groups(g), 256, 0, st>>>(g, map, aux, save, grad, marks, saved, lr_occ, lr_rgb,
+    k_gd_update<<<gd_update_groups(g), 256, 0, st>>>(g, map, aux, save, grad, list, saved, lr_occ, lr_rgb,
                                                      partials);
     return hipGetLastError();
 }

@@ -690,10 +690,53 @@ __global__ __launch_bounds__(256) void k_render_vjp(GridC g, CamC c, GridD gd, C
 // ---------------------------------------------------------------------------
 // gradient of the map-filter objective w.r.t. the map means (descent mapping)
 // ---------------------------------------------------------------------------
-// Adds coef * (trilinear weight) to plane[corner] for the 8 corners of the
-// cell that lie inside the grid.
-__device__ __forceinline__ void scatter_cell(const GridC& g, double* __restrict__ plane, const Cell& cl,
-                                             const float w[3], double coef) {
+// Per-workgroup accumulation table: the rays of an 8x8 tile touch a few
+// hundred distinct (plane, voxel) pairs through thousands of trilinear
+// corner contributions, so the contributions are summed in LDS first and each
+// distinct pair costs one global atomic.  Open addressing on the voxel index
+// (brick order) per plane; a contribution that finds no slot within a few
+// probes goes straight to global memory.
+constexpr int kAggSlots = 512;   // per plane (power of two)
+constexpr int kAggProbes = 8;
+
+struct GdAgg {
+    int key[4][kAggSlots];      // voxel index, -1 = empty
+    double val[4][kAggSlots];
+};
+
+// Sets the brick's bit; the caller that flips it appends the brick to the
+// list of bricks the step has to visit.
+__device__ __forceinline__ void mark_brick(unsigned* __restrict__ marks, int* __restrict__ list, int b) {
+    const unsigned bit = 1u << (b & 31);
+    if (marks[b >> 5] & bit) return;
+    const unsigned old = atomicOr(marks + (b >> 5), bit);
+    if (!(old & bit)) {
+        const int at = atomicAdd(list, 1);
+        list[1 + at] = b;
+    }
+}
+
+__device__ __forceinline__ void agg_add(GdAgg& A, int s, long long id, double val, double* __restrict__ grad,
+                                        long long nvox, unsigned* __restrict__ marks, int* __restrict__ list) {
+    const int key = (int)id;
+    unsigned h = ((unsigned)key * 2654435761u) >> (32 - 9);
+#pragma unroll 1
+    for (int p = 0; p < kAggProbes; ++p) {
+        const int slot = (int)((h + p) & (kAggSlots - 1));
+        const int prev = atomicCAS(&A.key[s][slot], -1, key);
+        if (prev == -1 || prev == key) {
+            __hip_atomic_fetch_add(&A.val[s][slot], val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            return;
+        }
+    }
+    unsafeAtomicAdd(grad + (long long)s * nvox + id, val);
+    mark_brick(marks, list, (int)(id >> 9));
+}
+
+// coef * (trilinear weight) for the in-grid corners of the cell
+__device__ __forceinline__ void agg_cell(const GridC& g, GdAgg& A, int s, const Cell& cl, const float w[3],
+                                         double coef, double* __restrict__ grad, unsigned* __restrict__ marks,
+                                         int* __restrict__ list) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
@@ -701,19 +744,7 @@ __device__ __forceinline__ void scatter_cell(const GridC& g, double* __restrict_
         if ((unsigned)i >= (unsigned)g.n || (unsigned)j >= (unsigned)g.n || (unsigned)k >= (unsigned)g.n) continue;
         const double hw = (double)(dx ? w[0] : 1.0f - w[0]) * (double)(dy ? w[1] : 1.0f - w[1]) *
                           (double)(dz ? w[2] : 1.0f - w[2]);
-        unsafeAtomicAdd(plane + vidx(g, i, j, k), coef * hw);
-    }
-}
-
-// Sets the bit of every brick holding an in-grid corner of the cell.
-__device__ __forceinline__ void mark_cell(const GridC& g, unsigned* __restrict__ marks, const Cell& cl) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int i = cl.i[0] + (q & 1), j = cl.i[1] + ((q >> 1) & 1), k = cl.i[2] + (q >> 2);
-        if ((unsigned)i >= (unsigned)g.n || (unsigned)j >= (unsigned)g.n || (unsigned)k >= (unsigned)g.n) continue;
-        const int b = ((k >> 3) * g.nb + (j >> 3)) * g.nb + (i >> 3);
-        const unsigned bit = 1u << (b & 31);
-        if (!(marks[b >> 5] & bit)) atomicOr(marks + (b >> 5), bit);
+        agg_add(A, s, vidx(g, i, j, k), coef * hw, grad, g.nvox, marks, list);
     }
 }
 
@@ -721,19 +752,25 @@ __device__ __forceinline__ void mark_cell(const GridC& g, unsigned* __restrict__
 // render-through rows (same validity, gates and weights as the P1 objective)
 // give the cost sum w r^2 (per-workgroup partial) and, through the adjoint of
 // the emission with the first crossing held, dE/dmean = sum 2 w r d(out)/dmean
-// accumulated in double precision into grad [4][n^3] (brick order).  The
-// bricks whose voxels receive a contribution are marked.
+// accumulated in double precision into grad [4][n^3] (brick order).  Every
+// brick that receives a contribution is marked, and appended to `list`
+// (count first) the first time.
 __global__ __launch_bounds__(256) void k_gd_grad(GridC g, CamC c, GridD gd, CamD cd, const float* __restrict__ map,
                                                  const unsigned* __restrict__ gbits,
                                                  const prism_pose* __restrict__ pose,
                                                  const float* __restrict__ obs_depth,
                                                  const float* __restrict__ obs_rgb, WeightsC wt,
                                                  double* __restrict__ grad, unsigned* __restrict__ marks,
-                                                 double* __restrict__ partials) {
+                                                 int* __restrict__ list, double* __restrict__ partials) {
     __shared__ BlockPose sp;
     __shared__ double wsum[4];
+    __shared__ GdAgg A;
     extern __shared__ unsigned lbits[];
-    const unsigned* bits = block_bits(g, gbits, lbits);
+    for (int e = threadIdx.x; e < 4 * kAggSlots; e += 256) {
+        (&A.key[0][0])[e] = -1;
+        (&A.val[0][0])[e] = 0.0;
+    }
+    const unsigned* bits = block_bits(g, gbits, lbits);   // synchronises the workgroup
     const BlockPose& P = block_pose(pose, &sp);
     int u, v, s;
     quad_pixel(c, blockIdx.x, u, v, s);
@@ -771,13 +808,8 @@ __global__ __launch_bounds__(256) void k_gd_grad(GridC g, CamC c, GridD gd, CamD
                 k0 = gout * (1.0 - q.alpha);
                 k1 = gout * q.alpha;
             }
-            double* plane = grad + (long long)s * g.nvox;
-            if (k0 != 0.0) scatter_cell(g, plane, c0, q.w0, k0);
-            if (k1 != 0.0) scatter_cell(g, plane, c1, q.w1, k1);
-            if (use_depth || use_rgb) {
-                if (s == 1) mark_cell(g, marks, c0);
-                if (s == 2) mark_cell(g, marks, c1);
-            }
+            if (k0 != 0.0) agg_cell(g, A, s, c0, q.w0, k0, grad, marks, list);
+            if (k1 != 0.0) agg_cell(g, A, s, c1, q.w1, k1, grad, marks, list);
         }
     }
 #pragma unroll
@@ -785,6 +817,14 @@ __global__ __launch_bounds__(256) void k_gd_grad(GridC g, CamC c, GridD gd, CamD
     if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = cost;
     __syncthreads();
     if (threadIdx.x == 0) partials[blockIdx.x] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+    // one global atomic per distinct (plane, voxel) of the tile
+    for (int e = threadIdx.x; e < 4 * kAggSlots; e += 256) {
+        const int key = (&A.key[0][0])[e];
+        if (key < 0) continue;
+        const int pl = e / kAggSlots;
+        unsafeAtomicAdd(grad + (long long)pl * g.nvox + key, (&A.val[0][0])[e]);
+        mark_brick(marks, list, key >> 9);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -855,9 +895,10 @@ hipError_t launch_render_jac(const GridC& g, const CamC& c, const GridD& gd, con
 
 hipError_t launch_gd_grad(const GridC& g, const CamC& c, const GridD& gd, const CamD& cd, const float* map,
                           const unsigned* bits, const prism_pose* pose, const float* obs_depth, const float* obs_rgb,
-                          const WeightsC& w, double* grad, unsigned* marks, double* partials, hipStream_t st) {
+                          const WeightsC& w, double* grad, unsigned* marks, int* list, double* partials,
+                          hipStream_t st) {
     k_gd_grad<<<render_blocks(c), 256, bits_lds(g, bits), st>>>(g, c, gd, cd, map, bits, pose, obs_depth, obs_rgb, w,
-                                                                grad, marks, partials);
+                                                                grad, marks, list, partials);
     return hipGetLastError();
 }
 
