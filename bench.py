@@ -200,6 +200,16 @@ def single_stream(P, torch, steps, warmup):
     ms_rj8 = timed(lambda: P.render_jacobian(grid, f.map, cam, poses, od, oc, w, want_render=False, ws=ws, out=rj,
                                              stream=stream), 20)
     rays = Wd * Ht
+    # adjoint of the emission (map means and pose), 8 frames, fixed first crossings
+    r8 = P.render(grid, f.map, cam, poses, hit_k=True, stream=stream)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(3)
+    g_d = torch.randn((8, Ht, Wd), generator=gen, device=dev)
+    g_c = torch.randn((8, Ht, Wd, 3), generator=gen, device=dev)
+    gm = torch.zeros((4, N ** 3), dtype=torch.float32, device=dev)
+    ms_vjp8 = timed(lambda: P.render_vjp(grid, f.map, cam, poses, r8["hit_k"], g_d, g_c, grad_mean=gm, ws=ws,
+                                         stream=stream), 20)
+    del gm
     pose_last = P.poses_tensor(np.concatenate([np.array(st.pose.t), np.array(st.pose.q)]))
     rout = P.render(grid, f.map, cam, pose_last, stream=stream)
     ms_r = timed(lambda: P.render(grid, f.map, cam, pose_last, out=rout, stream=stream), 50)
@@ -227,12 +237,96 @@ def single_stream(P, torch, steps, warmup):
     mu_gbs = mu_bytes / (ms_mu * 1e-3) / 1e9
 
     log(f"render_jacobian 1 frame {ms_rj1 * 1e3:.1f} us, 8 frames {ms_rj8 * 1e3:.1f} us; render {ms_r * 1e3:.1f} us; "
-        f"map_update call {ms_mu * 1e3:.1f} us ({mu_gbs:.0f} GB/s), {n_upd:.0f} voxels")
-    return dict(
+        f"adjoint 8 frames {ms_vjp8 * 1e3:.1f} us; map_update call {ms_mu * 1e3:.1f} us ({mu_gbs:.0f} GB/s), "
+        f"{n_upd:.0f} voxels")
+    return dict(us_vjp8=ms_vjp8 * 1e3, mrays_vjp8=8 * rays / (ms_vjp8 * 1e-3) / 1e6,
         ms_per_step=ms, p50_ms=float(np.percentile(per, 50)), p99_ms=float(np.percentile(per, 99)),
         pos_err=pos_err, mrays_1=rays / (ms_rj1 * 1e-3) / 1e6, mrays_8=8 * rays / (ms_rj8 * 1e-3) / 1e6,
         us_rj1=ms_rj1 * 1e3, us_rj8=ms_rj8 * 1e3, us_render=ms_r * 1e3, us_mu=ms_mu * 1e3,
         mu_bytes=mu_bytes, mu_gbs=mu_gbs, n_upd=n_upd)
+
+
+# ---------------------------------------------------------------------------
+# mapping: closed-form update against descent through the renderer
+# ---------------------------------------------------------------------------
+def mapping_comparison(P, torch, lr_occ=3e-6, lr_rgb=3e-3, n_prior=20):
+    """One frame fused into a map built from the previous `n_prior` frames
+    (closed form, true poses), once by the closed-form update and once by
+    gradient descent on the map-filter objective for a range of step counts.
+    Accuracy: the map re-rendered at the frame's pose against the noise-free
+    frame -- coverage of the valid ground-truth pixels, and depth / colour
+    mean absolute error on the pixels the previous map already rendered."""
+    import synth
+    dev = "cuda"
+    N, Wd, Ht, K = 256, 320, 240, 128
+    F = n_prior
+    case = synth.trajectory_case(seed=1, n=N, width=Wd, height=Ht, n_samples=K, n_frames=F + 1, frames=False)
+    tr, scene, cm = case["traj"], case["scene"], case["cam"]
+    D, C = synth.raycast_torch(scene, cm, tr.t, tr.q, 1, 0.01, 0.02)
+    Dg, Cg = synth.raycast_torch(scene, cm, tr.t[F:F + 1], tr.q[F:F + 1], 1, 0.0, 0.0)
+    grid = P.Grid.make(N, scene.voxel, tuple(float(v) for v in scene.origin))
+    cam = P.Camera.make(cm.width, cm.height, cm.fx, cm.fy, cm.cx, cm.cy, cm.d_near, cm.d_far, cm.n_samples)
+    poses = [P.poses_tensor(np.concatenate([tr.t[i], tr.q[i]])) for i in range(F + 1)]
+    trunc = 4 * scene.voxel
+    base = P.VoxelMap(grid).init()
+    for i in range(F):
+        P.map_update(grid, base, cam, poses[i], D[i], C[i], trunc)
+    gv = Dg[0] > 0
+    prior_valid = gv & (P.render(grid, base, cam, poses[F])["mask"][0] == 1)
+
+    def metrics(vm):
+        r = P.render(grid, vm, cam, poses[F])
+        valid = r["mask"][0] == 1
+        cov = (valid & gv).sum().item() / gv.sum().item()
+        s0 = prior_valid & valid
+        dmae = (r["depth"][0][s0] - Dg[0][s0]).abs().mean().item()
+        cmae = (r["rgb"][0][s0] - Cg[0][s0]).abs().mean().item()
+        return dict(coverage=round(cov, 4), depth_mae_mm=round(1e3 * dmae, 3), rgb_mae=round(cmae, 4))
+
+    def timed(fn, reps):
+        fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    vm = P.VoxelMap(grid)
+    vm.buf.copy_(base.buf)
+    us_cf = 1e3 * timed(lambda: P.map_update(grid, vm, cam, poses[F], D[F], C[F], trunc), 20)
+    vm.buf.copy_(base.buf)
+    P.map_update(grid, vm, cam, poses[F], D[F], C[F], trunc)
+    closed = dict(us=round(us_cf, 2), **metrics(vm))
+    prior = metrics(base)
+    w = P.Weights.make()
+    ws = P.map_gd_workspace(grid, cam)
+    n_timed = 100
+    vm.buf.copy_(base.buf)
+    us_gd = 1e3 * timed(lambda: P.map_gd(grid, vm, cam, poses[F], D[F], C[F], w, lr_occ, lr_rgb, n_timed, ws),
+                        1) / n_timed
+    curve, match, match_all = [], None, None
+    for n in (1, 2, 5, 10, 20, 50, 100, 200):
+        vm.buf.copy_(base.buf)
+        cost = torch.zeros(n, dtype=torch.float64, device=dev)
+        P.map_gd(grid, vm, cam, poses[F], D[F], C[F], w, lr_occ, lr_rgb, n, ws, cost)
+        torch.cuda.synchronize()
+        m = metrics(vm)
+        curve.append(dict(steps=n, ms=round(n * us_gd / 1e3, 3), objective=round(float(cost[-1].item()), 1), **m))
+        geo = m["depth_mae_mm"] <= closed["depth_mae_mm"] and m["coverage"] >= closed["coverage"]
+        if match is None and geo:
+            match = n
+        if match_all is None and geo and m["rgb_mae"] <= closed["rgb_mae"]:
+            match_all = n
+    log(f"mapping: closed form {us_cf:.1f} us {closed}; descent {us_gd:.1f} us/step, "
+        f"after 200 steps {curve[-1]}; depth and coverage matched after {match} steps, with colour {match_all}")
+    return {"workload": f"256^3 FP32 map from {F} closed-form frames (true poses), frame {F} fused; 320x240, "
+                        "K = 128; accuracy against the noise-free frame",
+            "prior": prior, "closed_form": closed,
+            "descent": {"lr_occ": lr_occ, "lr_rgb": lr_rgb, "us_per_step": round(us_gd, 2), "curve": curve},
+            "steps_to_match_closed_form": {"depth_and_coverage": match, "depth_coverage_and_colour": match_all}}
 
 
 # ---------------------------------------------------------------------------
@@ -396,6 +490,7 @@ def main():
         torch.cuda.synchronize()
 
     single = single_stream(P, torch, args.single_steps, 10)
+    mapping = mapping_comparison(P, torch)
 
     cpu = None
     if not args.no_cpu:
@@ -442,8 +537,12 @@ def main():
                                "p99_ms": r(single["p99_ms"], 4), "pos_err_m": r(single["pos_err"], 4)},
         "render_jacobian_mrays_per_s": {"1_frame": r(single["mrays_1"], 1), "8_frames": r(single["mrays_8"], 1),
                                         "workload": "256^3 FP32, 320x240, K = 128"},
+        "adjoint_mrays_per_s": {"8_frames": r(single["mrays_vjp8"], 1),
+                                "workload": "render_vjp, 256^3 FP32, 320x240, K = 128, 8 frames"},
         "kernels_us": {"render_jacobian_1f": r(single["us_rj1"], 2), "render_jacobian_8f": r(single["us_rj8"], 2),
-                       "render": r(single["us_render"], 2), "map_update": r(single["us_mu"], 2)},
+                       "render": r(single["us_render"], 2), "render_vjp_8f": r(single["us_vjp8"], 2),
+                       "map_update": r(single["us_mu"], 2)},
+        "mapping_gd_vs_closed_form": mapping,
         "roofline": roofline_obj(dominant, dom_roof, breakdown),
         "kernel_breakdown": breakdown,
         "roofline_map_update_single": {

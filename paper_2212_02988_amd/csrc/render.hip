@@ -619,6 +619,38 @@ __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, GridD gd, C
 // ---------------------------------------------------------------------------
 // adjoint of render w.r.t. map means (atomic scatter) and pose
 // ---------------------------------------------------------------------------
+// The 256 rays of a 16x16 tile reach a few hundred distinct voxels through
+// 4096 trilinear corners: the four planes' contributions of a voxel are
+// summed in an LDS table (open addressing on the voxel index), and each
+// distinct voxel then costs one global atomic per plane.  A corner that finds
+// no slot within a few probes is added to global memory directly.
+constexpr int kVjpSlots = 1024;   // power of two
+constexpr int kVjpProbes = 8;
+
+struct VjpAgg {
+    int key[kVjpSlots];          // voxel index, -1 = empty
+    float val[kVjpSlots][4];
+};
+
+__device__ __forceinline__ void vjp_add(VjpAgg& A, long long id, const float v[4], float* __restrict__ grad_mean,
+                                        long long nvox) {
+    const int key = (int)id;
+    const unsigned h = ((unsigned)key * 2654435761u) >> (32 - 10);
+#pragma unroll 1
+    for (int p = 0; p < kVjpProbes; ++p) {
+        const int slot = (int)((h + p) & (kVjpSlots - 1));
+        const int prev = atomicCAS(&A.key[slot], -1, key);
+        if (prev == -1 || prev == key) {
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch)
+                __hip_atomic_fetch_add(&A.val[slot][ch], v[ch], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            return;
+        }
+    }
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) atomicAdd(grad_mean + (long long)ch * nvox + id, v[ch]);
+}
+
 __global__ __launch_bounds__(256) void k_render_vjp(GridC g, CamC c, GridD gd, CamD cd, const float* __restrict__ map,
                                                     const prism_pose* __restrict__ poses,
                                                     const int32_t* __restrict__ hit_k,
@@ -628,7 +660,13 @@ __global__ __launch_bounds__(256) void k_render_vjp(GridC g, CamC c, GridD gd, C
                                                     double* __restrict__ partials) {
     __shared__ BlockPose sp;
     __shared__ double lds[kRedLds];
-    const BlockPose& P = block_pose(poses + blockIdx.y, &sp);
+    __shared__ VjpAgg A;
+    for (int e = threadIdx.x; e < kVjpSlots; e += 256) {
+        A.key[e] = -1;
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) A.val[e][ch] = 0.0f;
+    }
+    const BlockPose& P = block_pose(poses + blockIdx.y, &sp);   // synchronises the workgroup
     int u, v;
     tile_pixel(c, u, v);
     double acc[PRISM_NEQ];
@@ -674,17 +712,22 @@ __global__ __launch_bounds__(256) void k_render_vjp(GridC g, CamC c, GridD gd, C
                         const float* cw3 = sm ? s.w1 : s.w0;
                         float hw = (dx ? cw3[0] : 1.0f - cw3[0]) * (dy ? cw3[1] : 1.0f - cw3[1]) *
                                    (dz ? cw3[2] : 1.0f - cw3[2]);
-                        long long id = vidx(g, i, j, kk);
-                        atomicAdd(grad_mean + id, gf[sm] * hw);
-#pragma unroll
-                        for (int ch = 0; ch < 3; ++ch)
-                            atomicAdd(grad_mean + (long long)(1 + ch) * g.nvox + id, gc[ch] * cw[sm] * hw);
+                        const float vals[4] = {gf[sm] * hw, gc[0] * cw[sm] * hw, gc[1] * cw[sm] * hw,
+                                               gc[2] * cw[sm] * hw};
+                        vjp_add(A, vidx(g, i, j, kk), vals, grad_mean, g.nvox);
                     }
                 }
             }
         }
     }
     block_reduce29(acc, lds, partials + ((long long)blockIdx.y * gridDim.x + blockIdx.x) * PRISM_NEQ);
+    __syncthreads();
+    for (int e = threadIdx.x; e < kVjpSlots; e += 256) {
+        const int key = A.key[e];
+        if (key < 0) continue;
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) atomicAdd(grad_mean + (long long)ch * g.nvox + key, A.val[e][ch]);
+    }
 }
 
 // ---------------------------------------------------------------------------
