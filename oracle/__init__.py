@@ -30,6 +30,9 @@ map_gd                 Sec. 4.3.1 alternative: the map-filter objective
 predict / split        App. E.1 linearised transition, E.2 closed-form
                        propagation and split into pose prior + velocity
                        conditional
+adam_pose              Sec. 4.3.2 MAP pose by the paper's optimiser (App. G:
+                       Adam without momentum, per-component step sizes,
+                       sampled pixels)
 gn_solve / laplace     Sec. 4.3.2 MAP pose + Laplace approximation;
                        Sec. 5.1 / App. G.2 Hessian as squared Jacobian, EMA 0.8
 combine                Sec. 4.3.2 product of pose posterior and velocity
@@ -496,6 +499,48 @@ def gn_solve(neq: np.ndarray, Lp: np.ndarray, e_p: np.ndarray) -> np.ndarray:
     return np.linalg.solve(L.T, np.linalg.solve(L, b))
 
 
+def adam_gradient(cam: Cam, pose, prior, Lp, pose_prev, obs_depth, obs_rgb, anchor, params: Params,
+                  pixels: np.ndarray, decide32: bool = True) -> np.ndarray:
+    """Gradient w.r.t. the pose perturbation of the MAP objective whose data
+    term is the P2 rows of the sampled pixels (row-major indices; outside the
+    image: no rows; repeats count repeatedly), scaled by (image pixels /
+    sampled pixels) to estimate the full-frame sum:
+        scale * sum 2 w r dr/ddelta  +  Lp e(pose, prior)."""
+    H, W = cam.height, cam.width
+    out = track_p2(cam, pose, pose_prev, obs_depth, obs_rgb, anchor, params, decide32, want_J=True)
+    J = out["J"].reshape(H * W, 4, 6)
+    r = out["resid"].reshape(H * W, 4)
+    rm = out["rowmask"].reshape(H * W)
+    idx = np.asarray(pixels)
+    idx = idx[(idx >= 0) & (idx < H * W)]
+    g = np.zeros(6)
+    geo = idx[(rm[idx] & 1) != 0]
+    g += (1.0 / params.b_geo ** 2) * (r[geo, 0, None] * J[geo, 0]).sum(0)
+    pho = idx[(rm[idx] & 2) != 0]
+    g += (1.0 / params.b_rgb ** 2) * (r[pho, 1:, None] * J[pho, 1:]).sum((0, 1))
+    scale = H * W / len(pixels)
+    return 2.0 * scale * g + Lp @ pose_error(pose, prior)
+
+
+def adam_pose(cam: Cam, prior, Lp, pose_prev, obs_depth, obs_rgb, anchor, params: Params,
+              pixels: np.ndarray, lr_t: float, lr_r: float, beta2: float = 0.999, eps: float = 1e-8,
+              decide32: bool = True) -> np.ndarray:
+    """The paper's pose optimiser (App. G) on the MAP objective of Sec. 4.3.2
+    with the P2 data term: Adam with the first moment switched off (each
+    step follows the current gradient), per-component step sizes (lr_t for
+    translation, lr_r for rotation), one row of `pixels` per step, starting
+    from the prior mean.  Steps are left retractions, as in Gauss-Newton."""
+    lr = np.array([lr_t] * 3 + [lr_r] * 3)
+    it = _f64(prior).copy()
+    v = np.zeros(6)
+    for k in range(len(pixels)):
+        g = adam_gradient(cam, it, prior, Lp, pose_prev, obs_depth, obs_rgb, anchor, params, pixels[k], decide32)
+        v = beta2 * v + (1.0 - beta2) * g * g
+        vhat = v / (1.0 - beta2 ** (k + 1))
+        it = retract(it, -lr * g / (np.sqrt(vhat) + eps))
+    return it
+
+
 def laplace(neq: np.ndarray, Lp: np.ndarray) -> np.ndarray:
     """Laplace covariance at the MAP pose, Hessian from the squared Jacobian of
     the full objective including the dynamics prior: (2 H + Lp)^-1."""
@@ -573,7 +618,10 @@ class Filter:
         self.s.anchor_pose = pose.copy()
         self.s.last["n_updated"] = n
 
-    def step(self, depth: np.ndarray, rgb: np.ndarray, u: Optional[np.ndarray]) -> FilterState:
+    def step(self, depth: np.ndarray, rgb: np.ndarray, u: Optional[np.ndarray],
+             adam: Optional[Dict] = None) -> FilterState:
+        """One filter step; `adam` (keys pixels, lr_t, lr_r, beta2, eps)
+        replaces the Gauss-Newton iterations by the paper's optimiser."""
         s, p = self.s, self.p
         if s.step == 0:
             self._observe_and_anchor(s.pose, depth, rgb)
@@ -595,12 +643,19 @@ class Filter:
         Spp, D, Sv = split(Pm)
         Lp = np.linalg.inv(Spp)
         Lp = 0.5 * (Lp + Lp.T)
-        # MAP pose by Gauss-Newton from the prior mean (Sec. 4.3.2)
+        # MAP pose from the prior mean (Sec. 4.3.2): Gauss-Newton, or the
+        # paper's optimiser on sampled pixels (App. G)
         it = prior.copy()
-        for _ in range(p.n_gn):
-            neq = self._objective(it, depth, rgb)
-            delta = gn_solve(neq, Lp, pose_error(it, prior))
-            it = retract(it, delta)
+        if adam is not None:
+            assert p.objective == "p2"
+            it = adam_pose(self.cam, prior, Lp, self.s.anchor_pose, depth, rgb, self.s.anchor, p, adam["pixels"],
+                           adam["lr_t"], adam["lr_r"], adam.get("beta2", 0.999), adam.get("eps", 1e-8),
+                           self.decide32)
+        else:
+            for _ in range(p.n_gn):
+                neq = self._objective(it, depth, rgb)
+                delta = gn_solve(neq, Lp, pose_error(it, prior))
+                it = retract(it, delta)
         neq = self._objective(it, depth, rgb)
         S_lap = laplace(neq, Lp)
         s.Sbar = S_lap if s.Sbar is None else p.ema * s.Sbar + (1.0 - p.ema) * S_lap

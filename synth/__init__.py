@@ -447,6 +447,13 @@ def trajectory_case(seed: int = 1, n: int = 256, width: int = 320, height: int =
     return out
 
 
+def sample_pixels(seed: int, n_steps: int, n_pixels: int, height: int, width: int) -> np.ndarray:
+    """Pixel indices v*W+u drawn uniformly with replacement, one row of
+    n_pixels per optimisation step: int32 [n_steps][n_pixels]."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, height * width, size=(n_steps, n_pixels), dtype=np.int64).astype(np.int32)
+
+
 def pose7(t: np.ndarray, q: np.ndarray) -> np.ndarray:
     """Pose as the 7 doubles (tx, ty, tz, qw, qx, qy, qz)."""
     return np.concatenate([np.asarray(t, float), np.asarray(q, float)])
