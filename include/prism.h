@@ -132,7 +132,8 @@ const char *prism_version(void);
 
 /* sizeof() of a public struct given its name ("prism_grid", "prism_camera",
  * "prism_pose", "prism_weights", "prism_map_params", "prism_filter_cfg",
- * "prism_filter_state", "prism_frame"); 0 for an unknown name.  Lets
+ * "prism_filter_state", "prism_frame", "prism_adam_params"); 0 for an unknown
+ * name.  Lets
  * bindings verify their struct mirrors. */
 size_t prism_sizeof(const char *type_name);
 
@@ -389,6 +390,44 @@ prism_status prism_filter_reset(prism_filter *f, const double *x0, const double 
  * and combination with the velocity conditional.  Not valid for the first
  * frame. */
 prism_status prism_pose_update(prism_filter *f, const prism_frame *frame, hipStream_t stream);
+
+/* The paper's own pose optimiser (App. G): Adam with its momentum disabled,
+ * separate step sizes for translation and rotation, a fixed number of steps,
+ * each on pixels sampled uniformly from the frame. */
+typedef struct {
+    int32_t n_steps;  /* optimisation steps (paper: 1000), 1..1000000 */
+    int32_t n_pixels; /* pixels per step (paper: 200), 1..65536 */
+    double lr_t;      /* step size of the translation components (paper: 0.001) */
+    double lr_r;      /* step size of the rotation components (paper: 0.00036) */
+    double beta2;     /* second-moment decay, [0, 1) (Adam's default 0.999) */
+    double eps;       /* denominator floor, > 0 (Adam's default 1e-8) */
+} prism_adam_params;
+
+/* prism_pose_update with the Gauss-Newton iterations replaced by the
+ * paper's optimiser on the P2 objective (Sec. 4.3.2 MAP objective, App. E.3
+ * surrogate, App. G optimiser).  From the predicted pose, step k evaluates
+ * the rows of the pixels pixels[k][0..n_pixels) (row-major indices v*W+u into
+ * the frame, drawn by the caller; an index outside the image is a pixel
+ * without rows, repeats count repeatedly) and forms the gradient of the MAP
+ * objective with the data term scaled by W*H/n_pixels (an unbiased estimate
+ * of the full-frame sum): g = scale * sum 2 w r J + Lp e.  The step keeps a
+ * second moment v <- beta2 v + (1-beta2) g^2 per component, bias-corrects it,
+ * and moves the pose by -lr g / (sqrt(vhat) + eps) (left retraction, as the
+ * Gauss-Newton step).  The Laplace covariance then comes from the dense
+ * normal equations at the final pose, as in prism_pose_update.  The whole
+ * optimisation is one kernel launch (one workgroup).  Filters configured for
+ * the P1 objective return PRISM_UNSUPPORTED.
+ * pixels: device int32 [n_steps][n_pixels]. */
+prism_status prism_pose_update_adam(prism_filter *f, const prism_frame *frame,
+                                    const prism_adam_params *p, const int32_t *pixels,
+                                    hipStream_t stream);
+
+/* One filter step (as prism_filter_step for one handle) whose state filter
+ * is prism_pose_update_adam; a filter's first frame only updates the map and
+ * renders the anchor (p and pixels are still checked). */
+prism_status prism_filter_step_adam(prism_filter *f, const prism_frame *frame,
+                                    const prism_adam_params *p, const int32_t *pixels,
+                                    hipStream_t stream);
 
 /* One full filter step for each of n handles (Sec. 4.3): the state filter
  * as in prism_pose_update (skipped for a filter's first frame), then the map

@@ -352,6 +352,42 @@ prism_status pose_update_impl(prism_filter* f, const prism_frame* fr, hipStream_
     return PRISM_OK;
 }
 
+prism_status check_adam(const prism_filter* f, const prism_adam_params* p, const int32_t* pixels) {
+    if (f->cfg.objective != PRISM_OBJ_P2)
+        return fail(PRISM_UNSUPPORTED, "the Adam pose optimiser runs on the P2 objective only");
+    REQUIRE(p, "adam params are NULL");
+    REQUIRE(p->n_steps >= 1 && p->n_steps <= 1000000, "adam n_steps must be in [1, 1000000]");
+    REQUIRE(p->n_pixels >= 1 && p->n_pixels <= 65536, "adam n_pixels must be in [1, 65536]");
+    REQUIRE(isfinite(p->lr_t) && p->lr_t >= 0 && isfinite(p->lr_r) && p->lr_r >= 0,
+            "adam step sizes must be finite and >= 0");
+    REQUIRE(p->beta2 >= 0 && p->beta2 < 1, "adam beta2 must be in [0, 1)");
+    REQUIRE(isfinite(p->eps) && p->eps > 0, "adam eps must be finite and > 0");
+    REQUIRE(pixels && aligned(pixels, 4), "pixels must be non-NULL and 4-byte aligned");
+    return PRISM_OK;
+}
+
+prism_status pose_update_adam_impl(prism_filter* f, const prism_frame* fr, const prism_adam_params* p,
+                                   const int32_t* pixels, hipStream_t st) {
+    HIP_TRY(launch_predict(f->S, fr->u, f->tc, st));
+    AdamC ad;
+    for (int i = 0; i < 3; ++i) {
+        ad.lr[i] = p->lr_t;
+        ad.lr[3 + i] = p->lr_r;
+    }
+    ad.beta2 = p->beta2;
+    ad.eps = p->eps;
+    ad.scale = (double)f->c.W * (double)f->c.H / (double)p->n_pixels;
+    ad.n_steps = p->n_steps;
+    ad.n_pix = p->n_pixels;
+    HIP_TRY(launch_pose_adam(f->S, f->c, f->cd, fr->depth, fr->rgb, f->a_depth, f->a_rgb, f->a_mask, f->a_normals,
+                             f->a_nmask, f->w, pixels, ad, st));
+    int nb = 0;
+    prism_status s;
+    if ((s = eval_objective(f, fr, &nb, st))) return s;
+    HIP_TRY(launch_laplace_combine(f->S, f->partials, nb, f->cfg.ema, st));
+    return PRISM_OK;
+}
+
 prism_status map_and_anchor(prism_filter* f, const prism_frame* fr, hipStream_t st) {
     // the update's count of voxels is totalled by the normals kernel at the end
     MapAux aux = map_aux(&f->cfg.grid, f->map);
@@ -381,7 +417,8 @@ size_t prism_sizeof(const char* name) {
         {"prism_grid", sizeof(prism_grid)},         {"prism_camera", sizeof(prism_camera)},
         {"prism_pose", sizeof(prism_pose)},         {"prism_weights", sizeof(prism_weights)},
         {"prism_map_params", sizeof(prism_map_params)}, {"prism_filter_cfg", sizeof(prism_filter_cfg)},
-        {"prism_filter_state", sizeof(prism_filter_state)}, {"prism_frame", sizeof(prism_frame)}};
+        {"prism_filter_state", sizeof(prism_filter_state)}, {"prism_frame", sizeof(prism_frame)},
+        {"prism_adam_params", sizeof(prism_adam_params)}};
     for (auto& e : t)
         if (!strcmp(e.n, name)) return e.s;
     return 0;
@@ -769,6 +806,33 @@ prism_status prism_pose_update(prism_filter* f, const prism_frame* frame, hipStr
     if (s) return s;
     REQUIRE(f->steps > 0, "pose_update needs a filter past its first frame");
     return pose_update_impl(f, frame, stream);
+}
+
+prism_status prism_pose_update_adam(prism_filter* f, const prism_frame* frame, const prism_adam_params* p,
+                                    const int32_t* pixels, hipStream_t stream) {
+    REQUIRE(f, "filter is NULL");
+    prism_status s = check_frame(frame, true);
+    if (s) return s;
+    if ((s = check_adam(f, p, pixels))) return s;
+    REQUIRE(f->steps > 0, "pose_update_adam needs a filter past its first frame");
+    return pose_update_adam_impl(f, frame, p, pixels, stream);
+}
+
+prism_status prism_filter_step_adam(prism_filter* f, const prism_frame* frame, const prism_adam_params* p,
+                                    const int32_t* pixels, hipStream_t stream) {
+    REQUIRE(f, "filter is NULL");
+    prism_status s = check_frame(frame, f->steps > 0);
+    if (s) return s;
+    if ((s = check_adam(f, p, pixels))) return s;
+    if (f->steps == 0) {
+        if ((s = map_and_anchor(f, frame, stream))) return s;
+        HIP_TRY(launch_first_frame(f->S, stream));
+    } else {
+        if ((s = pose_update_adam_impl(f, frame, p, pixels, stream))) return s;
+        if ((s = map_and_anchor(f, frame, stream))) return s;
+    }
+    f->steps += 1;
+    return PRISM_OK;
 }
 
 namespace {

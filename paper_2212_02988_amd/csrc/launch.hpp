@@ -149,6 +149,17 @@ int gd_update_groups(const GridC& g);
 hipError_t launch_stage(const void* depth, const void* rgb, const void* u, float* d_out, float* c_out, double* u_out,
                         long long npix, hipStream_t st);
 
+// Adam (first moment off) on sampled pixels of the P2 objective
+struct AdamC {
+    double lr[6];              // step size per component (translation x3, rotation x3)
+    double beta2, eps, scale;  // scale: image pixels / pixels per step
+    int n_steps, n_pix;
+};
+hipError_t launch_pose_adam(prism_filter_state* S, const CamC& c, const CamD& cd, const float* obs_depth,
+                            const float* obs_rgb, const float* a_depth, const float* a_rgb, const uint8_t* a_mask,
+                            const float* a_normals, const uint8_t* a_nmask, const WeightsC& w, const int32_t* pixels,
+                            const AdamC& ad, hipStream_t st);
+
 hipError_t launch_predict(prism_filter_state* S, const double* u, const TransC& tc, hipStream_t st);
 hipError_t launch_gn_step(prism_filter_state* S, const double* partials, int nblocks, hipStream_t st);
 hipError_t launch_laplace_combine(prism_filter_state* S, const double* partials, int nblocks, double ema,

@@ -6,6 +6,7 @@
 // gathers around the reprojected location.
 #include "common.hpp"
 #include "launch.hpp"
+#include "se3.hpp"
 
 namespace prism {
 
@@ -13,6 +14,142 @@ struct Rel32 {
     float R[3][3], t[3];   // current camera -> anchor camera (association recipe)
     Pose64 cur, prev;      // both poses in double precision (values)
 };
+
+__device__ __forceinline__ void rel_of(const prism_pose* pose, const prism_pose* pose_prev, Rel32& rel) {
+    Pose64 P = load_pose64(pose), Q = load_pose64(pose_prev);
+    double d[3] = {P.t[0] - Q.t[0], P.t[1] - Q.t[1], P.t[2] - Q.t[2]};
+    for (int a = 0; a < 3; ++a) {
+        for (int b = 0; b < 3; ++b)
+            rel.R[a][b] = (float)((Q.R[0][a] * P.R[0][b] + Q.R[1][a] * P.R[1][b]) + Q.R[2][a] * P.R[2][b]);
+        rel.t[a] = (float)((Q.R[0][a] * d[0] + Q.R[1][a] * d[1]) + Q.R[2][a] * d[2]);
+    }
+    rel.cur = P;
+    rel.prev = Q;
+}
+
+// The rows of observed pixel p (row-major index): geometric row 0
+// (point-to-plane against the nearest anchor pixel) and colour rows 1-3
+// (bilinear anchor colour minus the observation), residuals in double
+// precision, Jacobians w.r.t. the pose perturbation in single precision.
+// rm: bit 0 the geometric row passed its gate, bit 1 the colour rows.
+__device__ __forceinline__ void p2_pixel(const CamC& c, const CamD& cd, const Rel32& rel, int p,
+                                         const float* __restrict__ obs_depth, const float* __restrict__ obs_rgb,
+                                         const float* __restrict__ a_depth, const float* __restrict__ a_rgb,
+                                         const uint8_t* __restrict__ a_mask, const float* __restrict__ a_normals,
+                                         const uint8_t* __restrict__ a_nmask, const WeightsC& wt, float J[4][6],
+                                         double r[4], int& rm) {
+    const int u = p % c.W, v = p / c.W;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        r[a] = 0.0;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) J[a][m] = 0.0f;
+    }
+    rm = 0;
+    float D = obs_depth[p];
+    if (!depth_ok(D)) return;
+    float rx = ((float)u + 0.5f - c.cx) * c.ifx;
+    float ry = ((float)v + 0.5f - c.cy) * c.ify;
+    float X[3] = {D * rx, D * ry, D};
+    float Y[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) Y[a] = ((rel.R[a][0] * X[0] + rel.R[a][1] * X[1]) + rel.R[a][2] * X[2]) + rel.t[a];
+    bool geo = false, pho = false;
+    int giu = 0, giv = 0, bix = 0, biy = 0;
+    float uu = 0.0f, vv = 0.0f;
+    if (Y[2] > 0.0f) {
+        uu = c.fx * (Y[0] / Y[2]) + c.cx;
+        vv = c.fy * (Y[1] / Y[2]) + c.cy;
+        if (uu >= 0.0f && uu < (float)c.W && vv >= 0.0f && vv < (float)c.H) {
+            giu = (int)uu;
+            giv = (int)vv;
+            geo = true;
+        }
+        float bx = uu - 0.5f, by = vv - 0.5f;
+        if (bx >= 0.0f && bx < (float)(c.W - 1) && by >= 0.0f && by < (float)(c.H - 1)) {
+            bix = (int)bx;
+            biy = (int)by;
+            pho = true;
+        }
+    }
+    if (geo) {
+        int q = giv * c.W + giu;
+        geo = a_mask[q] && a_nmask[q];
+    }
+    int q00 = biy * c.W + bix;
+    if (pho) pho = a_mask[q00] && a_mask[q00 + 1] && a_mask[q00 + c.W] && a_mask[q00 + c.W + 1];
+    if (!(geo || pho)) return;
+    // values in double precision: back-projected point, moved into the
+    // anchor camera; Jacobians in single precision
+    const Pose64& Pc = rel.cur;
+    const Pose64& Pp = rel.prev;
+    double rc[3], Xd[3], RXd[3], dW[3], Yd[3];
+    pixel_dir64(cd, u, v, rc);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) Xd[a] = (double)D * rc[a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) RXd[a] = Pc.R[a][0] * Xd[0] + Pc.R[a][1] * Xd[1] + Pc.R[a][2] * Xd[2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dW[a] = RXd[a] + Pc.t[a] - Pp.t[a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) Yd[a] = Pp.R[0][a] * dW[0] + Pp.R[1][a] * dW[1] + Pp.R[2][a] * dW[2];
+    // dY/ddelta = Rp^T [I | -[R X]x]
+    float RX[3] = {(float)RXd[0], (float)RXd[1], (float)RXd[2]};
+    float dY[3][6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float e0 = (float)Pp.R[0][a], e1 = (float)Pp.R[1][a], e2 = (float)Pp.R[2][a];
+        dY[a][0] = e0;
+        dY[a][1] = e1;
+        dY[a][2] = e2;
+        dY[a][3] = RX[1] * e2 - RX[2] * e1;
+        dY[a][4] = RX[2] * e0 - RX[0] * e2;
+        dY[a][5] = RX[0] * e1 - RX[1] * e0;
+    }
+    if (geo) {
+        int q = giv * c.W + giu;
+        double ra[3];
+        pixel_dir64(cd, giu, giv, ra);
+        double da = (double)a_depth[q];
+        double n0 = a_normals[3 * q], n1 = a_normals[3 * q + 1], n2 = a_normals[3 * q + 2];
+        double rg = n0 * (da * ra[0] - Yd[0]) + n1 * (da * ra[1] - Yd[1]) + n2 * (da * ra[2] - Yd[2]);
+        r[0] = rg;
+        float fn0 = (float)n0, fn1 = (float)n1, fn2 = (float)n2;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) J[0][m] = -(fn0 * dY[0][m] + fn1 * dY[1][m] + fn2 * dY[2][m]);
+        if (fabs(rg) <= wt.gate_depth) rm |= 1;
+    }
+    if (pho) {
+        double ud = cd.fx * Yd[0] / Yd[2] + cd.cx;
+        double vd = cd.fy * Yd[1] / Yd[2] + cd.cy;
+        double ax = (ud - 0.5) - (double)bix, ay = (vd - 0.5) - (double)biy;
+        float Y2 = (float)Yd[2];
+        float iz = 1.0f / Y2;
+        float du_[3] = {c.fx * iz, 0.0f, -c.fx * (float)Yd[0] * iz * iz};
+        float dv_[3] = {0.0f, c.fy * iz, -c.fy * (float)Yd[1] * iz * iz};
+        float dum[6], dvm[6];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            dum[m] = du_[0] * dY[0][m] + du_[2] * dY[2][m];
+            dvm[m] = dv_[1] * dY[1][m] + dv_[2] * dY[2][m];
+        }
+        double l1 = 0.0;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            double I00 = a_rgb[3 * q00 + ch], I10 = a_rgb[3 * (q00 + 1) + ch];
+            double I01 = a_rgb[3 * (q00 + c.W) + ch], I11 = a_rgb[3 * (q00 + c.W + 1) + ch];
+            double Ii = (1 - ax) * (1 - ay) * I00 + ax * (1 - ay) * I10 + (1 - ax) * ay * I01 + ax * ay * I11;
+            float gu = (float)((1 - ay) * (I10 - I00) + ay * (I11 - I01));
+            float gv = (float)((1 - ax) * (I01 - I00) + ax * (I11 - I10));
+            double rp = Ii - (double)obs_rgb[3 * p + ch];
+            r[1 + ch] = rp;
+            l1 += fabs(rp);
+#pragma unroll
+            for (int m = 0; m < 6; ++m) J[1 + ch][m] = gu * dum[m] + gv * dvm[m];
+        }
+        if (l1 <= wt.gate_rgb) rm |= 2;
+    }
+}
 
 // one workgroup (blk: its index within this frame's grid) of the tracking
 // objective; partials receives the workgroup's 29 sums at row blk
@@ -30,17 +167,7 @@ __device__ __forceinline__ void track_p2_block(int blk, const CamC& c, const Cam
                                                uint8_t* __restrict__ rowmask, double* __restrict__ partials) {
     __shared__ Rel32 srel;
     __shared__ double lds[kRedLds];
-    if (threadIdx.x == 0) {
-        Pose64 P = load_pose64(pose), Q = load_pose64(pose_prev);
-        double d[3] = {P.t[0] - Q.t[0], P.t[1] - Q.t[1], P.t[2] - Q.t[2]};
-        for (int a = 0; a < 3; ++a) {
-            for (int b = 0; b < 3; ++b)
-                srel.R[a][b] = (float)((Q.R[0][a] * P.R[0][b] + Q.R[1][a] * P.R[1][b]) + Q.R[2][a] * P.R[2][b]);
-            srel.t[a] = (float)((Q.R[0][a] * d[0] + Q.R[1][a] * d[1]) + Q.R[2][a] * d[2]);
-        }
-        srel.cur = P;
-        srel.prev = Q;
-    }
+    if (threadIdx.x == 0) rel_of(pose, pose_prev, srel);
     __syncthreads();
     const Rel32& rel = srel;
     // this pixel's rows summed in single precision (at most 4 rows of
@@ -51,129 +178,15 @@ __device__ __forceinline__ void track_p2_block(int blk, const CamC& c, const Cam
     for (int q = 0; q < PRISM_NEQ; ++q) pacc[q] = 0.0f;
     int p = blk * blockDim.x + threadIdx.x;
     if (p < c.W * c.H) {
-        int u = p % c.W, v = p / c.W;
         float J[4][6];
-        double r[4] = {0.0, 0.0, 0.0, 0.0};
+        double r[4];
+        int rm;
+        p2_pixel(c, cd, rel, p, obs_depth, obs_rgb, a_depth, a_rgb, a_mask, a_normals, a_nmask, wt, J, r, rm);
+        if (rm & 1) neq_add32(pacc, J[0], (float)r[0], (float)wt.w_depth);
+        if (rm & 2)
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int m = 0; m < 6; ++m) J[a][m] = 0.0f;
-        uint8_t rm = 0;
-        float D = obs_depth[p];
-        if (depth_ok(D)) {
-            float rx = ((float)u + 0.5f - c.cx) * c.ifx;
-            float ry = ((float)v + 0.5f - c.cy) * c.ify;
-            float X[3] = {D * rx, D * ry, D};
-            float Y[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-                Y[a] = ((rel.R[a][0] * X[0] + rel.R[a][1] * X[1]) + rel.R[a][2] * X[2]) + rel.t[a];
-            bool geo = false, pho = false;
-            int giu = 0, giv = 0, bix = 0, biy = 0;
-            float uu = 0.0f, vv = 0.0f;
-            if (Y[2] > 0.0f) {
-                uu = c.fx * (Y[0] / Y[2]) + c.cx;
-                vv = c.fy * (Y[1] / Y[2]) + c.cy;
-                if (uu >= 0.0f && uu < (float)c.W && vv >= 0.0f && vv < (float)c.H) {
-                    giu = (int)uu;
-                    giv = (int)vv;
-                    geo = true;
-                }
-                float bx = uu - 0.5f, by = vv - 0.5f;
-                if (bx >= 0.0f && bx < (float)(c.W - 1) && by >= 0.0f && by < (float)(c.H - 1)) {
-                    bix = (int)bx;
-                    biy = (int)by;
-                    pho = true;
-                }
-            }
-            if (geo) {
-                int q = giv * c.W + giu;
-                geo = a_mask[q] && a_nmask[q];
-            }
-            int q00 = biy * c.W + bix;
-            if (pho) pho = a_mask[q00] && a_mask[q00 + 1] && a_mask[q00 + c.W] && a_mask[q00 + c.W + 1];
-            if (geo || pho) {
-                // values in double precision: back-projected point, moved into
-                // the anchor camera; Jacobians in single precision
-                const Pose64& Pc = rel.cur;
-                const Pose64& Pp = rel.prev;
-                double rc[3], Xd[3], RXd[3], dW[3], Yd[3];
-                pixel_dir64(cd, u, v, rc);
-#pragma unroll
-                for (int a = 0; a < 3; ++a) Xd[a] = (double)D * rc[a];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) RXd[a] = Pc.R[a][0] * Xd[0] + Pc.R[a][1] * Xd[1] + Pc.R[a][2] * Xd[2];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) dW[a] = RXd[a] + Pc.t[a] - Pp.t[a];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) Yd[a] = Pp.R[0][a] * dW[0] + Pp.R[1][a] * dW[1] + Pp.R[2][a] * dW[2];
-                // dY/ddelta = Rp^T [I | -[R X]x]
-                float RX[3] = {(float)RXd[0], (float)RXd[1], (float)RXd[2]};
-                float dY[3][6];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    float e0 = (float)Pp.R[0][a], e1 = (float)Pp.R[1][a], e2 = (float)Pp.R[2][a];
-                    dY[a][0] = e0;
-                    dY[a][1] = e1;
-                    dY[a][2] = e2;
-                    dY[a][3] = RX[1] * e2 - RX[2] * e1;
-                    dY[a][4] = RX[2] * e0 - RX[0] * e2;
-                    dY[a][5] = RX[0] * e1 - RX[1] * e0;
-                }
-                if (geo) {
-                    int q = giv * c.W + giu;
-                    double ra[3];
-                    pixel_dir64(cd, giu, giv, ra);
-                    double da = (double)a_depth[q];
-                    double n0 = a_normals[3 * q], n1 = a_normals[3 * q + 1], n2 = a_normals[3 * q + 2];
-                    double rg = n0 * (da * ra[0] - Yd[0]) + n1 * (da * ra[1] - Yd[1]) + n2 * (da * ra[2] - Yd[2]);
-                    r[0] = rg;
-                    float fn0 = (float)n0, fn1 = (float)n1, fn2 = (float)n2;
-#pragma unroll
-                    for (int m = 0; m < 6; ++m) J[0][m] = -(fn0 * dY[0][m] + fn1 * dY[1][m] + fn2 * dY[2][m]);
-                    if (fabs(rg) <= wt.gate_depth) {
-                        neq_add32(pacc, J[0], (float)rg, (float)wt.w_depth);
-                        rm |= 1;
-                    }
-                }
-                if (pho) {
-                    double ud = cd.fx * Yd[0] / Yd[2] + cd.cx;
-                    double vd = cd.fy * Yd[1] / Yd[2] + cd.cy;
-                    double ax = (ud - 0.5) - (double)bix, ay = (vd - 0.5) - (double)biy;
-                    float Y2 = (float)Yd[2];
-                    float iz = 1.0f / Y2;
-                    float du_[3] = {c.fx * iz, 0.0f, -c.fx * (float)Yd[0] * iz * iz};
-                    float dv_[3] = {0.0f, c.fy * iz, -c.fy * (float)Yd[1] * iz * iz};
-                    float dum[6], dvm[6];
-#pragma unroll
-                    for (int m = 0; m < 6; ++m) {
-                        dum[m] = du_[0] * dY[0][m] + du_[2] * dY[2][m];
-                        dvm[m] = dv_[1] * dY[1][m] + dv_[2] * dY[2][m];
-                    }
-                    double l1 = 0.0;
-                    double rp[3];
-#pragma unroll
-                    for (int ch = 0; ch < 3; ++ch) {
-                        double I00 = a_rgb[3 * q00 + ch], I10 = a_rgb[3 * (q00 + 1) + ch];
-                        double I01 = a_rgb[3 * (q00 + c.W) + ch], I11 = a_rgb[3 * (q00 + c.W + 1) + ch];
-                        double Ii = (1 - ax) * (1 - ay) * I00 + ax * (1 - ay) * I10 + (1 - ax) * ay * I01 + ax * ay * I11;
-                        float gu = (float)((1 - ay) * (I10 - I00) + ay * (I11 - I01));
-                        float gv = (float)((1 - ax) * (I01 - I00) + ax * (I11 - I10));
-                        rp[ch] = Ii - (double)obs_rgb[3 * p + ch];
-                        r[1 + ch] = rp[ch];
-                        l1 += fabs(rp[ch]);
-#pragma unroll
-                        for (int m = 0; m < 6; ++m) J[1 + ch][m] = gu * dum[m] + gv * dvm[m];
-                    }
-                    if (l1 <= wt.gate_rgb) {
-#pragma unroll
-                        for (int ch = 0; ch < 3; ++ch) neq_add32(pacc, J[1 + ch], (float)rp[ch], (float)wt.w_rgb);
-                        rm |= 2;
-                    }
-                }
-                if (rm) pacc[28] = 1.0f;
-            }
-        }
+            for (int ch = 0; ch < 3; ++ch) neq_add32(pacc, J[1 + ch], (float)r[1 + ch], (float)wt.w_rgb);
+        if (rm) pacc[28] = 1.0f;
         if (Jout) {
             float4* jo = reinterpret_cast<float4*>(Jout + 24 * (long long)p);
 #pragma unroll
@@ -183,7 +196,7 @@ __device__ __forceinline__ void track_p2_block(int blk, const CamC& c, const Cam
         }
         if (resid)
             reinterpret_cast<float4*>(resid)[p] = make_float4((float)r[0], (float)r[1], (float)r[2], (float)r[3]);
-        if (rowmask) rowmask[p] = rm;
+        if (rowmask) rowmask[p] = (uint8_t)rm;
     }
     double acc[PRISM_NEQ];
 #pragma unroll
@@ -216,6 +229,102 @@ __global__ __launch_bounds__(256) void k_track_p2_batch(BatchArgs b) {
     track_p2_block(blockIdx.x - b.start[a], D.c, D.cd, &D.S->iter, &D.S->anchor, (const float*)fr.depth,
                    (const float*)fr.rgb, D.a_depth, D.a_rgb, D.a_mask, D.a_normals, D.a_nmask, D.w, nullptr, nullptr,
                    nullptr, D.partials);
+}
+
+// ---------------------------------------------------------------------------
+// the paper's pose optimiser: Adam without momentum on sampled pixels
+// ---------------------------------------------------------------------------
+// One workgroup runs the whole optimisation: at each step the 256 threads
+// evaluate the objective's rows on that step's sampled pixels (row-major
+// indices; an index outside the image is a pixel without rows; repeated
+// indices count repeatedly) at the current iterate, the gradient
+//   g = scale * sum 2 w r J + Lp e,   e = pose error of the iterate w.r.t. the prior,
+// is reduced in a fixed order, and thread 0 takes the step: second moment
+// v <- b2 v + (1 - b2) g^2 (first moment off: the step follows g itself),
+// bias-corrected vhat = v / (1 - b2^k), delta = -lr g / (sqrt(vhat) + eps),
+// iterate <- retract(iterate, delta).  scale = image pixels / sampled pixels
+// makes each step's data term an unbiased estimate of the full-image sum.
+// Skipped when the prediction already fell back (improper prior).
+__global__ __launch_bounds__(256) void k_pose_adam(prism_filter_state* __restrict__ S, CamC c, CamD cd,
+                                                   const float* __restrict__ obs_depth,
+                                                   const float* __restrict__ obs_rgb,
+                                                   const float* __restrict__ a_depth,
+                                                   const float* __restrict__ a_rgb,
+                                                   const uint8_t* __restrict__ a_mask,
+                                                   const float* __restrict__ a_normals,
+                                                   const uint8_t* __restrict__ a_nmask, WeightsC wt,
+                                                   const int32_t* __restrict__ pixels, AdamC ad) {
+    __shared__ Rel32 srel;
+    __shared__ double red[4][6];
+    __shared__ prism_pose it, prior, anchor;
+    __shared__ double Lp[36];
+    __shared__ int skip;
+    if (threadIdx.x == 0) {
+        it = S->iter;
+        prior = S->prior;
+        anchor = S->anchor;
+        skip = (S->flags & PRISM_FLAG_CHOL_FALLBACK) != 0;
+        rel_of(&it, &anchor, srel);
+    }
+    if (threadIdx.x < 36) Lp[threadIdx.x] = S->Lp[threadIdx.x];
+    __syncthreads();
+    if (skip) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int npix = c.W * c.H;
+    double v2[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // thread 0's second moments
+    double b2k = 1.0;
+    for (int step = 0; step < ad.n_steps; ++step) {
+        double g[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int j = threadIdx.x; j < ad.n_pix; j += 256) {
+            const int p = pixels[(long long)step * ad.n_pix + j];
+            if ((unsigned)p >= (unsigned)npix) continue;
+            float J[4][6];
+            double r[4];
+            int rm;
+            p2_pixel(c, cd, srel, p, obs_depth, obs_rgb, a_depth, a_rgb, a_mask, a_normals, a_nmask, wt, J, r, rm);
+            if (rm & 1)
+#pragma unroll
+                for (int m = 0; m < 6; ++m) g[m] += wt.w_depth * r[0] * (double)J[0][m];
+            if (rm & 2)
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch)
+#pragma unroll
+                    for (int m = 0; m < 6; ++m) g[m] += wt.w_rgb * r[1 + ch] * (double)J[1 + ch][m];
+        }
+#pragma unroll
+        for (int m = 0; m < 6; ++m)
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) g[m] += __shfl_xor(g[m], off, 64);
+        if (lane == 0)
+#pragma unroll
+            for (int m = 0; m < 6; ++m) red[wv][m] = g[m];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double e[6], d[6];
+            pose_err(it, prior, e);
+            b2k *= ad.beta2;
+            for (int i = 0; i < 6; ++i) {
+                double gi = 2.0 * ad.scale * ((red[0][i] + red[1][i]) + (red[2][i] + red[3][i]));
+                for (int k = 0; k < 6; ++k) gi += Lp[i * 6 + k] * e[k];
+                v2[i] = ad.beta2 * v2[i] + (1.0 - ad.beta2) * gi * gi;
+                const double vhat = v2[i] / (1.0 - b2k);
+                d[i] = -ad.lr[i] * gi / (sqrt(vhat) + ad.eps);
+            }
+            retract(it, d);
+            rel_of(&it, &anchor, srel);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) S->iter = it;
+}
+
+hipError_t launch_pose_adam(prism_filter_state* S, const CamC& c, const CamD& cd, const float* obs_depth,
+                            const float* obs_rgb, const float* a_depth, const float* a_rgb, const uint8_t* a_mask,
+                            const float* a_normals, const uint8_t* a_nmask, const WeightsC& w, const int32_t* pixels,
+                            const AdamC& ad, hipStream_t st) {
+    k_pose_adam<<<1, 256, 0, st>>>(S, c, cd, obs_depth, obs_rgb, a_depth, a_rgb, a_mask, a_normals, a_nmask, w, pixels,
+                                   ad);
+    return hipGetLastError();
 }
 
 int track_blocks(const CamC& c) { return (c.W * c.H + 255) / 256; }

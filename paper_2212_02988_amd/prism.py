@@ -96,6 +96,16 @@ class Frame(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_void_p), ("rgb", ctypes.c_void_p), ("u", ctypes.c_void_p)]
 
 
+class AdamParams(ctypes.Structure):
+    """The paper's pose optimiser (App. G): Adam without momentum."""
+    _fields_ = [("n_steps", ctypes.c_int32), ("n_pixels", ctypes.c_int32), ("lr_t", ctypes.c_double),
+                ("lr_r", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double)]
+
+    @staticmethod
+    def make(n_steps=1000, n_pixels=200, lr_t=0.001, lr_r=0.00036, beta2=0.999, eps=1e-8) -> "AdamParams":
+        return AdamParams(n_steps, n_pixels, lr_t, lr_r, beta2, eps)
+
+
 # ---------------------------------------------------------------------------
 # loading
 # ---------------------------------------------------------------------------
@@ -129,6 +139,8 @@ _SIGS = {
     "prism_filter_destroy": (["p"], None),
     "prism_filter_reset": (["p", "p", "p", "p"], None),
     "prism_pose_update": (["p", "p", "p"], None),
+    "prism_pose_update_adam": (["p", "p", "p", "p", "p"], None),
+    "prism_filter_step_adam": (["p", "p", "p", "p", "p"], None),
     "prism_filter_step": (["p", ctypes.c_int32, "p", "p"], None),
     "prism_filter_step_graph": (["p", ctypes.c_int32, "p", "p"], None),
     "prism_filter_set_slots": (["p", ctypes.c_int32, "p"], None),
@@ -549,6 +561,19 @@ class Filter:
     def pose_update(self, depth, rgb, u, stream=None):
         fr = self.frame(depth, rgb, u)
         _check(lib().prism_pose_update(self.h, _by(fr), _stream(stream)))
+
+    def _adam_args(self, params: AdamParams, pixels: torch.Tensor):
+        _dev(pixels, torch.int32, "pixels", (params.n_steps, params.n_pixels))
+        return _by(params), _ptr(pixels)
+
+    def pose_update_adam(self, depth, rgb, u, params: AdamParams, pixels: torch.Tensor, stream=None):
+        """State filter with the paper's optimiser; pixels: int32 [n_steps, n_pixels]."""
+        fr = self.frame(depth, rgb, u)
+        _check(lib().prism_pose_update_adam(self.h, _by(fr), *self._adam_args(params, pixels), _stream(stream)))
+
+    def step_adam(self, depth, rgb, u, params: AdamParams, pixels: torch.Tensor, stream=None):
+        fr = self.frame(depth, rgb, u)
+        _check(lib().prism_filter_step_adam(self.h, _by(fr), *self._adam_args(params, pixels), _stream(stream)))
 
     def state(self) -> FilterState:
         """Synchronous read-back of the device state."""

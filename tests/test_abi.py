@@ -36,7 +36,7 @@ def test_struct_mirrors(P):
     for name, cls in [("prism_grid", P.Grid), ("prism_camera", P.Camera), ("prism_pose", P.Pose),
                       ("prism_weights", P.Weights), ("prism_map_params", P.MapParams),
                       ("prism_filter_cfg", P.FilterCfg), ("prism_filter_state", P.FilterState),
-                      ("prism_frame", P.Frame)]:
+                      ("prism_frame", P.Frame), ("prism_adam_params", P.AdamParams)]:
         assert L.prism_sizeof(name.encode()) == ctypes.sizeof(cls), name
     assert L.prism_sizeof(b"nope") == 0
 

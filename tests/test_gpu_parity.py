@@ -590,3 +590,66 @@ def test_map_gd_edge_cases():
     with pytest.raises(P().PrismError, match="FP32"):
         P().map_gd(gb, vb, cam, pt, t(c["depth"][0]), t(c["rgb"][0]), w, 1e-6, 1e-3, 1,
                    P().map_gd_workspace(gb, cam))
+
+
+# ---------------------------------------------------------------------------
+# the paper's pose optimiser (Adam without momentum on sampled pixels)
+# ---------------------------------------------------------------------------
+def test_filter_adam_matches_oracle():
+    """Filter steps whose state filter is the App. G optimiser (100 steps of
+    200 sampled pixels, some indices repeated or outside the image) against
+    the oracle filter on the same frames and samples."""
+    banner("filter adam 64^3 80x60, 2 steps x 100 Adam steps")
+    c = synth.trajectory_case(seed=2, n=64, width=80, height=60, n_samples=32, n_frames=3)
+    tr = c["traj"]
+    g = grid_of(c["scene"], 0)
+    f = P().Filter(g, cam_of(c["cam"]), P().FilterParams(objective=0))
+    f.map.init()
+    x0 = np.concatenate([tr.t[0], tr.q[0], tr.v[0], tr.w[0]])
+    P0 = np.diag([1e-6] * 6 + [1e-4] * 6)
+    f.reset(x0, P0)
+    og = orc.grid_from_scene(c["scene"])
+    mean = np.zeros((4, 64, 64, 64)); mean[0] = np.float32(-0.001)
+    of = orc.Filter(og, orc.cam_from(c["cam"]), orc.Params(objective="p2"),
+                    dict(t=tr.t[0], q=tr.q[0], v=tr.v[0], w=tr.w[0]), P0, mean, np.full_like(mean, 1e4))
+    ap = P().AdamParams.make(n_steps=100, n_pixels=200)
+    H, W = c["cam"].height, c["cam"].width
+    for i in range(3):
+        pix = synth.sample_pixels(10 + i, ap.n_steps, ap.n_pixels, H, W)
+        pix[3, :4] = pix[3, 4:8]
+        pix[5, 0], pix[7, 1] = -1, H * W + 5
+        u = tr.u[i - 1] if i else None
+        f.step_adam(t(c["depth"][i]), t(c["rgb"][i]), t(u, torch.float64) if i else None, ap,
+                    t(pix, torch.int32))
+        of.step(c["depth"][i].astype(np.float64), c["rgb"][i].astype(np.float64), u,
+                adam=dict(pixels=pix, lr_t=ap.lr_t, lr_r=ap.lr_r, beta2=ap.beta2, eps=ap.eps))
+        s = f.state()
+        dt_ = np.linalg.norm(np.array(s.pose.t) - of.s.t)
+        dr = rot_angle(np.array(s.pose.q), of.s.q)
+        print(f"step {i}: flags {s.flags} |dt| {dt_:.3e} dR {dr:.3e} (moved {np.linalg.norm(of.s.t - tr.t[i]):.4f} "
+              f"m from truth)", flush=True)
+        assert s.flags == 0
+        assert dt_ <= 1e-5 and dr <= 1e-5
+        Pg = np.array(s.P).reshape(12, 12)
+        assert np.linalg.norm(Pg - of.s.P) <= 1e-4 * np.linalg.norm(of.s.P)
+        assert abs(int(s.n_updated) - of.s.last["n_updated"]) <= max(10, 1e-4 * of.s.last["n_updated"])
+
+
+def test_adam_rejects_p1_and_bad_samples():
+    banner("adam argument checks")
+    c = synth.trajectory_case(seed=2, n=64, width=80, height=60, n_samples=32, n_frames=1)
+    g = grid_of(c["scene"], 0)
+    ap = P().AdamParams.make(n_steps=4, n_pixels=8)
+    pix = torch.zeros((4, 8), dtype=torch.int32, device=DEV)
+    f1 = P().Filter(g, cam_of(c["cam"]), P().FilterParams(objective=1))
+    f1.map.init()
+    with pytest.raises(P().PrismError, match="P2"):
+        f1.step_adam(t(c["depth"][0]), t(c["rgb"][0]), None, ap, pix)
+    f2 = P().Filter(g, cam_of(c["cam"]), P().FilterParams(objective=0))
+    f2.map.init()
+    with pytest.raises(P().PrismError, match="n_pixels"):
+        f2.step_adam(t(c["depth"][0]), t(c["rgb"][0]), None, P().AdamParams.make(n_steps=4, n_pixels=0),
+                     torch.zeros((4, 0), dtype=torch.int32, device=DEV))
+    with pytest.raises(P().PrismError, match="beta2"):
+        f2.step_adam(t(c["depth"][0]), t(c["rgb"][0]), None, P().AdamParams.make(n_steps=4, n_pixels=8, beta2=1.0),
+                     pix)
