@@ -32,12 +32,12 @@ __device__ __forceinline__ void rel_of(const prism_pose* pose, const prism_pose*
 // (bilinear anchor colour minus the observation), residuals in double
 // precision, Jacobians w.r.t. the pose perturbation in single precision.
 // rm: bit 0 the geometric row passed its gate, bit 1 the colour rows.
-__device__ __forceinline__ void p2_pixel(const CamC& c, const CamD& cd, const Rel32& rel, int p,
-                                         const float* __restrict__ obs_depth, const float* __restrict__ obs_rgb,
-                                         const float* __restrict__ a_depth, const float* __restrict__ a_rgb,
-                                         const uint8_t* __restrict__ a_mask, const float* __restrict__ a_normals,
-                                         const uint8_t* __restrict__ a_nmask, const WeightsC& wt, float J[4][6],
-                                         double r[4], int& rm) {
+// D and orgb: the pixel's observed depth and colour (loaded by the caller).
+__device__ __forceinline__ void p2_pixel(const CamC& c, const CamD& cd, const Rel32& rel, int p, float D,
+                                         const float orgb[3], const float* __restrict__ a_depth,
+                                         const float* __restrict__ a_rgb, const uint8_t* __restrict__ a_mask,
+                                         const float* __restrict__ a_normals, const uint8_t* __restrict__ a_nmask,
+                                         const WeightsC& wt, float J[4][6], double r[4], int& rm) {
     const int u = p % c.W, v = p / c.W;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
@@ -46,7 +46,6 @@ __device__ __forceinline__ void p2_pixel(const CamC& c, const CamD& cd, const Re
         for (int m = 0; m < 6; ++m) J[a][m] = 0.0f;
     }
     rm = 0;
-    float D = obs_depth[p];
     if (!depth_ok(D)) return;
     float rx = ((float)u + 0.5f - c.cx) * c.ifx;
     float ry = ((float)v + 0.5f - c.cy) * c.ify;
@@ -141,7 +140,7 @@ __device__ __forceinline__ void p2_pixel(const CamC& c, const CamD& cd, const Re
             double Ii = (1 - ax) * (1 - ay) * I00 + ax * (1 - ay) * I10 + (1 - ax) * ay * I01 + ax * ay * I11;
             float gu = (float)((1 - ay) * (I10 - I00) + ay * (I11 - I01));
             float gv = (float)((1 - ax) * (I01 - I00) + ax * (I11 - I10));
-            double rp = Ii - (double)obs_rgb[3 * p + ch];
+            double rp = Ii - (double)orgb[ch];
             r[1 + ch] = rp;
             l1 += fabs(rp);
 #pragma unroll
@@ -181,7 +180,8 @@ __device__ __forceinline__ void track_p2_block(int blk, const CamC& c, const Cam
         float J[4][6];
         double r[4];
         int rm;
-        p2_pixel(c, cd, rel, p, obs_depth, obs_rgb, a_depth, a_rgb, a_mask, a_normals, a_nmask, wt, J, r, rm);
+        const float orgb[3] = {obs_rgb[3 * p], obs_rgb[3 * p + 1], obs_rgb[3 * p + 2]};
+        p2_pixel(c, cd, rel, p, obs_depth[p], orgb, a_depth, a_rgb, a_mask, a_normals, a_nmask, wt, J, r, rm);
         if (rm & 1) neq_add32(pacc, J[0], (float)r[0], (float)wt.w_depth);
         if (rm & 2)
 #pragma unroll
@@ -239,12 +239,36 @@ __global__ __launch_bounds__(256) void k_track_p2_batch(BatchArgs b) {
 // indices; an index outside the image is a pixel without rows; repeated
 // indices count repeatedly) at the current iterate, the gradient
 //   g = scale * sum 2 w r J + Lp e,   e = pose error of the iterate w.r.t. the prior,
-// is reduced in a fixed order, and thread 0 takes the step: second moment
+// is reduced in a fixed order, and the step is taken: second moment
 // v <- b2 v + (1 - b2) g^2 (first moment off: the step follows g itself),
 // bias-corrected vhat = v / (1 - b2^k), delta = -lr g / (sqrt(vhat) + eps),
 // iterate <- retract(iterate, delta).  scale = image pixels / sampled pixels
 // makes each step's data term an unbiased estimate of the full-image sum.
+// The serial part of a step is kept short: the prior term Lp e is formed by
+// the last thread while the others evaluate pixels, the six components'
+// moments by six lanes, and the iterate is carried as a rotation matrix
+// (converted back to a quaternion once, at the end).
 // Skipped when the prediction already fell back (improper prior).
+
+// Exp of a rotation vector; the series of sin(th)/th and (1 - cos(th))/th^2
+// to th^8 is exact in double precision below th = 0.01
+__device__ inline void so3_exp_step(const double w[3], double E[9]) {
+    const double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    if (th2 >= 1e-4) {
+        so3_exp(w, E, nullptr);
+        return;
+    }
+    const double A = 1.0 - th2 / 6.0 * (1.0 - th2 / 20.0 * (1.0 - th2 / 42.0 * (1.0 - th2 / 72.0)));
+    const double B = 0.5 * (1.0 - th2 / 12.0 * (1.0 - th2 / 30.0 * (1.0 - th2 / 56.0 * (1.0 - th2 / 90.0))));
+    double K[9], K2[9];
+    skew(w, K);
+    mat3mul(K, K, K2);
+    for (int i = 0; i < 9; ++i) E[i] = A * K[i] + B * K2[i];
+    E[0] += 1.0;
+    E[4] += 1.0;
+    E[8] += 1.0;
+}
+
 __global__ __launch_bounds__(256) void k_pose_adam(prism_filter_state* __restrict__ S, CamC c, CamD cd,
                                                    const float* __restrict__ obs_depth,
                                                    const float* __restrict__ obs_rgb,
@@ -254,34 +278,71 @@ __global__ __launch_bounds__(256) void k_pose_adam(prism_filter_state* __restric
                                                    const float* __restrict__ a_normals,
                                                    const uint8_t* __restrict__ a_nmask, WeightsC wt,
                                                    const int32_t* __restrict__ pixels, AdamC ad) {
-    __shared__ Rel32 srel;
+    __shared__ Rel32 srel;   // cur: the iterate (double R, t); prev: the anchor pose
     __shared__ double red[4][6];
-    __shared__ prism_pose it, prior, anchor;
+    __shared__ double lpe[6];
+    __shared__ double Rp[9], tp[3];
     __shared__ double Lp[36];
     __shared__ int skip;
     if (threadIdx.x == 0) {
-        it = S->iter;
-        prior = S->prior;
-        anchor = S->anchor;
+        const prism_pose it = S->iter, pr = S->prior, an = S->anchor;
         skip = (S->flags & PRISM_FLAG_CHOL_FALLBACK) != 0;
-        rel_of(&it, &anchor, srel);
+        rel_of(&it, &an, srel);
+        quat_to_R9(pr.q, Rp);
+        for (int i = 0; i < 3; ++i) tp[i] = pr.t[i];
     }
     if (threadIdx.x < 36) Lp[threadIdx.x] = S->Lp[threadIdx.x];
     __syncthreads();
     if (skip) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int npix = c.W * c.H;
-    double v2[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // thread 0's second moments
-    double b2k = 1.0;
+    double v2 = 0.0, b2k = 1.0;   // lanes 0..5 of wave 0: second moment of their component
+    // the observation at a thread's first sampled pixel does not depend on
+    // the pose: it is loaded one step ahead
+    auto fetch = [&](int step, int& p, float& D, float rgb[3]) {
+        p = -1;
+        if ((int)threadIdx.x < ad.n_pix) {
+            p = pixels[(long long)step * ad.n_pix + threadIdx.x];
+            if ((unsigned)p < (unsigned)npix) {
+                D = obs_depth[p];
+                rgb[0] = obs_rgb[3 * p];
+                rgb[1] = obs_rgb[3 * p + 1];
+                rgb[2] = obs_rgb[3 * p + 2];
+            } else {
+                p = -1;
+            }
+        }
+    };
+    int pn;
+    float Dn = 0.0f, cn[3] = {0.0f, 0.0f, 0.0f};
+    fetch(0, pn, Dn, cn);
     for (int step = 0; step < ad.n_steps; ++step) {
         double g[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        const int p0 = pn;
+        const float D0 = Dn, c0[3] = {cn[0], cn[1], cn[2]};
+        if (step + 1 < ad.n_steps) fetch(step + 1, pn, Dn, cn);
         for (int j = threadIdx.x; j < ad.n_pix; j += 256) {
-            const int p = pixels[(long long)step * ad.n_pix + j];
-            if ((unsigned)p >= (unsigned)npix) continue;
+            int p;
+            float D, orgb[3];
+            if (j == (int)threadIdx.x) {
+                p = p0;
+                D = D0;
+                orgb[0] = c0[0];
+                orgb[1] = c0[1];
+                orgb[2] = c0[2];
+                if (p < 0) continue;
+            } else {
+                p = pixels[(long long)step * ad.n_pix + j];
+                if ((unsigned)p >= (unsigned)npix) continue;
+                D = obs_depth[p];
+                orgb[0] = obs_rgb[3 * p];
+                orgb[1] = obs_rgb[3 * p + 1];
+                orgb[2] = obs_rgb[3 * p + 2];
+            }
             float J[4][6];
             double r[4];
             int rm;
-            p2_pixel(c, cd, srel, p, obs_depth, obs_rgb, a_depth, a_rgb, a_mask, a_normals, a_nmask, wt, J, r, rm);
+            p2_pixel(c, cd, srel, p, D, orgb, a_depth, a_rgb, a_mask, a_normals, a_nmask, wt, J, r, rm);
             if (rm & 1)
 #pragma unroll
                 for (int m = 0; m < 6; ++m) g[m] += wt.w_depth * r[0] * (double)J[0][m];
@@ -291,6 +352,21 @@ __global__ __launch_bounds__(256) void k_pose_adam(prism_filter_state* __restric
 #pragma unroll
                     for (int m = 0; m < 6; ++m) g[m] += wt.w_rgb * r[1 + ch] * (double)J[1 + ch][m];
         }
+        if (threadIdx.x == 255) {
+            // prior term at the current iterate: e = (t - tp, Log(R Rp^T))
+            double M[9], e[6];
+            for (int i = 0; i < 3; ++i)
+                for (int k = 0; k < 3; ++k)
+                    M[i * 3 + k] = srel.cur.R[i][0] * Rp[k * 3] + srel.cur.R[i][1] * Rp[k * 3 + 1] +
+                                   srel.cur.R[i][2] * Rp[k * 3 + 2];
+            for (int i = 0; i < 3; ++i) e[i] = srel.cur.t[i] - tp[i];
+            so3_log(M, e + 3);
+            for (int i = 0; i < 6; ++i) {
+                double s = 0.0;
+                for (int k = 0; k < 6; ++k) s += Lp[i * 6 + k] * e[k];
+                lpe[i] = s;
+            }
+        }
 #pragma unroll
         for (int m = 0; m < 6; ++m)
 #pragma unroll
@@ -299,23 +375,53 @@ __global__ __launch_bounds__(256) void k_pose_adam(prism_filter_state* __restric
 #pragma unroll
             for (int m = 0; m < 6; ++m) red[wv][m] = g[m];
         __syncthreads();
-        if (threadIdx.x == 0) {
-            double e[6], d[6];
-            pose_err(it, prior, e);
-            b2k *= ad.beta2;
-            for (int i = 0; i < 6; ++i) {
-                double gi = 2.0 * ad.scale * ((red[0][i] + red[1][i]) + (red[2][i] + red[3][i]));
-                for (int k = 0; k < 6; ++k) gi += Lp[i * 6 + k] * e[k];
-                v2[i] = ad.beta2 * v2[i] + (1.0 - ad.beta2) * gi * gi;
-                const double vhat = v2[i] / (1.0 - b2k);
-                d[i] = -ad.lr[i] * gi / (sqrt(vhat) + ad.eps);
+        if (wv == 0) {
+            double di = 0.0;
+            if (lane < 6) {
+                const double gi = 2.0 * ad.scale * ((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane])) +
+                                  lpe[lane];
+                b2k *= ad.beta2;
+                v2 = ad.beta2 * v2 + (1.0 - ad.beta2) * gi * gi;
+                const double vhat = v2 / (1.0 - b2k);
+                di = -ad.lr[lane] * gi / (sqrt(vhat) + ad.eps);
             }
-            retract(it, d);
-            rel_of(&it, &anchor, srel);
+            double d[6];
+#pragma unroll
+            for (int m = 0; m < 6; ++m) d[m] = __shfl(di, m, 64);
+            if (lane == 0) {
+                double E[9], R[9], R2[9];
+                so3_exp_step(d + 3, E);
+                for (int i = 0; i < 3; ++i)
+                    for (int k = 0; k < 3; ++k) R[i * 3 + k] = srel.cur.R[i][k];
+                mat3mul(E, R, R2);
+                const Pose64& Q = srel.prev;
+                double t[3], dd[3];
+                for (int i = 0; i < 3; ++i) {
+                    t[i] = srel.cur.t[i] + d[i];
+                    dd[i] = t[i] - Q.t[i];
+                }
+                for (int a = 0; a < 3; ++a) {
+                    for (int b = 0; b < 3; ++b)
+                        srel.R[a][b] = (float)((Q.R[0][a] * R2[b] + Q.R[1][a] * R2[3 + b]) + Q.R[2][a] * R2[6 + b]);
+                    srel.t[a] = (float)((Q.R[0][a] * dd[0] + Q.R[1][a] * dd[1]) + Q.R[2][a] * dd[2]);
+                }
+                for (int i = 0; i < 3; ++i) {
+                    srel.cur.t[i] = t[i];
+                    for (int k = 0; k < 3; ++k) srel.cur.R[i][k] = R2[i * 3 + k];
+                }
+            }
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) S->iter = it;
+    if (threadIdx.x == 0) {
+        double R[9];
+        for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 3; ++k) R[i * 3 + k] = srel.cur.R[i][k];
+        prism_pose it;
+        for (int i = 0; i < 3; ++i) it.t[i] = srel.cur.t[i];
+        R9_to_quat(R, it.q);
+        S->iter = it;
+    }
 }
 
 hipError_t launch_pose_adam(prism_filter_state* S, const CamC& c, const CamD& cd, const float* obs_depth,
