@@ -37,6 +37,9 @@ gn_solve / laplace     Sec. 4.3.2 MAP pose + Laplace approximation;
                        Sec. 5.1 / App. G.2 Hessian as squared Jacobian, EMA 0.8
 combine                Sec. 4.3.2 product of pose posterior and velocity
                        conditional
+rollout                Sec. 6 predictive rollout: generative transition
+                       (App. B) sampled from the belief, closed-form
+                       predicted moments (App. E.2), renders (App. B)
 filter_step            Sec. 4.3 map filter then state filter ordering
 =====================  ===================================================
 
@@ -563,6 +566,53 @@ def combine(pose_post: np.ndarray, S_pose: np.ndarray, prior_pose: np.ndarray, m
     P[6:, :6] = D @ S_pose
     P[6:, 6:] = S_v + D @ S_pose @ D.T
     return v_mean, 0.5 * (P + P.T)
+
+
+def transition_sample(x: Dict[str, np.ndarray], u: np.ndarray, n: np.ndarray, dt: float) -> Dict[str, np.ndarray]:
+    """One draw of the generative transition (App. B): Euler integration with
+    additive noise n = (n_t, n_theta, n_v, n_w): velocities first, then the
+    position with the new velocity, the rotation by Exp(w' dt) and the
+    rotation noise on the left."""
+    v = x["v"] + u[:3] * dt + n[6:9]
+    w = x["w"] + u[3:] * dt + n[9:12]
+    t = x["t"] + v * dt + n[0:3]
+    R = so3_exp(n[3:6]) @ so3_exp(w * dt) @ quat_to_rot(x["q"])
+    return dict(t=t, q=rot_to_quat(R), v=v, w=w)
+
+
+def rollout(grid: Grid, mean: np.ndarray, cam: Cam, x: Dict[str, np.ndarray], P: np.ndarray, u: np.ndarray,
+            noise: np.ndarray, params: Params, decide32: bool = True, frames: bool = True):
+    """Predictive rollout (Sec. 6): from the belief N(x, P) and the map means,
+    under controls u [k][6]: for each sample s the start state x (+) L z[s,0]
+    (P = L L^T; tangent order t, theta, v, w) and k draws of the transition
+    with noise sqrt(diag Q) z[s,j+1]; the closed-form predicted moments after
+    each control; the frames rendered at every sampled pose."""
+    k = len(u)
+    sig = np.sqrt([params.sigma_pose_t ** 2] * 3 + [params.sigma_pose_r ** 2] * 3 +
+                  [params.sigma_vel_t ** 2] * 3 + [params.sigma_vel_r ** 2] * 3)
+    try:
+        L = np.linalg.cholesky(P)
+        ok = True
+    except np.linalg.LinAlgError:
+        L, ok = np.zeros((12, 12)), False
+    poses = np.zeros((len(noise), k, 7))
+    for s in range(len(noise)):
+        e = L @ noise[s, 0]
+        p0 = retract(np.concatenate([x["t"], x["q"]]), e[:6])
+        xs = dict(t=p0[:3], q=p0[3:], v=x["v"] + e[6:9], w=x["w"] + e[9:12])
+        for j in range(k):
+            xs = transition_sample(xs, u[j], sig * noise[s, j + 1], params.dt)
+            poses[s, j] = np.concatenate([xs["t"], xs["q"]])
+    means, covs = np.zeros((k, 13)), np.zeros((k, 12, 12))
+    xm, Pm = dict(x), P
+    for j in range(k):
+        xm, Pm = predict(xm, Pm, u[j], params)
+        means[j] = np.concatenate([xm["t"], xm["q"], xm["v"], xm["w"]])
+        covs[j] = Pm
+    out = dict(poses=poses, mean=means, cov=covs, ok=ok)
+    if frames:
+        out["frames"] = [render(grid, mean, cam, poses[s, j], decide32) for s in range(len(noise)) for j in range(k)]
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -910,3 +910,54 @@ def test_filter_keeps_prediction_for_improper_covariance(orc):
         assert np.array_equal(getattr(f.s, k), xn[k])
     assert np.array_equal(f.s.P, Pm)
     assert np.array_equal(f.s.anchor_pose, np.concatenate([xn["t"], xn["q"]]))
+
+
+# ---------------------------------------------------------------------------
+# predictive rollouts (Sec. 6)
+# ---------------------------------------------------------------------------
+def _rollout_belief(rng):
+    x = dict(t=np.array([1.0, 2.0, 1.5]), q=np.array([0.9, 0.1, -0.2, 0.3]) / np.linalg.norm([0.9, 0.1, -0.2, 0.3]),
+             v=np.array([0.3, -0.1, 0.05]), w=np.array([0.2, 0.4, -0.3]))
+    A = rng.normal(size=(12, 12)) * 0.01
+    P = A @ A.T + np.diag([1e-5] * 6 + [1e-4] * 6)
+    u = rng.normal(size=(5, 6))
+    return x, P, u
+
+
+def test_rollout_without_noise_follows_the_predicted_mean(orc):
+    """Zero draws: every sampled trajectory is the noise-free transition of
+    the mean, i.e. the closed-form predicted means."""
+    rng = np.random.default_rng(0)
+    x, P, u = _rollout_belief(rng)
+    out = orc.rollout(None, None, None, x, P, u, np.zeros((2, 6, 12)), orc.Params(), frames=False)
+    for s in range(2):
+        np.testing.assert_allclose(out["poses"][s, :, :3], out["mean"][:, :3], rtol=0, atol=1e-12)
+        for j in range(5):
+            assert np.linalg.norm(orc.pose_error(out["poses"][s, j], out["mean"][j, :7])) < 1e-12
+
+
+def test_rollout_samples_match_the_linearised_moments(orc):
+    """Monte Carlo over the generative transition: the sampled poses' mean
+    and covariance (tangent at the predicted mean) agree with the closed-form
+    linearised prediction within sampling error."""
+    rng = np.random.default_rng(1)
+    x, P, u = _rollout_belief(rng)
+    S = 3000
+    out = orc.rollout(None, None, None, x, P, u, rng.normal(size=(S, 6, 12)), orc.Params(), frames=False)
+    for j in (0, 4):
+        e = np.array([orc.pose_error(out["poses"][s, j], out["mean"][j, :7]) for s in range(S)])
+        C = out["cov"][j][:6, :6]
+        sd = np.sqrt(np.diag(C))
+        assert np.all(np.abs(e.mean(0)) < 4 * sd / np.sqrt(S) + 1e-3 * sd)
+        Ce = np.cov(e.T)
+        assert np.linalg.norm(Ce - C) < 0.1 * np.linalg.norm(C), (j, np.linalg.norm(Ce - C) / np.linalg.norm(C))
+
+
+def test_rollout_improper_covariance_starts_at_the_mean(orc):
+    rng = np.random.default_rng(2)
+    x, _, u = _rollout_belief(rng)
+    z = rng.normal(size=(1, 6, 12))
+    z[:, 1:] = 0.0
+    out = orc.rollout(None, None, None, x, -np.eye(12), u, z, orc.Params(), frames=False)
+    assert not out["ok"]
+    assert np.linalg.norm(orc.pose_error(out["poses"][0, 0], out["mean"][0, :7])) < 1e-12
