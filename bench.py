@@ -210,6 +210,12 @@ def single_stream(P, torch, steps, warmup):
     ms_vjp8 = timed(lambda: P.render_vjp(grid, f.map, cam, poses, r8["hit_k"], g_d, g_c, grad_mean=gm, ws=ws,
                                          stream=stream), 20)
     del gm
+    # predictive rollout from the current belief: 16 sampled trajectories x
+    # 10 steps, every predicted frame rendered
+    k_roll, s_roll = 10, 16
+    u_roll = torch.zeros((k_roll, 6), dtype=torch.float64, device=dev)
+    z_roll = torch.randn((s_roll, k_roll + 1, 12), generator=gen, device=dev, dtype=torch.float64)
+    ms_roll = timed(lambda: f.rollout(u_roll, z_roll, moments=True, frames=True, stream=stream), 5)
     pose_last = P.poses_tensor(np.concatenate([np.array(st.pose.t), np.array(st.pose.q)]))
     rout = P.render(grid, f.map, cam, pose_last, stream=stream)
     ms_r = timed(lambda: P.render(grid, f.map, cam, pose_last, out=rout, stream=stream), 50)
@@ -237,9 +243,11 @@ def single_stream(P, torch, steps, warmup):
     mu_gbs = mu_bytes / (ms_mu * 1e-3) / 1e9
 
     log(f"render_jacobian 1 frame {ms_rj1 * 1e3:.1f} us, 8 frames {ms_rj8 * 1e3:.1f} us; render {ms_r * 1e3:.1f} us; "
-        f"adjoint 8 frames {ms_vjp8 * 1e3:.1f} us; map_update call {ms_mu * 1e3:.1f} us ({mu_gbs:.0f} GB/s), "
+        f"adjoint 8 frames {ms_vjp8 * 1e3:.1f} us; rollout 16 x 10 frames {ms_roll:.3f} ms; "
+        f"map_update call {ms_mu * 1e3:.1f} us ({mu_gbs:.0f} GB/s), "
         f"{n_upd:.0f} voxels")
-    return dict(us_vjp8=ms_vjp8 * 1e3, mrays_vjp8=8 * rays / (ms_vjp8 * 1e-3) / 1e6,
+    return dict(us_vjp8=ms_vjp8 * 1e3, mrays_vjp8=8 * rays / (ms_vjp8 * 1e-3) / 1e6, ms_roll=ms_roll,
+                mrays_roll=s_roll * k_roll * rays / (ms_roll * 1e-3) / 1e6,
         ms_per_step=ms, p50_ms=float(np.percentile(per, 50)), p99_ms=float(np.percentile(per, 99)),
         pos_err=pos_err, mrays_1=rays / (ms_rj1 * 1e-3) / 1e6, mrays_8=8 * rays / (ms_rj8 * 1e-3) / 1e6,
         us_rj1=ms_rj1 * 1e3, us_rj8=ms_rj8 * 1e3, us_render=ms_r * 1e3, us_mu=ms_mu * 1e3,
@@ -614,6 +622,9 @@ def main():
         "kernels_us": {"render_jacobian_1f": r(single["us_rj1"], 2), "render_jacobian_8f": r(single["us_rj8"], 2),
                        "render": r(single["us_render"], 2), "render_vjp_8f": r(single["us_vjp8"], 2),
                        "map_update": r(single["us_mu"], 2)},
+        "rollout": {"workload": "16 sampled trajectories x 10 steps from the belief, moments and all 160 frames "
+                                "rendered; 256^3 FP32, 320x240, K = 128",
+                    "ms": r(single["ms_roll"], 3), "mrays_per_s": r(single["mrays_roll"], 1)},
         "mapping_gd_vs_closed_form": mapping,
         "pose_optimisers": optimisers,
         "roofline": roofline_obj(dominant, dom_roof, breakdown),

@@ -429,6 +429,31 @@ prism_status prism_filter_step_adam(prism_filter *f, const prism_frame *frame,
                                     const prism_adam_params *p, const int32_t *pixels,
                                     hipStream_t stream);
 
+/* Predictive rollout (Sec. 6, prediction and control): from the handle's
+ * current state belief N(x, P) and map means, predict k steps ahead under
+ * the candidate controls u[0..k) with the generative transition (App. B):
+ * n_samples sampled trajectories, their poses and (optionally) the frames
+ * rendered from the map means at every sampled pose, plus the closed-form
+ * linearised moments of the predicted state (the uncertainty envelope).
+ * u:     device double [k][6] (linear then angular acceleration, world).
+ * noise: device double [n_samples][k+1][12] standard normal draws (the
+ *        caller's): row 0 draws the start state x (+) L z (P = L L^T, tangent
+ *        order t, theta, v, w, left retraction for the pose), row j+1 the
+ *        process noise of step j, n = sqrt(diag Q) z, entering as
+ *        v' = v + u_v dt + n_v, w' = w + u_w dt + n_w, t' = t + v' dt + n_t,
+ *        R' = Exp(n_theta) Exp(w' dt) R.
+ * poses: device [n_samples][k] (required when n_samples > 0).
+ * mean:  nullable device [k][13] (t, q, v, w); cov: nullable [k][144]: the
+ *        linearised prediction (App. E.2) after each control.
+ * depth/rgb/mask: nullable together, [n_samples*k][H][W] (rgb [..][3]), as
+ *        prism_render at poses (sample-major); needs n_samples*k <= 65535.
+ * flags: nullable device int32: PRISM_FLAG_CHOL_FALLBACK when P is not
+ *        positive definite (the samples then start at the mean), else 0. */
+prism_status prism_rollout(prism_filter *f, const double *u, int32_t k, int32_t n_samples,
+                           const double *noise, prism_pose *poses, double *mean, double *cov,
+                           float *depth, float *rgb, uint8_t *mask, int32_t *flags,
+                           hipStream_t stream);
+
 /* One full filter step for each of n handles (Sec. 4.3): the state filter
  * as in prism_pose_update (skipped for a filter's first frame), then the map
  * update at the posterior mean pose (App. C nominal state), then the anchor

@@ -160,6 +160,11 @@ hipError_t launch_pose_adam(prism_filter_state* S, const CamC& c, const CamD& cd
                             const float* a_normals, const uint8_t* a_nmask, const WeightsC& w, const int32_t* pixels,
                             const AdamC& ad, hipStream_t st);
 
+// predictive rollouts: sampled trajectories (n_samples x k poses) and the
+// closed-form predicted moments (nullable mean [k][13], cov [k][144])
+hipError_t launch_rollout(const prism_filter_state* S, const double* u, int k, int n_samples, const double* noise,
+                          const TransC& tc, prism_pose* poses, double* mean, double* cov, int32_t* flags,
+                          hipStream_t st);
 hipError_t launch_predict(prism_filter_state* S, const double* u, const TransC& tc, hipStream_t st);
 hipError_t launch_gn_step(prism_filter_state* S, const double* partials, int nblocks, hipStream_t st);
 hipError_t launch_laplace_combine(prism_filter_state* S, const double* partials, int nblocks, double ema,

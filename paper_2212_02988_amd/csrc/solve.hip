@@ -164,45 +164,40 @@ __device__ inline void state_out(const prism_filter_state* l, prism_filter_state
 // ---------------------------------------------------------------------------
 // predict + split
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void predict_block(prism_filter_state* __restrict__ Sg, const double* __restrict__ u,
-                                              const TransC& tc) {
-    __shared__ double M[144], G[144], T1[144], T2[144], P[144], Spp[36], L[36], Sinv[36];
-    __shared__ double vnew[6], E[9], Jl[9];
-    __shared__ int ok;
-    __shared__ prism_filter_state Ls;
-    state_in(Sg, &Ls);
-    prism_filter_state* S = &Ls;
-    if (threadIdx.x == 0) {
-        S->flags = 0;
-        for (int i = 0; i < 6; ++i) S->u[i] = u[i];
-        double v[3], w[3];
-        for (int i = 0; i < 3; ++i) {
-            v[i] = S->v[i] + u[i] * tc.dt;
-            w[i] = S->w[i] + u[3 + i] * tc.dt;
-            vnew[i] = v[i];
-            vnew[3 + i] = w[i];
-        }
-        double phi[3] = {w[0] * tc.dt, w[1] * tc.dt, w[2] * tc.dt};
-        double Ex[9], Jx[9], R[9], R2[9];
-        so3_exp(phi, Ex, Jx);
-        for (int e = 0; e < 9; ++e) { E[e] = Ex[e]; Jl[e] = Jx[e]; }
-        quat_to_R9(S->pose.q, R);
-        mat3mul(Ex, R, R2);
-        prism_pose pr;
-        for (int i = 0; i < 3; ++i) pr.t[i] = S->pose.t[i] + v[i] * tc.dt;
-        R9_to_quat(R2, pr.q);
-        S->prior = pr;
-        S->iter = pr;
-        for (int i = 0; i < 6; ++i) S->vel_prior[i] = vnew[i];
+// Mean of the Euler transition (App. B, E.1) of one state, on one thread:
+// new velocities (vnew = v', w'), E = Exp(w' dt) with its left Jacobian Jl,
+// and the new pose (t + v' dt, E R).
+__device__ inline void transition_mean_t0(const prism_pose& pose, const double* v0, const double* w0,
+                                          const double* u, const TransC& tc, double* vnew, double* E, double* Jl,
+                                          prism_pose& pr) {
+    double v[3], w[3];
+    for (int i = 0; i < 3; ++i) {
+        v[i] = v0[i] + u[i] * tc.dt;
+        w[i] = w0[i] + u[3 + i] * tc.dt;
+        vnew[i] = v[i];
+        vnew[3 + i] = w[i];
     }
+    double phi[3] = {w[0] * tc.dt, w[1] * tc.dt, w[2] * tc.dt};
+    double Ex[9], Jx[9], R[9], R2[9];
+    so3_exp(phi, Ex, Jx);
+    for (int e = 0; e < 9; ++e) { E[e] = Ex[e]; Jl[e] = Jx[e]; }
+    quat_to_R9(pose.q, R);
+    mat3mul(Ex, R, R2);
+    for (int i = 0; i < 3; ++i) pr.t[i] = pose.t[i] + v[i] * tc.dt;
+    R9_to_quat(R2, pr.q);
+}
+
+// Covariance of the linearised transition (App. E.2), whole workgroup:
+// T2 = M P M^T + G Q G^T (symmetrised) in the error state (dt, dtheta, dv,
+// dw), with E, Jl from transition_mean_t0; P, M, G, T1, T2: LDS [144].
+__device__ inline void transition_cov(const double* E, const double* Jl, const TransC& tc, const double* P,
+                                      double* M, double* G, double* T1, double* T2) {
     for (int e = threadIdx.x; e < 144; e += blockDim.x) {
-        P[e] = S->P[e];
         M[e] = 0.0;
         G[e] = 0.0;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        // error-state transition: rows/cols (dt, dtheta, dv, dw)
         for (int i = 0; i < 3; ++i) {
             M[i * 12 + i] = 1.0;
             M[i * 12 + 6 + i] = tc.dt;
@@ -232,6 +227,28 @@ __device__ __forceinline__ void predict_block(prism_filter_state* __restrict__ S
     }
     __syncthreads();
     symmetrize(T2, 12);
+}
+
+__device__ __forceinline__ void predict_block(prism_filter_state* __restrict__ Sg, const double* __restrict__ u,
+                                              const TransC& tc) {
+    __shared__ double M[144], G[144], T1[144], T2[144], P[144], Spp[36], L[36], Sinv[36];
+    __shared__ double vnew[6], E[9], Jl[9];
+    __shared__ int ok;
+    __shared__ prism_filter_state Ls;
+    state_in(Sg, &Ls);
+    prism_filter_state* S = &Ls;
+    if (threadIdx.x == 0) {
+        S->flags = 0;
+        for (int i = 0; i < 6; ++i) S->u[i] = u[i];
+        prism_pose pr;
+        transition_mean_t0(S->pose, S->v, S->w, u, tc, vnew, E, Jl, pr);
+        S->prior = pr;
+        S->iter = pr;
+        for (int i = 0; i < 6; ++i) S->vel_prior[i] = vnew[i];
+    }
+    for (int e = threadIdx.x; e < 144; e += blockDim.x) P[e] = S->P[e];
+    __syncthreads();
+    transition_cov(E, Jl, tc, P, M, G, T1, T2);
     // split: Spp, D = Svp Spp^-1, Sv = Svv - D Svp^T
     for (int e = threadIdx.x; e < 36; e += blockDim.x) {
         int i = e / 6, j = e % 6;
@@ -454,6 +471,126 @@ __global__ __launch_bounds__(512) void k_laplace_combine_batch(BatchArgs b) {
 }
 
 __global__ __launch_bounds__(64) void k_first_frame_batch(BatchArgs b) { first_frame_block(b.d[blockIdx.x]->S); }
+
+// ---------------------------------------------------------------------------
+// predictive rollouts from the state belief
+// ---------------------------------------------------------------------------
+// One workgroup per sample; its first thread draws the start state from the
+// belief, x0 = x (+) L z0 with P = L L^T (tangent order t, theta, v, w; the
+// pose part is the left retraction), then runs the generative transition
+// with process noise n = sqrt(Q) z_j for each of the k controls:
+//   v' = v + u_v dt + n_v,  w' = w + u_w dt + n_w,
+//   t' = t + v' dt + n_t,   R' = Exp(n_theta) Exp(w' dt) R.
+// If P is not positive definite every sample starts at the mean and *flags
+// gets PRISM_FLAG_CHOL_FALLBACK (else 0; written by the first workgroup).
+__global__ __launch_bounds__(64) void k_rollout_sample(const prism_filter_state* __restrict__ S,
+                                                       const double* __restrict__ u, int k,
+                                                       const double* __restrict__ noise, TransC tc,
+                                                       prism_pose* __restrict__ poses, int32_t* __restrict__ flags) {
+    __shared__ double A[144];
+    __shared__ int ok;
+    for (int e = threadIdx.x; e < 144; e += blockDim.x) A[e] = S->P[e];
+    __syncthreads();
+    if (threadIdx.x == 0) ok = chol<12>(A);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    if (blockIdx.x == 0 && flags) *flags = ok ? 0 : PRISM_FLAG_CHOL_FALLBACK;
+    const double* z = noise + (long long)blockIdx.x * (k + 1) * 12;
+    double e[12];
+    for (int i = 0; i < 12; ++i) {
+        double acc = 0.0;
+        if (ok)
+            for (int j = 0; j <= i; ++j) acc += A[i * 12 + j] * z[j];
+        e[i] = acc;
+    }
+    prism_pose x = S->pose;
+    retract(x, e);
+    double v[3], w[3], sq[12];
+    for (int i = 0; i < 3; ++i) {
+        v[i] = S->v[i] + e[6 + i];
+        w[i] = S->w[i] + e[9 + i];
+    }
+    for (int i = 0; i < 12; ++i) sq[i] = sqrt(tc.q[i]);
+    for (int j = 0; j < k; ++j) {
+        const double* zj = z + (j + 1) * 12;
+        const double* uj = u + 6 * j;
+        double n[12];
+        for (int i = 0; i < 12; ++i) n[i] = sq[i] * zj[i];
+        for (int i = 0; i < 3; ++i) {
+            v[i] = v[i] + uj[i] * tc.dt + n[6 + i];
+            w[i] = w[i] + uj[3 + i] * tc.dt + n[9 + i];
+        }
+        double phi[3] = {w[0] * tc.dt, w[1] * tc.dt, w[2] * tc.dt};
+        double E1[9], E2[9], R[9], T[9], R2[9];
+        so3_exp(n + 3, E1, nullptr);
+        so3_exp(phi, E2, nullptr);
+        quat_to_R9(x.q, R);
+        mat3mul(E2, R, T);
+        mat3mul(E1, T, R2);
+        for (int i = 0; i < 3; ++i) x.t[i] = x.t[i] + v[i] * tc.dt + n[i];
+        R9_to_quat(R2, x.q);
+        poses[(long long)blockIdx.x * k + j] = x;
+    }
+}
+
+// Closed-form (linearised) prediction of the belief over the k controls:
+// mean[j] = (t, q, v, w) after control j (13 doubles), cov[j] = its 12x12
+// covariance; the same propagation as the filter's prediction step.
+__global__ __launch_bounds__(256) void k_rollout_moments(const prism_filter_state* __restrict__ S,
+                                                         const double* __restrict__ u, int k, TransC tc,
+                                                         double* __restrict__ mean, double* __restrict__ cov) {
+    __shared__ double M[144], G[144], T1[144], T2[144], P[144];
+    __shared__ double vnew[6], E[9], Jl[9], v[3], w[3];
+    __shared__ prism_pose pose;
+    if (threadIdx.x == 0) {
+        pose = S->pose;
+        for (int i = 0; i < 3; ++i) {
+            v[i] = S->v[i];
+            w[i] = S->w[i];
+        }
+    }
+    for (int e = threadIdx.x; e < 144; e += blockDim.x) P[e] = S->P[e];
+    __syncthreads();
+    for (int j = 0; j < k; ++j) {
+        if (threadIdx.x == 0) {
+            prism_pose pr;
+            transition_mean_t0(pose, v, w, u + 6 * j, tc, vnew, E, Jl, pr);
+            pose = pr;
+            for (int i = 0; i < 3; ++i) {
+                v[i] = vnew[i];
+                w[i] = vnew[3 + i];
+            }
+            if (mean) {
+                double* m = mean + 13 * j;
+                for (int i = 0; i < 3; ++i) m[i] = pr.t[i];
+                for (int i = 0; i < 4; ++i) m[3 + i] = pr.q[i];
+                for (int i = 0; i < 6; ++i) m[7 + i] = vnew[i];
+            }
+        }
+        __syncthreads();
+        transition_cov(E, Jl, tc, P, M, G, T1, T2);
+        for (int e = threadIdx.x; e < 144; e += blockDim.x) {
+            P[e] = T2[e];
+            if (cov) cov[144 * j + e] = T2[e];
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_rollout(const prism_filter_state* S, const double* u, int k, int n_samples, const double* noise,
+                          const TransC& tc, prism_pose* poses, double* mean, double* cov, int32_t* flags,
+                          hipStream_t st) {
+    if (mean || cov) {
+        k_rollout_moments<<<1, 256, 0, st>>>(S, u, k, tc, mean, cov);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (n_samples > 0) {
+        k_rollout_sample<<<n_samples, 64, 0, st>>>(S, u, k, noise, tc, poses, flags);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
 
 // per-frame fixed-order sum of block partials; the first nvals values of
 // each frame go to out[frame * stride + q]

@@ -141,6 +141,7 @@ _SIGS = {
     "prism_pose_update": (["p", "p", "p"], None),
     "prism_pose_update_adam": (["p", "p", "p", "p", "p"], None),
     "prism_filter_step_adam": (["p", "p", "p", "p", "p"], None),
+    "prism_rollout": (["p", "p", ctypes.c_int32, ctypes.c_int32, "p", "p", "p", "p", "p", "p", "p", "p", "p"], None),
     "prism_filter_step": (["p", ctypes.c_int32, "p", "p"], None),
     "prism_filter_step_graph": (["p", ctypes.c_int32, "p", "p"], None),
     "prism_filter_set_slots": (["p", ctypes.c_int32, "p"], None),
@@ -574,6 +575,35 @@ class Filter:
     def step_adam(self, depth, rgb, u, params: AdamParams, pixels: torch.Tensor, stream=None):
         fr = self.frame(depth, rgb, u)
         _check(lib().prism_filter_step_adam(self.h, _by(fr), *self._adam_args(params, pixels), _stream(stream)))
+
+    def rollout(self, u: torch.Tensor, noise: Optional[torch.Tensor] = None, moments: bool = True,
+                frames: bool = False, stream=None) -> Dict[str, torch.Tensor]:
+        """Predictive rollout from the current belief: u float64 [k, 6]
+        controls; noise float64 [n_samples, k+1, 12] standard normals.
+        Returns poses [n_samples, k, 7], mean [k, 13] / cov [k, 12, 12] (if
+        moments), depth/rgb/mask [n_samples*k, ...] (if frames), flags [1]."""
+        k = u.shape[0]
+        _dev(u, torch.float64, "u", (k, 6))
+        dev = u.device
+        ns = 0 if noise is None else noise.shape[0]
+        if noise is not None:
+            _dev(noise, torch.float64, "noise", (ns, k + 1, 12))
+        out = dict(flags=torch.zeros(1, dtype=torch.int32, device=dev))
+        out["poses"] = torch.empty((max(ns, 1), k, 7), dtype=torch.float64, device=dev)
+        if moments:
+            out["mean"] = torch.empty((k, 13), dtype=torch.float64, device=dev)
+            out["cov"] = torch.empty((k, 12, 12), dtype=torch.float64, device=dev)
+        if frames:
+            H, W = self.cam.height, self.cam.width
+            out["depth"] = torch.empty((ns * k, H, W), dtype=torch.float32, device=dev)
+            out["rgb"] = torch.empty((ns * k, H, W, 3), dtype=torch.float32, device=dev)
+            out["mask"] = torch.empty((ns * k, H, W), dtype=torch.uint8, device=dev)
+        _check(lib().prism_rollout(self.h, _ptr(u), k, ns, _ptr(noise), _ptr(out["poses"]), _ptr(out.get("mean")),
+                                   _ptr(out.get("cov")), _ptr(out.get("depth")), _ptr(out.get("rgb")),
+                                   _ptr(out.get("mask")), _ptr(out["flags"]), _stream(stream)))
+        if ns == 0:
+            out["poses"] = out["poses"][:0]
+        return out
 
     def state(self) -> FilterState:
         """Synchronous read-back of the device state."""

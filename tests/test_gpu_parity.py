@@ -653,3 +653,61 @@ def test_adam_rejects_p1_and_bad_samples():
     with pytest.raises(P().PrismError, match="beta2"):
         f2.step_adam(t(c["depth"][0]), t(c["rgb"][0]), None, P().AdamParams.make(n_steps=4, n_pixels=8, beta2=1.0),
                      pix)
+
+
+# ---------------------------------------------------------------------------
+# predictive rollouts
+# ---------------------------------------------------------------------------
+def test_rollout_matches_oracle():
+    """Rollout from a seeded belief and the ground-truth map: sampled poses,
+    the closed-form moments and the frames rendered at the sampled poses
+    against the oracle on the same belief, map and draws."""
+    banner("rollout 64^3 80x60, 3 samples x 4 steps")
+    c = synth.trajectory_case(seed=2, n=64, width=80, height=60, n_samples=32, n_frames=1)
+    tr = c["traj"]
+    g = grid_of(c["scene"], 0)
+    cam = cam_of(c["cam"])
+    mean, var = synth.gt_map(c["scene"])
+    f = P().Filter(g, cam, P().FilterParams(objective=0), vmap=gpu_map(g, mean, var))
+    rng = np.random.default_rng(7)
+    A = rng.normal(size=(12, 12)) * 0.01
+    Pb = A @ A.T + np.diag([1e-5] * 6 + [1e-4] * 6)
+    x = dict(t=tr.t[0], q=tr.q[0], v=tr.v[0], w=tr.w[0])
+    f.reset(np.concatenate([x["t"], x["q"], x["v"], x["w"]]), Pb)
+    k, S = 4, 3
+    u = rng.normal(size=(k, 6))
+    z = rng.normal(size=(S, k + 1, 12))
+    out = f.rollout(t(u, torch.float64), t(z, torch.float64), moments=True, frames=True)
+    torch.cuda.synchronize()
+    ref = orc.rollout(orc.grid_from_scene(c["scene"]), oracle_map_values(mean, 0), orc.cam_from(c["cam"]), x, Pb,
+                      u, z, orc.Params())
+    assert int(out["flags"].item()) == 0 and ref["ok"]
+    pg = out["poses"].cpu().numpy()
+    for s in range(S):
+        for j in range(k):
+            assert np.linalg.norm(orc.pose_error(pg[s, j], ref["poses"][s, j])) < 1e-9
+    np.testing.assert_allclose(out["mean"].cpu().numpy(), ref["mean"], rtol=0, atol=1e-12)
+    cg = out["cov"].cpu().numpy()
+    assert np.linalg.norm(cg - ref["cov"]) <= 1e-10 * np.linalg.norm(ref["cov"])
+    hk_fail = 0
+    for n in range(S * k):
+        r = ref["frames"][n]
+        mk = out["mask"][n].cpu().numpy()
+        hk_fail += int((mk != r["mask"]).sum())
+        v = (mk == 1) & (r["mask"] == 1)
+        d = out["depth"][n].cpu().numpy()
+        assert np.all(depth_close(d[v], r["depth"][v]))
+        rgb = out["rgb"][n].cpu().numpy()
+        assert np.all(rgb_close(rgb[v], r["rgb"][v]))
+    print(f"mask mismatches over {S * k} frames: {hk_fail}", flush=True)
+    assert hk_fail == 0
+    # an improper covariance: flag raised, samples start at the mean
+    f.reset(np.concatenate([x["t"], x["q"], x["v"], x["w"]]), -np.eye(12))
+    z0 = z.copy()
+    z0[:, 1:] = 0.0
+    out = f.rollout(t(u, torch.float64), t(z0, torch.float64), moments=False)
+    ref = orc.rollout(None, None, None, x, -np.eye(12), u, z0, orc.Params(), frames=False)
+    assert int(out["flags"].item()) == P().FLAG_CHOL_FALLBACK and not ref["ok"]
+    pg = out["poses"].cpu().numpy()
+    for s in range(S):
+        assert np.linalg.norm(orc.pose_error(pg[s, 0], ref["poses"][s, 0])) < 1e-9
