@@ -211,6 +211,43 @@ __device__ __forceinline__ CellAddr cell_addr(const GridC& g, const Cell& c) {
 __device__ __forceinline__ float ldu(const float* p, unsigned i) { return p[i]; }
 __device__ __forceinline__ float ldu(const uint16_t* p, unsigned i) { return __uint_as_float(((uint32_t)p[i]) << 16); }
 
+// Explicit address spaces for the hottest loads: through a global-space
+// pointer with a 32-bit byte offset the compiler can use a scalar base and a
+// single vector offset register per load (instead of a flat load with a
+// 64-bit vector address), and LDS-space pointers become LDS reads.
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T*;
+using lds_u32 = const __attribute__((address_space(3))) unsigned;
+
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(const T* p) {
+    return (gptr<T>)p;
+}
+
+__device__ __forceinline__ float ldg(gptr<float> p, unsigned byte_off) {
+    return *(gptr<float>)((gptr<char>)p + byte_off);
+}
+__device__ __forceinline__ float ldg(gptr<uint16_t> p, unsigned byte_off) {
+    return __uint_as_float(((uint32_t) * (gptr<uint16_t>)((gptr<char>)p + byte_off)) << 16);
+}
+
+// corners_in through a global-space plane pointer (byte offsets; a plane is
+// at most 2^30 elements of at most 4 bytes, so offsets fit 32 bits)
+template <typename T>
+__device__ __forceinline__ void corners_in_g(gptr<T> plane, const CellAddr& a, float v[8]) {
+    constexpr unsigned sz = sizeof(T);
+    const unsigned o = (unsigned)a.base * sz, dx = (unsigned)a.dx * sz, dy = (unsigned)a.dy * sz,
+                   dz = (unsigned)a.dz * sz;
+    v[0] = ldg(plane, o);
+    v[1] = ldg(plane, o + dx);
+    v[2] = ldg(plane, o + dy);
+    v[3] = ldg(plane, o + dy + dx);
+    v[4] = ldg(plane, o + dz);
+    v[5] = ldg(plane, o + dz + dx);
+    v[6] = ldg(plane, o + dz + dy);
+    v[7] = ldg(plane, o + dz + dy + dx);
+}
+
 template <typename T>
 __device__ __forceinline__ void corners_in(const T* plane, const CellAddr& a, float v[8]) {
     const unsigned o = (unsigned)a.base;

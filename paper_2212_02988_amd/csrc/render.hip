@@ -43,9 +43,9 @@ __device__ __forceinline__ float occ_at(const GridC& g, const T* occ, const Cell
 // is <= 0 under round-to-nearest (rounding is monotonic and 0 is
 // representable), so the single-precision recipe would have produced a value
 // <= 0 as well and the sample cannot be the hit when tau == 0.
-__device__ __forceinline__ bool bit_of(const unsigned* bits, int b) { return (bits[b >> 5] >> (b & 31)) & 1u; }
+__device__ __forceinline__ bool bit_of(lds_u32* bits, int b) { return (bits[b >> 5] >> (b & 31)) & 1u; }
 
-__device__ __forceinline__ bool cell_free(const GridC& g, const unsigned* bits, const CellAddr& a) {
+__device__ __forceinline__ bool cell_free(const GridC& g, lds_u32* bits, const CellAddr& a) {
     if (!a.cross) return bit_of(bits, a.b0);
     const int sx = a.dx != 1 ? 1 : 0, sy = a.dy != 8 ? g.nb : 0, sz = a.dz != 64 ? g.nb * g.nb : 0;
     bool all = true;
@@ -56,36 +56,35 @@ __device__ __forceinline__ bool cell_free(const GridC& g, const unsigned* bits, 
 }
 
 // occupancy of a marched sample, or -1 when the free-space bits prove it is
-// <= 0 (bits non-NULL only when tau == 0)
+// <= 0 (bits: the workgroup's LDS copy, non-NULL only when tau == 0)
 template <typename T>
-__device__ __forceinline__ float march_occ(const GridC& g, const T* occ, const unsigned* bits, const Cell& cl) {
+__device__ __forceinline__ float march_occ(const GridC& g, const T* occ, lds_u32* bits, const Cell& cl) {
     if (cell_inside(g, cl)) {
         CellAddr a = cell_addr(g, cl);
         if (bits && cell_free(g, bits, a)) return -1.0f;
         float v[8];
-        corners_in(occ, a, v);
+        corners_in_g(as_global(occ), a, v);
         return trilerp(v, cl.w);
     }
     return occ_at(g, occ, cl);
 }
 
-// Free-space bits for this block: copied into LDS when they fit, else read
-// from global memory; NULL disables skipping.
-__device__ __forceinline__ const unsigned* block_bits(const GridC& g, const unsigned* __restrict__ gbits,
-                                                      unsigned* lbits) {
+// Free-space bits for this block, copied into LDS; NULL (no skipping) when
+// there are none or they do not fit (grids beyond n = 576).
+__device__ __forceinline__ lds_u32* block_bits(const GridC& g, const unsigned* __restrict__ gbits, unsigned* lbits) {
     if (!gbits) return nullptr;
     int nwords = (g.nb * g.nb * g.nb + 31) >> 5;
-    if (nwords > kMaxLdsWords) return gbits;
+    if (nwords > kMaxLdsWords) return nullptr;
     for (int i = threadIdx.x; i < nwords; i += blockDim.x) lbits[i] = gbits[i];
     __syncthreads();
-    return lbits;
+    return (lds_u32*)lbits;
 }
 
 // first sample whose occupancy exceeds tau (strictly), with the bracketing
 // cells (recomputed from k*: cheaper than keeping them in registers)
 template <typename T>
 __device__ __forceinline__ RayHit march(const GridC& g, const CamC& c, const Pose32& P,
-                                        const float dir[3], const T* occ, const unsigned* bits) {
+                                        const float dir[3], const T* occ, lds_u32* bits) {
     RayHit h;
     h.k = -1;
     h.f0 = h.f1 = 0.0f;
@@ -299,7 +298,7 @@ __device__ __forceinline__ float quad_bcastf(float x, int src_lane_in_quad) {
 // lane of the quad returns the same value
 template <typename T>
 __device__ __forceinline__ int march_quad(const GridC& g, const CamC& c, const Pose32& P, const float dir[3],
-                                          const T* occ, const unsigned* bits, int s) {
+                                          const T* occ, lds_u32* bits, int s) {
     constexpr int G = kLanes * kPerLane;
     for (int k0 = 0; k0 < c.K; k0 += G) {
         float f[kPerLane];
@@ -425,7 +424,7 @@ __device__ __forceinline__ void render_block(int blk, int frame, const GridC& g,
                                              uint8_t* __restrict__ mask, int32_t* __restrict__ hit_k) {
     __shared__ BlockPose sp;
     extern __shared__ unsigned lbits[];
-    const unsigned* bits = block_bits(g, gbits, lbits);
+    lds_u32* bits = block_bits(g, gbits, lbits);
     const BlockPose& P = block_pose(pose, &sp);
     int u, v, s;
     quad_pixel(c, blk, u, v, s);
@@ -552,7 +551,7 @@ __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, GridD gd, C
     __shared__ BlockPose sp;
     __shared__ double lds[kRedLds];
     extern __shared__ unsigned lbits[];
-    const unsigned* bits = block_bits(g, gbits, lbits);
+    lds_u32* bits = block_bits(g, gbits, lbits);
     const BlockPose& P = block_pose(poses + blockIdx.y, &sp);
     int u, v, s;
     quad_pixel(c, blockIdx.x, u, v, s);
@@ -813,7 +812,7 @@ __global__ __launch_bounds__(256) void k_gd_grad(GridC g, CamC c, GridD gd, CamD
         (&A.key[0][0])[e] = -1;
         (&A.val[0][0])[e] = 0.0;
     }
-    const unsigned* bits = block_bits(g, gbits, lbits);   // synchronises the workgroup
+    lds_u32* bits = block_bits(g, gbits, lbits);   // synchronises the workgroup
     const BlockPose& P = block_pose(pose, &sp);
     int u, v, s;
     quad_pixel(c, blockIdx.x, u, v, s);
@@ -896,8 +895,8 @@ hipError_t launch_render(const GridC& g, const CamC& c, const GridD& gd, const C
 }
 
 hipError_t launch_render_batch(const BatchArgs& b, int dtype, int max_bits_words, hipStream_t st) {
-    // filters whose bits fit copy them to LDS, the others read them from
-    // global memory (block_bits), so the allocation is the largest that fits
+    // filters whose bits fit copy them to LDS, the others march without
+    // skipping (block_bits), so the allocation is the largest that fits
     size_t lds = (size_t)(max_bits_words < kMaxLdsWords ? max_bits_words : kMaxLdsWords) * 4;
     if (dtype == PRISM_BF16)
         k_render_batch<uint16_t><<<b.start[b.n], 256, lds, st>>>(b);
