@@ -147,15 +147,20 @@ static void dec32_dir(const dec32 *d, int u, int v, float dir[3]) {
     for (int i = 0; i < 3; ++i) dir[i] = (d->R[i][0] * rx + d->R[i][1] * ry) + d->R[i][2];
 }
 
-/* occupancy at sample k along dir, single precision; also returns the cell */
+/* occupancy at sample k along dir, single precision; also returns the cell.
+ * Sample k sits at depth d_near + k*dstep along the ray (App. B sampling);
+ * its continuous grid coordinate is written as A + k*B with the per-ray
+ * terms B = (dir*dstep)/voxel and A = ((t + d_near*dir) - origin)/voxel - 1/2,
+ * in this order, 1/voxel rounded once. */
 static float dec32_sample(const dec32 *d, const double *occ, const float dir[3], int k, int cell[3]) {
-    float dk = d->dn + (float)k * d->dstep;
     float w[3];
     for (int a = 0; a < 3; ++a) {
-        float p = d->t[a] + dk * dir[a];
-        float g = (p - d->o[a]) * d->is - 0.5f;
-        g = fminf(fmaxf(g, -2.0f), (float)(d->n + 1));
-        int i0 = (int)floorf(g);
+        float B = (dir[a] * d->dstep) * d->is;
+        float A = ((d->t[a] + d->dn * dir[a]) - d->o[a]) * d->is - 0.5f;
+        float g = A + (float)k * B;
+        float fl = floorf(g);
+        /* samples more than 2^30 voxels away never reach the grid */
+        int i0 = fl < -1073741824.0f ? -1073741824 : fl > 1073741824.0f ? 1073741824 : (int)fl;
         cell[a] = i0;
         w[a] = g - (float)i0;
     }

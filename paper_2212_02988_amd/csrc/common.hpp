@@ -157,21 +157,36 @@ __device__ __forceinline__ void ray_dir32(const CamC& c, const Pose32& P, int u,
     for (int a = 0; a < 3; ++a) dir[a] = (P.R[a][0] * rx + P.R[a][1] * ry) + P.R[a][2];
 }
 
-// continuous grid coordinate of sample k, clamped; cell and weights
+// trilinear cell of a sample (base corner) and the weights within it
 struct Cell {
     int i[3];
     float w[3];
 };
 
-__device__ __forceinline__ Cell sample_cell(const GridC& g, const CamC& c, const Pose32& P,
-                                            const float dir[3], int k) {
-    Cell o;
-    float dk = c.dn + (float)k * c.dstep;
+// Per-ray coefficients of the sample recipe: the continuous grid coordinate
+// of sample k is A + k B per axis, with
+//   B = (dir * dstep) / voxel,  A = ((t + d_near dir) - origin) / voxel - 1/2
+// (single precision, this operation order, 1/voxel as a rounded factor).
+struct RayCoef {
+    float A[3], B[3];
+};
+
+__device__ __forceinline__ RayCoef ray_coef(const GridC& g, const CamC& c, const Pose32& P, const float dir[3]) {
+    RayCoef r;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        float p = P.t[a] + dk * dir[a];
-        float gc = (p - g.o[a]) * g.inv_s - 0.5f;
-        gc = fminf(fmaxf(gc, -2.0f), (float)(g.n + 1));
+        r.B[a] = (dir[a] * c.dstep) * g.inv_s;
+        r.A[a] = ((P.t[a] + c.dn * dir[a]) - g.o[a]) * g.inv_s - 0.5f;
+    }
+    return r;
+}
+
+__device__ __forceinline__ Cell sample_cell(const RayCoef& r, int k) {
+    Cell o;
+    const float fk = (float)k;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float gc = r.A[a] + fk * r.B[a];
         float fl = floorf(gc);
         o.i[a] = (int)fl;
         o.w[a] = gc - fl;

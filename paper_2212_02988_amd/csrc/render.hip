@@ -19,7 +19,6 @@
 
 namespace prism {
 
-constexpr int kUnroll = 8;      // samples per trip, one-lane-per-ray march
 constexpr int kLanes = 4;       // lanes per ray in render / render_jacobian
 constexpr int kPerLane = 2;     // samples per lane per trip
 constexpr int kMaxLdsWords = 12288;   // free-space bits kept in LDS up to 48 KB (grids up to n = 576)
@@ -78,37 +77,6 @@ __device__ __forceinline__ lds_u32* block_bits(const GridC& g, const unsigned* _
     for (int i = threadIdx.x; i < nwords; i += blockDim.x) lbits[i] = gbits[i];
     __syncthreads();
     return (lds_u32*)lbits;
-}
-
-// first sample whose occupancy exceeds tau (strictly), with the bracketing
-// cells (recomputed from k*: cheaper than keeping them in registers)
-template <typename T>
-__device__ __forceinline__ RayHit march(const GridC& g, const CamC& c, const Pose32& P,
-                                        const float dir[3], const T* occ, lds_u32* bits) {
-    RayHit h;
-    h.k = -1;
-    h.f0 = h.f1 = 0.0f;
-    for (int k0 = 0; k0 < c.K; k0 += kUnroll) {
-        float f[kUnroll];
-#pragma unroll
-        for (int j = 0; j < kUnroll; ++j) {
-            Cell cl = sample_cell(g, c, P, dir, min(k0 + j, c.K - 1));
-            f[j] = march_occ(g, occ, bits, cl);
-        }
-        int hit = -1;
-#pragma unroll
-        for (int j = kUnroll - 1; j >= 0; --j)
-            if (k0 + j < c.K && f[j] > c.tau) hit = j;
-        if (hit >= 0) {
-            h.k = k0 + hit;
-            break;
-        }
-    }
-    if (h.k >= 1) {
-        h.c0 = sample_cell(g, c, P, dir, h.k - 1);
-        h.c1 = sample_cell(g, c, P, dir, h.k);
-    }
-    return h;
 }
 
 struct Shade {
@@ -297,15 +265,15 @@ __device__ __forceinline__ float quad_bcastf(float x, int src_lane_in_quad) {
 // first sample index whose occupancy exceeds tau (strictly), or -1; every
 // lane of the quad returns the same value
 template <typename T>
-__device__ __forceinline__ int march_quad(const GridC& g, const CamC& c, const Pose32& P, const float dir[3],
-                                          const T* occ, lds_u32* bits, int s) {
+__device__ __forceinline__ int march_quad(const GridC& g, const CamC& c, const RayCoef& rc, const T* occ,
+                                          lds_u32* bits, int s) {
     constexpr int G = kLanes * kPerLane;
     for (int k0 = 0; k0 < c.K; k0 += G) {
         float f[kPerLane];
 #pragma unroll
         for (int j = 0; j < kPerLane; ++j) {
             int k = k0 + j * kLanes + s;
-            Cell cl = sample_cell(g, c, P, dir, min(k, c.K - 1));
+            Cell cl = sample_cell(rc, min(k, c.K - 1));
             f[j] = march_occ(g, occ, bits, cl);
         }
         int first = 0x7fffffff;
@@ -431,14 +399,15 @@ __device__ __forceinline__ void render_block(int blk, int frame, const GridC& g,
     if (u >= c.W || v >= c.H) return;   // whole quads leave together
     float dir[3];
     ray_dir32(c, P.f, u, v, dir);
-    int k = march_quad(g, c, P.f, dir, map, bits, s);
+    const RayCoef rc = ray_coef(g, c, P.f, dir);
+    int k = march_quad(g, c, rc, map, bits, s);
     long long pix = (long long)frame * c.W * c.H + (long long)v * c.W + u;
     if (s == 0) {
         if (hit_k) hit_k[pix] = k;
         mask[pix] = k >= 1 ? 1 : 0;
     }
     if (k >= 1) {
-        Cell c0 = sample_cell(g, c, P.f, dir, k - 1), c1 = sample_cell(g, c, P.f, dir, k);
+        Cell c0 = sample_cell(rc, k - 1), c1 = sample_cell(rc, k);
         QuadShade q = shade_quad(g, gd, cd, P.d, u, v, map, c0, c1, k, s);
         if (s == 0)
             depth[pix] = (float)q.value;
@@ -563,7 +532,8 @@ __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, GridD gd, C
     if (u < c.W && v < c.H) {
         float dir[3];
         ray_dir32(c, P.f, u, v, dir);
-        int k = march_quad(g, c, P.f, dir, map, bits, s);
+        const RayCoef rc = ray_coef(g, c, P.f, dir);
+        int k = march_quad(g, c, rc, map, bits, s);
         long long pix = (long long)blockIdx.y * c.W * c.H + (long long)v * c.W + u;
         float row[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         double r = 0.0;
@@ -571,7 +541,7 @@ __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, GridD gd, C
         bool valid = k >= 1;
         double value = 0.0;
         if (valid) {
-            Cell c0 = sample_cell(g, c, P.f, dir, k - 1), c1 = sample_cell(g, c, P.f, dir, k);
+            Cell c0 = sample_cell(rc, k - 1), c1 = sample_cell(rc, k);
             QuadShade q = shade_quad(g, gd, cd, P.d, u, v, map, c0, c1, k, s);
             value = q.value;
             float D = obs_depth[pix];
@@ -677,10 +647,11 @@ __global__ __launch_bounds__(256) void k_render_vjp(GridC g, CamC c, GridD gd, C
         if (k >= 1 && k < c.K) {
             float dir[3];
             ray_dir32(c, P.f, u, v, dir);
+            const RayCoef rc = ray_coef(g, c, P.f, dir);
             RayHit h;
             h.k = k;
-            h.c0 = sample_cell(g, c, P.f, dir, k - 1);
-            h.c1 = sample_cell(g, c, P.f, dir, k);
+            h.c0 = sample_cell(rc, k - 1);
+            h.c1 = sample_cell(rc, k);
             h.f0 = occ_at(g, map, h.c0);
             h.f1 = occ_at(g, map, h.c1);
             if (h.f1 > c.tau && !(h.f0 > c.tau)) {
@@ -820,11 +791,12 @@ __global__ __launch_bounds__(256) void k_gd_grad(GridC g, CamC c, GridD gd, CamD
     if (u < c.W && v < c.H) {
         float dir[3];
         ray_dir32(c, P.f, u, v, dir);
-        const int k = march_quad(g, c, P.f, dir, map, bits, s);
+        const RayCoef rc = ray_coef(g, c, P.f, dir);
+        const int k = march_quad(g, c, rc, map, bits, s);
         const long long pix = (long long)v * c.W + u;
         const float D = obs_depth[pix];
         if (k >= 1 && depth_ok(D)) {   // the same for the four lanes of a ray
-            const Cell c0 = sample_cell(g, c, P.f, dir, k - 1), c1 = sample_cell(g, c, P.f, dir, k);
+            const Cell c0 = sample_cell(rc, k - 1), c1 = sample_cell(rc, k);
             const QuadShade q = shade_quad(g, gd, cd, P.d, u, v, map, c0, c1, k, s);
             const double r = s == 0 ? q.value - (double)D : q.value - (double)obs_rgb[3 * pix + s - 1];
             double l1 = s == 0 ? 0.0 : fabs(r);
