@@ -596,11 +596,17 @@ hipError_t launch_planes(int n, int channels, const float* src, float* dst, int 
     return hipGetLastError();
 }
 
-// workgroups of the update kernel: enough to keep every CU busy, never more
-// than there are bricks
+// workgroups of the update kernel, sized to the work: a view frustum holds
+// roughly a tenth of a room's bricks, and a workgroup walks four bricks at a
+// time, so nb^3 / 32 workgroups give each wavefront about one brick (every
+// workgroup first scans the segment lengths, a fixed cost that many idle
+// workgroups would multiply); at least 64 (or every brick), at most
+// kUpdateGrid
 static int update_grid(const GridC& g) {
     int nbricks = g.nb * g.nb * g.nb;
-    return nbricks < kUpdateGrid ? nbricks : kUpdateGrid;
+    int ng = nbricks / 32;
+    if (ng < 64) ng = nbricks < 64 ? nbricks : 64;
+    return ng < kUpdateGrid ? ng : kUpdateGrid;
 }
 
 hipError_t launch_map_update(const GridC& g, const CamC& c, const GridD& gd, int dtype, void* map,
