@@ -26,7 +26,7 @@ render_vjp             adjoint of App. B's emission (App. B notes the
 map_gd                 Sec. 4.3.1 alternative: the map-filter objective
                        (emission likelihood times previous map belief)
                        minimised by gradient descent through the renderer,
-                       as compared against the closed form in Sec. 5
+                       as compared against the closed form in Sec. 5.3
 predict / split        App. E.1 linearised transition, E.2 closed-form
                        propagation and split into pose prior + velocity
                        conditional
@@ -37,7 +37,7 @@ gn_solve / laplace     Sec. 4.3.2 MAP pose + Laplace approximation;
                        Sec. 5.1 / App. G.2 Hessian as squared Jacobian, EMA 0.8
 combine                Sec. 4.3.2 product of pose posterior and velocity
                        conditional
-rollout                Sec. 6 predictive rollout: generative transition
+rollout                App. J predictive rollout: generative transition
                        (App. B) sampled from the belief, closed-form
                        predicted moments (App. E.2), renders (App. B)
 filter_step            Sec. 4.3 map filter then state filter ordering
@@ -582,7 +582,7 @@ def transition_sample(x: Dict[str, np.ndarray], u: np.ndarray, n: np.ndarray, dt
 
 def rollout(grid: Grid, mean: np.ndarray, cam: Cam, x: Dict[str, np.ndarray], P: np.ndarray, u: np.ndarray,
             noise: np.ndarray, params: Params, decide32: bool = True, frames: bool = True):
-    """Predictive rollout (Sec. 6): from the belief N(x, P) and the map means,
+    """Predictive rollout (App. J): from the belief N(x, P) and the map means,
     under controls u [k][6]: for each sample s the start state x (+) L z[s,0]
     (P = L L^T; tangent order t, theta, v, w) and k draws of the transition
     with noise sqrt(diag Q) z[s,j+1]; the closed-form predicted moments after

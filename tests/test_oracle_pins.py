@@ -544,7 +544,7 @@ def test_render_vjp_pose_is_jacobian_transpose(orc):
 
 
 # ---------------------------------------------------------------------------
-# map inference by gradient descent through the renderer (Sec. 4.3.1, Sec. 5)
+# map inference by gradient descent through the renderer (Sec. 4.3.1, Sec. 5.3)
 # ---------------------------------------------------------------------------
 def _gd_case(orc, seed=0):
     rng = np.random.default_rng(seed)
@@ -913,7 +913,7 @@ def test_filter_keeps_prediction_for_improper_covariance(orc):
 
 
 # ---------------------------------------------------------------------------
-# predictive rollouts (Sec. 6)
+# predictive rollouts (App. J)
 # ---------------------------------------------------------------------------
 def _rollout_belief(rng):
     x = dict(t=np.array([1.0, 2.0, 1.5]), q=np.array([0.9, 0.1, -0.2, 0.3]) / np.linalg.norm([0.9, 0.1, -0.2, 0.3]),
