@@ -87,6 +87,8 @@ typedef struct {
     double origin[3]; /* grid min corner (m) */
     double occ_out;   /* occupancy of corners outside the grid (paper: -0.001) */
     double rgb_out;   /* colour of corners outside the grid (paper: 0) */
+    int64_t capacity; /* 0: dense map.  > 0: brick-pool map with room for this many
+                         8^3 bricks, 1 <= capacity <= (n/8)^3 (see "Brick-pool maps") */
 } prism_grid;
 
 typedef struct {
@@ -152,19 +154,42 @@ size_t prism_sizeof(const char *type_name);
  * to exchange the planes with the dense layout [4][n][n][n] (channel, z, y,
  * x; x fastest). */
 
+/* Brick-pool maps (grid.capacity > 0; the memory-efficient representation
+ * the paper points to in Sec. 6 and App. I): only bricks that have received
+ * an update hold storage.  A dense table maps each 8^3 brick of the grid to a
+ * slot of a pool of `capacity` bricks (8 planes each, same storage type), or
+ * to none; a voxel of a brick without a slot reads as the grid's outside
+ * values (occ_out, rgb_out) with the variance given to prism_map_init, which
+ * is also how a dense map's untouched voxels read when it was initialised
+ * with occ0 = occ_out and rgb0 = rgb_out.  prism_map_update gives a brick a
+ * slot (filled with those values) the first time one of its voxels is
+ * updated; when the pool is full the brick's update is dropped and counted
+ * (prism_map_pool_usage).  With enough capacity every result equals the dense
+ * map's bit for bit.  Rendering, the P1 Jacobian, tracking, the filter and
+ * the serving calls accept both kinds; the adjoint and descent mapping need a
+ * dense FP32 map. */
+
 /* Bytes of a map of this grid (App. D map belief: mean and variance per
  * voxel and channel).  Fails on an unsupported grid. */
 prism_status prism_map_bytes(const prism_grid *grid, size_t *bytes);
 
 /* Sets every voxel to (occ0, rgb0, rgb0, rgb0) with variance var0 in all
  * four channels (App. B/G first map belief: occupancy -0.001, colour 0,
- * broad variance).  map: device, prism_map_bytes() bytes, 256-byte aligned. */
+ * broad variance).  map: device, prism_map_bytes() bytes, 256-byte aligned.
+ * A brick-pool map empties its pool; it requires occ0 == occ_out and
+ * rgb0 == rgb_out (as floats) and keeps var0 for bricks given a slot later. */
 prism_status prism_map_init(const prism_grid *grid, void *map, float occ0, float rgb0, float var0,
                             hipStream_t stream);
 
+/* Brick-pool maps: usage[0] = bricks holding a slot, usage[1] = brick
+ * updates dropped because the pool was full, both since prism_map_init.
+ * usage: device int32 [2], written asynchronously. */
+prism_status prism_map_pool_usage(const prism_grid *grid, const void *map, int32_t *usage,
+                                  hipStream_t stream);
+
 /* Dense FP32 [4][n][n][n] means and variances (device) -> map.  BF16 maps
  * round to nearest-even.  Either of mean4 / var4 may be NULL to leave that
- * half untouched. */
+ * half untouched.  Dense maps only. */
 prism_status prism_map_from_dense(const prism_grid *grid, void *map, const float *mean4,
                                   const float *var4, hipStream_t stream);
 
@@ -285,7 +310,7 @@ prism_status prism_map_update(const prism_grid *grid, void *map, const prism_cam
                               int64_t *n_updated, hipStream_t stream);
 
 /* ------------------------------------------------------------------------ */
-/* Map inference by gradient descent (Sec. 4.3.1 alternative, Sec. 5)       */
+/* Map inference by gradient descent (Sec. 4.3.1 alternative, Sec. 5.3)     */
 /* ------------------------------------------------------------------------ */
 /* The map-filter target of Sec. 4.3.1 (emission likelihood of one frame at
  * the nominal pose times the previous map belief) minimised directly by
@@ -429,7 +454,7 @@ prism_status prism_filter_step_adam(prism_filter *f, const prism_frame *frame,
                                     const prism_adam_params *p, const int32_t *pixels,
                                     hipStream_t stream);
 
-/* Predictive rollout (Sec. 6, prediction and control): from the handle's
+/* Predictive rollout (App. J, prediction and control): from the handle's
  * current state belief N(x, P) and map means, predict k steps ahead under
  * the candidate controls u[0..k) with the generative transition (App. B):
  * n_samples sampled trajectories, their poses and (optionally) the frames

@@ -50,6 +50,8 @@ prism_status check_grid(const prism_grid* g) {
     REQUIRE(isfinite(g->voxel) && g->voxel > 0, "grid voxel must be finite and > 0");
     REQUIRE(isfinite(g->origin[0]) && isfinite(g->origin[1]) && isfinite(g->origin[2]), "grid origin not finite");
     REQUIRE(isfinite(g->occ_out) && isfinite(g->rgb_out), "grid outside values not finite");
+    const long long nb3 = (long long)(g->n / 8) * (g->n / 8) * (g->n / 8);
+    REQUIRE(g->capacity >= 0 && g->capacity <= nb3, "grid capacity must be in [0, (n/8)^3]");
     return PRISM_OK;
 }
 
@@ -87,7 +89,27 @@ GridC grid_c(const prism_grid* g) {
     o.n = g->n;
     o.nb = g->n / 8;
     o.nvox = (long long)g->n * g->n * g->n;
+    o.table = nullptr;
+    o.pocc = o.occ_out;
+    o.prgb = o.rgb_out;
     return o;
+}
+
+// a single-precision value as the map's storage type holds it (BF16: round
+// to nearest even, as the kernels store)
+float stored_host(float v, int dtype) {
+    if (dtype != PRISM_BF16) return v;
+    uint32_t b;
+    memcpy(&b, &v, 4);
+    if ((b & 0x7fffffffu) > 0x7f800000u) {
+        b = (b | 0x400000u) & 0xffff0000u;
+    } else {
+        b += 0x7fffu + ((b >> 16) & 1u);
+        b &= 0xffff0000u;
+    }
+    float r;
+    memcpy(&r, &b, 4);
+    return r;
 }
 
 CamC cam_c(const prism_camera* c) {
@@ -137,7 +159,7 @@ size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // map buffer: 8 planes, then brick summary, free-space bits, update counts,
 // frustum brick list, its segment lengths, pose scratch
 struct MapLayout {
-    size_t bmax, bits, counts, list, segcnt, pose, total;
+    size_t bmax, bits, counts, list, segcnt, pose, table, pool, total;
 };
 
 MapLayout map_layout(const prism_grid* g) {
@@ -145,21 +167,48 @@ MapLayout map_layout(const prism_grid* g) {
     size_t nvox = (size_t)g->n * g->n * g->n;
     size_t nb3 = nvox / 512;
     size_t nseg = (nb3 + 255) / 256;
-    L.bmax = round_up(8 * nvox * elem_size(g->dtype), 256);
+    size_t plane = g->capacity > 0 ? (size_t)g->capacity * 512 : nvox;
+    L.bmax = round_up(8 * plane * elem_size(g->dtype), 256);
     L.bits = L.bmax + round_up(4 * nb3, 256);
     L.counts = L.bits + round_up(4 * ((nb3 + 31) / 32), 256);
     L.list = L.counts + round_up(4 * (size_t)kUpdateGrid, 256);
     L.segcnt = L.list + round_up(4 * nseg * 256, 256);
     L.pose = L.segcnt + round_up(4 * nseg, 256);
-    L.total = L.pose + 256;
+    L.table = L.pose + 256;
+    L.pool = L.table + (g->capacity > 0 ? round_up(4 * nb3, 256) : 0);
+    L.total = L.pool + (g->capacity > 0 ? 256 : 0);
     return L;
 }
 
 MapAux map_aux(const prism_grid* g, const void* map) {
     MapLayout L = map_layout(g);
     char* b = (char*)map;
-    return MapAux{(float*)(b + L.bmax), (unsigned*)(b + L.bits), (int*)(b + L.counts),
-                  (int*)(b + L.list),   (int*)(b + L.segcnt),    (void*)(b + L.pose)};
+    MapAux a{(float*)(b + L.bmax), (unsigned*)(b + L.bits), (int*)(b + L.counts),
+             (int*)(b + L.list),   (int*)(b + L.segcnt),    (void*)(b + L.pose)};
+    a.table = nullptr;
+    a.pool = nullptr;
+    a.var0 = nullptr;
+    a.capacity = 0;
+    if (g->capacity > 0) {
+        a.table = (int*)(b + L.table);
+        a.pool = (int*)(b + L.pool);
+        a.var0 = (float*)(b + L.pool + 8);
+        a.capacity = (int)g->capacity;
+    }
+    return a;
+}
+
+// constants of a grid bound to one map buffer (brick-pool maps: the slot
+// table, the pool's plane stride and the values of voxels without a slot)
+GridC grid_cm(const prism_grid* g, const void* map) {
+    GridC o = grid_c(g);
+    if (g->capacity > 0) {
+        o.table = map_aux(g, map).table;
+        o.nvox = (long long)g->capacity * 512;
+        o.pocc = stored_host(o.occ_out, g->dtype);
+        o.prgb = stored_host(o.rgb_out, g->dtype);
+    }
+    return o;
 }
 
 // free-space bits for the renderer, NULL when skipping is not exact (tau != 0)
@@ -437,7 +486,19 @@ prism_status prism_map_init(const prism_grid* grid, void* map, float occ0, float
     prism_status s = check_grid(grid);
     if (s) return s;
     REQUIRE(map && aligned(map, 256), "map must be non-NULL and 256-byte aligned");
-    HIP_TRY(launch_map_init(grid_c(grid), grid->dtype, map, occ0, rgb0, var0, map_aux(grid, map), stream));
+    REQUIRE(grid->capacity == 0 || (occ0 == (float)grid->occ_out && rgb0 == (float)grid->rgb_out),
+            "a brick-pool map must be initialised with occ0 == occ_out and rgb0 == rgb_out");
+    HIP_TRY(launch_map_init(grid_cm(grid, map), grid->dtype, map, occ0, rgb0, var0, map_aux(grid, map), stream));
+    return PRISM_OK;
+}
+
+prism_status prism_map_pool_usage(const prism_grid* grid, const void* map, int32_t* usage, hipStream_t stream) {
+    prism_status s = check_grid(grid);
+    if (s) return s;
+    if (grid->capacity == 0) return fail(PRISM_UNSUPPORTED, "map_pool_usage needs a brick-pool map");
+    REQUIRE(map && aligned(map, 256), "map must be non-NULL and 256-byte aligned");
+    REQUIRE(usage && aligned(usage, 4), "usage must be non-NULL and 4-byte aligned");
+    HIP_TRY(hipMemcpyAsync(usage, map_aux(grid, map).pool, 2 * sizeof(int32_t), hipMemcpyDeviceToDevice, stream));
     return PRISM_OK;
 }
 
@@ -446,10 +507,11 @@ prism_status prism_map_from_dense(const prism_grid* grid, void* map, const float
     prism_status s = check_grid(grid);
     if (s) return s;
     REQUIRE(map && aligned(map, 256), "map must be non-NULL and 256-byte aligned");
+    if (grid->capacity > 0) return fail(PRISM_UNSUPPORTED, "map_from_dense needs a dense map");
     REQUIRE(!mean4 || aligned(mean4, 4), "mean4 misaligned");
     REQUIRE(!var4 || aligned(var4, 4), "var4 misaligned");
     if (!mean4 && !var4) return PRISM_OK;
-    HIP_TRY(launch_from_dense(grid_c(grid), grid->dtype, map, mean4, var4, map_aux(grid, map), stream));
+    HIP_TRY(launch_from_dense(grid_cm(grid, map), grid->dtype, map, mean4, var4, map_aux(grid, map), stream));
     return PRISM_OK;
 }
 
@@ -457,7 +519,7 @@ prism_status prism_map_refresh(const prism_grid* grid, void* map, hipStream_t st
     prism_status s = check_grid(grid);
     if (s) return s;
     REQUIRE(map && aligned(map, 256), "map must be non-NULL and 256-byte aligned");
-    HIP_TRY(launch_brick_max(grid_c(grid), grid->dtype, map, map_aux(grid, map), stream));
+    HIP_TRY(launch_brick_max(grid_cm(grid, map), grid->dtype, map, map_aux(grid, map), stream));
     return PRISM_OK;
 }
 
@@ -469,7 +531,7 @@ prism_status prism_map_to_dense(const prism_grid* grid, const void* map, float* 
     REQUIRE(!mean4 || aligned(mean4, 4), "mean4 misaligned");
     REQUIRE(!var4 || aligned(var4, 4), "var4 misaligned");
     if (!mean4 && !var4) return PRISM_OK;
-    HIP_TRY(launch_to_dense(grid_c(grid), grid->dtype, map, mean4, var4, stream));
+    HIP_TRY(launch_to_dense(grid_cm(grid, map), grid->dtype, map, mean4, var4, map_aux(grid, map), stream));
     return PRISM_OK;
 }
 
@@ -506,7 +568,7 @@ prism_status prism_render(const prism_grid* grid, const void* map, const prism_c
     REQUIRE(!normals || (nmask && aligned(normals, 4)), "normals needs nmask (and 4-byte alignment)");
     REQUIRE(!normals || !isnan(normal_disc), "normal_disc is NaN");
     CamC c = cam_c(cam);
-    HIP_TRY(launch_render(grid_c(grid), c, grid_d(grid), cam_d(cam), grid->dtype, map, skip_table(grid, cam, map),
+    HIP_TRY(launch_render(grid_cm(grid, map), c, grid_d(grid), cam_d(cam), grid->dtype, map, skip_table(grid, cam, map),
                           poses, n_frames, depth, rgb, mask, hit_k, stream));
     if (normals)
         HIP_TRY(launch_normals(c, n_frames, depth, mask, (float)normal_disc, normals, nmask, nullptr, 0, nullptr,
@@ -541,7 +603,7 @@ prism_status prism_render_jacobian(const prism_grid* grid, const void* map, cons
     REQUIRE(workspace && aligned(workspace, 8) && workspace_bytes >= reduce_bytes(c, n_frames),
             "workspace too small: need %zu bytes", reduce_bytes(c, n_frames));
     double* part = (double*)workspace;
-    HIP_TRY(launch_render_jac(grid_c(grid), c, grid_d(grid), cam_d(cam), grid->dtype, map,
+    HIP_TRY(launch_render_jac(grid_cm(grid, map), c, grid_d(grid), cam_d(cam), grid->dtype, map,
                               skip_table(grid, cam, map), poses, n_frames, obs_depth, obs_rgb, weights_c(w),
                               depth, rgb, mask, J, resid, rowmask, part, stream));
     HIP_TRY(launch_finalize(part, render_blocks(c), n_frames, PRISM_NEQ, neq, PRISM_NEQ, stream));
@@ -578,7 +640,8 @@ prism_status prism_render_vjp(const prism_grid* grid, const void* map, const pri
                               size_t workspace_bytes, hipStream_t stream) {
     prism_status s;
     if ((s = check_grid(grid)) || (s = check_cam(cam))) return s;
-    if (grid->dtype != PRISM_F32) return fail(PRISM_UNSUPPORTED, "render_vjp needs an FP32 map");
+    if (grid->dtype != PRISM_F32 || grid->capacity > 0)
+        return fail(PRISM_UNSUPPORTED, "render_vjp needs a dense FP32 map");
     REQUIRE(map && aligned(map, 256), "map must be non-NULL and 256-byte aligned");
     REQUIRE(poses && aligned(poses, 8), "poses must be non-NULL and 8-byte aligned");
     REQUIRE(n_frames >= 1 && n_frames <= 65535, "n_frames must be in [1, 65535]");
@@ -609,7 +672,7 @@ prism_status prism_map_update(const prism_grid* grid, void* map, const prism_cam
     REQUIRE(!n_updated || aligned(n_updated, 8), "n_updated misaligned");
     hipEvent_t tb = nullptr, te = nullptr;
     if (!timer_pair(PRISM_STAGE_MAP_UPDATE, stream, &tb, &te)) tb = te = nullptr;
-    HIP_TRY(launch_map_update(grid_c(grid), cam_c(cam), grid_d(grid), grid->dtype, map, pose, obs_depth, obs_rgb,
+    HIP_TRY(launch_map_update(grid_cm(grid, map), cam_c(cam), grid_d(grid), grid->dtype, map, pose, obs_depth, obs_rgb,
                               p->trunc, p->lam_update, map_aux(grid, map), n_updated, stream, tb, te));
     return PRISM_OK;
 }
@@ -651,7 +714,8 @@ prism_status prism_map_gd(const prism_grid* grid, void* map, const prism_camera*
                           hipStream_t stream) {
     prism_status s;
     if ((s = check_grid(grid)) || (s = check_cam(cam)) || (s = check_weights(w))) return s;
-    if (grid->dtype != PRISM_F32) return fail(PRISM_UNSUPPORTED, "map_gd needs an FP32 map");
+    if (grid->dtype != PRISM_F32 || grid->capacity > 0)
+        return fail(PRISM_UNSUPPORTED, "map_gd needs a dense FP32 map");
     REQUIRE(map && aligned(map, 256), "map must be non-NULL and 256-byte aligned");
     REQUIRE(pose && aligned(pose, 8), "pose must be non-NULL and 8-byte aligned");
     REQUIRE(obs_depth && obs_rgb && aligned(obs_depth, 4) && aligned(obs_rgb, 4), "observations must be non-NULL, aligned");
@@ -707,7 +771,7 @@ prism_status prism_filter_create(const prism_filter_cfg* cfg, void* state_mem, v
     prism_filter* f = new (std::nothrow) prism_filter();
     if (!f) return fail(PRISM_INVALID_ARGUMENT, "out of host memory");
     f->cfg = *cfg;
-    f->g = grid_c(&cfg->grid);
+    f->g = grid_cm(&cfg->grid, map_mem);
     f->c = cam_c(&cfg->cam);
     f->gd = grid_d(&cfg->grid);
     f->cd = cam_d(&cfg->cam);

@@ -38,7 +38,10 @@ struct GridC {
     float occ_out, rgb_out;
     int n;       // voxels per axis
     int nb;      // bricks per axis
-    long long nvox;   // n^3 (plane stride in elements)
+    long long nvox;   // plane stride in elements: n^3 (dense), capacity * 512 (brick pool)
+    const int* table;   // brick-pool maps: slot of each brick or -1; NULL for dense maps
+    float pocc, prgb;   // brick-pool maps: occupancy / colour a voxel without a slot reads as
+                        // (the outside values as the storage type holds them)
 };
 
 struct CamC {
@@ -70,6 +73,11 @@ struct MapAux {
     int* list;        // [nb^3] bricks in the view frustum, in 256-brick segments
     int* segcnt;      // [ceil(nb^3/256)] entries used in each segment
     void* pose;       // Pose32 then Pose64 of the current update (256 bytes)
+    // brick-pool maps only (NULL for dense maps)
+    int* table;       // [nb^3] slot of each brick, -1 without one
+    int* pool;        // [0] slots handed out, [1] brick updates dropped (pool full)
+    float* var0;      // variance a brick's voxels take when it is given a slot
+    int capacity;     // slots in the pool
 };
 
 constexpr int kUpdateGrid = 2048;   // workgroups of the map-update kernel
@@ -141,10 +149,18 @@ __device__ __forceinline__ uint16_t f2bf(float v) {
 }
 __device__ __forceinline__ void st(uint16_t* p, long long i, float v) { p[i] = f2bf(v); }
 
-// brick-order index of voxel (i, j, k); all in [0, n)
+// Element index within a plane of voxel (i, j, k), all in [0, n): brick order
+// (brick b, then z, y, x inside the brick); in a brick-pool map the brick's
+// slot replaces b, and -1 means the brick has none (the voxel then reads as
+// the grid's outside values).
 __device__ __forceinline__ long long vidx(const GridC& g, int i, int j, int k) {
     long long b = ((long long)(k >> 3) * g.nb + (j >> 3)) * g.nb + (i >> 3);
-    return (b << 9) | ((k & 7) << 6) | ((j & 7) << 3) | (i & 7);
+    const long long loc = ((k & 7) << 6) | ((j & 7) << 3) | (i & 7);
+    if (g.table) {
+        const int slot = g.table[b];
+        return slot < 0 ? -1 : ((long long)slot << 9) | loc;
+    }
+    return (b << 9) | loc;
 }
 
 // ---------------------------------------------------------------------------
@@ -276,13 +292,28 @@ __device__ __forceinline__ void corners_in(const T* plane, const CellAddr& a, fl
     v[7] = ldu(plane, o + a.dz + a.dy + a.dx);
 }
 
-// 8 corner values of one plane (out-of-grid corners take `outv`)
+// 8 corner values of one plane: out-of-grid corners take `outv`, corners in
+// bricks without a slot (brick-pool maps) `priorv`
 template <typename T>
-__device__ __forceinline__ void corners(const GridC& g, const T* plane, const Cell& c, float outv,
+__device__ __forceinline__ void corners(const GridC& g, const T* plane, const Cell& c, float outv, float priorv,
                                         float v[8]) {
     if (cell_inside(g, c)) {
-        corners_in(plane, cell_addr(g, c), v);
-        return;
+        CellAddr a = cell_addr(g, c);
+        if (!g.table) {
+            corners_in(plane, a, v);
+            return;
+        }
+        if (!a.cross) {
+            // one brick: its slot, then the dense steps inside it
+            const int slot = g.table[a.b0];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = priorv;
+            if (slot >= 0) {
+                a.base = (slot << 9) | (a.base & 511);
+                corners_in(plane, a, v);
+            }
+            return;
+        }
     }
     bool okx0 = (unsigned)c.i[0] < (unsigned)g.n, okx1 = (unsigned)(c.i[0] + 1) < (unsigned)g.n;
     bool oky0 = (unsigned)c.i[1] < (unsigned)g.n, oky1 = (unsigned)(c.i[1] + 1) < (unsigned)g.n;
@@ -291,7 +322,8 @@ __device__ __forceinline__ void corners(const GridC& g, const T* plane, const Ce
     for (int q = 0; q < 8; ++q) {
         int dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
         bool ok = (dx ? okx1 : okx0) && (dy ? oky1 : oky0) && (dz ? okz1 : okz0);
-        v[q] = ok ? ld(plane, vidx(g, c.i[0] + dx, c.i[1] + dy, c.i[2] + dz)) : outv;
+        const long long e = ok ? vidx(g, c.i[0] + dx, c.i[1] + dy, c.i[2] + dz) : -1;
+        v[q] = e >= 0 ? ld(plane, e) : ok ? priorv : outv;
     }
 }
 

@@ -120,7 +120,7 @@ hipError_t launch_brick_max(const GridC& g, int dtype, const void* map, const Ma
 hipError_t launch_from_dense(const GridC& g, int dtype, void* map, const float* mean4, const float* var4,
                              const MapAux& aux, hipStream_t st);
 hipError_t launch_to_dense(const GridC& g, int dtype, const void* map, float* mean4, float* var4,
-                           hipStream_t st);
+                           const MapAux& aux, hipStream_t st);
 hipError_t launch_planes(int n, int channels, const float* src, float* dst, int to_dense, hipStream_t st);
 // n_updated (nullable): total of updated voxels, by an extra one-workgroup
 // kernel; t_begin / t_end (nullable): events recorded around the update kernel

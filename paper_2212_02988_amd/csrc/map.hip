@@ -49,6 +49,20 @@ __global__ __launch_bounds__(256) void k_map_init(long long nvox, T* __restrict_
     for (int c = 4; c < 8; ++c) st(map, c * nvox + i, var0);
 }
 
+// brick-pool map: every brick without a slot, bricks summarised by the
+// value their voxels read as, pool counters cleared, var0 kept
+__global__ __launch_bounds__(256) void k_pool_init(int nbricks, float pocc, float var0, MapAux aux) {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b == 0) {
+        aux.pool[0] = 0;
+        aux.pool[1] = 0;
+        *aux.var0 = var0;
+    }
+    if (b >= nbricks) return;
+    aux.table[b] = -1;
+    aux.bmax[b] = pocc;
+}
+
 // dense index (k*n + j)*n + i  <->  brick index
 __device__ __forceinline__ long long dense_of_brick(int n, int nb, long long b_idx) {
     long long b = b_idx >> 9;
@@ -87,6 +101,26 @@ __global__ __launch_bounds__(256) void k_to_dense(int n, int nb, const T* __rest
     }
 }
 
+// brick-pool map -> dense planes; voxels of bricks without a slot take the
+// values they read as (and var0)
+template <typename T>
+__global__ __launch_bounds__(256) void k_pool_to_dense(GridC g, const T* __restrict__ map, MapAux aux,
+                                                       float* __restrict__ mean4, float* __restrict__ var4) {
+    const long long nvox = (long long)g.n * g.n * g.n;
+    long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nvox) return;
+    const long long d = dense_of_brick(g.n, g.nb, b);
+    const int slot = g.table[b >> 9];
+    const long long e = ((long long)slot << 9) | (b & 511);
+    const float v0 = *aux.var0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const float prior = c == 0 ? g.pocc : g.prgb;
+        if (mean4) mean4[c * nvox + d] = slot >= 0 ? ld(map, c * g.nvox + e) : prior;
+        if (var4) var4[c * nvox + d] = slot >= 0 ? ld(map, (4 + c) * g.nvox + e) : stored<T>(v0);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_planes(int n, int nb, int channels, const float* __restrict__ src,
                                                 float* __restrict__ dst, int to_dense) {
     long long nvox = (long long)n * n * n;
@@ -116,7 +150,15 @@ __device__ __forceinline__ float block_max(float m, float* lds) {
 template <typename T>
 __global__ __launch_bounds__(256) void k_brick_max(GridC g, const T* __restrict__ map, MapAux aux) {
     __shared__ float lds[4];
-    long long base = (long long)blockIdx.x << 9;
+    long long slot = blockIdx.x;
+    if (g.table) {
+        slot = g.table[blockIdx.x];
+        if (slot < 0) {
+            if (threadIdx.x == 0) aux.bmax[blockIdx.x] = g.pocc;
+            return;
+        }
+    }
+    long long base = slot << 9;
     float m = fmaxf(ld(map, base + threadIdx.x), ld(map, base + threadIdx.x + 256));
     m = block_max(m, lds);
     if (threadIdx.x == 0) aux.bmax[blockIdx.x] = m;
@@ -296,23 +338,64 @@ __device__ __forceinline__ void map_update_block(int blk, int ngroups, const Gri
 #pragma unroll
         for (int h = 0; h < 8; ++h)
             if (upd[h]) Dv[h] = depth[pix[h]];
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+            if (upd[h]) {
+                const int k = (bz << 3) | h;
+                float x[3] = {g.o[0] + g.s * ((float)i + 0.5f), g.o[1] + g.s * ((float)j + 0.5f),
+                              g.o[2] + g.s * ((float)k + 0.5f)};
+                float d[3] = {x[0] - P.t[0], x[1] - P.t[1], x[2] - P.t[2]};
+                float X2 = (P.R[0][2] * d[0] + P.R[1][2] * d[1]) + P.R[2][2] * d[2];
+                upd[h] = depth_ok(Dv[h]) && X2 <= Dv[h] + mp.trunc32;
+            }
+        }
+        // brick-pool map: the brick's slot, handed out the first time one of
+        // its voxels is updated and filled with the values its voxels read as;
+        // with the pool full the brick's update is dropped and counted
+        long long slot = b;
+        bool fresh = false;
+        float pvar = 0.0f;
+        if (aux.table) {
+            int sl = aux.table[b];
+            int any = 0;
+#pragma unroll
+            for (int h = 0; h < 8; ++h) any |= upd[h] ? 1 : 0;
+            if (sl < 0 && __any(any)) {
+                int got = -1;
+                if (lane == 0) {
+                    const int s2 = atomicAdd(&aux.pool[0], 1);
+                    if (s2 < aux.capacity) {
+                        aux.table[b] = s2;
+                        got = s2;
+                    } else {
+                        // pool full: give the ticket back, count the drop
+                        atomicSub(&aux.pool[0], 1);
+                        atomicAdd(&aux.pool[1], 1);
+                    }
+                }
+                sl = __shfl(got, 0, 64);
+                fresh = sl >= 0;
+                pvar = stored<T>(*aux.var0);
+            }
+            if (sl < 0) continue;
+            slot = sl;
+        }
         float m = -INFINITY;
 #pragma unroll
         for (int h = 0; h < 8; ++h) {
             const int k = (bz << 3) | h;
-            const long long id = ((long long)b << 9) | (h << 6) | lane;
-            if (upd[h]) {
-                float X2;
-                {
-                    float x[3] = {g.o[0] + g.s * ((float)i + 0.5f), g.o[1] + g.s * ((float)j + 0.5f),
-                                  g.o[2] + g.s * ((float)k + 0.5f)};
-                    float d[3] = {x[0] - P.t[0], x[1] - P.t[1], x[2] - P.t[2]};
-                    X2 = (P.R[0][2] * d[0] + P.R[1][2] * d[1]) + P.R[2][2] * d[2];
-                }
-                upd[h] = depth_ok(Dv[h]) && X2 <= Dv[h] + mp.trunc32;
-            }
+            const long long id = (slot << 9) | (h << 6) | lane;
             if (!upd[h]) {
-                m = fmaxf(m, ld(map, id));
+                if (fresh) {
+#pragma unroll
+                    for (int ch = 0; ch < 4; ++ch) {
+                        st(map, ch * g.nvox + id, ch == 0 ? g.pocc : g.prgb);
+                        st(map, (4 + ch) * g.nvox + id, pvar);
+                    }
+                    m = fmaxf(m, g.pocc);
+                } else {
+                    m = fmaxf(m, ld(map, id));
+                }
                 continue;
             }
             // values in double precision: camera depth of the voxel centre,
@@ -331,8 +414,8 @@ __device__ __forceinline__ void map_update_block(int blk, int ngroups, const Gri
             double mu[4], var[4];
 #pragma unroll
             for (int ch = 0; ch < 4; ++ch) {
-                mu[ch] = (double)ld(map, ch * g.nvox + id);
-                var[ch] = (double)ld(map, (4 + ch) * g.nvox + id);
+                mu[ch] = fresh ? (double)(ch == 0 ? g.pocc : g.prgb) : (double)ld(map, ch * g.nvox + id);
+                var[ch] = fresh ? (double)pvar : (double)ld(map, (4 + ch) * g.nvox + id);
             }
             // App. D: new precision = old + update precision; new mean =
             // inverse of the new precision times the precision-weighted sum.
@@ -549,6 +632,12 @@ static hipError_t launch_pack(const GridC& g, const MapAux& aux, hipStream_t st)
 hipError_t launch_map_init(const GridC& g, int dtype, void* map, float occ0, float rgb0, float var0,
                            const MapAux& aux, hipStream_t st) {
     int nbricks = g.nb * g.nb * g.nb;
+    if (aux.table) {
+        k_pool_init<<<(unsigned)((nbricks + 255) / 256), 256, 0, st>>>(nbricks, g.pocc, var0, aux);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return launch_pack(g, aux, st);
+    }
     if (dtype == PRISM_BF16)
         k_map_init<uint16_t><<<blocks_for(g.nvox), 256, 0, st>>>(g.nvox, (uint16_t*)map, occ0, rgb0, var0, aux,
                                                                  nbricks);
@@ -582,7 +671,15 @@ hipError_t launch_from_dense(const GridC& g, int dtype, void* map, const float* 
 }
 
 hipError_t launch_to_dense(const GridC& g, int dtype, const void* map, float* mean4, float* var4,
-                           hipStream_t st) {
+                           const MapAux& aux, hipStream_t st) {
+    if (g.table) {
+        const long long nvox = (long long)g.n * g.n * g.n;
+        if (dtype == PRISM_BF16)
+            k_pool_to_dense<uint16_t><<<blocks_for(nvox), 256, 0, st>>>(g, (const uint16_t*)map, aux, mean4, var4);
+        else
+            k_pool_to_dense<float><<<blocks_for(nvox), 256, 0, st>>>(g, (const float*)map, aux, mean4, var4);
+        return hipGetLastError();
+    }
     if (dtype == PRISM_BF16)
         k_to_dense<uint16_t><<<blocks_for(g.nvox), 256, 0, st>>>(g.n, g.nb, (const uint16_t*)map, mean4, var4);
     else

@@ -32,7 +32,7 @@ struct RayHit {
 template <typename T>
 __device__ __forceinline__ float occ_at(const GridC& g, const T* occ, const Cell& c) {
     float v[8];
-    corners(g, occ, c, g.occ_out, v);
+    corners(g, occ, c, g.occ_out, g.pocc, v);
     return trilerp(v, c.w);
 }
 
@@ -61,6 +61,7 @@ __device__ __forceinline__ float march_occ(const GridC& g, const T* occ, lds_u32
     if (cell_inside(g, cl)) {
         CellAddr a = cell_addr(g, cl);
         if (bits && cell_free(g, bits, a)) return -1.0f;
+        if (g.table) return occ_at(g, occ, cl);   // brick-pool map: through the slot table
         float v[8];
         corners_in_g(as_global(occ), a, v);
         return trilerp(v, cl.w);
@@ -92,7 +93,7 @@ struct Shade {
 // corners of the product of 1-D hat weights (z, y, x order)
 template <typename T>
 __device__ __forceinline__ double tri64(const GridC& g, const T* plane, const double gc[3], const int cell[3],
-                                        double outv) {
+                                        double outv, float priorv) {
     double w0 = gc[0] - (double)cell[0], w1 = gc[1] - (double)cell[1], w2 = gc[2] - (double)cell[2];
     double s = 0.0;
 #pragma unroll
@@ -106,7 +107,8 @@ __device__ __forceinline__ double tri64(const GridC& g, const T* plane, const do
                 double hz = cz ? w2 : 1.0 - w2;
                 int i = cell[0] + cx, j = cell[1] + cy, k = cell[2] + cz;
                 bool in = (unsigned)i < (unsigned)g.n && (unsigned)j < (unsigned)g.n && (unsigned)k < (unsigned)g.n;
-                double V = in ? (double)ld(plane, vidx(g, i, j, k)) : outv;
+                const long long e = in ? vidx(g, i, j, k) : -1;
+                double V = e >= 0 ? (double)ld(plane, e) : in ? (double)priorv : outv;
                 s += hx * hy * hz * V;
             }
     return s;
@@ -135,8 +137,8 @@ __device__ __forceinline__ Shade shade(const GridC& g, const GridD& gd, const Ca
     grid_coord64(gd, cd, P, dir, h.k, gc1);
     double d0 = cd.dn + (double)(h.k - 1) * cd.step;
     double d1 = cd.dn + (double)h.k * cd.step;
-    s.f0 = tri64(g, map, gc0, h.c0.i, gd.occ_out);
-    s.f1 = tri64(g, map, gc1, h.c1.i, gd.occ_out);
+    s.f0 = tri64(g, map, gc0, h.c0.i, gd.occ_out, g.pocc);
+    s.f1 = tri64(g, map, gc1, h.c1.i, gd.occ_out, g.pocc);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         s.w0[a] = (float)(gc0[a] - (double)h.c0.i[a]);
@@ -147,8 +149,8 @@ __device__ __forceinline__ Shade shade(const GridC& g, const GridD& gd, const Ca
 #pragma unroll 1
     for (int ch = 0; ch < 3; ++ch) {
         const T* pl = map + (long long)(1 + ch) * g.nvox;
-        double c0 = tri64(g, pl, gc0, h.c0.i, gd.rgb_out);
-        double c1 = tri64(g, pl, gc1, h.c1.i, gd.rgb_out);
+        double c0 = tri64(g, pl, gc0, h.c0.i, gd.rgb_out, g.prgb);
+        double c1 = tri64(g, pl, gc1, h.c1.i, gd.rgb_out, g.prgb);
         s.rgb[ch] = al * c1 + (1.0 - al) * c0;
         s.c0[ch] = (float)c0;
         s.c1[ch] = (float)c1;
@@ -173,9 +175,9 @@ __device__ __forceinline__ void ray_jacobian(const GridC& g, const T* map, const
 #pragma unroll
     for (int i = 0; i < 3; ++i) { a0[i] = s.d0 * dir[i]; a1[i] = s.d1 * dir[i]; }
     float v[8], gr0[3], gr1[3], cr[3];
-    corners(g, map, h.c0, g.occ_out, v);
+    corners(g, map, h.c0, g.occ_out, g.pocc, v);
     trigrad(v, s.w0, gr0);
-    corners(g, map, h.c1, g.occ_out, v);
+    corners(g, map, h.c1, g.occ_out, g.pocc, v);
     trigrad(v, s.w1, gr1);
     float rf0[6], rf1[6];
 #pragma unroll
@@ -197,9 +199,9 @@ __device__ __forceinline__ void ray_jacobian(const GridC& g, const T* map, const
     for (int ch = 0; ch < 3; ++ch) {
         const T* pl = map + (long long)(1 + ch) * g.nvox;
         float G0[3], G1[3], g0[6], g1[6];
-        corners(g, pl, h.c0, g.rgb_out, v);
+        corners(g, pl, h.c0, g.rgb_out, g.prgb, v);
         trigrad(v, s.w0, G0);
-        corners(g, pl, h.c1, g.rgb_out, v);
+        corners(g, pl, h.c1, g.rgb_out, g.prgb, v);
         trigrad(v, s.w1, G1);
 #pragma unroll
         for (int i = 0; i < 3; ++i) { G0[i] *= g.inv_s; G1[i] *= g.inv_s; g0[i] = G0[i]; g1[i] = G1[i]; }
@@ -314,8 +316,9 @@ __device__ __forceinline__ QuadShade shade_quad(const GridC& g, const GridD& gd,
     double d1 = cd.dn + (double)k * cd.step;
     const T* pl = map + (long long)s * g.nvox;
     double outv = s == 0 ? gd.occ_out : gd.rgb_out;
-    q.v0 = tri64(g, pl, gc0, c0.i, outv);
-    q.v1 = tri64(g, pl, gc1, c1.i, outv);
+    float priorv = s == 0 ? g.pocc : g.prgb;
+    q.v0 = tri64(g, pl, gc0, c0.i, outv, priorv);
+    q.v1 = tri64(g, pl, gc1, c1.i, outv, priorv);
     q.f0 = quad_bcast(q.v0, 0);
     q.f1 = quad_bcast(q.v1, 0);
     q.alpha = (cd.tau - q.f0) / (q.f1 - q.f0);
@@ -339,11 +342,11 @@ __device__ __forceinline__ void jac_row_quad(const GridC& g, const T* map, const
 #pragma unroll
     for (int i = 0; i < 3; ++i) { a0[i] = q.d0 * dir[i]; a1[i] = q.d1 * dir[i]; }
     const T* pl = map + (long long)s * g.nvox;
-    float outv = s == 0 ? g.occ_out : g.rgb_out;
+    float outv = s == 0 ? g.occ_out : g.rgb_out, priorv = s == 0 ? g.pocc : g.prgb;
     float v[8], G0[3], G1[3], cr[3], r0[6], r1[6];
-    corners(g, pl, c0, outv, v);
+    corners(g, pl, c0, outv, priorv, v);
     trigrad(v, q.w0, G0);
-    corners(g, pl, c1, outv, v);
+    corners(g, pl, c1, outv, priorv, v);
     trigrad(v, q.w1, G1);
 #pragma unroll
     for (int i = 0; i < 3; ++i) { G0[i] *= g.inv_s; G1[i] *= g.inv_s; r0[i] = G0[i]; r1[i] = G1[i]; }

@@ -38,12 +38,14 @@ class PrismError(RuntimeError):
 # ---------------------------------------------------------------------------
 class Grid(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("dtype", ctypes.c_int32), ("voxel", ctypes.c_double),
-                ("origin", ctypes.c_double * 3), ("occ_out", ctypes.c_double), ("rgb_out", ctypes.c_double)]
+                ("origin", ctypes.c_double * 3), ("occ_out", ctypes.c_double), ("rgb_out", ctypes.c_double),
+                ("capacity", ctypes.c_int64)]
 
     @staticmethod
     def make(n: int, voxel: float, origin=(0.0, 0.0, 0.0), dtype: int = PRISM_F32,
-             occ_out: float = -0.001, rgb_out: float = 0.0) -> "Grid":
-        return Grid(n, dtype, voxel, (ctypes.c_double * 3)(*origin), occ_out, rgb_out)
+             occ_out: float = -0.001, rgb_out: float = 0.0, capacity: int = 0) -> "Grid":
+        """capacity 0: dense map; > 0: brick-pool map with that many brick slots."""
+        return Grid(n, dtype, voxel, (ctypes.c_double * 3)(*origin), occ_out, rgb_out, capacity)
 
 
 class Camera(ctypes.Structure):
@@ -117,6 +119,7 @@ _SIGS = {
     "prism_sizeof": ([ctypes.c_char_p], ctypes.c_size_t),
     "prism_map_bytes": (["p", "p"], None),
     "prism_map_init": (["p", "p", ctypes.c_float, ctypes.c_float, ctypes.c_float, "p"], None),
+    "prism_map_pool_usage": (["p", "p", "p", "p"], None),
     "prism_map_from_dense": (["p", "p", "p", "p", "p"], None),
     "prism_map_to_dense": (["p", "p", "p", "p", "p"], None),
     "prism_map_refresh": (["p", "p", "p"], None),
@@ -244,6 +247,12 @@ class VoxelMap:
             _dev(var4, torch.float32, "var4", (4, n, n, n))
         _check(lib().prism_map_from_dense(_by(self.grid), _ptr(self.buf), _ptr(mean4), _ptr(var4), _stream(stream)))
         return self
+
+    def pool_usage(self, stream=None) -> torch.Tensor:
+        """Brick-pool maps: int32 [bricks with a slot, dropped brick updates]."""
+        out = torch.zeros(2, dtype=torch.int32, device=self.buf.device)
+        _check(lib().prism_map_pool_usage(_by(self.grid), _ptr(self.buf), _ptr(out), _stream(stream)))
+        return out
 
     def refresh(self, stream=None):
         """Recompute the brick summary after writing the mean planes directly."""

@@ -98,3 +98,31 @@ def test_workspace_and_filter_sizes(P):
     assert b.value >= 30 * 320 * 240
     bad = P.filter_cfg(P.Grid.make(256, 0.025), cam, P.FilterParams(n_gn=100))
     assert L.prism_filter_bytes(ctypes.byref(bad), ctypes.byref(b)) == 1
+
+
+def test_brick_pool_map_bytes_and_init_checks(P):
+    """Brick-pool maps: size = pool planes + the dense summaries + the slot
+    table and pool header; capacity bounded by the brick count; init must use
+    the outside values (validation only, no device call)."""
+    L = P.lib()
+    b = ctypes.c_size_t()
+    r256 = lambda x: (x + 255) // 256 * 256
+    dense = P.Grid.make(64, 0.04)
+    assert L.prism_map_bytes(ctypes.byref(dense), ctypes.byref(b)) == 0
+    dense_bytes = b.value
+    nb3 = 8 ** 3
+    for cap in (1, 37, nb3):
+        g = P.Grid.make(64, 0.04, capacity=cap)
+        assert L.prism_map_bytes(ctypes.byref(g), ctypes.byref(b)) == 0
+        assert b.value == dense_bytes - 8 * 64 ** 3 * 4 + r256(8 * cap * 512 * 4) + r256(4 * nb3) + 256
+    for bad in (-1, nb3 + 1):
+        g = P.Grid.make(64, 0.04, capacity=bad)
+        assert L.prism_map_bytes(ctypes.byref(g), ctypes.byref(b)) == 1
+        assert b"capacity" in L.prism_last_error()
+    g = P.Grid.make(64, 0.04, capacity=10)
+    st = L.prism_map_init(ctypes.byref(g), ctypes.c_void_p(256), 0.5, 0.0, 1e4, None)
+    assert st == 1 and b"occ_out" in L.prism_last_error()
+    st = L.prism_map_from_dense(ctypes.byref(g), ctypes.c_void_p(256), None, None, None)
+    assert st == 2
+    st = L.prism_map_pool_usage(ctypes.byref(dense), ctypes.c_void_p(256), ctypes.c_void_p(256), None)
+    assert st == 2
