@@ -48,6 +48,20 @@ def log(msg):
 # ---------------------------------------------------------------------------
 # serving mix
 # ---------------------------------------------------------------------------
+def pooled(specs, P, frac):
+    """The same streams with brick-pool maps holding frac of each grid's bricks."""
+    import dataclasses
+    out = []
+    for s in specs:
+        g = s.grid
+        nb3 = (g.n // 8) ** 3
+        cap = max(1, min(nb3, int(np.ceil(frac * nb3))))
+        grid = P.Grid.make(g.n, g.voxel, tuple(g.origin), dtype=g.dtype, occ_out=g.occ_out, rgb_out=g.rgb_out,
+                           capacity=cap)
+        out.append(dataclasses.replace(s, grid=grid))
+    return out
+
+
 def build_mix(n_streams, n_frames, P, torch):
     import synth
     from paper_2212_02988_amd.serving import StreamSpec
@@ -513,6 +527,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=16.0)
     ap.add_argument("--calib", action="store_true", help="also run a 256 MiB device copy (counter calibration)")
+    ap.add_argument("--pool-frac", type=float, default=1.0,
+                    help="brick-pool run: fraction of each grid's bricks the pool holds")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported (agent streams are independent "
@@ -565,6 +581,19 @@ def main():
     bloop, bwall = run_mix(specs, frames, fps, realtime=False, budget=int(args.budget_gb * 2**30), **mk)
     log(f"{args.budget_gb:g} GB budget: {bloop.completed} steps in {bwall:.3f} s, max concurrent "
         f"{bloop.max_concurrent}")
+    # the same mix with brick-pool maps (storage for a fraction of each grid)
+    pspecs = pooled(specs, P, args.pool_frac)
+    pfoot = sum(footprint_bytes(s) for s in pspecs)
+    ploop, pwall = run_mix(pspecs, frames, fps, realtime=False, **mk)
+    used = [ploop.totals[s.stream_id]["pool_used"] / ploop.totals[s.stream_id]["pool_capacity"] for s in pspecs]
+    dropped = sum(ploop.totals[s.stream_id]["pool_dropped"] for s in pspecs)
+    pool_run = {"pool_fraction": args.pool_frac, "steps_per_s": round(ploop.completed / pwall, 1),
+                "footprint_gb": round(pfoot / 2**30, 3), "dense_footprint_gb": round(foot / 2**30, 3),
+                "max_pool_use": round(max(used), 3), "mean_pool_use": round(float(np.mean(used)), 3),
+                "dropped_brick_updates": int(dropped)}
+    log(f"brick-pool maps ({args.pool_frac:g} of each grid): {ploop.completed} steps in {pwall:.3f} s = "
+        f"{ploop.completed / pwall:.0f} steps/s, footprint {pfoot / 2**30:.2f} GiB (dense {foot / 2**30:.2f}), "
+        f"pool use max {max(used):.2f} mean {np.mean(used):.2f}, dropped {dropped}")
     # real-time arrivals at 10 Hz
     rloop, rwall = run_mix(specs, frames, args.rt_frames, realtime=True, **mk)
     rst = rloop.stats()
@@ -616,7 +645,8 @@ def main():
                     "budget_run": {"budget_gb": args.budget_gb, "steps_per_s": r(bloop.completed / bwall, 1),
                                    "max_concurrent": bloop.max_concurrent,
                                    "max_held_gb": r(bloop.max_held_bytes / 2**30)},
-                    "footprint_gb": r(foot / 2**30)},
+                    "footprint_gb": r(foot / 2**30),
+                    "brick_pool_run": pool_run},
         "single_stream_fp32": {"workload": "256^3 grid (2.5 cm), 320x240, K = 128, FP32 map, P2 x 3 GN, "
                                            "one HIP graph per step",
                                "steps_per_s": r(1e3 / single["ms_per_step"], 1),

@@ -1242,11 +1242,13 @@ prism_status step_batch_chunk(prism_filter* const* fs, int n, const int* slot, h
         StageScope t(PRISM_STAGE_CULL, st);
         HIP_TRY(launch_cull_batch(make_batch(fs, all, n_all, slot, 3), st));
     }
-    for (int dt = PRISM_F32; dt <= PRISM_BF16; ++dt) {
+    for (int kind = 0; kind < 4; ++kind) {
+        const int dt = kind & 1 ? PRISM_BF16 : PRISM_F32;
+        const bool pool = kind >= 2;
         int m = 0, max_nseg = 0, max_words = 0;
         for (int j = 0; j < n_all; ++j) {
             const prism_filter* f = fs[all[j]];
-            if (f->cfg.grid.dtype != dt) continue;
+            if (f->cfg.grid.dtype != dt || (f->cfg.grid.capacity > 0) != pool) continue;
             sub[m++] = all[j];
             if (f->desc.nseg > max_nseg) max_nseg = f->desc.nseg;
             int words = f->desc.bits ? (f->g.nb * f->g.nb * f->g.nb + 31) >> 5 : 0;
@@ -1255,11 +1257,11 @@ prism_status step_batch_chunk(prism_filter* const* fs, int n, const int* slot, h
         if (!m) continue;
         {
             StageScope t(PRISM_STAGE_MAP_UPDATE, st);
-            HIP_TRY(launch_map_update_batch(make_batch(fs, sub, m, slot, 4), dt, max_nseg, st));
+            HIP_TRY(launch_map_update_batch(make_batch(fs, sub, m, slot, 4), dt, pool, max_nseg, st));
         }
         {
             StageScope t(PRISM_STAGE_RENDER, st);
-            HIP_TRY(launch_render_batch(make_batch(fs, sub, m, slot, 5), dt, max_words, st));
+            HIP_TRY(launch_render_batch(make_batch(fs, sub, m, slot, 5), dt, pool, max_words, st));
         }
     }
     {

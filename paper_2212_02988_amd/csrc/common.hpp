@@ -153,10 +153,11 @@ __device__ __forceinline__ void st(uint16_t* p, long long i, float v) { p[i] = f
 // (brick b, then z, y, x inside the brick); in a brick-pool map the brick's
 // slot replaces b, and -1 means the brick has none (the voxel then reads as
 // the grid's outside values).
+template <bool Pool = false>
 __device__ __forceinline__ long long vidx(const GridC& g, int i, int j, int k) {
     long long b = ((long long)(k >> 3) * g.nb + (j >> 3)) * g.nb + (i >> 3);
     const long long loc = ((k & 7) << 6) | ((j & 7) << 3) | (i & 7);
-    if (g.table) {
+    if constexpr (Pool) {
         const int slot = g.table[b];
         return slot < 0 ? -1 : ((long long)slot << 9) | loc;
     }
@@ -294,12 +295,12 @@ __device__ __forceinline__ void corners_in(const T* plane, const CellAddr& a, fl
 
 // 8 corner values of one plane: out-of-grid corners take `outv`, corners in
 // bricks without a slot (brick-pool maps) `priorv`
-template <typename T>
+template <typename T, bool Pool>
 __device__ __forceinline__ void corners(const GridC& g, const T* plane, const Cell& c, float outv, float priorv,
                                         float v[8]) {
     if (cell_inside(g, c)) {
         CellAddr a = cell_addr(g, c);
-        if (!g.table) {
+        if constexpr (!Pool) {
             corners_in(plane, a, v);
             return;
         }
@@ -322,7 +323,7 @@ __device__ __forceinline__ void corners(const GridC& g, const T* plane, const Ce
     for (int q = 0; q < 8; ++q) {
         int dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
         bool ok = (dx ? okx1 : okx0) && (dy ? oky1 : oky0) && (dz ? okz1 : okz0);
-        const long long e = ok ? vidx(g, c.i[0] + dx, c.i[1] + dy, c.i[2] + dz) : -1;
+        const long long e = ok ? vidx<Pool>(g, c.i[0] + dx, c.i[1] + dy, c.i[2] + dz) : -1;
         v[q] = e >= 0 ? ld(plane, e) : ok ? priorv : outv;
     }
 }

@@ -258,7 +258,7 @@ __global__ __launch_bounds__(256) void k_cull(GridC g, CamC c, const prism_pose*
 
 
 // workgroup blk of ngroups of the update
-template <typename T>
+template <typename T, bool Pool>
 __device__ __forceinline__ void map_update_block(int blk, int ngroups, const GridC& g, const CamC& c, const GridD& gd,
                                                  T* __restrict__ map, const float* __restrict__ depth,
                                                  const float* __restrict__ rgb, const MapUpdC& mp, const MapAux& aux,
@@ -355,7 +355,7 @@ __device__ __forceinline__ void map_update_block(int blk, int ngroups, const Gri
         long long slot = b;
         bool fresh = false;
         float pvar = 0.0f;
-        if (aux.table) {
+        if constexpr (Pool) {
             int sl = aux.table[b];
             int any = 0;
 #pragma unroll
@@ -464,12 +464,12 @@ __device__ __forceinline__ void map_update_block(int blk, int ngroups, const Gri
     if (threadIdx.x == 0) aux.counts[blk] = lcnt[0] + lcnt[1] + lcnt[2] + lcnt[3];
 }
 
-template <typename T>
+template <typename T, bool Pool>
 __global__ __launch_bounds__(256) void k_map_update(GridC g, CamC c, GridD gd, T* __restrict__ map,
                                                     const float* __restrict__ depth,
                                                     const float* __restrict__ rgb, MapUpdC mp, MapAux aux,
                                                     int nseg) {
-    map_update_block<T>(blockIdx.x, gridDim.x, g, c, gd, map, depth, rgb, mp, aux, nseg);
+    map_update_block<T, Pool>(blockIdx.x, gridDim.x, g, c, gd, map, depth, rgb, mp, aux, nseg);
 }
 
 // batched: every filter culls / updates its map at its posterior mean with
@@ -480,12 +480,12 @@ __global__ __launch_bounds__(256) void k_cull_batch(BatchArgs b) {
     cull_block(blockIdx.x - b.start[a], D.g, D.c, &D.S->pose, D.aux);
 }
 
-template <typename T>
+template <typename T, bool Pool>
 __global__ __launch_bounds__(256) void k_map_update_batch(BatchArgs b) {
     const int a = batch_agent(b, blockIdx.x);
     const AgentDesc& D = *b.d[a];
     const prism_frame& fr = D.slots[b.slot[a]];
-    map_update_block<T>(blockIdx.x - b.start[a], D.upd_groups, D.g, D.c, D.gd, (T*)D.map, (const float*)fr.depth,
+    map_update_block<T, Pool>(blockIdx.x - b.start[a], D.upd_groups, D.g, D.c, D.gd, (T*)D.map, (const float*)fr.depth,
                         (const float*)fr.rgb, D.mp, D.aux, D.nseg);
 }
 
@@ -719,10 +719,15 @@ hipError_t launch_map_update(const GridC& g, const CamC& c, const GridD& gd, int
     int ng = update_grid(g);
     size_t lds = (size_t)(nseg + 1) * sizeof(int);
     if (t_begin && (e = hipEventRecord(t_begin, st)) != hipSuccess) return e;
-    if (dtype == PRISM_BF16)
-        k_map_update<uint16_t><<<ng, 256, lds, st>>>(g, c, gd, (uint16_t*)map, depth, rgb, mp, aux, nseg);
+    const bool pool = aux.table != nullptr;
+    if (dtype == PRISM_BF16 && pool)
+        k_map_update<uint16_t, true><<<ng, 256, lds, st>>>(g, c, gd, (uint16_t*)map, depth, rgb, mp, aux, nseg);
+    else if (dtype == PRISM_BF16)
+        k_map_update<uint16_t, false><<<ng, 256, lds, st>>>(g, c, gd, (uint16_t*)map, depth, rgb, mp, aux, nseg);
+    else if (pool)
+        k_map_update<float, true><<<ng, 256, lds, st>>>(g, c, gd, (float*)map, depth, rgb, mp, aux, nseg);
     else
-        k_map_update<float><<<ng, 256, lds, st>>>(g, c, gd, (float*)map, depth, rgb, mp, aux, nseg);
+        k_map_update<float, false><<<ng, 256, lds, st>>>(g, c, gd, (float*)map, depth, rgb, mp, aux, nseg);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (t_end && (e = hipEventRecord(t_end, st)) != hipSuccess) return e;
@@ -738,12 +743,16 @@ hipError_t launch_cull_batch(const BatchArgs& b, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_map_update_batch(const BatchArgs& b, int dtype, int max_nseg, hipStream_t st) {
+hipError_t launch_map_update_batch(const BatchArgs& b, int dtype, bool pool, int max_nseg, hipStream_t st) {
     size_t lds = (size_t)(max_nseg + 1) * sizeof(int);
-    if (dtype == PRISM_BF16)
-        k_map_update_batch<uint16_t><<<b.start[b.n], 256, lds, st>>>(b);
+    if (dtype == PRISM_BF16 && pool)
+        k_map_update_batch<uint16_t, true><<<b.start[b.n], 256, lds, st>>>(b);
+    else if (dtype == PRISM_BF16)
+        k_map_update_batch<uint16_t, false><<<b.start[b.n], 256, lds, st>>>(b);
+    else if (pool)
+        k_map_update_batch<float, true><<<b.start[b.n], 256, lds, st>>>(b);
     else
-        k_map_update_batch<float><<<b.start[b.n], 256, lds, st>>>(b);
+        k_map_update_batch<float, false><<<b.start[b.n], 256, lds, st>>>(b);
     return hipGetLastError();
 }
 

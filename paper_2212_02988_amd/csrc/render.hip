@@ -29,10 +29,10 @@ struct RayHit {
     Cell c0, c1;    // cells of samples k*-1, k*
 };
 
-template <typename T>
+template <typename T, bool Pool>
 __device__ __forceinline__ float occ_at(const GridC& g, const T* occ, const Cell& c) {
     float v[8];
-    corners(g, occ, c, g.occ_out, g.pocc, v);
+    corners<T, Pool>(g, occ, c, g.occ_out, g.pocc, v);
     return trilerp(v, c.w);
 }
 
@@ -56,17 +56,17 @@ __device__ __forceinline__ bool cell_free(const GridC& g, lds_u32* bits, const C
 
 // occupancy of a marched sample, or -1 when the free-space bits prove it is
 // <= 0 (bits: the workgroup's LDS copy, non-NULL only when tau == 0)
-template <typename T>
+template <typename T, bool Pool>
 __device__ __forceinline__ float march_occ(const GridC& g, const T* occ, lds_u32* bits, const Cell& cl) {
     if (cell_inside(g, cl)) {
         CellAddr a = cell_addr(g, cl);
         if (bits && cell_free(g, bits, a)) return -1.0f;
-        if (g.table) return occ_at(g, occ, cl);   // brick-pool map: through the slot table
+        if constexpr (Pool) return occ_at<T, Pool>(g, occ, cl);   // brick-pool map: through the slot table
         float v[8];
         corners_in_g(as_global(occ), a, v);
         return trilerp(v, cl.w);
     }
-    return occ_at(g, occ, cl);
+    return occ_at<T, Pool>(g, occ, cl);
 }
 
 // Free-space bits for this block, copied into LDS; NULL (no skipping) when
@@ -91,7 +91,7 @@ struct Shade {
 // trilinear value of one plane in double precision: cell from the decision
 // recipe, weights from the double-precision grid coordinate, sum over the 8
 // corners of the product of 1-D hat weights (z, y, x order)
-template <typename T>
+template <typename T, bool Pool>
 __device__ __forceinline__ double tri64(const GridC& g, const T* plane, const double gc[3], const int cell[3],
                                         double outv, float priorv) {
     double w0 = gc[0] - (double)cell[0], w1 = gc[1] - (double)cell[1], w2 = gc[2] - (double)cell[2];
@@ -107,7 +107,7 @@ __device__ __forceinline__ double tri64(const GridC& g, const T* plane, const do
                 double hz = cz ? w2 : 1.0 - w2;
                 int i = cell[0] + cx, j = cell[1] + cy, k = cell[2] + cz;
                 bool in = (unsigned)i < (unsigned)g.n && (unsigned)j < (unsigned)g.n && (unsigned)k < (unsigned)g.n;
-                const long long e = in ? vidx(g, i, j, k) : -1;
+                const long long e = in ? vidx<Pool>(g, i, j, k) : -1;
                 double V = e >= 0 ? (double)ld(plane, e) : in ? (double)priorv : outv;
                 s += hx * hy * hz * V;
             }
@@ -125,7 +125,7 @@ __device__ __forceinline__ void grid_coord64(const GridD& gd, const CamD& cd, co
     }
 }
 
-template <typename T>
+template <typename T, bool Pool>
 __device__ __forceinline__ Shade shade(const GridC& g, const GridD& gd, const CamD& cd, const Pose64& P, int u,
                                        int v, const T* map, const RayHit& h) {
     Shade s;
@@ -137,8 +137,8 @@ __device__ __forceinline__ Shade shade(const GridC& g, const GridD& gd, const Ca
     grid_coord64(gd, cd, P, dir, h.k, gc1);
     double d0 = cd.dn + (double)(h.k - 1) * cd.step;
     double d1 = cd.dn + (double)h.k * cd.step;
-    s.f0 = tri64(g, map, gc0, h.c0.i, gd.occ_out, g.pocc);
-    s.f1 = tri64(g, map, gc1, h.c1.i, gd.occ_out, g.pocc);
+    s.f0 = tri64<T, Pool>(g, map, gc0, h.c0.i, gd.occ_out, g.pocc);
+    s.f1 = tri64<T, Pool>(g, map, gc1, h.c1.i, gd.occ_out, g.pocc);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         s.w0[a] = (float)(gc0[a] - (double)h.c0.i[a]);
@@ -149,8 +149,8 @@ __device__ __forceinline__ Shade shade(const GridC& g, const GridD& gd, const Ca
 #pragma unroll 1
     for (int ch = 0; ch < 3; ++ch) {
         const T* pl = map + (long long)(1 + ch) * g.nvox;
-        double c0 = tri64(g, pl, gc0, h.c0.i, gd.rgb_out, g.prgb);
-        double c1 = tri64(g, pl, gc1, h.c1.i, gd.rgb_out, g.prgb);
+        double c0 = tri64<T, Pool>(g, pl, gc0, h.c0.i, gd.rgb_out, g.prgb);
+        double c1 = tri64<T, Pool>(g, pl, gc1, h.c1.i, gd.rgb_out, g.prgb);
         s.rgb[ch] = al * c1 + (1.0 - al) * c0;
         s.c0[ch] = (float)c0;
         s.c1[ch] = (float)c1;
@@ -168,16 +168,16 @@ __device__ __forceinline__ void cross3(const float a[3], const float b[3], float
 }
 
 // d(depth, r, g, b)/d(delta) of a valid ray (k* held fixed)
-template <typename T>
+template <typename T, bool Pool>
 __device__ __forceinline__ void ray_jacobian(const GridC& g, const T* map, const RayHit& h,
                                              const Shade& s, const float dir[3], float J[4][6]) {
     float a0[3], a1[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) { a0[i] = s.d0 * dir[i]; a1[i] = s.d1 * dir[i]; }
     float v[8], gr0[3], gr1[3], cr[3];
-    corners(g, map, h.c0, g.occ_out, g.pocc, v);
+    corners<T, Pool>(g, map, h.c0, g.occ_out, g.pocc, v);
     trigrad(v, s.w0, gr0);
-    corners(g, map, h.c1, g.occ_out, g.pocc, v);
+    corners<T, Pool>(g, map, h.c1, g.occ_out, g.pocc, v);
     trigrad(v, s.w1, gr1);
     float rf0[6], rf1[6];
 #pragma unroll
@@ -199,9 +199,9 @@ __device__ __forceinline__ void ray_jacobian(const GridC& g, const T* map, const
     for (int ch = 0; ch < 3; ++ch) {
         const T* pl = map + (long long)(1 + ch) * g.nvox;
         float G0[3], G1[3], g0[6], g1[6];
-        corners(g, pl, h.c0, g.rgb_out, g.prgb, v);
+        corners<T, Pool>(g, pl, h.c0, g.rgb_out, g.prgb, v);
         trigrad(v, s.w0, G0);
-        corners(g, pl, h.c1, g.rgb_out, g.prgb, v);
+        corners<T, Pool>(g, pl, h.c1, g.rgb_out, g.prgb, v);
         trigrad(v, s.w1, G1);
 #pragma unroll
         for (int i = 0; i < 3; ++i) { G0[i] *= g.inv_s; G1[i] *= g.inv_s; g0[i] = G0[i]; g1[i] = G1[i]; }
@@ -266,7 +266,7 @@ __device__ __forceinline__ float quad_bcastf(float x, int src_lane_in_quad) {
 
 // first sample index whose occupancy exceeds tau (strictly), or -1; every
 // lane of the quad returns the same value
-template <typename T>
+template <typename T, bool Pool>
 __device__ __forceinline__ int march_quad(const GridC& g, const CamC& c, const RayCoef& rc, const T* occ,
                                           lds_u32* bits, int s) {
     constexpr int G = kLanes * kPerLane;
@@ -276,7 +276,7 @@ __device__ __forceinline__ int march_quad(const GridC& g, const CamC& c, const R
         for (int j = 0; j < kPerLane; ++j) {
             int k = k0 + j * kLanes + s;
             Cell cl = sample_cell(rc, min(k, c.K - 1));
-            f[j] = march_occ(g, occ, bits, cl);
+            f[j] = march_occ<T, Pool>(g, occ, bits, cl);
         }
         int first = 0x7fffffff;
 #pragma unroll
@@ -301,7 +301,7 @@ struct QuadShade {
     float d0, d1;
 };
 
-template <typename T>
+template <typename T, bool Pool>
 __device__ __forceinline__ QuadShade shade_quad(const GridC& g, const GridD& gd, const CamD& cd, const Pose64& P,
                                                 int u, int v, const T* map, const Cell& c0, const Cell& c1, int k,
                                                 int s) {
@@ -317,8 +317,8 @@ __device__ __forceinline__ QuadShade shade_quad(const GridC& g, const GridD& gd,
     const T* pl = map + (long long)s * g.nvox;
     double outv = s == 0 ? gd.occ_out : gd.rgb_out;
     float priorv = s == 0 ? g.pocc : g.prgb;
-    q.v0 = tri64(g, pl, gc0, c0.i, outv, priorv);
-    q.v1 = tri64(g, pl, gc1, c1.i, outv, priorv);
+    q.v0 = tri64<T, Pool>(g, pl, gc0, c0.i, outv, priorv);
+    q.v1 = tri64<T, Pool>(g, pl, gc1, c1.i, outv, priorv);
     q.f0 = quad_bcast(q.v0, 0);
     q.f1 = quad_bcast(q.v1, 0);
     q.alpha = (cd.tau - q.f0) / (q.f1 - q.f0);
@@ -335,7 +335,7 @@ __device__ __forceinline__ QuadShade shade_quad(const GridC& g, const GridD& gd,
 
 // This lane's row of the 4x6 Jacobian d(depth, r, g, b)/d(delta), k* fixed.
 // Lane 0 forms d(alpha)/d(delta) from the occupancy gradients and shares it.
-template <typename T>
+template <typename T, bool Pool>
 __device__ __forceinline__ void jac_row_quad(const GridC& g, const T* map, const Cell& c0, const Cell& c1,
                                              const QuadShade& q, const float dir[3], int s, float row[6]) {
     float a0[3], a1[3];
@@ -344,9 +344,9 @@ __device__ __forceinline__ void jac_row_quad(const GridC& g, const T* map, const
     const T* pl = map + (long long)s * g.nvox;
     float outv = s == 0 ? g.occ_out : g.rgb_out, priorv = s == 0 ? g.pocc : g.prgb;
     float v[8], G0[3], G1[3], cr[3], r0[6], r1[6];
-    corners(g, pl, c0, outv, priorv, v);
+    corners<T, Pool>(g, pl, c0, outv, priorv, v);
     trigrad(v, q.w0, G0);
-    corners(g, pl, c1, outv, priorv, v);
+    corners<T, Pool>(g, pl, c1, outv, priorv, v);
     trigrad(v, q.w1, G1);
 #pragma unroll
     for (int i = 0; i < 3; ++i) { G0[i] *= g.inv_s; G1[i] *= g.inv_s; r0[i] = G0[i]; r1[i] = G1[i]; }
@@ -387,7 +387,7 @@ __device__ __forceinline__ void quad_pixel(const CamC& c, int blk, int& u, int& 
 // render
 // ---------------------------------------------------------------------------
 // workgroup blk (8x8 pixel tile) of frame `frame`, rendered at *pose
-template <typename T>
+template <typename T, bool Pool>
 __device__ __forceinline__ void render_block(int blk, int frame, const GridC& g, const CamC& c, const GridD& gd,
                                              const CamD& cd, const T* __restrict__ map,
                                              const unsigned* __restrict__ gbits, const prism_pose* __restrict__ pose,
@@ -403,7 +403,7 @@ __device__ __forceinline__ void render_block(int blk, int frame, const GridC& g,
     float dir[3];
     ray_dir32(c, P.f, u, v, dir);
     const RayCoef rc = ray_coef(g, c, P.f, dir);
-    int k = march_quad(g, c, rc, map, bits, s);
+    int k = march_quad<T, Pool>(g, c, rc, map, bits, s);
     long long pix = (long long)frame * c.W * c.H + (long long)v * c.W + u;
     if (s == 0) {
         if (hit_k) hit_k[pix] = k;
@@ -411,7 +411,7 @@ __device__ __forceinline__ void render_block(int blk, int frame, const GridC& g,
     }
     if (k >= 1) {
         Cell c0 = sample_cell(rc, k - 1), c1 = sample_cell(rc, k);
-        QuadShade q = shade_quad(g, gd, cd, P.d, u, v, map, c0, c1, k, s);
+        QuadShade q = shade_quad<T, Pool>(g, gd, cd, P.d, u, v, map, c0, c1, k, s);
         if (s == 0)
             depth[pix] = (float)q.value;
         else
@@ -424,22 +424,22 @@ __device__ __forceinline__ void render_block(int blk, int frame, const GridC& g,
     }
 }
 
-template <typename T>
+template <typename T, bool Pool>
 __global__ __launch_bounds__(256) void k_render(GridC g, CamC c, GridD gd, CamD cd, const T* __restrict__ map,
                                                 const unsigned* __restrict__ gbits,
                                                 const prism_pose* __restrict__ poses,
                                                 float* __restrict__ depth, float* __restrict__ rgb,
                                                 uint8_t* __restrict__ mask, int32_t* __restrict__ hit_k) {
-    render_block<T>(blockIdx.x, blockIdx.y, g, c, gd, cd, map, gbits, poses + blockIdx.y, depth, rgb, mask, hit_k);
+    render_block<T, Pool>(blockIdx.x, blockIdx.y, g, c, gd, cd, map, gbits, poses + blockIdx.y, depth, rgb, mask, hit_k);
 }
 
 // batched: every filter renders its next anchor from its updated map at its
 // posterior mean
-template <typename T>
+template <typename T, bool Pool>
 __global__ __launch_bounds__(256) void k_render_batch(BatchArgs b) {
     const int a = batch_agent(b, blockIdx.x);
     const AgentDesc& D = *b.d[a];
-    render_block<T>(blockIdx.x - b.start[a], 0, D.g, D.c, D.gd, D.cd, (const T*)D.map, D.bits, &D.S->pose, D.a_depth,
+    render_block<T, Pool>(blockIdx.x - b.start[a], 0, D.g, D.c, D.gd, D.cd, (const T*)D.map, D.bits, &D.S->pose, D.a_depth,
                     D.a_rgb, D.a_mask, nullptr);
 }
 
@@ -510,7 +510,7 @@ __global__ __launch_bounds__(256) void k_normals_batch(BatchArgs b) {
 // ---------------------------------------------------------------------------
 // render + P1 Jacobian + gated weighted normal equations
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool Pool>
 __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, GridD gd, CamD cd, const T* __restrict__ map,
                                                     const unsigned* __restrict__ gbits,
                                                     const prism_pose* __restrict__ poses,
@@ -536,7 +536,7 @@ __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, GridD gd, C
         float dir[3];
         ray_dir32(c, P.f, u, v, dir);
         const RayCoef rc = ray_coef(g, c, P.f, dir);
-        int k = march_quad(g, c, rc, map, bits, s);
+        int k = march_quad<T, Pool>(g, c, rc, map, bits, s);
         long long pix = (long long)blockIdx.y * c.W * c.H + (long long)v * c.W + u;
         float row[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         double r = 0.0;
@@ -545,11 +545,11 @@ __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, GridD gd, C
         double value = 0.0;
         if (valid) {
             Cell c0 = sample_cell(rc, k - 1), c1 = sample_cell(rc, k);
-            QuadShade q = shade_quad(g, gd, cd, P.d, u, v, map, c0, c1, k, s);
+            QuadShade q = shade_quad<T, Pool>(g, gd, cd, P.d, u, v, map, c0, c1, k, s);
             value = q.value;
             float D = obs_depth[pix];
             if (depth_ok(D)) {
-                jac_row_quad(g, map, c0, c1, q, dir, s, row);
+                jac_row_quad<T, Pool>(g, map, c0, c1, q, dir, s, row);
                 r = s == 0 ? value - (double)D : value - (double)obs_rgb[3 * pix + s - 1];
                 // colour gate on |r_r| + |r_g| + |r_b| (lanes 1-3), depth gate on lane 0
                 double l1 = s == 0 ? 0.0 : fabs(r);
@@ -655,14 +655,14 @@ __global__ __launch_bounds__(256) void k_render_vjp(GridC g, CamC c, GridD gd, C
             h.k = k;
             h.c0 = sample_cell(rc, k - 1);
             h.c1 = sample_cell(rc, k);
-            h.f0 = occ_at(g, map, h.c0);
-            h.f1 = occ_at(g, map, h.c1);
+            h.f0 = occ_at<float, false>(g, map, h.c0);
+            h.f1 = occ_at<float, false>(g, map, h.c1);
             if (h.f1 > c.tau && !(h.f0 > c.tau)) {
-                Shade s = shade(g, gd, cd, P.d, u, v, map, h);
+                Shade s = shade<float, false>(g, gd, cd, P.d, u, v, map, h);
                 float gd = g_depth[pix];
                 float gc[3] = {g_rgb[3 * pix], g_rgb[3 * pix + 1], g_rgb[3 * pix + 2]};
                 float J[4][6];
-                ray_jacobian(g, map, h, s, dir, J);
+                ray_jacobian<float, false>(g, map, h, s, dir, J);
 #pragma unroll
                 for (int m = 0; m < 6; ++m)
                     acc[m] = (double)(gd * J[0][m] + gc[0] * J[1][m] + gc[1] * J[2][m] + gc[2] * J[3][m]);
@@ -795,12 +795,12 @@ __global__ __launch_bounds__(256) void k_gd_grad(GridC g, CamC c, GridD gd, CamD
         float dir[3];
         ray_dir32(c, P.f, u, v, dir);
         const RayCoef rc = ray_coef(g, c, P.f, dir);
-        const int k = march_quad(g, c, rc, map, bits, s);
+        const int k = march_quad<float, false>(g, c, rc, map, bits, s);
         const long long pix = (long long)v * c.W + u;
         const float D = obs_depth[pix];
         if (k >= 1 && depth_ok(D)) {   // the same for the four lanes of a ray
             const Cell c0 = sample_cell(rc, k - 1), c1 = sample_cell(rc, k);
-            const QuadShade q = shade_quad(g, gd, cd, P.d, u, v, map, c0, c1, k, s);
+            const QuadShade q = shade_quad<float, false>(g, gd, cd, P.d, u, v, map, c0, c1, k, s);
             const double r = s == 0 ? q.value - (double)D : q.value - (double)obs_rgb[3 * pix + s - 1];
             double l1 = s == 0 ? 0.0 : fabs(r);
             l1 += __shfl_xor(l1, 1, 64);
@@ -860,23 +860,32 @@ hipError_t launch_render(const GridC& g, const CamC& c, const GridD& gd, const C
                          uint8_t* mask, int32_t* hit_k, hipStream_t st) {
     dim3 grid(render_blocks(c), n_frames);
     size_t lds = bits_lds(g, bits);
-    if (dtype == PRISM_BF16)
-        k_render<uint16_t><<<grid, 256, lds, st>>>(g, c, gd, cd, (const uint16_t*)map, bits, poses, depth, rgb, mask,
-                                                   hit_k);
+    const bool pool = g.table != nullptr;
+    const uint16_t* mh = (const uint16_t*)map;
+    const float* mf = (const float*)map;
+    if (dtype == PRISM_BF16 && pool)
+        k_render<uint16_t, true><<<grid, 256, lds, st>>>(g, c, gd, cd, mh, bits, poses, depth, rgb, mask, hit_k);
+    else if (dtype == PRISM_BF16)
+        k_render<uint16_t, false><<<grid, 256, lds, st>>>(g, c, gd, cd, mh, bits, poses, depth, rgb, mask, hit_k);
+    else if (pool)
+        k_render<float, true><<<grid, 256, lds, st>>>(g, c, gd, cd, mf, bits, poses, depth, rgb, mask, hit_k);
     else
-        k_render<float><<<grid, 256, lds, st>>>(g, c, gd, cd, (const float*)map, bits, poses, depth, rgb, mask,
-                                                hit_k);
+        k_render<float, false><<<grid, 256, lds, st>>>(g, c, gd, cd, mf, bits, poses, depth, rgb, mask, hit_k);
     return hipGetLastError();
 }
 
-hipError_t launch_render_batch(const BatchArgs& b, int dtype, int max_bits_words, hipStream_t st) {
+hipError_t launch_render_batch(const BatchArgs& b, int dtype, bool pool, int max_bits_words, hipStream_t st) {
     // filters whose bits fit copy them to LDS, the others march without
     // skipping (block_bits), so the allocation is the largest that fits
     size_t lds = (size_t)(max_bits_words < kMaxLdsWords ? max_bits_words : kMaxLdsWords) * 4;
-    if (dtype == PRISM_BF16)
-        k_render_batch<uint16_t><<<b.start[b.n], 256, lds, st>>>(b);
+    if (dtype == PRISM_BF16 && pool)
+        k_render_batch<uint16_t, true><<<b.start[b.n], 256, lds, st>>>(b);
+    else if (dtype == PRISM_BF16)
+        k_render_batch<uint16_t, false><<<b.start[b.n], 256, lds, st>>>(b);
+    else if (pool)
+        k_render_batch<float, true><<<b.start[b.n], 256, lds, st>>>(b);
     else
-        k_render_batch<float><<<b.start[b.n], 256, lds, st>>>(b);
+        k_render_batch<float, false><<<b.start[b.n], 256, lds, st>>>(b);
     return hipGetLastError();
 }
 
@@ -901,12 +910,21 @@ hipError_t launch_render_jac(const GridC& g, const CamC& c, const GridD& gd, con
                              hipStream_t st) {
     dim3 grid(render_blocks(c), n_frames);
     size_t lds = bits_lds(g, bits);
-    if (dtype == PRISM_BF16)
-        k_render_jac<uint16_t><<<grid, 256, lds, st>>>(g, c, gd, cd, (const uint16_t*)map, bits, poses, obs_depth,
-                                                       obs_rgb, w, depth, rgb, mask, J, resid, rowmask, partials);
+    const bool pool = g.table != nullptr;
+    const uint16_t* mh = (const uint16_t*)map;
+    const float* mf = (const float*)map;
+    if (dtype == PRISM_BF16 && pool)
+        k_render_jac<uint16_t, true><<<grid, 256, lds, st>>>(g, c, gd, cd, mh, bits, poses, obs_depth, obs_rgb, w,
+                                                             depth, rgb, mask, J, resid, rowmask, partials);
+    else if (dtype == PRISM_BF16)
+        k_render_jac<uint16_t, false><<<grid, 256, lds, st>>>(g, c, gd, cd, mh, bits, poses, obs_depth, obs_rgb, w,
+                                                              depth, rgb, mask, J, resid, rowmask, partials);
+    else if (pool)
+        k_render_jac<float, true><<<grid, 256, lds, st>>>(g, c, gd, cd, mf, bits, poses, obs_depth, obs_rgb, w,
+                                                          depth, rgb, mask, J, resid, rowmask, partials);
     else
-        k_render_jac<float><<<grid, 256, lds, st>>>(g, c, gd, cd, (const float*)map, bits, poses, obs_depth, obs_rgb,
-                                                    w, depth, rgb, mask, J, resid, rowmask, partials);
+        k_render_jac<float, false><<<grid, 256, lds, st>>>(g, c, gd, cd, mf, bits, poses, obs_depth, obs_rgb, w,
+                                                           depth, rgb, mask, J, resid, rowmask, partials);
     return hipGetLastError();
 }
 

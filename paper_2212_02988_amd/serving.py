@@ -208,6 +208,9 @@ class ServingLoop:
         # totals for throughput accounting (one small read of the state)
         st0 = ag.filter.state()
         self.totals[sid] = dict(steps=int(st0.step), n_updated_total=int(st0.n_updated_total))
+        if ag.spec.grid.capacity > 0:
+            used, dropped = (int(v) for v in ag.filter.map.pool_usage(stream=ag.stream).cpu())
+            self.totals[sid].update(pool_used=used, pool_dropped=dropped, pool_capacity=int(ag.spec.grid.capacity))
         if self.keep_final:
             st = ag.filter.state()
             mean, var = ag.filter.map.to_dense(stream=ag.stream)
