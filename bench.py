@@ -359,6 +359,54 @@ def mapping_comparison(P, torch, lr_occ=3e-6, lr_rgb=3e-3, n_prior=20):
 
 
 # ---------------------------------------------------------------------------
+# brick-pool maps in a large room
+# ---------------------------------------------------------------------------
+def large_room_pool(P, torch, n_frames=60):
+    """One stream in a 25.6 m room on a 512^3 BF16 grid (5 cm voxels), K = 128,
+    320x240: the same filter steps on a dense map and on a brick-pool map with
+    room for every brick; step time, map bytes, the fraction of bricks that
+    received a slot, and whether the two final states agree bit for bit."""
+    import synth
+    N, Wd, Ht, K, room = 512, 320, 240, 128, 25.6
+    case = synth.trajectory_case(seed=5, n=N, width=Wd, height=Ht, n_samples=K, n_frames=n_frames, room=room,
+                                 frames=False)
+    tr, scene, cm = case["traj"], case["scene"], case["cam"]
+    D, C = synth.raycast_torch(scene, cm, tr.t, tr.q, 5, 0.01, 0.02)
+    cam = P.Camera.make(cm.width, cm.height, cm.fx, cm.fy, cm.cx, cm.cy, cm.d_near, cm.d_far, cm.n_samples)
+    U = torch.from_numpy(np.concatenate([tr.u, tr.u[-1:]], 0)).to("cuda")
+    nb3 = (N // 8) ** 3
+    out, states = {}, {}
+    for name, cap in (("dense", 0), ("pool", nb3)):
+        grid = P.Grid.make(N, scene.voxel, tuple(float(v) for v in scene.origin), dtype=P.PRISM_BF16, capacity=cap)
+        f = P.Filter(grid, cam, P.FilterParams(n_gn=3, objective=P.OBJ_P2))
+        f.map.init()
+        f.reset(np.concatenate([tr.t[0], tr.q[0], tr.v[0], tr.w[0]]), np.diag([1e-6] * 6 + [1e-4] * 6))
+        torch.cuda.synchronize()
+        ms = []
+        for i in range(n_frames):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            f.step(D[i], C[i], U[i - 1] if i else None)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        states[name] = bytes(f.state())
+        o = {"map_gb": round(P.map_bytes(grid) / 2**30, 3), "step_ms": round(float(np.median(ms[5:])), 4)}
+        if cap:
+            used = int(f.map.pool_usage()[0].item())
+            o.update(bricks_used=used, fraction_used=round(used / nb3, 4),
+                     pool_gb_needed=round(used * 8 * 512 * 2 / 2**30, 3))
+        out[name] = o
+        del f
+    out["same_state"] = states["dense"] == states["pool"]
+    out["workload"] = (f"one stream, 512^3 BF16 grid over a 25.6 m room (5 cm voxels), 320x240, K = 128, "
+                       f"{n_frames} frames")
+    log(f"large room: dense {out['dense']}, pool {out['pool']}, same state {out['same_state']}")
+    return out
+
+
+# ---------------------------------------------------------------------------
 # pose optimisers: dense Gauss-Newton against the paper's Adam
 # ---------------------------------------------------------------------------
 def pose_optimisers(P, torch, n_frames=16):
@@ -607,6 +655,7 @@ def main():
     single = single_stream(P, torch, args.single_steps, 10)
     mapping = mapping_comparison(P, torch)
     optimisers = pose_optimisers(P, torch)
+    big_room = large_room_pool(P, torch)
 
     cpu = None
     if not args.no_cpu:
@@ -664,6 +713,7 @@ def main():
                     "ms": r(single["ms_roll"], 3), "mrays_per_s": r(single["mrays_roll"], 1)},
         "mapping_gd_vs_closed_form": mapping,
         "pose_optimisers": optimisers,
+        "large_room_pool": big_room,
         "roofline": roofline_obj(dominant, dom_roof, breakdown),
         "kernel_breakdown": breakdown,
         "roofline_map_update_single": {

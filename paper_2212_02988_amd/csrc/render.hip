@@ -61,7 +61,15 @@ __device__ __forceinline__ float march_occ(const GridC& g, const T* occ, lds_u32
     if (cell_inside(g, cl)) {
         CellAddr a = cell_addr(g, cl);
         if (bits && cell_free(g, bits, a)) return -1.0f;
-        if constexpr (Pool) return occ_at<T, Pool>(g, occ, cl);   // brick-pool map: through the slot table
+        if constexpr (Pool) {
+            // brick-pool map: a single-brick cell through its slot (a brick
+            // without one reads as the prior everywhere, and the trilinear
+            // blend of equal values is that value); others corner by corner
+            if (a.cross) return occ_at<T, Pool>(g, occ, cl);
+            const int slot = g.table[a.b0];
+            if (slot < 0) return g.pocc;
+            a.base = (slot << 9) | (a.base & 511);
+        }
         float v[8];
         corners_in_g(as_global(occ), a, v);
         return trilerp(v, cl.w);
