@@ -574,7 +574,7 @@ def main():
                     help="serve without batching (each agent's step its own graph launch)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=16.0)
-    ap.add_argument("--calib", action="store_true", help="also run a 256 MiB device copy (counter calibration)")
+    ap.add_argument("--calib", action="store_true", help="also run two 256 MiB device copies (counter calibration)")
     ap.add_argument("--pool-frac", type=float, default=1.0,
                     help="brick-pool run: fraction of each grid's bricks the pool holds")
     args = ap.parse_args()
@@ -649,7 +649,8 @@ def main():
     if args.calib:
         src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        dst.copy_(src)                     # the runtime's blit copy
+        torch.bitwise_not(src, out=dst)    # a plain elementwise kernel: reads and writes 256 MiB once
         torch.cuda.synchronize()
 
     single = single_stream(P, torch, args.single_steps, 10)
