@@ -147,6 +147,8 @@ CamD cam_d(const prism_camera* c) {
     o.dn = c->d_near;
     o.step = (c->d_far - c->d_near) / (c->n_samples - 1);
     o.tau = c->tau;
+    o.ifx = 1.0 / c->fx;
+    o.ify = 1.0 / c->fy;
     return o;
 }
 

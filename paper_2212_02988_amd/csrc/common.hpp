@@ -63,6 +63,7 @@ struct GridD {
 struct CamD {
     double fx, fy, cx, cy;
     double dn, step, tau;
+    double ifx, ify;   // 1 / fx, 1 / fy
 };
 
 // Derived data and scratch that live in the map buffer after the planes.
@@ -119,8 +120,8 @@ __device__ inline Pose64 load_pose64(const prism_pose* pp) {
 }
 
 __device__ __forceinline__ void pixel_dir64(const CamD& c, int u, int v, double r[3]) {
-    r[0] = (((double)u + 0.5) - c.cx) / c.fx;
-    r[1] = (((double)v + 0.5) - c.cy) / c.fy;
+    r[0] = (((double)u + 0.5) - c.cx) * c.ifx;
+    r[1] = (((double)v + 0.5) - c.cy) * c.ify;
     r[2] = 1.0;
 }
 
@@ -413,7 +414,8 @@ __device__ __forceinline__ void neq_add(double acc[PRISM_NEQ], const float j[6],
     acc[27] += w * r * r;
 }
 
-// the same in single precision, for one pixel's few rows
+// the same in single precision, for one pixel's few rows (fused multiply-
+// adds: these sums are values, no decision depends on their rounding)
 __device__ __forceinline__ void neq_add32(float acc[PRISM_NEQ], const float j[6], float r, float w) {
     float wj[6];
 #pragma unroll
@@ -422,10 +424,10 @@ __device__ __forceinline__ void neq_add32(float acc[PRISM_NEQ], const float j[6]
 #pragma unroll
     for (int a = 0; a < 6; ++a)
 #pragma unroll
-        for (int b = a; b < 6; ++b) acc[q++] += wj[a] * j[b];
+        for (int b = a; b < 6; ++b, ++q) acc[q] = fmaf(wj[a], j[b], acc[q]);
 #pragma unroll
-    for (int a = 0; a < 6; ++a) acc[21 + a] += wj[a] * r;
-    acc[27] += w * r * r;
+    for (int a = 0; a < 6; ++a) acc[21 + a] = fmaf(wj[a], r, acc[21 + a]);
+    acc[27] = fmaf(w * r, r, acc[27]);
 }
 
 struct WeightsC {

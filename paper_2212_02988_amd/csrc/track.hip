@@ -3,7 +3,9 @@
 // bilinearly interpolated anchor colour, with the fused reduction of the
 // gated, weighted normal equations.  One observed pixel per lane, pixels in
 // row-major order so observation reads are coalesced; anchor reads are
-// gathers around the reprojected location.
+// gathers around the reprojected location.  (Two or four pixels per lane,
+// paying the 29-sum reduction once for them, measured slower: the kernel is
+// bound by the latency of its dependent gathers, not by issue.)
 #include "common.hpp"
 #include "launch.hpp"
 #include "se3.hpp"
@@ -101,9 +103,9 @@ __device__ __forceinline__ void p2_pixel(const CamC& c, const CamD& cd, const Re
         dY[a][0] = e0;
         dY[a][1] = e1;
         dY[a][2] = e2;
-        dY[a][3] = RX[1] * e2 - RX[2] * e1;
-        dY[a][4] = RX[2] * e0 - RX[0] * e2;
-        dY[a][5] = RX[0] * e1 - RX[1] * e0;
+        dY[a][3] = fmaf(RX[1], e2, -RX[2] * e1);
+        dY[a][4] = fmaf(RX[2], e0, -RX[0] * e2);
+        dY[a][5] = fmaf(RX[0], e1, -RX[1] * e0);
     }
     if (geo) {
         int q = giv * c.W + giu;
@@ -115,12 +117,13 @@ __device__ __forceinline__ void p2_pixel(const CamC& c, const CamD& cd, const Re
         r[0] = rg;
         float fn0 = (float)n0, fn1 = (float)n1, fn2 = (float)n2;
 #pragma unroll
-        for (int m = 0; m < 6; ++m) J[0][m] = -(fn0 * dY[0][m] + fn1 * dY[1][m] + fn2 * dY[2][m]);
+        for (int m = 0; m < 6; ++m) J[0][m] = -fmaf(fn2, dY[2][m], fmaf(fn1, dY[1][m], fn0 * dY[0][m]));
         if (fabs(rg) <= wt.gate_depth) rm |= 1;
     }
     if (pho) {
-        double ud = cd.fx * Yd[0] / Yd[2] + cd.cx;
-        double vd = cd.fy * Yd[1] / Yd[2] + cd.cy;
+        const double izd = 1.0 / Yd[2];
+        double ud = cd.fx * Yd[0] * izd + cd.cx;
+        double vd = cd.fy * Yd[1] * izd + cd.cy;
         double ax = (ud - 0.5) - (double)bix, ay = (vd - 0.5) - (double)biy;
         float Y2 = (float)Yd[2];
         float iz = 1.0f / Y2;
@@ -129,8 +132,8 @@ __device__ __forceinline__ void p2_pixel(const CamC& c, const CamD& cd, const Re
         float dum[6], dvm[6];
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
-            dum[m] = du_[0] * dY[0][m] + du_[2] * dY[2][m];
-            dvm[m] = dv_[1] * dY[1][m] + dv_[2] * dY[2][m];
+            dum[m] = fmaf(du_[2], dY[2][m], du_[0] * dY[0][m]);
+            dvm[m] = fmaf(dv_[2], dY[2][m], dv_[1] * dY[1][m]);
         }
         double l1 = 0.0;
 #pragma unroll
@@ -144,7 +147,7 @@ __device__ __forceinline__ void p2_pixel(const CamC& c, const CamD& cd, const Re
             r[1 + ch] = rp;
             l1 += fabs(rp);
 #pragma unroll
-            for (int m = 0; m < 6; ++m) J[1 + ch][m] = gu * dum[m] + gv * dvm[m];
+            for (int m = 0; m < 6; ++m) J[1 + ch][m] = fmaf(gv, dvm[m], gu * dum[m]);
         }
         if (l1 <= wt.gate_rgb) rm |= 2;
     }
