@@ -172,7 +172,7 @@ MapLayout map_layout(const prism_grid* g) {
     size_t plane = g->capacity > 0 ? (size_t)g->capacity * 512 : nvox;
     L.bmax = round_up(8 * plane * elem_size(g->dtype), 256);
     L.bits = L.bmax + round_up(4 * nb3, 256);
-    L.counts = L.bits + round_up(4 * ((nb3 + 31) / 32), 256);
+    L.counts = L.bits + round_up(8 * ((nb3 + 31) / 32), 256);   // plain and dilated bits
     L.list = L.counts + round_up(4 * (size_t)kUpdateGrid, 256);
     L.segcnt = L.list + round_up(4 * nseg * 256, 256);
     L.pose = L.segcnt + round_up(4 * nseg, 256);
@@ -1176,6 +1176,7 @@ int blocks_of(const prism_filter* f, int stage) {
         case 3: return f->desc.nseg;                         // cull
         case 4: return f->desc.upd_groups;                   // update
         case 5: return render_blocks(c);
+        case 7: return (free_words(f->g.nb) + 255) / 256;   // dilated free-space bits
         default: return (c.W * c.H + 255) / 256;             // normals
     }
 }
@@ -1247,23 +1248,24 @@ prism_status step_batch_chunk(prism_filter* const* fs, int n, const int* slot, h
     for (int kind = 0; kind < 4; ++kind) {
         const int dt = kind & 1 ? PRISM_BF16 : PRISM_F32;
         const bool pool = kind >= 2;
-        int m = 0, max_nseg = 0, max_words = 0;
+        int m = 0, max_nseg = 0, max_lds = 0;
         for (int j = 0; j < n_all; ++j) {
             const prism_filter* f = fs[all[j]];
             if (f->cfg.grid.dtype != dt || (f->cfg.grid.capacity > 0) != pool) continue;
             sub[m++] = all[j];
             if (f->desc.nseg > max_nseg) max_nseg = f->desc.nseg;
-            int words = f->desc.bits ? (f->g.nb * f->g.nb * f->g.nb + 31) >> 5 : 0;
-            if (words > max_words) max_words = words;
+            int words = f->desc.bits ? free_lds_words(free_words(f->g.nb)) : 0;
+            if (words > max_lds) max_lds = words;
         }
         if (!m) continue;
         {
             StageScope t(PRISM_STAGE_MAP_UPDATE, st);
             HIP_TRY(launch_map_update_batch(make_batch(fs, sub, m, slot, 4), dt, pool, max_nseg, st));
+            HIP_TRY(launch_dilate_batch(make_batch(fs, sub, m, slot, 7), st));
         }
         {
             StageScope t(PRISM_STAGE_RENDER, st);
-            HIP_TRY(launch_render_batch(make_batch(fs, sub, m, slot, 5), dt, pool, max_words, st));
+            HIP_TRY(launch_render_batch(make_batch(fs, sub, m, slot, 5), dt, pool, max_lds, st));
         }
     }
     {

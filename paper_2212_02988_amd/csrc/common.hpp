@@ -69,7 +69,10 @@ struct CamD {
 // Derived data and scratch that live in the map buffer after the planes.
 struct MapAux {
     float* bmax;      // [nb^3] largest occupancy mean of each brick
-    unsigned* bits;   // [ceil(nb^3/32)] bit b set iff bmax[b] <= 0 (free-space bricks)
+    unsigned* bits;   // [2 ceil(nb^3/32)] bit b set iff bmax[b] <= 0 (free-space bricks), then the
+                      // dilated bits: bit b set iff bits b + {0, 1} + {0, nb} + {0, nb^2} are all
+                      // set (past the last brick: 0), i.e. for a brick off the grid's last layers
+                      // the 2x2x2 block of bricks with lowest corner b is free
     int* counts;      // [kUpdateGrid] updated voxels per workgroup of the last update
     int* list;        // [nb^3] bricks in the view frustum, in 256-brick segments
     int* segcnt;      // [ceil(nb^3/256)] entries used in each segment
@@ -82,6 +85,17 @@ struct MapAux {
 };
 
 constexpr int kUpdateGrid = 2048;   // workgroups of the map-update kernel
+
+// words of one free-space bitmap (one bit per brick)
+__host__ __device__ inline int free_words(int nb) { return (nb * nb * nb + 31) >> 5; }
+
+// LDS words a render workgroup keeps of a grid's free-space bits: both
+// bitmaps when they fit, else the plain bits (cells that span bricks are then
+// tested brick by brick), else none (no skipping)
+constexpr int kMaxLdsWords = 12288;   // 48 KB
+__host__ __device__ inline int free_lds_words(int nwords) {
+    return 2 * nwords <= kMaxLdsWords ? 2 * nwords : nwords <= kMaxLdsWords ? nwords : 0;
+}
 
 // ---------------------------------------------------------------------------
 // pose -> single-precision rotation/translation

@@ -78,8 +78,11 @@ hipError_t launch_gn_step_batch(const BatchArgs& b, hipStream_t st);
 hipError_t launch_laplace_combine_batch(const BatchArgs& b, hipStream_t st);
 hipError_t launch_first_frame_batch(const BatchArgs& b, hipStream_t st);
 hipError_t launch_cull_batch(const BatchArgs& b, hipStream_t st);
+// recompute the dilated free-space bits of one map / of every map of a batch
+hipError_t launch_dilate(const GridC& g, const MapAux& aux, hipStream_t st);
+hipError_t launch_dilate_batch(const BatchArgs& b, hipStream_t st);
 hipError_t launch_map_update_batch(const BatchArgs& b, int dtype, bool pool, int max_nseg, hipStream_t st);
-hipError_t launch_render_batch(const BatchArgs& b, int dtype, bool pool, int max_bits_words, hipStream_t st);
+hipError_t launch_render_batch(const BatchArgs& b, int dtype, bool pool, int max_lds_words, hipStream_t st);
 hipError_t launch_normals_batch(const BatchArgs& b, hipStream_t st);
 int stage_blocks(const CamC& c);
 

@@ -190,6 +190,38 @@ __global__ __launch_bounds__(256) void k_pack_bits(int nbricks, MapAux aux) {
     aux.bits[w] = word;
 }
 
+// The dilated free-space bits (second bitmap after the plain one): word w
+// is the AND of the 32-bit windows of the plain bits that start at bricks
+// 32 w + {0, 1} + {0, nb} + {0, nb^2}; words past the bitmap read as 0.  A
+// cell that spans bricks lies inside the 2x2x2 block of its base corner's
+// brick, so this one bit proves such a cell free (a cell within one brick
+// uses the plain bit).  Recomputed after every change of the plain bits.
+__device__ __forceinline__ unsigned bits_window(const unsigned* __restrict__ bits, int nwords, int bit) {
+    const int w = bit >> 5, sh = bit & 31;
+    const unsigned lo = w < nwords ? bits[w] : 0u, hi = w + 1 < nwords ? bits[w + 1] : 0u;
+    return sh ? (lo >> sh) | (hi << (32 - sh)) : lo;
+}
+
+__device__ __forceinline__ void dilate_block(int blk, int nb, unsigned* __restrict__ bits) {
+    const int nwords = free_words(nb);
+    const int w = blk * (int)blockDim.x + (int)threadIdx.x;
+    if (w >= nwords) return;
+    const int b = w << 5, sy = nb, sz = nb * nb;
+    unsigned d = bits[w];
+    d &= bits_window(bits, nwords, b + 1);
+    d &= bits_window(bits, nwords, b + sy);
+    d &= bits_window(bits, nwords, b + sy + 1);
+    d &= bits_window(bits, nwords, b + sz);
+    d &= bits_window(bits, nwords, b + sz + 1);
+    d &= bits_window(bits, nwords, b + sz + sy);
+    d &= bits_window(bits, nwords, b + sz + sy + 1);
+    bits[nwords + w] = d;
+}
+
+__global__ __launch_bounds__(256) void k_dilate_bits(int nb, unsigned* __restrict__ bits) {
+    dilate_block(blockIdx.x, nb, bits);
+}
+
 // Conservative brick cull: true if no voxel centre of the brick can pass the
 // per-voxel test.  Each test is a convex region (behind the camera, or beyond
 // one side plane of the frustum) checked on the 8 corners of the brick's
@@ -480,6 +512,12 @@ __global__ __launch_bounds__(256) void k_cull_batch(BatchArgs b) {
     cull_block(blockIdx.x - b.start[a], D.g, D.c, &D.S->pose, D.aux);
 }
 
+__global__ __launch_bounds__(256) void k_dilate_bits_batch(BatchArgs b) {
+    const int a = batch_agent(b, blockIdx.x);
+    const AgentDesc& D = *b.d[a];
+    dilate_block(blockIdx.x - b.start[a], D.g.nb, D.aux.bits);
+}
+
 template <typename T, bool Pool>
 __global__ __launch_bounds__(256) void k_map_update_batch(BatchArgs b) {
     const int a = batch_agent(b, blockIdx.x);
@@ -604,7 +642,9 @@ hipError_t launch_gd_update(const GridC& g, float* map, const MapAux& aux, float
                             hipStream_t st) {
     k_gd_update<<<gd_update_groups(g), 256, 0, st>>>(g, map, aux, save, grad, list, saved, lr_occ, lr_rgb,
                                                      partials);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_dilate(g, aux, st);
 }
 
 hipError_t launch_gd_cost(const double* pd, int nd, const double* pp, int np, double* cost, hipStream_t st) {
@@ -621,11 +661,18 @@ __global__ __launch_bounds__(256) void k_sum_counts(const int* __restrict__ coun
 
 static unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
 
+hipError_t launch_dilate(const GridC& g, const MapAux& aux, hipStream_t st) {
+    k_dilate_bits<<<(unsigned)((free_words(g.nb) + 255) / 256), 256, 0, st>>>(g.nb, aux.bits);
+    return hipGetLastError();
+}
+
 static hipError_t launch_pack(const GridC& g, const MapAux& aux, hipStream_t st) {
     int nbricks = g.nb * g.nb * g.nb;
     int nwords = (nbricks + 31) >> 5;
     k_pack_bits<<<(unsigned)((nwords + 255) / 256), 256, 0, st>>>(nbricks, aux);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_dilate(g, aux, st);
 }
 
 
@@ -730,6 +777,7 @@ hipError_t launch_map_update(const GridC& g, const CamC& c, const GridD& gd, int
         k_map_update<float, false><<<ng, 256, lds, st>>>(g, c, gd, (float*)map, depth, rgb, mp, aux, nseg);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if ((e = launch_dilate(g, aux, st)) != hipSuccess) return e;
     if (t_end && (e = hipEventRecord(t_end, st)) != hipSuccess) return e;
     if (!n_updated) return hipSuccess;
     k_sum_counts<<<1, 256, 0, st>>>(aux.counts, ng, n_updated);
@@ -740,6 +788,11 @@ int map_update_groups(const GridC& g) { return update_grid(g); }
 
 hipError_t launch_cull_batch(const BatchArgs& b, hipStream_t st) {
     k_cull_batch<<<b.start[b.n], 256, 0, st>>>(b);
+    return hipGetLastError();
+}
+
+hipError_t launch_dilate_batch(const BatchArgs& b, hipStream_t st) {
+    k_dilate_bits_batch<<<b.start[b.n], 256, 0, st>>>(b);
     return hipGetLastError();
 }
 

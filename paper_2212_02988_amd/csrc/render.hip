@@ -9,7 +9,7 @@
 // which shortens each ray's chain of dependent gathers four-fold and gives the
 // GPU four times more waves to overlap.  Samples in bricks whose occupancy
 // is <= 0 everywhere are decided without touching the map (free-space bits
-// in LDS).  At the hit the quad splits the double-precision shading and the
+// in LDS; a cell spanning bricks reads one dilated bit for its 2x2x2 block).  At the hit the quad splits the double-precision shading and the
 // Jacobian by channel: lane 0 occupancy / depth, lanes 1-3 one colour each.
 //
 // The adjoint keeps one ray per lane (16x16 pixels per workgroup): it
@@ -21,7 +21,6 @@ namespace prism {
 
 constexpr int kLanes = 4;       // lanes per ray in render / render_jacobian
 constexpr int kPerLane = 2;     // samples per lane per trip
-constexpr int kMaxLdsWords = 12288;   // free-space bits kept in LDS up to 48 KB (grids up to n = 576)
 
 struct RayHit {
     int k;          // k* or -1
@@ -44,23 +43,35 @@ __device__ __forceinline__ float occ_at(const GridC& g, const T* occ, const Cell
 // <= 0 as well and the sample cannot be the hit when tau == 0.
 __device__ __forceinline__ bool bit_of(lds_u32* bits, int b) { return (bits[b >> 5] >> (b & 31)) & 1u; }
 
-__device__ __forceinline__ bool cell_free(const GridC& g, lds_u32* bits, const CellAddr& a) {
-    if (!a.cross) return bit_of(bits, a.b0);
+// The workgroup's LDS copy of the free-space bits: w the plain bits, then,
+// when dil > 0, the dilated bits at word offset dil (w NULL: no skipping)
+struct FreeBits {
+    lds_u32* w;
+    int dil;
+};
+
+// A cell within one brick takes the brick's bit.  A cell that spans bricks
+// lies in the 2x2x2 block of bricks of its base corner: one dilated bit
+// covers it (the same LDS read for every lane); without the dilated bits
+// each spanned brick is tested.
+__device__ __forceinline__ bool cell_free(const GridC& g, const FreeBits& fb, const CellAddr& a) {
+    if (fb.dil) return bit_of(fb.w + (a.cross ? fb.dil : 0), a.b0);
+    if (!a.cross) return bit_of(fb.w, a.b0);
     const int sx = a.dx != 1 ? 1 : 0, sy = a.dy != 8 ? g.nb : 0, sz = a.dz != 64 ? g.nb * g.nb : 0;
     bool all = true;
 #pragma unroll
     for (int q = 0; q < 8; ++q)
-        all &= bit_of(bits, a.b0 + ((q & 1) ? sx : 0) + ((q & 2) ? sy : 0) + ((q & 4) ? sz : 0));
+        all &= bit_of(fb.w, a.b0 + ((q & 1) ? sx : 0) + ((q & 2) ? sy : 0) + ((q & 4) ? sz : 0));
     return all;
 }
 
 // occupancy of a marched sample, or -1 when the free-space bits prove it is
-// <= 0 (bits: the workgroup's LDS copy, non-NULL only when tau == 0)
+// <= 0 (fb: the workgroup's LDS copy, present only when tau == 0)
 template <typename T, bool Pool>
-__device__ __forceinline__ float march_occ(const GridC& g, const T* occ, lds_u32* bits, const Cell& cl) {
+__device__ __forceinline__ float march_occ(const GridC& g, const T* occ, const FreeBits& fb, const Cell& cl) {
     if (cell_inside(g, cl)) {
         CellAddr a = cell_addr(g, cl);
-        if (bits && cell_free(g, bits, a)) return -1.0f;
+        if (fb.w && cell_free(g, fb, a)) return -1.0f;
         if constexpr (Pool) {
             // brick-pool map: a single-brick cell through its slot (a brick
             // without one reads as the prior everywhere, and the trilinear
@@ -77,15 +88,19 @@ __device__ __forceinline__ float march_occ(const GridC& g, const T* occ, lds_u32
     return occ_at<T, Pool>(g, occ, cl);
 }
 
-// Free-space bits for this block, copied into LDS; NULL (no skipping) when
-// there are none or they do not fit (grids beyond n = 576).
-__device__ __forceinline__ lds_u32* block_bits(const GridC& g, const unsigned* __restrict__ gbits, unsigned* lbits) {
-    if (!gbits) return nullptr;
-    int nwords = (g.nb * g.nb * g.nb + 31) >> 5;
-    if (nwords > kMaxLdsWords) return nullptr;
-    for (int i = threadIdx.x; i < nwords; i += blockDim.x) lbits[i] = gbits[i];
+// Free-space bits for this block, copied into LDS: both bitmaps when they
+// fit, else the plain bits, else none (no skipping); as many words as
+// free_lds_words says, which is what the launch allocates.
+__device__ __forceinline__ FreeBits block_bits(const GridC& g, const unsigned* __restrict__ gbits, unsigned* lbits) {
+    FreeBits fb{nullptr, 0};
+    if (!gbits) return fb;
+    const int nwords = free_words(g.nb), nl = free_lds_words(nwords);
+    if (!nl) return fb;
+    for (int i = threadIdx.x; i < nl; i += blockDim.x) lbits[i] = gbits[i];
     __syncthreads();
-    return (lds_u32*)lbits;
+    fb.w = (lds_u32*)lbits;
+    fb.dil = nl > nwords ? nwords : 0;
+    return fb;
 }
 
 struct Shade {
@@ -276,7 +291,7 @@ __device__ __forceinline__ float quad_bcastf(float x, int src_lane_in_quad) {
 // lane of the quad returns the same value
 template <typename T, bool Pool>
 __device__ __forceinline__ int march_quad(const GridC& g, const CamC& c, const RayCoef& rc, const T* occ,
-                                          lds_u32* bits, int s) {
+                                          const FreeBits& fb, int s) {
     constexpr int G = kLanes * kPerLane;
     for (int k0 = 0; k0 < c.K; k0 += G) {
         float f[kPerLane];
@@ -284,7 +299,7 @@ __device__ __forceinline__ int march_quad(const GridC& g, const CamC& c, const R
         for (int j = 0; j < kPerLane; ++j) {
             int k = k0 + j * kLanes + s;
             Cell cl = sample_cell(rc, min(k, c.K - 1));
-            f[j] = march_occ<T, Pool>(g, occ, bits, cl);
+            f[j] = march_occ<T, Pool>(g, occ, fb, cl);
         }
         int first = 0x7fffffff;
 #pragma unroll
@@ -403,7 +418,7 @@ __device__ __forceinline__ void render_block(int blk, int frame, const GridC& g,
                                              uint8_t* __restrict__ mask, int32_t* __restrict__ hit_k) {
     __shared__ BlockPose sp;
     extern __shared__ unsigned lbits[];
-    lds_u32* bits = block_bits(g, gbits, lbits);
+    const FreeBits fb = block_bits(g, gbits, lbits);
     const BlockPose& P = block_pose(pose, &sp);
     int u, v, s;
     quad_pixel(c, blk, u, v, s);
@@ -411,7 +426,7 @@ __device__ __forceinline__ void render_block(int blk, int frame, const GridC& g,
     float dir[3];
     ray_dir32(c, P.f, u, v, dir);
     const RayCoef rc = ray_coef(g, c, P.f, dir);
-    int k = march_quad<T, Pool>(g, c, rc, map, bits, s);
+    int k = march_quad<T, Pool>(g, c, rc, map, fb, s);
     long long pix = (long long)frame * c.W * c.H + (long long)v * c.W + u;
     if (s == 0) {
         if (hit_k) hit_k[pix] = k;
@@ -531,7 +546,7 @@ __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, GridD gd, C
     __shared__ BlockPose sp;
     __shared__ double lds[kRedLds];
     extern __shared__ unsigned lbits[];
-    lds_u32* bits = block_bits(g, gbits, lbits);
+    const FreeBits fb = block_bits(g, gbits, lbits);
     const BlockPose& P = block_pose(poses + blockIdx.y, &sp);
     int u, v, s;
     quad_pixel(c, blockIdx.x, u, v, s);
@@ -544,7 +559,7 @@ __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, GridD gd, C
         float dir[3];
         ray_dir32(c, P.f, u, v, dir);
         const RayCoef rc = ray_coef(g, c, P.f, dir);
-        int k = march_quad<T, Pool>(g, c, rc, map, bits, s);
+        int k = march_quad<T, Pool>(g, c, rc, map, fb, s);
         long long pix = (long long)blockIdx.y * c.W * c.H + (long long)v * c.W + u;
         float row[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         double r = 0.0;
@@ -794,7 +809,7 @@ __global__ __launch_bounds__(256) void k_gd_grad(GridC g, CamC c, GridD gd, CamD
         (&A.key[0][0])[e] = -1;
         (&A.val[0][0])[e] = 0.0;
     }
-    lds_u32* bits = block_bits(g, gbits, lbits);   // synchronises the workgroup
+    const FreeBits fb = block_bits(g, gbits, lbits);   // synchronises the workgroup
     const BlockPose& P = block_pose(pose, &sp);
     int u, v, s;
     quad_pixel(c, blockIdx.x, u, v, s);
@@ -803,7 +818,7 @@ __global__ __launch_bounds__(256) void k_gd_grad(GridC g, CamC c, GridD gd, CamD
         float dir[3];
         ray_dir32(c, P.f, u, v, dir);
         const RayCoef rc = ray_coef(g, c, P.f, dir);
-        const int k = march_quad<float, false>(g, c, rc, map, bits, s);
+        const int k = march_quad<float, false>(g, c, rc, map, fb, s);
         const long long pix = (long long)v * c.W + u;
         const float D = obs_depth[pix];
         if (k >= 1 && depth_ok(D)) {   // the same for the four lanes of a ray
@@ -859,8 +874,7 @@ int render_blocks(const CamC& c) { return ((c.W + 7) >> 3) * ((c.H + 7) >> 3); }
 int vjp_blocks(const CamC& c) { return ((c.W + 15) >> 4) * ((c.H + 15) >> 4); }
 
 static size_t bits_lds(const GridC& g, const unsigned* bits) {
-    int nwords = (g.nb * g.nb * g.nb + 31) >> 5;
-    return (bits && nwords <= kMaxLdsWords) ? (size_t)nwords * 4 : 0;
+    return bits ? (size_t)free_lds_words(free_words(g.nb)) * 4 : 0;
 }
 
 hipError_t launch_render(const GridC& g, const CamC& c, const GridD& gd, const CamD& cd, int dtype, const void* map,
@@ -882,10 +896,10 @@ hipError_t launch_render(const GridC& g, const CamC& c, const GridD& gd, const C
     return hipGetLastError();
 }
 
-hipError_t launch_render_batch(const BatchArgs& b, int dtype, bool pool, int max_bits_words, hipStream_t st) {
-    // filters whose bits fit copy them to LDS, the others march without
-    // skipping (block_bits), so the allocation is the largest that fits
-    size_t lds = (size_t)(max_bits_words < kMaxLdsWords ? max_bits_words : kMaxLdsWords) * 4;
+hipError_t launch_render_batch(const BatchArgs& b, int dtype, bool pool, int max_lds_words, hipStream_t st) {
+    // every filter copies free_lds_words of its bits to LDS (block_bits):
+    // the allocation is the largest of these over the batch
+    size_t lds = (size_t)max_lds_words * 4;
     if (dtype == PRISM_BF16 && pool)
         k_render_batch<uint16_t, true><<<b.start[b.n], 256, lds, st>>>(b);
     else if (dtype == PRISM_BF16)

@@ -49,8 +49,8 @@ def test_map_bytes_and_validation(P):
     nb3 = (64 // 8) ** 3
     r256 = lambda x: (x + 255) // 256 * 256
     nseg = (nb3 + 255) // 256
-    # summary, free-space bits, counts, brick list, segment lengths, pose scratch
-    aux = r256(4 * nb3) + r256(4 * ((nb3 + 31) // 32)) + r256(4 * 2048) + r256(4 * nseg * 256) + r256(4 * nseg) + 256
+    # summary, free-space bits (plain and dilated), counts, brick list, segment lengths, pose scratch
+    aux = r256(4 * nb3) + r256(8 * ((nb3 + 31) // 32)) + r256(4 * 2048) + r256(4 * nseg * 256) + r256(4 * nseg) + 256
     assert b.value == 8 * 64 ** 3 * 4 + aux
     g = P.Grid.make(64, 0.04, dtype=P.PRISM_BF16)
     assert L.prism_map_bytes(ctypes.byref(g), ctypes.byref(b)) == 0
