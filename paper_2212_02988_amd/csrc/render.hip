@@ -88,21 +88,6 @@ __device__ __forceinline__ float march_occ(const GridC& g, const T* occ, const F
     return occ_at<T, Pool>(g, occ, cl);
 }
 
-// Free-space bits for this block, copied into LDS: both bitmaps when they
-// fit, else the plain bits, else none (no skipping); as many words as
-// free_lds_words says, which is what the launch allocates.
-__device__ __forceinline__ FreeBits block_bits(const GridC& g, const unsigned* __restrict__ gbits, unsigned* lbits) {
-    FreeBits fb{nullptr, 0};
-    if (!gbits) return fb;
-    const int nwords = free_words(g.nb), nl = free_lds_words(nwords);
-    if (!nl) return fb;
-    for (int i = threadIdx.x; i < nl; i += blockDim.x) lbits[i] = gbits[i];
-    __syncthreads();
-    fb.w = (lds_u32*)lbits;
-    fb.dil = nl > nwords ? nwords : 0;
-    return fb;
-}
-
 struct Shade {
     float alpha, d0, d1;       // single-precision copies for the Jacobian
     float c0[3], c1[3];
@@ -252,6 +237,30 @@ struct BlockPose {
     Pose64 d;
     Pose32 f;
 };
+
+// The prologue of a marching workgroup, one barrier: thread 0's pose loads
+// are issued first and are in flight while every thread copies the
+// free-space bits to LDS — both bitmaps when they fit, else the plain bits,
+// else none (no skipping): free_lds_words words, which the launch allocates.
+__device__ __forceinline__ FreeBits block_setup(const GridC& g, const unsigned* __restrict__ gbits, unsigned* lbits,
+                                                const prism_pose* pose, BlockPose* sp) {
+    prism_pose raw;
+    if (threadIdx.x == 0) raw = *pose;
+    FreeBits fb{nullptr, 0};
+    const int nwords = free_words(g.nb), nl = gbits ? free_lds_words(nwords) : 0;
+    for (int i = threadIdx.x; i < nl; i += blockDim.x) lbits[i] = gbits[i];
+    if (threadIdx.x == 0) {
+        quat_to_rot64(raw, sp->d.R);
+        for (int i = 0; i < 3; ++i) sp->d.t[i] = raw.t[i];
+        sp->f = to32(sp->d);
+    }
+    __syncthreads();
+    if (nl) {
+        fb.w = (lds_u32*)lbits;
+        fb.dil = nl > nwords ? nwords : 0;
+    }
+    return fb;
+}
 
 __device__ __forceinline__ const BlockPose& block_pose(const prism_pose* pose, BlockPose* sp) {
     if (threadIdx.x == 0) {
@@ -418,8 +427,8 @@ __device__ __forceinline__ void render_block(int blk, int frame, const GridC& g,
                                              uint8_t* __restrict__ mask, int32_t* __restrict__ hit_k) {
     __shared__ BlockPose sp;
     extern __shared__ unsigned lbits[];
-    const FreeBits fb = block_bits(g, gbits, lbits);
-    const BlockPose& P = block_pose(pose, &sp);
+    const FreeBits fb = block_setup(g, gbits, lbits, pose, &sp);
+    const BlockPose& P = sp;
     int u, v, s;
     quad_pixel(c, blk, u, v, s);
     if (u >= c.W || v >= c.H) return;   // whole quads leave together
@@ -546,8 +555,8 @@ __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, GridD gd, C
     __shared__ BlockPose sp;
     __shared__ double lds[kRedLds];
     extern __shared__ unsigned lbits[];
-    const FreeBits fb = block_bits(g, gbits, lbits);
-    const BlockPose& P = block_pose(poses + blockIdx.y, &sp);
+    const FreeBits fb = block_setup(g, gbits, lbits, poses + blockIdx.y, &sp);
+    const BlockPose& P = sp;
     int u, v, s;
     quad_pixel(c, blockIdx.x, u, v, s);
     // this lane's row in single precision, widened once for the
@@ -809,8 +818,8 @@ __global__ __launch_bounds__(256) void k_gd_grad(GridC g, CamC c, GridD gd, CamD
         (&A.key[0][0])[e] = -1;
         (&A.val[0][0])[e] = 0.0;
     }
-    const FreeBits fb = block_bits(g, gbits, lbits);   // synchronises the workgroup
-    const BlockPose& P = block_pose(pose, &sp);
+    const FreeBits fb = block_setup(g, gbits, lbits, pose, &sp);   // synchronises the workgroup
+    const BlockPose& P = sp;
     int u, v, s;
     quad_pixel(c, blockIdx.x, u, v, s);
     double cost = 0.0;
@@ -897,7 +906,7 @@ hipError_t launch_render(const GridC& g, const CamC& c, const GridD& gd, const C
 }
 
 hipError_t launch_render_batch(const BatchArgs& b, int dtype, bool pool, int max_lds_words, hipStream_t st) {
-    // every filter copies free_lds_words of its bits to LDS (block_bits):
+    // every filter copies free_lds_words of its bits to LDS (block_setup):
     // the allocation is the largest of these over the batch
     size_t lds = (size_t)max_lds_words * 4;
     if (dtype == PRISM_BF16 && pool)
