@@ -412,6 +412,40 @@ __device__ inline void block_reduce29(double acc[PRISM_NEQ], double* lds, double
     }
 }
 
+// The same for single-precision per-lane sums (a pixel's or ray's few rows):
+// the five halving steps inside each 32-lane half run in single precision
+// (one 4-byte exchange per value instead of two), each lane widens its one
+// remaining value, and the step across halves and the sum over waves are in
+// double precision.  A single-precision sum spans at most 32 lanes (relative
+// error below 32 ulp of the sum of magnitudes); the order is fixed, so
+// results are deterministic.
+__device__ inline void block_reduce29f(const float acc[PRISM_NEQ], double* lds, double* out) {
+    float v[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) v[q] = q < PRISM_NEQ ? acc[q] : 0.0f;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int half = 16; half >= 1; half >>= 1) {
+        bool hi = (lane & half) != 0;
+#pragma unroll
+        for (int j = 0; j < half; ++j) {
+            float send = hi ? v[j] : v[j + half];
+            float keep = hi ? v[j + half] : v[j];
+            v[j] = keep + __shfl_xor(send, half, 64);
+        }
+    }
+    const double h = (double)v[0];
+    double w = h + __shfl_xor(h, 32, 64);   // value (lane & 31), whole wave
+    const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (lane < 32) lds[lane * 16 + wv] = w;
+    __syncthreads();
+    if (threadIdx.x < PRISM_NEQ) {
+        double s = 0.0;
+        for (int k = 0; k < nw; ++k) s += lds[threadIdx.x * 16 + k];
+        out[threadIdx.x] = s;
+    }
+}
+
 // one residual row (Jacobian row j, residual r, weight w) into the
 // 29-double normal equations, products formed in double precision
 __device__ __forceinline__ void neq_add(double acc[PRISM_NEQ], const float j[6], double r, double w) {

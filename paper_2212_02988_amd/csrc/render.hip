@@ -559,8 +559,8 @@ __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, GridD gd, C
     const BlockPose& P = sp;
     int u, v, s;
     quad_pixel(c, blockIdx.x, u, v, s);
-    // this lane's row in single precision, widened once for the
-    // double-precision reduction over rays
+    // this lane's row in single precision, reduced over the workgroup by
+    // block_reduce29f (single precision within 32 lanes, then double)
     float pacc[PRISM_NEQ];
 #pragma unroll
     for (int q = 0; q < PRISM_NEQ; ++q) pacc[q] = 0.0f;
@@ -614,10 +614,7 @@ __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, GridD gd, C
         }
         if (resid) resid[4 * pix + s] = (float)r;
     }
-    double acc[PRISM_NEQ];
-#pragma unroll
-    for (int q = 0; q < PRISM_NEQ; ++q) acc[q] = (double)pacc[q];
-    block_reduce29(acc, lds, partials + ((long long)blockIdx.y * gridDim.x + blockIdx.x) * PRISM_NEQ);
+    block_reduce29f(pacc, lds, partials + ((long long)blockIdx.y * gridDim.x + blockIdx.x) * PRISM_NEQ);
 }
 
 // ---------------------------------------------------------------------------

@@ -173,8 +173,8 @@ __device__ __forceinline__ void track_p2_block(int blk, const CamC& c, const Cam
     __syncthreads();
     const Rel32& rel = srel;
     // this pixel's rows summed in single precision (at most 4 rows of
-    // single-precision Jacobians), widened once for the double-precision
-    // reduction over pixels
+    // single-precision Jacobians), reduced over the workgroup by
+    // block_reduce29f (single precision within 32 lanes, then double)
     float pacc[PRISM_NEQ];
 #pragma unroll
     for (int q = 0; q < PRISM_NEQ; ++q) pacc[q] = 0.0f;
@@ -201,10 +201,7 @@ __device__ __forceinline__ void track_p2_block(int blk, const CamC& c, const Cam
             reinterpret_cast<float4*>(resid)[p] = make_float4((float)r[0], (float)r[1], (float)r[2], (float)r[3]);
         if (rowmask) rowmask[p] = (uint8_t)rm;
     }
-    double acc[PRISM_NEQ];
-#pragma unroll
-    for (int q = 0; q < PRISM_NEQ; ++q) acc[q] = (double)pacc[q];
-    block_reduce29(acc, lds, partials + (long long)blk * PRISM_NEQ);
+    block_reduce29f(pacc, lds, partials + (long long)blk * PRISM_NEQ);
 }
 
 __global__ __launch_bounds__(256) void k_track_p2(CamC c, CamD cd, const prism_pose* __restrict__ pose,
