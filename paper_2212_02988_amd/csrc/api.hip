@@ -279,6 +279,7 @@ struct prism_filter {
     float *a_depth, *a_rgb, *a_normals;
     uint8_t *a_mask, *a_nmask;
     double* partials;
+    Rel32* rel;   // relative pose of the iterate to the anchor (written by predict / GN)
     void* map;
     int64_t steps;
     prism_filter_state host_state;   // source of prism_filter_reset uploads
@@ -320,7 +321,7 @@ hipError_t release_graph(prism_filter::StepGraph& G) {
 }
 
 struct StateLayout {
-    size_t state, a_depth, a_rgb, a_normals, a_mask, a_nmask, partials, desc, total;
+    size_t state, a_depth, a_rgb, a_normals, a_mask, a_nmask, partials, rel, desc, total;
 };
 
 StateLayout state_layout(const prism_camera* c) {
@@ -342,6 +343,8 @@ StateLayout state_layout(const prism_camera* c) {
     off = round_up(off + npix, 256);
     L.partials = off;
     off = round_up(off + reduce_bytes(cc, 1), 256);
+    L.rel = off;
+    off = round_up(off + sizeof(Rel32), 256);
     L.desc = off;
     off = round_up(off + sizeof(AgentDesc), 256);
     L.total = off;
@@ -373,8 +376,11 @@ prism_status check_frame(const prism_frame* fr, bool need_u) {
     return PRISM_OK;
 }
 
-// objective at S->iter into the handle's partials; returns the block count
-prism_status eval_objective(prism_filter* f, const prism_frame* fr, int* nb, hipStream_t st) {
+// objective at S->iter into the handle's partials; returns the block count.
+// rel_current: the handle's relative pose was formed from the current
+// iterate (after predict or a Gauss-Newton step), so tracking reads it
+prism_status eval_objective(prism_filter* f, const prism_frame* fr, int* nb, hipStream_t st,
+                            bool rel_current = true) {
     if (f->cfg.objective == PRISM_OBJ_P1) {
         HIP_TRY(launch_render_jac(f->g, f->c, f->gd, f->cd, f->cfg.grid.dtype, f->map,
                                   skip_table(&f->cfg.grid, &f->cfg.cam, f->map), &f->S->iter, 1, fr->depth,
@@ -384,19 +390,19 @@ prism_status eval_objective(prism_filter* f, const prism_frame* fr, int* nb, hip
     } else {
         HIP_TRY(launch_track_p2(f->c, f->cd, &f->S->iter, &f->S->anchor, fr->depth, fr->rgb, f->a_depth, f->a_rgb,
                                 f->a_mask, f->a_normals, f->a_nmask, f->w, nullptr, nullptr, nullptr, f->partials,
-                                st));
+                                rel_current ? f->rel : nullptr, st));
         *nb = track_blocks(f->c);
     }
     return PRISM_OK;
 }
 
 prism_status pose_update_impl(prism_filter* f, const prism_frame* fr, hipStream_t st) {
-    HIP_TRY(launch_predict(f->S, fr->u, f->tc, st));
+    HIP_TRY(launch_predict(f->S, fr->u, f->tc, f->rel, st));
     int nb = 0;
     prism_status s;
     for (int i = 0; i < f->cfg.n_gn; ++i) {
         if ((s = eval_objective(f, fr, &nb, st))) return s;
-        HIP_TRY(launch_gn_step(f->S, f->partials, nb, st));
+        HIP_TRY(launch_gn_step(f->S, f->partials, nb, f->rel, st));
     }
     if ((s = eval_objective(f, fr, &nb, st))) return s;
     HIP_TRY(launch_laplace_combine(f->S, f->partials, nb, f->cfg.ema, st));
@@ -419,7 +425,7 @@ prism_status check_adam(const prism_filter* f, const prism_adam_params* p, const
 
 prism_status pose_update_adam_impl(prism_filter* f, const prism_frame* fr, const prism_adam_params* p,
                                    const int32_t* pixels, hipStream_t st) {
-    HIP_TRY(launch_predict(f->S, fr->u, f->tc, st));
+    HIP_TRY(launch_predict(f->S, fr->u, f->tc, f->rel, st));
     AdamC ad;
     for (int i = 0; i < 3; ++i) {
         ad.lr[i] = p->lr_t;
@@ -434,7 +440,8 @@ prism_status pose_update_adam_impl(prism_filter* f, const prism_frame* fr, const
                              f->a_nmask, f->w, pixels, ad, st));
     int nb = 0;
     prism_status s;
-    if ((s = eval_objective(f, fr, &nb, st))) return s;
+    // the optimiser moved the iterate: the objective forms its own relative pose
+    if ((s = eval_objective(f, fr, &nb, st, false))) return s;
     HIP_TRY(launch_laplace_combine(f->S, f->partials, nb, f->cfg.ema, st));
     return PRISM_OK;
 }
@@ -631,7 +638,7 @@ prism_status prism_track_p2(const prism_camera* cam, const prism_pose* pose, con
             "workspace too small: need %zu bytes", reduce_bytes(c, 1));
     double* part = (double*)workspace;
     HIP_TRY(launch_track_p2(c, cam_d(cam), pose, pose_prev, obs_depth, obs_rgb, anchor_depth, anchor_rgb, anchor_mask,
-                            anchor_normals, anchor_nmask, weights_c(w), J, resid, rowmask, part, stream));
+                            anchor_normals, anchor_nmask, weights_c(w), J, resid, rowmask, part, nullptr, stream));
     HIP_TRY(launch_finalize(part, track_blocks(c), 1, PRISM_NEQ, neq, PRISM_NEQ, stream));
     return PRISM_OK;
 }
@@ -794,6 +801,7 @@ prism_status prism_filter_create(const prism_filter_cfg* cfg, void* state_mem, v
     f->a_mask = (uint8_t*)(base + L.a_mask);
     f->a_nmask = (uint8_t*)(base + L.a_nmask);
     f->partials = (double*)(base + L.partials);
+    f->rel = (Rel32*)(base + L.rel);
     f->map = map_mem;
     f->steps = 0;
     // batched-step descriptor (slots are filled in by prism_filter_set_slots)
@@ -822,6 +830,7 @@ prism_status prism_filter_create(const prism_filter_cfg* cfg, void* state_mem, v
     D.a_mask = f->a_mask;
     D.a_nmask = f->a_nmask;
     D.partials = f->partials;
+    D.rel = f->rel;
     f->desc_dev = (AgentDesc*)(base + L.desc);
     f->desc_dirty = true;
     *out = f;

@@ -133,6 +133,27 @@ __device__ inline Pose64 load_pose64(const prism_pose* pp) {
     return o;
 }
 
+// The current camera relative to the anchor camera, as the tracking objective
+// uses it: R, t (current -> anchor) in single precision for the association
+// recipe, both poses in double precision for the values.  A filter keeps its
+// own copy, formed whenever its iterate changes (predict, Gauss-Newton step).
+struct Rel32 {
+    float R[3][3], t[3];   // current camera -> anchor camera (association recipe)
+    Pose64 cur, prev;      // both poses in double precision (values)
+};
+
+__device__ __forceinline__ void rel_of(const prism_pose* pose, const prism_pose* pose_prev, Rel32& rel) {
+    Pose64 P = load_pose64(pose), Q = load_pose64(pose_prev);
+    double d[3] = {P.t[0] - Q.t[0], P.t[1] - Q.t[1], P.t[2] - Q.t[2]};
+    for (int a = 0; a < 3; ++a) {
+        for (int b = 0; b < 3; ++b)
+            rel.R[a][b] = (float)((Q.R[0][a] * P.R[0][b] + Q.R[1][a] * P.R[1][b]) + Q.R[2][a] * P.R[2][b]);
+        rel.t[a] = (float)((Q.R[0][a] * d[0] + Q.R[1][a] * d[1]) + Q.R[2][a] * d[2]);
+    }
+    rel.cur = P;
+    rel.prev = Q;
+}
+
 __device__ __forceinline__ void pixel_dir64(const CamD& c, int u, int v, double r[3]) {
     r[0] = (((double)u + 0.5) - c.cx) * c.ifx;
     r[1] = (((double)v + 0.5) - c.cy) * c.ify;

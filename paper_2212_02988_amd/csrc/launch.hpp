@@ -41,6 +41,7 @@ struct AgentDesc {
     float *a_depth, *a_rgb, *a_normals;
     uint8_t *a_mask, *a_nmask;
     double* partials;
+    Rel32* rel;   // relative pose of the current iterate to the anchor (predict / GN write it)
     prism_frame slots[4];
 };
 
@@ -113,7 +114,7 @@ hipError_t launch_track_p2(const CamC& c, const CamD& cd, const prism_pose* pose
                            const float* obs_depth, const float* obs_rgb, const float* a_depth,
                            const float* a_rgb, const uint8_t* a_mask, const float* a_normals,
                            const uint8_t* a_nmask, const WeightsC& w, float* J, float* resid,
-                           uint8_t* rowmask, double* partials, hipStream_t st);
+                           uint8_t* rowmask, double* partials, const Rel32* rel, hipStream_t st);
 hipError_t launch_finalize(const double* partials, int nblocks, int n_frames, int nvals, double* out,
                            int stride, hipStream_t st);
 
@@ -168,8 +169,8 @@ hipError_t launch_pose_adam(prism_filter_state* S, const CamC& c, const CamD& cd
 hipError_t launch_rollout(const prism_filter_state* S, const double* u, int k, int n_samples, const double* noise,
                           const TransC& tc, prism_pose* poses, double* mean, double* cov, int32_t* flags,
                           hipStream_t st);
-hipError_t launch_predict(prism_filter_state* S, const double* u, const TransC& tc, hipStream_t st);
-hipError_t launch_gn_step(prism_filter_state* S, const double* partials, int nblocks, hipStream_t st);
+hipError_t launch_predict(prism_filter_state* S, const double* u, const TransC& tc, Rel32* rel, hipStream_t st);
+hipError_t launch_gn_step(prism_filter_state* S, const double* partials, int nblocks, Rel32* rel, hipStream_t st);
 hipError_t launch_laplace_combine(prism_filter_state* S, const double* partials, int nblocks, double ema,
                                   hipStream_t st);
 hipError_t launch_first_frame(prism_filter_state* S, hipStream_t st);

@@ -280,12 +280,6 @@ __device__ __forceinline__ int quad_min(int x) {
     return x;
 }
 
-__device__ __forceinline__ float quad_sum(float x) {
-    x += __shfl_xor(x, 1, 64);
-    x += __shfl_xor(x, 2, 64);
-    return x;
-}
-
 __device__ __forceinline__ double quad_bcast(double x, int src_lane_in_quad) {
     int base = (threadIdx.x & 63) & ~3;
     return __shfl(x, base + src_lane_in_quad, 64);

@@ -230,7 +230,7 @@ __device__ inline void transition_cov(const double* E, const double* Jl, const T
 }
 
 __device__ __forceinline__ void predict_block(prism_filter_state* __restrict__ Sg, const double* __restrict__ u,
-                                              const TransC& tc) {
+                                              const TransC& tc, Rel32* __restrict__ rel) {
     __shared__ double M[144], G[144], T1[144], T2[144], P[144], Spp[36], L[36], Sinv[36];
     __shared__ double vnew[6], E[9], Jl[9];
     __shared__ int ok;
@@ -244,6 +244,7 @@ __device__ __forceinline__ void predict_block(prism_filter_state* __restrict__ S
         transition_mean_t0(S->pose, S->v, S->w, u, tc, vnew, E, Jl, pr);
         S->prior = pr;
         S->iter = pr;
+        if (rel) rel_of(&S->iter, &S->anchor, *rel);
         for (int i = 0; i < 6; ++i) S->vel_prior[i] = vnew[i];
     }
     for (int e = threadIdx.x; e < 144; e += blockDim.x) P[e] = S->P[e];
@@ -294,8 +295,8 @@ __device__ __forceinline__ void predict_block(prism_filter_state* __restrict__ S
 }
 
 __global__ __launch_bounds__(256) void k_predict(prism_filter_state* __restrict__ Sg,
-                                                 const double* __restrict__ u, TransC tc) {
-    predict_block(Sg, u, tc);
+                                                 const double* __restrict__ u, TransC tc, Rel32* __restrict__ rel) {
+    predict_block(Sg, u, tc, rel);
 }
 
 // ---------------------------------------------------------------------------
@@ -328,7 +329,8 @@ __device__ inline void gn_step_body(prism_filter_state* S, const double* neq) {
 }
 
 __device__ __forceinline__ void gn_step_block(prism_filter_state* __restrict__ Sg,
-                                              const double* __restrict__ partials, int nblocks) {
+                                              const double* __restrict__ partials, int nblocks,
+                                              Rel32* __restrict__ rel) {
     __shared__ double red[kRedLds], neq[PRISM_NEQ];
     __shared__ prism_filter_state Ls;
     state_in(Sg, &Ls);
@@ -338,12 +340,14 @@ __device__ __forceinline__ void gn_step_block(prism_filter_state* __restrict__ S
     if (threadIdx.x == 0) {
         Sg->iter = Ls.iter;
         Sg->flags = Ls.flags;
+        if (rel) rel_of(&Ls.iter, &Ls.anchor, *rel);
     }
 }
 
 __global__ __launch_bounds__(512) void k_gn_step(prism_filter_state* __restrict__ Sg,
-                                                 const double* __restrict__ partials, int nblocks) {
-    gn_step_block(Sg, partials, nblocks);
+                                                 const double* __restrict__ partials, int nblocks,
+                                                 Rel32* __restrict__ rel) {
+    gn_step_block(Sg, partials, nblocks, rel);
 }
 
 // ---------------------------------------------------------------------------
@@ -457,12 +461,12 @@ __global__ void k_first_frame(prism_filter_state* __restrict__ S) { first_frame_
 // batched: one workgroup per filter
 __global__ __launch_bounds__(256) void k_predict_batch(BatchArgs b) {
     const AgentDesc& D = *b.d[blockIdx.x];
-    predict_block(D.S, (const double*)D.slots[b.slot[blockIdx.x]].u, D.tc);
+    predict_block(D.S, (const double*)D.slots[b.slot[blockIdx.x]].u, D.tc, D.rel);
 }
 
 __global__ __launch_bounds__(512) void k_gn_step_batch(BatchArgs b) {
     const AgentDesc& D = *b.d[blockIdx.x];
-    gn_step_block(D.S, D.partials, D.track_blocks);
+    gn_step_block(D.S, D.partials, D.track_blocks, D.rel);
 }
 
 __global__ __launch_bounds__(512) void k_laplace_combine_batch(BatchArgs b) {
@@ -601,13 +605,14 @@ __global__ __launch_bounds__(512) void k_finalize(const double* __restrict__ par
     if ((int)threadIdx.x < nvals) out[(long long)blockIdx.x * stride + threadIdx.x] = neq[threadIdx.x];
 }
 
-hipError_t launch_predict(prism_filter_state* S, const double* u, const TransC& tc, hipStream_t st) {
-    k_predict<<<1, 256, 0, st>>>(S, u, tc);
+hipError_t launch_predict(prism_filter_state* S, const double* u, const TransC& tc, Rel32* rel, hipStream_t st) {
+    k_predict<<<1, 256, 0, st>>>(S, u, tc, rel);
     return hipGetLastError();
 }
 
-hipError_t launch_gn_step(prism_filter_state* S, const double* partials, int nblocks, hipStream_t st) {
-    k_gn_step<<<1, 512, 0, st>>>(S, partials, nblocks);
+hipError_t launch_gn_step(prism_filter_state* S, const double* partials, int nblocks, Rel32* rel,
+                          hipStream_t st) {
+    k_gn_step<<<1, 512, 0, st>>>(S, partials, nblocks, rel);
     return hipGetLastError();
 }
 

@@ -12,23 +12,6 @@
 
 namespace prism {
 
-struct Rel32 {
-    float R[3][3], t[3];   // current camera -> anchor camera (association recipe)
-    Pose64 cur, prev;      // both poses in double precision (values)
-};
-
-__device__ __forceinline__ void rel_of(const prism_pose* pose, const prism_pose* pose_prev, Rel32& rel) {
-    Pose64 P = load_pose64(pose), Q = load_pose64(pose_prev);
-    double d[3] = {P.t[0] - Q.t[0], P.t[1] - Q.t[1], P.t[2] - Q.t[2]};
-    for (int a = 0; a < 3; ++a) {
-        for (int b = 0; b < 3; ++b)
-            rel.R[a][b] = (float)((Q.R[0][a] * P.R[0][b] + Q.R[1][a] * P.R[1][b]) + Q.R[2][a] * P.R[2][b]);
-        rel.t[a] = (float)((Q.R[0][a] * d[0] + Q.R[1][a] * d[1]) + Q.R[2][a] * d[2]);
-    }
-    rel.cur = P;
-    rel.prev = Q;
-}
-
 // The rows of observed pixel p (row-major index): geometric row 0
 // (point-to-plane against the nearest anchor pixel) and colour rows 1-3
 // (bilinear anchor colour minus the observation), residuals in double
@@ -166,10 +149,20 @@ __device__ __forceinline__ void track_p2_block(int blk, const CamC& c, const Cam
                                                const float* __restrict__ a_normals,
                                                const uint8_t* __restrict__ a_nmask, const WeightsC& wt,
                                                float* __restrict__ Jout, float* __restrict__ resid,
-                                               uint8_t* __restrict__ rowmask, double* __restrict__ partials) {
+                                               uint8_t* __restrict__ rowmask, double* __restrict__ partials,
+                                               const Rel32* __restrict__ grel) {
     __shared__ Rel32 srel;
     __shared__ double lds[kRedLds];
-    if (threadIdx.x == 0) rel_of(pose, pose_prev, srel);
+    // the filter's relative pose when it keeps one (copied word by word),
+    // else formed here by thread 0
+    constexpr int kRelWords = (int)(sizeof(Rel32) / 4);
+    static_assert(sizeof(Rel32) % 4 == 0 && kRelWords <= 256, "Rel32 is copied by one word per thread");
+    if (grel) {
+        if (threadIdx.x < kRelWords)
+            reinterpret_cast<unsigned*>(&srel)[threadIdx.x] = reinterpret_cast<const unsigned*>(grel)[threadIdx.x];
+    } else if (threadIdx.x == 0) {
+        rel_of(pose, pose_prev, srel);
+    }
     __syncthreads();
     const Rel32& rel = srel;
     // this pixel's rows summed in single precision (at most 4 rows of
@@ -215,9 +208,9 @@ __global__ __launch_bounds__(256) void k_track_p2(CamC c, CamD cd, const prism_p
                                                   const uint8_t* __restrict__ a_nmask, WeightsC wt,
                                                   float* __restrict__ Jout, float* __restrict__ resid,
                                                   uint8_t* __restrict__ rowmask,
-                                                  double* __restrict__ partials) {
+                                                  double* __restrict__ partials, const Rel32* __restrict__ rel) {
     track_p2_block(blockIdx.x, c, cd, pose, pose_prev, obs_depth, obs_rgb, a_depth, a_rgb, a_mask, a_normals, a_nmask,
-                   wt, Jout, resid, rowmask, partials);
+                   wt, Jout, resid, rowmask, partials, rel);
 }
 
 // batched: every filter tracks its slot's frame from its current iterate
@@ -228,7 +221,7 @@ __global__ __launch_bounds__(256) void k_track_p2_batch(BatchArgs b) {
     const prism_frame& fr = D.slots[b.slot[a]];
     track_p2_block(blockIdx.x - b.start[a], D.c, D.cd, &D.S->iter, &D.S->anchor, (const float*)fr.depth,
                    (const float*)fr.rgb, D.a_depth, D.a_rgb, D.a_mask, D.a_normals, D.a_nmask, D.w, nullptr, nullptr,
-                   nullptr, D.partials);
+                   nullptr, D.partials, D.rel);
 }
 
 // ---------------------------------------------------------------------------
@@ -444,9 +437,9 @@ hipError_t launch_track_p2(const CamC& c, const CamD& cd, const prism_pose* pose
                            const float* obs_depth, const float* obs_rgb, const float* a_depth,
                            const float* a_rgb, const uint8_t* a_mask, const float* a_normals,
                            const uint8_t* a_nmask, const WeightsC& w, float* J, float* resid,
-                           uint8_t* rowmask, double* partials, hipStream_t st) {
+                           uint8_t* rowmask, double* partials, const Rel32* rel, hipStream_t st) {
     k_track_p2<<<track_blocks(c), 256, 0, st>>>(c, cd, pose, pose_prev, obs_depth, obs_rgb, a_depth, a_rgb,
-                                                a_mask, a_normals, a_nmask, w, J, resid, rowmask, partials);
+                                                a_mask, a_normals, a_nmask, w, J, resid, rowmask, partials, rel);
     return hipGetLastError();
 }
 
