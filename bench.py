@@ -718,7 +718,7 @@ def main():
         "roofline": roofline_obj(dominant, dom_roof, breakdown),
         "kernel_breakdown": breakdown,
         "roofline_map_update_single": {
-            "kernel": "prism_map_update call (cull + update + count), 256^3 FP32, 320x240, 4 rotating frames",
+            "kernel": "prism_map_update call (cull + update + dilated bits and count), 256^3 FP32, 320x240, 4 rotating frames",
             "bound": "hbm", "achieved": r(single["mu_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": r(single["mu_gbs"] / HBM_PEAK_GBS, 4), "algorithmic_bytes": int(single["mu_bytes"]),
             "updated_voxels": int(single["n_upd"]), "avg_call_us": r(single["us_mu"], 2)},

@@ -222,6 +222,16 @@ __global__ __launch_bounds__(256) void k_dilate_bits(int nb, unsigned* __restric
     dilate_block(blockIdx.x, nb, bits);
 }
 
+// the same, with workgroup 0 also totalling the update's per-workgroup
+// voxel counts (the whole workgroup, before any thread leaves)
+__global__ __launch_bounds__(256) void k_dilate_bits_sum(int nb, unsigned* __restrict__ bits,
+                                                         const int* __restrict__ counts, int ngroups,
+                                                         int64_t* __restrict__ n_updated) {
+    __shared__ long long part[4];
+    if (blockIdx.x == 0) sum_counts_block(counts, ngroups, n_updated, part);
+    dilate_block(blockIdx.x, nb, bits);
+}
+
 // Conservative brick cull: true if no voxel centre of the brick can pass the
 // per-voxel test.  Each test is a convex region (behind the camera, or beyond
 // one side plane of the frustum) checked on the 8 corners of the brick's
@@ -652,13 +662,6 @@ hipError_t launch_gd_cost(const double* pd, int nd, const double* pp, int np, do
     return hipGetLastError();
 }
 
-// n_updated = sum of the per-workgroup counts of the last update
-__global__ __launch_bounds__(256) void k_sum_counts(const int* __restrict__ counts, int ngroups,
-                                                    int64_t* __restrict__ n_updated) {
-    __shared__ long long part[4];
-    sum_counts_block(counts, ngroups, n_updated, part);
-}
-
 static unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
 
 hipError_t launch_dilate(const GridC& g, const MapAux& aux, hipStream_t st) {
@@ -777,11 +780,14 @@ hipError_t launch_map_update(const GridC& g, const CamC& c, const GridD& gd, int
         k_map_update<float, false><<<ng, 256, lds, st>>>(g, c, gd, (float*)map, depth, rgb, mp, aux, nseg);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if ((e = launch_dilate(g, aux, st)) != hipSuccess) return e;
-    if (t_end && (e = hipEventRecord(t_end, st)) != hipSuccess) return e;
-    if (!n_updated) return hipSuccess;
-    k_sum_counts<<<1, 256, 0, st>>>(aux.counts, ng, n_updated);
-    return hipGetLastError();
+    if (!n_updated) {
+        if ((e = launch_dilate(g, aux, st)) != hipSuccess) return e;
+        return t_end ? hipEventRecord(t_end, st) : hipSuccess;
+    }
+    k_dilate_bits_sum<<<(unsigned)((free_words(g.nb) + 255) / 256), 256, 0, st>>>(g.nb, aux.bits, aux.counts, ng,
+                                                                                 n_updated);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return t_end ? hipEventRecord(t_end, st) : hipSuccess;
 }
 
 int map_update_groups(const GridC& g) { return update_grid(g); }
