@@ -490,30 +490,41 @@ __device__ __forceinline__ void normals_block(int blk, const CamC& c, int n_fram
     int u = p % c.W, v = p / c.W;
     const float* D = depth + f * npix;
     const uint8_t* M = mask + f * npix;
+    // the five masks and depths in one round of loads (a border pixel reads
+    // itself in place of its missing neighbours; it is never valid), then
+    // one store of the result
+    const bool inner = u > 0 && v > 0 && u < c.W - 1 && v < c.H - 1;
+    const int pl = inner ? p - 1 : p, pr = inner ? p + 1 : p;
+    const int pu = inner ? p - c.W : p, pd = inner ? p + c.W : p;
+    const bool m = (M[p] & M[pl] & M[pr] & M[pu] & M[pd]) != 0;   // masks are 0 / 1
+    const float d = D[p], dl = D[pl], dr = D[pr], du = D[pu], dd = D[pd];
+    float o[3] = {0.0f, 0.0f, 0.0f};
+    uint8_t ok = 0;
+    if (inner && m &&
+        !(fabsf(dl - d) > disc || fabsf(dr - d) > disc || fabsf(du - d) > disc || fabsf(dd - d) > disc)) {
+        float xl = ((float)(u - 1) + 0.5f - c.cx) * c.ifx, xr = ((float)(u + 1) + 0.5f - c.cx) * c.ifx;
+        float x0 = ((float)u + 0.5f - c.cx) * c.ifx;
+        float yu = ((float)(v - 1) + 0.5f - c.cy) * c.ify, yd = ((float)(v + 1) + 0.5f - c.cy) * c.ify;
+        float y0 = ((float)v + 0.5f - c.cy) * c.ify;
+        float a[3] = {dr * xr - dl * xl, dr * y0 - dl * y0, dr - dl};
+        float b[3] = {dd * x0 - du * x0, dd * yd - du * yu, dd - du};
+        float n[3];
+        cross3(a, b, n);
+        float len = sqrtf(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        if (len > 0.0f) {
+            float sgn = (n[0] * x0 + n[1] * y0 + n[2]) * d < 0.0f ? 1.0f : -1.0f;
+            float il = sgn / len;
+            o[0] = n[0] * il;
+            o[1] = n[1] * il;
+            o[2] = n[2] * il;
+            ok = 1;
+        }
+    }
     float* N = normals + 3 * gid;
-    N[0] = N[1] = N[2] = 0.0f;
-    nmask[gid] = 0;
-    if (u == 0 || v == 0 || u == c.W - 1 || v == c.H - 1 || !M[p]) return;
-    if (!M[p - 1] || !M[p + 1] || !M[p - c.W] || !M[p + c.W]) return;
-    float d = D[p], dl = D[p - 1], dr = D[p + 1], du = D[p - c.W], dd = D[p + c.W];
-    if (fabsf(dl - d) > disc || fabsf(dr - d) > disc || fabsf(du - d) > disc || fabsf(dd - d) > disc)
-        return;
-    float xl = ((float)(u - 1) + 0.5f - c.cx) * c.ifx, xr = ((float)(u + 1) + 0.5f - c.cx) * c.ifx;
-    float x0 = ((float)u + 0.5f - c.cx) * c.ifx;
-    float yu = ((float)(v - 1) + 0.5f - c.cy) * c.ify, yd = ((float)(v + 1) + 0.5f - c.cy) * c.ify;
-    float y0 = ((float)v + 0.5f - c.cy) * c.ify;
-    float a[3] = {dr * xr - dl * xl, dr * y0 - dl * y0, dr - dl};
-    float b[3] = {dd * x0 - du * x0, dd * yd - du * yu, dd - du};
-    float n[3];
-    cross3(a, b, n);
-    float len = sqrtf(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-    if (!(len > 0.0f)) return;
-    float sgn = (n[0] * x0 + n[1] * y0 + n[2]) * d < 0.0f ? 1.0f : -1.0f;
-    float il = sgn / len;
-    N[0] = n[0] * il;
-    N[1] = n[1] * il;
-    N[2] = n[2] * il;
-    nmask[gid] = 1;
+    N[0] = o[0];
+    N[1] = o[1];
+    N[2] = o[2];
+    nmask[gid] = ok;
 }
 
 __global__ __launch_bounds__(256) void k_normals(CamC c, int n_frames, const float* __restrict__ depth,
