@@ -299,6 +299,23 @@ __global__ __launch_bounds__(256) void k_cull(GridC g, CamC c, const prism_pose*
 
 
 
+// plane p of a map as a global-space pointer (uniform, so it lives in
+// scalar registers), and element loads / stores through it
+template <typename T>
+__device__ __forceinline__ gptr<T> plane_g(const T* map, const GridC& g, int p) {
+    return as_global(map + (long long)p * g.nvox);
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* plane_w(T* map, const GridC& g, int p) {
+    return (__attribute__((address_space(1))) T*)(map + (long long)p * g.nvox);
+}
+__device__ __forceinline__ float ldp(gptr<float> p, unsigned i) { return p[i]; }
+__device__ __forceinline__ float ldp(gptr<uint16_t> p, unsigned i) { return __uint_as_float(((uint32_t)p[i]) << 16); }
+__device__ __forceinline__ void stp(__attribute__((address_space(1))) float* p, unsigned i, float v) { p[i] = v; }
+__device__ __forceinline__ void stp(__attribute__((address_space(1))) uint16_t* p, unsigned i, float v) {
+    p[i] = f2bf(v);
+}
+
 // workgroup blk of ngroups of the update
 template <typename T, bool Pool>
 __device__ __forceinline__ void map_update_block(int blk, int ngroups, const GridC& g, const CamC& c, const GridD& gd,
@@ -423,72 +440,99 @@ __device__ __forceinline__ void map_update_block(int blk, int ngroups, const Gri
             slot = sl;
         }
         float m = -INFINITY;
+        // the lane's eight z-slices in groups of two: a group's plane and
+        // colour loads are all issued before any of them is used (one memory
+        // round trip per group, not per voxel; groups of four cost more in
+        // registers, hence waves, than they save), through global-space
+        // plane pointers with 32-bit element offsets (a plane holds at most
+        // 2^30 elements)
+        const unsigned base = (unsigned)((slot << 9) | lane);
 #pragma unroll
-        for (int h = 0; h < 8; ++h) {
-            const int k = (bz << 3) | h;
-            const long long id = (slot << 9) | (h << 6) | lane;
-            if (!upd[h]) {
-                if (fresh) {
+        for (int h0 = 0; h0 < 8; h0 += 2) {
+            float lv[2][8], lc[2][3];
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                const int h = h0 + hh;
+                const unsigned id = base | (unsigned)(h << 6);
+                if (upd[h]) {
+                    if (!fresh) {
+#pragma unroll
+                        for (int pl = 0; pl < 8; ++pl) lv[hh][pl] = ldp(plane_g(map, g, pl), id);
+                    }
+                    const int px = pix[h];
+#pragma unroll
+                    for (int ch = 0; ch < 3; ++ch) lc[hh][ch] = rgb[3 * px + ch];
+                } else if (!fresh) {
+                    lv[hh][0] = ldp(plane_g(map, g, 0), id);
+                }
+            }
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                const int h = h0 + hh;
+                const int k = (bz << 3) | h;
+                const unsigned id = base | (unsigned)(h << 6);
+                if (!upd[h]) {
+                    if (fresh) {
+#pragma unroll
+                        for (int ch = 0; ch < 4; ++ch) {
+                            stp(plane_w(map, g, ch), id, ch == 0 ? g.pocc : g.prgb);
+                            stp(plane_w(map, g, 4 + ch), id, pvar);
+                        }
+                        m = fmaxf(m, g.pocc);
+                    } else {
+                        m = fmaxf(m, lv[hh][0]);
+                    }
+                    continue;
+                }
+                // values in double precision: camera depth of the voxel centre,
+                // truncated negative SDF, Gaussian product in precision form
+                double dd0 = (gd.o[0] + gd.s * ((double)i + 0.5)) - Q.t[0];
+                double dd1 = (gd.o[1] + gd.s * ((double)j + 0.5)) - Q.t[1];
+                double dd2 = (gd.o[2] + gd.s * ((double)k + 0.5)) - Q.t[2];
+                double zc = Q.R[0][2] * dd0 + Q.R[1][2] * dd1 + Q.R[2][2] * dd2;
+                double f[4];
+                f[0] = zc - (double)Dv[h];
+                if (f[0] < -mp.trunc) f[0] = -mp.trunc;
+                f[1] = (double)lc[hh][0];
+                f[2] = (double)lc[hh][1];
+                f[3] = (double)lc[hh][2];
+                double mu[4], var[4];
+#pragma unroll
+                for (int ch = 0; ch < 4; ++ch) {
+                    mu[ch] = fresh ? (double)(ch == 0 ? g.pocc : g.prgb) : (double)lv[hh][ch];
+                    var[ch] = fresh ? (double)pvar : (double)lv[hh][4 + ch];
+                }
+                // App. D: new precision = old + update precision; new mean =
+                // inverse of the new precision times the precision-weighted sum.
+                // The four channels of a voxel are always updated together with
+                // one update precision, so their variances are normally equal bit
+                // for bit: the precision algebra is then done once (same inputs,
+                // same operations, same results as per channel).
+                double lam[4], var2[4];
+                if (var[0] == var[1] && var[1] == var[2] && var[2] == var[3]) {
+                    double l = 1.0 / var[0];
+                    double v2 = 1.0 / (l + mp.lam_u);
 #pragma unroll
                     for (int ch = 0; ch < 4; ++ch) {
-                        st(map, ch * g.nvox + id, ch == 0 ? g.pocc : g.prgb);
-                        st(map, (4 + ch) * g.nvox + id, pvar);
+                        lam[ch] = l;
+                        var2[ch] = v2;
                     }
-                    m = fmaxf(m, g.pocc);
                 } else {
-                    m = fmaxf(m, ld(map, id));
-                }
-                continue;
-            }
-            // values in double precision: camera depth of the voxel centre,
-            // truncated negative SDF, Gaussian product in precision form
-            double dd0 = (gd.o[0] + gd.s * ((double)i + 0.5)) - Q.t[0];
-            double dd1 = (gd.o[1] + gd.s * ((double)j + 0.5)) - Q.t[1];
-            double dd2 = (gd.o[2] + gd.s * ((double)k + 0.5)) - Q.t[2];
-            double zc = Q.R[0][2] * dd0 + Q.R[1][2] * dd1 + Q.R[2][2] * dd2;
-            const int px = pix[h];
-            double f[4];
-            f[0] = zc - (double)Dv[h];
-            if (f[0] < -mp.trunc) f[0] = -mp.trunc;
-            f[1] = (double)rgb[3 * px];
-            f[2] = (double)rgb[3 * px + 1];
-            f[3] = (double)rgb[3 * px + 2];
-            double mu[4], var[4];
 #pragma unroll
-            for (int ch = 0; ch < 4; ++ch) {
-                mu[ch] = fresh ? (double)(ch == 0 ? g.pocc : g.prgb) : (double)ld(map, ch * g.nvox + id);
-                var[ch] = fresh ? (double)pvar : (double)ld(map, (4 + ch) * g.nvox + id);
-            }
-            // App. D: new precision = old + update precision; new mean =
-            // inverse of the new precision times the precision-weighted sum.
-            // The four channels of a voxel are always updated together with
-            // one update precision, so their variances are normally equal bit
-            // for bit: the precision algebra is then done once (same inputs,
-            // same operations, same results as per channel).
-            double lam[4], var2[4];
-            if (var[0] == var[1] && var[1] == var[2] && var[2] == var[3]) {
-                double l = 1.0 / var[0];
-                double v2 = 1.0 / (l + mp.lam_u);
+                    for (int ch = 0; ch < 4; ++ch) {
+                        lam[ch] = 1.0 / var[ch];
+                        var2[ch] = 1.0 / (lam[ch] + mp.lam_u);
+                    }
+                }
 #pragma unroll
                 for (int ch = 0; ch < 4; ++ch) {
-                    lam[ch] = l;
-                    var2[ch] = v2;
+                    float nm = (float)(var2[ch] * (lam[ch] * mu[ch] + mp.lam_u * f[ch]));
+                    stp(plane_w(map, g, ch), id, nm);
+                    stp(plane_w(map, g, 4 + ch), id, (float)var2[ch]);
+                    if (ch == 0) m = fmaxf(m, stored<T>(nm));
                 }
-            } else {
-#pragma unroll
-                for (int ch = 0; ch < 4; ++ch) {
-                    lam[ch] = 1.0 / var[ch];
-                    var2[ch] = 1.0 / (lam[ch] + mp.lam_u);
-                }
+                ++cnt;
             }
-#pragma unroll
-            for (int ch = 0; ch < 4; ++ch) {
-                float nm = (float)(var2[ch] * (lam[ch] * mu[ch] + mp.lam_u * f[ch]));
-                st(map, ch * g.nvox + id, nm);
-                st(map, (4 + ch) * g.nvox + id, (float)var2[ch]);
-                if (ch == 0) m = fmaxf(m, stored<T>(nm));
-            }
-            ++cnt;
         }
         for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
         if (lane == 0) {
