@@ -133,9 +133,55 @@ __device__ __forceinline__ void grid_coord64(const GridD& gd, const CamD& cd, co
     }
 }
 
-template <typename T, bool Pool>
-__device__ __forceinline__ Shade shade(const GridC& g, const GridD& gd, const CamD& cd, const Pose64& P, int u,
-                                       int v, const T* map, const RayHit& h) {
+// The eight corners of one cell in the four mean planes of an FP32 map,
+// loaded once for the adjoint: v[p][q] the stored value, or the plane's
+// outside value (single precision) for a corner outside the grid; e[q] the
+// corner's element index, -1 outside the grid.  The adjoint's occupancy
+// test, double-precision shading, Jacobian and scatter all read these.
+struct CellVals {
+    float v[4][8];
+    int e[8];
+};
+
+__device__ __forceinline__ void cell_vals(const GridC& g, const float* map, const Cell& c, CellVals& cv) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int i = c.i[0] + (q & 1), j = c.i[1] + ((q >> 1) & 1), k = c.i[2] + (q >> 2);
+        const bool in = (unsigned)i < (unsigned)g.n && (unsigned)j < (unsigned)g.n && (unsigned)k < (unsigned)g.n;
+        cv.e[q] = in ? (int)vidx<false>(g, i, j, k) : -1;
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            cv.v[p][q] = cv.e[q] >= 0 ? map[(long long)p * g.nvox + cv.e[q]] : (p == 0 ? g.occ_out : g.rgb_out);
+}
+
+// tri64 on preloaded corners: a corner outside the grid takes the plane's
+// double-precision outside value, exactly as tri64 does
+__device__ __forceinline__ double tri64v(const CellVals& cv, int p, double outv, const double gc[3],
+                                         const int cell[3]) {
+    double w0 = gc[0] - (double)cell[0], w1 = gc[1] - (double)cell[1], w2 = gc[2] - (double)cell[2];
+    double s = 0.0;
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+            for (int cx = 0; cx < 2; ++cx) {
+                const int q = cx + 2 * cy + 4 * cz;
+                double hx = cx ? w0 : 1.0 - w0;
+                double hy = cy ? w1 : 1.0 - w1;
+                double hz = cz ? w2 : 1.0 - w2;
+                double V = cv.e[q] >= 0 ? (double)cv.v[p][q] : outv;
+                s += hx * hy * hz * V;
+            }
+    return s;
+}
+
+// shading at a valid hit from the two cells' corner values
+__device__ __forceinline__ Shade shade_v(const GridD& gd, const CamD& cd, const Pose64& P, int u, int v,
+                                         const RayHit& h, const CellVals& v0, const CellVals& v1) {
     Shade s;
     double rc[3], dir[3], gc0[3], gc1[3];
     pixel_dir64(cd, u, v, rc);
@@ -145,8 +191,8 @@ __device__ __forceinline__ Shade shade(const GridC& g, const GridD& gd, const Ca
     grid_coord64(gd, cd, P, dir, h.k, gc1);
     double d0 = cd.dn + (double)(h.k - 1) * cd.step;
     double d1 = cd.dn + (double)h.k * cd.step;
-    s.f0 = tri64<T, Pool>(g, map, gc0, h.c0.i, gd.occ_out, g.pocc);
-    s.f1 = tri64<T, Pool>(g, map, gc1, h.c1.i, gd.occ_out, g.pocc);
+    s.f0 = tri64v(v0, 0, gd.occ_out, gc0, h.c0.i);
+    s.f1 = tri64v(v1, 0, gd.occ_out, gc1, h.c1.i);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         s.w0[a] = (float)(gc0[a] - (double)h.c0.i[a]);
@@ -154,11 +200,10 @@ __device__ __forceinline__ Shade shade(const GridC& g, const GridD& gd, const Ca
     }
     double al = (cd.tau - s.f0) / (s.f1 - s.f0);
     s.depth = al * d1 + (1.0 - al) * d0;
-#pragma unroll 1
+#pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
-        const T* pl = map + (long long)(1 + ch) * g.nvox;
-        double c0 = tri64<T, Pool>(g, pl, gc0, h.c0.i, gd.rgb_out, g.prgb);
-        double c1 = tri64<T, Pool>(g, pl, gc1, h.c1.i, gd.rgb_out, g.prgb);
+        double c0 = tri64v(v0, 1 + ch, gd.rgb_out, gc0, h.c0.i);
+        double c1 = tri64v(v1, 1 + ch, gd.rgb_out, gc1, h.c1.i);
         s.rgb[ch] = al * c1 + (1.0 - al) * c0;
         s.c0[ch] = (float)c0;
         s.c1[ch] = (float)c1;
@@ -175,18 +220,16 @@ __device__ __forceinline__ void cross3(const float a[3], const float b[3], float
     o[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-// d(depth, r, g, b)/d(delta) of a valid ray (k* held fixed)
-template <typename T, bool Pool>
-__device__ __forceinline__ void ray_jacobian(const GridC& g, const T* map, const RayHit& h,
+// d(depth, r, g, b)/d(delta) of a valid ray (k* held fixed), from the two
+// cells' preloaded corner values
+__device__ __forceinline__ void ray_jacobian(const GridC& g, const CellVals& v0, const CellVals& v1,
                                              const Shade& s, const float dir[3], float J[4][6]) {
     float a0[3], a1[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) { a0[i] = s.d0 * dir[i]; a1[i] = s.d1 * dir[i]; }
-    float v[8], gr0[3], gr1[3], cr[3];
-    corners<T, Pool>(g, map, h.c0, g.occ_out, g.pocc, v);
-    trigrad(v, s.w0, gr0);
-    corners<T, Pool>(g, map, h.c1, g.occ_out, g.pocc, v);
-    trigrad(v, s.w1, gr1);
+    float gr0[3], gr1[3], cr[3];
+    trigrad(v0.v[0], s.w0, gr0);
+    trigrad(v1.v[0], s.w1, gr1);
     float rf0[6], rf1[6];
 #pragma unroll
     for (int i = 0; i < 3; ++i) { gr0[i] *= g.inv_s; gr1[i] *= g.inv_s; rf0[i] = gr0[i]; rf1[i] = gr1[i]; }
@@ -205,12 +248,9 @@ __device__ __forceinline__ void ray_jacobian(const GridC& g, const T* map, const
     for (int m = 0; m < 6; ++m) J[0][m] = (s.d1 - s.d0) * dal[m];
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
-        const T* pl = map + (long long)(1 + ch) * g.nvox;
         float G0[3], G1[3], g0[6], g1[6];
-        corners<T, Pool>(g, pl, h.c0, g.rgb_out, g.prgb, v);
-        trigrad(v, s.w0, G0);
-        corners<T, Pool>(g, pl, h.c1, g.rgb_out, g.prgb, v);
-        trigrad(v, s.w1, G1);
+        trigrad(v0.v[1 + ch], s.w0, G0);
+        trigrad(v1.v[1 + ch], s.w1, G1);
 #pragma unroll
         for (int i = 0; i < 3; ++i) { G0[i] *= g.inv_s; G1[i] *= g.inv_s; g0[i] = G0[i]; g1[i] = G1[i]; }
         cross3(a0, G0, cr);
@@ -689,14 +729,18 @@ __global__ __launch_bounds__(256) void k_render_vjp(GridC g, CamC c, GridD gd, C
             h.k = k;
             h.c0 = sample_cell(rc, k - 1);
             h.c1 = sample_cell(rc, k);
-            h.f0 = occ_at<float, false>(g, map, h.c0);
-            h.f1 = occ_at<float, false>(g, map, h.c1);
+            // all 64 corner values of the two cells in one round of loads
+            CellVals v0, v1;
+            cell_vals(g, map, h.c0, v0);
+            cell_vals(g, map, h.c1, v1);
+            h.f0 = trilerp(v0.v[0], h.c0.w);
+            h.f1 = trilerp(v1.v[0], h.c1.w);
             if (h.f1 > c.tau && !(h.f0 > c.tau)) {
-                Shade s = shade<float, false>(g, gd, cd, P.d, u, v, map, h);
+                Shade s = shade_v(gd, cd, P.d, u, v, h, v0, v1);
                 float gd = g_depth[pix];
                 float gc[3] = {g_rgb[3 * pix], g_rgb[3 * pix + 1], g_rgb[3 * pix + 2]};
                 float J[4][6];
-                ray_jacobian<float, false>(g, map, h, s, dir, J);
+                ray_jacobian(g, v0, v1, s, dir, J);
 #pragma unroll
                 for (int m = 0; m < 6; ++m)
                     acc[m] = (double)(gd * J[0][m] + gc[0] * J[1][m] + gc[1] * J[2][m] + gc[2] * J[3][m]);
@@ -708,20 +752,17 @@ __global__ __launch_bounds__(256) void k_render_vjp(GridC g, CamC c, GridD gd, C
                 float cw[2] = {1.0f - al, al};
 #pragma unroll
                 for (int sm = 0; sm < 2; ++sm) {
-                    const Cell& cl = sm ? h.c1 : h.c0;
+                    const CellVals& cv = sm ? v1 : v0;
 #pragma unroll
                     for (int q = 0; q < 8; ++q) {
                         int dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
-                        int i = cl.i[0] + dx, j = cl.i[1] + dy, kk = cl.i[2] + dz;
-                        if ((unsigned)i >= (unsigned)g.n || (unsigned)j >= (unsigned)g.n ||
-                            (unsigned)kk >= (unsigned)g.n)
-                            continue;
+                        if (cv.e[q] < 0) continue;   // outside the grid
                         const float* cw3 = sm ? s.w1 : s.w0;
                         float hw = (dx ? cw3[0] : 1.0f - cw3[0]) * (dy ? cw3[1] : 1.0f - cw3[1]) *
                                    (dz ? cw3[2] : 1.0f - cw3[2]);
                         const float vals[4] = {gf[sm] * hw, gc[0] * cw[sm] * hw, gc[1] * cw[sm] * hw,
                                                gc[2] * cw[sm] * hw};
-                        vjp_add(A, vidx(g, i, j, kk), vals, grad_mean, g.nvox);
+                        vjp_add(A, cv.e[q], vals, grad_mean, g.nvox);
                     }
                 }
             }
