@@ -96,32 +96,6 @@ struct Shade {
     double f0, f1;
 };
 
-// trilinear value of one plane in double precision: cell from the decision
-// recipe, weights from the double-precision grid coordinate, sum over the 8
-// corners of the product of 1-D hat weights (z, y, x order)
-template <typename T, bool Pool>
-__device__ __forceinline__ double tri64(const GridC& g, const T* plane, const double gc[3], const int cell[3],
-                                        double outv, float priorv) {
-    double w0 = gc[0] - (double)cell[0], w1 = gc[1] - (double)cell[1], w2 = gc[2] - (double)cell[2];
-    double s = 0.0;
-#pragma unroll
-    for (int cz = 0; cz < 2; ++cz)
-#pragma unroll
-        for (int cy = 0; cy < 2; ++cy)
-#pragma unroll
-            for (int cx = 0; cx < 2; ++cx) {
-                double hx = cx ? w0 : 1.0 - w0;
-                double hy = cy ? w1 : 1.0 - w1;
-                double hz = cz ? w2 : 1.0 - w2;
-                int i = cell[0] + cx, j = cell[1] + cy, k = cell[2] + cz;
-                bool in = (unsigned)i < (unsigned)g.n && (unsigned)j < (unsigned)g.n && (unsigned)k < (unsigned)g.n;
-                const long long e = in ? vidx<Pool>(g, i, j, k) : -1;
-                double V = e >= 0 ? (double)ld(plane, e) : in ? (double)priorv : outv;
-                s += hx * hy * hz * V;
-            }
-    return s;
-}
-
 // double-precision sample point k of the ray with direction dir (world)
 __device__ __forceinline__ void grid_coord64(const GridD& gd, const CamD& cd, const Pose64& P, const double dir[3],
                                              int k, double gc[3]) {
@@ -157,8 +131,10 @@ __device__ __forceinline__ void cell_vals(const GridC& g, const float* map, cons
             cv.v[p][q] = cv.e[q] >= 0 ? map[(long long)p * g.nvox + cv.e[q]] : (p == 0 ? g.occ_out : g.rgb_out);
 }
 
-// tri64 on preloaded corners: a corner outside the grid takes the plane's
-// double-precision outside value, exactly as tri64 does
+// Trilinear value of plane p in double precision from the adjoint's
+// preloaded corners: weights from the double-precision grid coordinate, sum
+// over the 8 corners of the product of 1-D hat weights (z, y, x order); a
+// corner outside the grid takes the double-precision outside value.
 __device__ __forceinline__ double tri64v(const CellVals& cv, int p, double outv, const double gc[3],
                                          const int cell[3]) {
     double w0 = gc[0] - (double)cell[0], w1 = gc[1] - (double)cell[1], w2 = gc[2] - (double)cell[2];
@@ -365,7 +341,34 @@ struct QuadShade {
     double alpha, value;    // alpha and this lane's output (depth or colour)
     float w0[3], w1[3];
     float d0, d1;
+    float cv0[8], cv1[8];   // plane s at the corners of the two cells (as corners() gives them)
 };
+
+// Trilinear value of one plane in double precision at a marched sample:
+// cell from the decision recipe, weights from the double-precision grid
+// coordinate, sum over the 8 corners of the product of 1-D hat weights (z, y,
+// x order).  The corners are the ones corners() gathered; a corner outside
+// the grid takes the double-precision outside value.
+__device__ __forceinline__ double tri64c(const GridC& g, const float v[8], const double gc[3], const int cell[3],
+                                         double outv) {
+    double w0 = gc[0] - (double)cell[0], w1 = gc[1] - (double)cell[1], w2 = gc[2] - (double)cell[2];
+    double s = 0.0;
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+            for (int cx = 0; cx < 2; ++cx) {
+                double hx = cx ? w0 : 1.0 - w0;
+                double hy = cy ? w1 : 1.0 - w1;
+                double hz = cz ? w2 : 1.0 - w2;
+                int i = cell[0] + cx, j = cell[1] + cy, k = cell[2] + cz;
+                bool in = (unsigned)i < (unsigned)g.n && (unsigned)j < (unsigned)g.n && (unsigned)k < (unsigned)g.n;
+                double V = in ? (double)v[cx + 2 * cy + 4 * cz] : outv;
+                s += hx * hy * hz * V;
+            }
+    return s;
+}
 
 template <typename T, bool Pool>
 __device__ __forceinline__ QuadShade shade_quad(const GridC& g, const GridD& gd, const CamD& cd, const Pose64& P,
@@ -382,9 +385,12 @@ __device__ __forceinline__ QuadShade shade_quad(const GridC& g, const GridD& gd,
     double d1 = cd.dn + (double)k * cd.step;
     const T* pl = map + (long long)s * g.nvox;
     double outv = s == 0 ? gd.occ_out : gd.rgb_out;
-    float priorv = s == 0 ? g.pocc : g.prgb;
-    q.v0 = tri64<T, Pool>(g, pl, gc0, c0.i, outv, priorv);
-    q.v1 = tri64<T, Pool>(g, pl, gc1, c1.i, outv, priorv);
+    float outv32 = s == 0 ? g.occ_out : g.rgb_out, priorv = s == 0 ? g.pocc : g.prgb;
+    // the lane's plane at both cells, gathered once (the Jacobian row reuses them)
+    corners<T, Pool>(g, pl, c0, outv32, priorv, q.cv0);
+    corners<T, Pool>(g, pl, c1, outv32, priorv, q.cv1);
+    q.v0 = tri64c(g, q.cv0, gc0, c0.i, outv);
+    q.v1 = tri64c(g, q.cv1, gc1, c1.i, outv);
     q.f0 = quad_bcast(q.v0, 0);
     q.f1 = quad_bcast(q.v1, 0);
     q.alpha = (cd.tau - q.f0) / (q.f1 - q.f0);
@@ -401,19 +407,14 @@ __device__ __forceinline__ QuadShade shade_quad(const GridC& g, const GridD& gd,
 
 // This lane's row of the 4x6 Jacobian d(depth, r, g, b)/d(delta), k* fixed.
 // Lane 0 forms d(alpha)/d(delta) from the occupancy gradients and shares it.
-template <typename T, bool Pool>
-__device__ __forceinline__ void jac_row_quad(const GridC& g, const T* map, const Cell& c0, const Cell& c1,
-                                             const QuadShade& q, const float dir[3], int s, float row[6]) {
+__device__ __forceinline__ void jac_row_quad(const GridC& g, const QuadShade& q, const float dir[3], int s,
+                                             float row[6]) {
     float a0[3], a1[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) { a0[i] = q.d0 * dir[i]; a1[i] = q.d1 * dir[i]; }
-    const T* pl = map + (long long)s * g.nvox;
-    float outv = s == 0 ? g.occ_out : g.rgb_out, priorv = s == 0 ? g.pocc : g.prgb;
-    float v[8], G0[3], G1[3], cr[3], r0[6], r1[6];
-    corners<T, Pool>(g, pl, c0, outv, priorv, v);
-    trigrad(v, q.w0, G0);
-    corners<T, Pool>(g, pl, c1, outv, priorv, v);
-    trigrad(v, q.w1, G1);
+    float G0[3], G1[3], cr[3], r0[6], r1[6];
+    trigrad(q.cv0, q.w0, G0);
+    trigrad(q.cv1, q.w1, G1);
 #pragma unroll
     for (int i = 0; i < 3; ++i) { G0[i] *= g.inv_s; G1[i] *= g.inv_s; r0[i] = G0[i]; r1[i] = G1[i]; }
     cross3(a0, G0, cr);
@@ -626,7 +627,7 @@ __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, GridD gd, C
             value = q.value;
             float D = obs_depth[pix];
             if (depth_ok(D)) {
-                jac_row_quad<T, Pool>(g, map, c0, c1, q, dir, s, row);
+                jac_row_quad(g, q, dir, s, row);
                 r = s == 0 ? value - (double)D : value - (double)obs_rgb[3 * pix + s - 1];
                 // colour gate on |r_r| + |r_g| + |r_b| (lanes 1-3), depth gate on lane 0
                 double l1 = s == 0 ? 0.0 : fabs(r);
