@@ -135,6 +135,7 @@ GridD grid_d(const prism_grid* g) {
     o.s = g->voxel;
     o.occ_out = g->occ_out;
     o.rgb_out = g->rgb_out;
+    o.inv_s = 1.0 / g->voxel;
     return o;
 }
 

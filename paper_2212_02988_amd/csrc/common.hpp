@@ -58,6 +58,7 @@ struct GridD {
     double o[3];
     double s;
     double occ_out, rgb_out;
+    double inv_s;   // 1 / s
 };
 
 struct CamD {

@@ -103,7 +103,7 @@ __device__ __forceinline__ void grid_coord64(const GridD& gd, const CamD& cd, co
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         double p = P.t[a] + dk * dir[a];
-        gc[a] = (p - gd.o[a]) / gd.s - 0.5;
+        gc[a] = (p - gd.o[a]) * gd.inv_s - 0.5;
     }
 }
 
