@@ -352,6 +352,21 @@ struct QuadShade {
 __device__ __forceinline__ double tri64c(const GridC& g, const float v[8], const double gc[3], const int cell[3],
                                          double outv) {
     double w0 = gc[0] - (double)cell[0], w1 = gc[1] - (double)cell[1], w2 = gc[2] - (double)cell[2];
+    // a cell inside the grid (the usual case) needs no test per corner
+    const unsigned lim = (unsigned)(g.n - 1);
+    const bool inside = (unsigned)cell[0] < lim && (unsigned)cell[1] < lim && (unsigned)cell[2] < lim;
+    double V[8];
+    if (inside) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) V[q] = (double)v[q];
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            int i = cell[0] + (q & 1), j = cell[1] + ((q >> 1) & 1), k = cell[2] + (q >> 2);
+            bool in = (unsigned)i < (unsigned)g.n && (unsigned)j < (unsigned)g.n && (unsigned)k < (unsigned)g.n;
+            V[q] = in ? (double)v[q] : outv;
+        }
+    }
     double s = 0.0;
 #pragma unroll
     for (int cz = 0; cz < 2; ++cz)
@@ -362,10 +377,7 @@ __device__ __forceinline__ double tri64c(const GridC& g, const float v[8], const
                 double hx = cx ? w0 : 1.0 - w0;
                 double hy = cy ? w1 : 1.0 - w1;
                 double hz = cz ? w2 : 1.0 - w2;
-                int i = cell[0] + cx, j = cell[1] + cy, k = cell[2] + cz;
-                bool in = (unsigned)i < (unsigned)g.n && (unsigned)j < (unsigned)g.n && (unsigned)k < (unsigned)g.n;
-                double V = in ? (double)v[cx + 2 * cy + 4 * cz] : outv;
-                s += hx * hy * hz * V;
+                s += hx * hy * hz * V[cx + 2 * cy + 4 * cz];
             }
     return s;
 }
