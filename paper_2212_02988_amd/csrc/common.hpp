@@ -178,12 +178,9 @@ __device__ __forceinline__ float ld(const uint16_t* p, long long i) {
     return __uint_as_float(((uint32_t)p[i]) << 16);
 }
 __device__ __forceinline__ void st(float* p, long long i, float v) { p[i] = v; }
-__device__ __forceinline__ uint16_t f2bf(float v) {
-    uint32_t b = __float_as_uint(v);
-    if ((b & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((b >> 16) | 0x40);   // quiet NaN
-    b += 0x7fffu + ((b >> 16) & 1u);                                            // nearest even
-    return (uint16_t)(b >> 16);
-}
+// single precision -> BF16, round to nearest even (gfx950's conversion
+// instruction; a NaN stays a NaN)
+__device__ __forceinline__ uint16_t f2bf(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
 __device__ __forceinline__ void st(uint16_t* p, long long i, float v) { p[i] = f2bf(v); }
 
 // Element index within a plane of voxel (i, j, k), all in [0, n): brick order
