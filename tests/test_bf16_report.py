@@ -22,10 +22,11 @@ closed-loop drift mixed in:
 * anchor depth and colour rendered from the updated map: reported as
   quantiles; bounded loosely (BF16 moves the occupancy zero crossing).
 
-The report is written to $PRISM_REPORT_DIR (default ./gpurun_out) as
-bf16_error_report.json."""
+The report is written to $PRISM_REPORT_DIR (default: the system temporary
+directory) as bf16_error_report.json."""
 import json
 import os
+import tempfile
 
 import numpy as np
 import pytest
@@ -131,7 +132,7 @@ def test_bf16_per_output_error_vs_fp64_oracle():
         assert e_P <= 1e-4, row
         assert row["anchor_valid_mismatch_frac"] <= 0.01 and row["anchor_depth_rel"]["p50"] <= 1e-3, row
         del of, ao, ag, mean64, var64
-    out_dir = os.environ.get("PRISM_REPORT_DIR", "gpurun_out")
+    out_dir = os.environ.get("PRISM_REPORT_DIR") or tempfile.gettempdir()
     os.makedirs(out_dir, exist_ok=True)
     with open(os.path.join(out_dir, "bf16_error_report.json"), "w") as fh:
         json.dump(report, fh, indent=1)
