@@ -259,6 +259,27 @@ prism_status prism_render_jacobian(const prism_grid *grid, const void *map,
                                    float *J, float *resid, uint8_t *rowmask, double *neq,
                                    void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* prism_render_jacobian for callers that cannot allocate device memory or
+ * pass a workspace (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments and results, bit for
+ * bit, minus workspace/workspace_bytes: the per-workgroup partial sums go to
+ * a fixed array inside the library, one copy per GPU, of
+ * prism_render_jacobian_noalloc_max_bytes() bytes (8 MiB), held until the
+ * process ends.  A call needs n_frames * ceil(W/8) * ceil(H/8) * 232 bytes of
+ * it (320x240: 30 frames at most; 640x480: 7) and fails with
+ * PRISM_INVALID_ARGUMENT, queuing nothing, beyond that.  Allocates nothing:
+ * no hipMalloc, hipFree or allocating library call.  Every call on one GPU
+ * shares that GPU's array, so calls that overlap on one GPU (on different
+ * streams, or from different threads) race and give undefined results; calls
+ * in order on one stream are safe. */
+size_t prism_render_jacobian_noalloc_max_bytes(void);
+prism_status prism_render_jacobian_noalloc(const prism_grid *grid, const void *map,
+                                           const prism_camera *cam, const prism_pose *poses,
+                                           int32_t n_frames, const float *obs_depth,
+                                           const float *obs_rgb, const prism_weights *w, float *depth,
+                                           float *rgb, uint8_t *mask, float *J, float *resid,
+                                           uint8_t *rowmask, double *neq, hipStream_t stream);
+
 /* Prediction-to-observation objective (App. E.3, P2) for one frame: each
  * observed pixel with valid depth D is back-projected (D r_c), moved by the
  * pose iterate `pose` and brought into the camera of `pose_prev` (the pose the

@@ -620,6 +620,74 @@ prism_status prism_render_jacobian(const prism_grid* grid, const void* map, cons
     return PRISM_OK;
 }
 
+}  // extern "C"
+
+// ---- render Jacobian without a workspace argument --------------------------
+// The per-workgroup partial sums of prism_render_jacobian_noalloc live in this
+// file-scope device array (one copy per GPU, held until the process ends).  In
+// host code its name is only a stand-in: the device address of each GPU's copy
+// is looked up once per device with hipGetSymbolAddress and used from then on.
+constexpr size_t kNoAllocScratchBytes = size_t(8) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// device address of the current device's copy of `scratch`
+prism_status scratch_address(void** out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(PRISM_UNSUPPORTED, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(PRISM_HIP_ERROR, "hipGetSymbolAddress returned NULL for the scratch array");
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return PRISM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t prism_render_jacobian_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
+
+prism_status prism_render_jacobian_noalloc(const prism_grid* grid, const void* map, const prism_camera* cam,
+                                           const prism_pose* poses, int32_t n_frames, const float* obs_depth,
+                                           const float* obs_rgb, const prism_weights* w, float* depth, float* rgb,
+                                           uint8_t* mask, float* J, float* resid, uint8_t* rowmask, double* neq,
+                                           hipStream_t stream) {
+    prism_status s;
+    if ((s = check_grid(grid)) || (s = check_cam(cam)) || (s = check_weights(w))) return s;
+    REQUIRE(map && aligned(map, 256), "map must be non-NULL and 256-byte aligned");
+    REQUIRE(poses && aligned(poses, 8), "poses must be non-NULL and 8-byte aligned");
+    REQUIRE(n_frames >= 1 && n_frames <= 65535, "n_frames must be in [1, 65535]");
+    REQUIRE(obs_depth && obs_rgb && aligned(obs_depth, 4) && aligned(obs_rgb, 4), "observations must be non-NULL, aligned");
+    REQUIRE(neq && aligned(neq, 8), "neq must be non-NULL and 8-byte aligned");
+    REQUIRE((!J || aligned(J, 16)) && (!resid || aligned(resid, 16)), "J and resid must be 16-byte aligned");
+    REQUIRE((!depth || aligned(depth, 4)) && (!rgb || aligned(rgb, 4)), "outputs misaligned");
+    CamC c = cam_c(cam);
+    const size_t need = (size_t)render_blocks(c) * n_frames * PRISM_NEQ * sizeof(double);
+    REQUIRE(need <= kNoAllocScratchBytes,
+            "render_jacobian_noalloc: %d frames of %dx%d need %zu bytes of partial sums, more than the %zu-byte "
+            "scratch array (use prism_render_jacobian with a workspace)",
+            n_frames, cam->width, cam->height, need, kNoAllocScratchBytes);
+    void* part = nullptr;
+    if ((s = scratch_address(&part))) return s;
+    // every workgroup writes its own row of partial sums: nothing to clear
+    HIP_TRY(launch_render_jac(grid_cm(grid, map), c, grid_d(grid), cam_d(cam), grid->dtype, map,
+                              skip_table(grid, cam, map), poses, n_frames, obs_depth, obs_rgb, weights_c(w),
+                              depth, rgb, mask, J, resid, rowmask, (double*)part, stream));
+    HIP_TRY(launch_finalize((const double*)part, render_blocks(c), n_frames, PRISM_NEQ, neq, PRISM_NEQ, stream));
+    return PRISM_OK;
+}
+
 prism_status prism_track_p2(const prism_camera* cam, const prism_pose* pose, const prism_pose* pose_prev,
                             const float* obs_depth, const float* obs_rgb, const float* anchor_depth,
                             const float* anchor_rgb, const uint8_t* anchor_mask, const float* anchor_normals,

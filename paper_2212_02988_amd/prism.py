@@ -129,6 +129,9 @@ _SIGS = {
     "prism_reduce_workspace_bytes": (["p", ctypes.c_int32, "p"], None),
     "prism_render_jacobian": (["p", "p", "p", "p", ctypes.c_int32, "p", "p", "p", "p", "p", "p", "p", "p", "p",
                                "p", "p", ctypes.c_size_t, "p"], None),
+    "prism_render_jacobian_noalloc_max_bytes": ([], ctypes.c_size_t),
+    "prism_render_jacobian_noalloc": (["p", "p", "p", "p", ctypes.c_int32, "p", "p", "p", "p", "p", "p", "p", "p",
+                                       "p", "p", "p"], None),
     "prism_track_p2": (["p", "p", "p", "p", "p", "p", "p", "p", "p", "p", "p", "p", "p", "p", "p", "p",
                         ctypes.c_size_t, "p"], None),
     "prism_render_vjp": (["p", "p", "p", "p", ctypes.c_int32, "p", "p", "p", "p", "p", "p", ctypes.c_size_t,
@@ -361,6 +364,28 @@ def render_jacobian(grid: Grid, vmap: VoxelMap, cam: Camera, poses: torch.Tensor
                                        _ptr(out.get("rowmask")), _ptr(out["neq"]), _ptr(ws), ws.numel(),
                                        _stream(stream)))
     return out
+
+
+def render_jacobian_noalloc(grid: Grid, vmap: VoxelMap, cam: Camera, poses: torch.Tensor, obs_depth: torch.Tensor,
+                            obs_rgb: torch.Tensor, w: Weights, out: Dict, stream=None) -> Dict:
+    """render_jacobian through the allocation-free entry point: no workspace;
+    every output buffer comes from the caller in `out` (neq required; depth,
+    rgb, mask, J, resid, rowmask optional)."""
+    n = poses.shape[0]
+    H, W = cam.height, cam.width
+    _dev(poses, torch.float64, "poses", (n, 7))
+    _dev(obs_depth, torch.float32, "obs_depth", (n, H, W))
+    _dev(obs_rgb, torch.float32, "obs_rgb", (n, H, W, 3))
+    _dev(out["neq"], torch.float64, "neq", (n, NEQ))
+    _check(lib().prism_render_jacobian_noalloc(_by(grid), _ptr(vmap.buf), _by(cam), _ptr(poses), n, _ptr(obs_depth),
+                                               _ptr(obs_rgb), _by(w), _ptr(out.get("depth")), _ptr(out.get("rgb")),
+                                               _ptr(out.get("mask")), _ptr(out.get("J")), _ptr(out.get("resid")),
+                                               _ptr(out.get("rowmask")), _ptr(out["neq"]), _stream(stream)))
+    return out
+
+
+def render_jacobian_noalloc_max_bytes() -> int:
+    return int(lib().prism_render_jacobian_noalloc_max_bytes())
 
 
 def track_p2(cam: Camera, pose: torch.Tensor, pose_prev: torch.Tensor, obs_depth: torch.Tensor,
