@@ -961,3 +961,101 @@ def test_rollout_improper_covariance_starts_at_the_mean(orc):
     out = orc.rollout(None, None, None, x, -np.eye(12), u, z, orc.Params(), frames=False)
     assert not out["ok"]
     assert np.linalg.norm(orc.pose_error(out["poses"][0, 0], out["mean"][0, :7])) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# App. G.2 Laplace average and App. E.3 / G.3 anchor normals
+# ---------------------------------------------------------------------------
+def test_laplace_average_enters_the_state_covariance(orc):
+    """App. G: the Laplace pose covariances are smoothed by an exponential
+    moving average with coefficient 0.8 on the previous average, the first
+    average being the first Laplace covariance; the averaged covariance is
+    the pose block of the combined state belief (Sec. 4.3.2 product with
+    the velocity conditional).  Each Laplace covariance is formed here from
+    the recorded normal equations and the predicted pose precision,
+    (2 H + Lp)^-1, independently of the filter's own code path."""
+    P0 = np.diag([1e-6] * 6 + [1e-4] * 6)
+    case, tr, f = _small_filter(orc, P0, n_frames=4)
+    f.step(case["depth"][0], case["rgb"][0], None)
+    assert f.s.Sbar is None                      # the first frame has no pose update
+    laps = []
+    for i in (1, 2, 3):
+        s = f.s
+        _, Pm = orc.predict(dict(t=s.t, q=s.q, v=s.v, w=s.w), s.P, tr.u[i - 1], f.p)
+        Lp = np.linalg.inv(Pm[:6, :6])
+        f.step(case["depth"][i], case["rgb"][i], tr.u[i - 1])
+        neq = f.s.last["neq"]
+        assert neq[28] > 100
+        H = np.zeros((6, 6))
+        H[np.triu_indices(6)] = neq[:21]
+        H = H + np.triu(H, 1).T
+        laps.append(np.linalg.inv(2.0 * H + Lp))
+        if i == 1:
+            expect = laps[0]
+        else:
+            expect = 0.8 * prev + 0.2 * laps[-1]
+            swapped = 0.2 * prev + 0.8 * laps[-1]
+            # the two weightings differ well beyond the tolerance below
+            assert np.linalg.norm(swapped - expect) > 1e-4 * np.linalg.norm(expect)
+        np.testing.assert_allclose(f.s.Sbar, expect, rtol=1e-8, atol=1e-8 * np.abs(expect).max())
+        np.testing.assert_allclose(f.s.P[:6, :6], expect, rtol=1e-8, atol=1e-8 * np.abs(expect).max())
+        prev = expect
+
+
+def _plane_depth(cam, nrm, c):
+    """z-depth image of the plane nrm . X = c seen from the camera origin."""
+    u = (np.arange(cam.width) + 0.5 - cam.cx) / cam.fx
+    v = (np.arange(cam.height) + 0.5 - cam.cy) / cam.fy
+    rx, ry = np.meshgrid(u, v)
+    return c / (nrm[0] * rx + nrm[1] * ry + nrm[2])
+
+
+def test_anchor_normals_validity_and_plane_normal(orc):
+    """App. E.3: the anchor normal is the normal of the rendered depth image;
+    App. G: depth discontinuities are ignored.  On a constructed image of
+    two tilted planes with a 0.5 m step between the left and right halves,
+    a 0.05 m step inside the left half, and two invalid pixels, the valid
+    set is known from the construction: not the border, not an invalid pixel
+    or one of its four neighbours, not a pixel next to the 0.5 m step (the
+    0.05 m step stays below the 0.1 m threshold).  Away from both steps the
+    normal is the plane's unit normal, oriented towards the camera."""
+    W, H = 40, 30
+    cam = orc.Cam(W, H, 30.0, 30.0, 20.0, 15.0, 0.1, 5.0, 16)
+    nrm = np.array([0.3, -0.2, -1.0])
+    nrm /= np.linalg.norm(nrm)
+    cA = -1.5                                      # plane nrm . X = c, about 1.5 m away
+    dA = _plane_depth(cam, nrm, cA)
+    dB = _plane_depth(cam, nrm, cA - 0.5)          # 0.5 m further along the normal
+    dS = _plane_depth(cam, nrm, cA - 0.05)         # 0.05 m further
+    depth = dA.copy()
+    depth[:, 20:] = dB[:, 20:]
+    depth[22:, :20] = dS[22:, :20]
+    mask = np.ones((H, W), np.uint8)
+    holes = [(10, 5), (20, 30)]                    # (v, u)
+    for v, u in holes:
+        mask[v, u] = 0
+        depth[v, u] = 0.0
+    assert np.all(np.abs(depth[:, 20] - depth[:, 19]) > 0.1)
+    assert np.all(np.abs(depth[22, :20] - depth[21, :20]) < 0.1)
+    expect = np.ones((H, W), np.uint8)
+    expect[0, :] = expect[-1, :] = 0
+    expect[:, 0] = expect[:, -1] = 0
+    expect[:, 19:21] = 0                           # a neighbour across the 0.5 m step
+    for v, u in holes:
+        for dv, du in ((0, 0), (1, 0), (-1, 0), (0, 1), (0, -1)):
+            expect[v + dv, u + du] = 0
+    n_out, nmask = orc.normals_of(cam, depth, mask, 0.1)
+    np.testing.assert_array_equal(nmask, expect)
+    # the camera (origin) lies where nrm . X - c has the sign of -c, so the
+    # plane normal pointing to the camera's side is sign(-c) nrm
+    facing = nrm if cA < 0 else -nrm
+    flat = expect.astype(bool).copy()
+    flat[20:24, :20] = False                       # stencils straddling the small step
+    err = np.abs(n_out[flat] - facing).max()
+    assert err < 1e-9, err
+    # facing the camera: the normal opposes the back-projected point
+    rx = (np.arange(W) + 0.5 - cam.cx) / cam.fx
+    ry = (np.arange(H) + 0.5 - cam.cy) / cam.fy
+    Pt = depth[..., None] * np.stack([*np.meshgrid(rx, ry), np.ones((H, W))], -1)
+    assert np.all(np.einsum("ij,ij->i", n_out[flat], Pt[flat]) < 0)
+    assert np.all(n_out[~expect.astype(bool)] == 0.0)
