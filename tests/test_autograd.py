@@ -67,10 +67,24 @@ def test_autograd_matches_oracle_adjoint():
         gc = 2 * wc * mk[..., None] * (r["rgb"] - oc[i])
         gmi, gpi = orc.render_vjp(og, m32, ocm, pose, gd, gc)
         gm_ref += gmi
-        assert np.linalg.norm(gp[i] - gpi) <= 1e-4 * np.linalg.norm(gpi), (gp[i], gpi)
+        # each pose component against its accumulation scale: the sum over
+        # rays and rows of |J row| |upstream gradient| (oracle rows; an
+        # observation equal to the render keeps every row)
+        full = orc.render_jacobian(og, m32, ocm, pose, np.where(mk, r["depth"], 0.0), r["rgb"], orc.Params(),
+                                   want_J=True)
+        up = np.concatenate([gd[..., None], gc], -1)
+        scale = float(np.sum(np.linalg.norm(full["J"], axis=-1) * np.abs(up)))
+        ep = np.abs(gp[i] - gpi) / scale
+        print(f"[autograd pose {i}] max error / accumulation scale {ep.max():.2e}", flush=True)
+        assert ep.max() <= 1e-5, (gp[i], gpi, scale)
     nz = (gm != 0) | (gm_ref != 0)
     assert nz.sum() > 1000
-    assert np.linalg.norm(gm[nz] - gm_ref[nz]) <= 1e-4 * np.linalg.norm(gm_ref[nz])
+    # every voxel and channel, relative, with a floor of 1e-3 of the channel's
+    # largest gradient for entries that cancel
+    floor = 1e-3 * np.abs(gm_ref).reshape(4, -1).max(1)[:, None, None, None]
+    em = np.abs(gm - gm_ref) / np.maximum(np.abs(gm_ref), floor)
+    print(f"[autograd map] {int(nz.sum())} entries, max scaled error {em[nz].max():.2e}", flush=True)
+    assert em[nz].max() <= 1e-4, em[nz].max()
 
 
 @pytest.mark.gpu

@@ -6,8 +6,6 @@ association) are compared bit for bit; the oracle takes them with the same
 single-precision recipe as the kernels.  Values are compared with the
 tolerances in gpu_util.
 """
-import math
-
 import numpy as np
 import pytest
 import torch
@@ -81,12 +79,13 @@ def _render_compare(c, mean, var, pose, dtype, normals=True, label=""):
     rgb = out["rgb"][0].cpu().numpy()
     assert np.all(rgb_close(rgb[v], ref["rgb"][v])), np.max(np.abs(rgb[v] - ref["rgb"][v]))
     if normals:
+        # the normals kernel against the oracle's normals of the same image
+        n_ref, m_ref = orc.normals_of(oc, d.astype(np.float64), mk, 0.1)
         nm = out["nmask"][0].cpu().numpy()
-        agree = nm == ref["nmask"]
-        assert agree.mean() > 0.999, (agree.mean(), label)
-        both = (nm == 1) & (ref["nmask"] == 1)
+        np.testing.assert_array_equal(nm, m_ref, err_msg=f"normal mask {label}")
+        both = nm == 1
         nrm = out["normals"][0].cpu().numpy()
-        assert np.max(np.abs(nrm[both] - ref["normals"][both])) < 1e-3
+        assert np.max(np.abs(nrm[both] - n_ref[both])) <= 1e-4
     return out, ref
 
 
@@ -145,92 +144,6 @@ def test_render_full_size_frame(case2, dtype):
     tr = c["traj"]
     for i in (0, 3):
         _render_compare(c, mean, var, synth.pose7(tr.t[i], tr.q[i]), dtype, label=f"frame {i}")
-
-
-# ---------------------------------------------------------------------------
-def _row_err(J, R):
-    """Per-row error of 4x6 Jacobians relative to the row's norm (rows whose
-    norm is tiny are compared against 1e-6)."""
-    num = np.max(np.abs(J - R), axis=-1)
-    den = np.maximum(np.linalg.norm(R, axis=-1), 1e-6)
-    return num / den
-
-
-def _neq_close(a, b, rtol=1e-4):
-    Ha, ga, ca, na = orc.neq_unpack(a)
-    Hb, gb, cb, nb = orc.neq_unpack(b)
-    assert abs(na - nb) <= max(2, 1e-3 * nb), (na, nb)
-    assert np.linalg.norm(Ha - Hb) <= rtol * np.linalg.norm(Hb), np.linalg.norm(Ha - Hb) / np.linalg.norm(Hb)
-    # g can be small at the optimum: compare against the scale sqrt(|H| cost)
-    gs = max(np.linalg.norm(gb), 1e-3 * math.sqrt(np.linalg.norm(Hb) * max(cb, 1e-12)))
-    assert np.linalg.norm(ga - gb) <= 1e-3 * gs, (np.linalg.norm(ga - gb), gs)
-    assert abs(ca - cb) <= 1e-3 * max(cb, 1e-9)
-
-
-@pytest.mark.parametrize("dtype", [0, 1])
-def test_render_jacobian(case1, dtype):
-    banner(f"render_jacobian 64^3 dtype={dtype}")
-    c, mean, var = case1
-    g = grid_of(c["scene"], dtype)
-    cam = cam_of(c["cam"])
-    vm = gpu_map(g, mean, var)
-    rng = np.random.default_rng(3)
-    od, oc = synth.raycast(c["scene"], c["cam"], c["t_gt"], c["q_gt"], rng, 0.01, 0.02)
-    od = od.astype(np.float32); oc = oc.astype(np.float32)
-    pose = synth.pose7(c["t_init"], c["q_init"])
-    out = P().render_jacobian(g, vm, cam, P().poses_tensor(pose), t(od)[None], t(oc)[None], P().Weights.make(),
-                              want_J=True, want_resid=True)
-    torch.cuda.synchronize()
-    ref = orc.render_jacobian(orc.grid_from_scene(c["scene"]), oracle_map_values(mean, dtype),
-                              orc.cam_from(c["cam"]), pose, od, oc, orc.Params(), want_J=True)
-    np.testing.assert_array_equal(out["mask"][0].cpu().numpy(), ref["mask"])
-    rm = out["rowmask"][0].cpu().numpy()
-    assert np.mean(rm != ref["rowmask"]) < 1e-3
-    same = (rm == ref["rowmask"]) & (rm > 0)
-    J = out["J"][0].cpu().numpy()
-    err = _row_err(J[same], ref["J"][same])
-    assert np.quantile(err, 0.999) < 1e-4 and err.max() < 1e-2, (np.quantile(err, 0.999), err.max())
-    r = out["resid"][0].cpu().numpy()
-    assert np.max(np.abs(r[same] - ref["resid"][same])) < 1e-6
-    _neq_close(out["neq"][0].cpu().numpy(), ref["neq"])
-
-
-def _anchor(c, mean, pose):
-    og = orc.grid_from_scene(c["scene"])
-    a = orc.render(og, mean, orc.cam_from(c["cam"]), pose, normals=True)
-    # the GPU gets the float32 anchor; the oracle the same values in float64
-    a32 = {k: (v.astype(np.float32) if v.dtype == np.float64 else v) for k, v in a.items()}
-    a64 = {k: (v.astype(np.float64) if v.dtype == np.float32 else v) for k, v in a32.items()}
-    return a32, a64
-
-
-def test_track_p2(case1):
-    banner("track_p2 80x60")
-    c, mean, var = case1
-    prev = synth.pose7(c["t_gt"], c["q_gt"])
-    a32, a64 = _anchor(c, mean, prev)
-    rng = np.random.default_rng(4)
-    tt, qq = synth.perturb_pose(rng, c["t_gt"], c["q_gt"], 0.03, 0.03)
-    od, oc = synth.raycast(c["scene"], c["cam"], tt, qq, rng, 0.01, 0.02)
-    od = od.astype(np.float32); oc = oc.astype(np.float32)
-    cur = synth.pose7(*synth.perturb_pose(rng, tt, qq, 0.01, 0.01))
-    cam = cam_of(c["cam"])
-    anchor = {k: t(v, torch.uint8 if v.dtype == np.uint8 else torch.float32) for k, v in a32.items()
-              if k in ("depth", "rgb", "mask", "normals", "nmask")}
-    out = P().track_p2(cam, P().poses_tensor(cur), P().poses_tensor(prev), t(od), t(oc), anchor,
-                       P().Weights.make(), want_J=True, want_resid=True)
-    torch.cuda.synchronize()
-    ref = orc.track_p2(orc.cam_from(c["cam"]), cur, prev, od, oc, a64, orc.Params(), want_J=True)
-    rm = out["rowmask"].cpu().numpy()
-    assert np.mean(rm != ref["rowmask"]) < 2e-3
-    same = (rm == ref["rowmask"]) & (rm > 0)
-    assert same.sum() > 1000
-    r = out["resid"].cpu().numpy()
-    assert np.max(np.abs(r[same] - ref["resid"][same])) < 1e-6
-    J = out["J"].cpu().numpy()
-    err = _row_err(J[same], ref["J"][same])
-    assert np.quantile(err, 0.999) < 1e-4 and err.max() < 1e-2, (np.quantile(err, 0.999), err.max())
-    _neq_close(out["neq"][0].cpu().numpy(), ref["neq"])
 
 
 # ---------------------------------------------------------------------------
@@ -340,30 +253,6 @@ def test_free_space_bits_follow_updates(case2, dtype):
     mv = m.cpu().numpy().astype(np.float64)
     ref = orc.render(orc.grid_from_scene(c["scene"]), mv, orc.cam_from(c["cam"]), synth.pose7(tr.t[3], tr.q[3]))
     np.testing.assert_array_equal(a["hit_k"][1].cpu().numpy(), ref["hit_k"])
-
-
-# ---------------------------------------------------------------------------
-def test_render_vjp(case1):
-    banner("render_vjp 64^3")
-    c, mean, var = case1
-    g = grid_of(c["scene"])
-    cam = cam_of(c["cam"])
-    vm = gpu_map(g, mean, var)
-    pose = synth.pose7(c["t_init"], c["q_init"])
-    pt = P().poses_tensor(pose)
-    fwd = P().render(g, vm, cam, pt, hit_k=True)
-    rng = np.random.default_rng(6)
-    H, W = cam.height, cam.width
-    gd = rng.normal(size=(1, H, W)).astype(np.float32)
-    gc = rng.normal(size=(1, H, W, 3)).astype(np.float32)
-    gm, gp = P().render_vjp(g, vm, cam, pt, fwd["hit_k"], t(gd), t(gc))
-    gm_dense = P().bricks_to_dense(g.n, gm).cpu().numpy()
-    torch.cuda.synchronize()
-    rgm, rgp = orc.render_vjp(orc.grid_from_scene(c["scene"]), mean.astype(np.float32).astype(np.float64),
-                              orc.cam_from(c["cam"]), pose, gd[0], gc[0])
-    assert np.linalg.norm(gp[0].cpu().numpy() - rgp) <= 1e-4 * np.linalg.norm(rgp)
-    nz = (np.abs(rgm) > 0) | (np.abs(gm_dense) > 0)
-    assert np.linalg.norm(gm_dense[nz] - rgm[nz]) <= 1e-5 * np.linalg.norm(rgm[nz])
 
 
 # ---------------------------------------------------------------------------
