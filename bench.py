@@ -7,18 +7,23 @@ streams.  Stream i (seed 1000 + i) draws its image size from {160x120,
 (K = N/2 samples per ray in [0.1, 7.5] m), has its own room and UAV-like
 trajectory, a BF16 map resident in HBM, and runs the full filter step
 (predict/split, 3 Gauss-Newton iterations of the prediction-to-observation
-objective, Laplace + combine, map update, anchor render).  One step is one
-frame of one stream.  ``value`` is the aggregate steps/s of the whole job
-with every frame already resident in HBM at the start (backlog: each stream
-always has its next frame ready), from admission of the first stream to the
-completion of the last step.  ``p50_ms``/``p99_ms`` come from a second run
-of the same streams with frames arriving at 10 Hz (+ exponential jitter),
+objective, Laplace + combine, map update, anchor render).
+
+One bench step is one frame of every stream: 16 full filter steps, batched.
+The streams are admitted and take their first frame (map update and anchor
+only) and ``--warmup`` W further frames untimed; then exactly ``--steps`` K
+steps are timed, bracketed by device synchronisation, with every frame
+already resident in HBM (backlog: each stream always has its next frame
+ready).  ``value`` is filter steps/s = 16 K / wall.  ``p50_ms``/``p99_ms``
+come from a second run with frames arriving at 10 Hz (+ exponential jitter),
 measured from arrival to host-visible completion.
 
-Also reported: the same mix under an artificial 4 GB admission budget, the
-plain single-stream FP32 path (256^3, 320x240, K = 128, one HIP graph per
-step), render+Jacobian Mrays/s, the roofline of the map update, and the FP64
-CPU oracle timed on a bounded sample of the serving mix.
+Also reported: the same mix with FP32 maps run one stream after another (the
+plain single-stream path, the serving baseline), under an artificial
+admission budget, on brick-pool maps smaller than the grids; single-stream
+figures (render+Jacobian Mrays/s, adjoint, map update warm and cold, the
+single-frame workload, the 384^3 BF16 stream); the roofline of the dominant
+stage; and the FP64 CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -101,13 +106,76 @@ def run_mix(specs, frames, n_frames, realtime, budget=None, n_hip_streams=4, bat
     return loop, wall
 
 
-def stage_rooflines(loop, specs, fps):
-    """Per-stage share of the timed run and, for the three data-parallel
-    stages, achieved throughput against the roofline that bounds them:
-    map update HBM (algorithmic bytes: updated voxels x 32 B for BF16 / 64 B
-    for FP32 plus 16 B per frame pixel), render and tracking as stated in the
-    design notes (render: K samples x 40 FLOP per ray plus 200 FLOP of
-    shading, the emission's definition; tracking: 80 B per pixel)."""
+def phased_mix(specs, frames, W, K, P, torch, n_hip_streams=4, batched=True, timer=False):
+    """Admit every stream, run its first frame and W further frames untimed,
+    then time exactly K frames of every stream in backlog mode.  Returns the
+    loop, the timed wall time and each stream's voxel updates in the window."""
+    import dataclasses
+    from paper_2212_02988_amd.serving import ServingLoop
+    n_total = 1 + W + K
+    # one frame more than is fed, so no stream retires inside the timed window
+    sp = [dataclasses.replace(s, n_frames=n_total + 1) for s in specs]
+    loop = ServingLoop(n_hip_streams=n_hip_streams, batched=batched)
+    for s in sp:
+        loop.open_stream(s)
+    assert len(loop.agents) == len(sp), "the mix must fit the device"
+
+    def feed(a, b):
+        for s in sp:
+            fr = frames[s.stream_id]
+            for k in range(a, b):
+                loop.push_frame(s.stream_id, 0.0, fr["D"][k], fr["C"][k], None if k == 0 else fr["U"][k - 1], k)
+
+    def drive(target):
+        while loop.completed < target:
+            loop.poll()
+            loop.tick()
+
+    feed(0, 1 + W)
+    drive(len(sp) * (1 + W))
+    torch.cuda.synchronize()
+    upd0 = {sid: int(ag.filter.state().n_updated_total) for sid, ag in loop.agents.items()}
+    sub0, batches0 = loop.host_submit_s, loop.batches
+    if timer:
+        P.stage_timer_arm(1 << 14)
+    t0 = time.perf_counter()
+    feed(1 + W, n_total)
+    drive(len(sp) * n_total)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if timer:
+        loop.stage_times = P.stage_timer_read()
+    loop.window = dict(updated={sid: int(ag.filter.state().n_updated_total) - upd0[sid]
+                                for sid, ag in loop.agents.items()},
+                       host_submit_s=loop.host_submit_s - sub0, batches=loop.batches - batches0)
+    return loop, wall
+
+
+def marched_samples(loop, specs, P):
+    """Samples the emission evaluates per frame of each stream, up to and
+    including the first crossing (all K where a ray has none), and its valid
+    rays: from a render of each stream's map at its current pose."""
+    import torch
+    out = {}
+    for s in specs:
+        ag = loop.agents[s.stream_id]
+        st = ag.filter.state()
+        pose = P.poses_tensor(list(st.pose.t) + list(st.pose.q))
+        r = P.render(s.grid, ag.filter.map, s.cam, pose, hit_k=True)
+        hk = r["hit_k"][0].long()
+        K = s.cam.n_samples
+        n_eval = int(torch.where(hk < 0, torch.full_like(hk, K), torch.clamp(hk + 1, max=K)).sum().item())
+        out[s.stream_id] = (n_eval, int(r["mask"].sum().item()))
+    return out
+
+
+def stage_rooflines(loop, specs, K, samples):
+    """Per-stage share of the timed window and, for the three data-parallel
+    stages, achieved throughput against the roofline that bounds them: map
+    update HBM (algorithmic bytes: updated voxels x 32 B for BF16 / 64 B for
+    FP32 plus 16 B per frame pixel), render FP32 vector peak (40 operations
+    per evaluated sample up to the first crossing plus 200 of shading per
+    valid ray), tracking HBM (80 B per pixel)."""
     from paper_2212_02988_amd import prism as P
     times = loop.stage_times
     total_ms = sum(v[0] for v in times.values())
@@ -116,15 +184,12 @@ def stage_rooflines(loop, specs, fps):
         if n:
             out[name] = {"ms": round(ms, 3), "launches": int(n), "avg_us": round(1e3 * ms / n, 2),
                          "share": round(ms / total_ms, 4)}
-    pix = sum(s.cam.width * s.cam.height * fps for s in specs)
-    ray_flop = sum(s.cam.width * s.cam.height * (s.cam.n_samples * 40 + 200) * fps for s in specs)
-    trk_pix = sum(s.cam.width * s.cam.height * (s.params.n_gn + 1) * (fps - 1) for s in specs)
-    upd_bytes = 0
-    for s in specs:
-        tot = loop.totals.get(s.stream_id)
-        per = 32 if s.grid.dtype == P.PRISM_BF16 else 64
-        upd_bytes += (tot["n_updated_total"] if tot else 0) * per
-    upd_bytes += 16 * pix
+    pix = sum(s.cam.width * s.cam.height * K for s in specs)
+    ray_flop = sum((40 * samples[s.stream_id][0] + 200 * samples[s.stream_id][1]) * K for s in specs)
+    ray_flop_all_k = sum(s.cam.width * s.cam.height * (s.cam.n_samples * 40 + 200) * K for s in specs)
+    trk_pix = sum(s.cam.width * s.cam.height * (s.params.n_gn + 1) * K for s in specs)
+    upd_bytes = sum(loop.window["updated"][s.stream_id] * (32 if s.grid.dtype == P.PRISM_BF16 else 64)
+                    for s in specs) + 16 * pix
     roof = {}
     if "map_update" in out:
         ms, n = times["map_update"]
@@ -134,11 +199,16 @@ def stage_rooflines(loop, specs, fps):
     if "render" in out:
         ms, n = times["render"]
         a = ray_flop / (ms * 1e-3) / 1e12
-        roof["render"] = {"bound": "alu", "achieved": round(a, 2), "peak": round(FP32_OPS_PEAK_T, 2),
-                          "unit": "TFLOP/s", "frac": round(a / FP32_OPS_PEAK_T, 4),
+        roof["render"] = {"bound": "alu", "achieved": round(a, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                          "frac": round(a / FP32_PEAK_TFLOPS, 4),
                           "algorithmic_flop_per_launch": int(ray_flop / n),
-                          "peak_note": "single-precision ops without fusion or packing (256 CUs x 64 lanes x 2.4 GHz)",
-                          "frac_of_packed_fma_vector_peak": round(a / FP32_PEAK_TFLOPS, 4)}
+                          "flop_note": "40 per sample evaluated up to the first crossing (all K without one) + 200 "
+                                       "of shading per valid ray; samples from a render of each stream's map",
+                          "samples_per_ray": round(sum(v[0] for v in samples.values()) /
+                                                   sum(s.cam.width * s.cam.height for s in specs), 2),
+                          "frac_of_unfused_issue_rate": round(a / FP32_OPS_PEAK_T, 4),
+                          "frac_all_k_samples_counted": round(ray_flop_all_k / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
+                                                              4)}
     if "track" in out:
         ms, n = times["track"]
         a = 80 * trk_pix / (ms * 1e-3) / 1e9
@@ -148,6 +218,59 @@ def stage_rooflines(loop, specs, fps):
         out[k].update(roofline=v)
     dom = max(out, key=lambda k: out[k]["ms"])
     return out, dom, roof.get(dom)
+
+
+def stream_steps(spec, fr, W, K, P, torch):
+    """One stream on its own, as the plain path runs it: frames copied into
+    two input slots, each steady-state step replayed from the slot's HIP
+    graph, one stream.  First frame and W steps untimed, then K steps timed
+    with events.  Returns (ms per step, per-step ms)."""
+    H, Wd = spec.cam.height, spec.cam.width
+    hs = torch.cuda.Stream()
+    with torch.cuda.stream(hs):
+        f = P.Filter(spec.grid, spec.cam, spec.params)
+        f.map.init(stream=hs)
+        f.reset(spec.x0, spec.P0, stream=hs)
+        f.set_slots([(torch.empty((H, Wd), dtype=torch.float32, device="cuda"),
+                      torch.empty((H, Wd, 3), dtype=torch.float32, device="cuda"),
+                      torch.zeros(6, dtype=torch.float64, device="cuda")) for _ in range(2)])
+
+    def submit(k):
+        while f.submit(fr["D"][k], fr["C"][k], None if k == 0 else fr["U"][k - 1], stream=hs) is None:
+            pass
+    for k in range(1 + W):
+        submit(k)
+    hs.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    evs[0].record(hs)
+    for j in range(K):
+        submit(1 + W + j)
+        evs[j + 1].record(hs)
+    hs.synchronize()
+    per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(K)])
+    ms = evs[0].elapsed_time(evs[-1]) / K
+    del f
+    return ms, per
+
+
+def fp32_sequential(specs, frames, W, K, P, torch):
+    """The serving baseline: the same mix with FP32 maps, streams run one
+    after another on the plain single-stream path."""
+    import dataclasses
+    total_ms, per_all = 0.0, []
+    for s in specs:
+        g = s.grid
+        grid = P.Grid.make(g.n, g.voxel, tuple(g.origin), dtype=P.PRISM_F32, occ_out=g.occ_out, rgb_out=g.rgb_out)
+        ms, per = stream_steps(dataclasses.replace(s, grid=grid), frames[s.stream_id], W, K, P, torch)
+        total_ms += ms * K
+        per_all.append(per)
+        torch.cuda.empty_cache()
+    per_all = np.concatenate(per_all)
+    n = len(specs) * K
+    return {"steps_per_s": round(n / (total_ms * 1e-3), 1), "steps": n, "wall_ms": round(total_ms, 3),
+            "p50_ms": round(float(np.percentile(per_all, 50)), 4), "p99_ms": round(float(np.percentile(per_all, 99)), 4),
+            "workload": "the serving mix with FP32 maps, one stream at a time (frames staged into input slots, "
+                        "each step replayed from a HIP graph), first frame and warm-up untimed"}
 
 
 # ---------------------------------------------------------------------------
@@ -273,6 +396,124 @@ def single_stream(P, torch, steps, warmup):
         pos_err=pos_err, mrays_1=rays / (ms_rj1 * 1e-3) / 1e6, mrays_8=8 * rays / (ms_rj8 * 1e-3) / 1e6,
         us_rj1=ms_rj1 * 1e3, us_rj8=ms_rj8 * 1e3, us_render=ms_r * 1e3, us_mu=ms_mu * 1e3,
         mu_bytes=mu_bytes, mu_gbs=mu_gbs, n_upd=n_upd)
+
+
+# ---------------------------------------------------------------------------
+# map update, cold: the working set exceeds the 256 MB Infinity Cache
+# ---------------------------------------------------------------------------
+def map_update_cold(P, torch, n_maps=8, reps=64):
+    """The map-update call on 256^3 FP32 maps and 320x240 frames, rotating
+    over n_maps separate maps, each updated with a different frame of the
+    trajectory (frames 35 apart), so consecutive calls share no map data and
+    the rotation's working set (n_maps x ~85 MB of updated voxels) exceeds
+    the 256 MB MALL plus the L2s.  Call time from events around all calls;
+    update-kernel time from the library's stage events around each update
+    kernel."""
+    import synth
+    N, Wd, Ht, K = 256, 320, 240, 128
+    case = synth.trajectory_case(seed=1, n=N, width=Wd, height=Ht, n_samples=K, n_frames=300, frames=False)
+    tr, scene, cm = case["traj"], case["scene"], case["cam"]
+    fis = [35 * j for j in range(n_maps)]
+    D, C = synth.raycast_torch(scene, cm, tr.t[fis], tr.q[fis], 1, 0.01, 0.02)
+    grid = P.Grid.make(N, scene.voxel, tuple(float(v) for v in scene.origin))
+    cam = P.Camera.make(cm.width, cm.height, cm.fx, cm.fy, cm.cx, cm.cy, cm.d_near, cm.d_far, cm.n_samples)
+    maps = [P.VoxelMap(grid).init() for _ in range(n_maps)]
+    pts = [P.poses_tensor(np.concatenate([tr.t[i], tr.q[i]])) for i in fis]
+    nup = [torch.empty(1, dtype=torch.int64, device="cuda") for _ in range(n_maps)]
+    trunc = 4 * grid.voxel
+    for j in range(n_maps):                      # first touch of every map (untimed)
+        P.map_update(grid, maps[j], cam, pts[j], D[j], C[j], trunc, 1.0, n_updated=nup[j])
+    torch.cuda.synchronize()
+    counts = [int(x.item()) for x in nup]
+    P.stage_timer_arm(reps)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for r in range(reps):
+        j = r % n_maps
+        P.map_update(grid, maps[j], cam, pts[j], D[j], C[j], trunc, 1.0, n_updated=nup[j])
+    e1.record()
+    torch.cuda.synchronize()
+    st = P.stage_timer_read()
+    ms_call = e0.elapsed_time(e1) / reps
+    k_ms, k_n = st["map_update"]
+    ms_kernel = k_ms / max(k_n, 1)
+    n_upd = float(np.mean(counts))
+    nbytes = n_upd * 64 + Wd * Ht * 16
+    out = {"workload": f"prism_map_update, 256^3 FP32 maps, 320x240, rotating over {n_maps} maps "
+                       f"({n_maps} x {n_upd * 64 / 1e6:.0f} MB of updated voxels per rotation)",
+           "updated_voxels": int(n_upd), "algorithmic_bytes": int(nbytes),
+           "call_us": round(ms_call * 1e3, 2), "kernel_us": round(ms_kernel * 1e3, 2),
+           "call_gbs": round(nbytes / (ms_call * 1e-3) / 1e9, 1), "kernel_gbs": round(nbytes / (ms_kernel * 1e-3) / 1e9, 1)}
+    out["call_frac"] = round(out["call_gbs"] / HBM_PEAK_GBS, 4)
+    out["kernel_frac"] = round(out["kernel_gbs"] / HBM_PEAK_GBS, 4)
+    log(f"map update cold ({n_maps} maps): call {out['call_us']} us ({out['call_gbs']} GB/s), kernel "
+        f"{out['kernel_us']} us ({out['kernel_gbs']} GB/s), {int(n_upd)} voxels")
+    del maps
+    torch.cuda.empty_cache()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# the single-frame workload and the 384^3 BF16 stream
+# ---------------------------------------------------------------------------
+def single_frame_gpu(P, torch, reps=200):
+    """64^3 (4 cm), 80x60, K = 32, FP32, render-through objective with one
+    Gauss-Newton iteration: the full step (predict, render+Jacobian, GN,
+    render+Jacobian at the step, Laplace, map update, anchor) on the oracle's
+    render at the true pose, replayed from one HIP graph on a fixed frame."""
+    import oracle as orc
+    import synth
+    c = synth.single_frame_case(0)
+    scene, cm = c["scene"], c["cam"]
+    mean, _ = synth.gt_map(scene)
+    obs = orc.render(orc.grid_from_scene(scene), mean, orc.cam_from(cm), synth.pose7(c["t_gt"], c["q_gt"]))
+    D = torch.tensor(obs["depth"], dtype=torch.float32, device="cuda")
+    C = torch.tensor(obs["rgb"], dtype=torch.float32, device="cuda")
+    U = torch.zeros(6, dtype=torch.float64, device="cuda")
+    grid = P.Grid.make(scene.n, scene.voxel, tuple(float(v) for v in scene.origin))
+    cam = P.Camera.make(cm.width, cm.height, cm.fx, cm.fy, cm.cx, cm.cy, cm.d_near, cm.d_far, cm.n_samples)
+    hs = torch.cuda.Stream()
+    f = P.Filter(grid, cam, P.FilterParams(n_gn=1, objective=P.OBJ_P1))
+    with torch.cuda.stream(hs):
+        f.map.init(stream=hs)
+        f.reset(np.concatenate([c["t_init"], c["q_init"], np.zeros(6)]), np.diag([0.05 ** 2] * 3 + [0.02 ** 2] * 3 +
+                                                                             [1e-4] * 6), hs)
+        f.step(D, C, None, stream=hs)
+        for _ in range(10):
+            f.step_graph(D, C, U, hs)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(hs)
+        for _ in range(reps):
+            f.step_graph(D, C, U, hs)
+        e1.record(hs)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) / reps * 1e3
+    log(f"single-frame workload (64^3, 80x60, P1, 1 GN): {us:.1f} us per full step")
+    return {"workload": "64^3 (4 cm), 80x60, K = 32, FP32, render-through objective, 1 Gauss-Newton iteration, "
+                        "full filter step replayed from a HIP graph", "us_per_step": round(us, 2)}
+
+
+def bf16_stream_gpu(P, torch, W=5, K=40):
+    """The mixed-precision workload on one stream: 384^3 BF16 map (1.67 cm),
+    640x480, K = 192, P2 with 3 Gauss-Newton iterations, plain path."""
+    import synth
+    from paper_2212_02988_amd.serving import StreamSpec
+    n_fr = 1 + W + K
+    case = synth.trajectory_case(seed=4, n=384, width=640, height=480, n_samples=192, n_frames=n_fr, frames=False)
+    tr, scene, cm = case["traj"], case["scene"], case["cam"]
+    D, C = synth.raycast_torch(scene, cm, tr.t, tr.q, 4, 0.01, 0.02)
+    U = torch.from_numpy(np.concatenate([tr.u, tr.u[-1:]], 0)).to("cuda")
+    grid = P.Grid.make(384, scene.voxel, tuple(float(v) for v in scene.origin), dtype=P.PRISM_BF16)
+    cam = P.Camera.make(cm.width, cm.height, cm.fx, cm.fy, cm.cx, cm.cy, cm.d_near, cm.d_far, cm.n_samples)
+    spec = StreamSpec(0, grid, cam, P.FilterParams(n_gn=3, objective=P.OBJ_P2),
+                      np.concatenate([tr.t[0], tr.q[0], tr.v[0], tr.w[0]]), np.diag([1e-6] * 6 + [1e-4] * 6), n_fr)
+    ms, per = stream_steps(spec, dict(D=D, C=C, U=U), W, K, P, torch)
+    log(f"384^3 BF16 640x480 stream: {ms:.3f} ms per step")
+    return {"workload": "384^3 BF16 (1.67 cm), 640x480, K = 192, P2 x 3 GN, one stream, plain path",
+            "ms_per_step": round(ms, 4), "steps_per_s": round(1e3 / ms, 1),
+            "p50_ms": round(float(np.percentile(per, 50)), 4), "p99_ms": round(float(np.percentile(per, 99)), 4)}
 
 
 # ---------------------------------------------------------------------------
@@ -511,7 +752,44 @@ def cpu_baseline(frames, specs, budget_s):
     cores = min(cores, os.cpu_count() or cores)
     return {"value": round(steps / spent, 4), "unit": "steps/s", "cores": cores, "kind": "oracle",
             "sample": f"{steps} FP64 oracle filter steps over the 16 streams of the serving mix (the first frames of "
-                      f"each stream, about {per_stream:.1f} s per stream), {spent:.1f} s"}
+                      f"each stream, about {per_stream:.1f} s per stream), {spent:.1f} s",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_configs(frames, runs=3):
+    """The oracle on the single-stream workloads (configs 1-4 of the
+    benchmark: single frame, 256^3 trajectory, adjoint, 384^3 BF16
+    trajectory), with all host threads and with one, median of `runs`; each
+    run in its own process so that OpenMP starts with that many threads."""
+    import subprocess
+    all_threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    out = {"cpu_model": cpu_model(), "nproc": os.cpu_count(), "runs": runs}
+    for cfg in (1, 2, 3, 4):
+        for th in (all_threads, 1):
+            res = []
+            for _ in range(runs):
+                env = dict(os.environ, OMP_NUM_THREADS=str(th))
+                r = subprocess.run([sys.executable, "-m", "oracle.timing", "--config", str(cfg), "--frames",
+                                    str(frames)], cwd=ROOT, env=env, capture_output=True, text=True, timeout=1800)
+                if r.returncode != 0:
+                    raise RuntimeError(f"oracle timing config {cfg} failed:\n{r.stderr[-2000:]}")
+                res.append(json.loads(r.stdout.strip().splitlines()[-1]))
+            med = sorted(res, key=lambda d: d["seconds"])[len(res) // 2]
+            med["seconds_all_runs"] = [round(d["seconds"], 4) for d in res]
+            out[f"config{cfg}_{'1core' if th == 1 else f'{th}threads'}"] = med
+            log(f"oracle config {cfg} on {th} threads: median {med['seconds']:.3f} s")
+    return out
 
 
 STAGE_KERNELS = {"render": "k_render_batch", "track": "k_track_p2_batch", "map_update": "k_map_update_batch",
@@ -563,26 +841,32 @@ def roofline_obj(dominant, roof, breakdown):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1600, help="timed filter steps over all streams (backlog run)")
-    ap.add_argument("--warmup", type=int, default=48, help="untimed steps over all streams before the timed run")
+    ap.add_argument("--steps", type=int, default=200,
+                    help="timed bench steps; one step = one frame of every stream (16 filter steps)")
+    ap.add_argument("--warmup", type=int, default=20, help="untimed steps after each stream's first frame")
     ap.add_argument("--streams", type=int, default=16)
     ap.add_argument("--rt-frames", type=int, default=100, help="frames per stream of the 10 Hz real-time run")
-    ap.add_argument("--budget-gb", type=float, default=1.5, help="artificial admission budget of the third run")
+    ap.add_argument("--budget-gb", type=float, default=1.5, help="artificial admission budget of the budget run")
     ap.add_argument("--single-steps", type=int, default=100)
     ap.add_argument("--hip-streams", type=int, default=4, help="HIP streams the serving loop spreads agents over")
     ap.add_argument("--per-stream", action="store_true",
                     help="serve without batching (each agent's step its own graph launch)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=16.0)
+    ap.add_argument("--cpu-configs", action="store_true",
+                    help="also time the oracle on configs 1-4 (all threads and one, median of 3; minutes)")
+    ap.add_argument("--cpu-config-frames", type=int, default=20)
     ap.add_argument("--calib", action="store_true", help="also run two 256 MiB device copies (counter calibration)")
-    ap.add_argument("--pool-frac", type=float, default=1.0,
-                    help="brick-pool run: fraction of each grid's bricks the pool holds")
+    ap.add_argument("--quick", action="store_true", help="serving figures only (for profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported (agent streams are independent "
               "and would be placed whole on GPUs by free memory; see the sharding notes in the design document)",
               file=sys.stderr)
         sys.exit(2)
+    W, K = args.warmup, args.steps
+    if W < 0 or K < 1:
+        raise SystemExit("need --steps >= 1 and --warmup >= 0")
 
     import torch
     from paper_2212_02988_amd import prism as P
@@ -590,12 +874,9 @@ def main():
 
     torch.cuda.set_device(0)
     ns = args.streams
-    fps = max(2, args.steps // ns)                  # frames per stream of the timed run
-    steps = fps * ns
-    wfps = max(2, args.warmup // ns)
-    nfr = max(fps, args.rt_frames, wfps)
+    nfr = max(1 + W + K, args.rt_frames)
     if nfr > 300:
-        raise SystemExit("at most 300 frames per stream")
+        raise SystemExit("at most 300 frames per stream: need 1 + warmup + steps <= 300")
     t0 = time.time()
     specs, frames = build_mix(ns, nfr, P, torch)
     mix_desc = [f"{s.cam.width}x{s.cam.height}/{s.grid.n}^3" for s in specs]
@@ -603,65 +884,121 @@ def main():
     log(f"{ns} streams ({', '.join(mix_desc)}), {nfr} frames each, generated in {time.time() - t0:.1f}s; "
         f"resident footprint {foot / 2**30:.2f} GiB")
 
-    # warm-up pass (fresh filters), then the timed backlog run
+    # headline: W warm-up steps after each stream's first frame, then exactly K timed steps
     mk = dict(n_hip_streams=args.hip_streams, batched=not args.per_stream)
-    run_mix(specs, frames, wfps, realtime=False, **mk)
-    loop, wall = run_mix(specs, frames, fps, realtime=False, **mk)
-    assert loop.completed == steps
-    value = steps / wall
-    log(f"backlog run: {steps} steps in {wall:.3f} s = {value:.0f} steps/s, max concurrent {loop.max_concurrent}; "
-        f"host {1e6 * loop.host_submit_s / steps:.1f} us/step in submit, {1e6 * loop.host_poll_s / steps:.1f} us/step "
-        f"in poll, {loop.batches} batches (mean {steps / max(loop.batches, 1):.1f} steps)")
-    # kernel view: the same backlog on one HIP stream (batches of all 16
-    # streams, no overlap between streams), every stage launch timed with HIP
-    # events on the stream it runs on
+    loop, wall = phased_mix(specs, frames, W, K, P, torch, **mk)
+    n_steps = ns * K
+    value = n_steps / wall
+    host_us = 1e6 * loop.window["host_submit_s"] / n_steps
+    log(f"timed: {K} steps x {ns} streams = {n_steps} filter steps in {wall:.4f} s = {value:.0f} steps/s; host "
+        f"{host_us:.1f} us per filter step in submission, {loop.window['batches']} batches")
+    del loop
+    # kernel view: the same window on one HIP stream (batches of all streams),
+    # every stage launch timed with HIP events on its stream
     breakdown, dominant, dom_roof, kv_rate = {}, None, None, None
     if not args.per_stream:
-        kloop, kwall = run_mix(specs, frames, fps, realtime=False, n_hip_streams=1, timer=True)
-        kv_rate = kloop.completed / kwall
-        breakdown, dominant, dom_roof = stage_rooflines(kloop, specs, fps)
-        log(f"kernel view (one HIP stream): {kloop.completed} steps in {kwall:.3f} s = {kv_rate:.0f} steps/s, "
-            f"{kloop.batches} batches")
-    if breakdown:
+        kloop, kwall = phased_mix(specs, frames, W, K, P, torch, n_hip_streams=1, timer=True)
+        kv_rate = n_steps / kwall
+        samples = marched_samples(kloop, specs, P)
+        breakdown, dominant, dom_roof = stage_rooflines(kloop, specs, K, samples)
+        log(f"kernel view (one HIP stream): {n_steps} steps in {kwall:.4f} s = {kv_rate:.0f} steps/s")
         log("stage shares: " + ", ".join(f"{k} {v['share']:.1%} ({v['avg_us']:.0f} us)" for k, v in
                                          sorted(breakdown.items(), key=lambda kv: -kv[1]["ms"])))
-    # the same mix under an artificial admission budget
-    bloop, bwall = run_mix(specs, frames, fps, realtime=False, budget=int(args.budget_gb * 2**30), **mk)
+        del kloop
+    # the serving baseline: FP32 maps, one stream at a time, plain path
+    seq = fp32_sequential(specs, frames, W, K, P, torch)
+    log(f"FP32 sequential baseline: {seq['steps_per_s']} steps/s (p50 {seq['p50_ms']} ms, p99 {seq['p99_ms']} ms)")
+    # brick-pool maps: first with room for every brick of each grid, to see how
+    # many bricks the streams touch in the window, then with each pool sized
+    # to that use, which must reproduce the run with no dropped update
+    def pool_window(pspecs):
+        ploop, pwall = phased_mix(pspecs, frames, W, K, P, torch, **mk)
+        use = {s.stream_id: [int(v) for v in ploop.agents[s.stream_id].filter.map.pool_usage().cpu()]
+               for s in pspecs}
+        del ploop
+        return pwall, use
+    full = pooled(specs, P, 1.0)
+    fwall, fuse = pool_window(full)
+    sized = pooled(specs, P, 1.0)
+    for s in sized:
+        s.grid.capacity = max(1, fuse[s.stream_id][0])
+    swall, suse = pool_window(sized)
+    sfoot = sum(footprint_bytes(s) for s in sized)
+    frac_used = [fuse[s.stream_id][0] / (s.grid.n // 8) ** 3 for s in specs]
+    pool_run = {"frames_per_stream": 1 + W + K,
+                "full_pool": {"steps_per_s": round(n_steps / fwall, 1),
+                              "bricks_used_max": round(max(frac_used), 3),
+                              "bricks_used_mean": round(float(np.mean(frac_used)), 3),
+                              "footprint_gb": round(sum(footprint_bytes(s) for s in full) / 2**30, 3)},
+                "sized_to_use": {"steps_per_s": round(n_steps / swall, 1), "footprint_gb": round(sfoot / 2**30, 3),
+                                 "dropped_brick_updates": int(sum(u[1] for u in suse.values()))},
+                "dense_footprint_gb": round(foot / 2**30, 3),
+                "note": "a brick holds storage once one of its voxels is updated; the map update touches every "
+                        "voxel between the camera and the surface, so in these closed rooms use grows towards the "
+                        "whole grid with time"}
+    log(f"brick-pool maps: {pool_run['full_pool']['steps_per_s']} steps/s with room for every brick "
+        f"(bricks used max {max(frac_used):.2f}, mean {np.mean(frac_used):.2f}); sized to that use: "
+        f"{pool_run['sized_to_use']['steps_per_s']} steps/s, footprint {sfoot / 2**30:.2f} GiB (dense "
+        f"{foot / 2**30:.2f}), dropped {pool_run['sized_to_use']['dropped_brick_updates']}")
+    # the same mix under an artificial admission budget (streams admitted as others retire)
+    bfr = min(nfr, 1 + W + K)
+    bloop, bwall = run_mix(specs, frames, bfr, realtime=False, budget=int(args.budget_gb * 2**30), **mk)
     log(f"{args.budget_gb:g} GB budget: {bloop.completed} steps in {bwall:.3f} s, max concurrent "
         f"{bloop.max_concurrent}")
-    # the same mix with brick-pool maps (storage for a fraction of each grid)
-    pspecs = pooled(specs, P, args.pool_frac)
-    pfoot = sum(footprint_bytes(s) for s in pspecs)
-    ploop, pwall = run_mix(pspecs, frames, fps, realtime=False, **mk)
-    used = [ploop.totals[s.stream_id]["pool_used"] / ploop.totals[s.stream_id]["pool_capacity"] for s in pspecs]
-    dropped = sum(ploop.totals[s.stream_id]["pool_dropped"] for s in pspecs)
-    pool_run = {"pool_fraction": args.pool_frac, "steps_per_s": round(ploop.completed / pwall, 1),
-                "footprint_gb": round(pfoot / 2**30, 3), "dense_footprint_gb": round(foot / 2**30, 3),
-                "max_pool_use": round(max(used), 3), "mean_pool_use": round(float(np.mean(used)), 3),
-                "dropped_brick_updates": int(dropped)}
-    log(f"brick-pool maps ({args.pool_frac:g} of each grid): {ploop.completed} steps in {pwall:.3f} s = "
-        f"{ploop.completed / pwall:.0f} steps/s, footprint {pfoot / 2**30:.2f} GiB (dense {foot / 2**30:.2f}), "
-        f"pool use max {max(used):.2f} mean {np.mean(used):.2f}, dropped {dropped}")
+    budget_run = {"budget_gb": args.budget_gb, "frames_per_stream": bfr, "steps_per_s": round(ns * bfr / bwall, 1),
+                  "max_concurrent": bloop.max_concurrent, "max_held_gb": round(bloop.max_held_bytes / 2**30, 3),
+                  "note": "fresh streams admitted as others retire; includes admission and first frames"}
+    del bloop
     # real-time arrivals at 10 Hz
     rloop, rwall = run_mix(specs, frames, args.rt_frames, realtime=True, **mk)
     rst = rloop.stats()
     log(f"10 Hz run: {rloop.completed} steps in {rwall:.2f} s, p50 {rst['p50_ms']:.2f} ms, p99 {rst['p99_ms']:.2f} ms")
+    del rloop
+    torch.cuda.empty_cache()
     if args.calib:
         src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)                     # the runtime's blit copy
         torch.bitwise_not(src, out=dst)    # a plain elementwise kernel: reads and writes 256 MiB once
         torch.cuda.synchronize()
+        del src, dst
 
-    single = single_stream(P, torch, args.single_steps, 10)
-    mapping = mapping_comparison(P, torch)
-    optimisers = pose_optimisers(P, torch)
-    big_room = large_room_pool(P, torch)
+    extra = {}
+    if not args.quick:
+        single = single_stream(P, torch, args.single_steps, 10)
+        extra["single_stream_fp32"] = {
+            "workload": "256^3 grid (2.5 cm), 320x240, K = 128, FP32 map, P2 x 3 GN, one HIP graph per step",
+            "steps_per_s": round(1e3 / single["ms_per_step"], 1), "ms_per_step": round(single["ms_per_step"], 4),
+            "p50_ms": round(single["p50_ms"], 4), "p99_ms": round(single["p99_ms"], 4),
+            "pos_err_m": round(single["pos_err"], 4)}
+        extra["render_jacobian_mrays_per_s"] = {"1_frame": round(single["mrays_1"], 1),
+                                                "8_frames": round(single["mrays_8"], 1),
+                                                "workload": "256^3 FP32, 320x240, K = 128"}
+        extra["adjoint_mrays_per_s"] = {"8_frames": round(single["mrays_vjp8"], 1),
+                                        "workload": "render_vjp, 256^3 FP32, 320x240, K = 128, 8 frames"}
+        extra["kernels_us"] = {"render_jacobian_1f": round(single["us_rj1"], 2),
+                               "render_jacobian_8f": round(single["us_rj8"], 2), "render": round(single["us_render"], 2),
+                               "render_vjp_8f": round(single["us_vjp8"], 2), "map_update_warm": round(single["us_mu"], 2)}
+        extra["rollout"] = {"workload": "16 sampled trajectories x 10 steps from the belief, moments and all 160 "
+                                        "frames rendered; 256^3 FP32, 320x240, K = 128",
+                            "ms": round(single["ms_roll"], 3), "mrays_per_s": round(single["mrays_roll"], 1)}
+        extra["roofline_map_update_warm"] = {
+            "kernel": "prism_map_update call, 256^3 FP32, 320x240, one map, 4 consecutive frames (cache-resident)",
+            "achieved": round(single["mu_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(single["mu_gbs"] / HBM_PEAK_GBS, 4), "avg_call_us": round(single["us_mu"], 2)}
+        extra["roofline_map_update_cold"] = map_update_cold(P, torch)
+        extra["single_frame_workload"] = single_frame_gpu(P, torch)
+        extra["bf16_384_stream"] = bf16_stream_gpu(P, torch)
+        extra["mapping_gd_vs_closed_form"] = mapping_comparison(P, torch)
+        extra["pose_optimisers"] = pose_optimisers(P, torch)
+        extra["large_room_pool"] = large_room_pool(P, torch)
 
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(frames, specs, args.cpu_seconds)
-        log(f"cpu oracle: {cpu['value']} steps/s on {cpu['cores']} threads")
+        log(f"cpu oracle: {cpu['value']} steps/s on {cpu['cores']} threads ({cpu['cpu_model']})")
+        if args.cpu_configs:
+            cpu["per_config"] = cpu_configs(args.cpu_config_frames)
 
     r = lambda x, k=3: round(float(x), k)
     out = {
@@ -669,9 +1006,9 @@ def main():
         "value": r(value, 1),
         "unit": "steps/s",
         "n_gpus": 1,
-        "steps": steps,
-        "warmup": wfps * ns,
-        "ms_per_step": r(1e3 * wall / steps, 4),
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": r(1e3 * wall / K, 4),
         "p50_ms": r(rst["p50_ms"]),
         "p99_ms": r(rst["p99_ms"]),
         "higher_is_better": True,
@@ -682,46 +1019,26 @@ def main():
         "config": {"workload": f"serving mix: {ns} agent streams, image sizes from {{160x120, 320x240, 640x480}}, "
                                "grids from {128^3, 256^3, 384^3} over a 6.4 m room, K = N/2, BF16 maps resident in "
                                "HBM, P2 objective with 3 Gauss-Newton iterations, full filter step per frame",
-                   "streams": mix_desc, "frames_per_stream": fps, "hip_streams": args.hip_streams,
-                   "slots_per_stream": 2,
+                   "step": f"one frame of each of the {ns} streams ({ns} filter steps); value = filter steps/s",
+                   "filter_steps_timed": n_steps, "streams": mix_desc,
+                   "untimed_before_window": f"admission, each stream's first frame, {W} warm-up steps",
+                   "hip_streams": args.hip_streams, "slots_per_stream": 2,
                    "launch": ("hip-graph per step (recorded per input slot)" if args.per_stream else
                               "continuous batching: one launch per stage for all ready streams of a HIP stream"),
                    "latency_run": f"{args.rt_frames} frames per stream at 10 Hz + Exp(10 ms) jitter"},
-        "serving": {"backlog_steps_per_s": r(value, 1), "backlog_wall_s": r(wall),
-                    "backlog_one_hip_stream_steps_per_s": None if kv_rate is None else r(kv_rate, 1),
-                    "realtime": {"steps": rloop.completed, "wall_s": r(rwall, 2), "p50_ms": r(rst["p50_ms"]),
+        "serving": {"steps_per_s": r(value, 1), "timed_wall_s": r(wall, 5), "host_submit_us_per_step": r(host_us, 2),
+                    "one_hip_stream_steps_per_s": None if kv_rate is None else r(kv_rate, 1),
+                    "fp32_sequential_baseline": seq,
+                    "speedup_vs_fp32_sequential": r(value / seq["steps_per_s"], 2),
+                    "realtime": {"steps": rst["completed"], "wall_s": r(rwall, 2), "p50_ms": r(rst["p50_ms"]),
                                  "p99_ms": r(rst["p99_ms"]), "max_ms": r(rst["max_ms"]),
                                  "per_stream_hz": r(args.rt_frames / rwall, 2)},
-                    "budget_run": {"budget_gb": args.budget_gb, "steps_per_s": r(bloop.completed / bwall, 1),
-                                   "max_concurrent": bloop.max_concurrent,
-                                   "max_held_gb": r(bloop.max_held_bytes / 2**30)},
+                    "budget_run": budget_run,
                     "footprint_gb": r(foot / 2**30),
                     "brick_pool_run": pool_run},
-        "single_stream_fp32": {"workload": "256^3 grid (2.5 cm), 320x240, K = 128, FP32 map, P2 x 3 GN, "
-                                           "one HIP graph per step",
-                               "steps_per_s": r(1e3 / single["ms_per_step"], 1),
-                               "ms_per_step": r(single["ms_per_step"], 4), "p50_ms": r(single["p50_ms"], 4),
-                               "p99_ms": r(single["p99_ms"], 4), "pos_err_m": r(single["pos_err"], 4)},
-        "render_jacobian_mrays_per_s": {"1_frame": r(single["mrays_1"], 1), "8_frames": r(single["mrays_8"], 1),
-                                        "workload": "256^3 FP32, 320x240, K = 128"},
-        "adjoint_mrays_per_s": {"8_frames": r(single["mrays_vjp8"], 1),
-                                "workload": "render_vjp, 256^3 FP32, 320x240, K = 128, 8 frames"},
-        "kernels_us": {"render_jacobian_1f": r(single["us_rj1"], 2), "render_jacobian_8f": r(single["us_rj8"], 2),
-                       "render": r(single["us_render"], 2), "render_vjp_8f": r(single["us_vjp8"], 2),
-                       "map_update": r(single["us_mu"], 2)},
-        "rollout": {"workload": "16 sampled trajectories x 10 steps from the belief, moments and all 160 frames "
-                                "rendered; 256^3 FP32, 320x240, K = 128",
-                    "ms": r(single["ms_roll"], 3), "mrays_per_s": r(single["mrays_roll"], 1)},
-        "mapping_gd_vs_closed_form": mapping,
-        "pose_optimisers": optimisers,
-        "large_room_pool": big_room,
         "roofline": roofline_obj(dominant, dom_roof, breakdown),
         "kernel_breakdown": breakdown,
-        "roofline_map_update_single": {
-            "kernel": "prism_map_update call (cull + update + dilated bits and count), 256^3 FP32, 320x240, 4 rotating frames",
-            "bound": "hbm", "achieved": r(single["mu_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": r(single["mu_gbs"] / HBM_PEAK_GBS, 4), "algorithmic_bytes": int(single["mu_bytes"]),
-            "updated_voxels": int(single["n_upd"]), "avg_call_us": r(single["us_mu"], 2)},
+        **extra,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

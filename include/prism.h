@@ -145,8 +145,9 @@ size_t prism_sizeof(const char *type_name);
 /* The map is one opaque device buffer of prism_map_bytes() bytes: eight
  * planes (mean occupancy, mean R, G, B, then the four variances) of n^3
  * values of the grid's dtype, each plane in 8x8x8-brick order, followed by a
- * brick summary (largest occupancy mean per 8^3 brick, which the renderer
- * uses to skip free space when tau == 0) and a small scratch area used by
+ * brick summary (one value per 8^3 brick, <= 0 exactly when every occupancy
+ * mean of the brick is <= 0, the largest occupancy mean when that is > 0; the
+ * renderer uses it to skip free space when tau == 0) and a small scratch area used by
  * prism_map_update.  Every call of this library that writes the map keeps the
  * summary current; after writing the planes directly (e.g. a gradient step on
  * the means), call prism_map_refresh before rendering.  Calls that write the

@@ -2,8 +2,10 @@
 //
 // Storage: 8 planes (mean occ, R, G, B, var occ, R, G, B) of n^3 values in
 // 8x8x8-brick order, brick-major, x fastest inside a brick, followed by the
-// brick summary (largest occupancy mean of each brick), a bit per brick
-// telling whether that maximum is <= 0 (the renderer keeps these bits in LDS
+// brick summary (one value per brick whose sign is exact: <= 0 exactly when
+// every occupancy mean of the brick is <= 0, and then not necessarily the
+// largest; the largest occupancy mean when that is > 0), a bit per brick
+// telling whether the summary is <= 0 (the renderer keeps these bits in LDS
 // to skip free space) and per-workgroup update counts.
 //
 // The map update runs in three kernels and uses no global atomics.
@@ -14,12 +16,14 @@
 //           sums) and stores the segment length.  Block 0 also stores the
 //           pose in both precisions for the next kernel.
 //   update: a fixed grid of workgroups scans the segment lengths in LDS and
-//           walks the compacted list, one brick per workgroup at a time: each
-//           lane decides its two voxels with the single-precision recipe and
-//           updates only those, so HBM traffic is the updated voxels' 8 planes
-//           read and written once; the brick's occupancy maximum is refreshed
-//           in the same pass (its free-space bit toggled when it crosses 0),
-//           and each workgroup stores its update count.
+//           walks the compacted list, one brick per wavefront at a time: each
+//           lane decides its eight voxels (one column of the brick) with the
+//           single-precision recipe and updates only those, so HBM traffic is
+//           the updated voxels' 8 planes read and written once; the brick
+//           summary is refreshed in the same pass (its free-space bit toggled
+//           when its sign changes), reading the occupancy of voxels left alone
+//           only in bricks that held a voxel above 0, and each workgroup stores
+//           its update count.
 //   The count of updated voxels is the sum of the per-workgroup counts, taken
 //   by a one-wavefront kernel or by the next kernel of a filter step.
 #include "common.hpp"
@@ -439,6 +443,11 @@ __device__ __forceinline__ void map_update_block(int blk, int ngroups, const Gri
             if (sl < 0) continue;
             slot = sl;
         }
+        // occupancy of voxels this update leaves alone is read only where it
+        // can decide the brick's free-space bit: in a brick holding a voxel
+        // above 0 before the update (in a free brick every such voxel is <= 0)
+        const float bm_old = aux.bmax[b];
+        const bool need_occ = !fresh && !(bm_old <= 0.0f);
         float m = -INFINITY;
         // the lane's eight z-slices in groups of two: a group's plane and
         // colour loads are all issued before any of them is used (one memory
@@ -462,7 +471,7 @@ __device__ __forceinline__ void map_update_block(int blk, int ngroups, const Gri
                     const int px = pix[h];
 #pragma unroll
                     for (int ch = 0; ch < 3; ++ch) lc[hh][ch] = rgb[3 * px + ch];
-                } else if (!fresh) {
+                } else if (need_occ) {
                     lv[hh][0] = ldp(plane_g(map, g, 0), id);
                 }
             }
@@ -479,7 +488,7 @@ __device__ __forceinline__ void map_update_block(int blk, int ngroups, const Gri
                             stp(plane_w(map, g, 4 + ch), id, pvar);
                         }
                         m = fmaxf(m, g.pocc);
-                    } else {
+                    } else if (need_occ) {
                         m = fmaxf(m, lv[hh][0]);
                     }
                     continue;
@@ -536,11 +545,17 @@ __device__ __forceinline__ void map_update_block(int blk, int ngroups, const Gri
         }
         for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
         if (lane == 0) {
-            // keep the free-space bit equal to (maximum <= 0): toggle it when
-            // the brick crosses over (each brick has one owner per launch, so
-            // toggles of one word touch different bits)
-            bool was_free = aux.bmax[b] <= 0.0f, now_free = m <= 0.0f;
-            aux.bmax[b] = m;
+            // The summary keeps an exact sign: in a brick that held a voxel
+            // above 0, every voxel was read and m is the largest occupancy;
+            // in a free brick the voxels left alone are <= 0, so m > 0 is the
+            // largest occupancy and m <= 0 (or no update) leaves the brick
+            // free.  The free-space bit toggles when the sign changes (each
+            // brick has one owner per launch, so toggles of one word touch
+            // different bits).
+            const bool was_free = bm_old <= 0.0f;
+            const float bm_new = (was_free && !(m > 0.0f)) ? fmaxf(m, bm_old) : m;
+            const bool now_free = bm_new <= 0.0f;
+            aux.bmax[b] = bm_new;
             if (was_free != now_free) atomicXor(&aux.bits[b >> 5], 1u << (b & 31));
         }
     }

@@ -22,11 +22,10 @@ closed-loop drift mixed in:
 * anchor depth and colour rendered from the updated map: reported as
   quantiles; bounded loosely (BF16 moves the occupancy zero crossing).
 
-The report is written to $PRISM_REPORT_DIR (default: the system temporary
-directory) as bf16_error_report.json."""
+The report is written to $PRISM_REPORT_DIR (default: gpurun_out/ at the
+repository root, the folder GPU runs bring back) as bf16_error_report.json."""
 import json
 import os
-import tempfile
 
 import numpy as np
 import pytest
@@ -132,7 +131,8 @@ def test_bf16_per_output_error_vs_fp64_oracle():
         assert e_P <= 1e-4, row
         assert row["anchor_valid_mismatch_frac"] <= 0.01 and row["anchor_depth_rel"]["p50"] <= 1e-3, row
         del of, ao, ag, mean64, var64
-    out_dir = os.environ.get("PRISM_REPORT_DIR") or tempfile.gettempdir()
+    out_dir = os.environ.get("PRISM_REPORT_DIR") or os.path.join(
+        os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
     os.makedirs(out_dir, exist_ok=True)
     with open(os.path.join(out_dir, "bf16_error_report.json"), "w") as fh:
         json.dump(report, fh, indent=1)

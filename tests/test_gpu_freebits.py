@@ -1,6 +1,9 @@
 """The renderer's free-space bits on the GPU.  After every call that writes
 a map (initialisation, dense upload, closed-form update, filter steps single
-and batched, descent steps) the plain bits must equal "brick maximum <= 0"
+and batched, descent steps) the brick summary's sign must be exact (a brick
+is summarised by a value <= 0 exactly when every occupancy mean in its
+planes is <= 0; a positive summary is the brick's largest occupancy), the
+plain bits must equal "brick summary <= 0"
 and the dilated bits must equal the AND over each brick's 2x2x2 block of
 bricks, both recomputed here in numpy from the map's own brick maxima.  A
 wrong bit would let the renderer skip a sample whose occupancy can exceed
@@ -46,6 +49,13 @@ def _check(grid, vm, what):
     free = bmax <= 0.0
     bits = _unpack(plain, 32 * nw)
     assert np.array_equal(bits[:nb3], free), what
+    # the summary's sign is exact: a brick is free exactly when every
+    # occupancy mean stored in its planes is <= 0
+    occ = vm.to_dense()[0][0].cpu().numpy()
+    true_max = occ.reshape(nb, 8, nb, 8, nb, 8).max(axis=(1, 3, 5)).ravel()
+    assert np.array_equal(true_max <= 0.0, free), (what, "summary sign", int(((true_max <= 0) != free).sum()))
+    pos = true_max > 0
+    assert np.array_equal(bmax[pos], true_max[pos].astype(np.float32)), (what, "positive maxima are exact")
     assert not bits[nb3:].any(), what
     # dilated bit b: bits b + {0, 1} + {0, nb} + {0, nb^2}, zero past the last brick
     ext = np.zeros(32 * nw + nb * nb + nb + 2, dtype=bool)
