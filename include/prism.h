@@ -61,6 +61,8 @@ typedef int32_t prism_status;
 #define PRISM_UNSUPPORTED 2      /* dtype / shape outside the supported set */
 #define PRISM_HIP_ERROR 3        /* a HIP runtime call failed (message has the code) */
 #define PRISM_BUSY 4             /* every input slot of the handle holds a step still running */
+#define PRISM_CAPTURE_ERROR 5    /* a HIP graph could not be recorded or instantiated, or the call
+                                    cannot run on a stream that is being captured */
 
 /* Map storage types. */
 #define PRISM_F32 0
@@ -74,6 +76,10 @@ typedef int32_t prism_status;
                                         covariance itself was not positive definite: the
                                         whole state kept the predicted mean and joint
                                         covariance, the Laplace average is unchanged */
+#define PRISM_FLAG_LOW_INLIERS 8     /* the objective at the final iterate had fewer
+                                        contributing pixels than min_inlier_frac of the
+                                        image: the step ran, but the pose is weakly
+                                        constrained by the frame */
 
 /* Objectives for the pose update. */
 #define PRISM_OBJ_P2 0 /* prediction-to-observation surrogate against the previous
@@ -281,6 +287,14 @@ prism_status prism_render_jacobian_noalloc(const prism_grid *grid, const void *m
                                            float *rgb, uint8_t *mask, float *J, float *resid,
                                            uint8_t *rowmask, double *neq, hipStream_t stream);
 
+/* The pose perturbation all Jacobians are taken in (a left retraction in the
+ * world frame): out[i] = (t_i + dt_i, Exp(dtheta_i) R_i) for delta[i] =
+ * (dt_i, dtheta_i).  poses, out: device, n prism_pose (may alias); delta:
+ * device double [n][6].  The differentiable renderer (RenderFn) renders at
+ * these poses. */
+prism_status prism_pose_retract(const prism_pose *poses, const double *delta, int32_t n, prism_pose *out,
+                                hipStream_t stream);
+
 /* Prediction-to-observation objective (App. E.3, P2) for one frame: each
  * observed pixel with valid depth D is back-projected (D r_c), moved by the
  * pose iterate `pose` and brought into the camera of `pose_prev` (the pose the
@@ -321,9 +335,12 @@ prism_status prism_render_vjp(const prism_grid *grid, const void *map, const pri
  * voxel whose centre has camera depth z > 0, projects into the image at pixel
  * (floor(u), floor(v)) with observed depth D finite and > 0, and z <= D +
  * trunc, is multiplied per channel by the update Gaussian
- * N(f, 1/lam_update), f = (max(z - D, -trunc), observed rgb):
- *   lambda' = 1/var + lam_update,  mean' = (mean/var + lam_update f)/lambda',
- *   var' = 1/lambda'.  Other voxels are left bitwise unchanged.
+ * N(f, 1/lam_update), f = (max(z - D, -trunc), observed rgb), in the
+ * precision form of App. D, in double precision in this order and rounded
+ * once to the map's storage type:
+ *   lambda = 1/var,  var' = 1/(lambda + lam_update),
+ *   mean' = var' (lambda mean + lam_update f).
+ * Other voxels are left bitwise unchanged.
  * pose: device.  obs_depth [H][W], obs_rgb [H][W][3]: device float.
  * n_updated: nullable, device int64: receives the number of updated voxels. */
 prism_status prism_map_update(const prism_grid *grid, void *map, const prism_camera *cam,
@@ -377,6 +394,8 @@ typedef struct {
     int32_t objective;                  /* PRISM_OBJ_P2 or PRISM_OBJ_P1 */
     prism_map_params map;               /* update truncation and precision */
     double normal_disc;                 /* anchor-normal discontinuity threshold (m) */
+    double min_inlier_frac;             /* PRISM_FLAG_LOW_INLIERS below this fraction of the
+                                           image's pixels contributing, [0, 1] (0: never) */
 } prism_filter_cfg;
 
 /* Device-resident filter state (first bytes of the state buffer), FP64.
@@ -586,6 +605,31 @@ prism_status prism_filter_poll(prism_filter *f, int64_t *completed);
 
 /* prism_filter_poll for n handles: completed[i] for fs[i] (host array). */
 prism_status prism_filter_poll_batch(prism_filter *const *fs, int32_t n, int64_t *completed);
+
+/* ---- checkpoints: the belief (q_t(M), q_t(x)) in and out (Sec. 4.2-4.3) ---- */
+
+/* Bytes of a checkpoint of a filter of this configuration: a 512-byte header,
+ * the state buffer's belief part (state struct, anchor frame, relative pose)
+ * and the whole map buffer. */
+prism_status prism_filter_save_bytes(const prism_filter_cfg *cfg, size_t *bytes);
+
+/* Copies the filter's current belief (map and state, after every step queued
+ * before on `stream`) into dst, device or host memory (pinned host memory for
+ * an asynchronous copy) of at least prism_filter_save_bytes() bytes, 16-byte
+ * aligned.  Asynchronous on `stream`; dst is complete once the stream is.  The
+ * header (grid, camera, step counter) is copied from a buffer the handle
+ * owns, which the next save of the same handle reuses only after this copy
+ * has finished. */
+prism_status prism_filter_save(prism_filter *f, void *dst, size_t dst_bytes, hipStream_t stream);
+
+/* Restores a checkpoint into f (the same handle or another one made with the
+ * same grid and camera; the other configuration values may differ): map and
+ * state are overwritten, the next step continues from the saved belief,
+ * bit for bit as the saved filter would have.  Reads the header first, so
+ * the call waits for `stream` (PRISM_CAPTURE_ERROR while it is being
+ * captured) and fails with PRISM_INVALID_ARGUMENT, changing nothing, on a
+ * bad magic, version, size, grid or camera.  No step of f may be in flight. */
+prism_status prism_filter_load(prism_filter *f, const void *src, size_t src_bytes, hipStream_t stream);
 
 /* Device pointer to the filter's prism_filter_state (inside state_mem). */
 prism_status prism_filter_state_ptr(const prism_filter *f, prism_filter_state **state);

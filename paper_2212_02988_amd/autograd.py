@@ -8,8 +8,8 @@ the backward pass, which recomputes the two bracketing samples of each ray
 and scatters the gradient into the voxel means with atomic adds.
 
 Gradients w.r.t. the pose are taken in the tangent delta = (dt, dtheta) of a
-left perturbation, t <- t + dt, R <- Exp(dtheta) R, and are exact at
-delta = 0; a gradient step is applied by folding delta into the base pose.
+left perturbation, t <- t + dt, R <- Exp(dtheta) R (prism_pose_retract folds
+delta into the base poses), and are exact at delta = 0.
 """
 from __future__ import annotations
 
@@ -18,27 +18,6 @@ from typing import Tuple
 import torch
 
 from . import prism as P
-
-
-def _retract(poses: torch.Tensor, delta: torch.Tensor) -> torch.Tensor:
-    """Base poses [n,7] (t, q) perturbed by delta [n,6], in float64."""
-    d = delta.detach().to(torch.float64)
-    if not torch.any(d != 0):
-        return poses
-    t = poses[:, :3] + d[:, :3]
-    th = d[:, 3:]
-    ang = torch.linalg.norm(th, dim=1, keepdim=True)
-    half = 0.5 * ang
-    s = torch.where(ang > 1e-12, torch.sin(half) / ang.clamp_min(1e-300), 0.5 * torch.ones_like(ang))
-    dq = torch.cat([torch.cos(half), s * th], dim=1)           # Exp(dtheta) as a quaternion
-    q = poses[:, 3:]
-    w1, x1, y1, z1 = dq.unbind(1)
-    w2, x2, y2, z2 = q.unbind(1)
-    qn = torch.stack([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2,
-                      w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
-                      w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2,
-                      w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2], dim=1)
-    return torch.cat([t, qn], dim=1).contiguous()
 
 
 class RenderFn(torch.autograd.Function):
@@ -55,7 +34,9 @@ class RenderFn(torch.autograd.Function):
         if mean_planes.data_ptr() != vmap.mean_planes().data_ptr():
             raise P.PrismError("mean_planes must be vmap.mean_planes()")
         vmap.refresh()
-        p = _retract(poses, delta)
+        # the perturbation delta folded into the base poses by the library's
+        # retraction (t + dt, Exp(dtheta) R)
+        p = P.pose_retract(poses.contiguous(), delta.detach().to(torch.float64).contiguous())
         out = P.render(grid, vmap, cam, p, hit_k=True)
         ctx.save_for_backward(out["hit_k"], p)
         ctx.vmap, ctx.grid, ctx.cam = vmap, grid, cam

@@ -41,6 +41,16 @@ prism_status fail(prism_status code, const char* fmt, ...) {
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
+// PRISM_CAPTURE_ERROR when `stream` is being captured into a graph (calls
+// that wait on the host, record events they later query, or record graphs
+// of their own cannot run inside a capture)
+prism_status not_capturing(hipStream_t stream, const char* what) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(stream, &cs));
+    if (cs != hipStreamCaptureStatusNone) return fail(PRISM_CAPTURE_ERROR, "%s: stream is being captured", what);
+    return PRISM_OK;
+}
+
 prism_status check_grid(const prism_grid* g) {
     REQUIRE(g, "grid is NULL");
     if (g->dtype != PRISM_F32 && g->dtype != PRISM_BF16)
@@ -284,6 +294,10 @@ struct prism_filter {
     void* map;
     int64_t steps;
     prism_filter_state host_state;   // source of prism_filter_reset uploads
+    double min_inliers;              // contributing pixels below which a step raises PRISM_FLAG_LOW_INLIERS
+    // checkpoint header staged on the host, and the event after its last copy
+    alignas(64) unsigned char save_hdr[512];
+    hipEvent_t save_done;
     // executable graphs of a full step, keyed by the frame's buffer addresses
     struct StepGraph {
         const void *depth, *rgb, *u;
@@ -366,6 +380,7 @@ prism_status check_cfg(const prism_filter_cfg* cfg) {
     REQUIRE(cfg->objective == PRISM_OBJ_P2 || cfg->objective == PRISM_OBJ_P1, "objective must be P2 or P1");
     REQUIRE(cfg->map.trunc > 0 && cfg->map.lam_update > 0, "map trunc and lam_update must be > 0");
     REQUIRE(!isnan(cfg->normal_disc), "normal_disc is NaN");
+    REQUIRE(cfg->min_inlier_frac >= 0 && cfg->min_inlier_frac <= 1, "min_inlier_frac must be in [0, 1]");
     return PRISM_OK;
 }
 
@@ -406,7 +421,7 @@ prism_status pose_update_impl(prism_filter* f, const prism_frame* fr, hipStream_
         HIP_TRY(launch_gn_step(f->S, f->partials, nb, f->rel, st));
     }
     if ((s = eval_objective(f, fr, &nb, st))) return s;
-    HIP_TRY(launch_laplace_combine(f->S, f->partials, nb, f->cfg.ema, st));
+    HIP_TRY(launch_laplace_combine(f->S, f->partials, nb, f->cfg.ema, f->min_inliers, st));
     return PRISM_OK;
 }
 
@@ -443,7 +458,7 @@ prism_status pose_update_adam_impl(prism_filter* f, const prism_frame* fr, const
     prism_status s;
     // the optimiser moved the iterate: the objective forms its own relative pose
     if ((s = eval_objective(f, fr, &nb, st, false))) return s;
-    HIP_TRY(launch_laplace_combine(f->S, f->partials, nb, f->cfg.ema, st));
+    HIP_TRY(launch_laplace_combine(f->S, f->partials, nb, f->cfg.ema, f->min_inliers, st));
     return PRISM_OK;
 }
 
@@ -884,6 +899,8 @@ prism_status prism_filter_create(const prism_filter_cfg* cfg, void* state_mem, v
     D.mp = MapUpdC{(float)cfg->map.trunc, cfg->map.trunc, cfg->map.lam_update};
     D.aux = map_aux(&cfg->grid, map_mem);
     D.ema = cfg->ema;
+    f->min_inliers = ceil(cfg->min_inlier_frac * (double)cfg->cam.width * (double)cfg->cam.height);
+    D.min_inliers = f->min_inliers;
     D.normal_disc = (float)cfg->normal_disc;
     D.dtype = cfg->grid.dtype;
     D.n_gn = cfg->n_gn;
@@ -917,6 +934,11 @@ prism_status prism_filter_destroy(prism_filter* f) {
     for (int i = 0; i < f->n_graphs; ++i) {
         hipError_t ei = release_graph(f->graphs[i]);
         if (e == hipSuccess) e = ei;
+    }
+    if (f->save_done) {
+        hipError_t ei = hipEventSynchronize(f->save_done);
+        if (e == hipSuccess) e = ei;
+        (void)hipEventDestroy(f->save_done);
     }
     delete f;
     if (e != hipSuccess) return fail(PRISM_HIP_ERROR, "releasing step graphs: %s", hipGetErrorString(e));
@@ -1031,22 +1053,23 @@ prism_status check_batch(prism_filter* const* fs, int32_t n, const prism_frame* 
 // Records the steady-state step (state filter, map update, anchor) of f for
 // the buffers of fr into an executable graph.
 prism_status capture_step(prism_filter* f, const prism_frame* fr, hipStream_t stream, hipGraphExec_t* out) {
-    HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail(PRISM_CAPTURE_ERROR, "hipStreamBeginCapture: %s", hipGetErrorString(e));
     prism_status s = pose_update_impl(f, fr, stream);
     if (!s) s = map_and_anchor(f, fr, stream);
     hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(stream, &g);
+    e = hipStreamEndCapture(stream, &g);
     if (s) {
         if (g) (void)hipGraphDestroy(g);
         return s;
     }
     if (e != hipSuccess || !g) {
         if (g) (void)hipGraphDestroy(g);
-        return fail(PRISM_HIP_ERROR, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        return fail(PRISM_CAPTURE_ERROR, "hipStreamEndCapture: %s", hipGetErrorString(e));
     }
     e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return fail(PRISM_HIP_ERROR, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return fail(PRISM_CAPTURE_ERROR, "hipGraphInstantiate: %s", hipGetErrorString(e));
     return PRISM_OK;
 }
 
@@ -1104,9 +1127,8 @@ prism_status prism_filter_step_graph(prism_filter* const* fs, int32_t n, const p
     prism_status s = check_batch(fs, n, frames);
     if (s) return s;
     REQUIRE(stream != nullptr, "graph-replayed steps need a non-default stream");
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    HIP_TRY(hipStreamIsCapturing(stream, &cs));
-    REQUIRE(cs == hipStreamCaptureStatusNone, "stream is being captured: use prism_filter_step inside a capture");
+    prism_status cst = not_capturing(stream, "prism_filter_step_graph (use prism_filter_step inside a capture)");
+    if (cst) return cst;
     for (int i = 0; i < n; ++i) {
         prism_filter* f = fs[i];
         if (f->steps == 0) {
@@ -1169,6 +1191,7 @@ prism_status prism_filter_submit(prism_filter* f, const prism_frame* src, int32_
     REQUIRE(f, "filter is NULL");
     REQUIRE(f->n_slots > 0, "no input slots: call prism_filter_set_slots first");
     REQUIRE(stream != nullptr, "submission needs a non-default stream");
+    if (prism_status cst = not_capturing(stream, "prism_filter_submit")) return cst;
     REQUIRE(!f->submit_stream || f->completed == f->submitted || f->submit_stream == stream,
             "all in-flight submissions of a handle must use one stream");
     prism_status s = check_frame(src, f->steps > 0);
@@ -1363,6 +1386,7 @@ prism_status prism_filter_step_batch(prism_filter* const* fs, int32_t n, const p
                                      hipStream_t stream) {
     REQUIRE(fs && src && n >= 1, "need n >= 1 filters and frames");
     REQUIRE(stream != nullptr, "batched steps need a non-default stream");
+    if (prism_status cst = not_capturing(stream, "prism_filter_step_batch")) return cst;
     prism_status s;
     for (int i = 0; i < n; ++i) {
         prism_filter* f = fs[i];
@@ -1437,6 +1461,131 @@ prism_status prism_filter_poll(prism_filter* f, int64_t* completed) {
     prism_status s = poll_impl(f);
     if (s) return s;
     *completed = f->completed;
+    return PRISM_OK;
+}
+
+}  // extern "C"
+
+// ---- checkpoints -------------------------------------------------------------
+namespace {
+
+// Checkpoint layout: this header (512 bytes), then the state buffer's bytes
+// [0, partials) (state struct and anchor frame), then [rel, desc) (relative
+// pose of the iterate), then the whole map buffer.  The reduction partials
+// are scratch and the batched-step descriptor holds the handle's own device
+// addresses, so neither is saved.
+struct CkptHeader {
+    char magic[8];
+    uint32_t version, header_bytes;
+    prism_grid grid;
+    prism_camera cam;
+    int64_t steps;
+    uint64_t state_bytes, rel_bytes, map_bytes;
+};
+static_assert(sizeof(CkptHeader) <= 512, "checkpoint header exceeds its 512 bytes");
+constexpr char kCkptMagic[8] = {'P', 'R', 'I', 'S', 'M', 'C', 'K', '1'};
+constexpr size_t kCkptHeader = 512;
+
+size_t ckpt_bytes(const prism_filter_cfg* cfg, StateLayout* Lout = nullptr) {
+    StateLayout L = state_layout(&cfg->cam);
+    if (Lout) *Lout = L;
+    return kCkptHeader + L.partials + (L.desc - L.rel) + map_layout(&cfg->grid).total;
+}
+
+bool same_grid(const prism_grid& a, const prism_grid& b) {
+    return a.n == b.n && a.dtype == b.dtype && a.voxel == b.voxel && a.origin[0] == b.origin[0] &&
+           a.origin[1] == b.origin[1] && a.origin[2] == b.origin[2] && a.occ_out == b.occ_out &&
+           a.rgb_out == b.rgb_out && a.capacity == b.capacity;
+}
+
+bool same_cam(const prism_camera& a, const prism_camera& b) {
+    return a.width == b.width && a.height == b.height && a.fx == b.fx && a.fy == b.fy && a.cx == b.cx &&
+           a.cy == b.cy && a.d_near == b.d_near && a.d_far == b.d_far && a.n_samples == b.n_samples &&
+           a.tau == b.tau;
+}
+
+}  // namespace
+
+extern "C" {
+
+prism_status prism_filter_save_bytes(const prism_filter_cfg* cfg, size_t* bytes) {
+    prism_status s = check_cfg(cfg);
+    if (s) return s;
+    REQUIRE(bytes, "bytes is NULL");
+    *bytes = ckpt_bytes(cfg);
+    return PRISM_OK;
+}
+
+prism_status prism_filter_save(prism_filter* f, void* dst, size_t dst_bytes, hipStream_t stream) {
+    REQUIRE(f, "filter is NULL");
+    StateLayout L;
+    const size_t need = ckpt_bytes(&f->cfg, &L);
+    REQUIRE(dst && aligned(dst, 16) && dst_bytes >= need, "dst must be 16-byte aligned and hold %zu bytes", need);
+    const size_t mbytes = map_layout(&f->cfg.grid).total;
+    // the staged header may still be the source of the previous save's copy
+    if (f->save_done) {
+        HIP_TRY(hipEventSynchronize(f->save_done));
+    } else {
+        HIP_TRY(hipEventCreateWithFlags(&f->save_done, hipEventDisableTiming));
+    }
+    CkptHeader h;
+    memset(&h, 0, sizeof h);
+    memcpy(h.magic, kCkptMagic, 8);
+    h.version = 1;
+    h.header_bytes = (uint32_t)kCkptHeader;
+    h.grid = f->cfg.grid;
+    h.cam = f->cfg.cam;
+    h.steps = f->steps;
+    h.state_bytes = L.partials;
+    h.rel_bytes = L.desc - L.rel;
+    h.map_bytes = mbytes;
+    memset(f->save_hdr, 0, sizeof f->save_hdr);
+    memcpy(f->save_hdr, &h, sizeof h);
+    char* d = (char*)dst;
+    const char* st = (const char*)f->S;   // the state struct opens the state buffer
+    HIP_TRY(hipMemcpyAsync(d, f->save_hdr, kCkptHeader, hipMemcpyDefault, stream));
+    HIP_TRY(hipEventRecord(f->save_done, stream));
+    HIP_TRY(hipMemcpyAsync(d + kCkptHeader, st, L.partials, hipMemcpyDefault, stream));
+    HIP_TRY(hipMemcpyAsync(d + kCkptHeader + L.partials, st + L.rel, L.desc - L.rel, hipMemcpyDefault, stream));
+    HIP_TRY(hipMemcpyAsync(d + kCkptHeader + L.partials + (L.desc - L.rel), f->map, mbytes, hipMemcpyDefault,
+                           stream));
+    return PRISM_OK;
+}
+
+prism_status prism_filter_load(prism_filter* f, const void* src, size_t src_bytes, hipStream_t stream) {
+    REQUIRE(f, "filter is NULL");
+    StateLayout L;
+    const size_t need = ckpt_bytes(&f->cfg, &L);
+    REQUIRE(src && aligned(src, 16) && src_bytes >= need, "src must be 16-byte aligned and hold %zu bytes", need);
+    if (prism_status cst = not_capturing(stream, "prism_filter_load")) return cst;
+    CkptHeader h;
+    HIP_TRY(hipMemcpyAsync(&h, src, sizeof h, hipMemcpyDefault, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    REQUIRE(memcmp(h.magic, kCkptMagic, 8) == 0 && h.version == 1 && h.header_bytes == kCkptHeader,
+            "not a checkpoint of this library (magic or version)");
+    REQUIRE(same_grid(h.grid, f->cfg.grid), "checkpoint grid differs from the filter's grid");
+    REQUIRE(same_cam(h.cam, f->cfg.cam), "checkpoint camera differs from the filter's camera");
+    const size_t mbytes = map_layout(&f->cfg.grid).total;
+    REQUIRE(h.state_bytes == L.partials && h.rel_bytes == L.desc - L.rel && h.map_bytes == mbytes,
+            "checkpoint sizes do not match the filter");
+    REQUIRE(h.steps >= 0, "checkpoint step counter is negative");
+    const char* sp = (const char*)src;
+    char* st = (char*)f->S;
+    HIP_TRY(hipMemcpyAsync(st, sp + kCkptHeader, L.partials, hipMemcpyDefault, stream));
+    HIP_TRY(hipMemcpyAsync(st + L.rel, sp + kCkptHeader + L.partials, L.desc - L.rel, hipMemcpyDefault, stream));
+    HIP_TRY(hipMemcpyAsync(f->map, sp + kCkptHeader + L.partials + (L.desc - L.rel), mbytes, hipMemcpyDefault,
+                           stream));
+    f->steps = h.steps;
+    return PRISM_OK;
+}
+
+prism_status prism_pose_retract(const prism_pose* poses, const double* delta, int32_t n, prism_pose* out,
+                                hipStream_t stream) {
+    REQUIRE(n >= 0 && n <= (1 << 24), "n must be in [0, 2^24]");
+    if (n == 0) return PRISM_OK;
+    REQUIRE(poses && delta && out && aligned(poses, 8) && aligned(delta, 8) && aligned(out, 8),
+            "poses, delta and out must be non-NULL and 8-byte aligned");
+    HIP_TRY(launch_pose_retract(poses, delta, n, out, stream));
     return PRISM_OK;
 }
 

@@ -7,10 +7,11 @@
 // -ffp-contract=off; division is IEEE correctly rounded).  The order is:
 //   ray:    rx = ((float)u + 0.5f - cx) * ifx;  ry likewise;
 //           dir_i = (R_i0 rx + R_i1 ry) + R_i2
-//   sample: d_k = d_near + (float)k * dstep;  p_i = t_i + d_k dir_i;
-//           g_i = clamp((p_i - o_i) * inv_s - 0.5f, -2, n+1); cell = floor(g);
-//           w = g - cell;  occupancy = lerp_z(lerp_y(lerp_x(corners)))
-//           with lerp(a, b, w) = a + w (b - a)
+//   sample: per ray B_i = (dir_i * dstep) * inv_s and
+//           A_i = ((t_i + d_near * dir_i) - o_i) * inv_s - 0.5f; for sample k
+//           g_i = A_i + (float)k * B_i;  cell = floor(g);  w = g - cell;
+//           occupancy = lerp_z(lerp_y(lerp_x(corners))) with
+//           lerp(a, b, w) = a + w (b - a)
 //   voxel:  x_i = o_i + s ((float)i + 0.5f);  d = x - t;
 //           X_a = (R_0a d_0 + R_1a d_1) + R_2a d_2;
 //           u = fx (X_0 / X_2) + cx,  v = fy (X_1 / X_2) + cy

@@ -33,6 +33,7 @@ struct AgentDesc {
     MapUpdC mp;
     MapAux aux;
     double ema;
+    double min_inliers;   // contributing pixels below which a step raises PRISM_FLAG_LOW_INLIERS
     float normal_disc;
     int dtype, n_gn, nseg, upd_groups, track_blocks;
     void* map;
@@ -172,7 +173,9 @@ hipError_t launch_rollout(const prism_filter_state* S, const double* u, int k, i
 hipError_t launch_predict(prism_filter_state* S, const double* u, const TransC& tc, Rel32* rel, hipStream_t st);
 hipError_t launch_gn_step(prism_filter_state* S, const double* partials, int nblocks, Rel32* rel, hipStream_t st);
 hipError_t launch_laplace_combine(prism_filter_state* S, const double* partials, int nblocks, double ema,
-                                  hipStream_t st);
+                                  double min_inliers, hipStream_t st);
+// the left, world-frame retraction t <- t + dt, R <- Exp(dtheta) R of n poses
+hipError_t launch_pose_retract(const prism_pose* poses, const double* delta, int n, prism_pose* out, hipStream_t st);
 hipError_t launch_first_frame(prism_filter_state* S, hipStream_t st);
 
 }  // namespace prism

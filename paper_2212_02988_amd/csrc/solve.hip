@@ -354,7 +354,8 @@ __global__ __launch_bounds__(512) void k_gn_step(prism_filter_state* __restrict_
 // Laplace covariance, EMA, product with the velocity conditional
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void laplace_combine_block(prism_filter_state* __restrict__ Sg,
-                                                      const double* __restrict__ partials, int nblocks, double ema) {
+                                                      const double* __restrict__ partials, int nblocks, double ema,
+                                                      double min_inliers) {
     __shared__ double red[kRedLds], neq[PRISM_NEQ];
     __shared__ double A[36], Sl[36], Sb[36], D[36], T[36], P[144], e[6];
     __shared__ int ok;
@@ -368,6 +369,7 @@ __device__ __forceinline__ void laplace_combine_block(prism_filter_state* __rest
         // written by the predict kernel); the Laplace EMA is left unchanged
         if (threadIdx.x == 0) {
             if (!(neq[28] > 0.0)) S->flags |= PRISM_FLAG_NO_VALID_PIXELS;
+            if (neq[28] < min_inliers) S->flags |= PRISM_FLAG_LOW_INLIERS;
             for (int i = 0; i < 3; ++i) { S->v[i] = S->vel_prior[i]; S->w[i] = S->vel_prior[3 + i]; }
             S->iter = S->prior;
             S->pose = S->prior;
@@ -379,6 +381,8 @@ __device__ __forceinline__ void laplace_combine_block(prism_filter_state* __rest
     }
     if (threadIdx.x == 0) {
         if (!(neq[28] > 0.0)) S->flags |= PRISM_FLAG_NO_VALID_PIXELS;
+        // fewer contributing pixels at the final iterate than the filter asks for
+        if (neq[28] < min_inliers) S->flags |= PRISM_FLAG_LOW_INLIERS;
         double H[36], g[6];
         unpack_H(neq, H, g);
         for (int i = 0; i < 36; ++i) A[i] = 2.0 * H[i] + S->Lp[i];
@@ -444,8 +448,21 @@ __device__ __forceinline__ void laplace_combine_block(prism_filter_state* __rest
 
 __global__ __launch_bounds__(512) void k_laplace_combine(prism_filter_state* __restrict__ Sg,
                                                          const double* __restrict__ partials, int nblocks,
-                                                         double ema) {
-    laplace_combine_block(Sg, partials, nblocks, ema);
+                                                         double ema, double min_inliers) {
+    laplace_combine_block(Sg, partials, nblocks, ema, min_inliers);
+}
+
+// the left, world-frame retraction of n poses by n tangent increments
+__global__ __launch_bounds__(256) void k_pose_retract(const prism_pose* __restrict__ poses,
+                                                      const double* __restrict__ delta, int n,
+                                                      prism_pose* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    prism_pose p = poses[i];
+    double d[6];
+    for (int a = 0; a < 6; ++a) d[a] = delta[6 * i + a];
+    retract(p, d);
+    out[i] = p;
 }
 
 __device__ __forceinline__ void first_frame_block(prism_filter_state* __restrict__ S) {
@@ -471,7 +488,7 @@ __global__ __launch_bounds__(512) void k_gn_step_batch(BatchArgs b) {
 
 __global__ __launch_bounds__(512) void k_laplace_combine_batch(BatchArgs b) {
     const AgentDesc& D = *b.d[blockIdx.x];
-    laplace_combine_block(D.S, D.partials, D.track_blocks, D.ema);
+    laplace_combine_block(D.S, D.partials, D.track_blocks, D.ema, D.min_inliers);
 }
 
 __global__ __launch_bounds__(64) void k_first_frame_batch(BatchArgs b) { first_frame_block(b.d[blockIdx.x]->S); }
@@ -617,8 +634,13 @@ hipError_t launch_gn_step(prism_filter_state* S, const double* partials, int nbl
 }
 
 hipError_t launch_laplace_combine(prism_filter_state* S, const double* partials, int nblocks, double ema,
-                                  hipStream_t st) {
-    k_laplace_combine<<<1, 512, 0, st>>>(S, partials, nblocks, ema);
+                                  double min_inliers, hipStream_t st) {
+    k_laplace_combine<<<1, 512, 0, st>>>(S, partials, nblocks, ema, min_inliers);
+    return hipGetLastError();
+}
+
+hipError_t launch_pose_retract(const prism_pose* poses, const double* delta, int n, prism_pose* out, hipStream_t st) {
+    k_pose_retract<<<(n + 255) / 256, 256, 0, st>>>(poses, delta, n, out);
     return hipGetLastError();
 }
 

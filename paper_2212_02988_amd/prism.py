@@ -20,11 +20,12 @@ LIB_PATH = os.path.join(_HERE, "libprism.so")
 
 PRISM_F32, PRISM_BF16 = 0, 1
 OBJ_P2, OBJ_P1 = 0, 1
-FLAG_NO_VALID_PIXELS, FLAG_CHOL_FALLBACK, FLAG_PRIOR_NOT_PD = 1, 2, 4
+FLAG_NO_VALID_PIXELS, FLAG_CHOL_FALLBACK, FLAG_PRIOR_NOT_PD, FLAG_LOW_INLIERS = 1, 2, 4, 8
 NEQ = 29
 
 
 PRISM_BUSY = 4
+PRISM_CAPTURE_ERROR = 5
 SUBMIT_FROM_HOST = 1
 SUBMIT_EAGER = 2
 
@@ -81,7 +82,8 @@ class FilterCfg(ctypes.Structure):
                 ("sigma_vel_t", ctypes.c_double), ("sigma_vel_r", ctypes.c_double),
                 ("sigma_pose_t", ctypes.c_double), ("sigma_pose_r", ctypes.c_double),
                 ("w", Weights), ("ema", ctypes.c_double), ("n_gn", ctypes.c_int32),
-                ("objective", ctypes.c_int32), ("map", MapParams), ("normal_disc", ctypes.c_double)]
+                ("objective", ctypes.c_int32), ("map", MapParams), ("normal_disc", ctypes.c_double),
+                ("min_inlier_frac", ctypes.c_double)]
 
 
 class FilterState(ctypes.Structure):
@@ -158,6 +160,10 @@ _SIGS = {
     "prism_stage_timer_arm": ([ctypes.c_int32], None),
     "prism_stage_timer_read": (["p", "p"], None),
     "prism_filter_state_ptr": (["p", "p"], None),
+    "prism_filter_save_bytes": (["p", "p"], None),
+    "prism_filter_save": (["p", "p", ctypes.c_size_t, "p"], None),
+    "prism_filter_load": (["p", "p", ctypes.c_size_t, "p"], None),
+    "prism_pose_retract": (["p", "p", ctypes.c_int32, "p", "p"], None),
     "prism_filter_anchor": (["p", "p", "p", "p", "p", "p"], None),
 }
 
@@ -366,6 +372,18 @@ def render_jacobian(grid: Grid, vmap: VoxelMap, cam: Camera, poses: torch.Tensor
     return out
 
 
+def pose_retract(poses: torch.Tensor, delta: torch.Tensor, stream=None) -> torch.Tensor:
+    """Poses [n,7] (t, q) perturbed by delta [n,6] = (dt, dtheta): t + dt,
+    Exp(dtheta) R (the library's left, world-frame retraction), float64 on
+    the device."""
+    n = poses.shape[0]
+    _dev(poses, torch.float64, "poses", (n, 7))
+    _dev(delta, torch.float64, "delta", (n, 6))
+    out = torch.empty_like(poses)
+    _check(lib().prism_pose_retract(_ptr(poses), _ptr(delta), n, _ptr(out), _stream(stream)))
+    return out
+
+
 def render_jacobian_noalloc(grid: Grid, vmap: VoxelMap, cam: Camera, poses: torch.Tensor, obs_depth: torch.Tensor,
                             obs_rgb: torch.Tensor, w: Weights, out: Dict, stream=None) -> Dict:
     """render_jacobian through the allocation-free entry point: no workspace;
@@ -500,12 +518,14 @@ class FilterParams:
     trunc_voxels: float = 4.0
     sigma_update: float = 1.0
     normal_disc: float = 0.1
+    min_inlier_frac: float = 0.1
 
 
 def filter_cfg(grid: Grid, cam: Camera, p: FilterParams) -> FilterCfg:
     return FilterCfg(grid, cam, p.dt, p.sigma_vel_t, p.sigma_vel_r, p.sigma_pose_t, p.sigma_pose_r,
                      Weights.make(p.b_geo, p.b_rgb, p.gate_geo, p.gate_rgb), p.ema, p.n_gn, p.objective,
-                     MapParams(p.trunc_voxels * grid.voxel, 1.0 / p.sigma_update ** 2), p.normal_disc)
+                     MapParams(p.trunc_voxels * grid.voxel, 1.0 / p.sigma_update ** 2), p.normal_disc,
+                     p.min_inlier_frac)
 
 
 def filter_bytes(cfg: FilterCfg) -> int:
@@ -638,6 +658,30 @@ class Filter:
         if ns == 0:
             out["poses"] = out["poses"][:0]
         return out
+
+    def save_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        _check(lib().prism_filter_save_bytes(_by(self.cfg), _by(b)))
+        return b.value
+
+    def save(self, dst: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """Checkpoint of the belief (map and state) into dst, a uint8 tensor
+        (device, or pinned host) of save_bytes(); allocated on the device if
+        None.  Asynchronous on the stream."""
+        nb = self.save_bytes()
+        if dst is None:
+            dst = torch.empty(nb, dtype=torch.uint8, device=self.state_buf.device)
+        if dst.dtype != torch.uint8 or dst.numel() < nb or not dst.is_contiguous():
+            raise PrismError("checkpoint buffer must be a contiguous uint8 tensor of save_bytes()")
+        _check(lib().prism_filter_save(self.h, _ptr(dst), dst.numel(), _stream(stream)))
+        return dst
+
+    def load(self, src: torch.Tensor, stream=None):
+        """Restore a checkpoint made by save() of a filter with the same grid
+        and camera (waits for the stream to read its header)."""
+        if src.dtype != torch.uint8 or not src.is_contiguous():
+            raise PrismError("checkpoint must be a contiguous uint8 tensor")
+        _check(lib().prism_filter_load(self.h, _ptr(src), src.numel(), _stream(stream)))
 
     def state(self) -> FilterState:
         """Synchronous read-back of the device state."""

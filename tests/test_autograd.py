@@ -7,20 +7,26 @@ import oracle as orc
 import synth
 
 
+@pytest.mark.gpu
 def test_retract_matches_oracle():
-    """Pose perturbation used by the autograd wrapper (host-side float64):
-    t + dt, Exp(dtheta) R, against the oracle's retraction."""
-    from paper_2212_02988_amd.autograd import _retract
+    """prism_pose_retract (through the C ABI): t + dt, Exp(dtheta) R, against
+    the oracle's retraction, for rotations from small to large."""
+    from gpu_util import P
     rng = np.random.default_rng(0)
-    for _ in range(5):
-        t, q = rng.normal(size=3), rng.normal(size=4)
-        q /= np.linalg.norm(q)
-        d = rng.normal(0, 0.3, 6)
-        got = _retract(torch.tensor(np.concatenate([t, q])[None]), torch.tensor(d[None]))[0].numpy()
-        ref = orc.retract(np.concatenate([t, q]), d)
-        if got[3] * ref[3] < 0:
-            got[3:] = -got[3:]
-        np.testing.assert_allclose(got, ref, atol=1e-12)
+    n = 8
+    t, q = rng.normal(size=(n, 3)), rng.normal(size=(n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    d = rng.normal(0, 0.3, (n, 6))
+    d[0] = 0.0
+    d[1, 3:] = 1e-9                       # below the series switch of Exp
+    poses = np.concatenate([t, q], 1)
+    got = P().pose_retract(P().poses_tensor(poses), torch.tensor(d, device="cuda")).cpu().numpy()
+    for i in range(n):
+        ref = orc.retract(poses[i], d[i])
+        g = got[i].copy()
+        if g[3] * ref[3] < 0:
+            g[3:] = -g[3:]
+        np.testing.assert_allclose(g, ref, atol=1e-12)
 
 
 def _subcase():
@@ -97,7 +103,7 @@ def test_autograd_finite_differences():
     gradient kinks on cell faces); the adjoint is run with the same ray mask
     on its upstream gradients."""
     from gpu_util import banner, cam_of, gpu_map, grid_of, P
-    from paper_2212_02988_amd.autograd import _retract, render as drender
+    from paper_2212_02988_amd.autograd import render as drender
     banner("autograd finite differences")
     c, mean, var = _subcase()
     tr = c["traj"]
@@ -147,9 +153,10 @@ def test_autograd_finite_differences():
     for m in range(6):
         e = zero.clone()
         e[0, m] = eps
-        da, ca, ka = fwd(_retract(poses, e))
-        db, cb, kb = fwd(_retract(poses, -e))
-        same = np.all((cells(_retract(poses, e)) == c_base) & (cells(_retract(poses, -e)) == c_base), -1)
+        pa, pb = P().pose_retract(poses, e), P().pose_retract(poses, -e)
+        da, ca, ka = fwd(pa)
+        db, cb, kb = fwd(pb)
+        same = np.all((cells(pa) == c_base) & (cells(pb) == c_base), -1)
         S = ((ka == k0) & (kb == k0) & (k0 >= 1)).double() * torch.tensor(same[None], device="cuda")
         assert S.sum() > 0.8 * H * W * 0.5
         fd = (loss(da, ca, S) - loss(db, cb, S)) / (2 * eps)
