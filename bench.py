@@ -86,7 +86,8 @@ def build_mix(n_streams, n_frames, P, torch):
     return specs, frames
 
 
-def run_mix(specs, frames, n_frames, realtime, budget=None, n_hip_streams=4, batched=True, timer=False):
+def run_mix(specs, frames, n_frames, realtime, budget=None, n_hip_streams=4, batched=True, timer=False,
+            batch_graphs=True):
     import dataclasses
     from paper_2212_02988_amd.serving import ServingLoop, run_schedule
     sp = [dataclasses.replace(s, n_frames=n_frames) for s in specs]
@@ -96,7 +97,7 @@ def run_mix(specs, frames, n_frames, realtime, budget=None, n_hip_streams=4, bat
     def source(sid, k):
         fr = frames[sid]
         return fr["D"][k], fr["C"][k], None if k == 0 else fr["U"][k - 1]
-    loop = ServingLoop(hbm_budget=budget, n_hip_streams=n_hip_streams, batched=batched)
+    loop = ServingLoop(hbm_budget=budget, n_hip_streams=n_hip_streams, batched=batched, batch_graphs=batch_graphs)
     if timer:
         from paper_2212_02988_amd import prism as P
         P.stage_timer_arm(1 << 14)
@@ -106,7 +107,7 @@ def run_mix(specs, frames, n_frames, realtime, budget=None, n_hip_streams=4, bat
     return loop, wall
 
 
-def phased_mix(specs, frames, W, K, P, torch, n_hip_streams=4, batched=True, timer=False):
+def phased_mix(specs, frames, W, K, P, torch, n_hip_streams=4, batched=True, timer=False, batch_graphs=True):
     """Admit every stream, run its first frame and W further frames untimed,
     then time exactly K frames of every stream in backlog mode.  Returns the
     loop, the timed wall time and each stream's voxel updates in the window."""
@@ -115,7 +116,7 @@ def phased_mix(specs, frames, W, K, P, torch, n_hip_streams=4, batched=True, tim
     n_total = 1 + W + K
     # one frame more than is fed, so no stream retires inside the timed window
     sp = [dataclasses.replace(s, n_frames=n_total + 1) for s in specs]
-    loop = ServingLoop(n_hip_streams=n_hip_streams, batched=batched)
+    loop = ServingLoop(n_hip_streams=n_hip_streams, batched=batched, batch_graphs=batch_graphs)
     for s in sp:
         loop.open_stream(s)
     assert len(loop.agents) == len(sp), "the mix must fit the device"
@@ -893,11 +894,18 @@ def main():
     log(f"timed: {K} steps x {ns} streams = {n_steps} filter steps in {wall:.4f} s = {value:.0f} steps/s; host "
         f"{host_us:.1f} us per filter step in submission, {loop.window['batches']} batches")
     del loop
+    # the same window with every batched stage launched on its own (no graphs)
+    eloop, ewall = phased_mix(specs, frames, W, K, P, torch, batch_graphs=False, **mk)
+    eager_run = {"steps_per_s": round(n_steps / ewall, 1),
+                 "host_submit_us_per_step": round(1e6 * eloop.window["host_submit_s"] / n_steps, 2)}
+    log(f"batched stages launched one by one: {eager_run['steps_per_s']} steps/s, host "
+        f"{eager_run['host_submit_us_per_step']} us per filter step in submission")
+    del eloop
     # kernel view: the same window on one HIP stream (batches of all streams),
     # every stage launch timed with HIP events on its stream
     breakdown, dominant, dom_roof, kv_rate = {}, None, None, None
     if not args.per_stream:
-        kloop, kwall = phased_mix(specs, frames, W, K, P, torch, n_hip_streams=1, timer=True)
+        kloop, kwall = phased_mix(specs, frames, W, K, P, torch, n_hip_streams=1, timer=True, batch_graphs=False)
         kv_rate = n_steps / kwall
         samples = marched_samples(kloop, specs, P)
         breakdown, dominant, dom_roof = stage_rooflines(kloop, specs, K, samples)
@@ -954,6 +962,11 @@ def main():
     rst = rloop.stats()
     log(f"10 Hz run: {rloop.completed} steps in {rwall:.2f} s, p50 {rst['p50_ms']:.2f} ms, p99 {rst['p99_ms']:.2f} ms")
     del rloop
+    # the same arrivals with every batched stage launched on its own
+    rloop_e, rwall_e = run_mix(specs, frames, args.rt_frames, realtime=True, batch_graphs=False, **mk)
+    rst_e = rloop_e.stats()
+    log(f"10 Hz run, stages launched one by one: p50 {rst_e['p50_ms']:.2f} ms, p99 {rst_e['p99_ms']:.2f} ms")
+    del rloop_e
     torch.cuda.empty_cache()
     if args.calib:
         src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
@@ -1024,15 +1037,19 @@ def main():
                    "untimed_before_window": f"admission, each stream's first frame, {W} warm-up steps",
                    "hip_streams": args.hip_streams, "slots_per_stream": 2,
                    "launch": ("hip-graph per step (recorded per input slot)" if args.per_stream else
-                              "continuous batching: one launch per stage for all ready streams of a HIP stream"),
+                              "continuous batching: the ready streams of a HIP stream form one batch, its stages "
+                              "replayed from a HIP graph recorded per member set and input slots"),
                    "latency_run": f"{args.rt_frames} frames per stream at 10 Hz + Exp(10 ms) jitter"},
         "serving": {"steps_per_s": r(value, 1), "timed_wall_s": r(wall, 5), "host_submit_us_per_step": r(host_us, 2),
                     "one_hip_stream_steps_per_s": None if kv_rate is None else r(kv_rate, 1),
+                    "batched_eager_launches": eager_run,
                     "fp32_sequential_baseline": seq,
                     "speedup_vs_fp32_sequential": r(value / seq["steps_per_s"], 2),
                     "realtime": {"steps": rst["completed"], "wall_s": r(rwall, 2), "p50_ms": r(rst["p50_ms"]),
                                  "p99_ms": r(rst["p99_ms"]), "max_ms": r(rst["max_ms"]),
-                                 "per_stream_hz": r(args.rt_frames / rwall, 2)},
+                                 "per_stream_hz": r(args.rt_frames / rwall, 2),
+                                 "eager_launches": {"p50_ms": r(rst_e["p50_ms"]), "p99_ms": r(rst_e["p99_ms"]),
+                                                    "max_ms": r(rst_e["max_ms"])}},
                     "budget_run": budget_run,
                     "footprint_gb": r(foot / 2**30),
                     "brick_pool_run": pool_run},

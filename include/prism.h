@@ -553,6 +553,9 @@ prism_status prism_filter_set_slots(prism_filter *f, int32_t n_slots, const pris
 
 #define PRISM_SUBMIT_FROM_HOST 1 /* src buffers are host memory (pinned for an asynchronous copy) */
 #define PRISM_SUBMIT_EAGER 2     /* launch the step's kernels one by one instead of a graph */
+#define PRISM_SUBMIT_GRAPH 4     /* prism_filter_step_batch: replay the batch's stages from a HIP
+                                    graph recorded for its members, their slots and which of them
+                                    are on their first frame */
 
 /* Queues one filter step for the frame src (u may be NULL only for the
  * handle's first frame) without waiting: the frame is copied into the next
@@ -572,10 +575,17 @@ prism_status prism_filter_submit(prism_filter *f, const prism_frame *src, int32_
  * staging, predict, tracking, Gauss-Newton, Laplace/combine, cull, map
  * update, anchor render, normals) is one kernel launch for the whole batch,
  * workgroups assigned to handles by ragged block ranges, so handles of
- * different image and map sizes share launches.  Handles must use the P2
- * objective and have input slots registered; each takes its next slot.
- * Returns PRISM_BUSY, and queues nothing, when any handle has every slot in
- * flight.  flags: PRISM_SUBMIT_FROM_HOST as for prism_filter_submit. */
+ * different image and map sizes, storage types and objectives (P2 and P1)
+ * share launches.  Handles must have input slots registered; each takes its
+ * next slot.  Returns PRISM_BUSY, and queues nothing, when any handle has
+ * every slot in flight.  flags: PRISM_SUBMIT_FROM_HOST as for
+ * prism_filter_submit; PRISM_SUBMIT_GRAPH launches every stage after the
+ * frame staging from one HIP graph, recorded the first time the batch's
+ * members (in this order), their slots and their first-frame states occur
+ * and replayed afterwards (up to 64 graphs per process, least recently used
+ * evicted once its last launch has finished; a handle's graphs are released
+ * by prism_filter_destroy).  Same results, bit for bit.  stream must not be
+ * being captured (PRISM_CAPTURE_ERROR). */
 prism_status prism_filter_step_batch(prism_filter *const *fs, int32_t n, const prism_frame *src, int32_t flags,
                                      hipStream_t stream);
 

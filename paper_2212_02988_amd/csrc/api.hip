@@ -326,6 +326,9 @@ struct prism_filter {
 
 namespace {
 
+// releases every recorded batched-step graph that has f as a member
+hipError_t release_batch_graphs_of(const prism_filter* f);
+
 // Waits for the graph's last launch, then frees it.  Every earlier launch is
 // complete by then: a launch on a new stream first waits for the previous one.
 hipError_t release_graph(prism_filter::StepGraph& G) {
@@ -906,7 +909,7 @@ prism_status prism_filter_create(const prism_filter_cfg* cfg, void* state_mem, v
     D.n_gn = cfg->n_gn;
     D.nseg = (f->g.nb * f->g.nb * f->g.nb + 255) / 256;
     D.upd_groups = map_update_groups(f->g);
-    D.track_blocks = track_blocks(f->c);
+    D.obj_blocks = cfg->objective == PRISM_OBJ_P1 ? render_blocks(f->c) : track_blocks(f->c);
     D.map = map_mem;
     D.bits = skip_table(&cfg->grid, &cfg->cam, map_mem);
     D.S = f->S;
@@ -939,6 +942,10 @@ prism_status prism_filter_destroy(prism_filter* f) {
         hipError_t ei = hipEventSynchronize(f->save_done);
         if (e == hipSuccess) e = ei;
         (void)hipEventDestroy(f->save_done);
+    }
+    {
+        hipError_t ei = release_batch_graphs_of(f);
+        if (e == hipSuccess) e = ei;
     }
     delete f;
     if (e != hipSuccess) return fail(PRISM_HIP_ERROR, "releasing step graphs: %s", hipGetErrorString(e));
@@ -1278,6 +1285,7 @@ int blocks_of(const prism_filter* f, int stage) {
         case 4: return f->desc.upd_groups;                   // update
         case 5: return render_blocks(c);
         case 7: return (free_words(f->g.nb) + 255) / 256;   // dilated free-space bits
+        case 8: return render_blocks(c);                     // render-through objective
         default: return (c.W * c.H + 255) / 256;             // normals
     }
 }
@@ -1302,6 +1310,36 @@ BatchArgs make_batch(prism_filter* const* fs, const int* idx, int m, const int* 
     return b;
 }
 
+// the objective of every filter fs[idx[j]] at its iterate: one tracking
+// launch for the P2 filters, one render-through launch per map kind for the
+// P1 filters
+prism_status batch_objective(prism_filter* const* fs, const int* idx, int m, const int* slot, hipStream_t st) {
+    int p2[kMaxBatch], n2 = 0;
+    for (int j = 0; j < m; ++j)
+        if (fs[idx[j]]->cfg.objective == PRISM_OBJ_P2) p2[n2++] = idx[j];
+    if (n2) {
+        StageScope t(PRISM_STAGE_TRACK, st);
+        HIP_TRY(launch_track_p2_batch(make_batch(fs, p2, n2, slot, 2), st));
+    }
+    for (int kind = 0; kind < 4 && n2 < m; ++kind) {
+        const int dt = kind & 1 ? PRISM_BF16 : PRISM_F32;
+        const bool pool = kind >= 2;
+        int p1[kMaxBatch], n1 = 0, max_lds = 0;
+        for (int j = 0; j < m; ++j) {
+            const prism_filter* f = fs[idx[j]];
+            if (f->cfg.objective != PRISM_OBJ_P1 || f->cfg.grid.dtype != dt || (f->cfg.grid.capacity > 0) != pool)
+                continue;
+            p1[n1++] = idx[j];
+            int words = f->desc.bits ? free_lds_words(free_words(f->g.nb)) : 0;
+            if (words > max_lds) max_lds = words;
+        }
+        if (!n1) continue;
+        StageScope t(PRISM_STAGE_TRACK, st);
+        HIP_TRY(launch_render_jac_batch(make_batch(fs, p1, n1, slot, 8), dt, pool, max_lds, st));
+    }
+    return PRISM_OK;
+}
+
 // one batched step for up to kMaxBatch filters already staged into slot[i]
 prism_status step_batch_chunk(prism_filter* const* fs, int n, const int* slot, hipStream_t st) {
     int all[kMaxBatch], pu[kMaxBatch], ff[kMaxBatch], sub[kMaxBatch];
@@ -1324,19 +1362,15 @@ prism_status step_batch_chunk(prism_filter* const* fs, int n, const int* slot, h
             int m = 0;
             for (int j = 0; j < n_pu; ++j)
                 if (fs[pu[j]]->cfg.n_gn > it) sub[m++] = pu[j];
-            {
-                StageScope t(PRISM_STAGE_TRACK, st);
-                HIP_TRY(launch_track_p2_batch(make_batch(fs, sub, m, slot, 2), st));
-            }
+            prism_status so = batch_objective(fs, sub, m, slot, st);
+            if (so) return so;
             {
                 StageScope t(PRISM_STAGE_GN, st);
                 HIP_TRY(launch_gn_step_batch(make_batch(fs, sub, m, slot, 1), st));
             }
         }
-        {
-            StageScope t(PRISM_STAGE_TRACK, st);
-            HIP_TRY(launch_track_p2_batch(make_batch(fs, pu, n_pu, slot, 2), st));
-        }
+        prism_status so = batch_objective(fs, pu, n_pu, slot, st);
+        if (so) return so;
         {
             StageScope t(PRISM_STAGE_LAPLACE, st);
             HIP_TRY(launch_laplace_combine_batch(make_batch(fs, pu, n_pu, slot, 1), st));
@@ -1380,6 +1414,123 @@ prism_status step_batch_chunk(prism_filter* const* fs, int n, const int* slot, h
     return PRISM_OK;
 }
 
+// ---- batched steps replayed from HIP graphs ---------------------------------
+// A batched step's launches depend only on its members (their descriptors,
+// which the kernels read at run time, and their block ranges), each member's
+// input slot and whether it is on its first frame: a graph recorded for that
+// key replays the step for any later frames staged into the same slots.
+struct BatchGraph {
+    std::vector<const prism_filter*> fs;
+    std::vector<int> slot;
+    std::vector<char> first;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;          // recorded after each launch
+    hipStream_t last_stream = nullptr;  // stream of the latest launch (NULL: never launched)
+    uint64_t last_use = 0;
+};
+
+constexpr size_t kMaxBatchGraphs = 64;
+std::mutex g_bg_mu;
+std::vector<BatchGraph*> g_bg;
+uint64_t g_bg_clock = 0;
+
+hipError_t free_batch_graph(BatchGraph* G) {
+    hipError_t e = G->done ? hipEventSynchronize(G->done) : hipSuccess;
+    if (G->exec) (void)hipGraphExecDestroy(G->exec);
+    if (G->done) (void)hipEventDestroy(G->done);
+    delete G;
+    return e;
+}
+
+hipError_t release_batch_graphs_of(const prism_filter* f) {
+    std::lock_guard<std::mutex> lk(g_bg_mu);
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < g_bg.size();) {
+        BatchGraph* G = g_bg[i];
+        bool has = false;
+        for (const prism_filter* m : G->fs) has |= m == f;
+        if (!has) {
+            ++i;
+            continue;
+        }
+        hipError_t ei = free_batch_graph(G);
+        if (e == hipSuccess) e = ei;
+        g_bg.erase(g_bg.begin() + i);
+    }
+    return e;
+}
+
+// records the batched step of fs[0..n) with these slots into a graph
+prism_status capture_batch(prism_filter* const* fs, int n, const int* slot, hipStream_t st, hipGraphExec_t* out) {
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail(PRISM_CAPTURE_ERROR, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+    prism_status s = step_batch_chunk(fs, n, slot, st);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(st, &g);
+    if (s) {
+        if (g) (void)hipGraphDestroy(g);
+        return s;
+    }
+    if (e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(PRISM_CAPTURE_ERROR, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    }
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(PRISM_CAPTURE_ERROR, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    return PRISM_OK;
+}
+
+// the batched step of fs[0..n) launched from its graph (recorded on first use)
+prism_status step_batch_graph(prism_filter* const* fs, int n, const int* slot, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_bg_mu);
+    g_bg_clock += 1;
+    BatchGraph* G = nullptr;
+    for (BatchGraph* c : g_bg) {
+        if ((int)c->fs.size() != n) continue;
+        bool same = true;
+        for (int i = 0; i < n && same; ++i)
+            same = c->fs[i] == fs[i] && c->slot[i] == slot[i] && c->first[i] == (fs[i]->steps == 0);
+        if (same) {
+            G = c;
+            break;
+        }
+    }
+    if (!G) {
+        if (g_bg.size() >= kMaxBatchGraphs) {
+            size_t lru = 0;
+            for (size_t i = 1; i < g_bg.size(); ++i)
+                if (g_bg[i]->last_use < g_bg[lru]->last_use) lru = i;
+            BatchGraph* old = g_bg[lru];
+            g_bg.erase(g_bg.begin() + lru);
+            hipError_t e = free_batch_graph(old);   // waits for its last launch
+            if (e != hipSuccess) return fail(PRISM_HIP_ERROR, "releasing a batched-step graph: %s", hipGetErrorString(e));
+        }
+        G = new (std::nothrow) BatchGraph();
+        if (!G) return fail(PRISM_INVALID_ARGUMENT, "out of host memory");
+        for (int i = 0; i < n; ++i) {
+            G->fs.push_back(fs[i]);
+            G->slot.push_back(slot[i]);
+            G->first.push_back(fs[i]->steps == 0);
+        }
+        hipError_t e = hipEventCreateWithFlags(&G->done, hipEventDisableTiming);
+        prism_status s = e == hipSuccess ? capture_batch(fs, n, slot, st, &G->exec)
+                                         : fail(PRISM_HIP_ERROR, "hipEventCreate: %s", hipGetErrorString(e));
+        if (s) {
+            (void)free_batch_graph(G);
+            return s;
+        }
+        g_bg.push_back(G);
+    }
+    G->last_use = g_bg_clock;
+    // a graph never runs concurrently with itself
+    if (G->last_stream && G->last_stream != st) HIP_TRY(hipEventSynchronize(G->done));
+    HIP_TRY(hipGraphLaunch(G->exec, st));
+    HIP_TRY(hipEventRecord(G->done, st));
+    G->last_stream = st;
+    return PRISM_OK;
+}
+
 }  // namespace
 
 prism_status prism_filter_step_batch(prism_filter* const* fs, int32_t n, const prism_frame* src, int32_t flags,
@@ -1392,7 +1543,6 @@ prism_status prism_filter_step_batch(prism_filter* const* fs, int32_t n, const p
         prism_filter* f = fs[i];
         REQUIRE(f, "filter %d is NULL", i);
         REQUIRE(f->n_slots > 0, "filter %d has no input slots (prism_filter_set_slots)", i);
-        REQUIRE(f->cfg.objective == PRISM_OBJ_P2, "filter %d: batched steps take the P2 objective", i);
         REQUIRE(!f->submit_stream || f->completed == f->submitted || f->submit_stream == stream,
                 "filter %d: all in-flight submissions of a handle must use one stream", i);
         for (int j = 0; j < i; ++j) REQUIRE(fs[j] != f, "filter %d appears twice in the batch", i);
@@ -1433,7 +1583,9 @@ prism_status prism_filter_step_batch(prism_filter* const* fs, int32_t n, const p
             StageScope t(PRISM_STAGE_STAGING, stream);
             HIP_TRY(launch_stage_batch(make_batch(fc, dev_idx, n_dev, slot, 0), ss, stream));
         }
-        if ((s = step_batch_chunk(fc, m, slot, stream))) return s;
+        if ((s = (flags & PRISM_SUBMIT_GRAPH) ? step_batch_graph(fc, m, slot, stream)
+                                              : step_batch_chunk(fc, m, slot, stream)))
+            return s;
         for (int i = 0; i < m; ++i) {
             prism_filter* f = fc[i];
             HIP_TRY(hipEventRecord(f->slot_done[slot[i]], stream));

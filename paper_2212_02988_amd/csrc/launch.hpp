@@ -35,7 +35,9 @@ struct AgentDesc {
     double ema;
     double min_inliers;   // contributing pixels below which a step raises PRISM_FLAG_LOW_INLIERS
     float normal_disc;
-    int dtype, n_gn, nseg, upd_groups, track_blocks;
+    int dtype, n_gn, nseg, upd_groups;
+    int obj_blocks;   // workgroups (reduction partials) of one objective evaluation: tracking (P2) or
+                      // render-through (P1)
     void* map;
     const unsigned* bits;   // free-space bits for the renderer (NULL when tau != 0)
     prism_filter_state* S;
@@ -85,6 +87,8 @@ hipError_t launch_dilate(const GridC& g, const MapAux& aux, hipStream_t st);
 hipError_t launch_dilate_batch(const BatchArgs& b, hipStream_t st);
 hipError_t launch_map_update_batch(const BatchArgs& b, int dtype, bool pool, int max_nseg, hipStream_t st);
 hipError_t launch_render_batch(const BatchArgs& b, int dtype, bool pool, int max_lds_words, hipStream_t st);
+// the render-through (P1) objective of every filter of the batch at its iterate
+hipError_t launch_render_jac_batch(const BatchArgs& b, int dtype, bool pool, int max_lds_words, hipStream_t st);
 hipError_t launch_normals_batch(const BatchArgs& b, hipStream_t st);
 int stage_blocks(const CamC& c);
 

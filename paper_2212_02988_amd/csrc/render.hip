@@ -600,23 +600,25 @@ __global__ __launch_bounds__(256) void k_normals_batch(BatchArgs b) {
 // ---------------------------------------------------------------------------
 // render + P1 Jacobian + gated weighted normal equations
 // ---------------------------------------------------------------------------
+// workgroup blk (8x8 pixel tile) of frame `frame` at *pose; the
+// workgroup's 29 sums go to partial_row
 template <typename T, bool Pool>
-__global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, GridD gd, CamD cd, const T* __restrict__ map,
-                                                    const unsigned* __restrict__ gbits,
-                                                    const prism_pose* __restrict__ poses,
-                                                    const float* __restrict__ obs_depth,
-                                                    const float* __restrict__ obs_rgb, WeightsC wt,
-                                                    float* __restrict__ depth, float* __restrict__ rgb,
-                                                    uint8_t* __restrict__ mask, float* __restrict__ Jout,
-                                                    float* __restrict__ resid, uint8_t* __restrict__ rowmask,
-                                                    double* __restrict__ partials) {
+__device__ __forceinline__ void render_jac_block(int blk, int frame, const GridC& g, const CamC& c, const GridD& gd,
+                                                 const CamD& cd, const T* __restrict__ map,
+                                                 const unsigned* __restrict__ gbits, const prism_pose* __restrict__ pose,
+                                                 const float* __restrict__ obs_depth,
+                                                 const float* __restrict__ obs_rgb, const WeightsC& wt,
+                                                 float* __restrict__ depth, float* __restrict__ rgb,
+                                                 uint8_t* __restrict__ mask, float* __restrict__ Jout,
+                                                 float* __restrict__ resid, uint8_t* __restrict__ rowmask,
+                                                 double* __restrict__ partial_row) {
     __shared__ BlockPose sp;
     __shared__ double lds[kRedLds];
     extern __shared__ unsigned lbits[];
-    const FreeBits fb = block_setup(g, gbits, lbits, poses + blockIdx.y, &sp);
+    const FreeBits fb = block_setup(g, gbits, lbits, pose, &sp);
     const BlockPose& P = sp;
     int u, v, s;
-    quad_pixel(c, blockIdx.x, u, v, s);
+    quad_pixel(c, blk, u, v, s);
     // this lane's row in single precision, reduced over the workgroup by
     // block_reduce29f (single precision within 32 lanes, then double)
     float pacc[PRISM_NEQ];
@@ -627,7 +629,7 @@ __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, GridD gd, C
         ray_dir32(c, P.f, u, v, dir);
         const RayCoef rc = ray_coef(g, c, P.f, dir);
         int k = march_quad<T, Pool>(g, c, rc, map, fb, s);
-        long long pix = (long long)blockIdx.y * c.W * c.H + (long long)v * c.W + u;
+        long long pix = (long long)frame * c.W * c.H + (long long)v * c.W + u;
         float row[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         double r = 0.0;
         int rm = 0;
@@ -672,7 +674,35 @@ __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, GridD gd, C
         }
         if (resid) resid[4 * pix + s] = (float)r;
     }
-    block_reduce29f(pacc, lds, partials + ((long long)blockIdx.y * gridDim.x + blockIdx.x) * PRISM_NEQ);
+    block_reduce29f(pacc, lds, partial_row);
+}
+
+template <typename T, bool Pool>
+__global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, GridD gd, CamD cd, const T* __restrict__ map,
+                                                    const unsigned* __restrict__ gbits,
+                                                    const prism_pose* __restrict__ poses,
+                                                    const float* __restrict__ obs_depth,
+                                                    const float* __restrict__ obs_rgb, WeightsC wt,
+                                                    float* __restrict__ depth, float* __restrict__ rgb,
+                                                    uint8_t* __restrict__ mask, float* __restrict__ Jout,
+                                                    float* __restrict__ resid, uint8_t* __restrict__ rowmask,
+                                                    double* __restrict__ partials) {
+    render_jac_block<T, Pool>(blockIdx.x, blockIdx.y, g, c, gd, cd, map, gbits, poses + blockIdx.y, obs_depth, obs_rgb,
+                              wt, depth, rgb, mask, Jout, resid, rowmask,
+                              partials + ((long long)blockIdx.y * gridDim.x + blockIdx.x) * PRISM_NEQ);
+}
+
+// batched: the render-through objective of every filter at its current
+// iterate with its slot's frame (one frame each)
+template <typename T, bool Pool>
+__global__ __launch_bounds__(256) void k_render_jac_batch(BatchArgs b) {
+    const int a = batch_agent(b, blockIdx.x);
+    const AgentDesc& D = *b.d[a];
+    const prism_frame& fr = D.slots[b.slot[a]];
+    const int blk = blockIdx.x - b.start[a];
+    render_jac_block<T, Pool>(blk, 0, D.g, D.c, D.gd, D.cd, (const T*)D.map, D.bits, &D.S->iter,
+                              (const float*)fr.depth, (const float*)fr.rgb, D.w, nullptr, nullptr, nullptr, nullptr,
+                              nullptr, nullptr, D.partials + (long long)blk * PRISM_NEQ);
 }
 
 // ---------------------------------------------------------------------------
@@ -973,6 +1003,19 @@ hipError_t launch_render_batch(const BatchArgs& b, int dtype, bool pool, int max
         k_render_batch<float, true><<<b.start[b.n], 256, lds, st>>>(b);
     else
         k_render_batch<float, false><<<b.start[b.n], 256, lds, st>>>(b);
+    return hipGetLastError();
+}
+
+hipError_t launch_render_jac_batch(const BatchArgs& b, int dtype, bool pool, int max_lds_words, hipStream_t st) {
+    size_t lds = (size_t)max_lds_words * 4;
+    if (dtype == PRISM_BF16 && pool)
+        k_render_jac_batch<uint16_t, true><<<b.start[b.n], 256, lds, st>>>(b);
+    else if (dtype == PRISM_BF16)
+        k_render_jac_batch<uint16_t, false><<<b.start[b.n], 256, lds, st>>>(b);
+    else if (pool)
+        k_render_jac_batch<float, true><<<b.start[b.n], 256, lds, st>>>(b);
+    else
+        k_render_jac_batch<float, false><<<b.start[b.n], 256, lds, st>>>(b);
     return hipGetLastError();
 }
 

@@ -483,12 +483,12 @@ __global__ __launch_bounds__(256) void k_predict_batch(BatchArgs b) {
 
 __global__ __launch_bounds__(512) void k_gn_step_batch(BatchArgs b) {
     const AgentDesc& D = *b.d[blockIdx.x];
-    gn_step_block(D.S, D.partials, D.track_blocks, D.rel);
+    gn_step_block(D.S, D.partials, D.obj_blocks, D.rel);
 }
 
 __global__ __launch_bounds__(512) void k_laplace_combine_batch(BatchArgs b) {
     const AgentDesc& D = *b.d[blockIdx.x];
-    laplace_combine_block(D.S, D.partials, D.track_blocks, D.ema, D.min_inliers);
+    laplace_combine_block(D.S, D.partials, D.obj_blocks, D.ema, D.min_inliers);
 }
 
 __global__ __launch_bounds__(64) void k_first_frame_batch(BatchArgs b) { first_frame_block(b.d[blockIdx.x]->S); }

@@ -28,6 +28,7 @@ PRISM_BUSY = 4
 PRISM_CAPTURE_ERROR = 5
 SUBMIT_FROM_HOST = 1
 SUBMIT_EAGER = 2
+SUBMIT_GRAPH = 4
 
 
 class PrismError(RuntimeError):

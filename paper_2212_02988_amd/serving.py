@@ -13,8 +13,9 @@ resident in HBM for the stream's lifetime.  Frames arrive at their own pace
   are spread over a small pool of HIP streams at admission), and one library
   call (prism_filter_step_batch) stages their frames into their slots and runs
   the whole step for all of them with one kernel launch per stage, ragged over
-  their different image and map sizes; frames arriving while a batch runs
-  join the next one.  (batched=False submits each stream's step on its own,
+  their different image and map sizes (batch_graphs=True: the stages replayed
+  from a HIP graph recorded per member set and slots); frames arriving while a
+  batch runs join the next one.  (batched=False submits each stream's step on its own,
   as a HIP graph recorded per slot.)  Completions come from the library's
   per-slot events (prism_filter_poll on one member per batch);
 * allows up to ``depth`` steps of one agent in flight (they are ordered on its
@@ -147,7 +148,7 @@ class ServingLoop:
 
     def __init__(self, hbm_budget: Optional[int] = None, n_hip_streams: int = 4, depth: int = 2,
                  staged: bool = False, use_graphs: bool = True, reserve: int = 2 << 30, keep_final: bool = False,
-                 batched: bool = True):
+                 batched: bool = True, batch_graphs: bool = True):
         free, _ = torch.cuda.mem_get_info()
         cap = max(0, free - reserve)
         self.budget = cap if hbm_budget is None else min(int(hbm_budget), cap)
@@ -156,6 +157,7 @@ class ServingLoop:
         self.staged = staged
         self.use_graphs = use_graphs
         self.batched = batched
+        self.batch_graphs = batch_graphs   # batched steps replayed from graphs recorded per member set
         self.keep_final = keep_final
         self.batches = 0
         # launched batches per HIP stream, oldest first: (agents, probe agent,
@@ -276,8 +278,9 @@ class ServingLoop:
                         groups[id(ag.stream)].append(ag)
                 for ags in groups.values():
                     t0 = time.perf_counter()
+                    fl = (ags[0].flags & P.SUBMIT_FROM_HOST) | (P.SUBMIT_GRAPH if self.batch_graphs else 0)
                     ok = P.filter_step_batch([ag.filter for ag in ags], [ag.source() for ag in ags],
-                                             stream=ags[0].stream, flags=ags[0].flags & P.SUBMIT_FROM_HOST)
+                                             stream=ags[0].stream, flags=fl)
                     self.host_submit_s += time.perf_counter() - t0
                     if ok:
                         for ag in ags:

@@ -199,21 +199,26 @@ def test_submit_poll_via_c_abi():
 
 
 @pytest.mark.gpu
-def test_step_batch_matches_single_steps():
+@pytest.mark.parametrize("graphs", [False, True])
+def test_step_batch_matches_single_steps(graphs):
     """prism_filter_step_batch over filters of different image sizes, grid
-    sizes, storage types and Gauss-Newton counts, one of them joining (first
-    frame) while the others are mid-trajectory: every filter's state and map
-    equal its own sequence of prism_filter_step calls, bit for bit."""
+    sizes, storage types, objectives (P2 and the render-through P1) and
+    Gauss-Newton counts, one of them joining (first frame) while the others
+    are mid-trajectory: every filter's state and map equal its own sequence
+    of prism_filter_step calls, bit for bit -- with every batch launched
+    stage by stage, and replayed from the graphs recorded per member set,
+    slots and first-frame states (graphs=True)."""
     import dataclasses
     import torch
     from gpu_util import banner, P
-    banner("prism_filter_step_batch vs single steps (mixed batch)")
+    banner(f"prism_filter_step_batch vs single steps (mixed batch, graphs={graphs})")
     Pm = P()
     specs, frames = _specs(n_streams=4, n_frames=6)
-    kinds = [(Pm.PRISM_F32, 3), (Pm.PRISM_BF16, 2), (Pm.PRISM_BF16, 3), (Pm.PRISM_F32, 1)]
-    for sp, (dt, ngn) in zip(specs, kinds):
+    kinds = [(Pm.PRISM_F32, 3, Pm.OBJ_P2), (Pm.PRISM_BF16, 2, Pm.OBJ_P1), (Pm.PRISM_BF16, 3, Pm.OBJ_P2),
+             (Pm.PRISM_F32, 1, Pm.OBJ_P1)]
+    for sp, (dt, ngn, obj) in zip(specs, kinds):
         sp.grid = Pm.Grid.make(sp.grid.n, sp.grid.voxel, tuple(sp.grid.origin), dtype=dt)
-        sp.params = dataclasses.replace(sp.params, n_gn=ngn)
+        sp.params = dataclasses.replace(sp.params, n_gn=ngn, objective=obj)
     join = {0: 0, 1: 0, 2: 0, 3: 2}        # frame index at which each filter starts
     s = torch.cuda.Stream()
     ref, bat = [], []
@@ -240,7 +245,7 @@ def test_step_batch_matches_single_steps():
                 ref[i].step(D[k], C[k], u, stream=s)
                 members.append(bat[i])
                 srcs.append((D[k], C[k], u))
-            assert Pm.filter_step_batch(members, srcs, stream=s)
+            assert Pm.filter_step_batch(members, srcs, stream=s, flags=Pm.SUBMIT_GRAPH if graphs else 0)
             torch.cuda.synchronize()          # both slots are reused across iterations
     torch.cuda.synchronize()
     assert Pm.filters_poll(bat) == [6, 6, 6, 4]
