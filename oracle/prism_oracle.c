@@ -25,7 +25,8 @@
  * pixel a voxel projects to, the anchor pixel a point associates with), the
  * caller can ask for that decision to be taken in IEEE single precision with
  * a fixed operation order ("decide32"), the precision the GPU kernels decide
- * in.  That recipe is written out below in plain C with no contraction.
+ * in.  That recipe is written out below in plain C with no implicit
+ * contraction (fmaf where the recipe fuses a multiply and an add).
  *
  * Layouts: dense maps are double [4][N][N][N] (channel, k, j, i), x fastest;
  * channel 0 occupancy, 1..3 RGB.  Images are row-major [H][W] (rgb [H][W][3]).
@@ -151,13 +152,14 @@ static void dec32_dir(const dec32 *d, int u, int v, float dir[3]) {
  * Sample k sits at depth d_near + k*dstep along the ray (App. B sampling);
  * its continuous grid coordinate is written as A + k*B with the per-ray
  * terms B = (dir*dstep)/voxel and A = ((t + d_near*dir) - origin)/voxel - 1/2,
- * in this order, 1/voxel rounded once. */
+ * in this order, 1/voxel rounded once; A + k*B and each linear blend
+ * a + w*(b - a) are rounded once (fmaf: the exact product-sum, one rounding). */
 static float dec32_sample(const dec32 *d, const double *occ, const float dir[3], int k, int cell[3]) {
     float w[3];
     for (int a = 0; a < 3; ++a) {
         float B = (dir[a] * d->dstep) * d->is;
         float A = ((d->t[a] + d->dn * dir[a]) - d->o[a]) * d->is - 0.5f;
-        float g = A + (float)k * B;
+        float g = fmaf((float)k, B, A);
         float fl = floorf(g);
         /* samples more than 2^30 voxels away never reach the grid */
         int i0 = fl < -1073741824.0f ? -1073741824 : fl > 1073741824.0f ? 1073741824 : (int)fl;
@@ -176,9 +178,9 @@ static float dec32_sample(const dec32 *d, const double *occ, const float dir[3],
             }
     float l[2][2], m[2];
     for (int c = 0; c < 2; ++c)
-        for (int b = 0; b < 2; ++b) l[c][b] = v[c][b][0] + w[0] * (v[c][b][1] - v[c][b][0]);
-    for (int c = 0; c < 2; ++c) m[c] = l[c][0] + w[1] * (l[c][1] - l[c][0]);
-    return m[0] + w[2] * (m[1] - m[0]);
+        for (int b = 0; b < 2; ++b) l[c][b] = fmaf(w[0], v[c][b][1] - v[c][b][0], v[c][b][0]);
+    for (int c = 0; c < 2; ++c) m[c] = fmaf(w[1], l[c][1] - l[c][0], l[c][0]);
+    return fmaf(w[2], m[1] - m[0], m[0]);
 }
 
 /* ---------------------------------------------------------------------- */

@@ -16,7 +16,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # every integer decision is taken in single precision with a fixed
-    # operation order: no FMA contraction anywhere in the library
+    # operation order: no implicit FMA contraction anywhere in the library
+    # (the decision recipe writes its fused multiply-adds out)
     "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",

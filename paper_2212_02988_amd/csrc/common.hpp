@@ -9,9 +9,10 @@
 //           dir_i = (R_i0 rx + R_i1 ry) + R_i2
 //   sample: per ray B_i = (dir_i * dstep) * inv_s and
 //           A_i = ((t_i + d_near * dir_i) - o_i) * inv_s - 0.5f; for sample k
-//           g_i = A_i + (float)k * B_i;  cell = floor(g);  w = g - cell;
+//           g_i = fma((float)k, B_i, A_i);  cell = floor(g);  w = g - cell;
 //           occupancy = lerp_z(lerp_y(lerp_x(corners))) with
-//           lerp(a, b, w) = a + w (b - a)
+//           lerp(a, b, w) = fma(w, b - a, a)
+//           (fma: one rounding of the exact a*b + c, written out explicitly)
 //   voxel:  x_i = o_i + s ((float)i + 0.5f);  d = x - t;
 //           X_a = (R_0a d_0 + R_1a d_1) + R_2a d_2;
 //           u = fx (X_0 / X_2) + cx,  v = fy (X_1 / X_2) + cy
@@ -22,6 +23,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <climits>
 
 #include "../../include/prism.h"
 
@@ -233,12 +235,24 @@ __device__ __forceinline__ RayCoef ray_coef(const GridC& g, const CamC& c, const
     return r;
 }
 
+// continuous grid coordinate of sample fk (an integer held in a float) on axis a
+__device__ __forceinline__ float sample_gc(const RayCoef& r, float fk, int a) {
+    return __builtin_fmaf(fk, r.B[a], r.A[a]);
+}
+
+// floor(x) as an integer in one instruction (saturating outside the int range)
+__device__ __forceinline__ int floor_i32(float x) {
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 __device__ __forceinline__ Cell sample_cell(const RayCoef& r, int k) {
     Cell o;
     const float fk = (float)k;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        float gc = r.A[a] + fk * r.B[a];
+        float gc = sample_gc(r, fk, a);
         float fl = floorf(gc);
         o.i[a] = (int)fl;
         o.w[a] = gc - fl;
@@ -246,7 +260,7 @@ __device__ __forceinline__ Cell sample_cell(const RayCoef& r, int k) {
     return o;
 }
 
-__device__ __forceinline__ float lerp32(float a, float b, float w) { return a + w * (b - a); }
+__device__ __forceinline__ float lerp32(float a, float b, float w) { return __builtin_fmaf(w, b - a, a); }
 
 // Addressing of a trilinear cell whose 8 corners are all inside the grid:
 // the base corner's element index within a plane (32 bits: n <= 1024) and the

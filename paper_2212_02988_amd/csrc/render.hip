@@ -65,25 +65,88 @@ __device__ __forceinline__ bool cell_free(const GridC& g, const FreeBits& fb, co
     return all;
 }
 
-// occupancy of a marched sample, or -1 when the free-space bits prove it is
-// <= 0 (fb: the workgroup's LDS copy, present only when tau == 0)
-template <typename T, bool Pool>
-__device__ __forceinline__ float march_occ(const GridC& g, const T* occ, const FreeBits& fb, const Cell& cl) {
-    if (cell_inside(g, cl)) {
-        CellAddr a = cell_addr(g, cl);
-        if (fb.w && cell_free(g, fb, a)) return -1.0f;
+// Occupancy of marched sample fk (an integer held in a float), or -1 when the
+// free-space bits prove it is <= 0 (fb: the workgroup's LDS copy, present
+// only when tau == 0).  Most marched samples are decided by the bits alone,
+// so that path takes only the cell's base corner and its brick: with the
+// dilated bits every cell inside the grid reads the one bit of the 2x2x2
+// bricks from its base brick, whether or not the cell spans bricks (a
+// spanned brick is in that block; a cell within one brick loses little from
+// the coarser test).  The corner addressing and the weights are formed only
+// for samples that read the map.
+enum BitsMode { kNoBits = 0, kPlainBits = 1, kDilatedBits = 2 };
+
+// grid coordinate of a marched sample and its cell's base corner
+struct SamplePos {
+    float gc[3];
+    int i[3];
+};
+
+__device__ __forceinline__ SamplePos sample_pos(const RayCoef& rc, float fk) {
+    SamplePos p;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        p.gc[a] = sample_gc(rc, fk, a);
+        p.i[a] = floor_i32(p.gc[a]);
+    }
+    return p;
+}
+
+template <typename T, bool Pool, int Bits>
+__device__ __forceinline__ float march_sample(const GridC& g, const T* occ, const FreeBits& fb, const SamplePos& p) {
+    const float* gc = p.gc;
+    const int* i = p.i;
+    const unsigned lim = (unsigned)(g.n - 1);
+    if (max(max((unsigned)i[0], (unsigned)i[1]), (unsigned)i[2]) < lim) {
+        // all 8 corners inside: indices >= 0 and < 2^10, so 24-bit products
+        const unsigned bx = (unsigned)i[0] >> 3, by = (unsigned)i[1] >> 3, bz = (unsigned)i[2] >> 3;
+        const int b0 = (int)(__umul24(bz, (unsigned)(g.nb * g.nb)) + __umul24(by, (unsigned)g.nb) + bx);
+        if constexpr (Bits == kDilatedBits) {
+            // bit b0 of the dilated bits (the bit-field extract takes the low 5 bits of b0)
+            if (__builtin_amdgcn_ubfe(fb.w[fb.dil + (b0 >> 5)], (unsigned)b0, 1u)) return -1.0f;
+        }
+        const int lx = i[0] & 7, ly = i[1] & 7, lz = i[2] & 7;
+        CellAddr a;
+        a.b0 = b0;
+        a.base = (b0 << 9) | (lz << 6) | (ly << 3) | lx;
+        a.dx = lx == 7 ? 512 - 7 : 1;
+        a.dy = ly == 7 ? 512 * g.nb - 56 : 8;
+        a.dz = lz == 7 ? 512 * g.nb * g.nb - 448 : 64;
+        a.cross = (lx == 7) | (ly == 7) | (lz == 7);
+        // plain bits only (the dilated ones did not fit in LDS): per spanned brick
+        if constexpr (Bits == kPlainBits)
+            if (cell_free(g, fb, a)) return -1.0f;
+        // inside the grid g >= 0, where g - floor(g) is exact and fract(g) equals it
+        float w[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) w[q] = __builtin_amdgcn_fractf(gc[q]);
         if constexpr (Pool) {
             // brick-pool map: a single-brick cell through its slot (a brick
             // without one reads as the prior everywhere, and the trilinear
             // blend of equal values is that value); others corner by corner
-            if (a.cross) return occ_at<T, Pool>(g, occ, cl);
-            const int slot = g.table[a.b0];
-            if (slot < 0) return g.pocc;
-            a.base = (slot << 9) | (a.base & 511);
+            if (!a.cross) {
+                const int slot = g.table[b0];
+                if (slot < 0) return g.pocc;
+                a.base = (slot << 9) | (a.base & 511);
+            } else {
+                Cell cl;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) { cl.i[q] = i[q]; cl.w[q] = w[q]; }
+                return occ_at<T, Pool>(g, occ, cl);
+            }
         }
         float v[8];
         corners_in_g(as_global(occ), a, v);
-        return trilerp(v, cl.w);
+        return trilerp(v, w);
+    }
+    // Every corner outside the grid (on some axis both i and i + 1 are): the
+    // blend of 8 equal outside values is that value, lerp(a, a, w) = a.
+    if (max(max((unsigned)i[0] + 1u, (unsigned)i[1] + 1u), (unsigned)i[2] + 1u) > (unsigned)g.n) return g.occ_out;
+    Cell cl;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        cl.i[q] = i[q];
+        cl.w[q] = gc[q] - (float)i[q];
     }
     return occ_at<T, Pool>(g, occ, cl);
 }
@@ -290,9 +353,11 @@ __device__ __forceinline__ const BlockPose& block_pose(const prism_pose* pose, B
 // ---------------------------------------------------------------------------
 // quad (four lanes per ray) march and shading
 // ---------------------------------------------------------------------------
+// minimum over the four lanes of a quad (DPP quad permutations: lanes 1,0,3,2
+// then 2,3,0,1; a lane whose partner is inactive keeps its own value)
 __device__ __forceinline__ int quad_min(int x) {
-    x = min(x, __shfl_xor(x, 1, 64));
-    x = min(x, __shfl_xor(x, 2, 64));
+    x = min(x, __builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false));
+    x = min(x, __builtin_amdgcn_update_dpp(x, x, 0x4E, 0xF, 0xF, false));
     return x;
 }
 
@@ -308,17 +373,36 @@ __device__ __forceinline__ float quad_bcastf(float x, int src_lane_in_quad) {
 
 // first sample index whose occupancy exceeds tau (strictly), or -1; every
 // lane of the quad returns the same value
-template <typename T, bool Pool>
-__device__ __forceinline__ int march_quad(const GridC& g, const CamC& c, const RayCoef& rc, const T* occ,
-                                          const FreeBits& fb, int s) {
+template <typename T, bool Pool, int Bits>
+__device__ __forceinline__ int march_quad_b(const GridC& g, const CamC& c, const RayCoef& rc, const T* occ,
+                                            const FreeBits& fb, int s) {
     constexpr int G = kLanes * kPerLane;
-    for (int k0 = 0; k0 < c.K; k0 += G) {
+    // the sample index as a float, advanced exactly (K < 2^24); the last trip's
+    // samples past K - 1 are evaluated like any other and ignored
+    float fk0 = (float)s;
+    // The sample recipe is monotone in k on every axis, so once a sample's
+    // cell lies past the grid on an axis the ray moves away from it along,
+    // so do all later cells: their occupancy is the outside value.  When that
+    // value cannot cross tau the ray has no first crossing left.  The test
+    // per axis: cell index < lo (ray not moving up) or >= hi (not moving down).
+    const bool stop_outside = !(g.occ_out > c.tau);
+    int lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = rc.B[a] <= 0.0f ? -1 : INT_MIN;
+        hi[a] = rc.B[a] >= 0.0f ? g.n : INT_MAX;
+    }
+    for (int k0 = 0; k0 < c.K; k0 += G, fk0 += (float)G) {
         float f[kPerLane];
+        bool gone = false;
 #pragma unroll
         for (int j = 0; j < kPerLane; ++j) {
-            int k = k0 + j * kLanes + s;
-            Cell cl = sample_cell(rc, min(k, c.K - 1));
-            f[j] = march_occ<T, Pool>(g, occ, fb, cl);
+            const SamplePos p = sample_pos(rc, fk0 + (float)(j * kLanes));
+            f[j] = march_sample<T, Pool, Bits>(g, occ, fb, p);
+            if (j == kPerLane - 1) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) gone |= (p.i[a] < lo[a]) | (p.i[a] >= hi[a]);
+            }
         }
         int first = 0x7fffffff;
 #pragma unroll
@@ -328,8 +412,20 @@ __device__ __forceinline__ int march_quad(const GridC& g, const CamC& c, const R
         }
         first = quad_min(first);
         if (first != 0x7fffffff) return first;
+        // lane 3 holds the trip's last sample (DPP quad_perm 3,3,3,3)
+        if (stop_outside && __builtin_amdgcn_update_dpp(0, (int)gone, 0xFF, 0xF, 0xF, false)) return -1;
     }
     return -1;
+}
+
+// the march with the workgroup's free-space bits mode fixed (one uniform
+// branch per ray instead of one per sample)
+template <typename T, bool Pool>
+__device__ __forceinline__ int march_quad(const GridC& g, const CamC& c, const RayCoef& rc, const T* occ,
+                                          const FreeBits& fb, int s) {
+    if (fb.w && fb.dil) return march_quad_b<T, Pool, kDilatedBits>(g, c, rc, occ, fb, s);
+    if (fb.w) return march_quad_b<T, Pool, kPlainBits>(g, c, rc, occ, fb, s);
+    return march_quad_b<T, Pool, kNoBits>(g, c, rc, occ, fb, s);
 }
 
 // This lane's share of the shading at a valid hit: plane s (0 occupancy,
@@ -504,7 +600,9 @@ __device__ __forceinline__ void render_block(int blk, int frame, const GridC& g,
 }
 
 template <typename T, bool Pool>
-__global__ __launch_bounds__(256) void k_render(GridC g, CamC c, GridD gd, CamD cd, const T* __restrict__ map,
+// at least 6 waves per SIMD (80 VGPRs, no spills): the march hides gather
+// latency with waves; 7 or 8 would spill the double-precision shading
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_render(GridC g, CamC c, GridD gd, CamD cd, const T* __restrict__ map,
                                                 const unsigned* __restrict__ gbits,
                                                 const prism_pose* __restrict__ poses,
                                                 float* __restrict__ depth, float* __restrict__ rgb,
@@ -515,7 +613,7 @@ __global__ __launch_bounds__(256) void k_render(GridC g, CamC c, GridD gd, CamD 
 // batched: every filter renders its next anchor from its updated map at its
 // posterior mean
 template <typename T, bool Pool>
-__global__ __launch_bounds__(256) void k_render_batch(BatchArgs b) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_render_batch(BatchArgs b) {
     const int a = batch_agent(b, blockIdx.x);
     const AgentDesc& D = *b.d[a];
     render_block<T, Pool>(blockIdx.x - b.start[a], 0, D.g, D.c, D.gd, D.cd, (const T*)D.map, D.bits, &D.S->pose, D.a_depth,
