@@ -289,8 +289,6 @@ __device__ __forceinline__ CellAddr cell_addr(const GridC& g, const Cell& c) {
     return a;
 }
 
-__device__ __forceinline__ float ldu(const float* p, unsigned i) { return p[i]; }
-__device__ __forceinline__ float ldu(const uint16_t* p, unsigned i) { return __uint_as_float(((uint32_t)p[i]) << 16); }
 
 // Explicit address spaces for the hottest loads: through a global-space
 // pointer with a 32-bit byte offset the compiler can use a scalar base and a
@@ -329,19 +327,6 @@ __device__ __forceinline__ void corners_in_g(gptr<T> plane, const CellAddr& a, f
     v[7] = ldg(plane, o + dz + dy + dx);
 }
 
-template <typename T>
-__device__ __forceinline__ void corners_in(const T* plane, const CellAddr& a, float v[8]) {
-    const unsigned o = (unsigned)a.base;
-    v[0] = ldu(plane, o);
-    v[1] = ldu(plane, o + a.dx);
-    v[2] = ldu(plane, o + a.dy);
-    v[3] = ldu(plane, o + a.dy + a.dx);
-    v[4] = ldu(plane, o + a.dz);
-    v[5] = ldu(plane, o + a.dz + a.dx);
-    v[6] = ldu(plane, o + a.dz + a.dy);
-    v[7] = ldu(plane, o + a.dz + a.dy + a.dx);
-}
-
 // 8 corner values of one plane: out-of-grid corners take `outv`, corners in
 // bricks without a slot (brick-pool maps) `priorv`
 template <typename T, bool Pool>
@@ -350,7 +335,7 @@ __device__ __forceinline__ void corners(const GridC& g, const T* plane, const Ce
     if (cell_inside(g, c)) {
         CellAddr a = cell_addr(g, c);
         if constexpr (!Pool) {
-            corners_in(plane, a, v);
+            corners_in_g(as_global(plane), a, v);
             return;
         }
         if (!a.cross) {
@@ -360,7 +345,7 @@ __device__ __forceinline__ void corners(const GridC& g, const T* plane, const Ce
             for (int q = 0; q < 8; ++q) v[q] = priorv;
             if (slot >= 0) {
                 a.base = (slot << 9) | (a.base & 511);
-                corners_in(plane, a, v);
+                corners_in_g(as_global(plane), a, v);
             }
             return;
         }

@@ -20,7 +20,7 @@
 namespace prism {
 
 constexpr int kLanes = 4;       // lanes per ray in render / render_jacobian
-constexpr int kPerLane = 2;     // samples per lane per trip
+constexpr int kPerLane = 4;     // samples per lane per trip
 
 struct RayHit {
     int k;          // k* or -1
@@ -327,7 +327,16 @@ __device__ __forceinline__ FreeBits block_setup(const GridC& g, const unsigned* 
     if (threadIdx.x == 0) raw = *pose;
     FreeBits fb{nullptr, 0};
     const int nwords = free_words(g.nb), nl = gbits ? free_lds_words(nwords) : 0;
-    for (int i = threadIdx.x; i < nl; i += blockDim.x) lbits[i] = gbits[i];
+    if ((reinterpret_cast<uintptr_t>(gbits) & 15) == 0) {
+        // 16-byte copies (the workgroup's LDS copy is 16-byte aligned), then the tail
+        const int n4 = nl >> 2;
+        const uint4* g4 = reinterpret_cast<const uint4*>(gbits);
+        uint4* l4 = reinterpret_cast<uint4*>(lbits);
+        for (int i = threadIdx.x; i < n4; i += blockDim.x) l4[i] = g4[i];
+        for (int i = (n4 << 2) + threadIdx.x; i < nl; i += blockDim.x) lbits[i] = gbits[i];
+    } else {
+        for (int i = threadIdx.x; i < nl; i += blockDim.x) lbits[i] = gbits[i];
+    }
     if (threadIdx.x == 0) {
         quat_to_rot64(raw, sp->d.R);
         for (int i = 0; i < 3; ++i) sp->d.t[i] = raw.t[i];
@@ -442,12 +451,16 @@ struct QuadShade {
 
 // Trilinear value of one plane in double precision at a marched sample:
 // cell from the decision recipe, weights from the double-precision grid
-// coordinate, sum over the 8 corners of the product of 1-D hat weights (z, y,
-// x order).  The corners are the ones corners() gathered; a corner outside
-// the grid takes the double-precision outside value.
+// coordinate, blended along x, then y, then z (seven linear blends, each one
+// fused multiply-add; the same trilinear interpolant as the sum of the
+// corners weighted by products of 1-D hat weights, to rounding).  The
+// corners are the ones corners() gathered; a corner outside the grid takes
+// the double-precision outside value.
+__device__ __forceinline__ double lerp64(double a, double b, double w) { return __builtin_fma(w, b - a, a); }
+
 __device__ __forceinline__ double tri64c(const GridC& g, const float v[8], const double gc[3], const int cell[3],
                                          double outv) {
-    double w0 = gc[0] - (double)cell[0], w1 = gc[1] - (double)cell[1], w2 = gc[2] - (double)cell[2];
+    const double w0 = gc[0] - (double)cell[0], w1 = gc[1] - (double)cell[1], w2 = gc[2] - (double)cell[2];
     // a cell inside the grid (the usual case) needs no test per corner
     const unsigned lim = (unsigned)(g.n - 1);
     const bool inside = (unsigned)cell[0] < lim && (unsigned)cell[1] < lim && (unsigned)cell[2] < lim;
@@ -463,19 +476,9 @@ __device__ __forceinline__ double tri64c(const GridC& g, const float v[8], const
             V[q] = in ? (double)v[q] : outv;
         }
     }
-    double s = 0.0;
-#pragma unroll
-    for (int cz = 0; cz < 2; ++cz)
-#pragma unroll
-        for (int cy = 0; cy < 2; ++cy)
-#pragma unroll
-            for (int cx = 0; cx < 2; ++cx) {
-                double hx = cx ? w0 : 1.0 - w0;
-                double hy = cy ? w1 : 1.0 - w1;
-                double hz = cz ? w2 : 1.0 - w2;
-                s += hx * hy * hz * V[cx + 2 * cy + 4 * cz];
-            }
-    return s;
+    const double l00 = lerp64(V[0], V[1], w0), l10 = lerp64(V[2], V[3], w0);
+    const double l01 = lerp64(V[4], V[5], w0), l11 = lerp64(V[6], V[7], w0);
+    return lerp64(lerp64(l00, l10, w1), lerp64(l01, l11, w1), w2);
 }
 
 template <typename T, bool Pool>
@@ -569,7 +572,7 @@ __device__ __forceinline__ void render_block(int blk, int frame, const GridC& g,
                                              float* __restrict__ depth, float* __restrict__ rgb,
                                              uint8_t* __restrict__ mask, int32_t* __restrict__ hit_k) {
     __shared__ BlockPose sp;
-    extern __shared__ unsigned lbits[];
+    extern __shared__ __align__(16) unsigned lbits[];
     const FreeBits fb = block_setup(g, gbits, lbits, pose, &sp);
     const BlockPose& P = sp;
     int u, v, s;
@@ -712,7 +715,7 @@ __device__ __forceinline__ void render_jac_block(int blk, int frame, const GridC
                                                  double* __restrict__ partial_row) {
     __shared__ BlockPose sp;
     __shared__ double lds[kRedLds];
-    extern __shared__ unsigned lbits[];
+    extern __shared__ __align__(16) unsigned lbits[];
     const FreeBits fb = block_setup(g, gbits, lbits, pose, &sp);
     const BlockPose& P = sp;
     int u, v, s;
@@ -776,7 +779,8 @@ __device__ __forceinline__ void render_jac_block(int blk, int frame, const GridC
 }
 
 template <typename T, bool Pool>
-__global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, GridD gd, CamD cd, const T* __restrict__ map,
+// at least 5 waves per SIMD (96 VGPRs, no spills; 4 without the cap)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_render_jac(GridC g, CamC c, GridD gd, CamD cd, const T* __restrict__ map,
                                                     const unsigned* __restrict__ gbits,
                                                     const prism_pose* __restrict__ poses,
                                                     const float* __restrict__ obs_depth,
@@ -793,7 +797,7 @@ __global__ __launch_bounds__(256) void k_render_jac(GridC g, CamC c, GridD gd, C
 // batched: the render-through objective of every filter at its current
 // iterate with its slot's frame (one frame each)
 template <typename T, bool Pool>
-__global__ __launch_bounds__(256) void k_render_jac_batch(BatchArgs b) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_render_jac_batch(BatchArgs b) {
     const int a = batch_agent(b, blockIdx.x);
     const AgentDesc& D = *b.d[a];
     const prism_frame& fr = D.slots[b.slot[a]];
@@ -997,7 +1001,7 @@ __global__ __launch_bounds__(256) void k_gd_grad(GridC g, CamC c, GridD gd, CamD
     __shared__ BlockPose sp;
     __shared__ double wsum[4];
     __shared__ GdAgg A;
-    extern __shared__ unsigned lbits[];
+    extern __shared__ __align__(16) unsigned lbits[];
     for (int e = threadIdx.x; e < 4 * kAggSlots; e += 256) {
         (&A.key[0][0])[e] = -1;
         (&A.val[0][0])[e] = 0.0;
