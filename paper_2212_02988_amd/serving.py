@@ -57,6 +57,7 @@ class _Frame:
     rgb: object                      # [H, W, 3]
     u: object                        # [6] float64 or None (first frame)
     index: int
+    ready: object = None             # torch.cuda.Event after which device frames are complete
 
 
 def footprint_bytes(spec: StreamSpec, depth: int = 2, staged: bool = False) -> int:
@@ -109,6 +110,8 @@ class _Agent:
         into this step's pinned host slot first)."""
         fr = self.pending[0]
         if not self.staged:
+            if fr.ready is not None:
+                self.stream.wait_event(fr.ready)     # the frame's producer, on another stream
             return fr.depth, fr.rgb, fr.u
         hd, hc, hu = self.host[self.launched % self.depth]
         hd.numpy()[...] = fr.depth
@@ -226,8 +229,13 @@ class ServingLoop:
         self._admit()
 
     # ---- frames ----------------------------------------------------------
-    def push_frame(self, stream_id: int, arrival: float, depth, rgb, u, index: int):
-        fr = _Frame(arrival, depth, rgb, u, index)
+    def push_frame(self, stream_id: int, arrival: float, depth, rgb, u, index: int, ready=None):
+        """Queue a frame.  Device frames (staged=False) are read by the
+        library on the agent's HIP stream, which does not otherwise wait for
+        the stream that wrote them: pass `ready`, a torch.cuda.Event recorded
+        on the producing stream after the frame's tensors were written, or
+        push only frames that are already complete (e.g. synchronized)."""
+        fr = _Frame(arrival, depth, rgb, u, index, ready)
         ag = self.agents.get(stream_id)
         if ag is None:
             self.waiting[stream_id].append(fr)       # queued on the host until the stream is admitted
@@ -341,8 +349,9 @@ def run_schedule(loop: ServingLoop, specs: List[StreamSpec], schedule: List[tupl
         now = time.perf_counter() - t0
         while i < len(schedule) and (not realtime or schedule[i][0] <= now):
             ta, sid, idx = schedule[i]
-            d, c, u = frame_source(sid, idx)
-            loop.push_frame(sid, t0 + (ta if realtime else 0.0), d, c, u, idx)
+            src = frame_source(sid, idx)     # (depth, rgb, u) or (depth, rgb, u, ready event)
+            loop.push_frame(sid, t0 + (ta if realtime else 0.0), src[0], src[1], src[2], idx,
+                            ready=src[3] if len(src) > 3 else None)
             i += 1
         loop.poll()
         loop.tick()

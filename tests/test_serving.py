@@ -102,6 +102,38 @@ def test_serving_graph_eager_and_staged_agree():
 
 
 @pytest.mark.gpu
+def test_serving_waits_for_frames_from_another_stream():
+    """Device frames written on a producer stream (behind a spin) and pushed
+    with the producer's event: the agents' streams wait for them, so the
+    results equal a run on frames that were complete when pushed."""
+    import torch
+    from gpu_util import banner
+    banner("serving: frames produced on another HIP stream, pushed with an event")
+    specs, frames = _specs(n_streams=2, n_frames=5)
+    ids = [s.stream_id for s in specs]
+    ref, _ = _run(specs, frames, ids)
+    prod = torch.cuda.Stream()
+    keep = []
+
+    def produced(sid, k):
+        D, C, U, _ = frames[sid]
+        with torch.cuda.stream(prod):
+            torch.cuda._sleep(2_000_000)                 # the producer is still busy when the step is launched
+            d, c = D[k].clone(), C[k].clone()
+            u = None if k == 0 else U[k - 1].clone()
+            ev = torch.cuda.Event()
+            ev.record(prod)
+        keep.append((d, c, u))
+        return d, c, u, ev
+
+    from paper_2212_02988_amd.serving import ServingLoop, run_schedule
+    loop = ServingLoop(keep_final=True)
+    run_schedule(loop, [specs[i] for i in ids], _schedule(specs, frames, ids), produced, realtime=False, timeout=120)
+    for i in ids:
+        _same(ref.final[i], loop.final[i])
+
+
+@pytest.mark.gpu
 def test_serving_realtime_latency_and_budget_errors():
     from gpu_util import banner, P
     from paper_2212_02988_amd.serving import ServingLoop
