@@ -313,11 +313,17 @@ template <typename T>
 __device__ __forceinline__ __attribute__((address_space(1))) T* plane_w(T* map, const GridC& g, int p) {
     return (__attribute__((address_space(1))) T*)(map + (long long)p * g.nvox);
 }
-__device__ __forceinline__ float ldp(gptr<float> p, unsigned i) { return p[i]; }
-__device__ __forceinline__ float ldp(gptr<uint16_t> p, unsigned i) { return __uint_as_float(((uint32_t)p[i]) << 16); }
-__device__ __forceinline__ void stp(__attribute__((address_space(1))) float* p, unsigned i, float v) { p[i] = v; }
+// Element i of a plane through a 32-bit byte offset (a plane holds at most
+// 2^30 elements of at most 4 bytes): the plane's base stays in scalar
+// registers and one vector offset serves all eight planes (an element index
+// scaled in 64 bits would take a 64-bit vector address per plane).
+__device__ __forceinline__ float ldp(gptr<float> p, unsigned i) { return ldg(p, i * 4u); }
+__device__ __forceinline__ float ldp(gptr<uint16_t> p, unsigned i) { return ldg(p, i * 2u); }
+__device__ __forceinline__ void stp(__attribute__((address_space(1))) float* p, unsigned i, float v) {
+    *(__attribute__((address_space(1))) float*)((__attribute__((address_space(1))) char*)p + i * 4u) = v;
+}
 __device__ __forceinline__ void stp(__attribute__((address_space(1))) uint16_t* p, unsigned i, float v) {
-    p[i] = f2bf(v);
+    *(__attribute__((address_space(1))) uint16_t*)((__attribute__((address_space(1))) char*)p + i * 2u) = f2bf(v);
 }
 
 // workgroup blk of ngroups of the update
@@ -400,7 +406,7 @@ __device__ __forceinline__ void map_update_block(int blk, int ngroups, const Gri
         }
 #pragma unroll
         for (int h = 0; h < 8; ++h)
-            if (upd[h]) Dv[h] = depth[pix[h]];
+            if (upd[h]) Dv[h] = ldg(as_global(depth), (unsigned)pix[h] * 4u);
 #pragma unroll
         for (int h = 0; h < 8; ++h) {
             if (upd[h]) {
@@ -470,7 +476,7 @@ __device__ __forceinline__ void map_update_block(int blk, int ngroups, const Gri
                     }
                     const int px = pix[h];
 #pragma unroll
-                    for (int ch = 0; ch < 3; ++ch) lc[hh][ch] = rgb[3 * px + ch];
+                    for (int ch = 0; ch < 3; ++ch) lc[hh][ch] = ldg(as_global(rgb), (unsigned)(3 * px + ch) * 4u);
                 } else if (need_occ) {
                     lv[hh][0] = ldp(plane_g(map, g, 0), id);
                 }
@@ -499,45 +505,30 @@ __device__ __forceinline__ void map_update_block(int blk, int ngroups, const Gri
                 double dd1 = (gd.o[1] + gd.s * ((double)j + 0.5)) - Q.t[1];
                 double dd2 = (gd.o[2] + gd.s * ((double)k + 0.5)) - Q.t[2];
                 double zc = Q.R[0][2] * dd0 + Q.R[1][2] * dd1 + Q.R[2][2] * dd2;
-                double f[4];
-                f[0] = zc - (double)Dv[h];
-                if (f[0] < -mp.trunc) f[0] = -mp.trunc;
-                f[1] = (double)lc[hh][0];
-                f[2] = (double)lc[hh][1];
-                f[3] = (double)lc[hh][2];
-                double mu[4], var[4];
-#pragma unroll
-                for (int ch = 0; ch < 4; ++ch) {
-                    mu[ch] = fresh ? (double)(ch == 0 ? g.pocc : g.prgb) : (double)lv[hh][ch];
-                    var[ch] = fresh ? (double)pvar : (double)lv[hh][4 + ch];
-                }
+                double f0 = zc - (double)Dv[h];
+                if (f0 < -mp.trunc) f0 = -mp.trunc;
                 // App. D: new precision = old + update precision; new mean =
                 // inverse of the new precision times the precision-weighted sum.
                 // The four channels of a voxel are always updated together with
                 // one update precision, so their variances are normally equal bit
                 // for bit: the precision algebra is then done once (same inputs,
-                // same operations, same results as per channel).
-                double lam[4], var2[4];
-                if (var[0] == var[1] && var[1] == var[2] && var[2] == var[3]) {
-                    double l = 1.0 / var[0];
-                    double v2 = 1.0 / (l + mp.lam_u);
-#pragma unroll
-                    for (int ch = 0; ch < 4; ++ch) {
-                        lam[ch] = l;
-                        var2[ch] = v2;
-                    }
-                } else {
-#pragma unroll
-                    for (int ch = 0; ch < 4; ++ch) {
-                        lam[ch] = 1.0 / var[ch];
-                        var2[ch] = 1.0 / (lam[ch] + mp.lam_u);
-                    }
-                }
+                // same operations, same results as per channel).  Channels are
+                // valued one after another (few double-precision registers live).
+                const float vs0 = fresh ? pvar : lv[hh][4];
+                const bool same = fresh || (lv[hh][4] == lv[hh][5] && lv[hh][5] == lv[hh][6] && lv[hh][6] == lv[hh][7]);
+                double lam = 1.0 / (double)vs0;
+                double var2 = 1.0 / (lam + mp.lam_u);
 #pragma unroll
                 for (int ch = 0; ch < 4; ++ch) {
-                    float nm = (float)(var2[ch] * (lam[ch] * mu[ch] + mp.lam_u * f[ch]));
+                    if (ch > 0 && !same) {
+                        lam = 1.0 / (double)lv[hh][4 + ch];
+                        var2 = 1.0 / (lam + mp.lam_u);
+                    }
+                    const double mu = fresh ? (double)(ch == 0 ? g.pocc : g.prgb) : (double)lv[hh][ch];
+                    const double fc = ch == 0 ? f0 : (double)lc[hh][ch - 1];
+                    float nm = (float)(var2 * (lam * mu + mp.lam_u * fc));
                     stp(plane_w(map, g, ch), id, nm);
-                    stp(plane_w(map, g, 4 + ch), id, (float)var2[ch]);
+                    stp(plane_w(map, g, 4 + ch), id, (float)var2);
                     if (ch == 0) m = fmaxf(m, stored<T>(nm));
                 }
                 ++cnt;
