@@ -123,9 +123,14 @@ __device__ __forceinline__ void p2_pixel(const CamC& c, const CamD& cd, const Re
         for (int ch = 0; ch < 3; ++ch) {
             double I00 = a_rgb[3 * q00 + ch], I10 = a_rgb[3 * (q00 + 1) + ch];
             double I01 = a_rgb[3 * (q00 + c.W) + ch], I11 = a_rgb[3 * (q00 + c.W + 1) + ch];
-            double Ii = (1 - ax) * (1 - ay) * I00 + ax * (1 - ay) * I10 + (1 - ax) * ay * I01 + ax * ay * I11;
-            float gu = (float)((1 - ay) * (I10 - I00) + ay * (I11 - I01));
-            float gv = (float)((1 - ax) * (I01 - I00) + ax * (I11 - I10));
+            // bilinear value and its image gradient as linear blends (fused
+            // multiply-adds; the same interpolant as the hat-weight sum, to
+            // rounding): rows blended along x, then the rows along y
+            const double d0 = I10 - I00, d1 = I11 - I01;
+            const double t0 = __builtin_fma(ax, d0, I00), t1 = __builtin_fma(ax, d1, I01);
+            double Ii = __builtin_fma(ay, t1 - t0, t0);
+            float gu = (float)__builtin_fma(ay, d1 - d0, d0);
+            float gv = (float)(t1 - t0);
             double rp = Ii - (double)orgb[ch];
             r[1 + ch] = rp;
             l1 += fabs(rp);
