@@ -105,31 +105,40 @@ __device__ inline void chol_inverse(const double* L, double* Ainv) {
     __syncthreads();
 }
 
-// fixed-order block sum of partial normal equations into lds_out[29]; each
-// thread loads two rows per round so a few hundred to a few thousand rows
-// take only a couple of dependent memory round trips
+// Fixed-order block sum of partial normal equations (nblocks rows of 29
+// doubles) into lds_out[29].  The rows are read as one flat array with
+// coalesced loads: thread t < 29 G (G = row groups) reads elements t, t + 29 G,
+// ... which all belong to column t mod 29, keeping eight independent partial
+// sums in flight; the G sums of each column are then added in row-group order.
+// (Each thread reading whole rows made every load instruction touch 64 cache
+// lines, which one workgroup's vector memory path takes serially.)
 __device__ inline void sum_partials(const double* __restrict__ partials, int nblocks, double* lds_red,
                                     double* lds_out) {
-    double acc[PRISM_NEQ];
+    const int bd = min((int)blockDim.x, kRedLds);
+    const int G = bd / PRISM_NEQ, span = G * PRISM_NEQ;
+    const int t = threadIdx.x;
+    double acc = 0.0;
+    if (t < span) {
+        const long long total = (long long)nblocks * PRISM_NEQ;
+        double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        long long e = t;
+        for (; e + 7LL * span < total; e += 8LL * span) {
+            double x[8];
 #pragma unroll
-    for (int q = 0; q < PRISM_NEQ; ++q) acc[q] = 0.0;
-    const int bd = blockDim.x;
-    int b = threadIdx.x;
-    for (; b + bd < nblocks; b += 2 * bd) {
-        double x[PRISM_NEQ], y[PRISM_NEQ];
+            for (int u = 0; u < 8; ++u) x[u] = partials[e + u * (long long)span];
 #pragma unroll
-        for (int q = 0; q < PRISM_NEQ; ++q) {
-            x[q] = partials[(long long)b * PRISM_NEQ + q];
-            y[q] = partials[(long long)(b + bd) * PRISM_NEQ + q];
+            for (int u = 0; u < 8; ++u) a[u] += x[u];
         }
-#pragma unroll
-        for (int q = 0; q < PRISM_NEQ; ++q) acc[q] += x[q] + y[q];
+        for (; e < total; e += span) a[0] += partials[e];
+        acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+        lds_red[t] = acc;
     }
-    if (b < nblocks) {
-#pragma unroll
-        for (int q = 0; q < PRISM_NEQ; ++q) acc[q] += partials[(long long)b * PRISM_NEQ + q];
+    __syncthreads();
+    if (t < PRISM_NEQ) {
+        double sum = 0.0;
+        for (int r = 0; r < G; ++r) sum += lds_red[r * PRISM_NEQ + t];
+        lds_out[t] = sum;
     }
-    block_reduce29(acc, lds_red, lds_out);
     __syncthreads();
 }
 
