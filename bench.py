@@ -786,6 +786,7 @@ def cpu_configs(frames, runs=3):
                 if r.returncode != 0:
                     raise RuntimeError(f"oracle timing config {cfg} failed:\n{r.stderr[-2000:]}")
                 res.append(json.loads(r.stdout.strip().splitlines()[-1]))
+                log(f"oracle config {cfg} on {th} threads: run {len(res)} {res[-1]['seconds']:.3f} s")
             med = sorted(res, key=lambda d: d["seconds"])[len(res) // 2]
             med["seconds_all_runs"] = [round(d["seconds"], 4) for d in res]
             out[f"config{cfg}_{'1core' if th == 1 else f'{th}threads'}"] = med
