@@ -92,7 +92,7 @@ __device__ __forceinline__ SamplePos sample_pos(const RayCoef& rc, float fk) {
     return p;
 }
 
-template <typename T, bool Pool, int Bits>
+template <typename T, bool Pool, int Bits, bool DilTested = false>
 __device__ __forceinline__ float march_sample(const GridC& g, const T* occ, const FreeBits& fb, const SamplePos& p) {
     const float* gc = p.gc;
     const int* i = p.i;
@@ -101,7 +101,7 @@ __device__ __forceinline__ float march_sample(const GridC& g, const T* occ, cons
         // all 8 corners inside: indices >= 0 and < 2^10, so 24-bit products
         const unsigned bx = (unsigned)i[0] >> 3, by = (unsigned)i[1] >> 3, bz = (unsigned)i[2] >> 3;
         const int b0 = (int)(__umul24(bz, (unsigned)(g.nb * g.nb)) + __umul24(by, (unsigned)g.nb) + bx);
-        if constexpr (Bits == kDilatedBits) {
+        if constexpr (Bits == kDilatedBits && !DilTested) {
             // bit b0 of the dilated bits (the bit-field extract takes the low 5 bits of b0)
             if (__builtin_amdgcn_ubfe(fb.w[fb.dil + (b0 >> 5)], (unsigned)b0, 1u)) return -1.0f;
         }
@@ -404,13 +404,45 @@ __device__ __forceinline__ int march_quad_b(const GridC& g, const CamC& c, const
     for (int k0 = 0; k0 < c.K; k0 += G, fk0 += (float)G) {
         float f[kPerLane];
         bool gone = false;
+        if constexpr (Bits == kDilatedBits) {
+            // the round's free-space tests first, as straight-line code, so its
+            // LDS reads are in flight together (a sample outside the grid reads
+            // word 0 and ignores it); then the samples the bits do not decide,
+            // whose position is formed again (a few instructions, fewer live
+            // registers than keeping it)
+            const unsigned lim = (unsigned)(g.n - 1);
+            unsigned word[kPerLane];
+            int b0[kPerLane];
+            bool in[kPerLane];
 #pragma unroll
-        for (int j = 0; j < kPerLane; ++j) {
-            const SamplePos p = sample_pos(rc, fk0 + (float)(j * kLanes));
-            f[j] = march_sample<T, Pool, Bits>(g, occ, fb, p);
-            if (j == kPerLane - 1) {
+            for (int j = 0; j < kPerLane; ++j) {
+                const SamplePos p = sample_pos(rc, fk0 + (float)(j * kLanes));
+                const int* i = p.i;
+                in[j] = max(max((unsigned)i[0], (unsigned)i[1]), (unsigned)i[2]) < lim;
+                const int b = (int)(__umul24((unsigned)i[2] >> 3, (unsigned)(g.nb * g.nb)) +
+                                    __umul24((unsigned)i[1] >> 3, (unsigned)g.nb) + ((unsigned)i[0] >> 3));
+                b0[j] = in[j] ? b : 0;
+                word[j] = fb.w[fb.dil + (b0[j] >> 5)];
+                if (j == kPerLane - 1) {
 #pragma unroll
-                for (int a = 0; a < 3; ++a) gone |= (p.i[a] < lo[a]) | (p.i[a] >= hi[a]);
+                    for (int a = 0; a < 3; ++a) gone |= (i[a] < lo[a]) | (i[a] >= hi[a]);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kPerLane; ++j) {
+                const bool fr = in[j] && __builtin_amdgcn_ubfe(word[j], (unsigned)b0[j], 1u);
+                f[j] = fr ? -1.0f
+                          : march_sample<T, Pool, Bits, true>(g, occ, fb, sample_pos(rc, fk0 + (float)(j * kLanes)));
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kPerLane; ++j) {
+                const SamplePos p = sample_pos(rc, fk0 + (float)(j * kLanes));
+                f[j] = march_sample<T, Pool, Bits>(g, occ, fb, p);
+                if (j == kPerLane - 1) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) gone |= (p.i[a] < lo[a]) | (p.i[a] >= hi[a]);
+                }
             }
         }
         int first = 0x7fffffff;

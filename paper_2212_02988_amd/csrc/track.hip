@@ -63,6 +63,12 @@ __device__ __forceinline__ void p2_pixel(const CamC& c, const CamD& cd, const Re
     int q00 = biy * c.W + bix;
     if (pho) pho = a_mask[q00] && a_mask[q00 + 1] && a_mask[q00 + c.W] && a_mask[q00 + c.W + 1];
     if (!(geo || pho)) return;
+    {
+    // the value path may fuse multiplies and adds: the pixel decisions above
+    // stay in the fixed single-precision recipe; the residual gates below
+    // compare double-precision values, which differ from the oracle's by
+    // rounding either way
+#pragma clang fp contract(fast)
     // values in double precision: back-projected point, moved into the
     // anchor camera; Jacobians in single precision
     const Pose64& Pc = rel.cur;
@@ -138,6 +144,7 @@ __device__ __forceinline__ void p2_pixel(const CamC& c, const CamD& cd, const Re
             for (int m = 0; m < 6; ++m) J[1 + ch][m] = fmaf(gv, dvm[m], gu * dum[m]);
         }
         if (l1 <= wt.gate_rgb) rm |= 2;
+    }
     }
 }
 
