@@ -35,6 +35,40 @@ __device__ __forceinline__ float occ_at(const GridC& g, const T* occ, const Cell
     return trilerp(v, c.w);
 }
 
+// Occupancy of a cell that straddles the grid's boundary (on every axis one
+// of its two corner planes is inside; dense maps): corners outside take the
+// outside value.  A brick-order element index is a sum of one term per
+// axis, ((x >> 3) * brick stride + (x & 7) * voxel stride), so the two
+// candidates per axis are formed once, from coordinates clamped into the
+// grid (a clamped corner is loaded and then replaced), and each corner is
+// three adds away: a few dozen instructions instead of eight corners each
+// tested and indexed on its own.
+template <typename T>
+__device__ __forceinline__ float occ_partial(const GridC& g, const T* occ, const Cell& c) {
+    const unsigned bs[3] = {512u, 512u * (unsigned)g.nb, 512u * (unsigned)(g.nb * g.nb)};
+    const unsigned vs[3] = {1u, 8u, 64u};
+    unsigned off[3][2];
+    bool ok[3][2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            const int x = c.i[a] + d;    // in [-1, n] for a straddling cell
+            ok[a][d] = (unsigned)x < (unsigned)g.n;
+            const unsigned xc = (unsigned)min(max(x, 0), g.n - 1);
+            off[a][d] = (__umul24(xc >> 3, bs[a]) + (xc & 7u) * vs[a]) * (unsigned)sizeof(T);
+        }
+    float v[8];
+    const gptr<T> pl = as_global(occ);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
+        const float x = ldg(pl, off[0][dx] + off[1][dy] + off[2][dz]);
+        v[q] = (ok[0][dx] && ok[1][dy] && ok[2][dz]) ? x : g.occ_out;
+    }
+    return trilerp(v, c.w);
+}
+
 // True if the free-space bits prove that the sample's occupancy is <= 0:
 // every corner of its cell lies inside the grid and in bricks whose largest
 // occupancy mean is <= 0.  Each lerp of values <= 0 with a weight in [0, 1]
@@ -148,6 +182,7 @@ __device__ __forceinline__ float march_sample(const GridC& g, const T* occ, cons
         cl.i[q] = i[q];
         cl.w[q] = gc[q] - (float)i[q];
     }
+    if constexpr (!Pool) return occ_partial(g, occ, cl);
     return occ_at<T, Pool>(g, occ, cl);
 }
 
