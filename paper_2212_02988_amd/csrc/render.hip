@@ -405,14 +405,37 @@ __device__ __forceinline__ int quad_min(int x) {
     return x;
 }
 
-__device__ __forceinline__ double quad_bcast(double x, int src_lane_in_quad) {
-    int base = (threadIdx.x & 63) & ~3;
-    return __shfl(x, base + src_lane_in_quad, 64);
+// lane 0 of each quad to all four lanes (DPP quad_perm 0,0,0,0; whole quads
+// are active together)
+__device__ __forceinline__ float quad_bcast0f(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x00, 0xF, 0xF, false));
 }
 
-__device__ __forceinline__ float quad_bcastf(float x, int src_lane_in_quad) {
-    int base = (threadIdx.x & 63) & ~3;
-    return __shfl(x, base + src_lane_in_quad, 64);
+// sum over the quad (DPP quad permutations 1,0,3,2 then 2,3,0,1; every lane
+// ends with (x0 + x1) + (x2 + x3) up to the order of each addition)
+__device__ __forceinline__ double quad_xchg(double x, int ctrl_is_2301) {
+    const long long b = __double_as_longlong(x);
+    int lo, hi;
+    if (ctrl_is_2301) {
+        lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x4E, 0xF, 0xF, false);
+        hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x4E, 0xF, 0xF, false);
+    } else {
+        lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0xB1, 0xF, 0xF, false);
+        hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0xB1, 0xF, 0xF, false);
+    }
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double quad_sum(double x) {
+    x += quad_xchg(x, 0);
+    x += quad_xchg(x, 1);
+    return x;
+}
+
+__device__ __forceinline__ double quad_bcast0(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x00, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x00, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
 // first sample index whose occupancy exceeds tau (strictly), or -1; every
@@ -552,6 +575,9 @@ template <typename T, bool Pool>
 __device__ __forceinline__ QuadShade shade_quad(const GridC& g, const GridD& gd, const CamD& cd, const Pose64& P,
                                                 int u, int v, const T* map, const Cell& c0, const Cell& c1, int k,
                                                 int s) {
+    // values only from here (the hit index and cells are decided): the
+    // double-precision arithmetic may fuse multiplies and adds
+#pragma clang fp contract(fast)
     QuadShade q;
     double rc[3], dir[3], gc0[3], gc1[3];
     pixel_dir64(cd, u, v, rc);
@@ -569,8 +595,8 @@ __device__ __forceinline__ QuadShade shade_quad(const GridC& g, const GridD& gd,
     corners<T, Pool>(g, pl, c1, outv32, priorv, q.cv1);
     q.v0 = tri64c(g, q.cv0, gc0, c0.i, outv);
     q.v1 = tri64c(g, q.cv1, gc1, c1.i, outv);
-    q.f0 = quad_bcast(q.v0, 0);
-    q.f1 = quad_bcast(q.v1, 0);
+    q.f0 = quad_bcast0(q.v0);
+    q.f1 = quad_bcast0(q.v1);
     q.alpha = (cd.tau - q.f0) / (q.f1 - q.f0);
     q.value = s == 0 ? q.alpha * d1 + (1.0 - q.alpha) * d0 : q.alpha * q.v1 + (1.0 - q.alpha) * q.v0;
 #pragma unroll
@@ -606,7 +632,7 @@ __device__ __forceinline__ void jac_row_quad(const GridC& g, const QuadShade& q,
     float inv_den = (float)(1.0 / (q.f1 - q.f0));
     float dal[6];
 #pragma unroll
-    for (int m = 0; m < 6; ++m) dal[m] = quad_bcastf(-((1.0f - al) * r0[m] + al * r1[m]) * inv_den, 0);
+    for (int m = 0; m < 6; ++m) dal[m] = quad_bcast0f(-((1.0f - al) * r0[m] + al * r1[m]) * inv_den);
     if (s == 0) {
 #pragma unroll
         for (int m = 0; m < 6; ++m) row[m] = (q.d1 - q.d0) * dal[m];
@@ -813,9 +839,8 @@ __device__ __forceinline__ void render_jac_block(int blk, int frame, const GridC
                 r = s == 0 ? value - (double)D : value - (double)obs_rgb[3 * pix + s - 1];
                 // colour gate on |r_r| + |r_g| + |r_b| (lanes 1-3), depth gate on lane 0
                 double l1 = s == 0 ? 0.0 : fabs(r);
-                l1 += __shfl_xor(l1, 1, 64);
-                l1 += __shfl_xor(l1, 2, 64);
-                bool use_depth = fabs(quad_bcast(r, 0)) <= wt.gate_depth;
+                l1 = quad_sum(l1);
+                bool use_depth = fabs(quad_bcast0(r)) <= wt.gate_depth;
                 bool use_rgb = l1 <= wt.gate_rgb;
                 rm = (use_depth ? 1 : 0) | (use_rgb ? 2 : 0);
                 if (s == 0 ? use_depth : use_rgb)
@@ -1090,9 +1115,8 @@ __global__ __launch_bounds__(256) void k_gd_grad(GridC g, CamC c, GridD gd, CamD
             const QuadShade q = shade_quad<float, false>(g, gd, cd, P.d, u, v, map, c0, c1, k, s);
             const double r = s == 0 ? q.value - (double)D : q.value - (double)obs_rgb[3 * pix + s - 1];
             double l1 = s == 0 ? 0.0 : fabs(r);
-            l1 += __shfl_xor(l1, 1, 64);
-            l1 += __shfl_xor(l1, 2, 64);
-            const bool use_depth = fabs(quad_bcast(r, 0)) <= wt.gate_depth;
+            l1 = quad_sum(l1);
+            const bool use_depth = fabs(quad_bcast0(r)) <= wt.gate_depth;
             const bool use_rgb = l1 <= wt.gate_rgb;
             const bool keep = s == 0 ? use_depth : use_rgb;
             const double w = s == 0 ? wt.w_depth : wt.w_rgb;
