@@ -418,6 +418,15 @@ __device__ __forceinline__ void map_update_block(int blk, int ngroups, const Gri
                 upd[h] = depth_ok(Dv[h]) && X2 <= Dv[h] + mp.trunc32;
             }
         }
+        // a listed brick none of whose voxels this frame updates (in the
+        // frustum but behind the observed surfaces) keeps its values and its
+        // summary: nothing more to read or write
+        {
+            int any = 0;
+#pragma unroll
+            for (int h = 0; h < 8; ++h) any |= upd[h] ? 1 : 0;
+            if (!__any(any)) continue;
+        }
         // brick-pool map: the brick's slot, handed out the first time one of
         // its voxels is updated and filled with the values its voxels read as;
         // with the pool full the brick's update is dropped and counted
@@ -426,10 +435,7 @@ __device__ __forceinline__ void map_update_block(int blk, int ngroups, const Gri
         float pvar = 0.0f;
         if constexpr (Pool) {
             int sl = aux.table[b];
-            int any = 0;
-#pragma unroll
-            for (int h = 0; h < 8; ++h) any |= upd[h] ? 1 : 0;
-            if (sl < 0 && __any(any)) {
+            if (sl < 0) {
                 int got = -1;
                 if (lane == 0) {
                     const int s2 = atomicAdd(&aux.pool[0], 1);
