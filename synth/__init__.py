@@ -75,7 +75,8 @@ def _axis_angle(v: np.ndarray) -> np.ndarray:
 
 def camera_rotation(yaw: float, pitch: float = 0.0, roll: float = 0.0) -> np.ndarray:
     """Camera->world rotation for an optical axis at heading `yaw` (radians
-    about world z), tilted up by `pitch` and rolled by `roll` about the axis."""
+    about world z), tilted by `pitch` (positive lowers the axis towards -z)
+    and rolled by `roll` about the axis."""
     fwd = np.array([math.cos(yaw), math.sin(yaw), 0.0])
     right = np.array([math.sin(yaw), -math.cos(yaw), 0.0])
     down = np.array([0.0, 0.0, -1.0])

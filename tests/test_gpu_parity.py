@@ -121,6 +121,73 @@ def test_render_edge_cases(case1):
         assert np.all(depth_close(out["depth"][0].cpu().numpy()[v], ref["depth"][v]))
 
 
+def _shell_field(n, open_face=False):
+    """Occupancy 0.5 in the outermost voxel layer of the grid and -0.5 inside
+    (colour a ramp along x); with open_face the x = n-1 face is left empty,
+    so rays can leave the grid there."""
+    mean = np.zeros((4, n, n, n))
+    mean[0] = -0.5
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    shell = (x == 0) | (y == 0) | (z == 0) | (y == n - 1) | (z == n - 1)
+    if not open_face:
+        shell |= x == n - 1
+    mean[0][shell] = 0.5
+    for ch in (1, 2, 3):
+        mean[ch] = 0.2 * ch + 0.5 * x / n
+    return mean
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_render_crossings_at_the_grid_boundary(dtype):
+    """Crossings in the cells that straddle the grid's boundary, where some
+    trilinear corners are the outside value: a closed shell of occupied
+    voxels seen from outside (entry through the partial cells) and from
+    inside; an open shell whose outside value is positive (the crossing lies
+    beyond the last voxel, so the march may not stop where it leaves the
+    grid); and the same open shell with the negative default (rays leave the
+    grid and never hit).  hit_k and mask bit-exact, depth to tolerance."""
+    banner(f"render at the grid boundary dtype={dtype}")
+    n, vox = 32, 0.05
+    mid = 0.5 * n * vox           # voxel centres sit at (i + 1/2) voxel
+    cm = synth.Camera(40, 30, 30.0, 30.0, 19.5, 14.5, 0.05, 4.0, 96)
+    cam = cam_of(cm)
+
+    def pose_at(t, yaw, pitch=0.0):
+        return synth.pose7(np.asarray(t, float), orc.rot_to_quat(synth.camera_rotation(yaw, pitch)))
+
+    closed, opened = _shell_field(n), _shell_field(n, open_face=True)
+    cases = [
+        # closed shell, default outside value
+        (closed, -0.001, pose_at((-1.0, mid, mid), 0.0)),
+        (closed, -0.001, pose_at((-0.6, -0.6, -0.3), 0.75, -0.3)),
+        (closed, -0.001, pose_at((mid, mid, mid), 1.0, 0.4)),
+        (closed, -0.001, pose_at((0.1, 0.1, 0.1), 0.7, -0.5)),
+        # open x = n-1 face, positive outside value
+        (opened, 0.5, pose_at((mid, mid, mid), 0.0)),
+        (opened, 0.5, pose_at((mid, mid + 0.2, mid - 0.1), 0.3, -0.2)),
+        (opened, 0.5, pose_at((2.5, mid, mid), np.pi)),
+        # open face, default outside value
+        (opened, -0.001, pose_at((mid, mid, mid), 0.0)),
+        (opened, -0.001, pose_at((2.5, mid, mid), np.pi)),
+    ]
+    n_valid = n_invalid = 0
+    for field, occ_out, pose in cases:
+        g = P().Grid.make(n, vox, (0.0, 0.0, 0.0), dtype, occ_out=occ_out)
+        vm = gpu_map(g, field, np.ones_like(field))
+        og = orc.Grid(n, vox, (0.0, 0.0, 0.0), occ_out=occ_out)
+        out = P().render(g, vm, cam, P().poses_tensor(pose), hit_k=True)
+        ref = orc.render(og, oracle_map_values(field, dtype), orc.cam_from(cm), pose)
+        np.testing.assert_array_equal(out["hit_k"][0].cpu().numpy(), ref["hit_k"])
+        np.testing.assert_array_equal(out["mask"][0].cpu().numpy(), ref["mask"])
+        v = ref["mask"] == 1
+        n_valid += int(v.sum())
+        n_invalid += int((~v).sum())
+        assert np.all(depth_close(out["depth"][0].cpu().numpy()[v], ref["depth"][v]))
+        assert np.all(rgb_close(out["rgb"][0].cpu().numpy()[v], ref["rgb"][v]))
+    print(f"[boundary] {n_valid} hits, {n_invalid} misses over {len(cases)} views", flush=True)
+    assert n_valid > 4000 and n_invalid > 1000
+
+
 def test_render_batched_frames(case1):
     """n_frames > 1 in one launch equals the frames rendered one by one."""
     banner("render batched")
