@@ -176,6 +176,13 @@ class Params:
     sigma_update: float = 1.0    # App. G update scale
     normal_disc: float = 0.1     # depth discontinuity for anchor normals (m)
     objective: str = "p2"        # "p2" surrogate (paper) or "p1" render-through
+    # the paper's literal forms, off by default (each default is a reading)
+    transition_dt2: bool = False  # App. E.1 as printed: v' = v + u dt^2 (default v + u dt)
+    laplace_factor: float = 2.0   # Laplace covariance (factor H_o + Lp)^-1; Sec. 5.1 prints 2, 1 is the
+                                  # covariance of a Gaussian likelihood with precision w
+    irls: bool = False            # Gauss-Newton iterations minimise the L1 data terms of App. E.3 by
+                                  # iteratively reweighted least squares
+    irls_floor: float = 0.01      # IRLS residual floor, as a fraction of each row's Laplace scale b
 
     def weights(self) -> _Weights:
         return _Weights(1.0 / self.b_geo ** 2, 1.0 / self.b_rgb ** 2, self.gate_geo, self.gate_rgb)
@@ -183,6 +190,17 @@ class Params:
 
 def grid_from_scene(scene) -> Grid:
     return Grid(scene.n, scene.voxel, tuple(float(v) for v in scene.origin))
+
+
+def paper_sample_camera(width: int, height: int, fx: float, fy: float, cx: float, cy: float, voxel: float,
+                        max_depth: float, tau: float = 0.0) -> Cam:
+    """Camera whose ray samples are the paper's: depth offsets eps, 2 eps,
+    3 eps, ... (App. B) with eps = 0.4 voxel (App. G rendering), up to the
+    maximum camera depth (App. G: 7, 8 or 20 m): K = floor(max_depth / eps)
+    samples from eps to K eps."""
+    eps = 0.4 * voxel
+    K = int(math.floor(max_depth / eps))
+    return Cam(width, height, fx, fy, cx, cy, eps, K * eps, K, tau)
 
 
 def cam_from(c) -> Cam:
@@ -434,12 +452,14 @@ def neq_unpack(neq: np.ndarray) -> Tuple[np.ndarray, np.ndarray, float, float]:
     return H, np.array(neq[21:27]), float(neq[27]), float(neq[28])
 
 
-def transition_mean(x: Dict[str, np.ndarray], u: np.ndarray, dt: float) -> Dict[str, np.ndarray]:
+def transition_mean(x: Dict[str, np.ndarray], u: np.ndarray, dt: float, dt2: bool = False) -> Dict[str, np.ndarray]:
     """Euler integration (App. B / E.1): velocity first, then the pose with the
     *new* velocity.  Reading: v' = v + u dt (the printed (dt)^2 is read as a
-    typo for an acceleration control)."""
-    v = x["v"] + u[:3] * dt
-    w = x["w"] + u[3:] * dt
+    typo for an acceleration control); dt2 selects the printed form
+    v' = v + u dt^2."""
+    du = dt * dt if dt2 else dt
+    v = x["v"] + u[:3] * du
+    w = x["w"] + u[3:] * du
     t = x["t"] + v * dt
     R = so3_exp(w * dt) @ quat_to_rot(x["q"])
     return dict(t=t, q=rot_to_quat(R), v=v, w=w)
@@ -473,7 +493,7 @@ def transition_jacobians(x_new: Dict[str, np.ndarray], dt: float):
 def predict(x: Dict[str, np.ndarray], P: np.ndarray, u: np.ndarray, p: Params):
     """Closed-form propagation of the Gaussian state belief through the
     linearised transition (App. E.2): returns the prior mean and covariance."""
-    xn = transition_mean(x, u, p.dt)
+    xn = transition_mean(x, u, p.dt, p.transition_dt2)
     M, G = transition_jacobians(xn, p.dt)
     Qd = np.diag([p.sigma_pose_t ** 2] * 3 + [p.sigma_pose_r ** 2] * 3 +
                  [p.sigma_vel_t ** 2] * 3 + [p.sigma_vel_r ** 2] * 3)
@@ -500,6 +520,51 @@ def gn_solve(neq: np.ndarray, Lp: np.ndarray, e_p: np.ndarray) -> np.ndarray:
     b = -(2.0 * g + Lp @ e_p)
     L = np.linalg.cholesky(A)
     return np.linalg.solve(L.T, np.linalg.solve(L, b))
+
+
+def irls_weight(r, b: float, floor: float):
+    """IRLS weight of an L1 row |r|/b (App. E.3 objective) at the current
+    residual r0: |r| <= r^2 / (2|r0|) + |r0|/2 with equality at r = r0, so
+    the row enters the squared objective sum w r^2 with w = 1 / (2 b |r0|);
+    |r0| is held at least floor * b."""
+    return 1.0 / (2.0 * b * np.maximum(np.abs(r), floor * b))
+
+
+def neq_from_rows(J: np.ndarray, r: np.ndarray, rowmask: np.ndarray, w: np.ndarray) -> np.ndarray:
+    """Normal equations (the 29-vector: upper triangle of H = sum w J^T J,
+    g = sum w J^T r, cost sum w r^2, contributing pixels) of per-pixel rows
+    J [P][4][6], r [P][4] with row weights w [P][4]; rowmask bit 1 keeps a
+    pixel's depth row, bit 2 its three colour rows."""
+    J = J.reshape(-1, 4, 6)
+    r = r.reshape(-1, 4)
+    rm = rowmask.reshape(-1)
+    keep = np.zeros(r.shape, bool)
+    keep[:, 0] = (rm & 1) != 0
+    keep[:, 1:] = ((rm & 2) != 0)[:, None]
+    Jk, rk, wk = J[keep], r[keep], w.reshape(-1, 4)[keep]
+    H = Jk.T @ (wk[:, None] * Jk)
+    g = Jk.T @ (wk * rk)
+    out = np.zeros(29)
+    q = 0
+    for a in range(6):
+        for b2 in range(a, 6):
+            out[q] = H[a, b2]
+            q += 1
+    out[21:27] = g
+    out[27] = float(np.sum(wk * rk * rk))
+    out[28] = float(np.count_nonzero(rm))
+    return out
+
+
+def irls_neq(rows: Dict[str, np.ndarray], params: Params) -> np.ndarray:
+    """Normal equations of one IRLS iteration: the rows of the objective
+    with weights irls_weight at their current residuals (depth rows scale
+    b_geo, colour rows b_rgb; the gates are those of the squared form)."""
+    r = rows["resid"].reshape(-1, 4)
+    w = np.empty_like(r)
+    w[:, 0] = irls_weight(r[:, 0], params.b_geo, params.irls_floor)
+    w[:, 1:] = irls_weight(r[:, 1:], params.b_rgb, params.irls_floor)
+    return neq_from_rows(rows["J"], r, rows["rowmask"], w)
 
 
 def adam_gradient(cam: Cam, pose, prior, Lp, pose_prev, obs_depth, obs_rgb, anchor, params: Params,
@@ -544,11 +609,12 @@ def adam_pose(cam: Cam, prior, Lp, pose_prev, obs_depth, obs_rgb, anchor, params
     return it
 
 
-def laplace(neq: np.ndarray, Lp: np.ndarray) -> np.ndarray:
+def laplace(neq: np.ndarray, Lp: np.ndarray, factor: float = 2.0) -> np.ndarray:
     """Laplace covariance at the MAP pose, Hessian from the squared Jacobian of
-    the full objective including the dynamics prior: (2 H + Lp)^-1."""
+    the full objective including the dynamics prior: (2 H + Lp)^-1 as Sec. 5.1
+    prints it, or (H + Lp)^-1 with factor 1."""
     H, _, _, _ = neq_unpack(neq)
-    A = 2.0 * H + Lp
+    A = factor * H + Lp
     Ai = np.linalg.inv(A)
     return 0.5 * (Ai + Ai.T)
 
@@ -568,13 +634,16 @@ def combine(pose_post: np.ndarray, S_pose: np.ndarray, prior_pose: np.ndarray, m
     return v_mean, 0.5 * (P + P.T)
 
 
-def transition_sample(x: Dict[str, np.ndarray], u: np.ndarray, n: np.ndarray, dt: float) -> Dict[str, np.ndarray]:
+def transition_sample(x: Dict[str, np.ndarray], u: np.ndarray, n: np.ndarray, dt: float,
+                      dt2: bool = False) -> Dict[str, np.ndarray]:
     """One draw of the generative transition (App. B): Euler integration with
     additive noise n = (n_t, n_theta, n_v, n_w): velocities first, then the
     position with the new velocity, the rotation by Exp(w' dt) and the
-    rotation noise on the left."""
-    v = x["v"] + u[:3] * dt + n[6:9]
-    w = x["w"] + u[3:] * dt + n[9:12]
+    rotation noise on the left.  dt2: the control enters as u dt^2 (App. E.1
+    as printed)."""
+    du = dt * dt if dt2 else dt
+    v = x["v"] + u[:3] * du + n[6:9]
+    w = x["w"] + u[3:] * du + n[9:12]
     t = x["t"] + v * dt + n[0:3]
     R = so3_exp(n[3:6]) @ so3_exp(w * dt) @ quat_to_rot(x["q"])
     return dict(t=t, q=rot_to_quat(R), v=v, w=w)
@@ -601,7 +670,7 @@ def rollout(grid: Grid, mean: np.ndarray, cam: Cam, x: Dict[str, np.ndarray], P:
         p0 = retract(np.concatenate([x["t"], x["q"]]), e[:6])
         xs = dict(t=p0[:3], q=p0[3:], v=x["v"] + e[6:9], w=x["w"] + e[9:12])
         for j in range(k):
-            xs = transition_sample(xs, u[j], sig * noise[s, j + 1], params.dt)
+            xs = transition_sample(xs, u[j], sig * noise[s, j + 1], params.dt, params.transition_dt2)
             poses[s, j] = np.concatenate([xs["t"], xs["q"]])
     means, covs = np.zeros((k, 13)), np.zeros((k, 12, 12))
     xm, Pm = dict(x), P
@@ -703,11 +772,13 @@ class Filter:
                            self.decide32)
         else:
             for _ in range(p.n_gn):
-                neq = self._objective(it, depth, rgb)
+                neq = self._objective(it, depth, rgb, irls=p.irls)
                 delta = gn_solve(neq, Lp, pose_error(it, prior))
                 it = retract(it, delta)
+        # the Laplace Hessian is the squared Jacobian of the objective's rows
+        # (App. E.3), also when the iterations minimised the L1 form
         neq = self._objective(it, depth, rgb)
-        S_lap = laplace(neq, Lp)
+        S_lap = laplace(neq, Lp, p.laplace_factor)
         s.Sbar = S_lap if s.Sbar is None else p.ema * s.Sbar + (1.0 - p.ema) * S_lap
         vel_prior = np.concatenate([xn["v"], xn["w"]])
         v_mean, P = combine(it, s.Sbar, prior, vel_prior, D, Sv)
@@ -720,9 +791,11 @@ class Filter:
         s.step += 1
         return s
 
-    def _objective(self, pose, depth, rgb):
+    def _objective(self, pose, depth, rgb, irls: bool = False):
         if self.p.objective == "p1":
-            return render_jacobian(self.grid, self.mean, self.cam, pose, depth, rgb, self.p,
-                                   self.decide32)["neq"]
-        return track_p2(self.cam, pose, self.s.anchor_pose, depth, rgb, self.s.anchor, self.p,
-                        self.decide32)["neq"]
+            out = render_jacobian(self.grid, self.mean, self.cam, pose, depth, rgb, self.p,
+                                  self.decide32, want_J=irls)
+        else:
+            out = track_p2(self.cam, pose, self.s.anchor_pose, depth, rgb, self.s.anchor, self.p,
+                           self.decide32, want_J=irls)
+        return irls_neq(out, self.p) if irls else out["neq"]
