@@ -241,6 +241,16 @@ prism_status prism_render(const prism_grid *grid, const void *map, const prism_c
                           uint8_t *mask, int32_t *hit_k, float *normals, uint8_t *nmask,
                           double normal_disc, hipStream_t stream);
 
+/* The paper's ray sampling (App. B: ray points at depth offsets eps, 2 eps,
+ * 3 eps, ...; App. G: eps = 0.4 voxel, rays up to the maximum camera
+ * depth) as a camera's sampling: sets cam->d_near = eps, cam->n_samples =
+ * floor(max_depth / eps) and cam->d_far = n_samples eps, so that sample k
+ * lies at depth (k + 1) eps (to rounding).  Other fields are left as they
+ * are.  Host only, no GPU work.  PRISM_INVALID_ARGUMENT for a NULL camera or
+ * a voxel or max_depth that is not finite and > 0; PRISM_UNSUPPORTED when
+ * the count falls outside 2..4096 (cam then unchanged). */
+prism_status prism_camera_paper_sampling(prism_camera *cam, double voxel, double max_depth);
+
 /* Workspace bytes needed by prism_render_jacobian / prism_track_p2 /
  * prism_render_vjp for n_frames frames of this camera. */
 prism_status prism_reduce_workspace_bytes(const prism_camera *cam, int32_t n_frames, size_t *bytes);
@@ -382,6 +392,28 @@ prism_status prism_map_gd(const prism_grid *grid, void *map, const prism_camera 
 /* ------------------------------------------------------------------------ */
 /* Filter (Sec. 4.3; App. C, E)                                             */
 /* ------------------------------------------------------------------------ */
+/* The paper's literal forms a filter can select (prism_filter_cfg.modes,
+ * any combination; 0 keeps the readings the library takes by default, where
+ * the printed form is ambiguous or inconsistent):
+ *   PRISM_MODE_TRANSITION_DT2  the control enters the velocities as u dt^2,
+ *       as App. E.1 prints it (default u dt, an acceleration integrated over
+ *       the frame interval).  Predict steps and prism_rollout alike.
+ *   PRISM_MODE_LAPLACE_FACTOR1 Laplace covariance (H_o + Lp)^-1, the
+ *       posterior covariance under a Gaussian likelihood of precision w,
+ *       instead of Sec. 5.1's (2 H_o + Lp)^-1 (H_o = sum w J^T J over the
+ *       kept rows at the final iterate, Lp the prior pose precision).
+ *   PRISM_MODE_IRLS_L1 the Gauss-Newton iterations minimise the L1 data
+ *       terms of App. E.3, sum |r| / b with b = 1/sqrt(w) per row, plus the
+ *       prior, by iteratively reweighted least squares: in each iteration a
+ *       kept row weighs 1 / (2 b max(|r|, irls_floor b)) at the iterate's
+ *       residual r instead of w.  The gates are unchanged, and the Laplace
+ *       covariance still squares the rows' Jacobian with weights w (App. E.3
+ *       takes the curvature of the squared form).  prism_pose_update_adam
+ *       returns PRISM_UNSUPPORTED for filters with this mode. */
+#define PRISM_MODE_TRANSITION_DT2 1
+#define PRISM_MODE_LAPLACE_FACTOR1 2
+#define PRISM_MODE_IRLS_L1 4
+
 typedef struct {
     prism_grid grid;
     prism_camera cam;
@@ -396,6 +428,10 @@ typedef struct {
     double normal_disc;                 /* anchor-normal discontinuity threshold (m) */
     double min_inlier_frac;             /* PRISM_FLAG_LOW_INLIERS below this fraction of the
                                            image's pixels contributing, [0, 1] (0: never) */
+    int32_t modes;                      /* PRISM_MODE_* bits (0: the default readings) */
+    int32_t pad_;
+    double irls_floor;                  /* PRISM_MODE_IRLS_L1: residual floor as a fraction of each
+                                           row's scale b, finite and > 0; unused otherwise */
 } prism_filter_cfg;
 
 /* Device-resident filter state (first bytes of the state buffer), FP64.
@@ -453,8 +489,9 @@ prism_status prism_filter_reset(prism_filter *f, const double *x0, const double 
 /* State filter only (Sec. 4.3.2): predict and split the state belief with
  * the frame's control, n_gn Gauss-Newton steps of the configured objective
  * from the predicted pose, Laplace covariance at the final iterate (EMA'd),
- * and combination with the velocity conditional.  Not valid for the first
- * frame. */
+ * and combination with the velocity conditional (cfg->modes selects the
+ * paper's literal transition, Laplace factor and L1 objective).  Not valid
+ * for the first frame. */
 prism_status prism_pose_update(prism_filter *f, const prism_frame *frame, hipStream_t stream);
 
 /* The paper's own pose optimiser (App. G): Adam with its momentum disabled,
@@ -482,7 +519,7 @@ typedef struct {
  * Gauss-Newton step).  The Laplace covariance then comes from the dense
  * normal equations at the final pose, as in prism_pose_update.  The whole
  * optimisation is one kernel launch (one workgroup).  Filters configured for
- * the P1 objective return PRISM_UNSUPPORTED.
+ * the P1 objective or PRISM_MODE_IRLS_L1 return PRISM_UNSUPPORTED.
  * pixels: device int32 [n_steps][n_pixels]. */
 prism_status prism_pose_update_adam(prism_filter *f, const prism_frame *frame,
                                     const prism_adam_params *p, const int32_t *pixels,
@@ -507,6 +544,7 @@ prism_status prism_filter_step_adam(prism_filter *f, const prism_frame *frame,
  *        order t, theta, v, w, left retraction for the pose), row j+1 the
  *        process noise of step j, n = sqrt(diag Q) z, entering as
  *        v' = v + u_v dt + n_v, w' = w + u_w dt + n_w, t' = t + v' dt + n_t,
+ *        (u dt^2 in place of u dt under PRISM_MODE_TRANSITION_DT2),
  *        R' = Exp(n_theta) Exp(w' dt) R.
  * poses: device [n_samples][k] (required when n_samples > 0).
  * mean:  nullable device [k][13] (t, q, v, w); cov: nullable [k][144]: the

@@ -163,7 +163,24 @@ CamD cam_d(const prism_camera* c) {
     return o;
 }
 
-WeightsC weights_c(const prism_weights* w) { return WeightsC{w->w_depth, w->w_rgb, w->gate_depth, w->gate_rgb}; }
+WeightsC weights_c(const prism_weights* w) {
+    return WeightsC{w->w_depth, w->w_rgb, w->gate_depth, w->gate_rgb, 0.0f, 0.0f, 1.0f, 1.0f, 0};
+}
+
+// the weights of an iteratively reweighted least-squares step of the L1
+// objective: h = 1/(2b), f = floor * b with b = 1/sqrt(w) per row kind (a
+// zero weight gives h = 0, a row that contributes nothing)
+WeightsC weights_irls(const prism_weights* w, double floor) {
+    WeightsC o = weights_c(w);
+    const double bd = w->w_depth > 0 ? 1.0 / sqrt(w->w_depth) : 1.0;
+    const double br = w->w_rgb > 0 ? 1.0 / sqrt(w->w_rgb) : 1.0;
+    o.irls_h_depth = w->w_depth > 0 ? (float)(0.5 / bd) : 0.0f;
+    o.irls_h_rgb = w->w_rgb > 0 ? (float)(0.5 / br) : 0.0f;
+    o.irls_f_depth = (float)(floor * bd);
+    o.irls_f_rgb = (float)(floor * br);
+    o.irls = 1;
+    return o;
+}
 
 size_t elem_size(int dtype) { return dtype == PRISM_BF16 ? 2 : 4; }
 
@@ -285,7 +302,9 @@ struct prism_filter {
     GridD gd;
     CamD cd;
     WeightsC w;
+    WeightsC w_gn;   // rows of a Gauss-Newton iteration (the IRLS weights under PRISM_MODE_IRLS_L1, else w)
     TransC tc;
+    double lap_h;    // factor of H in the Laplace precision (2, or 1 under PRISM_MODE_LAPLACE_FACTOR1)
     prism_filter_state* S;
     float *a_depth, *a_rgb, *a_normals;
     uint8_t *a_mask, *a_nmask;
@@ -384,6 +403,10 @@ prism_status check_cfg(const prism_filter_cfg* cfg) {
     REQUIRE(cfg->map.trunc > 0 && cfg->map.lam_update > 0, "map trunc and lam_update must be > 0");
     REQUIRE(!isnan(cfg->normal_disc), "normal_disc is NaN");
     REQUIRE(cfg->min_inlier_frac >= 0 && cfg->min_inlier_frac <= 1, "min_inlier_frac must be in [0, 1]");
+    REQUIRE((cfg->modes & ~(PRISM_MODE_TRANSITION_DT2 | PRISM_MODE_LAPLACE_FACTOR1 | PRISM_MODE_IRLS_L1)) == 0,
+            "unknown bits in modes (0x%x)", (unsigned)cfg->modes);
+    REQUIRE(!(cfg->modes & PRISM_MODE_IRLS_L1) || (isfinite(cfg->irls_floor) && cfg->irls_floor > 0),
+            "PRISM_MODE_IRLS_L1 needs a finite irls_floor > 0");
     return PRISM_OK;
 }
 
@@ -397,18 +420,21 @@ prism_status check_frame(const prism_frame* fr, bool need_u) {
 
 // objective at S->iter into the handle's partials; returns the block count.
 // rel_current: the handle's relative pose was formed from the current
-// iterate (after predict or a Gauss-Newton step), so tracking reads it
+// iterate (after predict or a Gauss-Newton step), so tracking reads it.
+// gn: the rows of a Gauss-Newton iteration (reweighted under the L1 mode);
+// else the rows of the Laplace covariance
 prism_status eval_objective(prism_filter* f, const prism_frame* fr, int* nb, hipStream_t st,
-                            bool rel_current = true) {
+                            bool rel_current = true, bool gn = false) {
+    const WeightsC& w = gn ? f->w_gn : f->w;
     if (f->cfg.objective == PRISM_OBJ_P1) {
         HIP_TRY(launch_render_jac(f->g, f->c, f->gd, f->cd, f->cfg.grid.dtype, f->map,
                                   skip_table(&f->cfg.grid, &f->cfg.cam, f->map), &f->S->iter, 1, fr->depth,
-                                  fr->rgb, f->w,
+                                  fr->rgb, w,
                                   nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, f->partials, st));
         *nb = render_blocks(f->c);
     } else {
         HIP_TRY(launch_track_p2(f->c, f->cd, &f->S->iter, &f->S->anchor, fr->depth, fr->rgb, f->a_depth, f->a_rgb,
-                                f->a_mask, f->a_normals, f->a_nmask, f->w, nullptr, nullptr, nullptr, f->partials,
+                                f->a_mask, f->a_normals, f->a_nmask, w, nullptr, nullptr, nullptr, f->partials,
                                 rel_current ? f->rel : nullptr, st));
         *nb = track_blocks(f->c);
     }
@@ -420,17 +446,19 @@ prism_status pose_update_impl(prism_filter* f, const prism_frame* fr, hipStream_
     int nb = 0;
     prism_status s;
     for (int i = 0; i < f->cfg.n_gn; ++i) {
-        if ((s = eval_objective(f, fr, &nb, st))) return s;
+        if ((s = eval_objective(f, fr, &nb, st, true, true))) return s;
         HIP_TRY(launch_gn_step(f->S, f->partials, nb, f->rel, st));
     }
     if ((s = eval_objective(f, fr, &nb, st))) return s;
-    HIP_TRY(launch_laplace_combine(f->S, f->partials, nb, f->cfg.ema, f->min_inliers, st));
+    HIP_TRY(launch_laplace_combine(f->S, f->partials, nb, f->cfg.ema, f->min_inliers, f->lap_h, st));
     return PRISM_OK;
 }
 
 prism_status check_adam(const prism_filter* f, const prism_adam_params* p, const int32_t* pixels) {
     if (f->cfg.objective != PRISM_OBJ_P2)
         return fail(PRISM_UNSUPPORTED, "the Adam pose optimiser runs on the P2 objective only");
+    if (f->cfg.modes & PRISM_MODE_IRLS_L1)
+        return fail(PRISM_UNSUPPORTED, "the Adam pose optimiser does not run the IRLS-L1 objective");
     REQUIRE(p, "adam params are NULL");
     REQUIRE(p->n_steps >= 1 && p->n_steps <= 1000000, "adam n_steps must be in [1, 1000000]");
     REQUIRE(p->n_pixels >= 1 && p->n_pixels <= 65536, "adam n_pixels must be in [1, 65536]");
@@ -461,7 +489,7 @@ prism_status pose_update_adam_impl(prism_filter* f, const prism_frame* fr, const
     prism_status s;
     // the optimiser moved the iterate: the objective forms its own relative pose
     if ((s = eval_objective(f, fr, &nb, st, false))) return s;
-    HIP_TRY(launch_laplace_combine(f->S, f->partials, nb, f->cfg.ema, f->min_inliers, st));
+    HIP_TRY(launch_laplace_combine(f->S, f->partials, nb, f->cfg.ema, f->min_inliers, f->lap_h, st));
     return PRISM_OK;
 }
 
@@ -581,6 +609,21 @@ prism_status prism_bricks_to_dense(int32_t n, int32_t channels, const float* bri
 prism_status prism_dense_to_bricks(int32_t n, int32_t channels, const float* dense, float* bricks,
                                    hipStream_t stream) {
     return planes(n, channels, dense, bricks, 0, stream);
+}
+
+prism_status prism_camera_paper_sampling(prism_camera* cam, double voxel, double max_depth) {
+    REQUIRE(cam, "camera is NULL");
+    REQUIRE(isfinite(voxel) && voxel > 0 && isfinite(max_depth) && max_depth > 0,
+            "voxel and max_depth must be finite and > 0");
+    // App. B: offsets eps, 2 eps, ...; App. G: eps = 0.4 voxel, up to the maximum depth
+    const double eps = 0.4 * voxel;
+    const double k = floor(max_depth / eps);
+    if (k < 2 || k > 4096)
+        return fail(PRISM_UNSUPPORTED, "%.0f samples of %g m up to %g m (2..4096 supported)", k, eps, max_depth);
+    cam->d_near = eps;
+    cam->n_samples = (int32_t)k;
+    cam->d_far = k * eps;
+    return PRISM_OK;
 }
 
 prism_status prism_render(const prism_grid* grid, const void* map, const prism_camera* cam, const prism_pose* poses,
@@ -872,7 +915,10 @@ prism_status prism_filter_create(const prism_filter_cfg* cfg, void* state_mem, v
     f->gd = grid_d(&cfg->grid);
     f->cd = cam_d(&cfg->cam);
     f->w = weights_c(&cfg->w);
+    f->w_gn = (cfg->modes & PRISM_MODE_IRLS_L1) ? weights_irls(&cfg->w, cfg->irls_floor) : f->w;
+    f->lap_h = (cfg->modes & PRISM_MODE_LAPLACE_FACTOR1) ? 1.0 : 2.0;
     f->tc.dt = cfg->dt;
+    f->tc.du = (cfg->modes & PRISM_MODE_TRANSITION_DT2) ? cfg->dt * cfg->dt : cfg->dt;
     for (int i = 0; i < 3; ++i) {
         f->tc.q[i] = cfg->sigma_pose_t * cfg->sigma_pose_t;
         f->tc.q[3 + i] = cfg->sigma_pose_r * cfg->sigma_pose_r;
@@ -898,7 +944,9 @@ prism_status prism_filter_create(const prism_filter_cfg* cfg, void* state_mem, v
     D.gd = f->gd;
     D.cd = f->cd;
     D.w = f->w;
+    D.w_irls = f->w_gn;
     D.tc = f->tc;
+    D.lap_h = f->lap_h;
     D.mp = MapUpdC{(float)cfg->map.trunc, cfg->map.trunc, cfg->map.lam_update};
     D.aux = map_aux(&cfg->grid, map_mem);
     D.ema = cfg->ema;
@@ -1295,6 +1343,7 @@ int blocks_of(const prism_filter* f, int stage) {
 BatchArgs make_batch(prism_filter* const* fs, const int* idx, int m, const int* slot, int stage) {
     BatchArgs b;
     b.n = m;
+    b.irls = 0;
     b.start[0] = 0;
     for (int j = 0; j < m; ++j) {
         const prism_filter* f = fs[idx[j]];
@@ -1312,14 +1361,18 @@ BatchArgs make_batch(prism_filter* const* fs, const int* idx, int m, const int* 
 
 // the objective of every filter fs[idx[j]] at its iterate: one tracking
 // launch for the P2 filters, one render-through launch per map kind for the
-// P1 filters
-prism_status batch_objective(prism_filter* const* fs, const int* idx, int m, const int* slot, hipStream_t st) {
+// P1 filters; gn: the rows of a Gauss-Newton iteration (each filter's
+// reweighted rows under the L1 mode), else those of the Laplace covariance
+prism_status batch_objective(prism_filter* const* fs, const int* idx, int m, const int* slot, hipStream_t st,
+                             bool gn = false) {
     int p2[kMaxBatch], n2 = 0;
     for (int j = 0; j < m; ++j)
         if (fs[idx[j]]->cfg.objective == PRISM_OBJ_P2) p2[n2++] = idx[j];
     if (n2) {
         StageScope t(PRISM_STAGE_TRACK, st);
-        HIP_TRY(launch_track_p2_batch(make_batch(fs, p2, n2, slot, 2), st));
+        BatchArgs b = make_batch(fs, p2, n2, slot, 2);
+        b.irls = gn ? 1 : 0;
+        HIP_TRY(launch_track_p2_batch(b, st));
     }
     for (int kind = 0; kind < 4 && n2 < m; ++kind) {
         const int dt = kind & 1 ? PRISM_BF16 : PRISM_F32;
@@ -1335,7 +1388,9 @@ prism_status batch_objective(prism_filter* const* fs, const int* idx, int m, con
         }
         if (!n1) continue;
         StageScope t(PRISM_STAGE_TRACK, st);
-        HIP_TRY(launch_render_jac_batch(make_batch(fs, p1, n1, slot, 8), dt, pool, max_lds, st));
+        BatchArgs b = make_batch(fs, p1, n1, slot, 8);
+        b.irls = gn ? 1 : 0;
+        HIP_TRY(launch_render_jac_batch(b, dt, pool, max_lds, st));
     }
     return PRISM_OK;
 }
@@ -1362,7 +1417,7 @@ prism_status step_batch_chunk(prism_filter* const* fs, int n, const int* slot, h
             int m = 0;
             for (int j = 0; j < n_pu; ++j)
                 if (fs[pu[j]]->cfg.n_gn > it) sub[m++] = pu[j];
-            prism_status so = batch_objective(fs, sub, m, slot, st);
+            prism_status so = batch_objective(fs, sub, m, slot, st, true);
             if (so) return so;
             {
                 StageScope t(PRISM_STAGE_GN, st);

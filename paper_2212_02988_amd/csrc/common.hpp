@@ -497,9 +497,20 @@ __device__ __forceinline__ void neq_add32(float acc[PRISM_NEQ], const float j[6]
     acc[27] = fmaf(w * r, r, acc[27]);
 }
 
+// Weights and gates of the objective rows.  irls != 0: a kept row of the L1
+// objective (App. E.3) is reweighted at its current residual r by
+// h / max(|r|, f), with h = 1/(2b) and f = floor * b for its kind (b = 1/sqrt(w)).
 struct WeightsC {
     double w_depth, w_rgb, gate_depth, gate_rgb;
+    float irls_h_depth, irls_h_rgb, irls_f_depth, irls_f_rgb;
+    int irls;
 };
+
+// weight of a kept depth (rgb = false) or colour row with residual r
+__device__ __forceinline__ float row_weight(const WeightsC& wt, bool rgb, double r) {
+    if (!wt.irls) return (float)(rgb ? wt.w_rgb : wt.w_depth);
+    return (rgb ? wt.irls_h_rgb : wt.irls_h_depth) / fmaxf(fabsf((float)r), rgb ? wt.irls_f_rgb : wt.irls_f_depth);
+}
 
 __device__ __forceinline__ bool depth_ok(float d) { return d > 0.0f && isfinite(d); }
 

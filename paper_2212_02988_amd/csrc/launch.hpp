@@ -9,6 +9,7 @@ namespace prism {
 // tangent order (dt, dtheta, dv, dw)
 struct TransC {
     double dt;
+    double du;   // factor of the control in the velocity update: dt, or dt^2 (the printed form)
     double q[12];
 };
 
@@ -29,10 +30,12 @@ struct AgentDesc {
     GridD gd;
     CamD cd;
     WeightsC w;
+    WeightsC w_irls;      // the weights of a Gauss-Newton iteration (w when the L1 mode is off)
     TransC tc;
     MapUpdC mp;
     MapAux aux;
     double ema;
+    double lap_h;         // factor of H in the Laplace covariance (f H + Lp)^-1: 2, or 1
     double min_inliers;   // contributing pixels below which a step raises PRISM_FLAG_LOW_INLIERS
     float normal_disc;
     int dtype, n_gn, nseg, upd_groups;
@@ -58,6 +61,7 @@ struct BatchArgs {
     int start[kMaxBatch + 1];
     unsigned char slot[kMaxBatch];
     int n;
+    int irls;   // objective launches: 1 in Gauss-Newton iterations (rows weighted by w_irls), else 0
 };
 
 // filter of workgroup blk (the start table is uniform: a scalar search)
@@ -177,7 +181,7 @@ hipError_t launch_rollout(const prism_filter_state* S, const double* u, int k, i
 hipError_t launch_predict(prism_filter_state* S, const double* u, const TransC& tc, Rel32* rel, hipStream_t st);
 hipError_t launch_gn_step(prism_filter_state* S, const double* partials, int nblocks, Rel32* rel, hipStream_t st);
 hipError_t launch_laplace_combine(prism_filter_state* S, const double* partials, int nblocks, double ema,
-                                  double min_inliers, hipStream_t st);
+                                  double min_inliers, double lap_h, hipStream_t st);
 // the left, world-frame retraction t <- t + dt, R <- Exp(dtheta) R of n poses
 hipError_t launch_pose_retract(const prism_pose* poses, const double* delta, int n, prism_pose* out, hipStream_t st);
 hipError_t launch_first_frame(prism_filter_state* S, hipStream_t st);

@@ -844,7 +844,7 @@ __device__ __forceinline__ void render_jac_block(int blk, int frame, const GridC
                 bool use_rgb = l1 <= wt.gate_rgb;
                 rm = (use_depth ? 1 : 0) | (use_rgb ? 2 : 0);
                 if (s == 0 ? use_depth : use_rgb)
-                    neq_add32(pacc, row, (float)r, (float)(s == 0 ? wt.w_depth : wt.w_rgb));
+                    neq_add32(pacc, row, (float)r, row_weight(wt, s != 0, r));
                 if (rm && s == 0) pacc[28] = 1.0f;
             }
             if (!rm) {
@@ -895,8 +895,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     const prism_frame& fr = D.slots[b.slot[a]];
     const int blk = blockIdx.x - b.start[a];
     render_jac_block<T, Pool>(blk, 0, D.g, D.c, D.gd, D.cd, (const T*)D.map, D.bits, &D.S->iter,
-                              (const float*)fr.depth, (const float*)fr.rgb, D.w, nullptr, nullptr, nullptr, nullptr,
-                              nullptr, nullptr, D.partials + (long long)blk * PRISM_NEQ);
+                              (const float*)fr.depth, (const float*)fr.rgb, b.irls ? D.w_irls : D.w, nullptr, nullptr,
+                              nullptr, nullptr, nullptr, nullptr, D.partials + (long long)blk * PRISM_NEQ);
 }
 
 // ---------------------------------------------------------------------------

@@ -174,15 +174,16 @@ __device__ inline void state_out(const prism_filter_state* l, prism_filter_state
 // predict + split
 // ---------------------------------------------------------------------------
 // Mean of the Euler transition (App. B, E.1) of one state, on one thread:
-// new velocities (vnew = v', w'), E = Exp(w' dt) with its left Jacobian Jl,
-// and the new pose (t + v' dt, E R).
+// new velocities (vnew = v', w' = v + u du, w + u_w du with du = dt, or dt^2
+// as printed), E = Exp(w' dt) with its left Jacobian Jl, and the new pose
+// (t + v' dt, E R).
 __device__ inline void transition_mean_t0(const prism_pose& pose, const double* v0, const double* w0,
                                           const double* u, const TransC& tc, double* vnew, double* E, double* Jl,
                                           prism_pose& pr) {
     double v[3], w[3];
     for (int i = 0; i < 3; ++i) {
-        v[i] = v0[i] + u[i] * tc.dt;
-        w[i] = w0[i] + u[3 + i] * tc.dt;
+        v[i] = v0[i] + u[i] * tc.du;
+        w[i] = w0[i] + u[3 + i] * tc.du;
         vnew[i] = v[i];
         vnew[3 + i] = w[i];
     }
@@ -364,7 +365,7 @@ __global__ __launch_bounds__(512) void k_gn_step(prism_filter_state* __restrict_
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void laplace_combine_block(prism_filter_state* __restrict__ Sg,
                                                       const double* __restrict__ partials, int nblocks, double ema,
-                                                      double min_inliers) {
+                                                      double min_inliers, double lap_h) {
     __shared__ double red[kRedLds], neq[PRISM_NEQ];
     __shared__ double A[36], Sl[36], Sb[36], D[36], T[36], P[144], e[6];
     __shared__ int ok;
@@ -394,7 +395,8 @@ __device__ __forceinline__ void laplace_combine_block(prism_filter_state* __rest
         if (neq[28] < min_inliers) S->flags |= PRISM_FLAG_LOW_INLIERS;
         double H[36], g[6];
         unpack_H(neq, H, g);
-        for (int i = 0; i < 36; ++i) A[i] = 2.0 * H[i] + S->Lp[i];
+        // Laplace precision lap_h H + Lp (Sec. 5.1 prints lap_h = 2)
+        for (int i = 0; i < 36; ++i) A[i] = lap_h * H[i] + S->Lp[i];
         ok = !(S->flags & PRISM_FLAG_CHOL_FALLBACK) && chol<6>(A);
         if (!ok) {
             S->flags |= PRISM_FLAG_CHOL_FALLBACK;
@@ -457,8 +459,8 @@ __device__ __forceinline__ void laplace_combine_block(prism_filter_state* __rest
 
 __global__ __launch_bounds__(512) void k_laplace_combine(prism_filter_state* __restrict__ Sg,
                                                          const double* __restrict__ partials, int nblocks,
-                                                         double ema, double min_inliers) {
-    laplace_combine_block(Sg, partials, nblocks, ema, min_inliers);
+                                                         double ema, double min_inliers, double lap_h) {
+    laplace_combine_block(Sg, partials, nblocks, ema, min_inliers, lap_h);
 }
 
 // the left, world-frame retraction of n poses by n tangent increments
@@ -497,7 +499,7 @@ __global__ __launch_bounds__(512) void k_gn_step_batch(BatchArgs b) {
 
 __global__ __launch_bounds__(512) void k_laplace_combine_batch(BatchArgs b) {
     const AgentDesc& D = *b.d[blockIdx.x];
-    laplace_combine_block(D.S, D.partials, D.obj_blocks, D.ema, D.min_inliers);
+    laplace_combine_block(D.S, D.partials, D.obj_blocks, D.ema, D.min_inliers, D.lap_h);
 }
 
 __global__ __launch_bounds__(64) void k_first_frame_batch(BatchArgs b) { first_frame_block(b.d[blockIdx.x]->S); }
@@ -509,9 +511,9 @@ __global__ __launch_bounds__(64) void k_first_frame_batch(BatchArgs b) { first_f
 // belief, x0 = x (+) L z0 with P = L L^T (tangent order t, theta, v, w; the
 // pose part is the left retraction), then runs the generative transition
 // with process noise n = sqrt(Q) z_j for each of the k controls:
-//   v' = v + u_v dt + n_v,  w' = w + u_w dt + n_w,
-//   t' = t + v' dt + n_t,   R' = Exp(n_theta) Exp(w' dt) R.
-// If P is not positive definite every sample starts at the mean and *flags
+//   v' = v + u_v du + n_v,  w' = w + u_w du + n_w,
+//   t' = t + v' dt + n_t,   R' = Exp(n_theta) Exp(w' dt) R
+// (du = dt, or dt^2 in the printed form).  If P is not positive definite every sample starts at the mean and *flags
 // gets PRISM_FLAG_CHOL_FALLBACK (else 0; written by the first workgroup).
 __global__ __launch_bounds__(64) void k_rollout_sample(const prism_filter_state* __restrict__ S,
                                                        const double* __restrict__ u, int k,
@@ -547,8 +549,8 @@ __global__ __launch_bounds__(64) void k_rollout_sample(const prism_filter_state*
         double n[12];
         for (int i = 0; i < 12; ++i) n[i] = sq[i] * zj[i];
         for (int i = 0; i < 3; ++i) {
-            v[i] = v[i] + uj[i] * tc.dt + n[6 + i];
-            w[i] = w[i] + uj[3 + i] * tc.dt + n[9 + i];
+            v[i] = v[i] + uj[i] * tc.du + n[6 + i];
+            w[i] = w[i] + uj[3 + i] * tc.du + n[9 + i];
         }
         double phi[3] = {w[0] * tc.dt, w[1] * tc.dt, w[2] * tc.dt};
         double E1[9], E2[9], R[9], T[9], R2[9];
@@ -643,8 +645,8 @@ hipError_t launch_gn_step(prism_filter_state* S, const double* partials, int nbl
 }
 
 hipError_t launch_laplace_combine(prism_filter_state* S, const double* partials, int nblocks, double ema,
-                                  double min_inliers, hipStream_t st) {
-    k_laplace_combine<<<1, 512, 0, st>>>(S, partials, nblocks, ema, min_inliers);
+                                  double min_inliers, double lap_h, hipStream_t st) {
+    k_laplace_combine<<<1, 512, 0, st>>>(S, partials, nblocks, ema, min_inliers, lap_h);
     return hipGetLastError();
 }
 

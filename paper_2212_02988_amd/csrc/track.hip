@@ -190,10 +190,10 @@ __device__ __forceinline__ void track_p2_block(int blk, const CamC& c, const Cam
         int rm;
         const float orgb[3] = {obs_rgb[3 * p], obs_rgb[3 * p + 1], obs_rgb[3 * p + 2]};
         p2_pixel(c, cd, rel, p, obs_depth[p], orgb, a_depth, a_rgb, a_mask, a_normals, a_nmask, wt, J, r, rm);
-        if (rm & 1) neq_add32(pacc, J[0], (float)r[0], (float)wt.w_depth);
+        if (rm & 1) neq_add32(pacc, J[0], (float)r[0], row_weight(wt, false, r[0]));
         if (rm & 2)
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) neq_add32(pacc, J[1 + ch], (float)r[1 + ch], (float)wt.w_rgb);
+            for (int ch = 0; ch < 3; ++ch) neq_add32(pacc, J[1 + ch], (float)r[1 + ch], row_weight(wt, true, r[1 + ch]));
         if (rm) pacc[28] = 1.0f;
         if (Jout) {
             float4* jo = reinterpret_cast<float4*>(Jout + 24 * (long long)p);
@@ -232,8 +232,8 @@ __global__ __launch_bounds__(256) void k_track_p2_batch(BatchArgs b) {
     const AgentDesc& D = *b.d[a];
     const prism_frame& fr = D.slots[b.slot[a]];
     track_p2_block(blockIdx.x - b.start[a], D.c, D.cd, &D.S->iter, &D.S->anchor, (const float*)fr.depth,
-                   (const float*)fr.rgb, D.a_depth, D.a_rgb, D.a_mask, D.a_normals, D.a_nmask, D.w, nullptr, nullptr,
-                   nullptr, D.partials, D.rel);
+                   (const float*)fr.rgb, D.a_depth, D.a_rgb, D.a_mask, D.a_normals, D.a_nmask, b.irls ? D.w_irls : D.w,
+                   nullptr, nullptr, nullptr, D.partials, D.rel);
 }
 
 // ---------------------------------------------------------------------------

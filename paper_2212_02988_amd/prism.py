@@ -21,6 +21,8 @@ LIB_PATH = os.path.join(_HERE, "libprism.so")
 PRISM_F32, PRISM_BF16 = 0, 1
 OBJ_P2, OBJ_P1 = 0, 1
 FLAG_NO_VALID_PIXELS, FLAG_CHOL_FALLBACK, FLAG_PRIOR_NOT_PD, FLAG_LOW_INLIERS = 1, 2, 4, 8
+# the paper's literal forms (prism_filter_cfg.modes)
+MODE_TRANSITION_DT2, MODE_LAPLACE_FACTOR1, MODE_IRLS_L1 = 1, 2, 4
 NEQ = 29
 
 
@@ -60,6 +62,14 @@ class Camera(ctypes.Structure):
     def make(width, height, fx, fy, cx, cy, d_near, d_far, n_samples, tau=0.0) -> "Camera":
         return Camera(width, height, fx, fy, cx, cy, d_near, d_far, n_samples, 0, tau)
 
+    @staticmethod
+    def paper_sampling(width, height, fx, fy, cx, cy, voxel: float, max_depth: float, tau=0.0) -> "Camera":
+        """A camera whose samples lie at depths eps, 2 eps, ... up to max_depth,
+        eps = 0.4 voxel (the library's prism_camera_paper_sampling)."""
+        c = Camera(width, height, fx, fy, cx, cy, 0.0, 1.0, 2, 0, tau)
+        _check(lib().prism_camera_paper_sampling(ctypes.byref(c), voxel, max_depth))
+        return c
+
 
 class Weights(ctypes.Structure):
     _fields_ = [("w_depth", ctypes.c_double), ("w_rgb", ctypes.c_double),
@@ -84,7 +94,8 @@ class FilterCfg(ctypes.Structure):
                 ("sigma_pose_t", ctypes.c_double), ("sigma_pose_r", ctypes.c_double),
                 ("w", Weights), ("ema", ctypes.c_double), ("n_gn", ctypes.c_int32),
                 ("objective", ctypes.c_int32), ("map", MapParams), ("normal_disc", ctypes.c_double),
-                ("min_inlier_frac", ctypes.c_double)]
+                ("min_inlier_frac", ctypes.c_double), ("modes", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("irls_floor", ctypes.c_double)]
 
 
 class FilterState(ctypes.Structure):
@@ -130,6 +141,7 @@ _SIGS = {
     "prism_dense_to_bricks": ([ctypes.c_int32, ctypes.c_int32, "p", "p", "p"], None),
     "prism_render": (["p", "p", "p", "p", ctypes.c_int32, "p", "p", "p", "p", "p", "p", ctypes.c_double, "p"], None),
     "prism_reduce_workspace_bytes": (["p", ctypes.c_int32, "p"], None),
+    "prism_camera_paper_sampling": (["p", ctypes.c_double, ctypes.c_double], None),
     "prism_render_jacobian": (["p", "p", "p", "p", ctypes.c_int32, "p", "p", "p", "p", "p", "p", "p", "p", "p",
                                "p", "p", ctypes.c_size_t, "p"], None),
     "prism_render_jacobian_noalloc_max_bytes": ([], ctypes.c_size_t),
@@ -520,13 +532,15 @@ class FilterParams:
     sigma_update: float = 1.0
     normal_disc: float = 0.1
     min_inlier_frac: float = 0.1
+    modes: int = 0             # MODE_* bits: the paper's literal forms
+    irls_floor: float = 0.01   # MODE_IRLS_L1: residual floor as a fraction of each row's scale b
 
 
 def filter_cfg(grid: Grid, cam: Camera, p: FilterParams) -> FilterCfg:
     return FilterCfg(grid, cam, p.dt, p.sigma_vel_t, p.sigma_vel_r, p.sigma_pose_t, p.sigma_pose_r,
                      Weights.make(p.b_geo, p.b_rgb, p.gate_geo, p.gate_rgb), p.ema, p.n_gn, p.objective,
                      MapParams(p.trunc_voxels * grid.voxel, 1.0 / p.sigma_update ** 2), p.normal_disc,
-                     p.min_inlier_frac)
+                     p.min_inlier_frac, p.modes, 0, p.irls_floor)
 
 
 def filter_bytes(cfg: FilterCfg) -> int:

@@ -100,6 +100,50 @@ def test_workspace_and_filter_sizes(P):
     assert L.prism_filter_bytes(ctypes.byref(bad), ctypes.byref(b)) == 1
 
 
+def test_paper_modes_are_validated(P):
+    """cfg.modes takes the three documented bits in any combination; the L1
+    mode needs a positive floor; unknown bits are refused."""
+    L = P.lib()
+    cam = P.Camera.make(64, 48, 50, 50, 32, 24, 0.1, 4.0, 64)
+    g = P.Grid.make(64, 0.04)
+    b = ctypes.c_size_t()
+    for modes in range(8):
+        cfg = P.filter_cfg(g, cam, P.FilterParams(modes=modes))
+        assert L.prism_filter_bytes(ctypes.byref(cfg), ctypes.byref(b)) == 0, modes
+    for bad in (P.FilterParams(modes=8), P.FilterParams(modes=P.MODE_IRLS_L1, irls_floor=0.0),
+                P.FilterParams(modes=P.MODE_IRLS_L1, irls_floor=float("nan"))):
+        cfg = P.filter_cfg(g, cam, bad)
+        assert L.prism_filter_bytes(ctypes.byref(cfg), ctypes.byref(b)) == 1
+        assert b"modes" in L.prism_last_error() or b"irls_floor" in L.prism_last_error()
+    # the floor is not read without the L1 mode
+    cfg = P.filter_cfg(g, cam, P.FilterParams(modes=P.MODE_LAPLACE_FACTOR1, irls_floor=0.0))
+    assert L.prism_filter_bytes(ctypes.byref(cfg), ctypes.byref(b)) == 0
+
+
+def test_paper_sampling_camera_matches_the_oracle(P):
+    """prism_camera_paper_sampling gives the oracle's camera for the paper's
+    sampling (offsets eps, 2 eps, ... up to the maximum depth, eps = 0.4
+    voxel) bit for bit; counts outside 2..4096 and bad arguments are refused
+    and leave the camera unchanged."""
+    import oracle as orc
+    L = P.lib()
+    for voxel, dmax in ((0.025, 8.0), (0.05, 7.0), (0.1, 20.0), (0.0125, 8.0), (0.03, 0.025),
+                        (0.001, 8.0), (0.1, 0.05)):
+        ref = orc.paper_sample_camera(64, 48, 50.0, 50.0, 32.0, 24.0, voxel, dmax)
+        cam = P.Camera.make(64, 48, 50, 50, 32, 24, 0.1, 4.0, 64)
+        st = L.prism_camera_paper_sampling(ctypes.byref(cam), voxel, dmax)
+        if not 2 <= ref.n_samples <= 4096:
+            assert st == 2 and cam.n_samples == 64 and cam.d_near == 0.1 and cam.d_far == 4.0
+            continue
+        assert st == 0
+        assert (cam.d_near, cam.d_far, cam.n_samples) == (ref.d_near, ref.d_far, ref.n_samples)
+        assert (cam.width, cam.fx, cam.tau) == (64, 50.0, 0.0)
+    cam = P.Camera.make(64, 48, 50, 50, 32, 24, 0.1, 4.0, 64)
+    for voxel, dmax in ((0.0, 8.0), (-1.0, 8.0), (0.05, float("inf")), (0.05, 0.0)):
+        assert L.prism_camera_paper_sampling(ctypes.byref(cam), voxel, dmax) == 1
+    assert L.prism_camera_paper_sampling(None, 0.05, 8.0) == 1
+
+
 def test_brick_pool_map_bytes_and_init_checks(P):
     """Brick-pool maps: size = pool planes + the dense summaries + the slot
     table and pool header; capacity bounded by the brick count; init must use

@@ -234,8 +234,9 @@ def test_submit_poll_via_c_abi():
 @pytest.mark.parametrize("graphs", [False, True])
 def test_step_batch_matches_single_steps(graphs):
     """prism_filter_step_batch over filters of different image sizes, grid
-    sizes, storage types, objectives (P2 and the render-through P1) and
-    Gauss-Newton counts, one of them joining (first frame) while the others
+    sizes, storage types, objectives (P2 and the render-through P1),
+    Gauss-Newton counts and paper modes (IRLS rows beside plain ones in one
+    launch), one of them joining (first frame) while the others
     are mid-trajectory: every filter's state and map equal its own sequence
     of prism_filter_step calls, bit for bit -- with every batch launched
     stage by stage, and replayed from the graphs recorded per member set,
@@ -246,11 +247,12 @@ def test_step_batch_matches_single_steps(graphs):
     banner(f"prism_filter_step_batch vs single steps (mixed batch, graphs={graphs})")
     Pm = P()
     specs, frames = _specs(n_streams=4, n_frames=6)
-    kinds = [(Pm.PRISM_F32, 3, Pm.OBJ_P2), (Pm.PRISM_BF16, 2, Pm.OBJ_P1), (Pm.PRISM_BF16, 3, Pm.OBJ_P2),
-             (Pm.PRISM_F32, 1, Pm.OBJ_P1)]
-    for sp, (dt, ngn, obj) in zip(specs, kinds):
+    all_modes = Pm.MODE_TRANSITION_DT2 | Pm.MODE_LAPLACE_FACTOR1 | Pm.MODE_IRLS_L1
+    kinds = [(Pm.PRISM_F32, 3, Pm.OBJ_P2, 0), (Pm.PRISM_BF16, 2, Pm.OBJ_P1, Pm.MODE_IRLS_L1),
+             (Pm.PRISM_BF16, 3, Pm.OBJ_P2, all_modes), (Pm.PRISM_F32, 1, Pm.OBJ_P1, 0)]
+    for sp, (dt, ngn, obj, modes) in zip(specs, kinds):
         sp.grid = Pm.Grid.make(sp.grid.n, sp.grid.voxel, tuple(sp.grid.origin), dtype=dt)
-        sp.params = dataclasses.replace(sp.params, n_gn=ngn, objective=obj)
+        sp.params = dataclasses.replace(sp.params, n_gn=ngn, objective=obj, modes=modes)
     join = {0: 0, 1: 0, 2: 0, 3: 2}        # frame index at which each filter starts
     s = torch.cuda.Stream()
     ref, bat = [], []
