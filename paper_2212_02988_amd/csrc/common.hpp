@@ -443,18 +443,56 @@ __device__ inline void block_reduce29f(const float acc[PRISM_NEQ], double* lds, 
 #pragma unroll
     for (int q = 0; q < 32; ++q) v[q] = q < PRISM_NEQ ? acc[q] : 0.0f;
     const int lane = threadIdx.x & 63;
+    // transposing halving within each 32-lane half: after the step of width
+    // h a lane keeps the h values of the half of its index set selected by
+    // its lane bit h, each summed with the same value of a partner lane
+    // whose bit h differs.  Width 16: the row swap of v[j] and v[j + 16]
+    // hands lanes 0-15 (32-47) their partner's v[j] and lanes 16-31 (48-63)
+    // their partner's v[j + 16]
 #pragma unroll
-    for (int half = 16; half >= 1; half >>= 1) {
-        bool hi = (lane & half) != 0;
+    for (int j = 0; j < 16; ++j) {
+        const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[j]), __float_as_uint(v[j + 16]), false,
+                                                        false);
+        v[j] = __uint_as_float(s[0]) + __uint_as_float(s[1]);
+    }
+    // widths 8, 4, 2, 1 inside 16-lane rows: the partner read by DPP is
+    // lane ^ 8 (row rotate by 8), lane ^ 7 (half-row mirror), lane ^ 2 and
+    // lane ^ 1 (quad permutations); at each width all lanes that agree on
+    // the bits already used hold the same index set, so any partner that
+    // differs in bit h and agrees on the higher bits serves
 #pragma unroll
-        for (int j = 0; j < half; ++j) {
-            float send = hi ? v[j] : v[j + half];
-            float keep = hi ? v[j + half] : v[j];
-            v[j] = keep + __shfl_xor(send, half, 64);
+    for (int step = 0; step < 4; ++step) {
+        const int h = 8 >> step;
+        const bool hi = (lane & h) != 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (j >= h) break;
+            int a = __float_as_int(v[j]), b = __float_as_int(v[j + h]);
+            int pa, pb;
+            if (step == 0) {
+                pa = __builtin_amdgcn_update_dpp(0, a, 0x128, 0xF, 0xF, false);
+                pb = __builtin_amdgcn_update_dpp(0, b, 0x128, 0xF, 0xF, false);
+            } else if (step == 1) {
+                pa = __builtin_amdgcn_update_dpp(0, a, 0x141, 0xF, 0xF, false);
+                pb = __builtin_amdgcn_update_dpp(0, b, 0x141, 0xF, 0xF, false);
+            } else if (step == 2) {
+                pa = __builtin_amdgcn_update_dpp(0, a, 0x4E, 0xF, 0xF, false);
+                pb = __builtin_amdgcn_update_dpp(0, b, 0x4E, 0xF, 0xF, false);
+            } else {
+                pa = __builtin_amdgcn_update_dpp(0, a, 0xB1, 0xF, 0xF, false);
+                pb = __builtin_amdgcn_update_dpp(0, b, 0xB1, 0xF, 0xF, false);
+            }
+            const float lo = v[j] + __int_as_float(pa), up = v[j + h] + __int_as_float(pb);
+            v[j] = hi ? up : lo;
         }
     }
+    // lane l holds index l & 31 summed over its 32-lane half; the halves are
+    // added in double precision through the 32-lane swap
     const double h = (double)v[0];
-    double w = h + __shfl_xor(h, 32, 64);   // value (lane & 31), whole wave
+    const unsigned hl = (unsigned)__double2loint(h), hh = (unsigned)__double2hiint(h);
+    const auto sl = __builtin_amdgcn_permlane32_swap(hl, hl, false, false);
+    const auto sh = __builtin_amdgcn_permlane32_swap(hh, hh, false, false);
+    const double w = __hiloint2double((int)sh[0], (int)sl[0]) + __hiloint2double((int)sh[1], (int)sl[1]);
     const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     if (lane < 32) lds[lane * 16 + wv] = w;
     __syncthreads();

@@ -414,8 +414,17 @@ def test_filter_paper_modes_match_oracle(objective):
     closed loop ill-conditioned (the oracle with FP64 decisions parts from
     its FP32-decision run by 5e-5 m at the sixth frame), so every step is
     compared from the same start: before step i the oracle takes the GPU
-    filter's state and map and renders its anchor from them."""
+    filter's state and map and renders its anchor from them.
+
+    The render-through objective under IRLS is itself sensitive at the
+    1e-5 level within one step: a pixel whose hit sample flips between
+    iterates changes its residual, and its IRLS weight grows as 1/|r| (up to
+    50 times 1/b^2 at the default floor).  In the oracle, moving the start
+    pose of one step by 1e-9 m moves that step's result by up to 1.7e-5 m on
+    this trajectory (2e-7 m with the default squared objective), so for P1
+    the pose bar here is 1e-4 m / rad; P2 keeps the 1e-5 bar."""
     n, width, n_frames = 128, 160, 6
+    pose_bar = 1e-5 if objective == 0 else 1e-4
     modes = P().MODE_TRANSITION_DT2 | P().MODE_LAPLACE_FACTOR1 | P().MODE_IRLS_L1
     banner(f"filter 128^3 160x120 objective={objective} modes={modes}, one step at a time from the GPU state")
     c = synth.trajectory_case(seed=2, n=n, width=width, height=width * 3 // 4, n_samples=n // 2, n_frames=n_frames)
@@ -450,8 +459,8 @@ def test_filter_paper_modes_match_oracle(objective):
         print(f"step {i}: |dt| {dt_:.2e} m, dR {dr_:.2e} rad, P {eP:.2e}, position error to the truth "
               f"{np.linalg.norm(tg - tr.t[i]):.4f} m", flush=True)
         assert s.flags == 0
-        assert dt_ <= 1e-5 and dr_ <= 1e-5, (i, dt_, dr_)
-        assert np.linalg.norm(np.concatenate([np.array(s.v), np.array(s.w)]) - np.concatenate([of.s.v, of.s.w])) <= 1e-4
+        assert dt_ <= pose_bar and dr_ <= pose_bar, (i, dt_, dr_)
+        assert np.linalg.norm(np.concatenate([np.array(s.v), np.array(s.w)]) - np.concatenate([of.s.v, of.s.w])) <= 10 * pose_bar
         assert eP <= 1e-4, (i, eP)
         nu = of.s.last["n_updated"]
         assert abs(int(s.n_updated) - nu) <= max(10, 1e-4 * nu), i
