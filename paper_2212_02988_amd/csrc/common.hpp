@@ -422,11 +422,13 @@ __device__ inline void block_reduce29(double acc[PRISM_NEQ], double* lds, double
     }
     double w = v[0] + __shfl_xor(v[0], 32, 64);   // value (lane & 31), whole wave
     const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if (lane < 32) lds[lane * 16 + wv] = w;
+    // one row of 32 per wavefront: the stores of a wavefront and the loads of
+    // each step of the sum below hit consecutive doubles (no bank conflicts)
+    if (lane < 32) lds[wv * 32 + lane] = w;
     __syncthreads();
     if (threadIdx.x < PRISM_NEQ) {
         double s = 0.0;
-        for (int k = 0; k < nw; ++k) s += lds[threadIdx.x * 16 + k];
+        for (int k = 0; k < nw; ++k) s += lds[k * 32 + threadIdx.x];
         out[threadIdx.x] = s;
     }
 }
@@ -494,11 +496,13 @@ __device__ inline void block_reduce29f(const float acc[PRISM_NEQ], double* lds, 
     const auto sh = __builtin_amdgcn_permlane32_swap(hh, hh, false, false);
     const double w = __hiloint2double((int)sh[0], (int)sl[0]) + __hiloint2double((int)sh[1], (int)sl[1]);
     const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if (lane < 32) lds[lane * 16 + wv] = w;
+    // one row of 32 per wavefront: the stores of a wavefront and the loads of
+    // each step of the sum below hit consecutive doubles (no bank conflicts)
+    if (lane < 32) lds[wv * 32 + lane] = w;
     __syncthreads();
     if (threadIdx.x < PRISM_NEQ) {
         double s = 0.0;
-        for (int k = 0; k < nw; ++k) s += lds[threadIdx.x * 16 + k];
+        for (int k = 0; k < nw; ++k) s += lds[k * 32 + threadIdx.x];
         out[threadIdx.x] = s;
     }
 }
