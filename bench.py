@@ -800,14 +800,18 @@ STAGE_KERNELS = {"render": "k_render_batch", "track": "k_track_p2_batch", "map_u
 
 
 def source_digest():
-    """Digest of the kernel sources: measured HBM traffic is only reported for
-    the kernels it was measured on."""
+    """Digest of the kernel sources' code (comments and white space removed):
+    measured HBM traffic is only reported for the kernels it was measured on."""
     import hashlib
+    import re
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2212_02988_amd", "csrc")
     for name in sorted(os.listdir(d)):
-        with open(os.path.join(d, name), "rb") as fh:
-            h.update(name.encode() + fh.read())
+        with open(os.path.join(d, name), encoding="utf-8") as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(name.encode() + " ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -4,8 +4,9 @@
 // gated, weighted normal equations.  One observed pixel per lane, pixels in
 // row-major order so observation reads are coalesced; anchor reads are
 // gathers around the reprojected location.  (Two or four pixels per lane,
-// paying the 29-sum reduction once for them, measured slower: the kernel is
-// bound by the latency of its dependent gathers, not by issue.)
+// paying the 29-sum reduction once for them, measured slower: the running
+// sums stay live across a pixel's work, which takes 100-170 VGPRs and halves
+// the waves per SIMD.)
 #include "common.hpp"
 #include "launch.hpp"
 #include "se3.hpp"
