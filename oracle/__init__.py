@@ -183,6 +183,12 @@ class Params:
     irls: bool = False            # Gauss-Newton iterations minimise the L1 data terms of App. E.3 by
                                   # iteratively reweighted least squares
     irls_floor: float = 0.01      # IRLS residual floor, as a fraction of each row's Laplace scale b
+    # 15-D state: pose, velocities and an accelerometer bias (a reading added for
+    # trajectories simulated with a biased IMU; the paper's state is 12-D)
+    accel_bias: bool = False      # the linear control is the body-frame specific force f, the
+                                  # acceleration R (f - b) + g
+    sigma_bias: float = 0.001     # per-step bias random walk (m/s^2)
+    gravity: Tuple[float, float, float] = (0.0, 0.0, -9.81)
 
     def weights(self) -> _Weights:
         return _Weights(1.0 / self.b_geo ** 2, 1.0 / self.b_rgb ** 2, self.gate_geo, self.gate_rgb)
@@ -465,6 +471,46 @@ def transition_mean(x: Dict[str, np.ndarray], u: np.ndarray, dt: float, dt2: boo
     return dict(t=t, q=rot_to_quat(R), v=v, w=w)
 
 
+def transition_mean_bias(x: Dict[str, np.ndarray], u: np.ndarray, dt: float, g, dt2: bool = False):
+    """The transition with an accelerometer bias b in the state: the linear
+    control is the body-frame specific force f (the accelerometer's mean over
+    the interval), the acceleration a = R (f - b) + g with the state's own
+    rotation R; then as transition_mean (velocities first, the pose with the
+    new velocities); b is carried over (a random walk)."""
+    R = quat_to_rot(x["q"])
+    a = R @ (u[:3] - x["b"]) + np.asarray(g, float)
+    xn = transition_mean(x, np.concatenate([a, u[3:]]), dt, dt2)
+    xn["b"] = np.array(x["b"], float)
+    return xn
+
+
+def transition_jacobians_bias(x: Dict[str, np.ndarray], x_new: Dict[str, np.ndarray], u: np.ndarray, dt: float,
+                              dt2: bool = False):
+    """First-order error-state transition of the 15-D state (tangent order
+    dt, dtheta, dv, dw, db): the 12-D blocks of transition_jacobians plus the
+    acceleration's dependence on the rotation and the bias at the start of the
+    step, da = -[R (f - b)]x dtheta - R db (left perturbation R <- Exp(dtheta) R),
+    entering v' with the control factor du and t' through v' dt; the bias
+    noise n_b enters b' directly."""
+    du = dt * dt if dt2 else dt
+    M12, G12 = transition_jacobians(x_new, dt)
+    R = quat_to_rot(x["q"])
+    Ra = R @ (u[:3] - x["b"])
+    M = np.zeros((15, 15))
+    M[:12, :12] = M12
+    dv_dth = -du * skew(Ra)
+    dv_db = -du * R
+    M[6:9, 3:6] += dv_dth
+    M[6:9, 12:15] += dv_db
+    M[0:3, 3:6] += dt * dv_dth
+    M[0:3, 12:15] += dt * dv_db
+    M[12:15, 12:15] = np.eye(3)
+    G = np.zeros((15, 15))
+    G[:12, :12] = G12
+    G[12:15, 12:15] = np.eye(3)
+    return M, G
+
+
 def transition_jacobians(x_new: Dict[str, np.ndarray], dt: float):
     """First-order error-state transition (App. E.1 linearisation) for the
     tangent (dt, dtheta, dv, dw): returns M (12x12, old error -> new error)
@@ -492,11 +538,17 @@ def transition_jacobians(x_new: Dict[str, np.ndarray], dt: float):
 
 def predict(x: Dict[str, np.ndarray], P: np.ndarray, u: np.ndarray, p: Params):
     """Closed-form propagation of the Gaussian state belief through the
-    linearised transition (App. E.2): returns the prior mean and covariance."""
-    xn = transition_mean(x, u, p.dt, p.transition_dt2)
-    M, G = transition_jacobians(xn, p.dt)
-    Qd = np.diag([p.sigma_pose_t ** 2] * 3 + [p.sigma_pose_r ** 2] * 3 +
-                 [p.sigma_vel_t ** 2] * 3 + [p.sigma_vel_r ** 2] * 3)
+    linearised transition (App. E.2): returns the prior mean and covariance
+    (12-D, or 15-D with the accelerometer bias)."""
+    q = [p.sigma_pose_t ** 2] * 3 + [p.sigma_pose_r ** 2] * 3 + [p.sigma_vel_t ** 2] * 3 + [p.sigma_vel_r ** 2] * 3
+    if p.accel_bias:
+        xn = transition_mean_bias(x, u, p.dt, p.gravity, p.transition_dt2)
+        M, G = transition_jacobians_bias(x, xn, u, p.dt, p.transition_dt2)
+        q = q + [p.sigma_bias ** 2] * 3
+    else:
+        xn = transition_mean(x, u, p.dt, p.transition_dt2)
+        M, G = transition_jacobians(xn, p.dt)
+    Qd = np.diag(q)
     Pn = M @ P @ M.T + G @ Qd @ G.T
     return xn, 0.5 * (Pn + Pn.T)
 
@@ -626,7 +678,8 @@ def combine(pose_post: np.ndarray, S_pose: np.ndarray, prior_pose: np.ndarray, m
     pose) and the joint covariance [[S, S D^T], [D S, S_v + D S D^T]]."""
     e = pose_error(pose_post, prior_pose)
     v_mean = mu_v + D @ e
-    P = np.zeros((12, 12))
+    n = 6 + len(mu_v)
+    P = np.zeros((n, n))
     P[:6, :6] = S_pose
     P[:6, 6:] = S_pose @ D.T
     P[6:, :6] = D @ S_pose
@@ -655,7 +708,10 @@ def rollout(grid: Grid, mean: np.ndarray, cam: Cam, x: Dict[str, np.ndarray], P:
     under controls u [k][6]: for each sample s the start state x (+) L z[s,0]
     (P = L L^T; tangent order t, theta, v, w) and k draws of the transition
     with noise sqrt(diag Q) z[s,j+1]; the closed-form predicted moments after
-    each control; the frames rendered at every sampled pose."""
+    each control; the frames rendered at every sampled pose.  12-D state
+    only."""
+    if params.accel_bias:
+        raise NotImplementedError("rollouts are defined for the 12-D state")
     k = len(u)
     sig = np.sqrt([params.sigma_pose_t ** 2] * 3 + [params.sigma_pose_r ** 2] * 3 +
                   [params.sigma_vel_t ** 2] * 3 + [params.sigma_vel_r ** 2] * 3)
@@ -701,8 +757,9 @@ class FilterState:
     q: np.ndarray
     v: np.ndarray
     w: np.ndarray
-    P: np.ndarray                      # 12x12 covariance, tangent (dt, dth, dv, dw)
+    P: np.ndarray                      # 12x12 covariance, tangent (dt, dth, dv, dw); 15x15 with db
     Sbar: Optional[np.ndarray] = None  # EMA of Laplace pose covariances
+    b: Optional[np.ndarray] = None     # accelerometer bias (15-D state only)
     step: int = 0
     anchor: Optional[Dict[str, np.ndarray]] = None
     anchor_pose: Optional[np.ndarray] = None
@@ -723,7 +780,8 @@ class Filter:
         self.mean = _f64(mean).copy()
         self.var = _f64(var).copy()
         self.decide32 = decide32
-        self.s = FilterState(t=_f64(x0["t"]).copy(), q=_f64(x0["q"]).copy(),
+        self.s = FilterState(b=_f64(x0.get("b", np.zeros(3))).copy() if params.accel_bias else None,
+                             t=_f64(x0["t"]).copy(), q=_f64(x0["q"]).copy(),
                              v=_f64(x0["v"]).copy(), w=_f64(x0["w"]).copy(), P=_f64(P0).copy())
 
     def _observe_and_anchor(self, pose, depth, rgb):
@@ -747,13 +805,15 @@ class Filter:
             s.step += 1
             return s
         # predict and split (App. E.1-E.2)
-        xn, Pm = predict(dict(t=s.t, q=s.q, v=s.v, w=s.w), s.P, u, p)
+        xn, Pm = predict(dict(t=s.t, q=s.q, v=s.v, w=s.w, b=s.b), s.P, u, p)
         prior = np.concatenate([xn["t"], xn["q"]])
         if not _is_pd(Pm[:6, :6]):
             # the paper assumes a proper Gaussian belief; a predicted pose
             # covariance that is not positive definite has no MAP problem,
             # so the step keeps the prediction and still updates the map
             s.t, s.q, s.v, s.w, s.P = xn["t"], xn["q"], xn["v"], xn["w"], Pm
+            if p.accel_bias:
+                s.b = xn["b"]
             s.last.update(neq=None, S_lap=None, prior=prior, prior_not_pd=True)
             self._observe_and_anchor(prior, depth, rgb)
             s.step += 1
@@ -780,10 +840,12 @@ class Filter:
         neq = self._objective(it, depth, rgb)
         S_lap = laplace(neq, Lp, p.laplace_factor)
         s.Sbar = S_lap if s.Sbar is None else p.ema * s.Sbar + (1.0 - p.ema) * S_lap
-        vel_prior = np.concatenate([xn["v"], xn["w"]])
+        vel_prior = np.concatenate([xn["v"], xn["w"]] + ([xn["b"]] if p.accel_bias else []))
         v_mean, P = combine(it, s.Sbar, prior, vel_prior, D, Sv)
         s.t, s.q = it[:3].copy(), it[3:].copy()
-        s.v, s.w = v_mean[:3].copy(), v_mean[3:].copy()
+        s.v, s.w = v_mean[:3].copy(), v_mean[3:6].copy()
+        if p.accel_bias:
+            s.b = v_mean[6:9].copy()
         s.P = P
         s.last.update(neq=neq, S_lap=S_lap, prior=prior)
         # map filter with the current state mean, then the next anchor

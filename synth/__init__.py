@@ -24,7 +24,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import Dict, List, Tuple
+from typing import Dict, List, Optional, Tuple
 
 import numpy as np
 
@@ -310,6 +310,10 @@ class Trajectory:
     v: np.ndarray      # [T, 3] linear velocity (world)
     w: np.ndarray      # [T, 3] angular velocity (world)
     u: np.ndarray      # [T-1, 6] controls between frames: (lin. accel, ang. accel), world
+    # [T-1, 6] the same with the accelerometer's body-frame specific force (its
+    # mean over the interval, bias and noise included) as the linear part
+    u_body: Optional[np.ndarray] = None
+    acc_bias: Optional[np.ndarray] = None   # [T-1, 3] true accelerometer bias at each interval's start
 
 
 def _skew_inv(S):
@@ -371,12 +375,16 @@ def uav_trajectory(seed: int, n_frames: int, centre: np.ndarray, dt: float = 0.1
     hs = dt / n_sub
     ba = np.zeros(3); bg = np.zeros(3)
     U = np.zeros((T - 1, 6))
+    UB = np.zeros((T - 1, 6))
+    BA = np.zeros((T - 1, 3))
     for i in range(T - 1):
-        accs = []
+        accs, fbs = [], []
+        BA[i] = ba
         for j in range(n_sub + 1):
             tt = ts[i] + j * hs
             _, R = pose_at(tt)
             f_b = R.T @ (acc_at(tt) - G_WORLD) + ba + rng.normal(0, acc_noise, 3)
+            fbs.append(f_b)
             accs.append(R @ (f_b - 0.0) + G_WORLD)
             ba = ba + rng.normal(0, acc_bias_walk, 3)
         gy = []
@@ -388,7 +396,9 @@ def uav_trajectory(seed: int, n_frames: int, centre: np.ndarray, dt: float = 0.1
             bg = bg + rng.normal(0, gyro_bias_walk, 3)
         U[i, :3] = np.mean(accs[:-1], axis=0)
         U[i, 3:] = (gy[1] - gy[0]) / dt
-    return Trajectory(dt=dt, t=P, q=Q, v=V, w=W, u=U)
+        UB[i, :3] = np.mean(fbs[:-1], axis=0)
+        UB[i, 3:] = U[i, 3:]
+    return Trajectory(dt=dt, t=P, q=Q, v=V, w=W, u=U, u_body=UB, acc_bias=BA)
 
 
 # --------------------------------------------------------------------------
