@@ -140,7 +140,8 @@ const char *prism_version(void);
 
 /* sizeof() of a public struct given its name ("prism_grid", "prism_camera",
  * "prism_pose", "prism_weights", "prism_map_params", "prism_filter_cfg",
- * "prism_filter_state", "prism_frame", "prism_adam_params"); 0 for an unknown
+ * "prism_filter_state", "prism_filter_bias_state", "prism_frame",
+ * "prism_adam_params"); 0 for an unknown
  * name.  Lets
  * bindings verify their struct mirrors. */
 size_t prism_sizeof(const char *type_name);
@@ -409,10 +410,24 @@ prism_status prism_map_gd(const prism_grid *grid, void *map, const prism_camera 
  *       residual r instead of w.  The gates are unchanged, and the Laplace
  *       covariance still squares the rows' Jacobian with weights w (App. E.3
  *       takes the curvature of the squared form).  prism_pose_update_adam
- *       returns PRISM_UNSUPPORTED for filters with this mode. */
+ *       returns PRISM_UNSUPPORTED for filters with this mode.
+ *   PRISM_MODE_ACCEL_BIAS a 15-D state: pose, velocities and an accelerometer
+ *       bias b (body frame; the paper's state is 12-D, App. E, and this
+ *       extension serves inputs from a biased IMU).  The linear part of each
+ *       frame's control is then the accelerometer's body-frame specific force
+ *       f (its mean over the frame interval), the acceleration R (f - b) + g
+ *       with the state's own rotation R and cfg->gravity; b follows a random
+ *       walk of cfg->sigma_bias per step.  Prediction, split and combination
+ *       run over the 15x15 covariance (tangent dt, dtheta, dv, dw, db) with a
+ *       9-D velocity-and-bias conditional; the pose objective is unchanged.
+ *       The bias, the full covariance and the conditional are in the filter's
+ *       prism_filter_bias_state (prism_filter_bias_state_ptr); the state's
+ *       P holds the leading 12x12 block.  Set the belief with
+ *       prism_filter_reset_bias.  prism_rollout returns PRISM_UNSUPPORTED. */
 #define PRISM_MODE_TRANSITION_DT2 1
 #define PRISM_MODE_LAPLACE_FACTOR1 2
 #define PRISM_MODE_IRLS_L1 4
+#define PRISM_MODE_ACCEL_BIAS 8
 
 typedef struct {
     prism_grid grid;
@@ -432,6 +447,9 @@ typedef struct {
     int32_t pad_;
     double irls_floor;                  /* PRISM_MODE_IRLS_L1: residual floor as a fraction of each
                                            row's scale b, finite and > 0; unused otherwise */
+    double sigma_bias;                  /* PRISM_MODE_ACCEL_BIAS: bias random walk per step (m/s^2),
+                                           >= 0; unused otherwise */
+    double gravity[3];                  /* PRISM_MODE_ACCEL_BIAS: gravity in the world frame (m/s^2) */
 } prism_filter_cfg;
 
 /* Device-resident filter state (first bytes of the state buffer), FP64.
@@ -457,6 +475,17 @@ typedef struct {
     int32_t has_sbar;
     int64_t n_updated_total; /* voxels updated by all map updates of the filter's steps */
 } prism_filter_state;
+
+/* The accelerometer-bias part of a PRISM_MODE_ACCEL_BIAS filter's state
+ * (device, FP64; in the state buffer after prism_filter_state).
+ * Covariances are row-major over the tangent (dt, dtheta, dv, dw, db). */
+typedef struct {
+    double b[3];          /* posterior mean bias */
+    double P[225];        /* 15x15 state covariance */
+    double D[54];         /* 9x6 gain of (dv, dw, db) on the pose offset */
+    double Sv[81];        /* 9x9 covariance of (dv, dw, db) given the pose */
+    double rest_prior[9]; /* predicted (v, w, b) */
+} prism_filter_bias_state;
 
 typedef struct prism_filter prism_filter;
 
@@ -485,6 +514,17 @@ prism_status prism_filter_destroy(prism_filter *f);
  * given).  Does not touch the map. */
 prism_status prism_filter_reset(prism_filter *f, const double *x0, const double *P0,
                                 hipStream_t stream);
+
+/* prism_filter_reset for PRISM_MODE_ACCEL_BIAS filters: x0 = (t[3], q[4],
+ * v[3], w[3], b[3]) and P0 [15x15] (tangent dt, dtheta, dv, dw, db), both
+ * host.  PRISM_UNSUPPORTED for filters without the mode (and
+ * prism_filter_reset is refused for filters with it). */
+prism_status prism_filter_reset_bias(prism_filter *f, const double *x0, const double *P0,
+                                     hipStream_t stream);
+
+/* Device address of a PRISM_MODE_ACCEL_BIAS filter's bias state (read it
+ * after the stream's work completes); PRISM_UNSUPPORTED without the mode. */
+prism_status prism_filter_bias_state_ptr(const prism_filter *f, prism_filter_bias_state **out);
 
 /* State filter only (Sec. 4.3.2): predict and split the state belief with
  * the frame's control, n_gn Gauss-Newton steps of the configured objective
@@ -657,8 +697,8 @@ prism_status prism_filter_poll_batch(prism_filter *const *fs, int32_t n, int64_t
 /* ---- checkpoints: the belief (q_t(M), q_t(x)) in and out (Sec. 4.2-4.3) ---- */
 
 /* Bytes of a checkpoint of a filter of this configuration: a 512-byte header,
- * the state buffer's belief part (state struct, anchor frame, relative pose)
- * and the whole map buffer. */
+ * the state buffer's belief part (state struct and bias state, anchor frame,
+ * relative pose) and the whole map buffer. */
 prism_status prism_filter_save_bytes(const prism_filter_cfg *cfg, size_t *bytes);
 
 /* Copies the filter's current belief (map and state, after every step queued
@@ -671,12 +711,14 @@ prism_status prism_filter_save_bytes(const prism_filter_cfg *cfg, size_t *bytes)
 prism_status prism_filter_save(prism_filter *f, void *dst, size_t dst_bytes, hipStream_t stream);
 
 /* Restores a checkpoint into f (the same handle or another one made with the
- * same grid and camera; the other configuration values may differ): map and
+ * same grid, camera and state size (12-D, or 15-D under PRISM_MODE_ACCEL_BIAS);
+ * the other configuration values may differ): map and
  * state are overwritten, the next step continues from the saved belief,
  * bit for bit as the saved filter would have.  Reads the header first, so
  * the call waits for `stream` (PRISM_CAPTURE_ERROR while it is being
  * captured) and fails with PRISM_INVALID_ARGUMENT, changing nothing, on a
- * bad magic, version, size, grid or camera.  No step of f may be in flight. */
+ * bad magic, version, size, grid, camera or state size.  No step of f may be
+ * in flight. */
 prism_status prism_filter_load(prism_filter *f, const void *src, size_t src_bytes, hipStream_t stream);
 
 /* Device pointer to the filter's prism_filter_state (inside state_mem). */

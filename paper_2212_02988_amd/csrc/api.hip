@@ -306,6 +306,7 @@ struct prism_filter {
     TransC tc;
     double lap_h;    // factor of H in the Laplace precision (2, or 1 under PRISM_MODE_LAPLACE_FACTOR1)
     prism_filter_state* S;
+    prism_filter_bias_state* X;   // the 15-D state's bias part (NULL without PRISM_MODE_ACCEL_BIAS)
     float *a_depth, *a_rgb, *a_normals;
     uint8_t *a_mask, *a_nmask;
     double* partials;
@@ -313,6 +314,7 @@ struct prism_filter {
     void* map;
     int64_t steps;
     prism_filter_state host_state;   // source of prism_filter_reset uploads
+    prism_filter_bias_state host_bias;   // source of prism_filter_reset_bias uploads
     double min_inliers;              // contributing pixels below which a step raises PRISM_FLAG_LOW_INLIERS
     // checkpoint header staged on the host, and the event after its last copy
     alignas(64) unsigned char save_hdr[512];
@@ -358,7 +360,7 @@ hipError_t release_graph(prism_filter::StepGraph& G) {
 }
 
 struct StateLayout {
-    size_t state, a_depth, a_rgb, a_normals, a_mask, a_nmask, partials, rel, desc, total;
+    size_t state, bias, a_depth, a_rgb, a_normals, a_mask, a_nmask, partials, rel, desc, total;
 };
 
 StateLayout state_layout(const prism_camera* c) {
@@ -368,6 +370,8 @@ StateLayout state_layout(const prism_camera* c) {
     size_t off = 0;
     L.state = off;
     off = round_up(off + sizeof(prism_filter_state), 256);
+    L.bias = off;   // the 15-D state's bias part (kept for every filter, a few KB)
+    off = round_up(off + sizeof(prism_filter_bias_state), 256);
     L.a_depth = off;
     off = round_up(off + 4 * npix, 256);
     L.a_rgb = off;
@@ -403,8 +407,13 @@ prism_status check_cfg(const prism_filter_cfg* cfg) {
     REQUIRE(cfg->map.trunc > 0 && cfg->map.lam_update > 0, "map trunc and lam_update must be > 0");
     REQUIRE(!isnan(cfg->normal_disc), "normal_disc is NaN");
     REQUIRE(cfg->min_inlier_frac >= 0 && cfg->min_inlier_frac <= 1, "min_inlier_frac must be in [0, 1]");
-    REQUIRE((cfg->modes & ~(PRISM_MODE_TRANSITION_DT2 | PRISM_MODE_LAPLACE_FACTOR1 | PRISM_MODE_IRLS_L1)) == 0,
+    REQUIRE((cfg->modes & ~(PRISM_MODE_TRANSITION_DT2 | PRISM_MODE_LAPLACE_FACTOR1 | PRISM_MODE_IRLS_L1 |
+                            PRISM_MODE_ACCEL_BIAS)) == 0,
             "unknown bits in modes (0x%x)", (unsigned)cfg->modes);
+    REQUIRE(!(cfg->modes & PRISM_MODE_ACCEL_BIAS) ||
+                (isfinite(cfg->sigma_bias) && cfg->sigma_bias >= 0 && isfinite(cfg->gravity[0]) &&
+                 isfinite(cfg->gravity[1]) && isfinite(cfg->gravity[2])),
+            "PRISM_MODE_ACCEL_BIAS needs a finite sigma_bias >= 0 and a finite gravity");
     REQUIRE(!(cfg->modes & PRISM_MODE_IRLS_L1) || (isfinite(cfg->irls_floor) && cfg->irls_floor > 0),
             "PRISM_MODE_IRLS_L1 needs a finite irls_floor > 0");
     return PRISM_OK;
@@ -442,7 +451,7 @@ prism_status eval_objective(prism_filter* f, const prism_frame* fr, int* nb, hip
 }
 
 prism_status pose_update_impl(prism_filter* f, const prism_frame* fr, hipStream_t st) {
-    HIP_TRY(launch_predict(f->S, fr->u, f->tc, f->rel, st));
+    HIP_TRY(launch_predict(f->S, f->X, fr->u, f->tc, f->rel, st));
     int nb = 0;
     prism_status s;
     for (int i = 0; i < f->cfg.n_gn; ++i) {
@@ -450,7 +459,7 @@ prism_status pose_update_impl(prism_filter* f, const prism_frame* fr, hipStream_
         HIP_TRY(launch_gn_step(f->S, f->partials, nb, f->rel, st));
     }
     if ((s = eval_objective(f, fr, &nb, st))) return s;
-    HIP_TRY(launch_laplace_combine(f->S, f->partials, nb, f->cfg.ema, f->min_inliers, f->lap_h, st));
+    HIP_TRY(launch_laplace_combine(f->S, f->X, f->partials, nb, f->cfg.ema, f->min_inliers, f->lap_h, st));
     return PRISM_OK;
 }
 
@@ -472,7 +481,7 @@ prism_status check_adam(const prism_filter* f, const prism_adam_params* p, const
 
 prism_status pose_update_adam_impl(prism_filter* f, const prism_frame* fr, const prism_adam_params* p,
                                    const int32_t* pixels, hipStream_t st) {
-    HIP_TRY(launch_predict(f->S, fr->u, f->tc, f->rel, st));
+    HIP_TRY(launch_predict(f->S, f->X, fr->u, f->tc, f->rel, st));
     AdamC ad;
     for (int i = 0; i < 3; ++i) {
         ad.lr[i] = p->lr_t;
@@ -489,7 +498,7 @@ prism_status pose_update_adam_impl(prism_filter* f, const prism_frame* fr, const
     prism_status s;
     // the optimiser moved the iterate: the objective forms its own relative pose
     if ((s = eval_objective(f, fr, &nb, st, false))) return s;
-    HIP_TRY(launch_laplace_combine(f->S, f->partials, nb, f->cfg.ema, f->min_inliers, f->lap_h, st));
+    HIP_TRY(launch_laplace_combine(f->S, f->X, f->partials, nb, f->cfg.ema, f->min_inliers, f->lap_h, st));
     return PRISM_OK;
 }
 
@@ -522,7 +531,8 @@ size_t prism_sizeof(const char* name) {
         {"prism_grid", sizeof(prism_grid)},         {"prism_camera", sizeof(prism_camera)},
         {"prism_pose", sizeof(prism_pose)},         {"prism_weights", sizeof(prism_weights)},
         {"prism_map_params", sizeof(prism_map_params)}, {"prism_filter_cfg", sizeof(prism_filter_cfg)},
-        {"prism_filter_state", sizeof(prism_filter_state)}, {"prism_frame", sizeof(prism_frame)},
+        {"prism_filter_state", sizeof(prism_filter_state)},
+        {"prism_filter_bias_state", sizeof(prism_filter_bias_state)}, {"prism_frame", sizeof(prism_frame)},
         {"prism_adam_params", sizeof(prism_adam_params)}};
     for (auto& e : t)
         if (!strcmp(e.n, name)) return e.s;
@@ -919,15 +929,19 @@ prism_status prism_filter_create(const prism_filter_cfg* cfg, void* state_mem, v
     f->lap_h = (cfg->modes & PRISM_MODE_LAPLACE_FACTOR1) ? 1.0 : 2.0;
     f->tc.dt = cfg->dt;
     f->tc.du = (cfg->modes & PRISM_MODE_TRANSITION_DT2) ? cfg->dt * cfg->dt : cfg->dt;
+    const bool bias = (cfg->modes & PRISM_MODE_ACCEL_BIAS) != 0;
     for (int i = 0; i < 3; ++i) {
         f->tc.q[i] = cfg->sigma_pose_t * cfg->sigma_pose_t;
         f->tc.q[3 + i] = cfg->sigma_pose_r * cfg->sigma_pose_r;
         f->tc.q[6 + i] = cfg->sigma_vel_t * cfg->sigma_vel_t;
         f->tc.q[9 + i] = cfg->sigma_vel_r * cfg->sigma_vel_r;
+        f->tc.q[12 + i] = bias ? cfg->sigma_bias * cfg->sigma_bias : 0.0;
+        f->tc.g[i] = bias ? cfg->gravity[i] : 0.0;
     }
     StateLayout L = state_layout(&cfg->cam);
     char* base = (char*)state_mem;
     f->S = (prism_filter_state*)(base + L.state);
+    f->X = bias ? (prism_filter_bias_state*)(base + L.bias) : nullptr;
     f->a_depth = (float*)(base + L.a_depth);
     f->a_rgb = (float*)(base + L.a_rgb);
     f->a_normals = (float*)(base + L.a_normals);
@@ -961,6 +975,7 @@ prism_status prism_filter_create(const prism_filter_cfg* cfg, void* state_mem, v
     D.map = map_mem;
     D.bits = skip_table(&cfg->grid, &cfg->cam, map_mem);
     D.S = f->S;
+    D.X = f->X;
     D.a_depth = f->a_depth;
     D.a_rgb = f->a_rgb;
     D.a_normals = f->a_normals;
@@ -1002,6 +1017,7 @@ prism_status prism_filter_destroy(prism_filter* f) {
 
 prism_status prism_filter_reset(prism_filter* f, const double* x0, const double* P0, hipStream_t stream) {
     REQUIRE(f && x0 && P0, "filter, x0 and P0 must be non-NULL");
+    if (f->X) return fail(PRISM_UNSUPPORTED, "the filter has the 15-D state: use prism_filter_reset_bias");
     for (int i = 0; i < 13; ++i) REQUIRE(isfinite(x0[i]), "x0 not finite");
     for (int i = 0; i < 144; ++i) REQUIRE(isfinite(P0[i]), "P0 not finite");
     prism_filter_state& h = f->host_state;
@@ -1017,6 +1033,33 @@ prism_status prism_filter_reset(prism_filter* f, const double* x0, const double*
     h.prior = h.pose;
     h.iter = h.pose;
     HIP_TRY(hipMemcpyAsync(f->S, &h, sizeof h, hipMemcpyHostToDevice, stream));
+    f->steps = 0;
+    return PRISM_OK;
+}
+
+prism_status prism_filter_reset_bias(prism_filter* f, const double* x0, const double* P0, hipStream_t stream) {
+    REQUIRE(f && x0 && P0, "filter, x0 and P0 must be non-NULL");
+    if (!f->X) return fail(PRISM_UNSUPPORTED, "prism_filter_reset_bias needs PRISM_MODE_ACCEL_BIAS");
+    for (int i = 0; i < 16; ++i) REQUIRE(isfinite(x0[i]), "x0 not finite");
+    for (int i = 0; i < 225; ++i) REQUIRE(isfinite(P0[i]), "P0 not finite");
+    prism_filter_state& h = f->host_state;
+    memset(&h, 0, sizeof h);
+    for (int i = 0; i < 3; ++i) h.pose.t[i] = x0[i];
+    for (int i = 0; i < 4; ++i) h.pose.q[i] = x0[3 + i];
+    for (int i = 0; i < 3; ++i) {
+        h.v[i] = x0[7 + i];
+        h.w[i] = x0[10 + i];
+    }
+    for (int i = 0; i < 144; ++i) h.P[i] = P0[(i / 12) * 15 + i % 12];
+    h.anchor = h.pose;
+    h.prior = h.pose;
+    h.iter = h.pose;
+    prism_filter_bias_state& hb = f->host_bias;
+    memset(&hb, 0, sizeof hb);
+    for (int i = 0; i < 3; ++i) hb.b[i] = x0[13 + i];
+    memcpy(hb.P, P0, sizeof hb.P);
+    HIP_TRY(hipMemcpyAsync(f->S, &h, sizeof h, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(f->X, &hb, sizeof hb, hipMemcpyHostToDevice, stream));
     f->steps = 0;
     return PRISM_OK;
 }
@@ -1060,6 +1103,7 @@ prism_status prism_rollout(prism_filter* f, const double* u, int32_t k, int32_t 
                            prism_pose* poses, double* mean, double* cov, float* depth, float* rgb, uint8_t* mask,
                            int32_t* flags, hipStream_t stream) {
     REQUIRE(f, "filter is NULL");
+    if (f->X) return fail(PRISM_UNSUPPORTED, "rollouts are defined for the 12-D state");
     REQUIRE(k >= 1 && k <= 4096, "k must be in [1, 4096]");
     REQUIRE(n_samples >= 0 && n_samples <= 65535, "n_samples must be in [0, 65535]");
     REQUIRE(u && aligned(u, 8), "controls u must be non-NULL and 8-byte aligned");
@@ -1688,9 +1732,11 @@ struct CkptHeader {
     prism_camera cam;
     int64_t steps;
     uint64_t state_bytes, rel_bytes, map_bytes;
+    int32_t state_dim;   // 12, or 15 with the accelerometer bias
 };
 static_assert(sizeof(CkptHeader) <= 512, "checkpoint header exceeds its 512 bytes");
 constexpr char kCkptMagic[8] = {'P', 'R', 'I', 'S', 'M', 'C', 'K', '1'};
+constexpr uint32_t kCkptVersion = 2;
 constexpr size_t kCkptHeader = 512;
 
 size_t ckpt_bytes(const prism_filter_cfg* cfg, StateLayout* Lout = nullptr) {
@@ -1738,7 +1784,8 @@ prism_status prism_filter_save(prism_filter* f, void* dst, size_t dst_bytes, hip
     CkptHeader h;
     memset(&h, 0, sizeof h);
     memcpy(h.magic, kCkptMagic, 8);
-    h.version = 1;
+    h.version = kCkptVersion;
+    h.state_dim = f->X ? 15 : 12;
     h.header_bytes = (uint32_t)kCkptHeader;
     h.grid = f->cfg.grid;
     h.cam = f->cfg.cam;
@@ -1768,8 +1815,10 @@ prism_status prism_filter_load(prism_filter* f, const void* src, size_t src_byte
     CkptHeader h;
     HIP_TRY(hipMemcpyAsync(&h, src, sizeof h, hipMemcpyDefault, stream));
     HIP_TRY(hipStreamSynchronize(stream));
-    REQUIRE(memcmp(h.magic, kCkptMagic, 8) == 0 && h.version == 1 && h.header_bytes == kCkptHeader,
+    REQUIRE(memcmp(h.magic, kCkptMagic, 8) == 0 && h.version == kCkptVersion && h.header_bytes == kCkptHeader,
             "not a checkpoint of this library (magic or version)");
+    REQUIRE(h.state_dim == (f->X ? 15 : 12), "checkpoint state is %d-D, the filter's %d-D", (int)h.state_dim,
+            f->X ? 15 : 12);
     REQUIRE(same_grid(h.grid, f->cfg.grid), "checkpoint grid differs from the filter's grid");
     REQUIRE(same_cam(h.cam, f->cfg.cam), "checkpoint camera differs from the filter's camera");
     const size_t mbytes = map_layout(&f->cfg.grid).total;
@@ -1799,6 +1848,13 @@ prism_status prism_pose_retract(const prism_pose* poses, const double* delta, in
 prism_status prism_filter_state_ptr(const prism_filter* f, prism_filter_state** state) {
     REQUIRE(f && state, "filter and state must be non-NULL");
     *state = f->S;
+    return PRISM_OK;
+}
+
+prism_status prism_filter_bias_state_ptr(const prism_filter* f, prism_filter_bias_state** out) {
+    REQUIRE(f && out, "filter and out must be non-NULL");
+    if (!f->X) return fail(PRISM_UNSUPPORTED, "the filter has no bias state (PRISM_MODE_ACCEL_BIAS)");
+    *out = f->X;
     return PRISM_OK;
 }
 

@@ -10,7 +10,8 @@ namespace prism {
 struct TransC {
     double dt;
     double du;   // factor of the control in the velocity update: dt, or dt^2 (the printed form)
-    double q[12];
+    double q[15];   // (q[12..14]: the bias random walk of the 15-D state)
+    double g[3];    // gravity (15-D state: the linear control is a body-frame specific force)
 };
 
 struct MapUpdC {
@@ -44,6 +45,7 @@ struct AgentDesc {
     void* map;
     const unsigned* bits;   // free-space bits for the renderer (NULL when tau != 0)
     prism_filter_state* S;
+    prism_filter_bias_state* X;   // the 15-D state's bias part (NULL for the 12-D state)
     float *a_depth, *a_rgb, *a_normals;
     uint8_t *a_mask, *a_nmask;
     double* partials;
@@ -178,10 +180,11 @@ hipError_t launch_pose_adam(prism_filter_state* S, const CamC& c, const CamD& cd
 hipError_t launch_rollout(const prism_filter_state* S, const double* u, int k, int n_samples, const double* noise,
                           const TransC& tc, prism_pose* poses, double* mean, double* cov, int32_t* flags,
                           hipStream_t st);
-hipError_t launch_predict(prism_filter_state* S, const double* u, const TransC& tc, Rel32* rel, hipStream_t st);
+hipError_t launch_predict(prism_filter_state* S, prism_filter_bias_state* X, const double* u, const TransC& tc,
+                          Rel32* rel, hipStream_t st);
 hipError_t launch_gn_step(prism_filter_state* S, const double* partials, int nblocks, Rel32* rel, hipStream_t st);
-hipError_t launch_laplace_combine(prism_filter_state* S, const double* partials, int nblocks, double ema,
-                                  double min_inliers, double lap_h, hipStream_t st);
+hipError_t launch_laplace_combine(prism_filter_state* S, prism_filter_bias_state* X, const double* partials,
+                                  int nblocks, double ema, double min_inliers, double lap_h, hipStream_t st);
 // the left, world-frame retraction t <- t + dt, R <- Exp(dtheta) R of n poses
 hipError_t launch_pose_retract(const prism_pose* poses, const double* delta, int n, prism_pose* out, hipStream_t st);
 hipError_t launch_first_frame(prism_filter_state* S, hipStream_t st);

@@ -304,9 +304,153 @@ __device__ __forceinline__ void predict_block(prism_filter_state* __restrict__ S
     state_out(S, Sg);
 }
 
+// The 15-D state (pose, velocities, accelerometer bias b): the linear
+// control u[0..2] is the body-frame specific force f, the acceleration
+// a = R (f - b) + g with the state's rotation R; then the mean transition
+// above with a as the linear acceleration.  Ra = R (f - b) and R are kept
+// for the linearisation.  One thread.
+__device__ inline void transition_mean_bias_t0(const prism_pose& pose, const double* v0, const double* w0,
+                                               const double* b, const double* u, const TransC& tc, double* vnew,
+                                               double* E, double* Jl, double* Ra, double* R0, prism_pose& pr) {
+    double R[9];
+    quat_to_R9(pose.q, R);
+    const double f[3] = {u[0] - b[0], u[1] - b[1], u[2] - b[2]};
+    double a[6];
+    for (int i = 0; i < 3; ++i) {
+        Ra[i] = R[i * 3] * f[0] + R[i * 3 + 1] * f[1] + R[i * 3 + 2] * f[2];
+        a[i] = Ra[i] + tc.g[i];
+        a[3 + i] = u[3 + i];
+    }
+    for (int e = 0; e < 9; ++e) R0[e] = R[e];
+    transition_mean_t0(pose, v0, w0, a, tc, vnew, E, Jl, pr);
+}
+
+// Covariance of the linearised 15-D transition, whole workgroup: the blocks
+// of transition_cov plus the acceleration's dependence on the rotation and
+// the bias at the start of the step, da = -[R (f - b)]x dtheta - R db,
+// entering v' over du and t' through v' dt; the bias is a random walk.
+// P, M, G, T1, T2: LDS [225].
+__device__ inline void transition_cov_bias(const double* E, const double* Jl, const double* Ra, const double* R0,
+                                           const TransC& tc, const double* P, double* M, double* G, double* T1,
+                                           double* T2) {
+    constexpr int N = 15;
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+        M[e] = 0.0;
+        G[e] = 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double K[9] = {0.0, -Ra[2], Ra[1], Ra[2], 0.0, -Ra[0], -Ra[1], Ra[0], 0.0};
+        for (int i = 0; i < 3; ++i) {
+            M[i * N + i] = 1.0;
+            M[i * N + 6 + i] = tc.dt;
+            M[(6 + i) * N + 6 + i] = 1.0;
+            M[(9 + i) * N + 9 + i] = 1.0;
+            M[(12 + i) * N + 12 + i] = 1.0;
+            G[i * N + i] = 1.0;
+            G[i * N + 6 + i] = tc.dt;
+            G[(3 + i) * N + 3 + i] = 1.0;
+            G[(6 + i) * N + 6 + i] = 1.0;
+            G[(9 + i) * N + 9 + i] = 1.0;
+            G[(12 + i) * N + 12 + i] = 1.0;
+            for (int j = 0; j < 3; ++j) {
+                M[(3 + i) * N + 3 + j] = E[i * 3 + j];
+                M[(3 + i) * N + 9 + j] = tc.dt * Jl[i * 3 + j];
+                G[(3 + i) * N + 9 + j] = tc.dt * Jl[i * 3 + j];
+                const double vth = -tc.du * K[i * 3 + j], vb = -tc.du * R0[i * 3 + j];
+                M[(6 + i) * N + 3 + j] = vth;
+                M[(6 + i) * N + 12 + j] = vb;
+                M[i * N + 3 + j] = tc.dt * vth;
+                M[i * N + 12 + j] = tc.dt * vb;
+            }
+        }
+    }
+    __syncthreads();
+    mm(M, P, T1, N, N, N, false);       // M P
+    mm(T1, M, T2, N, N, N, true);       // M P M^T
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+        int i = e / N, j = e % N;
+        double s = 0.0;
+        for (int q = 0; q < N; ++q) s += G[i * N + q] * tc.q[q] * G[j * N + q];
+        T2[e] += s;
+    }
+    __syncthreads();
+    symmetrize(T2, N);
+}
+
+// predict + split of the 15-D state: the pose prior as for the 12-D state,
+// the 9-D conditional of (v, w, b) given the pose into X
+__device__ __forceinline__ void predict_block_bias(prism_filter_state* __restrict__ Sg,
+                                                   prism_filter_bias_state* __restrict__ X,
+                                                   const double* __restrict__ u, const TransC& tc,
+                                                   Rel32* __restrict__ rel) {
+    constexpr int N = 15, NR = 9;
+    __shared__ double M[N * N], G[N * N], T1[N * N], T2[N * N], P[N * N], L[36], Sinv[36];
+    __shared__ double vnew[6], E[9], Jl[9], Ra[3], R0[9], b[3];
+    __shared__ int ok;
+    __shared__ prism_filter_state Ls;
+    state_in(Sg, &Ls);
+    prism_filter_state* S = &Ls;
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) P[e] = X->P[e];
+    if (threadIdx.x < 3) b[threadIdx.x] = X->b[threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        S->flags = 0;
+        for (int i = 0; i < 6; ++i) S->u[i] = u[i];
+        prism_pose pr;
+        transition_mean_bias_t0(S->pose, S->v, S->w, b, u, tc, vnew, E, Jl, Ra, R0, pr);
+        S->prior = pr;
+        S->iter = pr;
+        if (rel) rel_of(&S->iter, &S->anchor, *rel);
+        for (int i = 0; i < 6; ++i) S->vel_prior[i] = vnew[i];
+    }
+    __syncthreads();
+    transition_cov_bias(E, Jl, Ra, R0, tc, P, M, G, T1, T2);
+    for (int e = threadIdx.x; e < 36; e += blockDim.x) L[e] = T2[(e / 6) * N + e % 6];
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) X->P[e] = T2[e];
+    for (int e = threadIdx.x; e < 144; e += blockDim.x) S->P[e] = T2[(e / 12) * N + e % 12];
+    if (threadIdx.x < 6) X->rest_prior[threadIdx.x] = vnew[threadIdx.x];
+    else if (threadIdx.x < NR) X->rest_prior[threadIdx.x] = b[threadIdx.x - 6];
+    __syncthreads();
+    if (threadIdx.x == 0) ok = chol<6>(L);
+    __syncthreads();
+    if (!ok) {
+        // no MAP problem: the step keeps the predicted mean and covariance
+        if (threadIdx.x == 0) S->flags |= PRISM_FLAG_CHOL_FALLBACK | PRISM_FLAG_PRIOR_NOT_PD;
+        state_out(S, Sg);
+        return;
+    }
+    chol_inverse<6>(L, Sinv);
+    symmetrize(Sinv, 6);
+    // D = P_rp Sinv [9 x 6], Sv = P_rr - D P_rp^T [9 x 9]
+    for (int e = threadIdx.x; e < NR * 6; e += blockDim.x) {
+        int i = e / 6, j = e % 6;
+        double s = 0.0;
+        for (int q = 0; q < 6; ++q) s += T2[(6 + i) * N + q] * Sinv[q * 6 + j];
+        T1[e] = s;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < NR * NR; e += blockDim.x) {
+        int i = e / NR, j = e % NR;
+        double s = 0.0;
+        for (int q = 0; q < 6; ++q) s += T1[i * 6 + q] * T2[(6 + j) * N + q];
+        P[e] = T2[(6 + i) * N + 6 + j] - s;
+    }
+    __syncthreads();
+    symmetrize(P, NR);
+    for (int e = threadIdx.x; e < 36; e += blockDim.x) S->Lp[e] = Sinv[e];
+    for (int e = threadIdx.x; e < NR * 6; e += blockDim.x) X->D[e] = T1[e];
+    for (int e = threadIdx.x; e < NR * NR; e += blockDim.x) X->Sv[e] = P[e];
+    state_out(S, Sg);
+}
+
 __global__ __launch_bounds__(256) void k_predict(prism_filter_state* __restrict__ Sg,
+                                                 prism_filter_bias_state* __restrict__ X,
                                                  const double* __restrict__ u, TransC tc, Rel32* __restrict__ rel) {
-    predict_block(Sg, u, tc, rel);
+    if (X)
+        predict_block_bias(Sg, X, u, tc, rel);
+    else
+        predict_block(Sg, u, tc, rel);
 }
 
 // ---------------------------------------------------------------------------
@@ -363,7 +507,48 @@ __global__ __launch_bounds__(512) void k_gn_step(prism_filter_state* __restrict_
 // ---------------------------------------------------------------------------
 // Laplace covariance, EMA, product with the velocity conditional
 // ---------------------------------------------------------------------------
+// The product with the 9-D conditional of (v, w, b) of the 15-D state:
+// joint covariance [[Sb, Sb D^T], [D Sb, Sv + D Sb D^T]] over 15 dimensions,
+// means rest_prior + D e; the leading 12x12 block also into S->P.
+__device__ inline void combine_bias(prism_filter_state* S, prism_filter_bias_state* __restrict__ X,
+                                    const double* Sb, const double* e) {
+    constexpr int N = 15, NR = 9;
+    __shared__ double D9[NR * 6], T9[NR * 6], P15[N * N];
+    for (int i = threadIdx.x; i < NR * 6; i += blockDim.x) D9[i] = X->D[i];
+    __syncthreads();
+    mm(D9, Sb, T9, NR, 6, 6, false);   // D Sb
+    for (int e2 = threadIdx.x; e2 < N * N; e2 += blockDim.x) {
+        int i = e2 / N, j = e2 % N;
+        double s;
+        if (i < 6 && j < 6) s = Sb[i * 6 + j];
+        else if (i < 6) s = T9[(j - 6) * 6 + i];
+        else if (j < 6) s = T9[(i - 6) * 6 + j];
+        else {
+            s = X->Sv[(i - 6) * NR + (j - 6)];
+            for (int q = 0; q < 6; ++q) s += T9[(i - 6) * 6 + q] * D9[(j - 6) * 6 + q];
+        }
+        P15[e2] = s;
+    }
+    __syncthreads();
+    symmetrize(P15, N);
+    for (int e2 = threadIdx.x; e2 < N * N; e2 += blockDim.x) X->P[e2] = P15[e2];
+    for (int e2 = threadIdx.x; e2 < 144; e2 += blockDim.x) S->P[e2] = P15[(e2 / 12) * N + e2 % 12];
+    if (threadIdx.x == 0) {
+        double vm[NR];
+        for (int i = 0; i < NR; ++i) {
+            vm[i] = X->rest_prior[i];
+            for (int j = 0; j < 6; ++j) vm[i] += D9[i * 6 + j] * e[j];
+        }
+        for (int i = 0; i < 3; ++i) {
+            S->v[i] = vm[i];
+            S->w[i] = vm[3 + i];
+            X->b[i] = vm[6 + i];
+        }
+    }
+}
+
 __device__ __forceinline__ void laplace_combine_block(prism_filter_state* __restrict__ Sg,
+                                                      prism_filter_bias_state* __restrict__ X,
                                                       const double* __restrict__ partials, int nblocks, double ema,
                                                       double min_inliers, double lap_h) {
     __shared__ double red[kRedLds], neq[PRISM_NEQ];
@@ -381,6 +566,8 @@ __device__ __forceinline__ void laplace_combine_block(prism_filter_state* __rest
             if (!(neq[28] > 0.0)) S->flags |= PRISM_FLAG_NO_VALID_PIXELS;
             if (neq[28] < min_inliers) S->flags |= PRISM_FLAG_LOW_INLIERS;
             for (int i = 0; i < 3; ++i) { S->v[i] = S->vel_prior[i]; S->w[i] = S->vel_prior[3 + i]; }
+            if (X)
+                for (int i = 0; i < 3; ++i) X->b[i] = X->rest_prior[6 + i];
             S->iter = S->prior;
             S->pose = S->prior;
             S->anchor = S->prior;
@@ -424,6 +611,18 @@ __device__ __forceinline__ void laplace_combine_block(prism_filter_state* __rest
     }
     if (threadIdx.x == 0) pose_err(S->iter, S->prior, e);
     __syncthreads();
+    if (X) {
+        combine_bias(S, X, Sb, e);
+        if (threadIdx.x < 36) S->Sbar[threadIdx.x] = Sb[threadIdx.x];
+        if (threadIdx.x == 0) {
+            S->has_sbar = 1;
+            S->pose = S->iter;
+            S->anchor = S->iter;
+            S->step += 1;
+        }
+        state_out(S, Sg);
+        return;
+    }
     // joint covariance [[Sb, Sb D^T], [D Sb, Sv + D Sb D^T]]
     mm(D, Sb, T, 6, 6, 6, false);   // D Sb
     for (int e2 = threadIdx.x; e2 < 144; e2 += blockDim.x) {
@@ -458,9 +657,10 @@ __device__ __forceinline__ void laplace_combine_block(prism_filter_state* __rest
 }
 
 __global__ __launch_bounds__(512) void k_laplace_combine(prism_filter_state* __restrict__ Sg,
+                                                         prism_filter_bias_state* __restrict__ X,
                                                          const double* __restrict__ partials, int nblocks,
                                                          double ema, double min_inliers, double lap_h) {
-    laplace_combine_block(Sg, partials, nblocks, ema, min_inliers, lap_h);
+    laplace_combine_block(Sg, X, partials, nblocks, ema, min_inliers, lap_h);
 }
 
 // the left, world-frame retraction of n poses by n tangent increments
@@ -489,7 +689,10 @@ __global__ void k_first_frame(prism_filter_state* __restrict__ S) { first_frame_
 // batched: one workgroup per filter
 __global__ __launch_bounds__(256) void k_predict_batch(BatchArgs b) {
     const AgentDesc& D = *b.d[blockIdx.x];
-    predict_block(D.S, (const double*)D.slots[b.slot[blockIdx.x]].u, D.tc, D.rel);
+    if (D.X)
+        predict_block_bias(D.S, D.X, (const double*)D.slots[b.slot[blockIdx.x]].u, D.tc, D.rel);
+    else
+        predict_block(D.S, (const double*)D.slots[b.slot[blockIdx.x]].u, D.tc, D.rel);
 }
 
 __global__ __launch_bounds__(512) void k_gn_step_batch(BatchArgs b) {
@@ -499,7 +702,7 @@ __global__ __launch_bounds__(512) void k_gn_step_batch(BatchArgs b) {
 
 __global__ __launch_bounds__(512) void k_laplace_combine_batch(BatchArgs b) {
     const AgentDesc& D = *b.d[blockIdx.x];
-    laplace_combine_block(D.S, D.partials, D.obj_blocks, D.ema, D.min_inliers, D.lap_h);
+    laplace_combine_block(D.S, D.X, D.partials, D.obj_blocks, D.ema, D.min_inliers, D.lap_h);
 }
 
 __global__ __launch_bounds__(64) void k_first_frame_batch(BatchArgs b) { first_frame_block(b.d[blockIdx.x]->S); }
@@ -633,8 +836,9 @@ __global__ __launch_bounds__(512) void k_finalize(const double* __restrict__ par
     if ((int)threadIdx.x < nvals) out[(long long)blockIdx.x * stride + threadIdx.x] = neq[threadIdx.x];
 }
 
-hipError_t launch_predict(prism_filter_state* S, const double* u, const TransC& tc, Rel32* rel, hipStream_t st) {
-    k_predict<<<1, 256, 0, st>>>(S, u, tc, rel);
+hipError_t launch_predict(prism_filter_state* S, prism_filter_bias_state* X, const double* u, const TransC& tc,
+                          Rel32* rel, hipStream_t st) {
+    k_predict<<<1, 256, 0, st>>>(S, X, u, tc, rel);
     return hipGetLastError();
 }
 
@@ -644,9 +848,9 @@ hipError_t launch_gn_step(prism_filter_state* S, const double* partials, int nbl
     return hipGetLastError();
 }
 
-hipError_t launch_laplace_combine(prism_filter_state* S, const double* partials, int nblocks, double ema,
-                                  double min_inliers, double lap_h, hipStream_t st) {
-    k_laplace_combine<<<1, 512, 0, st>>>(S, partials, nblocks, ema, min_inliers, lap_h);
+hipError_t launch_laplace_combine(prism_filter_state* S, prism_filter_bias_state* X, const double* partials,
+                                  int nblocks, double ema, double min_inliers, double lap_h, hipStream_t st) {
+    k_laplace_combine<<<1, 512, 0, st>>>(S, X, partials, nblocks, ema, min_inliers, lap_h);
     return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@ PRISM_F32, PRISM_BF16 = 0, 1
 OBJ_P2, OBJ_P1 = 0, 1
 FLAG_NO_VALID_PIXELS, FLAG_CHOL_FALLBACK, FLAG_PRIOR_NOT_PD, FLAG_LOW_INLIERS = 1, 2, 4, 8
 # the paper's literal forms (prism_filter_cfg.modes)
-MODE_TRANSITION_DT2, MODE_LAPLACE_FACTOR1, MODE_IRLS_L1 = 1, 2, 4
+MODE_TRANSITION_DT2, MODE_LAPLACE_FACTOR1, MODE_IRLS_L1, MODE_ACCEL_BIAS = 1, 2, 4, 8
 NEQ = 29
 
 
@@ -95,7 +95,7 @@ class FilterCfg(ctypes.Structure):
                 ("w", Weights), ("ema", ctypes.c_double), ("n_gn", ctypes.c_int32),
                 ("objective", ctypes.c_int32), ("map", MapParams), ("normal_disc", ctypes.c_double),
                 ("min_inlier_frac", ctypes.c_double), ("modes", ctypes.c_int32), ("pad_", ctypes.c_int32),
-                ("irls_floor", ctypes.c_double)]
+                ("irls_floor", ctypes.c_double), ("sigma_bias", ctypes.c_double), ("gravity", ctypes.c_double * 3)]
 
 
 class FilterState(ctypes.Structure):
@@ -106,6 +106,11 @@ class FilterState(ctypes.Structure):
                 ("S_lap", ctypes.c_double * 36), ("neq", ctypes.c_double * 29), ("u", ctypes.c_double * 6),
                 ("step", ctypes.c_int64), ("n_updated", ctypes.c_int64), ("flags", ctypes.c_int32),
                 ("has_sbar", ctypes.c_int32), ("n_updated_total", ctypes.c_int64)]
+
+
+class BiasState(ctypes.Structure):
+    _fields_ = [("b", ctypes.c_double * 3), ("P", ctypes.c_double * 225), ("D", ctypes.c_double * 54),
+                ("Sv", ctypes.c_double * 81), ("rest_prior", ctypes.c_double * 9)]
 
 
 class Frame(ctypes.Structure):
@@ -159,6 +164,8 @@ _SIGS = {
     "prism_filter_create": (["p", "p", "p", "p"], None),
     "prism_filter_destroy": (["p"], None),
     "prism_filter_reset": (["p", "p", "p", "p"], None),
+    "prism_filter_reset_bias": (["p", "p", "p", "p"], None),
+    "prism_filter_bias_state_ptr": (["p", "p"], None),
     "prism_pose_update": (["p", "p", "p"], None),
     "prism_pose_update_adam": (["p", "p", "p", "p", "p"], None),
     "prism_filter_step_adam": (["p", "p", "p", "p", "p"], None),
@@ -532,15 +539,18 @@ class FilterParams:
     sigma_update: float = 1.0
     normal_disc: float = 0.1
     min_inlier_frac: float = 0.1
-    modes: int = 0             # MODE_* bits: the paper's literal forms
+    modes: int = 0             # MODE_* bits: the paper's literal forms, the 15-D state
     irls_floor: float = 0.01   # MODE_IRLS_L1: residual floor as a fraction of each row's scale b
+    sigma_bias: float = 0.001  # MODE_ACCEL_BIAS: bias random walk per step (m/s^2)
+    gravity: tuple = (0.0, 0.0, -9.81)   # MODE_ACCEL_BIAS: world-frame gravity
 
 
 def filter_cfg(grid: Grid, cam: Camera, p: FilterParams) -> FilterCfg:
     return FilterCfg(grid, cam, p.dt, p.sigma_vel_t, p.sigma_vel_r, p.sigma_pose_t, p.sigma_pose_r,
                      Weights.make(p.b_geo, p.b_rgb, p.gate_geo, p.gate_rgb), p.ema, p.n_gn, p.objective,
                      MapParams(p.trunc_voxels * grid.voxel, 1.0 / p.sigma_update ** 2), p.normal_disc,
-                     p.min_inlier_frac, p.modes, 0, p.irls_floor)
+                     p.min_inlier_frac, p.modes, 0, p.irls_floor, p.sigma_bias,
+                     (ctypes.c_double * 3)(*[float(v) for v in p.gravity]))
 
 
 def filter_bytes(cfg: FilterCfg) -> int:
@@ -577,9 +587,13 @@ class Filter:
             pass
 
     def reset(self, x0, P0, stream=None):
-        x = (ctypes.c_double * 13)(*[float(v) for v in x0])
-        P = (ctypes.c_double * 144)(*[float(v) for v in torch.as_tensor(P0, dtype=torch.float64).flatten()])
-        _check(lib().prism_filter_reset(self.h, x, P, _stream(stream)))
+        """x0 = (t, q, v, w) and P0 12x12; with MODE_ACCEL_BIAS x0 = (t, q, v,
+        w, b) and P0 15x15."""
+        n = 15 if self.params.modes & MODE_ACCEL_BIAS else 12
+        x = (ctypes.c_double * (n + 1))(*[float(v) for v in x0])
+        P = (ctypes.c_double * (n * n))(*[float(v) for v in torch.as_tensor(P0, dtype=torch.float64).flatten()])
+        fn = lib().prism_filter_reset_bias if n == 15 else lib().prism_filter_reset
+        _check(fn(self.h, x, P, _stream(stream)))
         # the source buffer of the upload lives in the handle; no sync needed
 
     @staticmethod
@@ -703,6 +717,15 @@ class Filter:
         nb = ctypes.sizeof(FilterState)
         raw = self.state_buf[self._state_off:self._state_off + nb].cpu().numpy().tobytes()
         return FilterState.from_buffer_copy(raw)
+
+    def bias_state(self) -> BiasState:
+        """Synchronous read-back of the 15-D state's bias part (MODE_ACCEL_BIAS)."""
+        p = ctypes.c_void_p()
+        _check(lib().prism_filter_bias_state_ptr(self.h, _by(p)))
+        off = p.value - self.state_buf.data_ptr()
+        nb = ctypes.sizeof(BiasState)
+        raw = self.state_buf[off:off + nb].cpu().numpy().tobytes()
+        return BiasState.from_buffer_copy(raw)
 
     def anchor(self) -> Dict[str, torch.Tensor]:
         ptrs = [ctypes.c_void_p() for _ in range(5)]

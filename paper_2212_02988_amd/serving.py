@@ -45,8 +45,8 @@ class StreamSpec:
     grid: P.Grid
     cam: P.Camera
     params: P.FilterParams
-    x0: np.ndarray                   # (t, q, v, w), 13 values
-    P0: np.ndarray                   # 12 x 12
+    x0: np.ndarray                   # (t, q, v, w), 13 values; (t, q, v, w, b), 16 with MODE_ACCEL_BIAS
+    P0: np.ndarray                   # 12 x 12; 15 x 15 with MODE_ACCEL_BIAS
     n_frames: int                    # the stream closes after this many frames
 
 

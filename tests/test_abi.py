@@ -36,6 +36,7 @@ def test_struct_mirrors(P):
     for name, cls in [("prism_grid", P.Grid), ("prism_camera", P.Camera), ("prism_pose", P.Pose),
                       ("prism_weights", P.Weights), ("prism_map_params", P.MapParams),
                       ("prism_filter_cfg", P.FilterCfg), ("prism_filter_state", P.FilterState),
+                      ("prism_filter_bias_state", P.BiasState),
                       ("prism_frame", P.Frame), ("prism_adam_params", P.AdamParams)]:
         assert L.prism_sizeof(name.encode()) == ctypes.sizeof(cls), name
     assert L.prism_sizeof(b"nope") == 0
@@ -101,20 +102,23 @@ def test_workspace_and_filter_sizes(P):
 
 
 def test_paper_modes_are_validated(P):
-    """cfg.modes takes the three documented bits in any combination; the L1
-    mode needs a positive floor; unknown bits are refused."""
+    """cfg.modes takes the four documented bits in any combination; the L1
+    mode needs a positive floor, the 15-D state a finite bias walk and
+    gravity; unknown bits are refused."""
     L = P.lib()
     cam = P.Camera.make(64, 48, 50, 50, 32, 24, 0.1, 4.0, 64)
     g = P.Grid.make(64, 0.04)
     b = ctypes.c_size_t()
-    for modes in range(8):
+    for modes in range(16):
         cfg = P.filter_cfg(g, cam, P.FilterParams(modes=modes))
         assert L.prism_filter_bytes(ctypes.byref(cfg), ctypes.byref(b)) == 0, modes
-    for bad in (P.FilterParams(modes=8), P.FilterParams(modes=P.MODE_IRLS_L1, irls_floor=0.0),
-                P.FilterParams(modes=P.MODE_IRLS_L1, irls_floor=float("nan"))):
+    for bad in (P.FilterParams(modes=16), P.FilterParams(modes=P.MODE_IRLS_L1, irls_floor=0.0),
+                P.FilterParams(modes=P.MODE_IRLS_L1, irls_floor=float("nan")),
+                P.FilterParams(modes=P.MODE_ACCEL_BIAS, sigma_bias=-1.0),
+                P.FilterParams(modes=P.MODE_ACCEL_BIAS, gravity=(0.0, 0.0, float("inf")))):
         cfg = P.filter_cfg(g, cam, bad)
         assert L.prism_filter_bytes(ctypes.byref(cfg), ctypes.byref(b)) == 1
-        assert b"modes" in L.prism_last_error() or b"irls_floor" in L.prism_last_error()
+        assert any(k in L.prism_last_error() for k in (b"modes", b"irls_floor", b"sigma_bias"))
     # the floor is not read without the L1 mode
     cfg = P.filter_cfg(g, cam, P.FilterParams(modes=P.MODE_LAPLACE_FACTOR1, irls_floor=0.0))
     assert L.prism_filter_bytes(ctypes.byref(cfg), ctypes.byref(b)) == 0

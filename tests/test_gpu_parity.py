@@ -6,6 +6,8 @@ association) are compared bit for bit; the oracle takes them with the same
 single-precision recipe as the kernels.  Values are compared with the
 tolerances in gpu_util.
 """
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -464,6 +466,94 @@ def test_filter_paper_modes_match_oracle(objective):
         assert eP <= 1e-4, (i, eP)
         nu = of.s.last["n_updated"]
         assert abs(int(s.n_updated) - nu) <= max(10, 1e-4 * nu), i
+
+
+@pytest.mark.parametrize("objective", [0, 1])
+def test_filter_bias_state_matches_oracle(objective):
+    """The 15-D state (pose, velocities, accelerometer bias), fed the
+    accelerometer's body-frame force: 128^3 / 160x120, six frames, every step
+    compared from the same start (the oracle takes the GPU filter's state,
+    bias state and map before each step): pose within 1e-5, velocities and
+    bias within 1e-4, the 15x15 covariance within 1e-4 relative."""
+    n, width, n_frames = 128, 160, 6
+    banner(f"filter 128^3 160x120 objective={objective} 15-D state, one step at a time from the GPU state")
+    c = synth.trajectory_case(seed=2, n=n, width=width, height=width * 3 // 4, n_samples=n // 2, n_frames=n_frames)
+    tr = c["traj"]
+    fp = P().FilterParams(objective=objective, modes=P().MODE_ACCEL_BIAS)
+    f = P().Filter(grid_of(c["scene"]), cam_of(c["cam"]), fp)
+    f.map.init()
+    P0 = np.diag([1e-6] * 6 + [1e-4] * 6 + [1e-4] * 3)
+    f.reset(np.concatenate([tr.t[0], tr.q[0], tr.v[0], tr.w[0], np.zeros(3)]), P0)
+    og, ocm = orc.grid_from_scene(c["scene"]), orc.cam_from(c["cam"])
+    op = orc.Params(objective="p1" if objective else "p2", accel_bias=True, sigma_bias=fp.sigma_bias,
+                    gravity=tuple(fp.gravity))
+    D = t(c["depth"]); C = t(c["rgb"]); U = t(tr.u_body, torch.float64)
+    for i in range(n_frames):
+        s0, x0 = f.state(), f.bias_state()
+        m0, v0 = f.map.to_dense()
+        pose0 = np.concatenate([np.array(s0.pose.t), np.array(s0.pose.q)])
+        of = orc.Filter(og, ocm, op, dict(t=pose0[:3], q=pose0[3:], v=np.array(s0.v), w=np.array(s0.w),
+                                          b=np.array(x0.b)),
+                        np.array(x0.P).reshape(15, 15), m0.cpu().numpy().astype(np.float64),
+                        v0.cpu().numpy().astype(np.float64))
+        if i:
+            of.s.step = i
+            of.s.Sbar = np.array(s0.Sbar).reshape(6, 6) if s0.has_sbar else None
+            of.s.anchor = orc.render(og, of.mean, ocm, pose0, normals=True)
+            of.s.anchor_pose = pose0.copy()
+        f.step(D[i], C[i], U[i - 1] if i else None)
+        of.step(c["depth"][i].astype(np.float64), c["rgb"][i].astype(np.float64), tr.u_body[i - 1] if i else None)
+        s, xb = f.state(), f.bias_state()
+        tg, qg = np.array(s.pose.t), np.array(s.pose.q)
+        Pg = np.array(xb.P).reshape(15, 15)
+        dt_, dr_ = np.linalg.norm(tg - of.s.t), rot_angle(qg, of.s.q)
+        eP = np.linalg.norm(Pg - of.s.P) / np.linalg.norm(of.s.P)
+        db = np.linalg.norm(np.array(xb.b) - of.s.b)
+        print(f"step {i}: |dt| {dt_:.2e} m, dR {dr_:.2e} rad, |db| {db:.2e}, P {eP:.2e}, position error to the "
+              f"truth {np.linalg.norm(tg - tr.t[i]):.4f} m, bias {np.array(xb.b)}", flush=True)
+        assert s.flags == 0
+        assert dt_ <= 1e-5 and dr_ <= 1e-5, (i, dt_, dr_)
+        assert np.linalg.norm(np.concatenate([np.array(s.v), np.array(s.w)]) - np.concatenate([of.s.v, of.s.w])) <= 1e-4
+        assert db <= 1e-4, (i, db)
+        assert eP <= 1e-4, (i, eP)
+        np.testing.assert_array_equal(np.array(s.P).reshape(12, 12), Pg[:12, :12])
+        nu = of.s.last["n_updated"]
+        assert abs(int(s.n_updated) - nu) <= max(10, 1e-4 * nu), i
+
+
+def test_filter_bias_state_entry_points():
+    """The 15-D state's entry points refuse the wrong state size: the 12-D
+    reset and rollouts on a 15-D filter, the 15-D reset and bias read-back on
+    a 12-D one, and a 12-D checkpoint loaded into a 15-D filter."""
+    banner("15-D state entry points")
+    c = synth.trajectory_case(seed=2, n=64, width=80, height=60, n_samples=32, n_frames=2)
+    tr = c["traj"]
+    g, cam = grid_of(c["scene"]), cam_of(c["cam"])
+    f15 = P().Filter(g, cam, P().FilterParams(modes=P().MODE_ACCEL_BIAS))
+    f12 = P().Filter(g, cam, P().FilterParams())
+    x12 = np.concatenate([tr.t[0], tr.q[0], tr.v[0], tr.w[0]])
+    L = P().lib()
+    x = (ctypes.c_double * 13)(*x12)
+    Pm = (ctypes.c_double * 144)(*np.eye(12).ravel())
+    assert L.prism_filter_reset(f15.h, x, Pm, None) == 2
+    x = (ctypes.c_double * 16)(*np.concatenate([x12, np.zeros(3)]))
+    Pm = (ctypes.c_double * 225)(*np.eye(15).ravel())
+    assert L.prism_filter_reset_bias(f12.h, x, Pm, None) == 2
+    out = ctypes.c_void_p()
+    assert L.prism_filter_bias_state_ptr(f12.h, ctypes.byref(out)) == 2
+    assert L.prism_filter_bias_state_ptr(f15.h, ctypes.byref(out)) == 0 and out.value
+    u = torch.zeros(6, dtype=torch.float64, device=DEV)
+    assert L.prism_rollout(f15.h, ctypes.c_void_p(u.data_ptr()), 1, 0, None, None, None, None, None, None, None,
+                           None, None) == 2
+    f12.reset(x12, np.diag([1e-6] * 6 + [1e-4] * 6))
+    f12.map.init()
+    nbytes = ctypes.c_size_t()
+    assert L.prism_filter_save_bytes(ctypes.byref(f12.cfg), ctypes.byref(nbytes)) == 0
+    buf = torch.empty(nbytes.value, dtype=torch.uint8, device=DEV)
+    assert L.prism_filter_save(f12.h, ctypes.c_void_p(buf.data_ptr()), nbytes.value, None) == 0
+    torch.cuda.synchronize()
+    assert L.prism_filter_load(f15.h, ctypes.c_void_p(buf.data_ptr()), nbytes.value, None) == 1
+    assert b"state" in L.prism_last_error()
 
 
 @pytest.mark.parametrize("mode", ["dt2", "factor1", "irls"])

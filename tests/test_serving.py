@@ -247,12 +247,19 @@ def test_step_batch_matches_single_steps(graphs):
     banner(f"prism_filter_step_batch vs single steps (mixed batch, graphs={graphs})")
     Pm = P()
     specs, frames = _specs(n_streams=4, n_frames=6)
-    all_modes = Pm.MODE_TRANSITION_DT2 | Pm.MODE_LAPLACE_FACTOR1 | Pm.MODE_IRLS_L1
+    all_modes = Pm.MODE_TRANSITION_DT2 | Pm.MODE_LAPLACE_FACTOR1 | Pm.MODE_IRLS_L1 | Pm.MODE_ACCEL_BIAS
     kinds = [(Pm.PRISM_F32, 3, Pm.OBJ_P2, 0), (Pm.PRISM_BF16, 2, Pm.OBJ_P1, Pm.MODE_IRLS_L1),
-             (Pm.PRISM_BF16, 3, Pm.OBJ_P2, all_modes), (Pm.PRISM_F32, 1, Pm.OBJ_P1, 0)]
+             (Pm.PRISM_BF16, 3, Pm.OBJ_P2, all_modes), (Pm.PRISM_F32, 1, Pm.OBJ_P1, Pm.MODE_ACCEL_BIAS)]
     for sp, (dt, ngn, obj, modes) in zip(specs, kinds):
         sp.grid = Pm.Grid.make(sp.grid.n, sp.grid.voxel, tuple(sp.grid.origin), dtype=dt)
         sp.params = dataclasses.replace(sp.params, n_gn=ngn, objective=obj, modes=modes)
+    # the 15-D members take the accelerometer's body-frame force and a 15-D belief
+    streams = synth.serving_streams(4, 6, sizes=((80, 60), (160, 120)), grids=(64, 128))
+    for i in (2, 3):
+        D_, C_, _, arr = frames[i]
+        frames[i] = (D_, C_, torch.tensor(streams[i]["traj"].u_body, dtype=torch.float64, device="cuda"), arr)
+        specs[i].x0 = np.concatenate([specs[i].x0, np.zeros(3)])
+        specs[i].P0 = np.diag([1e-6] * 6 + [1e-4] * 6 + [1e-4] * 3)
     join = {0: 0, 1: 0, 2: 0, 3: 2}        # frame index at which each filter starts
     s = torch.cuda.Stream()
     ref, bat = [], []
@@ -283,8 +290,10 @@ def test_step_batch_matches_single_steps(graphs):
             torch.cuda.synchronize()          # both slots are reused across iterations
     torch.cuda.synchronize()
     assert Pm.filters_poll(bat) == [6, 6, 6, 4]
-    for fa, fb in zip(ref, bat):
+    for i, (fa, fb) in enumerate(zip(ref, bat)):
         assert bytes(fa.state()) == bytes(fb.state())
+        if i in (2, 3):
+            assert bytes(fa.bias_state()) == bytes(fb.bias_state())
         ma, va = fa.map.to_dense()
         mb, vb = fb.map.to_dense()
         assert torch.equal(ma, mb) and torch.equal(va, vb)
