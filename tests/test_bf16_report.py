@@ -22,8 +22,13 @@ closed-loop drift mixed in:
 * anchor depth and colour rendered from the updated map: reported as
   quantiles; bounded loosely (BF16 moves the occupancy zero crossing).
 
-The report is written to $PRISM_REPORT_DIR (default: gpurun_out/ at the
-repository root, the folder GPU runs bring back) as bf16_error_report.json."""
+Run twice: with the paper's 12-D state, and with the 15-D state that adds an
+accelerometer bias (fed the accelerometer's body-frame force; the 15x15
+covariance and the bias are compared too, the bias within 1e-4).
+
+The reports are written to $PRISM_REPORT_DIR (default: gpurun_out/ at the
+repository root, the folder GPU runs bring back) as bf16_error_report.json
+and bf16_error_report_15d.json."""
 import json
 import os
 
@@ -42,27 +47,32 @@ def _q(x, qs=(50, 99, 100)):
 
 
 @pytest.mark.gpu
-def test_bf16_per_output_error_vs_fp64_oracle():
+@pytest.mark.parametrize("state_dim", [12, 15])
+def test_bf16_per_output_error_vs_fp64_oracle(state_dim):
     import torch
     from gpu_util import banner, P, rot_angle
     Pm = P()
-    banner("BF16 384^3 640x480 K=192, 200 frames: per-output error vs FP64 oracle")
+    bias = state_dim == 15
+    banner(f"BF16 384^3 640x480 K=192, 200 frames, {state_dim}-D state: per-output error vs FP64 oracle")
     n, W, H, K, nf = 384, 640, 480, 192, 200
     case = synth.trajectory_case(seed=4, n=n, width=W, height=H, n_samples=K, n_frames=nf, frames=False)
     sc, cm, tr = case["scene"], case["cam"], case["traj"]
     D, C = synth.raycast_torch(sc, cm, tr.t, tr.q, 4, 0.01, 0.02)
-    U = torch.tensor(tr.u, dtype=torch.float64, device="cuda")
+    U = torch.tensor(tr.u_body if bias else tr.u, dtype=torch.float64, device="cuda")
     grid = Pm.Grid.make(n, sc.voxel, tuple(float(v) for v in sc.origin), dtype=Pm.PRISM_BF16)
     cam = Pm.Camera.make(cm.width, cm.height, cm.fx, cm.fy, cm.cx, cm.cy, cm.d_near, cm.d_far, cm.n_samples)
-    params = Pm.FilterParams(n_gn=3, objective=Pm.OBJ_P2)
-    op = orc.Params(n_gn=3, objective="p2")
+    params = Pm.FilterParams(n_gn=3, objective=Pm.OBJ_P2, modes=Pm.MODE_ACCEL_BIAS if bias else 0)
+    op = orc.Params(n_gn=3, objective="p2", accel_bias=bias, sigma_bias=params.sigma_bias,
+                    gravity=tuple(params.gravity))
     og, oc = orc.grid_from_scene(sc), orc.cam_from(cm)
     torch.cuda.synchronize()
     f = Pm.Filter(grid, cam, params)
     f.map.init()
-    P0 = np.diag([1e-6] * 6 + [1e-4] * 6)
-    f.reset(np.concatenate([tr.t[0], tr.q[0], tr.v[0], tr.w[0]]), P0)
-    report = {"workload": "384^3 BF16 map, 640x480, K=192, P2 x 3 GN, 200 frames", "frames": []}
+    P0 = np.diag([1e-6] * 6 + [1e-4] * 6 + ([1e-4] * 3 if bias else []))
+    f.reset(np.concatenate([tr.t[0], tr.q[0], tr.v[0], tr.w[0]] + ([np.zeros(3)] if bias else [])), P0)
+    report = {"workload": f"384^3 BF16 map, 640x480, K=192, P2 x 3 GN, 200 frames, {state_dim}-D state"
+                          + (" (accelerometer bias; body-frame force as the linear control)" if bias else ""),
+              "frames": []}
     rel_bound = 2.0 ** -8 + 2.0 ** -22      # round to 8 significant bits, after the FP32 rounding
     for k in range(nf):
         u = None if k == 0 else U[k - 1]
@@ -78,8 +88,13 @@ def test_bf16_per_output_error_vs_fp64_oracle():
         del mean, var
         # oracle state filter from the GPU's state (its map is not used by the P2 objective)
         x0 = dict(t=np.array(st.pose.t), q=np.array(st.pose.q), v=np.array(st.v), w=np.array(st.w))
+        Pst = np.array(st.P).reshape(12, 12)
+        if bias:
+            xb = f.bias_state()
+            x0["b"] = np.array(xb.b)
+            Pst = np.array(xb.P).reshape(15, 15)
         dummy = np.zeros((4, 1, 1, 1))
-        of = orc.Filter(og, oc, op, x0, np.array(st.P).reshape(12, 12), dummy, dummy)
+        of = orc.Filter(og, oc, op, x0, Pst, dummy, dummy)
         of._observe_and_anchor = lambda pose, depth, rgb: None
         of.s.step = int(st.step)
         if st.has_sbar:
@@ -96,14 +111,17 @@ def test_bf16_per_output_error_vs_fp64_oracle():
         assert sg.flags == 0
         e_t = float(np.linalg.norm(np.array(sg.pose.t) - of.s.t))
         e_r = rot_angle(np.array(sg.pose.q), of.s.q)
-        Pg = np.array(sg.P).reshape(12, 12)
+        Pg = np.array(f.bias_state().P).reshape(15, 15) if bias else np.array(sg.P).reshape(12, 12)
         e_P = float(np.linalg.norm(Pg - of.s.P) / np.linalg.norm(of.s.P))
+        e_b = float(np.linalg.norm(np.array(f.bias_state().b) - of.s.b)) if bias else 0.0
         # oracle map filter and anchor with float64 storage, at the GPU's posterior mean
         pose_g = np.concatenate([np.array(sg.pose.t), np.array(sg.pose.q)])
         orc.map_update(og, mean64, var64, oc, pose_g, d64, c64, op)
         ao = orc.render(og, mean64, oc, pose_g, normals=True, normal_disc=op.normal_disc)
         mg, vg = f.map.to_dense()
         row = {"frame": k, "pose_t_m": e_t, "pose_r_rad": e_r, "cov_rel_fro": e_P}
+        if bias:
+            row["bias_m_s2"] = e_b
         for name, g, o in (("map_mean", mg, mean64), ("map_var", vg, var64)):
             g = g.cpu().numpy().astype(np.float64)
             diff = np.abs(g - o)
@@ -129,10 +147,11 @@ def test_bf16_per_output_error_vs_fp64_oracle():
         print(json.dumps(row), flush=True)
         assert e_t <= 1e-5 and e_r <= 1e-5, row
         assert e_P <= 1e-4, row
+        assert e_b <= 1e-4, row
         assert row["anchor_valid_mismatch_frac"] <= 0.01 and row["anchor_depth_rel"]["p50"] <= 1e-3, row
         del of, ao, ag, mean64, var64
     out_dir = os.environ.get("PRISM_REPORT_DIR") or os.path.join(
         os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
     os.makedirs(out_dir, exist_ok=True)
-    with open(os.path.join(out_dir, "bf16_error_report.json"), "w") as fh:
+    with open(os.path.join(out_dir, "bf16_error_report_15d.json" if bias else "bf16_error_report.json"), "w") as fh:
         json.dump(report, fh, indent=1)

@@ -34,28 +34,34 @@ def _filter(c, dtype=0, capacity=0, **kw):
     f = P().Filter(g, cam_of(c["cam"]), P().FilterParams(**kw))
     f.map.init()
     tr = c["traj"]
-    f.reset(np.concatenate([tr.t[0], tr.q[0], tr.v[0], tr.w[0]]), np.diag([1e-6] * 6 + [1e-4] * 6))
+    if kw.get("modes", 0) & P().MODE_ACCEL_BIAS:
+        f.reset(np.concatenate([tr.t[0], tr.q[0], tr.v[0], tr.w[0], np.zeros(3)]),
+                np.diag([1e-6] * 6 + [1e-4] * 6 + [1e-4] * 3))
+    else:
+        f.reset(np.concatenate([tr.t[0], tr.q[0], tr.v[0], tr.w[0]]), np.diag([1e-6] * 6 + [1e-4] * 6))
     return f
 
 
-def _frames(c):
-    return t(c["depth"]), t(c["rgb"]), t(c["traj"].u, torch.float64)
+def _frames(c, body=False):
+    return t(c["depth"]), t(c["rgb"]), t(c["traj"].u_body if body else c["traj"].u, torch.float64)
 
 
 def _snapshot(f):
     m, v = f.map.to_dense()
     a = f.anchor()
     torch.cuda.synchronize()
-    return (bytes(f.state()), m.cpu().numpy().tobytes(), v.cpu().numpy().tobytes(),
+    bias = bytes(f.bias_state()) if f.params.modes & P().MODE_ACCEL_BIAS else b""
+    return (bytes(f.state()), bias, m.cpu().numpy().tobytes(), v.cpu().numpy().tobytes(),
             a["depth"].cpu().numpy().tobytes(), a["normals"].cpu().numpy().tobytes())
 
 
-@pytest.mark.parametrize("kind", ["fp32", "bf16_pool"])
+@pytest.mark.parametrize("kind", ["fp32", "bf16_pool", "fp32_15d"])
 def test_checkpoint_continues_bit_for_bit(traj, kind):
     banner(f"checkpoint round trip, {kind}")
     c = traj
-    kw = dict(dtype=0) if kind == "fp32" else dict(dtype=1, capacity=(c["scene"].n // 8) ** 3 // 2)
-    D, C, U = _frames(c)
+    kw = {"fp32": dict(dtype=0), "bf16_pool": dict(dtype=1, capacity=(c["scene"].n // 8) ** 3 // 2),
+          "fp32_15d": dict(dtype=0, modes=P().MODE_ACCEL_BIAS)}[kind]
+    D, C, U = _frames(c, body=kind == "fp32_15d")
     a = _filter(c, **kw)
     for i in range(4):
         a.step(D[i], C[i], U[i - 1] if i else None)
