@@ -496,23 +496,29 @@ def single_frame_gpu(P, torch, reps=200):
                         "full filter step replayed from a HIP graph", "us_per_step": round(us, 2)}
 
 
-def bf16_stream_gpu(P, torch, W=5, K=40):
+def bf16_stream_gpu(P, torch, W=5, K=40, bias=False):
     """The mixed-precision workload on one stream: 384^3 BF16 map (1.67 cm),
-    640x480, K = 192, P2 with 3 Gauss-Newton iterations, plain path."""
+    640x480, K = 192, P2 with 3 Gauss-Newton iterations, plain path; with
+    bias=True the 15-D state (accelerometer bias, 15x15 covariance) fed the
+    accelerometer's body-frame force."""
     import synth
     from paper_2212_02988_amd.serving import StreamSpec
     n_fr = 1 + W + K
     case = synth.trajectory_case(seed=4, n=384, width=640, height=480, n_samples=192, n_frames=n_fr, frames=False)
     tr, scene, cm = case["traj"], case["scene"], case["cam"]
     D, C = synth.raycast_torch(scene, cm, tr.t, tr.q, 4, 0.01, 0.02)
-    U = torch.from_numpy(np.concatenate([tr.u, tr.u[-1:]], 0)).to("cuda")
+    u = tr.u_body if bias else tr.u
+    U = torch.from_numpy(np.concatenate([u, u[-1:]], 0)).to("cuda")
     grid = P.Grid.make(384, scene.voxel, tuple(float(v) for v in scene.origin), dtype=P.PRISM_BF16)
     cam = P.Camera.make(cm.width, cm.height, cm.fx, cm.fy, cm.cx, cm.cy, cm.d_near, cm.d_far, cm.n_samples)
-    spec = StreamSpec(0, grid, cam, P.FilterParams(n_gn=3, objective=P.OBJ_P2),
-                      np.concatenate([tr.t[0], tr.q[0], tr.v[0], tr.w[0]]), np.diag([1e-6] * 6 + [1e-4] * 6), n_fr)
+    x0 = [tr.t[0], tr.q[0], tr.v[0], tr.w[0]] + ([np.zeros(3)] if bias else [])
+    P0 = np.diag([1e-6] * 6 + [1e-4] * 6 + ([1e-4] * 3 if bias else []))
+    spec = StreamSpec(0, grid, cam, P.FilterParams(n_gn=3, objective=P.OBJ_P2, modes=P.MODE_ACCEL_BIAS if bias else 0),
+                      np.concatenate(x0), P0, n_fr)
     ms, per = stream_steps(spec, dict(D=D, C=C, U=U), W, K, P, torch)
-    log(f"384^3 BF16 640x480 stream: {ms:.3f} ms per step")
-    return {"workload": "384^3 BF16 (1.67 cm), 640x480, K = 192, P2 x 3 GN, one stream, plain path",
+    state = "15-D state (accelerometer bias, 15x15 covariance)" if bias else "12-D state"
+    log(f"384^3 BF16 640x480 stream, {state}: {ms:.3f} ms per step")
+    return {"workload": f"384^3 BF16 (1.67 cm), 640x480, K = 192, P2 x 3 GN, one stream, plain path, {state}",
             "ms_per_step": round(ms, 4), "steps_per_s": round(1e3 / ms, 1),
             "p50_ms": round(float(np.percentile(per, 50)), 4), "p99_ms": round(float(np.percentile(per, 99)), 4)}
 
@@ -1013,6 +1019,7 @@ def main():
         extra["roofline_map_update_cold"] = map_update_cold(P, torch)
         extra["single_frame_workload"] = single_frame_gpu(P, torch)
         extra["bf16_384_stream"] = bf16_stream_gpu(P, torch)
+        extra["bf16_384_stream_15d"] = bf16_stream_gpu(P, torch, bias=True)
         extra["mapping_gd_vs_closed_form"] = mapping_comparison(P, torch)
         extra["pose_optimisers"] = pose_optimisers(P, torch)
         extra["large_room_pool"] = large_room_pool(P, torch)
