@@ -641,6 +641,51 @@ def test_filter_step_with_improper_covariance():
         assert abs(int(s.n_updated) - nu_o) <= 10
 
 
+def test_filter_bias_state_degenerate_steps():
+    """The 15-D state's degenerate steps against the oracle: an improper
+    covariance (the pose block of -I predicts no proper prior) keeps the
+    predicted mean, bias and 15x15 covariance; a frame without valid depth is
+    pure prediction followed by the combination."""
+    banner("15-D state degenerate steps")
+    c = synth.trajectory_case(seed=4, n=64, width=80, height=60, n_samples=32, n_frames=3)
+    tr = c["traj"]
+    for case, P0, frames in (("improper", -np.eye(15), {}),
+                             ("no depth", np.diag([1e-6] * 6 + [1e-4] * 6 + [1e-4] * 3),
+                              {1: (np.zeros_like(c["depth"][1]), c["rgb"][1])})):
+        f = P().Filter(grid_of(c["scene"], 0), cam_of(c["cam"]), P().FilterParams(modes=P().MODE_ACCEL_BIAS))
+        f.map.init()
+        b0 = np.array([0.02, -0.01, 0.03])
+        f.reset(np.concatenate([tr.t[0], tr.q[0], tr.v[0], tr.w[0], b0]), P0)
+        mean = np.zeros((4, 64, 64, 64)); mean[0] = np.float32(-0.001)
+        of = orc.Filter(orc.grid_from_scene(c["scene"]), orc.cam_from(c["cam"]),
+                        orc.Params(objective="p2", accel_bias=True, sigma_bias=0.001),
+                        dict(t=tr.t[0], q=tr.q[0], v=tr.v[0], w=tr.w[0], b=b0), P0, mean, np.full_like(mean, 1e4))
+        for i in range(3):
+            d, rgb = frames.get(i, (c["depth"][i], c["rgb"][i]))
+            u = tr.u_body[i - 1] if i else None
+            f.step(t(d), t(rgb), t(u, torch.float64) if i else None)
+            of.step(d.astype(np.float64), rgb.astype(np.float64), u)
+            if i == 0:
+                continue
+            s, xb = f.state(), f.bias_state()
+            Pg = np.array(xb.P).reshape(15, 15)
+            print(f"[{case}] step {i}: flags {s.flags}, |db| {np.linalg.norm(np.array(xb.b) - of.s.b):.1e}, "
+                  f"P {np.linalg.norm(Pg - of.s.P) / np.linalg.norm(of.s.P):.1e}", flush=True)
+            if case == "improper":
+                assert s.flags & P().FLAG_CHOL_FALLBACK and s.flags & P().FLAG_PRIOR_NOT_PD
+                np.testing.assert_array_equal(np.array(xb.b), b0)
+            elif i == 1:
+                assert s.flags & P().FLAG_NO_VALID_PIXELS and not s.flags & P().FLAG_CHOL_FALLBACK
+            # a degenerate step is prediction (and combination) only: FP64 on
+            # both sides; the tracked step after the frame without depth has
+            # the bar of any filter step
+            tol = 1e-9 if case == "improper" or i == 1 else 1e-5
+            assert np.linalg.norm(np.array(s.pose.t) - of.s.t) <= tol
+            assert rot_angle(np.array(s.pose.q), of.s.q) <= tol
+            assert np.linalg.norm(np.array(xb.b) - of.s.b) <= tol
+            assert np.linalg.norm(Pg - of.s.P) <= (1e-9 if tol == 1e-9 else 1e-4) * np.linalg.norm(of.s.P)
+
+
 # ---------------------------------------------------------------------------
 # map inference by gradient descent through the renderer
 # ---------------------------------------------------------------------------
