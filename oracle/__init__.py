@@ -702,37 +702,55 @@ def transition_sample(x: Dict[str, np.ndarray], u: np.ndarray, n: np.ndarray, dt
     return dict(t=t, q=rot_to_quat(R), v=v, w=w)
 
 
+def transition_sample_bias(x: Dict[str, np.ndarray], u: np.ndarray, n: np.ndarray, dt: float, g,
+                           dt2: bool = False) -> Dict[str, np.ndarray]:
+    """One draw of the 15-D transition: the acceleration R (f - b) + g from the
+    draw's own rotation and bias, then transition_sample with the first 12
+    noise components; the bias walks by n_b = n[12:15]."""
+    R = quat_to_rot(x["q"])
+    a = R @ (u[:3] - x["b"]) + np.asarray(g, float)
+    xn = transition_sample(x, np.concatenate([a, u[3:]]), n[:12], dt, dt2)
+    xn["b"] = x["b"] + n[12:15]
+    return xn
+
+
 def rollout(grid: Grid, mean: np.ndarray, cam: Cam, x: Dict[str, np.ndarray], P: np.ndarray, u: np.ndarray,
             noise: np.ndarray, params: Params, decide32: bool = True, frames: bool = True):
     """Predictive rollout (App. J): from the belief N(x, P) and the map means,
     under controls u [k][6]: for each sample s the start state x (+) L z[s,0]
-    (P = L L^T; tangent order t, theta, v, w) and k draws of the transition
-    with noise sqrt(diag Q) z[s,j+1]; the closed-form predicted moments after
-    each control; the frames rendered at every sampled pose.  12-D state
-    only."""
-    if params.accel_bias:
-        raise NotImplementedError("rollouts are defined for the 12-D state")
+    (P = L L^T; tangent order t, theta, v, w, and b for the 15-D state) and k
+    draws of the transition with noise sqrt(diag Q) z[s,j+1]; the closed-form
+    predicted moments after each control (means t, q, v, w and b); the frames
+    rendered at every sampled pose."""
     k = len(u)
+    nd = 15 if params.accel_bias else 12
     sig = np.sqrt([params.sigma_pose_t ** 2] * 3 + [params.sigma_pose_r ** 2] * 3 +
-                  [params.sigma_vel_t ** 2] * 3 + [params.sigma_vel_r ** 2] * 3)
+                  [params.sigma_vel_t ** 2] * 3 + [params.sigma_vel_r ** 2] * 3 +
+                  ([params.sigma_bias ** 2] * 3 if params.accel_bias else []))
     try:
         L = np.linalg.cholesky(P)
         ok = True
     except np.linalg.LinAlgError:
-        L, ok = np.zeros((12, 12)), False
+        L, ok = np.zeros((nd, nd)), False
     poses = np.zeros((len(noise), k, 7))
     for s in range(len(noise)):
         e = L @ noise[s, 0]
         p0 = retract(np.concatenate([x["t"], x["q"]]), e[:6])
         xs = dict(t=p0[:3], q=p0[3:], v=x["v"] + e[6:9], w=x["w"] + e[9:12])
+        if params.accel_bias:
+            xs["b"] = x["b"] + e[12:15]
         for j in range(k):
-            xs = transition_sample(xs, u[j], sig * noise[s, j + 1], params.dt, params.transition_dt2)
+            if params.accel_bias:
+                xs = transition_sample_bias(xs, u[j], sig * noise[s, j + 1], params.dt, params.gravity,
+                                            params.transition_dt2)
+            else:
+                xs = transition_sample(xs, u[j], sig * noise[s, j + 1], params.dt, params.transition_dt2)
             poses[s, j] = np.concatenate([xs["t"], xs["q"]])
-    means, covs = np.zeros((k, 13)), np.zeros((k, 12, 12))
+    means, covs = np.zeros((k, nd + 1)), np.zeros((k, nd, nd))
     xm, Pm = dict(x), P
     for j in range(k):
         xm, Pm = predict(xm, Pm, u[j], params)
-        means[j] = np.concatenate([xm["t"], xm["q"], xm["v"], xm["w"]])
+        means[j] = np.concatenate([xm["t"], xm["q"], xm["v"], xm["w"]] + ([xm["b"]] if params.accel_bias else []))
         covs[j] = Pm
     out = dict(poses=poses, mean=means, cov=covs, ok=ok)
     if frames:

@@ -182,3 +182,46 @@ def test_bias_filter_follows_the_trajectory(orc):
         of.step(c["depth"][i].astype(np.float64), c["rgb"][i].astype(np.float64), tr.u_body[i - 1] if i else None)
         assert of.s.P.shape == (15, 15) and of.s.b.shape == (3,)
     assert np.linalg.norm(of.s.t - tr.t[5]) < 0.05
+
+
+def _rollout_belief15(rng):
+    x = dict(t=np.array([1.0, 2.0, 1.5]), q=np.array([0.9, 0.1, -0.2, 0.3]) / np.linalg.norm([0.9, 0.1, -0.2, 0.3]),
+             v=np.array([0.3, -0.1, 0.05]), w=np.array([0.2, 0.4, -0.3]), b=np.array([0.02, -0.03, 0.01]))
+    A = rng.normal(size=(15, 15)) * 0.01
+    P = A @ A.T + np.diag([1e-5] * 6 + [1e-4] * 6 + [1e-5] * 3)
+    u = rng.normal(size=(5, 6)) + np.array([0.0, 0.0, 9.81, 0.0, 0.0, 0.0])
+    return x, P, u
+
+
+def test_bias_rollout_without_noise_follows_the_predicted_mean(orc):
+    """Zero draws from the 15-D belief: every sampled trajectory is the
+    noise-free transition of the mean, i.e. the closed-form predicted means
+    (the bias stays at its mean)."""
+    rng = np.random.default_rng(46)
+    x, P, u = _rollout_belief15(rng)
+    p = orc.Params(accel_bias=True, gravity=tuple(G))
+    out = orc.rollout(None, None, None, x, P, u, np.zeros((2, 6, 15)), p, frames=False)
+    assert out["mean"].shape == (5, 16) and out["cov"].shape == (5, 15, 15)
+    for s in range(2):
+        np.testing.assert_allclose(out["poses"][s, :, :3], out["mean"][:, :3], rtol=0, atol=1e-12)
+        for j in range(5):
+            assert np.linalg.norm(orc.pose_error(out["poses"][s, j], out["mean"][j, :7])) < 1e-12
+    np.testing.assert_allclose(out["mean"][:, 13:16], np.tile(x["b"], (5, 1)), rtol=0, atol=0)
+
+
+def test_bias_rollout_samples_match_the_linearised_moments(orc):
+    """Monte Carlo over the 15-D generative transition (bias walk included):
+    the sampled poses' mean and covariance agree with the closed-form
+    linearised prediction within sampling error."""
+    rng = np.random.default_rng(47)
+    x, P, u = _rollout_belief15(rng)
+    p = orc.Params(accel_bias=True, gravity=tuple(G), sigma_bias=0.01)
+    S = 3000
+    out = orc.rollout(None, None, None, x, P, u, rng.normal(size=(S, 6, 15)), p, frames=False)
+    for j in (0, 4):
+        e = np.array([orc.pose_error(out["poses"][s, j], out["mean"][j, :7]) for s in range(S)])
+        C = out["cov"][j][:6, :6]
+        sd = np.sqrt(np.diag(C))
+        assert np.all(np.abs(e.mean(0)) < 4 * sd / np.sqrt(S) + 1e-3 * sd)
+        Ce = np.cov(e.T)
+        assert np.linalg.norm(Ce - C) < 0.1 * np.linalg.norm(C), (j, np.linalg.norm(Ce - C) / np.linalg.norm(C))
