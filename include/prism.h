@@ -423,7 +423,8 @@ prism_status prism_map_gd(const prism_grid *grid, void *map, const prism_camera 
  *       The bias, the full covariance and the conditional are in the filter's
  *       prism_filter_bias_state (prism_filter_bias_state_ptr); the state's
  *       P holds the leading 12x12 block.  Set the belief with
- *       prism_filter_reset_bias.  prism_rollout returns PRISM_UNSUPPORTED. */
+ *       prism_filter_reset_bias.  prism_rollout draws and predicts the 15-D
+ *       state (its noise rows and moments are 15-D). */
 #define PRISM_MODE_TRANSITION_DT2 1
 #define PRISM_MODE_LAPLACE_FACTOR1 2
 #define PRISM_MODE_IRLS_L1 4
@@ -586,9 +587,14 @@ prism_status prism_filter_step_adam(prism_filter *f, const prism_frame *frame,
  *        v' = v + u_v dt + n_v, w' = w + u_w dt + n_w, t' = t + v' dt + n_t,
  *        (u dt^2 in place of u dt under PRISM_MODE_TRANSITION_DT2),
  *        R' = Exp(n_theta) Exp(w' dt) R.
+ *        PRISM_MODE_ACCEL_BIAS filters: rows of 15 draws (the bias last;
+ *        start state b + L z, process noise n_b walking the bias), u_v is
+ *        the body-frame specific force and the acceleration R (u_v - b) + g
+ *        uses the draw's own rotation and bias.
  * poses: device [n_samples][k] (required when n_samples > 0).
  * mean:  nullable device [k][13] (t, q, v, w); cov: nullable [k][144]: the
- *        linearised prediction (App. E.2) after each control.
+ *        linearised prediction (App. E.2) after each control.  With
+ *        PRISM_MODE_ACCEL_BIAS: mean [k][16] (t, q, v, w, b), cov [k][225].
  * depth/rgb/mask: nullable together, [n_samples*k][H][W] (rgb [..][3]), as
  *        prism_render at poses (sample-major); needs n_samples*k <= 65535.
  * flags: nullable device int32: PRISM_FLAG_CHOL_FALLBACK when P is not

@@ -1103,7 +1103,6 @@ prism_status prism_rollout(prism_filter* f, const double* u, int32_t k, int32_t 
                            prism_pose* poses, double* mean, double* cov, float* depth, float* rgb, uint8_t* mask,
                            int32_t* flags, hipStream_t stream) {
     REQUIRE(f, "filter is NULL");
-    if (f->X) return fail(PRISM_UNSUPPORTED, "rollouts are defined for the 12-D state");
     REQUIRE(k >= 1 && k <= 4096, "k must be in [1, 4096]");
     REQUIRE(n_samples >= 0 && n_samples <= 65535, "n_samples must be in [0, 65535]");
     REQUIRE(u && aligned(u, 8), "controls u must be non-NULL and 8-byte aligned");
@@ -1116,7 +1115,7 @@ prism_status prism_rollout(prism_filter* f, const double* u, int32_t k, int32_t 
             "depth, rgb and mask go together (4-byte aligned)");
     REQUIRE(!frames || (n_samples >= 1 && (long long)n_samples * k <= 65535),
             "rendering needs 1 <= n_samples * k <= 65535");
-    HIP_TRY(launch_rollout(f->S, u, k, n_samples, noise, f->tc, poses, mean, cov, flags, stream));
+    HIP_TRY(launch_rollout(f->S, f->X, u, k, n_samples, noise, f->tc, poses, mean, cov, flags, stream));
     if (frames)
         HIP_TRY(launch_render(f->g, f->c, f->gd, f->cd, f->cfg.grid.dtype, f->map,
                               skip_table(&f->cfg.grid, &f->cfg.cam, f->map), poses, n_samples * k, depth, rgb, mask,

@@ -176,8 +176,10 @@ hipError_t launch_pose_adam(prism_filter_state* S, const CamC& c, const CamD& cd
                             const AdamC& ad, hipStream_t st);
 
 // predictive rollouts: sampled trajectories (n_samples x k poses) and the
-// closed-form predicted moments (nullable mean [k][13], cov [k][144])
-hipError_t launch_rollout(const prism_filter_state* S, const double* u, int k, int n_samples, const double* noise,
+// closed-form predicted moments (nullable mean [k][13], cov [k][144]; for the
+// 15-D state, X non-NULL, mean [k][16] and cov [k][225])
+hipError_t launch_rollout(const prism_filter_state* S, const prism_filter_bias_state* X, const double* u, int k,
+                          int n_samples, const double* noise,
                           const TransC& tc, prism_pose* poses, double* mean, double* cov, int32_t* flags,
                           hipStream_t st);
 hipError_t launch_predict(prism_filter_state* S, prism_filter_bias_state* X, const double* u, const TransC& tc,

@@ -716,44 +716,63 @@ __global__ __launch_bounds__(64) void k_first_frame_batch(BatchArgs b) { first_f
 // with process noise n = sqrt(Q) z_j for each of the k controls:
 //   v' = v + u_v du + n_v,  w' = w + u_w du + n_w,
 //   t' = t + v' dt + n_t,   R' = Exp(n_theta) Exp(w' dt) R
-// (du = dt, or dt^2 in the printed form).  If P is not positive definite every sample starts at the mean and *flags
-// gets PRISM_FLAG_CHOL_FALLBACK (else 0; written by the first workgroup).
+// (du = dt, or dt^2 in the printed form).  The 15-D state (X non-NULL)
+// draws 15 components per row (the bias last), takes the acceleration
+// R (u_v - b) + g with the draw's rotation and bias, and walks the bias by
+// n_b.  If P is not positive definite every sample starts at the mean and
+// *flags gets PRISM_FLAG_CHOL_FALLBACK (else 0; written by the first
+// workgroup).
 __global__ __launch_bounds__(64) void k_rollout_sample(const prism_filter_state* __restrict__ S,
+                                                       const prism_filter_bias_state* __restrict__ X,
                                                        const double* __restrict__ u, int k,
                                                        const double* __restrict__ noise, TransC tc,
                                                        prism_pose* __restrict__ poses, int32_t* __restrict__ flags) {
-    __shared__ double A[144];
+    __shared__ double A[225];
     __shared__ int ok;
-    for (int e = threadIdx.x; e < 144; e += blockDim.x) A[e] = S->P[e];
+    const int N = X ? 15 : 12;
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) A[e] = X ? X->P[e] : S->P[e];
     __syncthreads();
-    if (threadIdx.x == 0) ok = chol<12>(A);
+    if (threadIdx.x == 0) ok = X ? chol<15>(A) : chol<12>(A);
     __syncthreads();
     if (threadIdx.x != 0) return;
     if (blockIdx.x == 0 && flags) *flags = ok ? 0 : PRISM_FLAG_CHOL_FALLBACK;
-    const double* z = noise + (long long)blockIdx.x * (k + 1) * 12;
-    double e[12];
-    for (int i = 0; i < 12; ++i) {
+    const double* z = noise + (long long)blockIdx.x * (k + 1) * N;
+    double e[15];
+    for (int i = 0; i < N; ++i) {
         double acc = 0.0;
         if (ok)
-            for (int j = 0; j <= i; ++j) acc += A[i * 12 + j] * z[j];
+            for (int j = 0; j <= i; ++j) acc += A[i * N + j] * z[j];
         e[i] = acc;
     }
     prism_pose x = S->pose;
     retract(x, e);
-    double v[3], w[3], sq[12];
+    double v[3], w[3], b[3], sq[15];
     for (int i = 0; i < 3; ++i) {
         v[i] = S->v[i] + e[6 + i];
         w[i] = S->w[i] + e[9 + i];
+        b[i] = X ? X->b[i] + e[12 + i] : 0.0;
     }
-    for (int i = 0; i < 12; ++i) sq[i] = sqrt(tc.q[i]);
+    for (int i = 0; i < N; ++i) sq[i] = sqrt(tc.q[i]);
     for (int j = 0; j < k; ++j) {
-        const double* zj = z + (j + 1) * 12;
+        const double* zj = z + (j + 1) * N;
         const double* uj = u + 6 * j;
-        double n[12];
-        for (int i = 0; i < 12; ++i) n[i] = sq[i] * zj[i];
-        for (int i = 0; i < 3; ++i) {
-            v[i] = v[i] + uj[i] * tc.du + n[6 + i];
-            w[i] = w[i] + uj[3 + i] * tc.du + n[9 + i];
+        double n[15];
+        for (int i = 0; i < N; ++i) n[i] = sq[i] * zj[i];
+        if (X) {
+            double R[9];
+            quat_to_R9(x.q, R);
+            const double f[3] = {uj[0] - b[0], uj[1] - b[1], uj[2] - b[2]};
+            for (int i = 0; i < 3; ++i) {
+                const double a = R[i * 3] * f[0] + R[i * 3 + 1] * f[1] + R[i * 3 + 2] * f[2] + tc.g[i];
+                v[i] = v[i] + a * tc.du + n[6 + i];
+                w[i] = w[i] + uj[3 + i] * tc.du + n[9 + i];
+            }
+            for (int i = 0; i < 3; ++i) b[i] += n[12 + i];
+        } else {
+            for (int i = 0; i < 3; ++i) {
+                v[i] = v[i] + uj[i] * tc.du + n[6 + i];
+                w[i] = w[i] + uj[3 + i] * tc.du + n[9 + i];
+            }
         }
         double phi[3] = {w[0] * tc.dt, w[1] * tc.dt, w[2] * tc.dt};
         double E1[9], E2[9], R[9], T[9], R2[9];
@@ -812,16 +831,66 @@ __global__ __launch_bounds__(256) void k_rollout_moments(const prism_filter_stat
     }
 }
 
-hipError_t launch_rollout(const prism_filter_state* S, const double* u, int k, int n_samples, const double* noise,
-                          const TransC& tc, prism_pose* poses, double* mean, double* cov, int32_t* flags,
-                          hipStream_t st) {
+// The same for the 15-D state: mean[j] = (t, q, v, w, b) (16 doubles),
+// cov[j] its 15x15 covariance.
+__global__ __launch_bounds__(256) void k_rollout_moments_bias(const prism_filter_state* __restrict__ S,
+                                                              const prism_filter_bias_state* __restrict__ X,
+                                                              const double* __restrict__ u, int k, TransC tc,
+                                                              double* __restrict__ mean, double* __restrict__ cov) {
+    constexpr int N = 15;
+    __shared__ double M[N * N], G[N * N], T1[N * N], T2[N * N], P[N * N];
+    __shared__ double vnew[6], E[9], Jl[9], Ra[3], R0[9], v[3], w[3], b[3];
+    __shared__ prism_pose pose;
+    if (threadIdx.x == 0) {
+        pose = S->pose;
+        for (int i = 0; i < 3; ++i) {
+            v[i] = S->v[i];
+            w[i] = S->w[i];
+            b[i] = X->b[i];
+        }
+    }
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) P[e] = X->P[e];
+    __syncthreads();
+    for (int j = 0; j < k; ++j) {
+        if (threadIdx.x == 0) {
+            prism_pose pr;
+            transition_mean_bias_t0(pose, v, w, b, u + 6 * j, tc, vnew, E, Jl, Ra, R0, pr);
+            pose = pr;
+            for (int i = 0; i < 3; ++i) {
+                v[i] = vnew[i];
+                w[i] = vnew[3 + i];
+            }
+            if (mean) {
+                double* m = mean + 16 * j;
+                for (int i = 0; i < 3; ++i) m[i] = pr.t[i];
+                for (int i = 0; i < 4; ++i) m[3 + i] = pr.q[i];
+                for (int i = 0; i < 6; ++i) m[7 + i] = vnew[i];
+                for (int i = 0; i < 3; ++i) m[13 + i] = b[i];
+            }
+        }
+        __syncthreads();
+        transition_cov_bias(E, Jl, Ra, R0, tc, P, M, G, T1, T2);
+        for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+            P[e] = T2[e];
+            if (cov) cov[N * N * j + e] = T2[e];
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_rollout(const prism_filter_state* S, const prism_filter_bias_state* X, const double* u, int k,
+                          int n_samples, const double* noise, const TransC& tc, prism_pose* poses, double* mean,
+                          double* cov, int32_t* flags, hipStream_t st) {
     if (mean || cov) {
-        k_rollout_moments<<<1, 256, 0, st>>>(S, u, k, tc, mean, cov);
+        if (X)
+            k_rollout_moments_bias<<<1, 256, 0, st>>>(S, X, u, k, tc, mean, cov);
+        else
+            k_rollout_moments<<<1, 256, 0, st>>>(S, u, k, tc, mean, cov);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (n_samples > 0) {
-        k_rollout_sample<<<n_samples, 64, 0, st>>>(S, u, k, noise, tc, poses, flags);
+        k_rollout_sample<<<n_samples, 64, 0, st>>>(S, X, u, k, noise, tc, poses, flags);
         return hipGetLastError();
     }
     return hipSuccess;

@@ -662,20 +662,22 @@ class Filter:
     def rollout(self, u: torch.Tensor, noise: Optional[torch.Tensor] = None, moments: bool = True,
                 frames: bool = False, stream=None) -> Dict[str, torch.Tensor]:
         """Predictive rollout from the current belief: u float64 [k, 6]
-        controls; noise float64 [n_samples, k+1, 12] standard normals.
-        Returns poses [n_samples, k, 7], mean [k, 13] / cov [k, 12, 12] (if
-        moments), depth/rgb/mask [n_samples*k, ...] (if frames), flags [1]."""
+        controls; noise float64 [n_samples, k+1, n] standard normals (n = 12,
+        15 with MODE_ACCEL_BIAS).  Returns poses [n_samples, k, 7], mean
+        [k, n+1] / cov [k, n, n] (if moments), depth/rgb/mask [n_samples*k,
+        ...] (if frames), flags [1]."""
         k = u.shape[0]
+        n = 15 if self.params.modes & MODE_ACCEL_BIAS else 12
         _dev(u, torch.float64, "u", (k, 6))
         dev = u.device
         ns = 0 if noise is None else noise.shape[0]
         if noise is not None:
-            _dev(noise, torch.float64, "noise", (ns, k + 1, 12))
+            _dev(noise, torch.float64, "noise", (ns, k + 1, n))
         out = dict(flags=torch.zeros(1, dtype=torch.int32, device=dev))
         out["poses"] = torch.empty((max(ns, 1), k, 7), dtype=torch.float64, device=dev)
         if moments:
-            out["mean"] = torch.empty((k, 13), dtype=torch.float64, device=dev)
-            out["cov"] = torch.empty((k, 12, 12), dtype=torch.float64, device=dev)
+            out["mean"] = torch.empty((k, n + 1), dtype=torch.float64, device=dev)
+            out["cov"] = torch.empty((k, n, n), dtype=torch.float64, device=dev)
         if frames:
             H, W = self.cam.height, self.cam.width
             out["depth"] = torch.empty((ns * k, H, W), dtype=torch.float32, device=dev)

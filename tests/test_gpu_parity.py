@@ -523,8 +523,8 @@ def test_filter_bias_state_matches_oracle(objective):
 
 def test_filter_bias_state_entry_points():
     """The 15-D state's entry points refuse the wrong state size: the 12-D
-    reset and rollouts on a 15-D filter, the 15-D reset and bias read-back on
-    a 12-D one, and a 12-D checkpoint loaded into a 15-D filter."""
+    reset on a 15-D filter, the 15-D reset and bias read-back on a 12-D one,
+    and a 12-D checkpoint loaded into a 15-D filter."""
     banner("15-D state entry points")
     c = synth.trajectory_case(seed=2, n=64, width=80, height=60, n_samples=32, n_frames=2)
     tr = c["traj"]
@@ -542,9 +542,6 @@ def test_filter_bias_state_entry_points():
     out = ctypes.c_void_p()
     assert L.prism_filter_bias_state_ptr(f12.h, ctypes.byref(out)) == 2
     assert L.prism_filter_bias_state_ptr(f15.h, ctypes.byref(out)) == 0 and out.value
-    u = torch.zeros(6, dtype=torch.float64, device=DEV)
-    assert L.prism_rollout(f15.h, ctypes.c_void_p(u.data_ptr()), 1, 0, None, None, None, None, None, None, None,
-                           None, None) == 2
     f12.reset(x12, np.diag([1e-6] * 6 + [1e-4] * 6))
     f12.map.init()
     nbytes = ctypes.c_size_t()
@@ -861,6 +858,48 @@ def test_adam_rejects_p1_and_bad_samples():
 # ---------------------------------------------------------------------------
 # predictive rollouts
 # ---------------------------------------------------------------------------
+def test_rollout_15d_matches_oracle():
+    """Rollout from a seeded 15-D belief (accelerometer bias, body-frame force
+    controls) and the ground-truth map: sampled poses, the 16-value means and
+    15x15 covariances, and the frames, against the oracle on the same
+    belief, map and draws."""
+    banner("rollout 15-D state, 64^3 80x60, 3 samples x 4 steps")
+    c = synth.trajectory_case(seed=2, n=64, width=80, height=60, n_samples=32, n_frames=1)
+    tr = c["traj"]
+    g = grid_of(c["scene"], 0)
+    mean, var = synth.gt_map(c["scene"])
+    fp = P().FilterParams(objective=0, modes=P().MODE_ACCEL_BIAS, sigma_bias=0.01)
+    f = P().Filter(g, cam_of(c["cam"]), fp, vmap=gpu_map(g, mean, var))
+    rng = np.random.default_rng(8)
+    A = rng.normal(size=(15, 15)) * 0.01
+    Pb = A @ A.T + np.diag([1e-5] * 6 + [1e-4] * 6 + [1e-5] * 3)
+    x = dict(t=tr.t[0], q=tr.q[0], v=tr.v[0], w=tr.w[0], b=np.array([0.02, -0.03, 0.01]))
+    f.reset(np.concatenate([x["t"], x["q"], x["v"], x["w"], x["b"]]), Pb)
+    k, S = 4, 3
+    u = rng.normal(size=(k, 6)) + np.array([0.0, 0.0, 9.81, 0.0, 0.0, 0.0])
+    z = rng.normal(size=(S, k + 1, 15))
+    out = f.rollout(t(u, torch.float64), t(z, torch.float64), moments=True, frames=True)
+    torch.cuda.synchronize()
+    op = orc.Params(accel_bias=True, sigma_bias=fp.sigma_bias, gravity=tuple(fp.gravity))
+    ref = orc.rollout(orc.grid_from_scene(c["scene"]), oracle_map_values(mean, 0), orc.cam_from(c["cam"]), x, Pb,
+                      u, z, op)
+    assert int(out["flags"].item()) == 0 and ref["ok"]
+    pg = out["poses"].cpu().numpy()
+    for s_ in range(S):
+        for j in range(k):
+            assert np.linalg.norm(orc.pose_error(pg[s_, j], ref["poses"][s_, j])) < 1e-9
+    np.testing.assert_allclose(out["mean"].cpu().numpy(), ref["mean"], rtol=0, atol=1e-12)
+    cg = out["cov"].cpu().numpy()
+    assert cg.shape == (k, 15, 15)
+    assert np.linalg.norm(cg - ref["cov"]) <= 1e-10 * np.linalg.norm(ref["cov"])
+    for n in range(S * k):
+        r = ref["frames"][n]
+        mk = out["mask"][n].cpu().numpy()
+        np.testing.assert_array_equal(mk, r["mask"])
+        v = mk == 1
+        assert np.all(depth_close(out["depth"][n].cpu().numpy()[v], r["depth"][v]))
+
+
 def test_rollout_matches_oracle():
     """Rollout from a seeded belief and the ground-truth map: sampled poses,
     the closed-form moments and the frames rendered at the sampled poses
