@@ -369,14 +369,24 @@ __device__ __forceinline__ void map_update_block(int blk, int ngroups, const Gri
     // of a slice is 64 consecutive elements; no workgroup barrier per brick
     const int nwaves = ngroups * 4;
     int cnt = 0;
-    for (int e = blk * 4 + wv; e < total; e += nwaves) {
-        // segment holding entry e (binary search over the prefix sums)
+    // brick of list entry e: the segment holding e (binary search over the
+    // prefix sums), then its list slot
+    auto brick_of = [&](int e) {
         int a = 0, z = nseg;
         while (z - a > 1) {
             int mid = (a + z) >> 1;
             if (sstart[mid] <= e) a = mid; else z = mid;
         }
-        const int b = aux.list[a * 256 + (e - sstart[a])];
+        return aux.list[a * 256 + (e - sstart[a])];
+    };
+    // the next brick's index is loaded while this one is processed, so the
+    // list read is off each brick's chain of memory round trips
+    int b_next = blk * 4 + wv < total ? brick_of(blk * 4 + wv) : 0;
+    for (int e = blk * 4 + wv; e < total; e += nwaves) {
+        const int b = b_next;
+        if (e + nwaves < total) b_next = brick_of(e + nwaves);
+        // the brick's summary, issued with the depth gathers below
+        const float bm_old = aux.bmax[b];
         const int bx = b % g.nb, by = (b / g.nb) % g.nb, bz = b / (g.nb * g.nb);
         const int i = (bx << 3) | (lane & 7), j = (by << 3) | (lane >> 3);
         // decisions for the lane's 8 voxels in single precision
@@ -458,7 +468,6 @@ __device__ __forceinline__ void map_update_block(int blk, int ngroups, const Gri
         // occupancy of voxels this update leaves alone is read only where it
         // can decide the brick's free-space bit: in a brick holding a voxel
         // above 0 before the update (in a free brick every such voxel is <= 0)
-        const float bm_old = aux.bmax[b];
         const bool need_occ = !fresh && !(bm_old <= 0.0f);
         float m = -INFINITY;
         // the lane's eight z-slices in groups of two: a group's plane and
