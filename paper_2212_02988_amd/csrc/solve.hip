@@ -112,11 +112,24 @@ __device__ inline void chol_inverse(const double* L, double* Ainv) {
 // sums in flight; the G sums of each column are then added in row-group order.
 // (Each thread reading whole rows made every load instruction touch 64 cache
 // lines, which one workgroup's vector memory path takes serially.)
+// With sg given, the filter state is copied into ls on the way: its words
+// are loaded together with the first partials (not one round trip before
+// them) and stored to LDS before the sum's barrier.
 __device__ inline void sum_partials(const double* __restrict__ partials, int nblocks, double* lds_red,
-                                    double* lds_out) {
+                                    double* lds_out, const prism_filter_state* __restrict__ sg = nullptr,
+                                    prism_filter_state* ls = nullptr) {
+    constexpr int kStateWords = (int)(sizeof(prism_filter_state) / 8);
+    static_assert(sizeof(prism_filter_state) % 8 == 0 && kStateWords <= 2 * 256, "state copied in two words per thread");
     const int bd = min((int)blockDim.x, kRedLds);
     const int G = bd / PRISM_NEQ, span = G * PRISM_NEQ;
     const int t = threadIdx.x;
+    unsigned long long sw0 = 0, sw1 = 0;
+    const int t1 = t + (int)blockDim.x;
+    if (sg) {
+        const unsigned long long* src = reinterpret_cast<const unsigned long long*>(sg);
+        if (t < kStateWords) sw0 = src[t];
+        if (t1 < kStateWords) sw1 = src[t1];
+    }
     double acc = 0.0;
     if (t < span) {
         const long long total = (long long)nblocks * PRISM_NEQ;
@@ -132,6 +145,11 @@ __device__ inline void sum_partials(const double* __restrict__ partials, int nbl
         for (; e < total; e += span) a[0] += partials[e];
         acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
         lds_red[t] = acc;
+    }
+    if (ls) {
+        unsigned long long* dst = reinterpret_cast<unsigned long long*>(ls);
+        if (t < kStateWords) dst[t] = sw0;
+        if (t1 < kStateWords) dst[t1] = sw1;
     }
     __syncthreads();
     if (t < PRISM_NEQ) {
@@ -487,8 +505,7 @@ __device__ __forceinline__ void gn_step_block(prism_filter_state* __restrict__ S
                                               Rel32* __restrict__ rel) {
     __shared__ double red[kRedLds], neq[PRISM_NEQ];
     __shared__ prism_filter_state Ls;
-    state_in(Sg, &Ls);
-    sum_partials(partials, nblocks, red, neq);
+    sum_partials(partials, nblocks, red, neq, Sg, &Ls);
     if (threadIdx.x == 0) gn_step_body(&Ls, neq);
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -555,9 +572,8 @@ __device__ __forceinline__ void laplace_combine_block(prism_filter_state* __rest
     __shared__ double A[36], Sl[36], Sb[36], D[36], T[36], P[144], e[6];
     __shared__ int ok;
     __shared__ prism_filter_state Ls;
-    state_in(Sg, &Ls);
     prism_filter_state* S = &Ls;
-    sum_partials(partials, nblocks, red, neq);
+    sum_partials(partials, nblocks, red, neq, Sg, &Ls);
     if (threadIdx.x < PRISM_NEQ) S->neq[threadIdx.x] = neq[threadIdx.x];
     if (S->flags & PRISM_FLAG_PRIOR_NOT_PD) {
         // predicted mean and covariance as they are (the covariance was
