@@ -2,11 +2,13 @@
 // linearised transition + propagation + split into pose prior and velocity
 // conditional; Gauss-Newton step of the MAP pose objective; Laplace
 // covariance (squared-Jacobian Hessian, with the dynamics prior), its EMA,
-// and the product with the velocity conditional.
+// and the product with the velocity conditional; the same over the 15-D
+// state with an accelerometer bias; predictive rollouts.
 //
-// Each kernel is one workgroup of 256 threads per filter: the block partial
-// sums of the normal equations are reduced in a fixed order, matrix products
-// are spread over the threads, and the 6x6 Cholesky factorisations run on
+// Each kernel is one workgroup per filter (256 threads for the prediction,
+// 512 for the Gauss-Newton and Laplace kernels, which first reduce the block
+// partial sums of the normal equations in a fixed order): matrix products
+// are spread over the threads, and the small Cholesky factorisations run on
 // one thread.  Everything stays on the device so a filter step can be
 // captured in a HIP graph.
 #include "common.hpp"
