@@ -5,12 +5,14 @@
 // 8x2 pixel strip per wave, an 8x8 tile per workgroup, blockIdx.y = frame.
 // A single frame is only ~10^5 rays, so the march is latency-bound: the four
 // lanes of a ray evaluate interleaved samples (lane s takes k0 + s + 4 j,
-// j < kPerLane) and a two-step shuffle finds the first crossing of the trip,
-// which shortens each ray's chain of dependent gathers four-fold and gives the
-// GPU four times more waves to overlap.  Samples in bricks whose occupancy
-// is <= 0 everywhere are decided without touching the map (free-space bits
-// in LDS; a cell spanning bricks reads one dilated bit for its 2x2x2 block).  At the hit the quad splits the double-precision shading and the
-// Jacobian by channel: lane 0 occupancy / depth, lanes 1-3 one colour each.
+// j < kPerLane) and two DPP quad permutations find the first crossing of the
+// trip, which shortens each ray's chain of dependent gathers four-fold and
+// gives the GPU four times more waves to overlap.  Samples in bricks whose
+// occupancy is <= 0 everywhere are decided without touching the map
+// (free-space bits in LDS; every cell reads the dilated bit of its base
+// corner's 2x2x2 block of bricks).  At the hit the quad splits the
+// double-precision shading and the Jacobian by channel: lane 0 occupancy /
+// depth, lanes 1-3 one colour each.
 //
 // The adjoint keeps one ray per lane (16x16 pixels per workgroup): it
 // recomputes two samples per ray from the given hit index, nothing to march.
