@@ -777,7 +777,8 @@ def cpu_model():
 def cpu_configs(frames, runs=3):
     """The oracle on the single-stream workloads (configs 1-4 of the
     benchmark: single frame, 256^3 trajectory, adjoint, 384^3 BF16
-    trajectory), with all host threads and with one, median of `runs`; each
+    trajectory with the 15-D state), with all host threads and with one,
+    median of `runs`; each
     run in its own process so that OpenMP starts with that many threads."""
     import subprocess
     all_threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))

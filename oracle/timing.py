@@ -16,8 +16,9 @@ thread count is fixed when the oracle's library loads):
 3. adjoint, 256^3 ground-truth map, 320x240, K = 128: one frame of the
    renderer's adjoint with random upstream gradients;
 4. mixed-precision workload, 384^3 (1.67 cm), 640x480, K = 192: the first F
-   frames of the filter on BF16-rounded inputs (the oracle computes in FP64
-   either way).
+   frames of the filter with the 15-D state (accelerometer bias, 15x15
+   covariance; the accelerometer's body-frame force as the linear control)
+   on BF16-rounded inputs (the oracle computes in FP64 either way).
 """
 from __future__ import annotations
 
@@ -66,7 +67,7 @@ def config1(reps=50):
                          f"Laplace, map update), mean of {reps}", "voxels_updated": n_upd}
 
 
-def _filter_frames(n, width, height, K, frames, bf16=False, seed=1):
+def _filter_frames(n, width, height, K, frames, bf16=False, seed=1, bias=False):
     c = synth.trajectory_case(seed=seed, n=n, width=width, height=height, n_samples=K, n_frames=frames)
     tr = c["traj"]
     g, cam = orc.grid_from_scene(c["scene"]), orc.cam_from(c["cam"])
@@ -74,15 +75,20 @@ def _filter_frames(n, width, height, K, frames, bf16=False, seed=1):
     if bf16:
         mean = synth.bf16_round(mean).astype(np.float64)
         var = synth.bf16_round(var).astype(np.float64)
-    f = orc.Filter(g, cam, orc.Params(), dict(t=tr.t[0], q=tr.q[0], v=tr.v[0], w=tr.w[0]),
-                   np.diag([1e-6] * 6 + [1e-4] * 6), mean, var)
+    x0 = dict(t=tr.t[0], q=tr.q[0], v=tr.v[0], w=tr.w[0])
+    P0 = np.diag([1e-6] * 6 + [1e-4] * 6)
+    if bias:
+        x0["b"] = np.zeros(3)
+        P0 = np.diag([1e-6] * 6 + [1e-4] * 6 + [1e-4] * 3)
+    f = orc.Filter(g, cam, orc.Params(accel_bias=bias), x0, P0, mean, var)
+    u = tr.u_body if bias else tr.u
     del mean, var
     times = []
     for i in range(frames):
         d = c["depth"][i].astype(np.float64)
         rgb = c["rgb"][i].astype(np.float64)
         t0 = time.perf_counter()
-        f.step(d, rgb, tr.u[i - 1] if i else None)
+        f.step(d, rgb, u[i - 1] if i else None)
         times.append(time.perf_counter() - t0)
     # one render and one map update on their own, at the last pose
     pose = f.s.pose
@@ -126,7 +132,7 @@ def main():
     elif a.config == 3:
         out = config3()
     else:
-        out = _filter_frames(384, 640, 480, 192, a.frames, bf16=True, seed=4)
+        out = _filter_frames(384, 640, 480, 192, a.frames, bf16=True, seed=4, bias=True)
     out.update(config=a.config, threads=int(os.environ.get("OMP_NUM_THREADS", "0")) or None)
     print(json.dumps(out), flush=True)
 
