@@ -822,6 +822,72 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
+def measured_counter(kernel, key):
+    """A per-launch counter figure of `kernel` (e.g. its waves or vector-load
+    instructions per wave) from the committed counter summary, or None when
+    the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "serving_mix_traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_digest") != source_digest():
+        return None
+    return t.get("kernels", {}).get(kernel, {}).get(key)
+
+
+def gather_ceiling(torch, render_avg_us=None, blocks=2048, rounds=64, reps=5):
+    """Measured ceilings of cache-resident gathers (the probe library): waves
+    of 256-thread workgroups each issuing 8 x `rounds` 64-lane 4-byte loads
+    from a 16 KB (L1-resident) or 2 MB (L2-resident) buffer, lanes reading
+    consecutive words or independent random words; as 64-lane load
+    instructions per second and per CU clock.  Beside them the renderer's
+    vector-load rate on the serving mix: its load instructions per launch
+    (waves x loads per wave, from the committed counters) over the launch
+    time measured in this run."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2212_02988_amd", "libprism_probe.so"))
+    fn = lib.prism_probe_gather
+    fn.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                   ctypes.c_void_p]
+    fn.restype = ctypes.c_int
+    st = torch.cuda.Stream()
+    sink = torch.zeros(1, device="cuda")
+    wave_loads = blocks * 4 * rounds * 8
+    out = {"workload": f"{blocks} workgroups x 256 threads, {8 * rounds} loads of 4 bytes per lane, median of {reps}"}
+    for name, words in (("l1_16KB", 4096), ("l2_2MB", 1 << 19)):
+        buf = torch.ones(words, device="cuda")
+        for random in (0, 1):
+            times = []
+            for _ in range(reps + 1):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(st)
+                err = fn(buf.data_ptr(), words, rounds, random, blocks, sink.data_ptr(), ctypes.c_void_p(st.cuda_stream))
+                if err != 0:
+                    raise RuntimeError(f"gather probe failed ({err})")
+                e1.record(st)
+                st.synchronize()
+                times.append(e0.elapsed_time(e1))
+            ms = float(np.median(times[1:]))
+            rate = wave_loads / (ms * 1e-3)
+            out[f"{name}_{'random' if random else 'coalesced'}"] = {
+                "us": round(ms * 1e3, 2), "loads_per_s": float(f"{rate:.4g}"),
+                "loads_per_cu_clock": round(rate / (256 * 2.4e9), 4)}
+        del buf
+    waves = measured_counter("k_render_batch", "waves")
+    per_wave = measured_counter("k_render_batch", "vmem_rd_per_wave")
+    if render_avg_us and waves and per_wave:
+        rate = waves * per_wave / (render_avg_us * 1e-6)
+        out["render_batch"] = {"loads_per_launch": int(waves * per_wave), "avg_launch_us": render_avg_us,
+                               "loads_per_s": float(f"{rate:.4g}"),
+                               "loads_per_cu_clock": round(rate / (256 * 2.4e9), 4),
+                               "frac_of_l2_random": round(rate / out["l2_2MB_random"]["loads_per_s"], 3),
+                               "frac_of_l1_coalesced": round(rate / out["l1_16KB_coalesced"]["loads_per_s"], 3)}
+    log(f"gather ceilings: " + ", ".join(f"{k} {v['loads_per_cu_clock']}" for k, v in out.items() if isinstance(v, dict)))
+    return out
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` in this workload from the committed
     counter summary (FETCH_SIZE, WRITE_SIZE scaled by a plain copy), or None
@@ -1018,6 +1084,7 @@ def main():
             "achieved": round(single["mu_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(single["mu_gbs"] / HBM_PEAK_GBS, 4), "avg_call_us": round(single["us_mu"], 2)}
         extra["roofline_map_update_cold"] = map_update_cold(P, torch)
+        extra["gather_ceiling"] = gather_ceiling(torch, breakdown.get("render", {}).get("avg_us"))
         extra["single_frame_workload"] = single_frame_gpu(P, torch)
         extra["bf16_384_stream"] = bf16_stream_gpu(P, torch)
         extra["bf16_384_stream_15d"] = bf16_stream_gpu(P, torch, bias=True)

@@ -1,4 +1,6 @@
-"""Compile the gfx950 HIP library (libprism.so) in-tree with hipcc."""
+"""Compile the gfx950 HIP library (libprism.so) in-tree with hipcc, and the
+gather-rate probe the benchmark uses (libprism_probe.so, not part of the
+library's interface)."""
 from __future__ import annotations
 
 import concurrent.futures as cf
@@ -10,6 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libprism.so")
+PROBE_SRC = os.path.join(HERE, "probe", "probe.hip")
+PROBE_OUT = os.path.join(HERE, "libprism_probe.so")
 SOURCES = ["render.hip", "track.hip", "map.hip", "solve.hip", "stage.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -45,8 +49,14 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, OUT)
+    tmp = PROBE_OUT + ".tmp"
+    cmd = [HIPCC, *FLAGS, "-shared", PROBE_SRC, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on the probe:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, PROBE_OUT)
     if verbose:
-        print("built", OUT)
+        print("built", OUT, "and", PROBE_OUT)
     return OUT
 
 
