@@ -611,9 +611,11 @@ def mapping_comparison(P, torch, lr_occ=3e-6, lr_rgb=3e-3, n_prior=20):
 # ---------------------------------------------------------------------------
 def large_room_pool(P, torch, n_frames=60):
     """One stream in a 25.6 m room on a 512^3 BF16 grid (5 cm voxels), K = 128,
-    320x240: the same filter steps on a dense map and on a brick-pool map with
-    room for every brick; step time, map bytes, the fraction of bricks that
-    received a slot, and whether the two final states agree bit for bit."""
+    320x240: the same filter steps on a dense map, on a brick-pool map with
+    room for every brick and on one with room for half of them; step time,
+    map bytes, the fraction of bricks that received a slot, dropped brick
+    updates, and whether the final states agree bit for bit with the dense
+    map's."""
     import synth
     N, Wd, Ht, K, room = 512, 320, 240, 128, 25.6
     case = synth.trajectory_case(seed=5, n=N, width=Wd, height=Ht, n_samples=K, n_frames=n_frames, room=room,
@@ -624,7 +626,7 @@ def large_room_pool(P, torch, n_frames=60):
     U = torch.from_numpy(np.concatenate([tr.u, tr.u[-1:]], 0)).to("cuda")
     nb3 = (N // 8) ** 3
     out, states = {}, {}
-    for name, cap in (("dense", 0), ("pool", nb3)):
+    for name, cap in (("dense", 0), ("pool", nb3), ("pool_half", nb3 // 2)):
         grid = P.Grid.make(N, scene.voxel, tuple(float(v) for v in scene.origin), dtype=P.PRISM_BF16, capacity=cap)
         f = P.Filter(grid, cam, P.FilterParams(n_gn=3, objective=P.OBJ_P2))
         f.map.init()
@@ -642,15 +644,17 @@ def large_room_pool(P, torch, n_frames=60):
         states[name] = bytes(f.state())
         o = {"map_gb": round(P.map_bytes(grid) / 2**30, 3), "step_ms": round(float(np.median(ms[5:])), 4)}
         if cap:
-            used = int(f.map.pool_usage()[0].item())
-            o.update(bricks_used=used, fraction_used=round(used / nb3, 4),
-                     pool_gb_needed=round(used * 8 * 512 * 2 / 2**30, 3))
+            used, dropped = (int(x) for x in f.map.pool_usage().cpu())
+            o.update(capacity_bricks=cap, bricks_used=used, fraction_used=round(used / nb3, 4),
+                     dropped_updates=dropped, pool_gb_needed=round(used * 8 * 512 * 2 / 2**30, 3))
         out[name] = o
         del f
     out["same_state"] = states["dense"] == states["pool"]
+    out["same_state_half"] = states["dense"] == states["pool_half"]
     out["workload"] = (f"one stream, 512^3 BF16 grid over a 25.6 m room (5 cm voxels), 320x240, K = 128, "
                        f"{n_frames} frames")
-    log(f"large room: dense {out['dense']}, pool {out['pool']}, same state {out['same_state']}")
+    log(f"large room: dense {out['dense']}, pool {out['pool']}, half pool {out['pool_half']}, "
+        f"same state {out['same_state']} / {out['same_state_half']}")
     return out
 
 
