@@ -14,8 +14,9 @@
 // double-precision shading and the Jacobian by channel: lane 0 occupancy /
 // depth, lanes 1-3 one colour each.
 //
-// The adjoint keeps one ray per lane (16x16 pixels per workgroup): it
-// recomputes two samples per ray from the given hit index, nothing to march.
+// The adjoint takes four lanes per ray as well (8x8 pixels per workgroup):
+// from the given hit index it recomputes the two samples, nothing to march,
+// and lane s scatters the gradient of plane s.
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -23,12 +24,6 @@ namespace prism {
 
 constexpr int kLanes = 4;       // lanes per ray in render / render_jacobian
 constexpr int kPerLane = 4;     // samples per lane per trip
-
-struct RayHit {
-    int k;          // k* or -1
-    float f0, f1;   // occupancy at k*-1, k*
-    Cell c0, c1;    // cells of samples k*-1, k*
-};
 
 template <typename T, bool Pool>
 __device__ __forceinline__ float occ_at(const GridC& g, const T* occ, const Cell& c) {
@@ -188,14 +183,6 @@ __device__ __forceinline__ float march_sample(const GridC& g, const T* occ, cons
     return occ_at<T, Pool>(g, occ, cl);
 }
 
-struct Shade {
-    float alpha, d0, d1;       // single-precision copies for the Jacobian
-    float c0[3], c1[3];
-    float w0[3], w1[3];        // interpolation weights from the double-precision points
-    double depth, rgb[3];      // double-precision values at the hit
-    double f0, f1;
-};
-
 // double-precision sample point k of the ray with direction dir (world)
 __device__ __forceinline__ void grid_coord64(const GridD& gd, const CamD& cd, const Pose64& P, const double dir[3],
                                              int k, double gc[3]) {
@@ -207,146 +194,10 @@ __device__ __forceinline__ void grid_coord64(const GridD& gd, const CamD& cd, co
     }
 }
 
-// The eight corners of one cell in the four mean planes of an FP32 map,
-// loaded once for the adjoint: v[p][q] the stored value, or the plane's
-// outside value (single precision) for a corner outside the grid; e[q] the
-// corner's element index, -1 outside the grid.  The adjoint's occupancy
-// test, double-precision shading, Jacobian and scatter all read these.
-struct CellVals {
-    float v[4][8];
-    int e[8];
-};
-
-__device__ __forceinline__ void cell_vals(const GridC& g, const float* map, const Cell& c, CellVals& cv) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int i = c.i[0] + (q & 1), j = c.i[1] + ((q >> 1) & 1), k = c.i[2] + (q >> 2);
-        const bool in = (unsigned)i < (unsigned)g.n && (unsigned)j < (unsigned)g.n && (unsigned)k < (unsigned)g.n;
-        cv.e[q] = in ? (int)vidx<false>(g, i, j, k) : -1;
-    }
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            cv.v[p][q] = cv.e[q] >= 0 ? map[(long long)p * g.nvox + cv.e[q]] : (p == 0 ? g.occ_out : g.rgb_out);
-}
-
-// Trilinear value of plane p in double precision from the adjoint's
-// preloaded corners: weights from the double-precision grid coordinate, sum
-// over the 8 corners of the product of 1-D hat weights (z, y, x order); a
-// corner outside the grid takes the double-precision outside value.
-__device__ __forceinline__ double tri64v(const CellVals& cv, int p, double outv, const double gc[3],
-                                         const int cell[3]) {
-    double w0 = gc[0] - (double)cell[0], w1 = gc[1] - (double)cell[1], w2 = gc[2] - (double)cell[2];
-    double s = 0.0;
-#pragma unroll
-    for (int cz = 0; cz < 2; ++cz)
-#pragma unroll
-        for (int cy = 0; cy < 2; ++cy)
-#pragma unroll
-            for (int cx = 0; cx < 2; ++cx) {
-                const int q = cx + 2 * cy + 4 * cz;
-                double hx = cx ? w0 : 1.0 - w0;
-                double hy = cy ? w1 : 1.0 - w1;
-                double hz = cz ? w2 : 1.0 - w2;
-                double V = cv.e[q] >= 0 ? (double)cv.v[p][q] : outv;
-                s += hx * hy * hz * V;
-            }
-    return s;
-}
-
-// shading at a valid hit from the two cells' corner values
-__device__ __forceinline__ Shade shade_v(const GridD& gd, const CamD& cd, const Pose64& P, int u, int v,
-                                         const RayHit& h, const CellVals& v0, const CellVals& v1) {
-    Shade s;
-    double rc[3], dir[3], gc0[3], gc1[3];
-    pixel_dir64(cd, u, v, rc);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) dir[a] = P.R[a][0] * rc[0] + P.R[a][1] * rc[1] + P.R[a][2] * rc[2];
-    grid_coord64(gd, cd, P, dir, h.k - 1, gc0);
-    grid_coord64(gd, cd, P, dir, h.k, gc1);
-    double d0 = cd.dn + (double)(h.k - 1) * cd.step;
-    double d1 = cd.dn + (double)h.k * cd.step;
-    s.f0 = tri64v(v0, 0, gd.occ_out, gc0, h.c0.i);
-    s.f1 = tri64v(v1, 0, gd.occ_out, gc1, h.c1.i);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        s.w0[a] = (float)(gc0[a] - (double)h.c0.i[a]);
-        s.w1[a] = (float)(gc1[a] - (double)h.c1.i[a]);
-    }
-    double al = (cd.tau - s.f0) / (s.f1 - s.f0);
-    s.depth = al * d1 + (1.0 - al) * d0;
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-        double c0 = tri64v(v0, 1 + ch, gd.rgb_out, gc0, h.c0.i);
-        double c1 = tri64v(v1, 1 + ch, gd.rgb_out, gc1, h.c1.i);
-        s.rgb[ch] = al * c1 + (1.0 - al) * c0;
-        s.c0[ch] = (float)c0;
-        s.c1[ch] = (float)c1;
-    }
-    s.alpha = (float)al;
-    s.d0 = (float)d0;
-    s.d1 = (float)d1;
-    return s;
-}
-
 __device__ __forceinline__ void cross3(const float a[3], const float b[3], float o[3]) {
     o[0] = a[1] * b[2] - a[2] * b[1];
     o[1] = a[2] * b[0] - a[0] * b[2];
     o[2] = a[0] * b[1] - a[1] * b[0];
-}
-
-// d(depth, r, g, b)/d(delta) of a valid ray (k* held fixed), from the two
-// cells' preloaded corner values
-__device__ __forceinline__ void ray_jacobian(const GridC& g, const CellVals& v0, const CellVals& v1,
-                                             const Shade& s, const float dir[3], float J[4][6]) {
-    float a0[3], a1[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) { a0[i] = s.d0 * dir[i]; a1[i] = s.d1 * dir[i]; }
-    float gr0[3], gr1[3], cr[3];
-    trigrad(v0.v[0], s.w0, gr0);
-    trigrad(v1.v[0], s.w1, gr1);
-    float rf0[6], rf1[6];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) { gr0[i] *= g.inv_s; gr1[i] *= g.inv_s; rf0[i] = gr0[i]; rf1[i] = gr1[i]; }
-    cross3(a0, gr0, cr);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) rf0[3 + i] = cr[i];
-    cross3(a1, gr1, cr);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) rf1[3 + i] = cr[i];
-    float inv_den = (float)(1.0 / (s.f1 - s.f0));
-    float al = s.alpha;
-    float dal[6];
-#pragma unroll
-    for (int m = 0; m < 6; ++m) dal[m] = -((1.0f - al) * rf0[m] + al * rf1[m]) * inv_den;
-#pragma unroll
-    for (int m = 0; m < 6; ++m) J[0][m] = (s.d1 - s.d0) * dal[m];
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-        float G0[3], G1[3], g0[6], g1[6];
-        trigrad(v0.v[1 + ch], s.w0, G0);
-        trigrad(v1.v[1 + ch], s.w1, G1);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) { G0[i] *= g.inv_s; G1[i] *= g.inv_s; g0[i] = G0[i]; g1[i] = G1[i]; }
-        cross3(a0, G0, cr);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) g0[3 + i] = cr[i];
-        cross3(a1, G1, cr);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) g1[3 + i] = cr[i];
-        float dc = s.c1[ch] - s.c0[ch];
-#pragma unroll
-        for (int m = 0; m < 6; ++m) J[1 + ch][m] = dc * dal[m] + al * g1[m] + (1.0f - al) * g0[m];
-    }
-}
-
-__device__ __forceinline__ void tile_pixel(const CamC& c, int& u, int& v) {
-    int tiles_x = (c.W + 15) >> 4;
-    int bx = blockIdx.x % tiles_x, by = blockIdx.x / tiles_x;
-    int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
-    u = (bx << 4) + ((wv & 1) << 3) + (l & 7);
-    v = (by << 4) + ((wv >> 1) << 3) + (l >> 3);
 }
 
 struct BlockPose {
@@ -904,36 +755,56 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
 // ---------------------------------------------------------------------------
 // adjoint of render w.r.t. map means (atomic scatter) and pose
 // ---------------------------------------------------------------------------
-// The 256 rays of a 16x16 tile reach a few hundred distinct voxels through
-// 4096 trilinear corners: the four planes' contributions of a voxel are
-// summed in an LDS table (open addressing on the voxel index), and each
-// distinct voxel then costs one global atomic per plane.  A corner that finds
-// no slot within a few probes is added to global memory directly.
-constexpr int kVjpSlots = 1024;   // power of two
+// Four lanes per ray, as in the render: lane s recomputes plane s of the
+// forward pass at the ray's first crossing (the plane's corners at the two
+// cells, the double-precision shading, its row of the Jacobian) and scatters
+// its share of the upstream gradient to the plane's 16 corners.  The 64 rays
+// of an 8x8 tile reach a few hundred distinct voxels through 1024 corners per
+// plane: the contributions are summed in an LDS table per plane (open
+// addressing on the voxel index), and each distinct (plane, voxel) then costs
+// one global atomic.  A corner that finds no slot within a few probes is
+// added to global memory directly.
+constexpr int kVjpSlots = 512;   // per plane (power of two)
 constexpr int kVjpProbes = 8;
 
 struct VjpAgg {
-    int key[kVjpSlots];          // voxel index, -1 = empty
-    float val[kVjpSlots][4];
+    int key[4][kVjpSlots];       // voxel index, -1 = empty
+    float val[4][kVjpSlots];
 };
 
-__device__ __forceinline__ void vjp_add(VjpAgg& A, long long id, const float v[4], float* __restrict__ grad_mean,
+__device__ __forceinline__ void vjp_add(VjpAgg& A, int s, int id, float val, float* __restrict__ grad_mean,
                                         long long nvox) {
-    const int key = (int)id;
-    const unsigned h = ((unsigned)key * 2654435761u) >> (32 - 10);
+    const unsigned h = ((unsigned)id * 2654435761u) >> (32 - 9);
 #pragma unroll 1
     for (int p = 0; p < kVjpProbes; ++p) {
         const int slot = (int)((h + p) & (kVjpSlots - 1));
-        const int prev = atomicCAS(&A.key[slot], -1, key);
-        if (prev == -1 || prev == key) {
-#pragma unroll
-            for (int ch = 0; ch < 4; ++ch)
-                __hip_atomic_fetch_add(&A.val[slot][ch], v[ch], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int prev = atomicCAS(&A.key[s][slot], -1, id);
+        if (prev == -1 || prev == id) {
+            __hip_atomic_fetch_add(&A.val[s][slot], val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             return;
         }
     }
+    atomicAdd(grad_mean + (long long)s * nvox + id, val);
+}
+
+// coef * (trilinear weight) into plane s at the in-grid corners of the cell
+__device__ __forceinline__ void vjp_cell(const GridC& g, VjpAgg& A, int s, const Cell& cl, const float w[3],
+                                         float coef, float* __restrict__ grad_mean) {
 #pragma unroll
-    for (int ch = 0; ch < 4; ++ch) atomicAdd(grad_mean + (long long)ch * nvox + id, v[ch]);
+    for (int q = 0; q < 8; ++q) {
+        const int dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
+        const int i = cl.i[0] + dx, j = cl.i[1] + dy, k = cl.i[2] + dz;
+        if ((unsigned)i >= (unsigned)g.n || (unsigned)j >= (unsigned)g.n || (unsigned)k >= (unsigned)g.n) continue;
+        const float hw = (dx ? w[0] : 1.0f - w[0]) * (dy ? w[1] : 1.0f - w[1]) * (dz ? w[2] : 1.0f - w[2]);
+        vjp_add(A, s, (int)vidx(g, i, j, k), coef * hw, grad_mean, g.nvox);
+    }
+}
+
+// sum over the quad in single precision (every lane ends with (x0 + x1) + (x2 + x3))
+__device__ __forceinline__ float quad_sumf(float x) {
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, false));
+    return x;
 }
 
 __global__ __launch_bounds__(256) void k_render_vjp(GridC g, CamC c, GridD gd, CamD cd, const float* __restrict__ map,
@@ -946,74 +817,53 @@ __global__ __launch_bounds__(256) void k_render_vjp(GridC g, CamC c, GridD gd, C
     __shared__ BlockPose sp;
     __shared__ double lds[kRedLds];
     __shared__ VjpAgg A;
-    for (int e = threadIdx.x; e < kVjpSlots; e += 256) {
-        A.key[e] = -1;
-#pragma unroll
-        for (int ch = 0; ch < 4; ++ch) A.val[e][ch] = 0.0f;
+    for (int e = threadIdx.x; e < 4 * kVjpSlots; e += 256) {
+        (&A.key[0][0])[e] = -1;
+        (&A.val[0][0])[e] = 0.0f;
     }
     const BlockPose& P = block_pose(poses + blockIdx.y, &sp);   // synchronises the workgroup
-    int u, v;
-    tile_pixel(c, u, v);
+    int u, v, s;
+    quad_pixel(c, blockIdx.x, u, v, s);
     double acc[PRISM_NEQ];
 #pragma unroll
     for (int q = 0; q < PRISM_NEQ; ++q) acc[q] = 0.0;
     if (u < c.W && v < c.H) {
-        long long pix = (long long)blockIdx.y * c.W * c.H + (long long)v * c.W + u;
-        int k = hit_k[pix];
-        if (k >= 1 && k < c.K) {
+        const long long pix = (long long)blockIdx.y * c.W * c.H + (long long)v * c.W + u;
+        const int k = hit_k[pix];
+        if (k >= 1 && k < c.K) {   // the same for the four lanes of a ray
             float dir[3];
             ray_dir32(c, P.f, u, v, dir);
             const RayCoef rc = ray_coef(g, c, P.f, dir);
-            RayHit h;
-            h.k = k;
-            h.c0 = sample_cell(rc, k - 1);
-            h.c1 = sample_cell(rc, k);
-            // all 64 corner values of the two cells in one round of loads
-            CellVals v0, v1;
-            cell_vals(g, map, h.c0, v0);
-            cell_vals(g, map, h.c1, v1);
-            h.f0 = trilerp(v0.v[0], h.c0.w);
-            h.f1 = trilerp(v1.v[0], h.c1.w);
-            if (h.f1 > c.tau && !(h.f0 > c.tau)) {
-                Shade s = shade_v(gd, cd, P.d, u, v, h, v0, v1);
-                float gd = g_depth[pix];
-                float gc[3] = {g_rgb[3 * pix], g_rgb[3 * pix + 1], g_rgb[3 * pix + 2]};
-                float J[4][6];
-                ray_jacobian(g, v0, v1, s, dir, J);
+            const Cell c0 = sample_cell(rc, k - 1), c1 = sample_cell(rc, k);
+            const QuadShade q = shade_quad<float, false>(g, gd, cd, P.d, u, v, map, c0, c1, k, s);
+            // the forward pass's crossing test on lane 0's occupancy corners
+            const int crossing = trilerp(q.cv1, c1.w) > c.tau && !(trilerp(q.cv0, c0.w) > c.tau) ? 1 : 0;
+            if (__builtin_amdgcn_update_dpp(0, crossing, 0x00, 0xF, 0xF, false)) {
+                const float gs = s == 0 ? g_depth[pix] : g_rgb[3 * pix + s - 1];
+                // pose: the upstream gradient times this output's Jacobian row
+                float row[6];
+                jac_row_quad(g, q, dir, s, row);
 #pragma unroll
-                for (int m = 0; m < 6; ++m)
-                    acc[m] = (double)(gd * J[0][m] + gc[0] * J[1][m] + gc[1] * J[2][m] + gc[2] * J[3][m]);
-                float al = s.alpha;
-                float ga = gd * (s.d1 - s.d0) + gc[0] * (s.c1[0] - s.c0[0]) + gc[1] * (s.c1[1] - s.c0[1]) +
-                           gc[2] * (s.c1[2] - s.c0[2]);
-                float inv_den = (float)(1.0 / (s.f1 - s.f0));
-                float gf[2] = {-ga * (1.0f - al) * inv_den, -ga * al * inv_den};
-                float cw[2] = {1.0f - al, al};
-#pragma unroll
-                for (int sm = 0; sm < 2; ++sm) {
-                    const CellVals& cv = sm ? v1 : v0;
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        int dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
-                        if (cv.e[q] < 0) continue;   // outside the grid
-                        const float* cw3 = sm ? s.w1 : s.w0;
-                        float hw = (dx ? cw3[0] : 1.0f - cw3[0]) * (dy ? cw3[1] : 1.0f - cw3[1]) *
-                                   (dz ? cw3[2] : 1.0f - cw3[2]);
-                        const float vals[4] = {gf[sm] * hw, gc[0] * cw[sm] * hw, gc[1] * cw[sm] * hw,
-                                               gc[2] * cw[sm] * hw};
-                        vjp_add(A, cv.e[q], vals, grad_mean, g.nvox);
-                    }
-                }
+                for (int m = 0; m < 6; ++m) acc[m] = (double)(gs * row[m]);
+                // means: every output depends on the two occupancies through
+                // alpha; colour plane s also through its own blend
+                const float ga = quad_sumf(gs * (s == 0 ? q.d1 - q.d0 : (float)q.v1 - (float)q.v0));
+                const float al = (float)q.alpha;
+                const float inv_den = (float)(1.0 / (q.f1 - q.f0));
+                const float k0 = s == 0 ? -ga * (1.0f - al) * inv_den : gs * (1.0f - al);
+                const float k1 = s == 0 ? -ga * al * inv_den : gs * al;
+                vjp_cell(g, A, s, c0, q.w0, k0, grad_mean);
+                vjp_cell(g, A, s, c1, q.w1, k1, grad_mean);
             }
         }
     }
     block_reduce29(acc, lds, partials + ((long long)blockIdx.y * gridDim.x + blockIdx.x) * PRISM_NEQ);
     __syncthreads();
-    for (int e = threadIdx.x; e < kVjpSlots; e += 256) {
-        const int key = A.key[e];
+    // one global atomic per distinct (plane, voxel) of the tile
+    for (int e = threadIdx.x; e < 4 * kVjpSlots; e += 256) {
+        const int key = (&A.key[0][0])[e];
         if (key < 0) continue;
-#pragma unroll
-        for (int ch = 0; ch < 4; ++ch) atomicAdd(grad_mean + (long long)ch * g.nvox + key, A.val[e][ch]);
+        atomicAdd(grad_mean + (long long)(e / kVjpSlots) * g.nvox + key, (&A.val[0][0])[e]);
     }
 }
 
@@ -1161,7 +1011,7 @@ __global__ __launch_bounds__(256) void k_gd_grad(GridC g, CamC c, GridD gd, CamD
 // launchers
 // ---------------------------------------------------------------------------
 int render_blocks(const CamC& c) { return ((c.W + 7) >> 3) * ((c.H + 7) >> 3); }
-int vjp_blocks(const CamC& c) { return ((c.W + 15) >> 4) * ((c.H + 15) >> 4); }
+int vjp_blocks(const CamC& c) { return render_blocks(c); }
 
 static size_t bits_lds(const GridC& g, const unsigned* bits) {
     return bits ? (size_t)free_lds_words(free_words(g.nb)) * 4 : 0;
