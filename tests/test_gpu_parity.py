@@ -101,7 +101,7 @@ def test_render_small(case1, dtype):
 
 def test_render_edge_cases(case1):
     """Camera outside the grid looking away (no hits), camera inside a solid
-    (k* = 0 everywhere: invalid), ragged image (not a multiple of the 16x16
+    (k* = 0 everywhere: invalid), ragged image (not a multiple of the 8x8
     tile), minimal sample count."""
     banner("render edge cases")
     c, mean, var = case1
