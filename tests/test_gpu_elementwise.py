@@ -9,7 +9,8 @@ precision decisions.
 * Anchor normals: the GPU normals kernel and the oracle's normals on the same
   rendered depth image, mask bit for bit.
 * Adjoint: every component of the pose gradient and every voxel of the map
-  gradient.
+  gradient, at 80x60 and at the 8-frame 256^3 / 320x240 / K = 128 call of
+  the adjoint throughput figure.
 * Double-precision decisions: the oracle with every decision in FP64 (not
   the kernels' single-precision recipe); a hit sample, updated voxel or
   tracking row may differ only where the FP64 decision margin is below 1e-4
@@ -266,6 +267,53 @@ def test_render_vjp_per_element(small):
           f"maximum; with 1e-3: {e3[nz].max():.2e}, 99.9% {np.quantile(e3[nz], 0.999):.2e}); worst: channel "
           f"{w[0]}, |grad| / channel max {abs(rgm[w]) / cmax[w[0], 0, 0, 0]:.2e}", flush=True)
     assert em[nz].max() <= 1e-4, em[nz].max()
+
+
+def test_render_vjp_8_frames_full_size(big):
+    """The call behind the adjoint throughput figure: 8 frames in one launch,
+    256^3 FP32 (ground-truth means), 320x240, K = 128, upstream gradients
+    N(0, 1) on every output.  Pose gradient of each frame against its
+    accumulation scale; the map gradient, summed over the 8 frames, voxel by
+    voxel with a floor of 1e-2 of the channel's largest gradient."""
+    banner("render_vjp per element, 8 frames 256^3 320x240 K=128")
+    c, mean, _ = big
+    tr = c["traj"]
+    g = grid_of(c["scene"])
+    cam = cam_of(c["cam"])
+    vm = gpu_map(g, mean, np.full_like(mean, 1e-2))
+    rng = np.random.default_rng(22)
+    poses = np.stack([synth.pose7(*synth.perturb_pose(rng, tr.t[i], tr.q[i], 0.01, 0.01)) for i in range(8)])
+    pt = P().poses_tensor(poses)
+    H, W = cam.height, cam.width
+    gd = rng.normal(size=(8, H, W)).astype(np.float32)
+    gc = rng.normal(size=(8, H, W, 3)).astype(np.float32)
+    fwd = P().render(g, vm, cam, pt, hit_k=True)
+    gm, gp = P().render_vjp(g, vm, cam, pt, fwd["hit_k"], t(gd), t(gc))
+    gm = P().bricks_to_dense(g.n, gm).cpu().numpy().reshape(4, -1)
+    gp = gp.cpu().numpy()
+    torch.cuda.synchronize()
+    og, ocm, m64 = orc.grid_from_scene(c["scene"]), orc.cam_from(c["cam"]), mean.astype(np.float64)
+    rgm = np.zeros((4, g.n ** 3))
+    for i in range(8):
+        fm, fp = orc.render_vjp(og, m64, ocm, poses[i], gd[i], gc[i])
+        rgm += fm.reshape(4, -1)
+        del fm
+        r = orc.render(og, m64, ocm, poses[i])
+        full = orc.render_jacobian(og, m64, ocm, poses[i], np.where(r["mask"] == 1, r["depth"], 0.0), r["rgb"],
+                                   orc.Params(), want_J=True)
+        assert int(full["neq"][28]) == int(r["mask"].sum()) > 30000
+        up = np.concatenate([gd[i][..., None], gc[i]], -1).astype(np.float64)
+        scale = float(np.sum(np.linalg.norm(full["J"], axis=-1) * np.abs(up)))
+        ep = np.abs(gp[i] - fp) / scale
+        print(f"[vjp pose, frame {i}] max error / accumulation scale {ep.max():.2e}", flush=True)
+        assert ep.max() <= 1e-6, (i, ep)
+    nz = np.nonzero((rgm != 0) | (gm != 0))
+    assert nz[0].size > 100000
+    cmax = np.abs(rgm).max(1)
+    a, b = rgm[nz], gm[nz].astype(np.float64)
+    em = np.abs(b - a) / np.maximum(np.abs(a), 1e-2 * cmax[nz[0]])
+    print(f"[vjp map, 8 frames] {nz[0].size} entries, max scaled error {em.max():.2e}", flush=True)
+    assert em.max() <= 1e-4, em.max()
 
 
 # ---------------------------------------------------------------------------
