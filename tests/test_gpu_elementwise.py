@@ -316,6 +316,46 @@ def test_render_vjp_8_frames_full_size(big):
     assert em.max() <= 1e-4, em.max()
 
 
+def test_map_gd_full_size(big):
+    """Descent mapping at the size of the closed-form comparison: 256^3 FP32,
+    320x240, K = 128, one step from a perturbed previous belief (means of
+    the ground truth plus noise, variances U[0.5, 2]); the objective and every
+    mean after the step against the oracle (the same decisions on both
+    sides)."""
+    banner("map_gd 256^3 320x240 K=128, 1 step")
+    c, mean, _ = big
+    tr = c["traj"]
+    rng = np.random.default_rng(23)
+    m0 = (mean + np.concatenate([rng.normal(0, 0.01, (1,) + mean.shape[1:]),
+                                 rng.normal(0, 0.05, (3,) + mean.shape[1:])]).astype(np.float32)).astype(np.float32)
+    v0 = rng.uniform(0.5, 2.0, m0.shape).astype(np.float32)
+    pose = synth.pose7(tr.t[3], tr.q[3])
+    od, oc = c["depth"][3], c["rgb"][3]
+    g = grid_of(c["scene"], 0)
+    cam = cam_of(c["cam"])
+    p = orc.Params()
+    w = P().Weights.make(p.b_geo, p.b_rgb, p.gate_geo, p.gate_rgb)
+    lro, lrc = 3e-6, 3e-3
+    vm = gpu_map(g, m0, v0)
+    ws = P().map_gd_workspace(g, cam)
+    cost = torch.zeros(1, dtype=torch.float64, device=DEV)
+    P().map_gd(g, vm, cam, P().poses_tensor(pose), t(od), t(oc), w, lro, lrc, 1, ws, cost)
+    mg, _ = vm.to_dense()
+    mg = mg.cpu().numpy()
+    cg = float(cost.cpu().numpy()[0])
+    torch.cuda.synchronize()
+    ref, rcost = orc.map_gd(orc.grid_from_scene(c["scene"]), m0.astype(np.float64), v0.astype(np.float64),
+                            orc.cam_from(c["cam"]), pose, od, oc, p, lro, lrc, 1)
+    print(f"cost gpu {cg} oracle {rcost[0]}", flush=True)
+    assert abs(cg - rcost[0]) <= 1e-5 * abs(rcost[0])
+    moved = ref != m0
+    err = np.abs(mg.astype(np.float64) - ref)
+    print(f"voxels moved {int(moved.sum())}, max err {err.max():.3e}", flush=True)
+    assert moved.sum() > 100000
+    assert np.all(err <= 1e-6 * np.maximum(np.abs(ref), 1e-2))
+    assert np.array_equal(mg[~moved], m0[~moved])
+
+
 # ---------------------------------------------------------------------------
 # double-precision decisions (tier ii)
 # ---------------------------------------------------------------------------
