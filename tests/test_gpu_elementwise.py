@@ -18,6 +18,8 @@ precision decisions.
 * The FP32 filter at the single-stream trajectory size (256^3, 320x240,
   K = 128) for 6 frames, and brick-pool maps smaller than the grid against
   the oracle.
+* Descent mapping (one step) and the rollout (16 x 10, sampled frames) at
+  256^3 / 320x240 / K = 128.
 """
 import numpy as np
 import pytest
@@ -354,6 +356,51 @@ def test_map_gd_full_size(big):
     assert moved.sum() > 100000
     assert np.all(err <= 1e-6 * np.maximum(np.abs(ref), 1e-2))
     assert np.array_equal(mg[~moved], m0[~moved])
+
+
+def test_rollout_full_size(big):
+    """The rollout of the throughput figure: 16 sampled trajectories x 10
+    steps with moments and every predicted frame, 256^3 FP32 (ground-truth
+    means), 320x240, K = 128.  Every sampled pose and the moments against the
+    oracle; four of the 160 frames (first and last steps of two
+    trajectories) against the oracle's render at its own sampled pose, mask
+    bit for bit."""
+    banner("rollout 256^3 320x240 K=128, 16 samples x 10 steps")
+    c, mean, var = big
+    tr = c["traj"]
+    g = grid_of(c["scene"], 0)
+    cam = cam_of(c["cam"])
+    f = P().Filter(g, cam, P().FilterParams(objective=0), vmap=gpu_map(g, mean, var))
+    rng = np.random.default_rng(24)
+    A = rng.normal(size=(12, 12)) * 0.01
+    Pb = A @ A.T + np.diag([1e-5] * 6 + [1e-4] * 6)
+    x = dict(t=tr.t[2], q=tr.q[2], v=tr.v[2], w=tr.w[2])
+    f.reset(np.concatenate([x["t"], x["q"], x["v"], x["w"]]), Pb)
+    k, S = 10, 16
+    u = rng.normal(size=(k, 6))
+    z = rng.normal(size=(S, k + 1, 12))
+    out = f.rollout(t(u, torch.float64), t(z, torch.float64), moments=True, frames=True)
+    torch.cuda.synchronize()
+    og, ocm = orc.grid_from_scene(c["scene"]), orc.cam_from(c["cam"])
+    ref = orc.rollout(og, None, ocm, x, Pb, u, z, orc.Params(), frames=False)
+    assert int(out["flags"].item()) == 0 and ref["ok"]
+    pg = out["poses"].cpu().numpy()
+    err = max(np.linalg.norm(orc.pose_error(pg[s, j], ref["poses"][s, j])) for s in range(S) for j in range(k))
+    print(f"[rollout] max pose error over {S * k} poses {err:.2e}", flush=True)
+    assert err < 1e-9
+    np.testing.assert_allclose(out["mean"].cpu().numpy(), ref["mean"], rtol=0, atol=1e-12)
+    cg = out["cov"].cpu().numpy()
+    assert np.linalg.norm(cg - ref["cov"]) <= 1e-10 * np.linalg.norm(ref["cov"])
+    m64 = mean.astype(np.float64)
+    for s, j in ((0, 0), (0, k - 1), (S - 1, 0), (S - 1, k - 1)):
+        n = s * k + j
+        r = orc.render(og, m64, ocm, ref["poses"][s, j])
+        mk = out["mask"][n].cpu().numpy()
+        np.testing.assert_array_equal(mk, r["mask"], err_msg=f"frame of sample {s}, step {j}")
+        v = mk == 1
+        assert v.sum() > 1000
+        assert np.all(depth_close(out["depth"][n].cpu().numpy()[v], r["depth"][v]))
+        assert np.all(rgb_close(out["rgb"][n].cpu().numpy()[v], r["rgb"][v]))
 
 
 # ---------------------------------------------------------------------------
