@@ -18,8 +18,9 @@ precision decisions.
 * The FP32 filter at the single-stream trajectory size (256^3, 320x240,
   K = 128) for 6 frames, and brick-pool maps smaller than the grid against
   the oracle.
-* Descent mapping (one step) and the rollout (16 x 10, sampled frames) at
-  256^3 / 320x240 / K = 128.
+* Descent mapping (one step), the rollout (16 x 10, sampled frames) and
+  filter steps with the paper's optimiser (1000 x 200 pixels) at 256^3 /
+  320x240 / K = 128.
 """
 import numpy as np
 import pytest
@@ -401,6 +402,43 @@ def test_rollout_full_size(big):
         assert v.sum() > 1000
         assert np.all(depth_close(out["depth"][n].cpu().numpy()[v], r["depth"][v]))
         assert np.all(rgb_close(out["rgb"][n].cpu().numpy()[v], r["rgb"][v]))
+
+
+def test_filter_adam_full_size(big):
+    """The paper's optimiser at its own settings (1000 steps of 200 sampled
+    pixels) in filter steps at 256^3 FP32, 320x240, K = 128: two steps from
+    the prior map against the oracle filter on the same frames and samples."""
+    banner("filter adam 256^3 320x240 K=128, 2 steps x 1000 Adam steps")
+    c, _, _ = big
+    tr = c["traj"]
+    n = c["scene"].n
+    g = grid_of(c["scene"], 0)
+    f = P().Filter(g, cam_of(c["cam"]), P().FilterParams(objective=0))
+    f.map.init()
+    x0 = np.concatenate([tr.t[0], tr.q[0], tr.v[0], tr.w[0]])
+    P0 = np.diag([1e-6] * 6 + [1e-4] * 6)
+    f.reset(x0, P0)
+    mean = np.zeros((4, n, n, n)); mean[0] = np.float32(-0.001)
+    of = orc.Filter(orc.grid_from_scene(c["scene"]), orc.cam_from(c["cam"]), orc.Params(objective="p2"),
+                    dict(t=tr.t[0], q=tr.q[0], v=tr.v[0], w=tr.w[0]), P0, mean, np.full_like(mean, 1e4))
+    del mean
+    ap = P().AdamParams.make(n_steps=1000, n_pixels=200)
+    H, W = c["cam"].height, c["cam"].width
+    for i in range(3):
+        pix = synth.sample_pixels(30 + i, ap.n_steps, ap.n_pixels, H, W)
+        u = tr.u[i - 1] if i else None
+        f.step_adam(t(c["depth"][i]), t(c["rgb"][i]), t(u, torch.float64) if i else None, ap,
+                    t(pix, torch.int32))
+        of.step(c["depth"][i].astype(np.float64), c["rgb"][i].astype(np.float64), u,
+                adam=dict(pixels=pix, lr_t=ap.lr_t, lr_r=ap.lr_r, beta2=ap.beta2, eps=ap.eps))
+        s = f.state()
+        dt_ = np.linalg.norm(np.array(s.pose.t) - of.s.t)
+        dr = rot_angle(np.array(s.pose.q), of.s.q)
+        print(f"step {i}: flags {s.flags} |dt| {dt_:.3e} dR {dr:.3e}", flush=True)
+        assert s.flags == 0
+        assert dt_ <= 1e-5 and dr <= 1e-5
+        Pg = np.array(s.P).reshape(12, 12)
+        assert np.linalg.norm(Pg - of.s.P) <= 1e-4 * np.linalg.norm(of.s.P)
 
 
 # ---------------------------------------------------------------------------
