@@ -970,7 +970,7 @@ prism_status prism_filter_create(const prism_filter_cfg* cfg, void* state_mem, v
     D.dtype = cfg->grid.dtype;
     D.n_gn = cfg->n_gn;
     D.nseg = (f->g.nb * f->g.nb * f->g.nb + 255) / 256;
-    D.upd_groups = map_update_groups(f->g);
+    D.upd_groups = map_update_groups_batch(f->g);
     D.obj_blocks = cfg->objective == PRISM_OBJ_P1 ? render_blocks(f->c) : track_blocks(f->c);
     D.map = map_mem;
     D.bits = skip_table(&cfg->grid, &cfg->cam, map_mem);

@@ -143,8 +143,10 @@ hipError_t launch_map_update(const GridC& g, const CamC& c, const GridD& gd, int
                              const prism_pose* pose, const float* depth, const float* rgb, double trunc, double lam_u,
                              const MapAux& aux, int64_t* n_updated, hipStream_t st, hipEvent_t t_begin = nullptr,
                              hipEvent_t t_end = nullptr);
-// workgroups (and per-workgroup counts) of one update launch
+// workgroups (and per-workgroup counts) of one update launch, alone or
+// within a batched launch
 int map_update_groups(const GridC& g);
+int map_update_groups_batch(const GridC& g);
 
 // descent mapping (gradient pass, step on marked bricks, cost total)
 // list: [0] number of bricks, then the bricks, in the order first touched
